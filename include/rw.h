@@ -1,0 +1,186 @@
+/*
+ * rw.h -- C ABI of the refined-wall Stokes solver for AMD MI355X (gfx950).
+ *
+ * Method: Zhang, Gillman & Veerapaneni, "A fast direct solver for integral
+ * equations on locally refined boundary discretizations and its application
+ * to multiphase flow simulations" (arXiv:2108.07205).
+ *
+ * The library solves the interior Stokes Dirichlet problem (Sec. 2.1, eq.
+ * model_bvp) on a closed star curve with the double-layer representation,
+ * Nystrom-discretized as A = -1/2 I + D + N (eqs. interior_BIE_discretized2
+ * and null), on a wall whose discretization is locally refined (Sec. 3.1).
+ * Per refinement it follows Algorithm 1 (Sec. 3.2):
+ *   precompute: Q ~= L R (Secs. 3.3-3.4), A_pp^{-1}, X = A~^{-1} L and the
+ *               Woodbury operator W = I + R X with its LU;
+ *   solve:      y = A~^{-1} g_ext (reference HBS inverse + A_pp^{-1}) and
+ *               tau_ext = y - X W^{-1} R y (eq. wood),
+ * followed by FP64 iterative refinement on the exact refined Nystrom residual.
+ *
+ * Conventions (all calls):
+ *  - Return value: RW_OK (0) or a negative RW_E* code; rw_last_error() gives
+ *    a message.  A call that fails leaves no partially built handle behind.
+ *  - Handles (rw_ctx, rw_wall, rw_refined) are opaque and library-owned;
+ *    free them with the matching *_free/*_destroy call.  A wall must outlive
+ *    the refined handles made from it; a ctx must outlive its walls.
+ *  - Arrays named *_dev are device pointers (HBM of the ctx's device),
+ *    owned by the caller, read/written on the ctx's HIP stream.  Arrays named
+ *    *_host are host pointers owned by the caller.
+ *  - Unknowns are node-major with (u_x, u_y) interleaved: unknown 2i is the
+ *    x component at node i, 2i+1 the y component.  Nodes follow the panel
+ *    order of the discretization (increasing curve parameter theta), 16 (or
+ *    `order`) Gauss-Legendre nodes per panel.
+ *  - Multi-column arrays are column-major with leading dimension 2*N (no
+ *    padding).
+ *  - Calls on one ctx are not thread-safe; use one ctx per host thread.
+ */
+#ifndef RW_H
+#define RW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rw_ctx rw_ctx;
+typedef struct rw_wall rw_wall;
+typedef struct rw_refined rw_refined;
+
+enum rw_status {
+  RW_OK = 0,
+  RW_EINVAL = -1,     /* bad argument: ids out of range, duplicates, level < 0 or > 8, nrhs <= 0, ... */
+  RW_ENOMEM = -2,     /* the request does not fit the ctx's HBM budget, or hipMalloc failed */
+  RW_ESINGULAR = -3,  /* zero / non-finite pivot in W, A_pp or an HBS node block */
+  RW_ENOCONV = -4,    /* iterative refinement did not reach the requested residual */
+  RW_EDEVICE = -5     /* a HIP runtime call or a kernel reported an error */
+};
+
+/* Storage precision of the reference HBS generators used by the solve
+ * (the FP64 copy is always kept for the iterative-refinement path). */
+enum rw_precision { RW_F64 = 0, RW_F32 = 1 };
+
+/* Star curve gamma(theta) = (1 + a cos(m theta)) (cos theta, sin theta),
+ * theta in [0, 2 pi), counter-clockwise (a = 0: unit circle). */
+typedef struct {
+  double a;
+  int32_t m;
+} rw_curve;
+
+/* Solver options of a ctx (defaults in brackets). */
+typedef struct {
+  double ir_tol;             /* stop refinement when ||g - A tau|| / ||g|| <= ir_tol, per column [1e-13] */
+  int32_t ir_maxit;          /* max refinement corrections; 0 = plain Woodbury solve [6] */
+  int32_t sketch_cols;       /* columns of the random sketch used for the row IDs of Q, 32..128 [64] */
+  uint64_t seed;             /* seed of the sketching matrix (counter-based, reproducible) [0x5eed] */
+} rw_options;
+
+/* Counts and timings reported by rw_refine / rw_solve. */
+typedef struct {
+  int64_t n_k, n_c, n_p;     /* kept / cut / added node counts (Sec. 3.1) */
+  int32_t k_k, k_p, k;       /* ranks of the k-row and p-row IDs of Q, k = k_k + k_p */
+  int32_t ir_iters;          /* refinement corrections applied by the last rw_solve */
+  double resid;              /* max over columns of ||g - A_nn tau|| / ||g|| after the last rw_solve */
+  double t_refine_ms;        /* wall time of the last rw_refine / rw_coarsen (host clock) */
+  double t_solve_ms;         /* wall time of the last rw_solve */
+} rw_info;
+
+/* Reference-wall statistics reported by rw_wall_stats. */
+typedef struct {
+  int64_t n_nodes;           /* N_o */
+  int32_t n_levels;          /* tree depth (root = level 0, leaves = level n_levels) */
+  int32_t max_rank;          /* largest skeleton size of any tree node */
+  int64_t gen_entries;       /* sum over nodes of |E| + |F| + |G| (the generators one apply reads) */
+  int64_t gen_bytes_f64;     /* 8 * gen_entries */
+  double t_build_ms;         /* host + device time of rw_wall_build */
+} rw_wall_stats;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a ctx bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t; NULL = the legacy default stream).  `hbm_budget_bytes`
+ * caps the device memory the library itself allocates for this ctx
+ * (0 = no cap).  Errors: RW_EINVAL (bad device), RW_EDEVICE. */
+int rw_ctx_create(rw_ctx** out, int device, void* hip_stream, size_t hbm_budget_bytes);
+void rw_ctx_destroy(rw_ctx* ctx);
+/* Message of the last error on this ctx ("" if none).  Valid until the next call. */
+const char* rw_last_error(const rw_ctx* ctx);
+/* Message of the last error of a failed rw_ctx_create (ctx does not exist yet). */
+const char* rw_create_error(void);
+int rw_set_options(rw_ctx* ctx, const rw_options* opt);
+int rw_get_options(const rw_ctx* ctx, rw_options* opt);
+/* Bytes the library currently holds on the device for this ctx. */
+size_t rw_ctx_bytes(const rw_ctx* ctx);
+
+/* ---- reference wall (static; Sec. 3, "given a fast direct solver for the
+ *      original discretization") ------------------------------------------ */
+
+/* Discretize the curve with n_panels Gauss-Legendre panels of `order`
+ * nodes, uniform in theta, and build the HBS compressed inverse A_oo^{-1}
+ * (tree of contiguous arcs, leaves of `leaf_nodes` nodes; interpolative
+ * decompositions at relative tolerance id_tol, Definition 3.1).  The
+ * generators are uploaded to HBM.  Requirements: order in [2, 32],
+ * n_panels*order divisible by leaf_nodes, leaf_nodes % order == 0,
+ * n_panels*order/leaf_nodes a power of two >= 2.
+ * Errors: RW_EINVAL, RW_ENOMEM, RW_ESINGULAR, RW_EDEVICE. */
+int rw_wall_build(rw_ctx* ctx, const rw_curve* curve, int32_t n_panels, int32_t order,
+                  int32_t leaf_nodes, double id_tol, int32_t precision, rw_wall** out);
+void rw_wall_free(rw_wall* wall);
+int rw_wall_stats_get(const rw_wall* wall, rw_wall_stats* st);
+/* Node arrays of the reference discretization (host, caller-owned, length
+ * 2*N_o for xy/normals, N_o for weights; NULL arrays are skipped).
+ * *n_nodes in: capacity in nodes, out: N_o. */
+int rw_wall_nodes(const rw_wall* wall, double* xy_host, double* normals_host,
+                  double* weights_host, int64_t* n_nodes);
+
+/* x = A_oo^{-1} b with the HBS inverse (Algorithm 1, solve step 1, first
+ * block).  b_dev, x_dev: 2*N_o x nrhs column-major, may not alias.
+ * Errors: RW_EINVAL (nrhs <= 0), RW_ENOMEM, RW_EDEVICE. */
+int rw_hbs_apply(rw_wall* wall, const double* b_dev, int32_t nrhs, double* x_dev);
+
+/* ---- refinement (per time step; Algorithm 1 pre-computation) ------------ */
+
+/* Refine reference panels panel_ids[i] into 2^levels[i] equal-theta
+ * children (levels[i] = 0 keeps the panel but still routes it through the
+ * extended system), then build Q ~= L R, A_pp^{-1}, X = A~^{-1} L and the LU
+ * of W = I + R X.  n_sel = 0 gives the unrefined wall (k = 0).
+ * Errors: RW_EINVAL (ids out of [0, n_panels), duplicates, levels outside
+ * [0, 8]), RW_ENOMEM, RW_ESINGULAR, RW_EDEVICE. */
+int rw_refine(rw_wall* wall, const int32_t* panel_ids_host, const int32_t* levels_host,
+              int32_t n_sel, rw_refined** out);
+/* Coarsen: give panel_ids_host[i] back its reference discretization and
+ * redo the pre-computation for the remaining refinement (coarsening all
+ * refined panels returns the reference problem).  Ids that are not refined
+ * are an error (RW_EINVAL).  On error the handle is unchanged. */
+int rw_coarsen(rw_refined* ref, const int32_t* panel_ids_host, int32_t n_sel);
+void rw_refined_free(rw_refined* ref);
+int rw_refined_info(const rw_refined* ref, rw_info* info);
+/* Node arrays of the refined discretization I_n (host), as rw_wall_nodes. */
+int rw_nodes(const rw_refined* ref, double* xy_host, double* normals_host,
+             double* weights_host, int64_t* n_nodes);
+
+/* ---- solve (Algorithm 1 solve steps + FP64 refinement) ------------------ */
+
+/* tau = A_nn^{-1} g for nrhs right-hand sides: Woodbury solve (eq. wood)
+ * then iterative refinement with the exact refined Nystrom residual until
+ * ||g - A_nn tau|| / ||g|| <= ir_tol (per column) or ir_maxit corrections.
+ * g_dev, tau_dev: 2*N_n x nrhs column-major, may not alias.  The stream is
+ * synchronized before return.  Errors: RW_EINVAL, RW_ENOMEM,
+ * RW_ENOCONV (result written, residual above tolerance), RW_EDEVICE. */
+int rw_solve(rw_refined* ref, const double* g_dev, int32_t nrhs, double* tau_dev);
+
+/* r = g - A_nn tau on the refined discretization (exact Nystrom operator,
+ * entries generated on the fly).  Shapes as rw_solve. */
+int rw_residual(rw_refined* ref, const double* g_dev, const double* tau_dev,
+                int32_t nrhs, double* r_dev);
+
+/* Boundary data of exterior Stokeslets (eq. stokeslet, mu = 1) at the refined
+ * nodes: g(x_i) = sum_m S(x_i, z_m) f_m.  z_host, f_host: n_src x 2 row-major
+ * (host).  g_dev: 2*N_n (one column).  Errors: RW_EINVAL, RW_EDEVICE. */
+int rw_stokeslet_rhs(rw_refined* ref, const double* z_host, const double* f_host,
+                     int32_t n_src, double* g_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RW_H */
