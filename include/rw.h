@@ -20,7 +20,7 @@
  *  - Return value: RW_OK (0) or a negative RW_E* code; rw_last_error() gives
  *    a message.  A call that fails leaves no partially built handle behind.
  *  - Handles (rw_ctx, rw_wall, rw_refined) are opaque and library-owned;
- *    free them with the matching *_free/*_destroy call.  A wall must outlive
+ *    free them with the matching free or destroy call.  A wall must outlive
  *    the refined handles made from it; a ctx must outlive its walls.
  *  - Arrays named *_dev are device pointers (HBM of the ctx's device),
  *    owned by the caller, read/written on the ctx's HIP stream.  Arrays named
@@ -73,6 +73,8 @@ typedef struct {
   int32_t ir_maxit;          /* max refinement corrections; 0 = plain Woodbury solve [6] */
   int32_t sketch_cols;       /* columns of the random sketch used for the row IDs of Q, 32..128 [64] */
   uint64_t seed;             /* seed of the sketching matrix (counter-based, reproducible) [0x5eed] */
+  int32_t app_dense_max_nodes; /* A_pp^{-1} by dense LU up to this many added nodes, else by an HBS
+                                  inverse built on the GPU (Algorithm 1 step 2) [1024] */
 } rw_options;
 
 /* Counts and timings reported by rw_refine / rw_solve. */
@@ -109,8 +111,25 @@ const char* rw_last_error(const rw_ctx* ctx);
 const char* rw_create_error(void);
 int rw_set_options(rw_ctx* ctx, const rw_options* opt);
 int rw_get_options(const rw_ctx* ctx, rw_options* opt);
-/* Bytes the library currently holds on the device for this ctx. */
+/* Bytes the library currently holds on the device for this ctx, including
+ * blocks kept for reuse by its caching allocator (freed handles return their
+ * device memory to that cache, so a steady refine / solve loop stops calling
+ * hipMalloc once warm). */
 size_t rw_ctx_bytes(const rw_ctx* ctx);
+/* Return the cached (unused) device blocks of this ctx to the HIP runtime. */
+int rw_ctx_trim(rw_ctx* ctx);
+
+/* Phase profiler: when enabled, every step of Algorithm 1 (a1_geometry,
+ * a2_sketch, a2_row_id, a2_interp_rows, a3_app_assemble, a3_app_lu, a4_X,
+ * a5_W, a6_hbs_apply, a6_app_solve, a7_woodbury, a8_residual) is bracketed by
+ * HIP events on the ctx stream; rw_profile_json writes
+ *   {"phase": {"ms": total, "calls": n, "flops": algorithmic flops,
+ *              "bytes": algorithmic HBM bytes}, ...}
+ * into buf (NUL-terminated, truncated to len) and returns the length needed
+ * including the NUL (or a negative error). */
+int rw_profile_enable(rw_ctx* ctx, int on);
+int rw_profile_reset(rw_ctx* ctx);
+int64_t rw_profile_json(rw_ctx* ctx, char* buf, int64_t len);
 
 /* ---- reference wall (static; Sec. 3, "given a fast direct solver for the
  *      original discretization") ------------------------------------------ */

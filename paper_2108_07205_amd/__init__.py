@@ -1,0 +1,441 @@
+"""Refined-wall Stokes solver for AMD MI355X (gfx950): Python binding.
+
+Thin ctypes marshalling over the C ABI in ``include/rw.h`` (``librw.so``,
+built by ``python -m paper_2108_07205_amd.build``).  Every step of the solve
+runs in the library's HIP kernels; PyTorch only provides device memory and
+the HIP stream.  The module-level functions carry the C names
+(``rw_ctx_create``, ``rw_wall_build``, ``rw_refine``, ``rw_solve`` ...); the
+``Context`` / ``Wall`` / ``Refined`` classes are small conveniences on top.
+
+Importing this package never falls back to anything: if ``librw.so`` is
+missing, ``load_library()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "RwError", "load_library", "Context", "Wall", "Refined",
+    "rw_ctx_create", "rw_ctx_destroy", "rw_set_options", "rw_get_options", "rw_wall_build",
+    "rw_wall_free", "rw_wall_stats_get", "rw_wall_nodes", "rw_hbs_apply", "rw_refine", "rw_coarsen",
+    "rw_refined_free", "rw_refined_info", "rw_nodes", "rw_solve", "rw_residual", "rw_stokeslet_rhs",
+    "rw_ctx_trim", "rw_profile_enable", "rw_profile_reset", "rw_profile_json",
+    "RW_OK", "RW_EINVAL", "RW_ENOMEM", "RW_ESINGULAR", "RW_ENOCONV", "RW_EDEVICE", "RW_F64", "RW_F32",
+    "EXPORTED_SYMBOLS",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librw.so")
+
+RW_OK, RW_EINVAL, RW_ENOMEM, RW_ESINGULAR, RW_ENOCONV, RW_EDEVICE = 0, -1, -2, -3, -4, -5
+RW_F64, RW_F32 = 0, 1
+_CODES = {RW_EINVAL: "RW_EINVAL", RW_ENOMEM: "RW_ENOMEM", RW_ESINGULAR: "RW_ESINGULAR",
+          RW_ENOCONV: "RW_ENOCONV", RW_EDEVICE: "RW_EDEVICE"}
+
+
+class RwError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class rw_curve(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("m", ctypes.c_int32)]
+
+
+class rw_options(ctypes.Structure):
+    _fields_ = [("ir_tol", ctypes.c_double), ("ir_maxit", ctypes.c_int32),
+                ("sketch_cols", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("app_dense_max_nodes", ctypes.c_int32)]
+
+
+class rw_info(ctypes.Structure):
+    _fields_ = [("n_k", ctypes.c_int64), ("n_c", ctypes.c_int64), ("n_p", ctypes.c_int64),
+                ("k_k", ctypes.c_int32), ("k_p", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("ir_iters", ctypes.c_int32), ("resid", ctypes.c_double),
+                ("t_refine_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
+
+
+class rw_wall_stats(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_levels", ctypes.c_int32), ("max_rank", ctypes.c_int32),
+                ("gen_entries", ctypes.c_int64), ("gen_bytes_f64", ctypes.c_int64),
+                ("t_build_ms", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_DP = ctypes.POINTER(ctypes.c_double)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+
+# symbol -> (restype, argtypes); the set of exported C functions of rw.h
+_SIGS = {
+    "rw_ctx_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P, ctypes.c_size_t]),
+    "rw_ctx_destroy": (None, [_P]),
+    "rw_last_error": (ctypes.c_char_p, [_P]),
+    "rw_create_error": (ctypes.c_char_p, []),
+    "rw_set_options": (ctypes.c_int, [_P, ctypes.POINTER(rw_options)]),
+    "rw_get_options": (ctypes.c_int, [_P, ctypes.POINTER(rw_options)]),
+    "rw_ctx_bytes": (ctypes.c_size_t, [_P]),
+    "rw_ctx_trim": (ctypes.c_int, [_P]),
+    "rw_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
+    "rw_profile_reset": (ctypes.c_int, [_P]),
+    "rw_profile_json": (ctypes.c_int64, [_P, ctypes.c_char_p, ctypes.c_int64]),
+    "rw_wall_build": (ctypes.c_int, [_P, ctypes.POINTER(rw_curve), ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "rw_wall_free": (None, [_P]),
+    "rw_wall_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(rw_wall_stats)]),
+    "rw_wall_nodes": (ctypes.c_int, [_P, _DP, _DP, _DP, _I64P]),
+    "rw_hbs_apply": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
+    "rw_refine": (ctypes.c_int, [_P, _I32P, _I32P, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "rw_coarsen": (ctypes.c_int, [_P, _I32P, ctypes.c_int32]),
+    "rw_refined_free": (None, [_P]),
+    "rw_refined_info": (ctypes.c_int, [_P, ctypes.POINTER(rw_info)]),
+    "rw_nodes": (ctypes.c_int, [_P, _DP, _DP, _DP, _I64P]),
+    "rw_solve": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
+    "rw_residual": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P]),
+    "rw_stokeslet_rhs": (ctypes.c_int, [_P, _DP, _DP, ctypes.c_int32, _P]),
+}
+EXPORTED_SYMBOLS = tuple(_SIGS)
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load ``librw.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_2108_07205_amd.build`")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int, ctx=None):
+    if rc != RW_OK:
+        lib = load_library()
+        msg = lib.rw_last_error(ctx).decode() if ctx else lib.rw_create_error().decode()
+        raise RwError(rc, msg)
+
+
+def _dev_ptr(t, name: str, rows: int = None):
+    """Pointer and column count of a contiguous float64 device tensor of shape
+    (rows,) or (ncols, rows) (= column-major rows x ncols)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a torch tensor on a HIP device")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.dim() == 1:
+        n, ncols = t.shape[0], 1
+    elif t.dim() == 2:
+        ncols, n = t.shape
+    else:
+        raise ValueError(f"{name} must be 1-D or 2-D")
+    if rows is not None and n != rows:
+        raise ValueError(f"{name} has {n} rows, expected {rows}")
+    return ctypes.c_void_p(t.data_ptr()), int(ncols)
+
+
+# ----------------------------------------------------------------- C names
+def rw_ctx_create(device: int = 0, stream: Optional[int] = None, hbm_budget_bytes: int = 0):
+    lib = load_library()
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream(device).cuda_stream
+    out = _P()
+    _check(lib.rw_ctx_create(ctypes.byref(out), device, _P(stream), hbm_budget_bytes))
+    return out
+
+
+def rw_ctx_destroy(ctx):
+    load_library().rw_ctx_destroy(ctx)
+
+
+def rw_set_options(ctx, ir_tol=None, ir_maxit=None, sketch_cols=None, seed=None, app_dense_max_nodes=None):
+    lib = load_library()
+    o = rw_options()
+    _check(lib.rw_get_options(ctx, ctypes.byref(o)), ctx)
+    if ir_tol is not None:
+        o.ir_tol = ir_tol
+    if ir_maxit is not None:
+        o.ir_maxit = ir_maxit
+    if sketch_cols is not None:
+        o.sketch_cols = sketch_cols
+    if seed is not None:
+        o.seed = seed
+    if app_dense_max_nodes is not None:
+        o.app_dense_max_nodes = app_dense_max_nodes
+    _check(lib.rw_set_options(ctx, ctypes.byref(o)), ctx)
+
+
+def rw_get_options(ctx) -> dict:
+    o = rw_options()
+    _check(load_library().rw_get_options(ctx, ctypes.byref(o)), ctx)
+    return {f: getattr(o, f) for f, _ in rw_options._fields_}
+
+
+def rw_ctx_trim(ctx):
+    _check(load_library().rw_ctx_trim(ctx), ctx)
+
+
+def rw_profile_enable(ctx, on: bool = True):
+    _check(load_library().rw_profile_enable(ctx, 1 if on else 0), ctx)
+
+
+def rw_profile_reset(ctx):
+    _check(load_library().rw_profile_reset(ctx), ctx)
+
+
+def rw_profile_json(ctx) -> dict:
+    import json
+    lib = load_library()
+    n = lib.rw_profile_json(ctx, None, 0)
+    if n < 0:
+        _check(int(n), ctx)
+    buf = ctypes.create_string_buffer(int(n) + 16)
+    lib.rw_profile_json(ctx, buf, len(buf))
+    return json.loads(buf.value.decode())
+
+
+def rw_wall_build(ctx, n_panels: int, order: int = 16, leaf_nodes: int = 64, id_tol: float = 1e-10,
+                  precision: int = RW_F64, a: float = 0.3, m: int = 5):
+    out = _P()
+    cv = rw_curve(a, m)
+    _check(load_library().rw_wall_build(ctx, ctypes.byref(cv), n_panels, order, leaf_nodes, id_tol,
+                                        precision, ctypes.byref(out)), ctx)
+    return out
+
+
+def rw_wall_free(wall):
+    load_library().rw_wall_free(wall)
+
+
+def rw_wall_stats_get(ctx, wall) -> dict:
+    st = rw_wall_stats()
+    _check(load_library().rw_wall_stats_get(wall, ctypes.byref(st)), ctx)
+    return {f: getattr(st, f) for f, _ in rw_wall_stats._fields_}
+
+
+def _nodes(fn, ctx, h):
+    n = ctypes.c_int64(0)
+    _check(fn(h, None, None, None, ctypes.byref(n)), ctx)
+    xy = np.empty(2 * n.value)
+    nr = np.empty(2 * n.value)
+    w = np.empty(n.value)
+    _check(fn(h, xy.ctypes.data_as(_DP), nr.ctypes.data_as(_DP), w.ctypes.data_as(_DP), ctypes.byref(n)), ctx)
+    return xy.reshape(-1, 2), nr.reshape(-1, 2), w
+
+
+def rw_wall_nodes(ctx, wall):
+    return _nodes(load_library().rw_wall_nodes, ctx, wall)
+
+
+def rw_hbs_apply(ctx, wall, b, x, n_unknowns: int):
+    pb, nb = _dev_ptr(b, "b", n_unknowns)
+    px, nx = _dev_ptr(x, "x", n_unknowns)
+    if nb != nx:
+        raise ValueError("b and x column counts differ")
+    _check(load_library().rw_hbs_apply(wall, pb, nb, px), ctx)
+
+
+def rw_refine(ctx, wall, panel_ids: Sequence[int], levels: Sequence[int]):
+    ids = np.ascontiguousarray(panel_ids, dtype=np.int32)
+    lev = np.ascontiguousarray(levels, dtype=np.int32)
+    if ids.shape != lev.shape:
+        raise ValueError("panel_ids and levels differ in length")
+    out = _P()
+    _check(load_library().rw_refine(wall, ids.ctypes.data_as(_I32P), lev.ctypes.data_as(_I32P), ids.size,
+                                    ctypes.byref(out)), ctx)
+    return out
+
+
+def rw_coarsen(ctx, ref, panel_ids: Sequence[int]):
+    ids = np.ascontiguousarray(panel_ids, dtype=np.int32)
+    _check(load_library().rw_coarsen(ref, ids.ctypes.data_as(_I32P), ids.size), ctx)
+
+
+def rw_refined_free(ref):
+    load_library().rw_refined_free(ref)
+
+
+def rw_refined_info(ctx, ref) -> dict:
+    inf = rw_info()
+    _check(load_library().rw_refined_info(ref, ctypes.byref(inf)), ctx)
+    return {f: getattr(inf, f) for f, _ in rw_info._fields_}
+
+
+def rw_nodes(ctx, ref):
+    return _nodes(load_library().rw_nodes, ctx, ref)
+
+
+def rw_solve(ctx, ref, g, tau, n_unknowns: int, check: bool = True):
+    pg, ng = _dev_ptr(g, "g", n_unknowns)
+    pt, nt = _dev_ptr(tau, "tau", n_unknowns)
+    if ng != nt:
+        raise ValueError("g and tau column counts differ")
+    rc = load_library().rw_solve(ref, pg, ng, pt)
+    if check:
+        _check(rc, ctx)
+    return rc
+
+
+def rw_residual(ctx, ref, g, tau, r, n_unknowns: int):
+    pg, ng = _dev_ptr(g, "g", n_unknowns)
+    pt, _ = _dev_ptr(tau, "tau", n_unknowns)
+    pr, _ = _dev_ptr(r, "r", n_unknowns)
+    _check(load_library().rw_residual(ref, pg, pt, ng, pr), ctx)
+
+
+def rw_stokeslet_rhs(ctx, ref, z, f, g, n_unknowns: int):
+    z = np.ascontiguousarray(z, dtype=np.float64).reshape(-1, 2)
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1, 2)
+    pg, _ = _dev_ptr(g, "g", n_unknowns)
+    _check(load_library().rw_stokeslet_rhs(ref, z.ctypes.data_as(_DP), f.ctypes.data_as(_DP), z.shape[0], pg), ctx)
+
+
+# ----------------------------------------------------------------- classes
+class Context:
+    """A device + stream + HBM budget; owns nothing but scratch flags."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None, hbm_budget_bytes: int = 0, **opts):
+        self.device = device
+        self.h = rw_ctx_create(device, stream, hbm_budget_bytes)
+        if opts:
+            rw_set_options(self.h, **opts)
+
+    def set_options(self, **opts):
+        rw_set_options(self.h, **opts)
+
+    def options(self) -> dict:
+        return rw_get_options(self.h)
+
+    def bytes(self) -> int:
+        return int(load_library().rw_ctx_bytes(self.h))
+
+    def trim(self):
+        rw_ctx_trim(self.h)
+
+    def profile(self, on: bool = True):
+        rw_profile_enable(self.h, on)
+
+    def profile_reset(self):
+        rw_profile_reset(self.h)
+
+    def profile_json(self) -> dict:
+        return rw_profile_json(self.h)
+
+    def close(self):
+        if self.h:
+            rw_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Wall:
+    """Reference wall with its HBS compressed inverse resident in HBM."""
+
+    def __init__(self, ctx: Context, n_panels: int, order: int = 16, leaf_nodes: int = 64,
+                 id_tol: float = 1e-10, precision: int = RW_F64, a: float = 0.3, m: int = 5):
+        self.ctx = ctx
+        self.h = rw_wall_build(ctx.h, n_panels, order, leaf_nodes, id_tol, precision, a, m)
+        self.n_nodes = n_panels * order
+        self.n_panels = n_panels
+
+    def stats(self) -> dict:
+        return rw_wall_stats_get(self.ctx.h, self.h)
+
+    def nodes(self):
+        return rw_wall_nodes(self.ctx.h, self.h)
+
+    def hbs_apply(self, b):
+        import torch
+        x = torch.empty_like(b)
+        rw_hbs_apply(self.ctx.h, self.h, b, x, 2 * self.n_nodes)
+        return x
+
+    def refine(self, panel_ids, levels) -> "Refined":
+        return Refined(self, panel_ids, levels)
+
+    def close(self):
+        if self.h:
+            rw_wall_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Refined:
+    """A locally refined discretization with its Algorithm-1 factors."""
+
+    def __init__(self, wall: Wall, panel_ids, levels):
+        self.wall = wall
+        self.ctx = wall.ctx
+        self.h = rw_refine(self.ctx.h, wall.h, panel_ids, levels)
+        self._refresh()
+
+    def _refresh(self):
+        self.info_ = rw_refined_info(self.ctx.h, self.h)
+        self.n_nodes = int(self.info_["n_k"] + self.info_["n_p"])
+
+    @property
+    def n_unknowns(self) -> int:
+        return 2 * self.n_nodes
+
+    def info(self) -> dict:
+        return rw_refined_info(self.ctx.h, self.h)
+
+    def coarsen(self, panel_ids):
+        rw_coarsen(self.ctx.h, self.h, panel_ids)
+        self._refresh()
+
+    def nodes(self):
+        return rw_nodes(self.ctx.h, self.h)
+
+    def stokeslet_rhs(self, z, f):
+        import torch
+        g = torch.empty(self.n_unknowns, dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        rw_stokeslet_rhs(self.ctx.h, self.h, z, f, g, self.n_unknowns)
+        return g
+
+    def solve(self, g, check: bool = True):
+        import torch
+        tau = torch.empty_like(g)
+        rw_solve(self.ctx.h, self.h, g, tau, self.n_unknowns, check=check)
+        return tau
+
+    def residual(self, g, tau):
+        import torch
+        r = torch.empty_like(g)
+        rw_residual(self.ctx.h, self.h, g, tau, r, self.n_unknowns)
+        return r
+
+    def close(self):
+        if self.h:
+            rw_refined_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

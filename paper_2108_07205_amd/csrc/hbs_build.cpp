@@ -1,0 +1,270 @@
+#include "hbs_build.h"
+
+#include <algorithm>
+#include <cmath>
+
+#include "hostla.h"
+
+namespace {
+
+// 2x2 block of A = -1/2 I + D + N for target t and source s (w_s folded in).
+inline void a_block(const NodeRec& t, const NodeRec& s, bool self, double B[4]) {
+  if (self) {
+    B[0] = s.s00; B[1] = s.s01; B[2] = s.s01; B[3] = s.s11;
+    return;
+  }
+  const double rx = t.x - s.x, ry = t.y - s.y;
+  const double r2 = rx * rx + ry * ry;
+  const double c = (rx * s.nx + ry * s.ny) * s.w / (M_PI * r2 * r2);
+  B[0] = c * rx * rx + s.w * t.nx * s.nx;
+  B[1] = c * rx * ry + s.w * t.nx * s.ny;
+  B[2] = c * ry * rx + s.w * t.ny * s.nx;
+  B[3] = c * ry * ry + s.w * t.ny * s.ny;
+}
+
+inline double a_entry(const std::vector<NodeRec>& nd, int rdof, int cdof) {
+  double B[4];
+  const int i = rdof >> 1, j = cdof >> 1;
+  a_block(nd[i], nd[j], i == j, B);
+  return B[(rdof & 1) * 2 + (cdof & 1)];
+}
+
+// A(rows, cols) column-major (ld = rows.size()).
+void a_sub(const std::vector<NodeRec>& nd, const std::vector<int>& rows, const std::vector<int>& cols,
+           std::vector<double>& out) {
+  const size_t m = rows.size();
+  out.resize(m * cols.size());
+  for (size_t c = 0; c < cols.size(); ++c)
+    for (size_t r = 0; r < m; ++r) out[r + c * m] = a_entry(nd, rows[r], cols[c]);
+}
+
+struct CNode {
+  int64_t n0 = 0, n1 = 0;  // node range [n0, n1)
+  std::vector<int> candr, candc;
+  int k = 0;
+  std::vector<int> Jr, Jc;
+  std::vector<double> U, V;  // m x k column-major
+};
+
+// Stokeslet S(x, p) (1/(4 pi)) (-log r I + r r^T / r^2), r = x - p.
+inline void stokeslet(double rx, double ry, double S[4]) {
+  const double r2 = rx * rx + ry * ry;
+  const double a = -0.25 / M_PI * 0.5 * std::log(r2);
+  const double b = 0.25 / M_PI / r2;
+  S[0] = a + b * rx * rx;
+  S[1] = b * rx * ry;
+  S[2] = S[1];
+  S[3] = a + b * ry * ry;
+}
+
+// Double layer D(x, y) with normal ny (unit weight), r = x - y.
+inline void dlayer(double rx, double ry, double nx, double ny, double D[4]) {
+  const double r2 = rx * rx + ry * ry;
+  const double c = (rx * nx + ry * ny) / (M_PI * r2 * r2);
+  D[0] = c * rx * rx;
+  D[1] = c * rx * ry;
+  D[2] = D[1];
+  D[3] = c * ry * ry;
+}
+
+void compress_node(const std::vector<NodeRec>& nd, const HbsParams& prm, CNode& cn) {
+  const int64_t N = (int64_t)nd.size();
+  // proxy circle around the node's points
+  double cx = 0, cy = 0;
+  for (int64_t i = cn.n0; i < cn.n1; ++i) { cx += nd[i].x; cy += nd[i].y; }
+  cx /= double(cn.n1 - cn.n0);
+  cy /= double(cn.n1 - cn.n0);
+  double R = 0;
+  for (int64_t i = cn.n0; i < cn.n1; ++i) R = std::max(R, std::hypot(nd[i].x - cx, nd[i].y - cy));
+  const double Rp = prm.proxy_ratio * R;
+  std::vector<int> near;
+  bool all_near = true;
+  for (int64_t i = 0; i < N; ++i) {
+    if (i >= cn.n0 && i < cn.n1) continue;
+    if (std::hypot(nd[i].x - cx, nd[i].y - cy) < Rp) {
+      near.push_back(2 * (int)i);
+      near.push_back(2 * (int)i + 1);
+    } else {
+      all_near = false;
+    }
+  }
+  const int np = all_near ? 0 : prm.n_proxy;
+  std::vector<double> px(np), py(np), pnx(np), pny(np);
+  for (int l = 0; l < np; ++l) {
+    const double th = 2.0 * M_PI * l / np;
+    pnx[l] = std::cos(th);
+    pny[l] = std::sin(th);
+    px[l] = cx + Rp * pnx[l];
+    py[l] = cy + Rp * pny[l];
+  }
+
+  // ---- row ID: rows = candr, columns = [near | Stokeslet proxies | DLP proxies | n]
+  const double wp = np ? 2.0 * M_PI * Rp / np : 0.0;  // proxy-circle quadrature weight
+  const int m_r = (int)cn.candr.size();
+  const int ncol = (int)near.size() + (np ? 4 * np + 1 : 0);
+  std::vector<double> MrT((size_t)ncol * m_r);  // transposed: column i = row i of M_r
+  for (int i = 0; i < m_r; ++i) {
+    const int rd = cn.candr[i], a = rd >> 1, ca = rd & 1;
+    double* col = MrT.data() + (size_t)i * ncol;
+    for (size_t q = 0; q < near.size(); ++q) col[q] = a_entry(nd, rd, near[q]);
+    if (np) {
+      double* pc = col + near.size();
+      for (int l = 0; l < np; ++l) {
+        double S[4], D[4];
+        const double rx = nd[a].x - px[l], ry = nd[a].y - py[l];
+        stokeslet(rx, ry, S);
+        dlayer(rx, ry, pnx[l], pny[l], D);
+        pc[2 * l] = S[ca * 2 + 0];
+        pc[2 * l + 1] = S[ca * 2 + 1];
+        pc[2 * np + 2 * l] = wp * D[ca * 2 + 0];
+        pc[2 * np + 2 * l + 1] = wp * D[ca * 2 + 1];
+      }
+      pc[4 * np] = ca ? nd[a].ny : nd[a].nx;
+    }
+  }
+  // ---- column ID: columns = candc, rows = [near | DLP at proxies (2 comps) | flux]
+  const int m_c = (int)cn.candc.size();
+  const int nrow = (int)near.size() + (np ? 2 * np + 1 : 0);
+  std::vector<double> Mc((size_t)nrow * m_c);
+  for (int j = 0; j < m_c; ++j) {
+    const int cd = cn.candc[j], b = cd >> 1, cb = cd & 1;
+    double* col = Mc.data() + (size_t)j * nrow;
+    for (size_t q = 0; q < near.size(); ++q) col[q] = a_entry(nd, near[q], cd);
+    if (np) {
+      double* pc = col + near.size();
+      for (int l = 0; l < np; ++l) {
+        double D[4];
+        dlayer(px[l] - nd[b].x, py[l] - nd[b].y, nd[b].nx, nd[b].ny, D);
+        pc[2 * l] = nd[b].w * D[0 * 2 + cb];
+        pc[2 * l + 1] = nd[b].w * D[1 * 2 + cb];
+      }
+      pc[2 * np] = nd[b].w * (cb ? nd[b].ny : nd[b].nx);
+    }
+  }
+  std::vector<double> MrT_keep = MrT, Mc_keep = Mc;
+  Cpqr fr = hcpqr(ncol, m_r, MrT, prm.tol, 0);
+  Cpqr fc = hcpqr(nrow, m_c, Mc, prm.tol, 0);
+  int k = std::max(fr.k_tol, fc.k_tol);
+  k = std::min(k, std::min(m_r, m_c));
+  if (fr.steps < k) { MrT = MrT_keep; fr = hcpqr(ncol, m_r, MrT, prm.tol, k); }
+  if (fc.steps < k) { Mc = Mc_keep; fc = hcpqr(nrow, m_c, Mc, prm.tol, k); }
+  k = std::min(k, std::min(fr.steps, fc.steps));
+  cn.k = k;
+  auto interp = [&](const Cpqr& f, int m, std::vector<double>& P) {
+    std::vector<double> T = cpqr_interp(f, m, k);
+    P.assign((size_t)m * k, 0.0);
+    for (int i = 0; i < k; ++i) P[f.perm[i] + (size_t)i * m] = 1.0;
+    for (int q = 0; q < m - k; ++q)
+      for (int i = 0; i < k; ++i) P[f.perm[k + q] + (size_t)i * m] = T[i + (size_t)q * k];
+  };
+  interp(fr, m_r, cn.U);
+  interp(fc, m_c, cn.V);
+  cn.Jr.resize(k);
+  cn.Jc.resize(k);
+  for (int i = 0; i < k; ++i) {
+    cn.Jr[i] = cn.candr[fr.perm[i]];
+    cn.Jc[i] = cn.candc[fc.perm[i]];
+  }
+}
+
+}  // namespace
+
+void hbs_build_inverse(const std::vector<NodeRec>& nd, const HbsParams& prm, HbsInverse& out) {
+  const int64_t N = (int64_t)nd.size();
+  const int64_t nleaf = N / prm.leaf_nodes;
+  int L = 0;
+  while ((int64_t(1) << L) < nleaf) ++L;
+  if ((int64_t(1) << L) != nleaf || nleaf * prm.leaf_nodes != N || L < 1)
+    RW_THROW(RW_EINVAL, "HBS tree needs N / leaf_nodes to be a power of two >= 2");
+  out = HbsInverse();
+  out.L = L;
+  out.lev.resize(L + 1);
+  std::vector<std::vector<CNode>> cn(L + 1);
+
+  // ---- compression, leaves to level 1
+  for (int l = L; l >= 1; --l) {
+    const int64_t cnt = int64_t(1) << l, sz = N / cnt;
+    cn[l].resize(cnt);
+    parallel_for(cnt, [&](int64_t j) {
+      CNode& c = cn[l][j];
+      c.n0 = j * sz;
+      c.n1 = (j + 1) * sz;
+      if (l == L) {
+        for (int64_t d = 2 * c.n0; d < 2 * c.n1; ++d) c.candr.push_back((int)d);
+        c.candc = c.candr;
+      } else {
+        const CNode& a = cn[l + 1][2 * j];
+        const CNode& b = cn[l + 1][2 * j + 1];
+        c.candr = a.Jr;
+        c.candr.insert(c.candr.end(), b.Jr.begin(), b.Jr.end());
+        c.candc = a.Jc;
+        c.candc.insert(c.candc.end(), b.Jc.begin(), b.Jc.end());
+      }
+      compress_node(nd, prm, c);
+    }, prm.threads);
+  }
+
+  // ---- inverse, leaves to root
+  std::vector<std::vector<std::vector<double>>> Dhat(L + 1);
+  for (int l = L; l >= 0; --l) {
+    const int64_t cnt = int64_t(1) << l;
+    if (l >= 1) out.lev[l].resize(cnt);
+    Dhat[l].resize(cnt);
+    parallel_for(cnt, [&](int64_t j) {
+      std::vector<double> Dm;
+      int n;
+      if (l == L) {
+        const CNode& c = cn[l][j];
+        n = (int)c.candr.size();
+        a_sub(nd, c.candr, c.candc, Dm);
+      } else {
+        const CNode& a = cn[l + 1][2 * j];
+        const CNode& b = cn[l + 1][2 * j + 1];
+        const int ka = a.k, kb = b.k;
+        n = ka + kb;
+        Dm.assign((size_t)n * n, 0.0);
+        const std::vector<double>& Da = Dhat[l + 1][2 * j];
+        const std::vector<double>& Db = Dhat[l + 1][2 * j + 1];
+        for (int c = 0; c < ka; ++c)
+          for (int r = 0; r < ka; ++r) Dm[r + (size_t)c * n] = Da[r + (size_t)c * ka];
+        for (int c = 0; c < kb; ++c)
+          for (int r = 0; r < kb; ++r) Dm[ka + r + (size_t)(ka + c) * n] = Db[r + (size_t)c * kb];
+        for (int c = 0; c < kb; ++c)
+          for (int r = 0; r < ka; ++r) Dm[r + (size_t)(ka + c) * n] = a_entry(nd, a.Jr[r], b.Jc[c]);
+        for (int c = 0; c < ka; ++c)
+          for (int r = 0; r < kb; ++r) Dm[ka + r + (size_t)c * n] = a_entry(nd, b.Jr[r], a.Jc[c]);
+      }
+      if (hinv(n, Dm.data(), n)) RW_THROW(RW_ESINGULAR, "singular diagonal block in the HBS inverse");
+      if (l == 0) {
+        out.nroot = n;
+        out.Groot = std::move(Dm);
+        return;
+      }
+      const CNode& c = cn[l][j];
+      const int k = c.k;
+      // DinvU (n x k), VtDinv (k x n)
+      std::vector<double> DinvU((size_t)n * k), VtDinv((size_t)k * n), S((size_t)k * k);
+      hgemm('N', 'N', n, k, n, 1.0, Dm.data(), n, c.U.data(), n, 0.0, DinvU.data(), n);
+      hgemm('T', 'N', k, n, n, 1.0, c.V.data(), n, Dm.data(), n, 0.0, VtDinv.data(), k);
+      hgemm('N', 'N', k, k, n, 1.0, VtDinv.data(), k, c.U.data(), n, 0.0, S.data(), k);
+      if (k > 0 && hinv(k, S.data(), k)) RW_THROW(RW_ESINGULAR, "singular V* D^-1 U in the HBS inverse");
+      HbsNodeGen& g = out.lev[l][j];
+      g.nin = n;
+      g.k = k;
+      g.E.assign((size_t)n * k, 0.0);
+      g.Ft.assign((size_t)k * n, 0.0);
+      hgemm('N', 'N', n, k, k, 1.0, DinvU.data(), n, S.data(), k, 0.0, g.E.data(), n);
+      hgemm('N', 'N', k, n, k, 1.0, S.data(), k, VtDinv.data(), k, 0.0, g.Ft.data(), k);
+      g.G = Dm;
+      hgemm('N', 'N', n, n, k, -1.0, g.E.data(), n, VtDinv.data(), k, 1.0, g.G.data(), n);
+      Dhat[l][j] = std::move(S);
+    }, prm.threads);
+  }
+  out.max_rank = 0;
+  out.entries = (int64_t)out.nroot * out.nroot;
+  for (int l = 1; l <= L; ++l)
+    for (auto& g : out.lev[l]) {
+      out.max_rank = std::max(out.max_rank, g.k);
+      out.entries += (int64_t)g.E.size() + (int64_t)g.Ft.size() + (int64_t)g.G.size();
+    }
+}

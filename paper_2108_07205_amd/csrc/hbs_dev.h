@@ -1,0 +1,39 @@
+// HBS compressed inverse resident in HBM, and its apply (level sweeps).
+// Built either on the host (hbs_build.h, the static reference wall) or on
+// the GPU per refinement (hbs_gpu_build, the refined arc's A_pp).
+#pragma once
+
+#include "hbs_build.h"
+#include "kernels.h"
+
+struct HbsDev {
+  rw_ctx* ctx = nullptr;
+  int L = 0, nroot = 0;
+  std::vector<HbsLevelDev> lev;  // index 1..L
+  std::vector<int64_t> S, K;     // S[l]: level input length; K[l]: sum of skeleton sizes at level l
+  DBuf<int> d_ints;              // nin / k per level
+  DBuf<int64_t> d_offs;          // in_off / kout_off / up_off / e_off per level
+  DBuf<double> gen;              // packed generators: [F*; G] ((k + nin) x nin) and E (nin x k) per node
+  DBuf<float> gen32;             // FP32 copy (optional)
+  DBuf<double> groot;            // G_root (nroot x nroot)
+  int64_t entries = 0;           // sum of |E| + |F| + |G| + |G_root|
+  int max_rank = 0;
+  // apply workspace
+  DBuf<double> ws;
+  int ws_nrhs = 0;
+  std::vector<double*> U, GB, X;
+  int64_t n_unknowns() const { return lev.size() > 1 ? S[L] : 0; }
+};
+
+// Pack a host-built inverse into HBM.
+void hbs_upload(rw_ctx* ctx, const HbsInverse& H, bool with_f32, HbsDev& out);
+// x = A^{-1} b (b, x: n x nrhs column-major with leading dimensions ldb, ldx).
+void hbs_dev_apply(HbsDev& h, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32);
+
+// GPU build of the HBS inverse of the Nystrom matrix of one node set
+// (contiguous arcs, balanced binary tree with leaves of at most leaf_max
+// nodes).  d_nodes: device copy of h_nodes.  Same generator layout as
+// hbs_upload.  Throws RW_ESINGULAR on a singular node block or a rank that
+// exceeds the node sketch.
+void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRec>& h_nodes, int leaf_max,
+                   double tol, uint64_t seed, HbsDev& out);

@@ -1,0 +1,798 @@
+// HBS inverse in HBM: upload of a host-built inverse, the level-sweep apply,
+// and the batched GPU build used per refinement for A_pp (Algorithm 1 step 2:
+// "build an approximate inverse of A_pp via a fast direct solver such as
+// HBS" when the added point count is large).
+//
+// GPU build, per tree level (leaves to root), one workgroup per node:
+//  1. sketch: Y = M Omega (m x 96) of the node's off-diagonal block row
+//     (row ID) and block column (column ID), where M holds the exact kernel
+//     entries to the nodes inside the node's proxy circle and, for everything
+//     outside it, 48 proxy points on that circle (Stokeslet and double-layer
+//     columns / double-layer rows) plus the rank-one nullspace column / flux
+//     row; Omega = +-1 from a counter-based hash.  Entries are generated on the
+//     fly, never stored.
+//  2. row ID of each sketch by pivoted Gram-Schmidt over rows in LDS; the
+//     node rank is the larger of the two tolerance ranks.
+//  3. interpolation matrices U, V and the skeleton lists (the parent's
+//     candidate rows / columns).
+//  4. node inverse: D (leaf block, or [[D^_a, A(Jr_a, Jc_b)], [A(Jr_b, Jc_a),
+//     D^_b]]), D^ = (V* D^-1 U)^-1, E = D^-1 U D^, F* = D^ V* D^-1,
+//     G = D^-1 - D^-1 U D^ V* D^-1; the root stores G_root = D_root^-1.
+#include <algorithm>
+#include <cmath>
+
+#include "hbs_dev.h"
+
+namespace {
+
+constexpr double kInvPi = 0.31830988618379067154;
+constexpr int SK_R = 96;       // sketch columns per node
+constexpr int SK_KCAP = 88;    // largest node rank (sketch columns minus oversampling)
+constexpr int SK_NP = 48;      // proxy points
+constexpr int SK_EXTRA = 16;   // Gram-Schmidt steps past the tolerance rank
+constexpr double SK_RATIO = 2.0;
+
+inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+struct GNode {
+  int64_t n0, n1;       // node range
+  double cx, cy, rp;    // proxy circle
+  int m;                // candidate count (rows = columns = node input size)
+  int k;                // rank (after the ID)
+  int64_t cand_off;     // offset in the level's candidate arrays (= input offset)
+  int64_t uv_off;       // U / V slot (m x k, column-major)
+  int64_t dhat_off;     // D^ (k x k) of this node
+  int64_t ws_off;       // inverse workspace
+  int64_t up_off, e_off;
+};
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// A = -1/2 I + D + N block for target t and source s (w_s folded in).
+__device__ __forceinline__ void a_blk(const NodeRec& t, const NodeRec& s, bool self, double B[4]) {
+  if (self) { B[0] = s.s00; B[1] = s.s01; B[2] = s.s01; B[3] = s.s11; return; }
+  const double rx = t.x - s.x, ry = t.y - s.y;
+  const double r2 = rx * rx + ry * ry;
+  const double cf = (rx * s.nx + ry * s.ny) * s.w * kInvPi / (r2 * r2);
+  B[0] = cf * rx * rx + s.w * t.nx * s.nx;
+  B[1] = cf * rx * ry + s.w * t.nx * s.ny;
+  B[2] = cf * ry * rx + s.w * t.ny * s.nx;
+  B[3] = cf * ry * ry + s.w * t.ny * s.ny;
+}
+
+// ---------------------------------------------------------------- 1. sketch
+// grid (nodes, 2): side 0 = row sketch of candr, side 1 = column sketch of candc.
+// thread t: candidate row (t & 127) of the current pass, columns 48*(t >> 7) ..
+__global__ __launch_bounds__(256) void node_sketch_kernel(const GNode* __restrict__ gn, const int* __restrict__ candr,
+                                                          const int* __restrict__ candc,
+                                                          const NodeRec* __restrict__ nd, int64_t N, uint64_t seed,
+                                                          double* __restrict__ Sr, double* __restrict__ Sc) {
+  const GNode g = gn[blockIdx.x];
+  const int side = blockIdx.y;
+  const int* cand = (side == 0 ? candr : candc) + g.cand_off;
+  double* S = (side == 0 ? Sr : Sc) + g.cand_off * SK_R;
+  const int half = threadIdx.x >> 7, ri = threadIdx.x & 127;
+  const double rp2 = g.rp * g.rp;
+  const double wp = 2.0 * M_PI * g.rp / SK_NP;
+  const uint64_t base = seed * 0x9E3779B97F4A7C15ull;
+  for (int row0 = 0; row0 < g.m; row0 += 128) {
+    const int i = row0 + ri;
+    const bool valid = i < g.m;
+    const int dof = cand[valid ? i : 0];
+    const NodeRec a = nd[dof >> 1];
+    const int ca = dof & 1;
+    double acc[48];
+#pragma unroll
+    for (int c = 0; c < 48; ++c) acc[c] = 0.0;
+    // Entities: near nodes (2 entries each), then -- if any node lies outside
+    // the proxy circle -- the proxy points (side 0: 4 entries, side 1: 2) and
+    // the nullspace column / flux row (1 entry).  Each entry e with Omega row
+    // `pos` is folded into the 48 accumulators by one shared loop.
+    const int64_t n_ent = N + SK_NP + 1;
+    bool any_far = false;
+    for (int64_t j = 0; j < n_ent; ++j) {
+      double e[4];
+      int64_t pos0 = 0;
+      int cnt = 0;
+      if (j < N) {
+        if (j >= g.n0 && j < g.n1) continue;
+        const NodeRec q = nd[j];
+        const double dx = q.x - g.cx, dy = q.y - g.cy;
+        if (dx * dx + dy * dy >= rp2) { any_far = true; continue; }
+        double B[4];
+        if (side == 0) {
+          a_blk(a, q, false, B);                 // A(a, j)
+          e[0] = B[ca * 2 + 0];
+          e[1] = B[ca * 2 + 1];
+        } else {
+          a_blk(q, a, false, B);                 // A(j, a)
+          e[0] = B[0 * 2 + ca];
+          e[1] = B[1 * 2 + ca];
+        }
+        pos0 = 2 * j;
+        cnt = 2;
+      } else if (!any_far) {
+        break;
+      } else if (j < N + SK_NP) {
+        const int l = (int)(j - N);
+        const double th = 2.0 * M_PI * l / SK_NP;
+        const double ux = cos(th), uy = sin(th);
+        const double px = g.cx + g.rp * ux, py = g.cy + g.rp * uy;
+        if (side == 0) {
+          const double rx = a.x - px, ry = a.y - py, r2 = rx * rx + ry * ry;
+          const double lg = -0.125 * kInvPi * log(r2), b = 0.25 * kInvPi / r2;
+          const double rc = ca ? ry : rx;
+          const double cf = (rx * ux + ry * uy) * kInvPi / (r2 * r2) * wp;
+          e[0] = (ca == 0 ? lg : 0.0) + b * rc * rx;   // Stokeslet, source comp 0
+          e[1] = (ca == 1 ? lg : 0.0) + b * rc * ry;   // Stokeslet, source comp 1
+          e[2] = cf * rc * rx;                          // double layer (radial normal)
+          e[3] = cf * rc * ry;
+          cnt = 4;
+        } else {
+          const double rx = px - a.x, ry = py - a.y, r2 = rx * rx + ry * ry;
+          const double cf = (rx * a.nx + ry * a.ny) * a.w * kInvPi / (r2 * r2);
+          const double rd = ca ? ry : rx;
+          e[0] = cf * rx * rd;                          // target comp 0 at the proxy
+          e[1] = cf * ry * rd;                          // target comp 1
+          cnt = 2;
+        }
+        pos0 = 2 * N + 4 * (int64_t)l;
+      } else {
+        e[0] = (side == 0) ? (ca ? a.ny : a.nx) : a.w * (ca ? a.ny : a.nx);
+        pos0 = 2 * N + 4 * (int64_t)SK_NP;
+        cnt = 1;
+      }
+      for (int t = 0; t < cnt; ++t) {
+        const double v = e[t];
+        const uint64_t key = base ^ ((uint64_t)(pos0 + t) * 0xD1B54A32D192ED03ull);
+        const uint64_t h0 = mix64(key);
+        const uint64_t h1 = mix64(key ^ 0x5851F42D4C957F2Dull);
+        // columns 48*half .. 48*half+47 of the 96-bit sign pattern (h0 | h1)
+        const uint64_t lo = half ? ((h0 >> 48) | (h1 << 16)) : h0;
+        const uint64_t hi = half ? (h1 >> 48) : 0;
+        (void)hi;
+#pragma unroll
+        for (int c = 0; c < 48; ++c) acc[c] += ((lo >> c) & 1) ? -v : v;
+      }
+    }
+    if (valid)
+#pragma unroll
+      for (int c = 0; c < 48; ++c) S[(int64_t)i * SK_R + half * 48 + c] = acc[c];
+  }
+}
+
+// ---------------------------------------------------------------- 2. row ID
+// grid (nodes, 2); rows of the sketch in LDS; pivoted Gram-Schmidt (two passes).
+// Outputs per (node, side): piv[SK_KCAP], C (m x SK_KCAP row-major at cand_off*SK_KCAP),
+// info[0] = tolerance rank, info[1] = steps taken.
+__global__ __launch_bounds__(256) void node_id_kernel(const GNode* __restrict__ gn, const double* __restrict__ Sr,
+                                                      const double* __restrict__ Sc, double tol2,
+                                                      int* __restrict__ piv, double* __restrict__ Cr,
+                                                      double* __restrict__ Cc, int* __restrict__ info) {
+  extern __shared__ double sh[];
+  const GNode g = gn[blockIdx.x];
+  const int side = blockIdx.y;
+  const int m = g.m, tid = threadIdx.x;
+  const double* S = (side == 0 ? Sr : Sc) + g.cand_off * SK_R;
+  double* C = (side == 0 ? Cr : Cc) + g.cand_off * SK_KCAP;
+  int* pv = piv + ((int64_t)blockIdx.x * 2 + side) * SK_KCAP;
+  constexpr int LD = SK_R + 1;
+  double* Y = sh;                    // m x LD
+  double* q = Y + m * LD;            // SK_R
+  double* rn = q + SK_R;             // m
+  double* rv = rn + m;               // 256
+  int* ri = (int*)(rv + 256);        // 256
+  for (int idx = tid; idx < m * SK_R; idx += 256) Y[(idx / SK_R) * LD + idx % SK_R] = S[idx];
+  __syncthreads();
+  for (int i = tid; i < m; i += 256) {
+    double s = 0;
+    for (int c = 0; c < SK_R; ++c) s += Y[i * LD + c] * Y[i * LD + c];
+    rn[i] = s;
+  }
+  __syncthreads();
+  double n0 = 0;
+  int rank = -1, step = 0;
+  const int kmax = min(SK_KCAP, m);
+  for (; step < kmax; ++step) {
+    double bv = -1.0;
+    int bi = -1;
+    for (int i = tid; i < m; i += 256)
+      if (rn[i] > bv || (rn[i] == bv && bi >= 0 && i < bi)) { bv = rn[i]; bi = i; }
+    rv[tid] = bv;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) {
+        const double v2 = rv[tid + w];
+        const int i2 = ri[tid + w];
+        if (i2 >= 0 && (v2 > rv[tid] || (v2 == rv[tid] && (ri[tid] < 0 || i2 < ri[tid])))) { rv[tid] = v2; ri[tid] = i2; }
+      }
+      __syncthreads();
+    }
+    const double v = rv[0];
+    const int p = ri[0];
+    __syncthreads();
+    if (step == 0) n0 = v;
+    if (rank < 0 && !(v > tol2 * n0)) rank = step;
+    if ((rank >= 0 && step >= rank + SK_EXTRA) || p < 0 || !(v > 0.0)) break;
+    const double inv = 1.0 / sqrt(v);
+    for (int c = tid; c < SK_R; c += 256) q[c] = Y[p * LD + c] * inv;
+    __syncthreads();
+    if (tid == 0) pv[step] = p;
+    for (int i = tid; i < m; i += 256) {
+      double* row = Y + i * LD;
+      double cf = 0;
+      for (int pass = 0; pass < 2; ++pass) {
+        double d = 0;
+        for (int c = 0; c < SK_R; ++c) d += row[c] * q[c];
+        for (int c = 0; c < SK_R; ++c) row[c] -= d * q[c];
+        cf += d;
+      }
+      C[(int64_t)i * SK_KCAP + step] = cf;
+      if (rn[i] >= 0.0) {
+        double s = 0;
+        for (int c = 0; c < SK_R; ++c) s += row[c] * row[c];
+        rn[i] = (i == p) ? -1.0 : s;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    info[(blockIdx.x * 2 + side) * 2] = rank < 0 ? step : rank;
+    info[(blockIdx.x * 2 + side) * 2 + 1] = step;
+  }
+}
+
+// ---------------------------------------------------------------- 3. interpolation
+// grid (nodes, 2).  P = C(:, 0:k) C_J^{-1} -> U (side 0) or V (side 1), m x k
+// column-major; the skeleton dofs go to the parent's candidate list.
+__global__ __launch_bounds__(256) void node_interp_kernel(const GNode* __restrict__ gn, const int* __restrict__ candr,
+                                                          const int* __restrict__ candc, const int* __restrict__ piv,
+                                                          const double* __restrict__ Cr, const double* __restrict__ Cc,
+                                                          double* __restrict__ U, double* __restrict__ V,
+                                                          const int64_t* __restrict__ par_pos,
+                                                          int* __restrict__ pcandr, int* __restrict__ pcandc) {
+  extern __shared__ double iv[];  // k x k: iv[s * k + t] = Inv(s, t)
+  const GNode g = gn[blockIdx.x];
+  const int side = blockIdx.y;
+  const int k = g.k, m = g.m, tid = threadIdx.x;
+  const int* pv = piv + ((int64_t)blockIdx.x * 2 + side) * SK_KCAP;
+  const double* C = (side == 0 ? Cr : Cc) + g.cand_off * SK_KCAP;
+  double* P = (side == 0 ? U : V) + g.uv_off;
+  for (int idx = tid; idx < k * k; idx += 256) iv[idx] = 0.0;
+  __syncthreads();
+  if (tid < k) {
+    const int t = tid;
+    for (int s = t; s < k; ++s) {
+      const double* cs = C + (int64_t)pv[s] * SK_KCAP;
+      double v = (s == t) ? 1.0 : 0.0;
+      for (int u = t; u < s; ++u) v -= cs[u] * iv[u * k + t];
+      iv[s * k + t] = v / cs[s];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < m; i += 256) {
+    const double* ci = C + (int64_t)i * SK_KCAP;
+    for (int t = 0; t < k; ++t) {
+      double v = 0;
+      for (int s = t; s < k; ++s) v += ci[s] * iv[s * k + t];
+      P[i + (int64_t)t * m] = v;
+    }
+  }
+  __syncthreads();
+  for (int s = tid; s < k; s += 256) {
+    const int p = pv[s];
+    for (int t = 0; t < k; ++t) P[p + (int64_t)t * m] = (t == s) ? 1.0 : 0.0;
+  }
+  if (par_pos) {
+    const int* cand = (side == 0 ? candr : candc) + g.cand_off;
+    int* pc = (side == 0 ? pcandr : pcandc) + par_pos[blockIdx.x];
+    for (int s = tid; s < k; s += 256) pc[s] = cand[pv[s]];
+  }
+}
+
+// ---------------------------------------------------------------- 4. inverse
+// One workgroup: in-place Gauss-Jordan inverse with partial pivoting of
+// A (n x n, ld n) into Inv; returns false on a zero / non-finite pivot.
+__device__ bool wg_inverse(double* A, double* Inv, int n, double* rv, int* ri) {
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < n * n; idx += 256) Inv[idx] = ((idx % n) == (idx / n)) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    double bv = -1.0;
+    int bi = -1;
+    for (int i = j + tid; i < n; i += 256) {
+      const double v = fabs(A[i + (int64_t)j * n]);
+      if (v > bv) { bv = v; bi = i; }
+    }
+    rv[tid] = bv;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w && ri[tid + w] >= 0 && (rv[tid + w] > rv[tid] || (rv[tid + w] == rv[tid] && ri[tid + w] < ri[tid]))) {
+        rv[tid] = rv[tid + w];
+        ri[tid] = ri[tid + w];
+      }
+      __syncthreads();
+    }
+    const int p = ri[0];
+    const double pvabs = rv[0];
+    __syncthreads();
+    if (p < 0 || !(pvabs > 0.0) || !isfinite(pvabs)) return false;
+    if (p != j)
+      for (int c = tid; c < n; c += 256) {
+        double t = A[j + (int64_t)c * n]; A[j + (int64_t)c * n] = A[p + (int64_t)c * n]; A[p + (int64_t)c * n] = t;
+        t = Inv[j + (int64_t)c * n]; Inv[j + (int64_t)c * n] = Inv[p + (int64_t)c * n]; Inv[p + (int64_t)c * n] = t;
+      }
+    __syncthreads();
+    const double sc = 1.0 / A[j + (int64_t)j * n];
+    __syncthreads();
+    for (int c = tid; c < n; c += 256) {
+      A[j + (int64_t)c * n] *= sc;
+      Inv[j + (int64_t)c * n] *= sc;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < n * n; idx += 256) {
+      const int i = idx % n, c = idx / n;
+      if (i == j) continue;
+      const double f = A[i + (int64_t)j * n];
+      if (c != j) A[i + (int64_t)c * n] -= f * A[j + (int64_t)c * n];
+      Inv[i + (int64_t)c * n] -= f * Inv[j + (int64_t)c * n];
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += 256)
+      if (i != j) A[i + (int64_t)j * n] = 0.0;
+    __syncthreads();
+  }
+  return true;
+}
+
+// C (m x n, ldc) = alpha op(A) op(B) + beta C, all column-major, one workgroup.
+__device__ void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda,
+                        const double* B, int ldb, double beta, double* C, int ldc) {
+  for (int idx = threadIdx.x; idx < m * n; idx += 256) {
+    const int i = idx % m, j = idx / m;
+    double s = 0;
+    for (int l = 0; l < k; ++l) {
+      const double a = ta ? A[l + (int64_t)i * lda] : A[i + (int64_t)l * lda];
+      const double b = tb ? B[j + (int64_t)l * ldb] : B[l + (int64_t)j * ldb];
+      s += a * b;
+    }
+    C[i + (int64_t)j * ldc] = alpha * s + (beta == 0.0 ? 0.0 : beta * C[i + (int64_t)j * ldc]);
+  }
+  __syncthreads();
+}
+
+// grid (nodes).  leaf: D = A(candr, candc); parent: children's D^ on the
+// diagonal, kernel blocks between the children's skeletons off it.
+// root (is_root): writes D^-1 to G_root only.
+__global__ __launch_bounds__(256) void node_inverse_kernel(const GNode* __restrict__ gn, const GNode* __restrict__ gch,
+                                                           int is_leaf, int is_root, const int* __restrict__ candr,
+                                                           const int* __restrict__ candc,
+                                                           const NodeRec* __restrict__ nd, const double* __restrict__ U,
+                                                           const double* __restrict__ V,
+                                                           const double* __restrict__ dhat_ch, double* __restrict__ dhat,
+                                                           double* __restrict__ ws, double* __restrict__ gen,
+                                                           double* __restrict__ groot, int* __restrict__ fail) {
+  __shared__ double rv[256];
+  __shared__ int ri[256];
+  const GNode g = gn[blockIdx.x];
+  const int n = g.m, k = g.k, tid = threadIdx.x;
+  const int* cr = candr + g.cand_off;
+  const int* cc = candc + g.cand_off;
+  double* Dm = ws + g.ws_off;          // n x n
+  double* Inv = Dm + (int64_t)n * n;   // n x n
+  // assemble D
+  if (is_leaf) {
+    for (int idx = tid; idx < n * n; idx += 256) {
+      const int i = idx % n, j = idx / n;
+      const int ra = cr[i], cb = cc[j];
+      double B[4];
+      a_blk(nd[ra >> 1], nd[cb >> 1], (ra >> 1) == (cb >> 1), B);
+      Dm[idx] = B[(ra & 1) * 2 + (cb & 1)];
+    }
+  } else {
+    const GNode ca = gch[2 * blockIdx.x], cbn = gch[2 * blockIdx.x + 1];
+    const int ka = ca.k, kb = cbn.k;
+    const double* Da = dhat_ch + ca.dhat_off;
+    const double* Db = dhat_ch + cbn.dhat_off;
+    for (int idx = tid; idx < n * n; idx += 256) {
+      const int i = idx % n, j = idx / n;
+      double v;
+      if (i < ka && j < ka) v = Da[i + j * ka];
+      else if (i >= ka && j >= ka) v = Db[(i - ka) + (j - ka) * kb];
+      else {
+        const int ra = cr[i], cb = cc[j];
+        double B[4];
+        a_blk(nd[ra >> 1], nd[cb >> 1], false, B);
+        v = B[(ra & 1) * 2 + (cb & 1)];
+      }
+      Dm[idx] = v;
+    }
+  }
+  __syncthreads();
+  if (!wg_inverse(Dm, Inv, n, rv, ri)) {
+    if (tid == 0) atomicExch(fail, 1);
+    return;
+  }
+  if (is_root) {
+    for (int idx = tid; idx < n * n; idx += 256) groot[idx] = Inv[idx];
+    return;
+  }
+  const double* Un = U + g.uv_off;
+  const double* Vn = V + g.uv_off;
+  double* DinvU = Inv + (int64_t)n * n;        // n x k (after D and D^-1)
+  double* VtDinv = DinvU + (int64_t)n * k;     // k x n
+  double* Sm = VtDinv + (int64_t)k * n;        // k x k
+  double* Si = Sm + (int64_t)k * k;            // k x k
+  wg_gemm(false, false, n, k, n, 1.0, Inv, n, Un, n, 0.0, DinvU, n);
+  wg_gemm(true, false, k, n, n, 1.0, Vn, n, Inv, n, 0.0, VtDinv, k);
+  wg_gemm(false, false, k, k, n, 1.0, VtDinv, k, Un, n, 0.0, Sm, k);
+  if (!wg_inverse(Sm, Si, k, rv, ri)) {
+    if (tid == 0) atomicExch(fail, 2);
+    return;
+  }
+  double* up = gen + g.up_off;                 // (k + n) x n
+  double* E = gen + g.e_off;                   // n x k
+  const int rows = k + n;
+  wg_gemm(false, false, n, k, k, 1.0, DinvU, n, Si, k, 0.0, E, n);
+  wg_gemm(false, false, k, n, k, 1.0, Si, k, VtDinv, k, 0.0, up, rows);     // F* into rows 0..k-1
+  for (int idx = tid; idx < n * n; idx += 256) {
+    const int i = idx % n, j = idx / n;
+    up[k + i + (int64_t)j * rows] = Inv[idx];
+  }
+  __syncthreads();
+  wg_gemm(false, false, n, n, k, -1.0, E, n, VtDinv, k, 1.0, up + k, rows); // G = Inv - E V* D^-1
+  for (int idx = tid; idx < k * k; idx += 256) dhat[g.dhat_off + idx] = Si[idx];
+}
+
+}  // namespace
+
+// ================================================================== upload / apply
+void hbs_upload(rw_ctx* ctx, const HbsInverse& H, bool with_f32, HbsDev& w) {
+  hipStream_t s = ctx->stream;
+  w.ctx = ctx;
+  w.L = H.L;
+  w.nroot = H.nroot;
+  w.lev.assign(w.L + 1, HbsLevelDev());
+  w.S.assign(w.L + 2, 0);
+  w.K.assign(w.L + 2, 0);
+  std::vector<int> ints;
+  std::vector<int64_t> offs;
+  std::vector<double> gen;
+  std::vector<size_t> int_base(w.L + 1), off_base(w.L + 1);
+  for (int l = 1; l <= w.L; ++l) {
+    const auto& nodes = H.lev[l];
+    const int nn = (int)nodes.size();
+    int_base[l] = ints.size();
+    off_base[l] = offs.size();
+    for (int j = 0; j < nn; ++j) ints.push_back(nodes[j].nin);
+    for (int j = 0; j < nn; ++j) ints.push_back(nodes[j].k);
+    int64_t in_off = 0, k_off = 0;
+    std::vector<int64_t> io(nn), ko(nn), uo(nn), eo(nn);
+    int max_nin = 0, max_k = 0;
+    for (int j = 0; j < nn; ++j) {
+      const HbsNodeGen& g = nodes[j];
+      io[j] = in_off;
+      ko[j] = k_off;
+      in_off += g.nin;
+      k_off += g.k;
+      max_nin = std::max(max_nin, g.nin);
+      max_k = std::max(max_k, g.k);
+      uo[j] = (int64_t)gen.size();
+      const int rows = g.k + g.nin;
+      gen.resize(gen.size() + (size_t)rows * g.nin);
+      double* up = gen.data() + uo[j];
+      for (int c = 0; c < g.nin; ++c) {
+        for (int r = 0; r < g.k; ++r) up[r + (size_t)c * rows] = g.Ft[r + (size_t)c * g.k];
+        for (int r = 0; r < g.nin; ++r) up[g.k + r + (size_t)c * rows] = g.G[r + (size_t)c * g.nin];
+      }
+      eo[j] = (int64_t)gen.size();
+      gen.insert(gen.end(), g.E.begin(), g.E.end());
+    }
+    offs.insert(offs.end(), io.begin(), io.end());
+    offs.insert(offs.end(), ko.begin(), ko.end());
+    offs.insert(offs.end(), uo.begin(), uo.end());
+    offs.insert(offs.end(), eo.begin(), eo.end());
+    HbsLevelDev& d = w.lev[l];
+    d.nnodes = nn;
+    d.max_nin = max_nin;
+    d.max_k = max_k;
+    d.S = in_off;
+    d.K = k_off;
+    w.S[l] = in_off;
+    w.K[l] = k_off;
+  }
+  w.S[0] = w.nroot;
+  w.d_ints.alloc(ctx, ints.size());
+  w.d_ints.upload(ints.data(), ints.size(), s);
+  w.d_offs.alloc(ctx, offs.size());
+  w.d_offs.upload(offs.data(), offs.size(), s);
+  w.gen.alloc(ctx, gen.size());
+  w.gen.upload(gen.data(), gen.size(), s);
+  if (with_f32) {
+    std::vector<float> g32(gen.begin(), gen.end());
+    w.gen32.alloc(ctx, g32.size());
+    w.gen32.upload(g32.data(), g32.size(), s);
+    HIP_CHECK(hipStreamSynchronize(s));
+  }
+  w.groot.alloc(ctx, H.Groot.size());
+  w.groot.upload(H.Groot.data(), H.Groot.size(), s);
+  for (int l = 1; l <= w.L; ++l) {
+    HbsLevelDev& d = w.lev[l];
+    const int nn = d.nnodes;
+    d.nin = w.d_ints.p + int_base[l];
+    d.k = w.d_ints.p + int_base[l] + nn;
+    d.in_off = w.d_offs.p + off_base[l];
+    d.kout_off = w.d_offs.p + off_base[l] + nn;
+    d.up_off = w.d_offs.p + off_base[l] + 2 * nn;
+    d.e_off = w.d_offs.p + off_base[l] + 3 * nn;
+  }
+  HIP_CHECK(hipStreamSynchronize(s));
+  w.entries = H.entries;
+  w.max_rank = H.max_rank;
+}
+
+static void hbs_ensure_ws(HbsDev& w, int nrhs) {
+  if (nrhs <= w.ws_nrhs) return;
+  int64_t tot = 0;
+  for (int l = 1; l <= w.L; ++l) tot += w.K[l] + w.S[l];
+  for (int l = 0; l < w.L; ++l) tot += w.S[l];
+  w.ws.alloc(w.ctx, (size_t)tot * nrhs);
+  w.U.assign(w.L + 1, nullptr);
+  w.GB.assign(w.L + 1, nullptr);
+  w.X.assign(w.L + 1, nullptr);
+  double* p = w.ws.p;
+  for (int l = 1; l <= w.L; ++l) { w.U[l] = p; p += w.K[l] * nrhs; w.GB[l] = p; p += w.S[l] * nrhs; }
+  for (int l = 0; l < w.L; ++l) { w.X[l] = p; p += w.S[l] * nrhs; }
+  w.ws_nrhs = nrhs;
+}
+
+void hbs_dev_apply(HbsDev& w, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32) {
+  if (nrhs <= 0) return;
+  hbs_ensure_ws(w, nrhs);
+  hipStream_t s = w.ctx->stream;
+  const bool f32 = use_f32 && w.gen32.p;
+  for (int l = w.L; l >= 1; --l) {
+    const double* in = (l == w.L) ? b : w.U[l + 1];
+    const int64_t ldin = (l == w.L) ? ldb : w.K[l + 1];
+    if (f32)
+      launch_hbs_up_f32(w.lev[l], w.gen32.p, in, ldin, w.U[l], w.K[l], w.GB[l], w.S[l], nrhs, s);
+    else
+      launch_hbs_up(w.lev[l], w.gen.p, in, ldin, w.U[l], w.K[l], w.GB[l], w.S[l], nrhs, s);
+  }
+  launch_hbs_root(w.nroot, w.groot.p, w.U[1], w.K[1], w.X[0], w.S[0], nrhs, s);
+  for (int l = 1; l <= w.L; ++l) {
+    double* out = (l == w.L) ? x : w.X[l];
+    const int64_t ldout = (l == w.L) ? ldx : w.S[l];
+    if (f32)
+      launch_hbs_down_f32(w.lev[l], w.gen32.p, w.X[l - 1], w.S[l - 1], w.GB[l], w.S[l], out, ldout, nrhs, s);
+    else
+      launch_hbs_down(w.lev[l], w.gen.p, w.X[l - 1], w.S[l - 1], w.GB[l], w.S[l], out, ldout, nrhs, s);
+  }
+}
+
+// ================================================================== GPU build
+void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRec>& hn, int leaf_max, double tol,
+                   uint64_t seed, HbsDev& w) {
+  hipStream_t s = ctx->stream;
+  const int64_t N = (int64_t)hn.size();
+  if (N < 2) RW_THROW(RW_EINVAL, "HBS build needs at least two nodes");
+  int L = 1;
+  while ((N >> L) > leaf_max) ++L;
+  if (2 * ((N + (int64_t(1) << L) - 1) >> L) > 2 * leaf_max + 2) RW_THROW(RW_EINVAL, "leaf size");
+  // ---- level plans (ranges, proxy circles)
+  std::vector<std::vector<GNode>> G(L + 1);
+  for (int l = 0; l <= L; ++l) {
+    const int64_t nn = int64_t(1) << l;
+    G[l].resize(nn);
+    for (int64_t j = 0; j < nn; ++j) {
+      GNode& g = G[l][j];
+      memset(&g, 0, sizeof g);
+      g.n0 = (j * N) >> l;
+      g.n1 = ((j + 1) * N) >> l;
+      double cx = 0, cy = 0;
+      for (int64_t i = g.n0; i < g.n1; ++i) { cx += hn[i].x; cy += hn[i].y; }
+      cx /= double(g.n1 - g.n0);
+      cy /= double(g.n1 - g.n0);
+      double R = 0;
+      for (int64_t i = g.n0; i < g.n1; ++i) R = std::max(R, std::hypot(hn[i].x - cx, hn[i].y - cy));
+      g.cx = cx;
+      g.cy = cy;
+      g.rp = SK_RATIO * R;
+      if (l == L) g.m = (int)(2 * (g.n1 - g.n0));
+    }
+  }
+  // ---- buffers sized by the bounds m <= max(2 leaf_max, 2 SK_KCAP), k <= SK_KCAP
+  const int mmax = std::max(2 * leaf_max + 2, 2 * SK_KCAP);
+  int64_t cap_total = 0, gen_bound = 0;
+  for (int l = 1; l <= L; ++l) {
+    const int64_t nn = int64_t(1) << l;
+    const int64_t mb = (l == L) ? 2 * ((N + nn - 1) / nn) : 2 * SK_KCAP;
+    cap_total = std::max(cap_total, nn * mb);
+    gen_bound += nn * ((SK_KCAP + mb) * mb + mb * SK_KCAP);
+  }
+  DBuf<GNode> dg(ctx, (size_t)(int64_t(2) << L));
+  DBuf<int> candr(ctx, cap_total), candc(ctx, cap_total), pcandr(ctx, cap_total), pcandc(ctx, cap_total);
+  DBuf<double> Sr(ctx, cap_total * SK_R), Sc(ctx, cap_total * SK_R);
+  DBuf<double> Cr(ctx, cap_total * SK_KCAP), Cc(ctx, cap_total * SK_KCAP);
+  DBuf<int> piv(ctx, (size_t)(int64_t(2) << L) * SK_KCAP), info(ctx, (size_t)(int64_t(4) << L)), fail(ctx, 4);
+  DBuf<double> Ub(ctx, cap_total * SK_KCAP), Vb(ctx, cap_total * SK_KCAP);
+  DBuf<double> dhA(ctx, (int64_t(1) << L) * SK_KCAP * SK_KCAP), dhB(ctx, (int64_t(1) << L) * SK_KCAP * SK_KCAP);
+  DBuf<double> ws(ctx, (int64_t(1) << L) * (int64_t)mmax * mmax * 2);
+  DBuf<int64_t> dpar(ctx, (size_t)(int64_t(1) << L));
+  w.gen.alloc(ctx, gen_bound);
+  HIP_CHECK(hipMemsetAsync(fail.p, 0, sizeof(int) * 4, s));
+  // leaf candidate lists: all dofs of the range
+  {
+    std::vector<int> c;
+    c.reserve(2 * N);
+    for (int64_t d = 0; d < 2 * N; ++d) c.push_back((int)d);
+    candr.upload(c.data(), c.size(), s);
+    candc.upload(c.data(), c.size(), s);
+    HIP_CHECK(hipStreamSynchronize(s));
+  }
+  w.ctx = ctx;
+  w.L = L;
+  w.lev.assign(L + 1, HbsLevelDev());
+  w.S.assign(L + 2, 0);
+  w.K.assign(L + 2, 0);
+  std::vector<std::vector<int>> lev_ints(L + 1);
+  std::vector<std::vector<int64_t>> lev_offs(L + 1);
+  int64_t gen_used = 0;
+  w.entries = 0;
+  w.max_rank = 0;
+  double* dh_child = dhB.p;
+  double* dh_cur = dhA.p;
+  for (int l = L; l >= 1; --l) {
+    const int nn = 1 << l;
+    std::vector<GNode>& gl = G[l];
+    int64_t off = 0;
+    int mx = 0;
+    for (int j = 0; j < nn; ++j) { gl[j].cand_off = off; off += gl[j].m; mx = std::max(mx, gl[j].m); }
+    if (mx > mmax) RW_THROW(RW_ESINGULAR, "HBS node input exceeds the sketch bound");
+    dg.upload(gl.data(), nn, s);
+    hipLaunchKernelGGL(node_sketch_kernel, dim3(nn, 2), dim3(256), 0, s, dg.p, candr.p, candc.p, d_nodes, N,
+                       seed + 7919ull * l, Sr.p, Sc.p);
+    KERNEL_CHECK("node_sketch");
+    const size_t sh = sizeof(double) * ((size_t)mx * (SK_R + 1) + SK_R + mx + 256) + sizeof(int) * 256;
+    HIP_CHECK(hipFuncSetAttribute((const void*)node_id_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+    hipLaunchKernelGGL(node_id_kernel, dim3(nn, 2), dim3(256), sh, s, dg.p, Sr.p, Sc.p, tol * tol, piv.p, Cr.p, Cc.p,
+                       info.p);
+    KERNEL_CHECK("node_id");
+    std::vector<int> hinfo(4 * nn);
+    info.download(hinfo.data(), hinfo.size(), s);
+    HIP_CHECK(hipStreamSynchronize(s));
+    // ranks and offsets
+    int64_t uv = 0, dho = 0, wso = 0;
+    for (int j = 0; j < nn; ++j) {
+      const int kr = hinfo[4 * j], sr = hinfo[4 * j + 1], kc = hinfo[4 * j + 2], sc = hinfo[4 * j + 3];
+      int k = std::max(kr, kc);
+      k = std::min(k, std::min(sr, sc));
+      if (std::max(kr, kc) >= SK_KCAP) RW_THROW(RW_ESINGULAR, "HBS node rank reached the sketch size");
+      GNode& g = gl[j];
+      g.k = k;
+      g.uv_off = uv;
+      uv += (int64_t)g.m * k;
+      g.dhat_off = dho;
+      dho += (int64_t)k * k;
+      g.ws_off = wso;
+      wso += 2 * (int64_t)g.m * g.m + 2 * (int64_t)g.m * k + 2 * (int64_t)k * k;
+      g.up_off = gen_used;
+      gen_used += (int64_t)(k + g.m) * g.m;
+      g.e_off = gen_used;
+      gen_used += (int64_t)g.m * k;
+      w.max_rank = std::max(w.max_rank, k);
+      w.entries += 2 * (int64_t)g.m * k + (int64_t)g.m * g.m;
+    }
+    if (gen_used > (int64_t)w.gen.n) RW_THROW(RW_ESINGULAR, "HBS generator bound exceeded");
+    // parent candidate sizes and positions of each child's skeleton in them
+    std::vector<int64_t> ppos(nn);
+    if (l >= 1) {
+      int64_t po = 0;
+      for (int pj = 0; pj < nn / 2; ++pj) {
+        ppos[2 * pj] = po;
+        ppos[2 * pj + 1] = po + gl[2 * pj].k;
+        G[l - 1][pj].m = gl[2 * pj].k + gl[2 * pj + 1].k;
+        po += G[l - 1][pj].m;
+      }
+      dpar.upload(ppos.data(), nn, s);
+    }
+    dg.upload(gl.data(), nn, s);
+    const size_t shi = sizeof(double) * SK_KCAP * SK_KCAP;
+    HIP_CHECK(hipFuncSetAttribute((const void*)node_interp_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shi));
+    hipLaunchKernelGGL(node_interp_kernel, dim3(nn, 2), dim3(256), shi, s, dg.p, candr.p, candc.p, piv.p, Cr.p, Cc.p,
+                       Ub.p, Vb.p, dpar.p, pcandr.p, pcandc.p);
+    KERNEL_CHECK("node_interp");
+    // children (level l + 1) descriptors for the parent assembly
+    DBuf<GNode> dch;
+    if (l < L) {
+      dch.alloc(ctx, (size_t)(2 * nn));
+      dch.upload(G[l + 1].data(), 2 * nn, s);
+    }
+    if (ws.n < (size_t)wso) ws.alloc(ctx, wso);
+    hipLaunchKernelGGL(node_inverse_kernel, dim3(nn), dim3(256), 0, s, dg.p, l < L ? dch.p : dg.p, l == L ? 1 : 0, 0,
+                       candr.p, candc.p, d_nodes, Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, (double*)nullptr, fail.p);
+    KERNEL_CHECK("node_inverse");
+    // level descriptors for the apply
+    std::vector<int>& li = lev_ints[l];
+    std::vector<int64_t>& lo = lev_offs[l];
+    li.resize(2 * nn);
+    lo.resize(4 * nn);
+    int64_t kk = 0;
+    int max_nin = 0, max_k = 0;
+    for (int j = 0; j < nn; ++j) {
+      li[j] = gl[j].m;
+      li[nn + j] = gl[j].k;
+      lo[j] = gl[j].cand_off;
+      lo[nn + j] = kk;
+      kk += gl[j].k;
+      lo[2 * nn + j] = gl[j].up_off;
+      lo[3 * nn + j] = gl[j].e_off;
+      max_nin = std::max(max_nin, gl[j].m);
+      max_k = std::max(max_k, gl[j].k);
+    }
+    HbsLevelDev& d = w.lev[l];
+    d.nnodes = nn;
+    d.max_nin = max_nin;
+    d.max_k = max_k;
+    d.S = off;
+    d.K = kk;
+    w.S[l] = off;
+    w.K[l] = kk;
+    HIP_CHECK(hipStreamSynchronize(s));
+    std::swap(candr, pcandr);
+    std::swap(candc, pcandc);
+    std::swap(dh_child, dh_cur);
+  }
+  // ---- root
+  {
+    GNode& g = G[0][0];
+    g.cand_off = 0;
+    g.k = 0;
+    g.ws_off = 0;
+    w.nroot = g.m;
+    w.S[0] = g.m;
+    dg.upload(&g, 1, s);
+    DBuf<GNode> dch(ctx, 2);
+    dch.upload(G[1].data(), 2, s);
+    w.groot.alloc(ctx, (size_t)g.m * g.m);
+    hipLaunchKernelGGL(node_inverse_kernel, dim3(1), dim3(256), 0, s, dg.p, dch.p, 0, 1, candr.p, candc.p, d_nodes,
+                       Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, w.groot.p, fail.p);
+    KERNEL_CHECK("node_inverse_root");
+    w.entries += (int64_t)g.m * g.m;
+    int hf[4];
+    fail.download(hf, 4, s);
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (hf[0]) RW_THROW(RW_ESINGULAR, "singular block in the GPU HBS build (" + std::to_string(hf[0]) + ")");
+  }
+  // ---- pack level descriptors
+  std::vector<int> ints;
+  std::vector<int64_t> offs;
+  std::vector<size_t> ib(L + 1), ob(L + 1);
+  for (int l = 1; l <= L; ++l) {
+    ib[l] = ints.size();
+    ob[l] = offs.size();
+    ints.insert(ints.end(), lev_ints[l].begin(), lev_ints[l].end());
+    offs.insert(offs.end(), lev_offs[l].begin(), lev_offs[l].end());
+  }
+  w.d_ints.alloc(ctx, ints.size());
+  w.d_ints.upload(ints.data(), ints.size(), s);
+  w.d_offs.alloc(ctx, offs.size());
+  w.d_offs.upload(offs.data(), offs.size(), s);
+  for (int l = 1; l <= L; ++l) {
+    HbsLevelDev& d = w.lev[l];
+    const int nn = d.nnodes;
+    d.nin = w.d_ints.p + ib[l];
+    d.k = w.d_ints.p + ib[l] + nn;
+    d.in_off = w.d_offs.p + ob[l];
+    d.kout_off = w.d_offs.p + ob[l] + nn;
+    d.up_off = w.d_offs.p + ob[l] + 2 * nn;
+    d.e_off = w.d_offs.p + ob[l] + 3 * nn;
+  }
+  HIP_CHECK(hipStreamSynchronize(s));
+}

@@ -1,0 +1,702 @@
+// Dense FP64 linear algebra on gfx950 for the refinement pre-computation
+// (Algorithm 1 steps 1-4) and the Woodbury solve:
+//  * row interpolative decomposition (Definition 3.1) of a tall sketch by
+//    column-pivoted Gram-Schmidt over rows, one cooperative kernel with a
+//    grid barrier per pivot; interpolation P = C C_J^{-1};
+//  * tall-skinny products A^T B (W = I + R X, z = R y), Y -= X W;
+//  * Gauss-Jordan inverse with partial pivoting of the small Woodbury
+//    operator W (always FP64);
+//  * blocked right-looking LU without pivoting of A_pp with the trailing
+//    update on the FP64 matrix cores, and blocked triangular solves.
+#include <hip/hip_cooperative_groups.h>
+
+#include "kernels.h"
+
+namespace cg = cooperative_groups;
+
+namespace {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+// ================================================================ row ID
+struct RowIdArgs {
+  const double* Y;
+  int64_t m;
+  int ncols;
+  double tol2;         // tol^2 (squared row norms are compared)
+  int kmax;
+  int rows_per;        // rows owned by one workgroup
+  int lds_rows;        // 1 if the owned rows live in LDS
+  double* Yw;          // global working copy (used when lds_rows == 0)
+  int* J;
+  double* C;           // m x kmax row-major
+  double* slot_norm;   // 2 * G
+  int64_t* slot_idx;   // 2 * G
+  double* slot_vec;    // 2 * G * ncols
+  int* out_k;
+};
+
+__device__ __forceinline__ bool better(double v1, int64_t i1, double v2, int64_t i2) {
+  if (i1 < 0) return false;
+  if (i2 < 0) return true;
+  return (v1 > v2) || (v1 == v2 && i1 < i2);
+}
+
+__global__ __launch_bounds__(256) void rowid_kernel(RowIdArgs a) {
+  extern __shared__ double sh[];
+  cg::grid_group grid = cg::this_grid();
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  const int NC = a.ncols;
+  const int64_t r0 = (int64_t)g * a.rows_per;
+  const int nloc = (int)max<int64_t>(0, min<int64_t>(a.rows_per, a.m - r0));
+  const int stride = a.lds_rows ? NC + 1 : NC;
+  double* rows = a.lds_rows ? sh : a.Yw + r0 * NC;
+  double* q = sh + (a.lds_rows ? (size_t)a.rows_per * (NC + 1) : 0);
+  double* rn = q + NC;                 // rows_per squared norms (-1 = selected)
+  double* redv = rn + a.rows_per;      // 256
+  int64_t* redi = (int64_t*)(redv + 256);  // 256
+  int* redb = (int*)(redi + 256);      // 256
+
+  for (int idx = tid; idx < nloc * NC; idx += 256) {
+    const int i = idx / NC, c = idx - i * NC;
+    rows[i * stride + c] = a.Y[(r0 + i) * NC + c];
+  }
+  __syncthreads();
+  for (int i = tid; i < nloc; i += 256) {
+    double s = 0;
+    for (int c = 0; c < NC; ++c) s += rows[i * stride + c] * rows[i * stride + c];
+    rn[i] = s;
+  }
+  __syncthreads();
+  double nrm0 = 0.0;
+  int k = 0;
+  for (int step = 0; step < a.kmax; ++step) {
+    // ---- local argmax
+    double bv = -1.0;
+    int64_t bi = -1;
+    for (int i = tid; i < nloc; i += 256)
+      if (rn[i] >= 0.0 && better(rn[i], r0 + i, bv, bi)) { bv = rn[i]; bi = r0 + i; }
+    redv[tid] = bv;
+    redi[tid] = bi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w && better(redv[tid + w], redi[tid + w], redv[tid], redi[tid])) {
+        redv[tid] = redv[tid + w];
+        redi[tid] = redi[tid + w];
+      }
+      __syncthreads();
+    }
+    const int par = step & 1;
+    const int64_t lbest = redi[0];
+    if (tid == 0) {
+      a.slot_norm[par * G + g] = redv[0];
+      a.slot_idx[par * G + g] = lbest;
+    }
+    for (int c = tid; c < NC; c += 256)
+      a.slot_vec[((size_t)par * G + g) * NC + c] = (lbest >= 0) ? rows[(lbest - r0) * stride + c] : 0.0;
+    __threadfence();
+    grid.sync();
+    // ---- global argmax (identical in every workgroup)
+    bv = -1.0;
+    bi = -1;
+    int bb = -1;
+    for (int s = tid; s < G; s += 256) {
+      const double v = a.slot_norm[par * G + s];
+      const int64_t i = a.slot_idx[par * G + s];
+      if (better(v, i, bv, bi)) { bv = v; bi = i; bb = s; }
+    }
+    __syncthreads();
+    redv[tid] = bv;
+    redi[tid] = bi;
+    redb[tid] = bb;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w && better(redv[tid + w], redi[tid + w], redv[tid], redi[tid])) {
+        redv[tid] = redv[tid + w];
+        redi[tid] = redi[tid + w];
+        redb[tid] = redb[tid + w];
+      }
+      __syncthreads();
+    }
+    const double gv = redv[0];
+    const int64_t gi = redi[0];
+    const int gb = redb[0];
+    if (step == 0) nrm0 = gv;
+    if (gi < 0 || !(gv > a.tol2 * nrm0) || !(gv > 0.0)) break;
+    for (int c = tid; c < NC; c += 256) q[c] = a.slot_vec[((size_t)par * G + gb) * NC + c];
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0;
+      for (int c = 0; c < NC; ++c) s += q[c] * q[c];
+      redv[0] = 1.0 / sqrt(s);
+    }
+    __syncthreads();
+    const double inv = redv[0];
+    for (int c = tid; c < NC; c += 256) q[c] *= inv;
+    __syncthreads();
+    if (g == 0 && tid == 0) a.J[step] = (int)gi;
+    // ---- project every owned row against q (two passes) and record the coefficient
+    for (int i = tid; i < nloc; i += 256) {
+      double* row = rows + (size_t)i * stride;
+      double cf = 0;
+      for (int pass = 0; pass < 2; ++pass) {
+        double d = 0;
+        for (int c = 0; c < NC; ++c) d += row[c] * q[c];
+        for (int c = 0; c < NC; ++c) row[c] -= d * q[c];
+        cf += d;
+      }
+      a.C[(r0 + i) * a.kmax + step] = cf;
+      if (rn[i] >= 0.0) {
+        double s = 0;
+        for (int c = 0; c < NC; ++c) s += row[c] * row[c];
+        rn[i] = (r0 + i == gi) ? -1.0 : s;
+      }
+    }
+    __syncthreads();
+    k = step + 1;
+  }
+  if (g == 0 && tid == 0) *a.out_k = k;
+}
+
+// C_J(s, t) = C(J[s], t) is lower triangular (row J[s] has no component on
+// q_t for t > s).  cj_inv_kernel writes Inv = C_J^{-1} (k x k, row-major,
+// lower triangular); rowid_interp_kernel forms P(i, :) = C(i, 0:k) Inv and
+// writes it to L(pos[i], col0 + t).  Skeleton rows then get exact unit rows.
+__global__ __launch_bounds__(256) void cj_inv_kernel(const double* __restrict__ C, int kmax, int k,
+                                                     const int* __restrict__ J, double* __restrict__ inv) {
+  extern __shared__ double x[];  // k x k row-major: x[s * k + t] = Inv(s, t)
+  const int t = threadIdx.x;
+  for (int idx = t; idx < k * k; idx += blockDim.x) x[idx] = 0.0;
+  __syncthreads();
+  if (t < k) {
+    // column t of Inv: C_J x = e_t, forward substitution over s >= t
+    for (int s = t; s < k; ++s) {
+      double v = (s == t) ? 1.0 : 0.0;
+      const double* cs = C + (int64_t)J[s] * kmax;
+      for (int u = t; u < s; ++u) v -= cs[u] * x[u * k + t];
+      x[s * k + t] = v / cs[s];
+    }
+  }
+  __syncthreads();
+  for (int idx = t; idx < k * k; idx += blockDim.x) inv[idx] = x[idx];
+}
+
+__global__ __launch_bounds__(256) void rowid_interp_kernel(const double* __restrict__ C, int64_t m, int kmax, int k,
+                                                           const double* __restrict__ inv,
+                                                           const int* __restrict__ pos, double* __restrict__ L,
+                                                           int64_t ldL, int col0) {
+  extern __shared__ double iv[];  // k x k
+  for (int idx = threadIdx.x; idx < k * k; idx += 256) iv[idx] = inv[idx];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= m) return;
+  const double* ci = C + i * kmax;
+  const int64_t row = pos ? pos[i] : i;
+  for (int t = 0; t < k; ++t) {
+    double v = 0.0;
+    for (int s = t; s < k; ++s) v += ci[s] * iv[s * k + t];
+    L[row + (int64_t)(col0 + t) * ldL] = v;
+  }
+}
+
+__global__ void rowid_unit_rows_kernel(int k, const int* __restrict__ J, const int* __restrict__ pos,
+                                       double* __restrict__ L, int64_t ldL, int col0) {
+  const int s = blockIdx.x;
+  const int64_t row = pos ? pos[J[s]] : J[s];
+  for (int t = threadIdx.x; t < k; t += blockDim.x) L[row + (int64_t)(col0 + t) * ldL] = (t == s) ? 1.0 : 0.0;
+}
+
+// ================================================================ A^T B
+constexpr int TN_CH = 32;  // rows per LDS chunk
+constexpr int TN_ACC = 32; // outputs per thread per pass
+
+__global__ __launch_bounds__(256) void gemm_tn_part_kernel(const double* __restrict__ A, int64_t lda,
+                                                           const double* __restrict__ B, int64_t ldb, int64_t M,
+                                                           int ka, int kb, int64_t rows_per,
+                                                           double* __restrict__ part) {
+  extern __shared__ double sm[];
+  double* As = sm;                 // TN_CH x ka
+  double* Bs = sm + TN_CH * ka;    // TN_CH x kb
+  const int64_t e0 = (int64_t)blockIdx.x * rows_per;
+  const int64_t e1 = min(M, e0 + rows_per);
+  const int nout = ka * kb;
+  double* pb = part + (int64_t)blockIdx.x * nout;
+  for (int base = 0; base < nout; base += 256 * TN_ACC) {
+    double acc[TN_ACC];
+#pragma unroll
+    for (int u = 0; u < TN_ACC; ++u) acc[u] = 0.0;
+    for (int64_t c0 = e0; c0 < e1; c0 += TN_CH) {
+      const int cnt = (int)min<int64_t>(TN_CH, e1 - c0);
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < TN_CH * ka; idx += 256) {
+        const int col = idx / TN_CH, r = idx - col * TN_CH;
+        As[r * ka + col] = (r < cnt) ? A[c0 + r + (int64_t)col * lda] : 0.0;
+      }
+      for (int idx = threadIdx.x; idx < TN_CH * kb; idx += 256) {
+        const int col = idx / TN_CH, r = idx - col * TN_CH;
+        Bs[r * kb + col] = (r < cnt) ? B[c0 + r + (int64_t)col * ldb] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < TN_ACC; ++u) {
+        const int o = base + u * 256 + threadIdx.x;
+        if (o < nout) {
+          const int ia = o % ka, ib = o / ka;
+          double s = acc[u];
+          for (int r = 0; r < TN_CH; ++r) s += As[r * ka + ia] * Bs[r * kb + ib];
+          acc[u] = s;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TN_ACC; ++u) {
+      const int o = base + u * 256 + threadIdx.x;
+      if (o < nout) pb[o] = acc[u];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void gemm_tn_reduce_kernel(const double* __restrict__ part, int nparts, int ka,
+                                                             int kb, double* __restrict__ C, int64_t ldc, int ident) {
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  if (o >= ka * kb) return;
+  double s = 0;
+  for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * ka * kb + o];
+  const int ia = o % ka, ib = o / ka;
+  if (ident && ia == ib) s += 1.0;
+  C[ia + (int64_t)ib * ldc] = s;
+}
+
+int gemm_tn_nparts(int64_t M) {
+  int64_t p = (M + 511) / 512;
+  return (int)(p < 1 ? 1 : (p > 256 ? 256 : p));
+}
+
+// ================================================================ Y -= X W
+__global__ __launch_bounds__(256) void sub_xw_kernel(const double* __restrict__ X, int64_t ldx, int64_t M, int k,
+                                                     const double* __restrict__ W, double* __restrict__ Y,
+                                                     int64_t ldy, int nrhs) {
+  extern __shared__ double ws[];  // k x nrhs
+  for (int idx = threadIdx.x; idx < k * nrhs; idx += 256) ws[idx] = W[idx];
+  __syncthreads();
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= M) return;
+  for (int c = 0; c < nrhs; ++c) {
+    double s = 0;
+    for (int j = 0; j < k; ++j) s += X[e + (int64_t)j * ldx] * ws[j + c * k];
+    Y[e + (int64_t)c * ldy] -= s;
+  }
+}
+
+// ================================================================ small inverse
+// Gauss-Jordan with partial pivoting, one workgroup, matrix in global memory
+// (k x k, ld = k), inverse built in `inv` then copied back.
+__global__ __launch_bounds__(256) void small_inverse_kernel(double* __restrict__ A, double* __restrict__ inv, int k,
+                                                            int* __restrict__ info) {
+  __shared__ double rv[256];
+  __shared__ int ri[256];
+  __shared__ double pivrow_scale;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < k * k; idx += 256) inv[idx] = ((idx % k) == (idx / k)) ? 1.0 : 0.0;
+  if (tid == 0) *info = 0;
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    double bv = -1.0;
+    int bi = -1;
+    for (int i = j + tid; i < k; i += 256) {
+      const double v = fabs(A[i + j * k]);
+      if (v > bv) { bv = v; bi = i; }
+    }
+    rv[tid] = bv;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w && (rv[tid + w] > rv[tid] || (rv[tid + w] == rv[tid] && ri[tid + w] >= 0 && ri[tid + w] < ri[tid]))) {
+        rv[tid] = rv[tid + w];
+        ri[tid] = ri[tid + w];
+      }
+      __syncthreads();
+    }
+    const int p = ri[0];
+    const double pv = rv[0];
+    if (!(pv > 0.0) || !isfinite(pv) || p < 0) {
+      if (tid == 0) *info = j + 1;
+      return;
+    }
+    if (p != j)
+      for (int c = tid; c < k; c += 256) {
+        double t = A[j + c * k]; A[j + c * k] = A[p + c * k]; A[p + c * k] = t;
+        t = inv[j + c * k]; inv[j + c * k] = inv[p + c * k]; inv[p + c * k] = t;
+      }
+    __syncthreads();
+    if (tid == 0) pivrow_scale = 1.0 / A[j + j * k];
+    __syncthreads();
+    const double sc = pivrow_scale;
+    for (int c = tid; c < k; c += 256) {
+      A[j + c * k] *= sc;
+      inv[j + c * k] *= sc;
+    }
+    __syncthreads();
+    // eliminate column j from every other row
+    for (int idx = tid; idx < k * k; idx += 256) {
+      const int i = idx % k, c = idx / k;
+      if (i == j) continue;
+      const double f = A[i + j * k];
+      if (c != j) A[i + c * k] -= f * A[j + c * k];
+      inv[i + c * k] -= f * inv[j + c * k];
+    }
+    __syncthreads();
+    for (int i = tid; i < k; i += 256)
+      if (i != j) A[i + j * k] = 0.0;
+    __syncthreads();
+  }
+  for (int idx = tid; idx < k * k; idx += 256) A[idx] = inv[idx];
+}
+
+__global__ __launch_bounds__(256) void small_gemm_kernel(const double* __restrict__ Wi, int k,
+                                                         const double* __restrict__ z, int nrhs,
+                                                         double* __restrict__ out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= k) return;
+  double s = 0;
+  for (int j = 0; j < k; ++j) s += Wi[i + j * k] * z[j + c * k];
+  out[i + c * k] = s;
+}
+
+// ================================================================ LU (no pivoting)
+constexpr int LU_NB = 64;
+
+// Block 0: factor A11 and write it back; blocks 1..nrt: L21 tiles; the rest:
+// U12 tiles.  Every block factors A11 in LDS from the same input.
+__global__ __launch_bounds__(256) void lu_panel_kernel(double* __restrict__ A, int64_t n, int64_t ld, int64_t K0,
+                                                       int nrt, int* __restrict__ info) {
+  __shared__ double D[LU_NB][LU_NB + 1];
+  __shared__ double T[LU_NB][LU_NB + 1];
+  const int tid = threadIdx.x;
+  const int nb = (int)min<int64_t>(LU_NB, n - K0);
+  for (int idx = tid; idx < nb * nb; idx += 256) {
+    const int r = idx % nb, c = idx / nb;
+    D[r][c] = A[K0 + r + (K0 + c) * ld];
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const double pv = D[j][j];
+    if (!(fabs(pv) > 0.0) || !isfinite(pv)) {
+      if (blockIdx.x == 0 && tid == 0 && *info == 0) *info = (int)(K0 + j + 1);
+      return;
+    }
+    for (int i = j + 1 + tid; i < nb; i += 256) D[i][j] /= pv;
+    __syncthreads();
+    const int rem = nb - j - 1;
+    for (int idx = tid; idx < rem * rem; idx += 256) {
+      const int i = j + 1 + idx % rem, c = j + 1 + idx / rem;
+      D[i][c] -= D[i][j] * D[j][c];
+    }
+    __syncthreads();
+  }
+  const int b = blockIdx.x;
+  if (b == 0) {
+    for (int idx = tid; idx < nb * nb; idx += 256) {
+      const int r = idx % nb, c = idx / nb;
+      A[K0 + r + (K0 + c) * ld] = D[r][c];
+    }
+    return;
+  }
+  const int64_t start = K0 + nb;
+  if (b <= nrt) {
+    // L21 tile: rows start + (b-1)*64 .. ; solve X U11 = A21 (row-wise)
+    const int64_t rbase = start + (int64_t)(b - 1) * LU_NB;
+    const int rows = (int)min<int64_t>(LU_NB, n - rbase);
+    for (int idx = tid; idx < rows * nb; idx += 256) {
+      const int r = idx % rows, c = idx / rows;
+      T[r][c] = A[rbase + r + (K0 + c) * ld];
+    }
+    __syncthreads();
+    if (tid < rows) {
+      for (int c = 0; c < nb; ++c) {
+        double v = T[tid][c];
+        for (int t = 0; t < c; ++t) v -= T[tid][t] * D[t][c];
+        T[tid][c] = v / D[c][c];
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < rows * nb; idx += 256) {
+      const int r = idx % rows, c = idx / rows;
+      A[rbase + r + (K0 + c) * ld] = T[r][c];
+    }
+  } else {
+    // U12 tile: cols start + (b-1-nrt)*64 ..; solve L11 Y = A12 (unit lower)
+    const int64_t cbase = start + (int64_t)(b - 1 - nrt) * LU_NB;
+    const int cols = (int)min<int64_t>(LU_NB, n - cbase);
+    for (int idx = tid; idx < nb * cols; idx += 256) {
+      const int r = idx % nb, c = idx / nb;
+      T[r][c] = A[K0 + r + (cbase + c) * ld];
+    }
+    __syncthreads();
+    if (tid < cols) {
+      for (int r = 0; r < nb; ++r) {
+        double v = T[r][tid];
+        for (int t = 0; t < r; ++t) v -= D[r][t] * T[t][tid];
+        T[r][tid] = v;
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nb * cols; idx += 256) {
+      const int r = idx % nb, c = idx / nb;
+      A[K0 + r + (cbase + c) * ld] = T[r][c];
+    }
+  }
+}
+
+// C -= A B, 64 x 64 tile per workgroup, FP64 MFMA 16x16x4.
+__global__ __launch_bounds__(256) void gemm_nn_sub_kernel(const double* __restrict__ A, int64_t lda,
+                                                          const double* __restrict__ B, int64_t ldb,
+                                                          double* __restrict__ C, int64_t ldc, int64_t m, int64_t n,
+                                                          int64_t kk) {
+  __shared__ double As[16][64 + 1];  // [k][row]
+  __shared__ double Bs[16][64 + 1];  // [k][col]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  const int wr = wave & 1, wc = wave >> 1;
+  const int64_t row0 = (int64_t)blockIdx.x * 64, col0 = (int64_t)blockIdx.y * 64;
+  double4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = 0; k0 < kk; k0 += 16) {
+    __syncthreads();
+    for (int idx = tid; idx < 64 * 16; idx += 256) {
+      const int r = idx & 63, kc = idx >> 6;
+      const int64_t gr = row0 + r, gk = k0 + kc;
+      As[kc][r] = (gr < m && gk < kk) ? A[gr + gk * lda] : 0.0;
+      const int kc2 = idx & 15, c = idx >> 4;
+      const int64_t gc = col0 + c, gk2 = k0 + kc2;
+      Bs[kc2][c] = (gc < n && gk2 < kk) ? B[gk2 + gc * ldb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[ks * 4 + k4][wr * 32 + i * 16 + i16];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[ks * 4 + k4][wc * 32 + j * 16 + i16];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // item r of lane l holds D[l / 16 + 4 r][l % 16]
+        const int64_t gr = row0 + wr * 32 + i * 16 + k4 + 4 * r;
+        const int64_t gc = col0 + wc * 32 + j * 16 + i16;
+        if (gr < m && gc < n) C[gr + gc * ldc] -= acc[i][j][r];
+      }
+}
+
+// C -= A X for few columns (GEMV-like): thread per row.
+__global__ __launch_bounds__(256) void gemv_sub_kernel(const double* __restrict__ A, int64_t lda,
+                                                       const double* __restrict__ X, int64_t ldx,
+                                                       double* __restrict__ C, int64_t ldc, int64_t m, int64_t kk,
+                                                       int nrhs) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= m) return;
+  double s = 0;
+  const double* x = X + (int64_t)c * ldx;
+#pragma unroll 4
+  for (int64_t t = 0; t < kk; ++t) s += A[i + t * lda] * x[t];
+  C[i + (int64_t)c * ldc] -= s;
+}
+
+constexpr int TS_NB = 128;
+
+// In-place triangular solve on one diagonal block (rows b0 .. b0+nbs) of the
+// packed LU: lower = unit lower (forward), else upper (backward).
+__global__ __launch_bounds__(256) void trsv_diag_kernel(const double* __restrict__ LU, int64_t ld, int64_t b0,
+                                                        int nbs, double* __restrict__ B, int64_t ldb, int lower) {
+  __shared__ double x[TS_NB];
+  const int c = blockIdx.x;  // right-hand side
+  double* b = B + (int64_t)c * ldb + b0;
+  for (int i = threadIdx.x; i < nbs; i += 256) x[i] = b[i];
+  __syncthreads();
+  if (lower) {
+    for (int j = 0; j < nbs; ++j) {
+      const double xj = x[j];
+      for (int i = j + 1 + threadIdx.x; i < nbs; i += 256) x[i] -= LU[b0 + i + (b0 + j) * ld] * xj;
+      __syncthreads();
+    }
+  } else {
+    for (int j = nbs - 1; j >= 0; --j) {
+      if (threadIdx.x == 0) x[j] /= LU[b0 + j + (b0 + j) * ld];
+      __syncthreads();
+      const double xj = x[j];
+      for (int i = threadIdx.x; i < j; i += 256) x[i] -= LU[b0 + i + (b0 + j) * ld] * xj;
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < nbs; i += 256) b[i] = x[i];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+size_t rowid_work_bytes(int64_t m, int ncols, int kmax, int ngroups) {
+  (void)kmax;
+  return sizeof(double) * (size_t)(2 * ngroups) + sizeof(int64_t) * (size_t)(2 * ngroups) +
+         sizeof(double) * (size_t)(2 * ngroups) * ncols + sizeof(double) * (size_t)m * ncols + 1024;
+}
+
+int launch_rowid(rw_ctx* ctx, const double* Y, int64_t m, int ncols, double tol, int kmax, int* J, double* C,
+                 void* work, hipStream_t s) {
+  if (m <= 0) return 0;
+  const int ncu = ctx->n_cu > 0 ? ctx->n_cu : 256;
+  // rows per workgroup: keep them in LDS when they fit (<= 120 KiB of rows)
+  const int64_t lds_budget = 120 * 1024;
+  int64_t rows_per = (m + ncu - 1) / ncu;
+  if (rows_per < 32) rows_per = 32;
+  int G = (int)((m + rows_per - 1) / rows_per);
+  const bool lds_rows = rows_per * (ncols + 1) * 8 <= lds_budget;
+  const size_t extra = sizeof(double) * ((size_t)ncols + rows_per + 256) + sizeof(int64_t) * 256 + sizeof(int) * 256;
+  const size_t shmem = (lds_rows ? sizeof(double) * rows_per * (ncols + 1) : 0) + extra;
+  char* w = (char*)work;
+  RowIdArgs a{};
+  a.Y = Y;
+  a.m = m;
+  a.ncols = ncols;
+  a.tol2 = tol * tol;
+  a.kmax = kmax;
+  a.rows_per = (int)rows_per;
+  a.lds_rows = lds_rows ? 1 : 0;
+  a.slot_norm = (double*)w; w += sizeof(double) * 2 * G;
+  a.slot_idx = (int64_t*)w; w += sizeof(int64_t) * 2 * G;
+  a.slot_vec = (double*)w; w += sizeof(double) * 2 * G * ncols;
+  a.Yw = (double*)w; w += sizeof(double) * m * ncols;
+  a.J = J;
+  a.C = C;
+  int* dk = (int*)ctx->d_sync;
+  a.out_k = dk;
+  if (!lds_rows) HIP_CHECK(hipMemcpyAsync(a.Yw, Y, sizeof(double) * m * ncols, hipMemcpyDeviceToDevice, s));
+  void* args[] = {&a};
+  HIP_CHECK(hipFuncSetAttribute((const void*)rowid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  HIP_CHECK(hipLaunchCooperativeKernel((const void*)rowid_kernel, dim3(G), dim3(256), args, shmem, s));
+  KERNEL_CHECK("rowid");
+  int k = 0;
+  HIP_CHECK(hipMemcpyAsync(&k, dk, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  return k;
+}
+
+void launch_rowid_interp(const double* C, int64_t m, int kmax, int k, const int* J, const int* pos, double* L,
+                         int64_t ldL, int col0, double* inv_work, hipStream_t s) {
+  if (k <= 0 || m <= 0) return;
+  if (k > 128) RW_THROW(RW_EINVAL, "row ID rank above 128");
+  const size_t sh = sizeof(double) * k * k;
+  HIP_CHECK(hipFuncSetAttribute((const void*)cj_inv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+  HIP_CHECK(hipFuncSetAttribute((const void*)rowid_interp_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+  hipLaunchKernelGGL(cj_inv_kernel, dim3(1), dim3(128), sh, s, C, kmax, k, J, inv_work);
+  KERNEL_CHECK("cj_inv");
+  hipLaunchKernelGGL(rowid_interp_kernel, dim3(blocks(m)), dim3(256), sh, s, C, m, kmax, k, inv_work, pos, L, ldL,
+                     col0);
+  KERNEL_CHECK("rowid_interp");
+  hipLaunchKernelGGL(rowid_unit_rows_kernel, dim3(k), dim3(64), 0, s, k, J, pos, L, ldL, col0);
+  KERNEL_CHECK("rowid_unit_rows");
+}
+
+size_t gemm_tn_part_doubles(int64_t M, int ka, int kb) { return (size_t)gemm_tn_nparts(M) * ka * kb; }
+
+void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int ka, int kb, double* C,
+                    int64_t ldc, bool add_identity, double* part, hipStream_t s) {
+  if (ka <= 0 || kb <= 0) return;
+  const int np = gemm_tn_nparts(M);
+  const int64_t rows_per = (M + np - 1) / np;
+  const size_t sh = sizeof(double) * TN_CH * (ka + kb);
+  HIP_CHECK(hipFuncSetAttribute((const void*)gemm_tn_part_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+  hipLaunchKernelGGL(gemm_tn_part_kernel, dim3(np), dim3(256), sh, s, A, lda, B, ldb, M, ka, kb, rows_per, part);
+  KERNEL_CHECK("gemm_tn_part");
+  hipLaunchKernelGGL(gemm_tn_reduce_kernel, dim3(blocks((int64_t)ka * kb)), dim3(256), 0, s, part, np, ka, kb, C, ldc,
+                     add_identity ? 1 : 0);
+  KERNEL_CHECK("gemm_tn_reduce");
+}
+
+void launch_sub_xw(const double* X, int64_t ldx, int64_t M, int k, const double* W, double* Y, int64_t ldy, int nrhs,
+                   hipStream_t s) {
+  if (k <= 0 || M <= 0) return;
+  const size_t sh = sizeof(double) * k * nrhs;
+  if (sh > 150 * 1024) RW_THROW(RW_EINVAL, "too many right-hand sides for one Woodbury pass");
+  HIP_CHECK(hipFuncSetAttribute((const void*)sub_xw_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+  hipLaunchKernelGGL(sub_xw_kernel, dim3(blocks(M)), dim3(256), sizeof(double) * k * nrhs, s, X, ldx, M, k, W, Y, ldy,
+                     nrhs);
+  KERNEL_CHECK("sub_xw");
+}
+
+void launch_small_inverse(double* W, int k, int* info, hipStream_t s) {
+  // the inverse is built in the k*k doubles that follow W
+  hipLaunchKernelGGL(small_inverse_kernel, dim3(1), dim3(256), 0, s, W, W + (size_t)k * k, k, info);
+  KERNEL_CHECK("small_inverse");
+}
+
+void launch_small_gemm(const double* Winv, int k, const double* z, int nrhs, double* out, hipStream_t s) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(small_gemm_kernel, dim3(blocks(k), nrhs), dim3(256), 0, s, Winv, k, z, nrhs, out);
+  KERNEL_CHECK("small_gemm");
+}
+
+size_t lu_work_doubles(int64_t n) { (void)n; return 0; }
+
+void launch_gemm_nn_sub(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc, int64_t m,
+                        int64_t n, int64_t kk, hipStream_t s) {
+  if (m <= 0 || n <= 0 || kk <= 0) return;
+  if (n <= 8) {
+    hipLaunchKernelGGL(gemv_sub_kernel, dim3(blocks(m), (unsigned)n), dim3(256), 0, s, A, lda, B, ldb, C, ldc, m, kk,
+                       (int)n);
+    KERNEL_CHECK("gemv_sub");
+    return;
+  }
+  dim3 grid((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64));
+  hipLaunchKernelGGL(gemm_nn_sub_kernel, grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, m, n, kk);
+  KERNEL_CHECK("gemm_nn_sub");
+}
+
+void launch_lu_nopiv(double* A, int64_t n, int64_t ld, int* info, double* work, hipStream_t s) {
+  (void)work;
+  HIP_CHECK(hipMemsetAsync(info, 0, sizeof(int), s));
+  for (int64_t K0 = 0; K0 < n; K0 += LU_NB) {
+    const int nb = (int)std::min<int64_t>(LU_NB, n - K0);
+    const int64_t rest = n - K0 - nb;
+    const int nrt = (int)((rest + LU_NB - 1) / LU_NB);
+    hipLaunchKernelGGL(lu_panel_kernel, dim3(1 + 2 * nrt), dim3(256), 0, s, A, n, ld, K0, nrt, info);
+    KERNEL_CHECK("lu_panel");
+    if (rest > 0)
+      launch_gemm_nn_sub(A + (K0 + nb) + K0 * ld, ld, A + K0 + (K0 + nb) * ld, ld, A + (K0 + nb) + (K0 + nb) * ld, ld,
+                         rest, rest, nb, s);
+  }
+}
+
+void launch_lu_solve(const double* LU, int64_t n, int64_t ld, double* B, int64_t ldb, int nrhs, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  for (int64_t b0 = 0; b0 < n; b0 += TS_NB) {
+    const int nbs = (int)std::min<int64_t>(TS_NB, n - b0);
+    hipLaunchKernelGGL(trsv_diag_kernel, dim3(nrhs), dim3(256), 0, s, LU, ld, b0, nbs, B, ldb, 1);
+    KERNEL_CHECK("trsv_lower");
+    const int64_t rest = n - b0 - nbs;
+    if (rest > 0) launch_gemm_nn_sub(LU + b0 + nbs + b0 * ld, ld, B + b0, ldb, B + b0 + nbs, ldb, rest, nrhs, nbs, s);
+  }
+  const int64_t nblk = (n + TS_NB - 1) / TS_NB;
+  for (int64_t bi = nblk - 1; bi >= 0; --bi) {
+    const int64_t b0 = bi * TS_NB;
+    const int nbs = (int)std::min<int64_t>(TS_NB, n - b0);
+    hipLaunchKernelGGL(trsv_diag_kernel, dim3(nrhs), dim3(256), 0, s, LU, ld, b0, nbs, B, ldb, 0);
+    KERNEL_CHECK("trsv_upper");
+    if (b0 > 0) launch_gemm_nn_sub(LU + b0 * ld, ld, B + b0, ldb, B, ldb, b0, nrhs, nbs, s);
+  }
+}

@@ -1,0 +1,519 @@
+// Kernels that generate entries of the Stokes Nystrom operator on the fly
+// (Sec. 2: A = -1/2 I + D + N with
+//   D(x, y) = (1/pi) (r r^T / r^2) (r . n_y / r^2),  r = x - y,
+//   N(x, y) = n_x n_y^T, weights w_j folded into the source side).
+//
+//  * residual r = g - A tau on one discretization (FP64 VALU: one division
+//    and ~12 FMAs per 2x2 block and right-hand side);
+//  * Stokeslet boundary data (eq. stokeslet, mu = 1);
+//  * dense assembly of A(targets, sources);
+//  * skeleton rows R of the update matrix Q (uniform row-ID format);
+//  * the random sketch Y = A(tgt, src) Omega of the off-diagonal blocks of Q,
+//    with the kernel tile generated in registers and contracted on the FP64
+//    matrix cores (v_mfma_f64_16x16x4f64); Omega = +-1 from a counter-based
+//    hash (SplitMix64 finalizer), so it is never stored.
+#include "kernels.h"
+
+namespace {
+
+constexpr double kInvPi = 0.31830988618379067154;
+
+// ---------------------------------------------------------------- residual
+constexpr int RT = 128;  // targets per block
+constexpr int RRB = 4;   // right-hand sides per pass
+
+int resid_splits(int64_t n, int nrhs) {
+  const int64_t tb = (n + RT - 1) / RT;
+  const int64_t chunks = (nrhs + RRB - 1) / RRB;
+  int64_t s = (2048 + tb * chunks - 1) / (tb * chunks);
+  s = s < 1 ? 1 : (s > 32 ? 32 : s);
+  const int64_t maxs = (n + RT - 1) / RT;  // at least one source tile per split
+  if (s > maxs) s = maxs;
+  return (int)(s < 1 ? 1 : s);
+}
+
+__global__ __launch_bounds__(RT) void resid_tiles_kernel(const NodeRec* __restrict__ nd, int64_t n,
+                                                         const double* __restrict__ tau, int nrhs, int nsplit,
+                                                         double* __restrict__ part) {
+  __shared__ double sx[RT], sy[RT], snx[RT], sny[RT], stx[RRB][RT], sty[RRB][RT];
+  const int64_t t = (int64_t)blockIdx.x * RT + threadIdx.x;
+  const int r0 = blockIdx.y * RRB;
+  const int nr = min(RRB, nrhs - r0);
+  const int z = blockIdx.z;
+  const int64_t chunk = (n + nsplit - 1) / nsplit;
+  const int64_t s0 = z * chunk, s1 = min(n, s0 + chunk);
+  const int64_t ld = 2 * n;
+  double xi = 0, yi = 0;
+  if (t < n) { xi = nd[t].x; yi = nd[t].y; }
+  double ax[RRB], ay[RRB];
+#pragma unroll
+  for (int c = 0; c < RRB; ++c) { ax[c] = 0; ay[c] = 0; }
+  for (int64_t b0 = s0; b0 < s1; b0 += RT) {
+    const int64_t sj = b0 + threadIdx.x;
+    __syncthreads();
+    if (sj < s1) {
+      const NodeRec q = nd[sj];
+      sx[threadIdx.x] = q.x;
+      sy[threadIdx.x] = q.y;
+      snx[threadIdx.x] = q.nx * q.w * kInvPi;
+      sny[threadIdx.x] = q.ny * q.w * kInvPi;
+#pragma unroll
+      for (int c = 0; c < RRB; ++c) {
+        stx[c][threadIdx.x] = (c < nr) ? tau[2 * sj + (int64_t)(r0 + c) * ld] : 0.0;
+        sty[c][threadIdx.x] = (c < nr) ? tau[2 * sj + 1 + (int64_t)(r0 + c) * ld] : 0.0;
+      }
+    } else {
+      sx[threadIdx.x] = 1e300; sy[threadIdx.x] = 1e300;  // far away; zero weight
+      snx[threadIdx.x] = 0; sny[threadIdx.x] = 0;
+#pragma unroll
+      for (int c = 0; c < RRB; ++c) { stx[c][threadIdx.x] = 0; sty[c][threadIdx.x] = 0; }
+    }
+    __syncthreads();
+    const int cnt = (int)min<int64_t>(RT, s1 - b0);
+    for (int s = 0; s < cnt; ++s) {
+      const double rx = xi - sx[s], ry = yi - sy[s];
+      const double r2 = rx * rx + ry * ry;
+      const double inv = r2 > 0.0 ? 1.0 / r2 : 0.0;  // r = 0 only on the diagonal
+      const double cf = (rx * snx[s] + ry * sny[s]) * inv * inv;
+#pragma unroll
+      for (int c = 0; c < RRB; ++c) {
+        const double d = cf * (rx * stx[c][s] + ry * sty[c][s]);
+        ax[c] += d * rx;
+        ay[c] += d * ry;
+      }
+    }
+  }
+  if (t < n)
+    for (int c = 0; c < nr; ++c) {
+      double* p = part + ((int64_t)z * nrhs + r0 + c) * ld;
+      p[2 * t] = ax[c];
+      p[2 * t + 1] = ay[c];
+    }
+}
+
+// s_N[c] = sum_j w_j n_j . tau_j  (the rank-one nullspace term)
+__global__ __launch_bounds__(256) void flux_kernel(const NodeRec* __restrict__ nd, int64_t n,
+                                                   const double* __restrict__ tau, double* __restrict__ sN) {
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  const double* tc = tau + (int64_t)c * 2 * n;
+  double s = 0.0;
+  for (int64_t j = threadIdx.x; j < n; j += 256) s += nd[j].w * (nd[j].nx * tc[2 * j] + nd[j].ny * tc[2 * j + 1]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sN[c] = red[0];
+}
+
+__global__ __launch_bounds__(256) void resid_finalize_kernel(const NodeRec* __restrict__ nd, int64_t n,
+                                                             const double* __restrict__ g,
+                                                             const double* __restrict__ tau, int nrhs, int nsplit,
+                                                             const double* __restrict__ part,
+                                                             const double* __restrict__ sN,
+                                                             double* __restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n) return;
+  const int64_t ld = 2 * n;
+  const NodeRec q = nd[i];
+  const double tx = tau[2 * i + (int64_t)c * ld], ty = tau[2 * i + 1 + (int64_t)c * ld];
+  // self block without its nullspace part (added through s_N below)
+  const double a00 = q.s00 - q.w * q.nx * q.nx, a01 = q.s01 - q.w * q.nx * q.ny, a11 = q.s11 - q.w * q.ny * q.ny;
+  double ax = a00 * tx + a01 * ty + q.nx * sN[c];
+  double ay = a01 * tx + a11 * ty + q.ny * sN[c];
+  for (int z = 0; z < nsplit; ++z) {
+    const double* p = part + ((int64_t)z * nrhs + c) * ld;
+    ax += p[2 * i];
+    ay += p[2 * i + 1];
+  }
+  r[2 * i + (int64_t)c * ld] = g[2 * i + (int64_t)c * ld] - ax;
+  r[2 * i + 1 + (int64_t)c * ld] = g[2 * i + 1 + (int64_t)c * ld] - ay;
+}
+
+__global__ __launch_bounds__(256) void colnorms2_kernel(const double* __restrict__ a,
+                                                        const double* __restrict__ b, int64_t rows,
+                                                        int nrhs, double* __restrict__ out) {
+  __shared__ double ra[256], rb[256];
+  const int c = blockIdx.x;
+  double sa = 0, sb = 0;
+  for (int64_t i = threadIdx.x; i < rows; i += 256) {
+    const double x = a[i + (int64_t)c * rows];
+    const double y = b[i + (int64_t)c * rows];
+    sa += x * x;
+    sb += y * y;
+  }
+  ra[threadIdx.x] = sa;
+  rb[threadIdx.x] = sb;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) { ra[threadIdx.x] += ra[threadIdx.x + w]; rb[threadIdx.x] += rb[threadIdx.x + w]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { out[c] = ra[0]; out[nrhs + c] = rb[0]; }
+}
+
+// ---------------------------------------------------------------- RHS
+__global__ __launch_bounds__(256) void stokeslet_kernel(const NodeRec* __restrict__ nd, int64_t n,
+                                                        const double* __restrict__ zf, int n_src,
+                                                        double* __restrict__ g) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double x = nd[i].x, y = nd[i].y;
+  double ux = 0, uy = 0;
+  for (int m = 0; m < n_src; ++m) {
+    const double rx = x - zf[4 * m], ry = y - zf[4 * m + 1];
+    const double fx = zf[4 * m + 2], fy = zf[4 * m + 3];
+    const double r2 = rx * rx + ry * ry;
+    const double lg = -0.5 * log(r2);
+    const double rf = (rx * fx + ry * fy) / r2;
+    ux += lg * fx + rf * rx;
+    uy += lg * fy + rf * ry;
+  }
+  const double s = 0.25 * kInvPi;
+  g[2 * i] = s * ux;
+  g[2 * i + 1] = s * uy;
+}
+
+// ---------------------------------------------------------------- assembly
+__device__ __forceinline__ void a_block(const NodeRec& t, const NodeRec& q, double B[4]) {
+  const double rx = t.x - q.x, ry = t.y - q.y;
+  const double r2 = rx * rx + ry * ry;
+  const double cf = (rx * q.nx + ry * q.ny) * q.w * kInvPi / (r2 * r2);
+  B[0] = cf * rx * rx + q.w * t.nx * q.nx;
+  B[1] = cf * rx * ry + q.w * t.nx * q.ny;
+  B[2] = cf * ry * rx + q.w * t.ny * q.nx;
+  B[3] = cf * ry * ry + q.w * t.ny * q.ny;
+}
+
+__global__ __launch_bounds__(256) void assemble_kernel(const NodeRec* __restrict__ tgt, int64_t nt,
+                                                       const NodeRec* __restrict__ src, int64_t ns, int same,
+                                                       double* __restrict__ A, int64_t ld) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i >= nt) return;
+  double B[4];
+  if (same && i == j) {
+    const NodeRec q = src[j];
+    B[0] = q.s00; B[1] = q.s01; B[2] = q.s01; B[3] = q.s11;
+  } else {
+    a_block(tgt[i], src[j], B);
+  }
+  A[2 * i + (2 * j) * ld] = B[0];
+  A[2 * i + 1 + (2 * j) * ld] = B[2];
+  A[2 * i + (2 * j + 1) * ld] = B[1];
+  A[2 * i + 1 + (2 * j + 1) * ld] = B[3];
+}
+
+// R rows.  mode 0 (k skeleton rows): row = [0 at kept, -A(t, cut) at cut | A(t, p)]
+//          mode 1 (p skeleton rows): row = [A(t, kept) at kept, 0 at cut | 0]
+// ref_kind[o] = 0 kept, 1 cut.
+__global__ __launch_bounds__(256) void r_rows_kernel(const NodeRec* __restrict__ tnodes,
+                                                     const int* __restrict__ skel, const NodeRec* __restrict__ ref,
+                                                     const int* __restrict__ ref_kind, int64_t n_o,
+                                                     const NodeRec* __restrict__ pn, int64_t n_p, int mode,
+                                                     double* __restrict__ R, int64_t ldR) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int a = blockIdx.y;
+  if (e >= 2 * (n_o + n_p)) return;
+  const int sd = skel[a];
+  const NodeRec t = tnodes[sd >> 1];
+  const int c = sd & 1;
+  double v = 0.0;
+  double B[4];
+  if (e < 2 * n_o) {
+    const int64_t o = e >> 1;
+    const int d = (int)(e & 1);
+    const int kind = ref_kind[o];
+    if (mode == 0 && kind == 1) { a_block(t, ref[o], B); v = -B[c * 2 + d]; }
+    if (mode == 1 && kind == 0) { a_block(t, ref[o], B); v = B[c * 2 + d]; }
+  } else if (mode == 0) {
+    const int64_t q = (e - 2 * n_o) >> 1;
+    const int d = (int)(e & 1);
+    a_block(t, pn[q], B);
+    v = B[c * 2 + d];
+  }
+  R[(int64_t)a * ldR + e] = v;
+}
+
+// ---------------------------------------------------------------- sketch
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+struct SegArgs {
+  const NodeRec* src[2];
+  int64_t ns[2];
+  double sign[2];
+  int64_t orow[2];
+  int nseg;
+};
+
+__device__ __forceinline__ double omega_pm1(uint64_t seed, int64_t row, int col) {
+  uint64_t z = seed ^ ((uint64_t)row * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)(col + 1) * 0xD1B54A32D192ED03ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return (z >> 63) ? -1.0 : 1.0;
+}
+
+template <int NC>
+__global__ __launch_bounds__(256) void sketch_kernel(const NodeRec* __restrict__ tgt, int64_t nt, SegArgs sa,
+                                                     uint64_t seed, int col_off, int nsplit, double* __restrict__ out) {
+  constexpr int NCOL = 16 * NC;
+  __shared__ double red[64 * NCOL];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  const int64_t tb = blockIdx.x;  // 32 target nodes = 64 rows
+  const int z = blockIdx.y;
+  // target data of this lane's 4 row blocks
+  double tx[4], ty[4], tnc[4];
+  bool tvalid[4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const int row = rb * 16 + i16;
+    const int64_t tn = tb * 32 + (row >> 1);
+    tvalid[rb] = tn < nt;
+    const NodeRec t = tgt[tvalid[rb] ? tn : 0];
+    tx[rb] = t.x;
+    ty[rb] = t.y;
+    tnc[rb] = (row & 1) ? t.ny : t.nx;
+  }
+  const int ccomp = i16 & 1;
+  const int dcomp = k4 & 1;
+  const int64_t ntot = sa.ns[0] + (sa.nseg > 1 ? sa.ns[1] : 0);
+  const int64_t npairs = (ntot + 1) / 2;
+  const int64_t pchunk = (npairs + nsplit - 1) / nsplit;
+  const int64_t p0 = z * pchunk, p1 = min(npairs, p0 + pchunk);
+  double4_t acc[4][NC];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) acc[rb][cb] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  for (int64_t p = p0 + wave; p < p1; p += 4) {
+    const int64_t gs = 2 * p + (k4 >> 1);
+    double sx = 0, sy = 0, snx = 0, sny = 0, sw = 0, sgn = 0, snd = 0;
+    int64_t orow = 0;
+    if (gs < ntot) {
+      const int sg = (gs < sa.ns[0]) ? 0 : 1;
+      const int64_t li = sg ? gs - sa.ns[0] : gs;
+      const NodeRec q = sa.src[sg][li];
+      sx = q.x; sy = q.y; snx = q.nx; sny = q.ny; sw = q.w; sgn = sa.sign[sg];
+      snd = dcomp ? q.ny : q.nx;
+      orow = sa.orow[sg] + 2 * li + dcomp;
+    }
+    double afr[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const double rx = tx[rb] - sx, ry = ty[rb] - sy;
+      const double r2 = rx * rx + ry * ry;
+      const double cf = sgn * sw * kInvPi * (rx * snx + ry * sny) / (r2 * r2);
+      const double rc = ccomp ? ry : rx;
+      const double rd = dcomp ? ry : rx;
+      const double v = cf * rc * rd + sgn * sw * tnc[rb] * snd;
+      afr[rb] = (tvalid[rb] && gs < ntot) ? v : 0.0;
+    }
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) {
+      const double bfr = (gs < ntot) ? omega_pm1(seed, orow, col_off + cb * 16 + i16) : 0.0;
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[rb], bfr, acc[rb][cb], 0, 0, 0);
+    }
+  }
+  // reduce the four waves (deterministic order) and write this split's part
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            // v_mfma_f64_16x16x4f64: item r of lane l holds D[l / 16 + 4 r][l % 16]
+            const int row = rb * 16 + k4 + 4 * r, col = cb * 16 + i16;
+            if (w == 0) red[row * NCOL + col] = acc[rb][cb][r];
+            else red[row * NCOL + col] += acc[rb][cb][r];
+          }
+    }
+    __syncthreads();
+  }
+  const int64_t rows_tot = 2 * nt;
+  double* o = out + (int64_t)z * rows_tot * NCOL;
+  for (int idx = threadIdx.x; idx < 64 * NCOL; idx += 256) {
+    const int row = idx / NCOL, col = idx - row * NCOL;
+    const int64_t grow = tb * 64 + row;
+    if (grow < rows_tot) o[grow * NCOL + col] = red[idx];
+  }
+}
+
+// Y(:, col_off .. col_off + w) = sum over splits of part[z] (rows x w, row-major)
+__global__ __launch_bounds__(256) void sum_parts_kernel(const double* __restrict__ part, int nsplit, int64_t rows,
+                                                        int w, double* __restrict__ Y, int ldY, int col_off) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t len = rows * w;
+  if (i >= len) return;
+  double s = 0.0;
+  for (int z = 0; z < nsplit; ++z) s += part[(int64_t)z * len + i];
+  const int64_t r = i / w;
+  const int c = (int)(i - r * w);
+  Y[r * ldY + col_off + c] = s;
+}
+
+int sketch_splits(int64_t nt, int64_t nsrc) {
+  const int64_t rb = (2 * nt + 63) / 64;
+  int64_t s = (2048 + rb - 1) / rb;
+  const int64_t pairs = (nsrc + 1) / 2;
+  const int64_t maxs = pairs / 16 > 0 ? pairs / 16 : 1;
+  if (s > maxs) s = maxs;
+  if (s > 64) s = 64;
+  return (int)(s < 1 ? 1 : s);
+}
+
+// ---------------------------------------------------------------- orderings
+__global__ __launch_bounds__(256) void to_ext_kernel(const double* __restrict__ g, int64_t ld_g, int64_t n_new,
+                                                     const int* __restrict__ new2ext, double* __restrict__ ext,
+                                                     int64_t ld_ext) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n_new) return;
+  const int64_t e = new2ext[i];
+  ext[2 * e + c * ld_ext] = g[2 * i + c * ld_g];
+  ext[2 * e + 1 + c * ld_ext] = g[2 * i + 1 + c * ld_g];
+}
+
+__global__ __launch_bounds__(256) void from_ext_kernel(const double* __restrict__ ext, int64_t ld_ext,
+                                                       int64_t n_new, const int* __restrict__ new2ext,
+                                                       double* __restrict__ out, int64_t ld_out, int acc) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n_new) return;
+  const int64_t e = new2ext[i];
+  const double vx = ext[2 * e + c * ld_ext], vy = ext[2 * e + 1 + c * ld_ext];
+  if (acc) {
+    out[2 * i + c * ld_out] += vx;
+    out[2 * i + 1 + c * ld_out] += vy;
+  } else {
+    out[2 * i + c * ld_out] = vx;
+    out[2 * i + 1 + c * ld_out] = vy;
+  }
+}
+
+__global__ __launch_bounds__(256) void gather_nodes_kernel(const NodeRec* __restrict__ src, const int* __restrict__ idx,
+                                                           int64_t n, NodeRec* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+
+inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+size_t resid_part_doubles(int64_t n, int nrhs) {
+  return (size_t)resid_splits(n, nrhs) * nrhs * 2 * n + 64 + nrhs;
+}
+
+void launch_residual(const NodeRec* nodes, int64_t n, const double* g, const double* tau, double* r, int nrhs,
+                     double* part, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  const int ns = resid_splits(n, nrhs);
+  double* sN = part + (size_t)ns * nrhs * 2 * n;
+  dim3 grid(blocks(n, RT), (nrhs + RRB - 1) / RRB, ns);
+  hipLaunchKernelGGL(resid_tiles_kernel, grid, dim3(RT), 0, s, nodes, n, tau, nrhs, ns, part);
+  KERNEL_CHECK("resid_tiles");
+  hipLaunchKernelGGL(flux_kernel, dim3(nrhs), dim3(256), 0, s, nodes, n, tau, sN);
+  KERNEL_CHECK("flux");
+  hipLaunchKernelGGL(resid_finalize_kernel, dim3(blocks(n), nrhs), dim3(256), 0, s, nodes, n, g, tau, nrhs, ns,
+                     part, sN, r);
+  KERNEL_CHECK("resid_finalize");
+}
+
+void launch_colnorms2(const double* a, const double* b, int64_t rows, int nrhs, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(colnorms2_kernel, dim3(nrhs), dim3(256), 0, s, a, b, rows, nrhs, out);
+  KERNEL_CHECK("colnorms2");
+}
+
+void launch_stokeslet_rhs(const NodeRec* nodes, int64_t n, const double* zf, int n_src, double* g,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(stokeslet_kernel, dim3(blocks(n)), dim3(256), 0, s, nodes, n, zf, n_src, g);
+  KERNEL_CHECK("stokeslet_rhs");
+}
+
+void launch_assemble(const NodeRec* tgt, int64_t nt, const NodeRec* src, int64_t ns, bool same, double* A,
+                     int64_t ld, hipStream_t s) {
+  if (nt <= 0 || ns <= 0) return;
+  hipLaunchKernelGGL(assemble_kernel, dim3(blocks(nt), (unsigned)ns), dim3(256), 0, s, tgt, nt, src, ns,
+                     same ? 1 : 0, A, ld);
+  KERNEL_CHECK("assemble");
+}
+
+void launch_r_rows(const NodeRec* tnodes, const int* skel_dof, int nrows, const NodeRec* ref_nodes,
+                   const int* ref_kind, int64_t n_o, const NodeRec* pnodes, int64_t n_p, int mode, double* R,
+                   int64_t ldR, hipStream_t s) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(r_rows_kernel, dim3(blocks(2 * (n_o + n_p)), nrows), dim3(256), 0, s, tnodes, skel_dof,
+                     ref_nodes, ref_kind, n_o, pnodes, n_p, mode, R, ldR);
+  KERNEL_CHECK("r_rows");
+}
+
+size_t sketch_part_doubles(int64_t nt, int64_t nsrc) { return (size_t)sketch_splits(nt, nsrc) * 2 * nt * 64; }
+
+void launch_sketch(const NodeRec* tgt, int64_t nt, const SketchSeg* segs, int nseg, int ncols, uint64_t seed,
+                   double* Y, double* part, hipStream_t s) {
+  if (nt <= 0) return;
+  if (ncols != 32 && ncols != 64 && ncols != 96 && ncols != 128)
+    RW_THROW(RW_EINVAL, "sketch_cols must be 32, 64, 96 or 128");
+  SegArgs sa{};
+  sa.nseg = nseg;
+  int64_t nsrc = 0;
+  for (int i = 0; i < nseg && i < 2; ++i) {
+    sa.src[i] = segs[i].src;
+    sa.ns[i] = segs[i].ns;
+    sa.sign[i] = segs[i].sign;
+    sa.orow[i] = segs[i].omega_row0;
+    nsrc += segs[i].ns;
+  }
+  if (nseg < 2) { sa.src[1] = segs[0].src; sa.ns[1] = 0; }
+  const int64_t rows = 2 * nt;
+  if (nsrc == 0) {
+    HIP_CHECK(hipMemsetAsync(Y, 0, sizeof(double) * rows * ncols, s));
+    return;
+  }
+  const int ns = sketch_splits(nt, nsrc);
+  dim3 grid((unsigned)((rows + 63) / 64), ns);
+  // passes of 64 columns (32 for the remainder): the 64-wide tile keeps the
+  // accumulators in registers without spilling
+  for (int off = 0; off < ncols;) {
+    const int w = (ncols - off >= 64) ? 64 : 32;
+    if (w == 64)
+      hipLaunchKernelGGL(sketch_kernel<4>, grid, dim3(256), 0, s, tgt, nt, sa, seed, off, ns, part);
+    else
+      hipLaunchKernelGGL(sketch_kernel<2>, grid, dim3(256), 0, s, tgt, nt, sa, seed, off, ns, part);
+    KERNEL_CHECK("sketch");
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(blocks(rows * w)), dim3(256), 0, s, part, ns, rows, w, Y, ncols, off);
+    KERNEL_CHECK("sketch_sum");
+    off += w;
+  }
+}
+
+void launch_to_ext(const double* g, int64_t ld_g, int64_t n_new, const int* new2ext, double* ext, int64_t ld_ext,
+                   int64_t n_ext_dofs, int nrhs, hipStream_t s) {
+  for (int c = 0; c < nrhs; ++c)
+    HIP_CHECK(hipMemsetAsync(ext + (int64_t)c * ld_ext, 0, sizeof(double) * n_ext_dofs, s));
+  hipLaunchKernelGGL(to_ext_kernel, dim3(blocks(n_new), nrhs), dim3(256), 0, s, g, ld_g, n_new, new2ext, ext,
+                     ld_ext);
+  KERNEL_CHECK("to_ext");
+}
+
+void launch_from_ext(const double* ext, int64_t ld_ext, int64_t n_new, const int* new2ext, double* out,
+                     int64_t ld_out, int nrhs, bool accumulate, hipStream_t s) {
+  hipLaunchKernelGGL(from_ext_kernel, dim3(blocks(n_new), nrhs), dim3(256), 0, s, ext, ld_ext, n_new, new2ext,
+                     out, ld_out, accumulate ? 1 : 0);
+  KERNEL_CHECK("from_ext");
+}
+
+void launch_gather_nodes(const NodeRec* src, const int* idx, int64_t n, NodeRec* dst, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(gather_nodes_kernel, dim3(blocks(n)), dim3(256), 0, s, src, idx, n, dst);
+  KERNEL_CHECK("gather_nodes");
+}

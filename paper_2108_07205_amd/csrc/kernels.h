@@ -1,0 +1,108 @@
+// Launchers of the gfx950 kernels of the refined-wall solver.  All device
+// matrices are column-major unless stated; every launcher enqueues on the
+// given stream and checks the launch.
+#pragma once
+
+#include "common.h"
+
+// ---------------------------------------------------------------- HBS apply
+// One tree level of packed HBS inverse generators (device arrays, per node).
+struct HbsLevelDev {
+  int nnodes = 0;
+  int max_nin = 0, max_k = 0;
+  int64_t S = 0;              // sum of input sizes (this level's vector length)
+  int64_t K = 0;              // sum of skeleton sizes (parent level's vector length)
+  const int* nin = nullptr;
+  const int* k = nullptr;
+  const int64_t* in_off = nullptr;    // node input offset in this level's vectors
+  const int64_t* kout_off = nullptr;  // node skeleton offset in the parent level's vectors
+  const int64_t* up_off = nullptr;    // offset of [F*; G] ((k + nin) x nin) in the generator array
+  const int64_t* e_off = nullptr;     // offset of E (nin x k)
+};
+
+// up: bhat = F* b (to the parent level's vector), gb = G b (this level).
+void launch_hbs_up(const HbsLevelDev& L, const double* gen, const double* in, int64_t ld_in,
+                   double* bhat, int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s);
+void launch_hbs_up_f32(const HbsLevelDev& L, const float* gen, const double* in, int64_t ld_in,
+                       double* bhat, int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s);
+// root: out = G_root in.
+void launch_hbs_root(int nroot, const double* G, const double* in, int64_t ld_in, double* out,
+                     int64_t ld_out, int nrhs, hipStream_t s);
+// down: out = E xhat + gb.
+void launch_hbs_down(const HbsLevelDev& L, const double* gen, const double* xhat, int64_t ld_xh,
+                     const double* gb, int64_t ld_gb, double* out, int64_t ld_out, int nrhs, hipStream_t s);
+void launch_hbs_down_f32(const HbsLevelDev& L, const float* gen, const double* xhat, int64_t ld_xh,
+                         const double* gb, int64_t ld_gb, double* out, int64_t ld_out, int nrhs, hipStream_t s);
+
+// ----------------------------------------------------------- Stokes tiles
+// r = g - A tau on one node set (exact Nystrom operator, tiles on the fly).
+// part: workspace of resid_part_doubles(n, nrhs) doubles.
+size_t resid_part_doubles(int64_t n, int nrhs);
+void launch_residual(const NodeRec* nodes, int64_t n, const double* g, const double* tau, double* r,
+                     int nrhs, double* part, hipStream_t s);
+// column sums of squares of two 2n x nrhs arrays -> out[0..nrhs) and out[nrhs..2 nrhs)
+void launch_colnorms2(const double* a, const double* b, int64_t rows, int nrhs, double* out, hipStream_t s);
+// g = sum_m S(x_i, z_m) f_m at all nodes (z, f device arrays, n_src x 2 row-major)
+void launch_stokeslet_rhs(const NodeRec* nodes, int64_t n, const double* zf, int n_src, double* g,
+                          hipStream_t s);
+// dense A(targets, sources) (2 nt x 2 ns, column-major, ld) for two node sets
+// that are either identical (self blocks on the diagonal) or disjoint.
+void launch_assemble(const NodeRec* tgt, int64_t nt, const NodeRec* src, int64_t ns, bool same,
+                     double* A, int64_t ld, hipStream_t s);
+// Rows of R = skeleton rows of Q (uniform ID format): see kern_stokes.hip.
+void launch_r_rows(const NodeRec* tnodes, const int* skel_dof, int nrows, const NodeRec* ref_nodes,
+                   const int* ref_kind, int64_t n_o, const NodeRec* pnodes, int64_t n_p, int mode,
+                   double* R, int64_t ldR, hipStream_t s);
+// Y(2 nt x ncols, row-major) = sum over source segments sign * A(tgt, seg) Omega(seg rows, :)
+// with Omega = counter-based +-1 entries; MFMA FP64.
+struct SketchSeg {
+  const NodeRec* src;
+  int64_t ns;
+  double sign;
+  int64_t omega_row0;   // first Omega row of this segment
+};
+size_t sketch_part_doubles(int64_t nt, int64_t nsrc);  // workspace of launch_sketch
+void launch_sketch(const NodeRec* tgt, int64_t nt, const SketchSeg* segs, int nseg, int ncols,
+                   uint64_t seed, double* Y, double* part, hipStream_t s);
+
+// gather / scatter between refined order and extended order
+void launch_to_ext(const double* g, int64_t ld_g, int64_t n_new, const int* new2ext, double* ext,
+                   int64_t ld_ext, int64_t n_ext_dofs, int nrhs, hipStream_t s);
+void launch_from_ext(const double* ext, int64_t ld_ext, int64_t n_new, const int* new2ext, double* out,
+                     int64_t ld_out, int nrhs, bool accumulate, hipStream_t s);
+void launch_gather_nodes(const NodeRec* src, const int* idx, int64_t n, NodeRec* dst, hipStream_t s);
+
+// ------------------------------------------------------- dense FP64 algebra
+// cooperative row ID of Y (m x ncols, row-major): pivots J (k), coefficient
+// matrix C (m x kmax, row-major) and k; then P = C C_J^{-1} written into
+// L (column-major, ld) at rows pos[i], columns col0..col0+k.
+struct RowIdResult {
+  int k = 0;
+};
+size_t rowid_work_bytes(int64_t m, int ncols, int kmax, int ngroups);
+int launch_rowid(rw_ctx* ctx, const double* Y, int64_t m, int ncols, double tol, int kmax, int* J,
+                 double* C, void* work, hipStream_t s);   // returns k (synchronizes)
+void launch_rowid_interp(const double* C, int64_t m, int kmax, int k, const int* J, const int* pos,
+                         double* L, int64_t ldL, int col0, double* inv_work /* k*k doubles */, hipStream_t s);
+// C_out = A^T B for tall A (M x ka), B (M x kb), column-major; beta: C_out = beta*C_out + ...
+size_t gemm_tn_part_doubles(int64_t M, int ka, int kb);
+void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int ka,
+                    int kb, double* C, int64_t ldc, bool add_identity, double* part, hipStream_t s);
+// Y = Y - X W (X: M x k col-major, W: k x nrhs col-major ld=k)
+void launch_sub_xw(const double* X, int64_t ldx, int64_t M, int k, const double* W, double* Y,
+                   int64_t ldy, int nrhs, hipStream_t s);
+// in-place inverse of a small k x k matrix (Gauss-Jordan, partial pivoting);
+// writes 0 / pivot index + 1 to *info (device int)
+void launch_small_inverse(double* W, int k, int* info, hipStream_t s);
+// out = Winv z (k x k times k x nrhs)
+void launch_small_gemm(const double* Winv, int k, const double* z, int nrhs, double* out, hipStream_t s);
+
+// unpivoted blocked LU of an n x n matrix (ld), in place; *info = first tiny pivot + 1
+void launch_lu_nopiv(double* A, int64_t n, int64_t ld, int* info, double* work, hipStream_t s);
+size_t lu_work_doubles(int64_t n);
+// B = U^{-1} L^{-1} B (nrhs columns, ldb) with the factors of launch_lu_nopiv
+void launch_lu_solve(const double* LU, int64_t n, int64_t ld, double* B, int64_t ldb, int nrhs,
+                     hipStream_t s);
+// C -= A B (m x kk times kk x n, all column-major)
+void launch_gemm_nn_sub(const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+                        int64_t ldc, int64_t m, int64_t n, int64_t kk, hipStream_t s);

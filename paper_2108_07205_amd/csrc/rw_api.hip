@@ -1,0 +1,746 @@
+// C ABI of the refined-wall solver (include/rw.h): objects, the static
+// reference-wall build, Algorithm 1 pre-computation per refinement and the
+// Woodbury solve with FP64 iterative refinement.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <set>
+
+#include "geometry.h"
+#include "hbs_dev.h"
+
+// ======================================================================== ctx
+// Caching allocator: a freed block goes back to ctx->cache and is reused by a
+// later request of the same or a slightly smaller size, so the per-step
+// refine / solve cycle does not call hipMalloc or hipFree once warm.
+void* dev_alloc(rw_ctx* ctx, size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  auto it = ctx->cache.lower_bound(bytes);
+  if (it != ctx->cache.end() && it->first <= bytes + bytes / 4 + 4096) {
+    void* p = it->second;
+    ctx->cached -= it->first;
+    ctx->cache.erase(it);
+    return p;
+  }
+  if (ctx->budget && ctx->used + bytes > ctx->budget) {
+    // release cached blocks before giving up
+    for (auto& kv : ctx->cache) { (void)hipFree(kv.second); ctx->used -= std::min(ctx->used, kv.first); }
+    ctx->cache.clear();
+    ctx->cached = 0;
+    if (ctx->used + bytes > ctx->budget)
+      RW_THROW(RW_ENOMEM, "HBM budget exceeded: need " + std::to_string(ctx->used + bytes) + " bytes, budget " +
+                              std::to_string(ctx->budget));
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    for (auto& kv : ctx->cache) { (void)hipFree(kv.second); ctx->used -= std::min(ctx->used, kv.first); }
+    ctx->cache.clear();
+    ctx->cached = 0;
+    e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      RW_THROW(RW_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+  }
+  ctx->used += bytes;
+  return p;
+}
+
+// Blocks return to the cache; the caller's stream order makes reuse safe
+// (all library work on a ctx is issued on its one stream).
+void dev_free(rw_ctx* ctx, void* p, size_t bytes) {
+  if (!p) return;
+  bytes = (bytes + 255) & ~size_t(255);
+  ctx->cache.emplace(bytes, p);
+  ctx->cached += bytes;
+}
+
+static void ctx_release_cache(rw_ctx* ctx) {
+  for (auto& kv : ctx->cache) {
+    (void)hipFree(kv.second);
+    ctx->used -= std::min(ctx->used, kv.first);
+  }
+  ctx->cache.clear();
+  ctx->cached = 0;
+}
+
+PhaseTimer::PhaseTimer(rw_ctx* c, const char* name, double flops, double bytes) : ctx(c), on(c && c->prof) {
+  if (!on) return;
+  p.name = name;
+  p.flops = flops;
+  p.bytes = bytes;
+  for (int i = 0; i < 2; ++i) {
+    hipEvent_t e;
+    if (!ctx->event_pool.empty()) { e = ctx->event_pool.back(); ctx->event_pool.pop_back(); }
+    else HIP_CHECK(hipEventCreate(&e));
+    (i == 0 ? p.a : p.b) = e;
+  }
+  HIP_CHECK(hipEventRecord(p.a, ctx->stream));
+}
+
+PhaseTimer::~PhaseTimer() {
+  if (!on) return;
+  if (hipEventRecord(p.b, ctx->stream) == hipSuccess) ctx->pending.push_back(p);
+}
+
+void prof_flush(rw_ctx* ctx) {
+  for (auto& q : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(q.b) == hipSuccess && hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
+      PhaseStat& st = ctx->phases[q.name];
+      st.ms += ms;
+      st.calls += 1;
+      st.flops += q.flops;
+      st.bytes += q.bytes;
+    }
+    ctx->event_pool.push_back(q.a);
+    ctx->event_pool.push_back(q.b);
+  }
+  ctx->pending.clear();
+}
+
+namespace {
+thread_local std::string g_create_err;
+
+template <class F>
+int guarded(rw_ctx* ctx, F&& f) {
+  try {
+    if (ctx) {
+      ctx->err.clear();
+      HIP_CHECK(hipSetDevice(ctx->device));
+    }
+    f();
+    return RW_OK;
+  } catch (const RwError& e) {
+    if (ctx) ctx->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->err = "host allocation failed";
+    return RW_ENOMEM;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->err = e.what();
+    return RW_EDEVICE;
+  }
+}
+}  // namespace
+
+// ======================================================================= wall
+struct rw_wall {
+  rw_ctx* ctx = nullptr;
+  rw_curve curve{};
+  int P = 0, q = 16, leaf = 64, precision = RW_F64;
+  double tol = 1e-10;
+  std::vector<double> gl_s, gl_w;
+  Discretization disc;
+  DBuf<NodeRec> d_nodes;
+  HbsDev hbs;                             // A_oo^{-1}
+  rw_wall_stats stats{};
+};
+
+namespace {
+
+void hbs_apply(rw_wall* w, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32) {
+  hbs_dev_apply(w->hbs, b, ldb, x, ldx, nrhs, use_f32);
+}
+
+void build_wall(rw_ctx* ctx, const rw_curve& cv, int P, int q, int leaf, double tol, int precision, rw_wall& w) {
+  const double t0 = wall_ms();
+  w.ctx = ctx;
+  w.curve = cv;
+  w.P = P;
+  w.q = q;
+  w.leaf = leaf;
+  w.tol = tol;
+  w.precision = precision;
+  gauss_legendre(q, w.gl_s, w.gl_w);
+  discretize(cv.a, cv.m, q, w.gl_s, w.gl_w, reference_panels(P), w.disc);
+  HbsParams prm;
+  prm.leaf_nodes = leaf;
+  prm.tol = tol;
+  HbsInverse H;
+  hbs_build_inverse(w.disc.nodes, prm, H);
+  hipStream_t s = ctx->stream;
+  w.d_nodes.alloc(ctx, w.disc.nodes.size());
+  w.d_nodes.upload(w.disc.nodes.data(), w.disc.nodes.size(), s);
+  hbs_upload(ctx, H, precision == RW_F32, w.hbs);
+  HIP_CHECK(hipStreamSynchronize(s));
+  w.stats.n_nodes = (int64_t)w.disc.nodes.size();
+  w.stats.n_levels = w.hbs.L;
+  w.stats.max_rank = H.max_rank;
+  w.stats.gen_entries = H.entries;
+  w.stats.gen_bytes_f64 = 8 * H.entries;
+  w.stats.t_build_ms = wall_ms() - t0;
+}
+
+}  // namespace
+
+// =================================================================== refined
+struct rw_refined {
+  rw_wall* wall = nullptr;
+  rw_ctx* ctx = nullptr;
+  std::vector<int32_t> level_of_panel;
+  Discretization disc;                 // refined discretization I_n
+  int64_t No = 0, Nk = 0, Nc = 0, Np = 0, Nn = 0, Next = 0;
+  DBuf<NodeRec> d_ext;                 // [reference nodes | added nodes]
+  DBuf<NodeRec> d_new, d_k, d_c, d_p;
+  DBuf<int> d_new2ext, d_ref_kind, d_pos_k, d_pos_p;
+  int k_k = 0, k_p = 0, k = 0;
+  DBuf<double> L, R, X, W;             // W: k x k inverse + k x k scratch
+  DBuf<int> d_J;                       // J_k then J_p
+  DBuf<double> App;                    // LU of A_pp (dense path)
+  bool app_hbs_on = false;             // A_pp^{-1} by a GPU-built HBS inverse instead
+  HbsDev app_hbs;
+  // solve workspace
+  DBuf<double> gext, y, z, wv, r, tmp, part, norms;
+  int ws_nrhs = 0;
+  rw_info info{};
+};
+
+namespace {
+
+void refined_ensure_ws(rw_refined* f, int nrhs) {
+  if (nrhs <= f->ws_nrhs) return;
+  const int64_t M = 2 * f->Next;
+  f->gext.alloc(f->ctx, (size_t)M * nrhs);
+  f->y.alloc(f->ctx, (size_t)M * nrhs);
+  f->z.alloc(f->ctx, (size_t)std::max(1, f->k) * nrhs);
+  f->wv.alloc(f->ctx, (size_t)std::max(1, f->k) * nrhs);
+  f->r.alloc(f->ctx, (size_t)2 * f->Nn * nrhs);
+  f->tmp.alloc(f->ctx, (size_t)2 * f->Nn * nrhs);
+  const size_t part = std::max(resid_part_doubles(f->Nn, nrhs),
+                               gemm_tn_part_doubles(M, std::max(1, f->k), nrhs));
+  f->part.alloc(f->ctx, part);
+  f->norms.alloc(f->ctx, (size_t)2 * nrhs);
+  f->ws_nrhs = nrhs;
+}
+
+// dst (2 N_n x nrhs) = (A~ + L R)^{-1} src via eq. (wood); accumulate: dst += ...
+void woodbury_apply(rw_refined* f, const double* src, double* dst, int nrhs, bool accumulate) {
+  rw_wall* w = f->wall;
+  hipStream_t s = f->ctx->stream;
+  const int64_t M = 2 * f->Next, Mo = 2 * f->No, Mp = 2 * f->Np;
+  launch_to_ext(src, 2 * f->Nn, f->Nn, f->d_new2ext.p, f->gext.p, M, M, nrhs, s);
+  // y = A~^{-1} g_ext: reference HBS inverse on the o-part, LU of A_pp on the p-part
+  {
+    const double gb = (w->precision == RW_F32 ? 4.0 : 8.0) * w->stats.gen_entries;
+    PhaseTimer t(f->ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * nrhs, gb * ((nrhs + 7) / 8));
+    hbs_apply(w, f->gext.p, M, f->y.p, M, nrhs, w->precision == RW_F32);
+  }
+  if (f->Np > 0 && f->app_hbs_on) {
+    PhaseTimer t(f->ctx, "a6_app_solve", 2.0 * f->app_hbs.entries * nrhs, 8.0 * f->app_hbs.entries * ((nrhs + 7) / 8));
+    hbs_dev_apply(f->app_hbs, f->gext.p + Mo, M, f->y.p + Mo, M, nrhs, false);
+  } else if (f->Np > 0) {
+    PhaseTimer t(f->ctx, "a6_app_solve", 2.0 * (double)Mp * Mp * nrhs, 8.0 * (double)Mp * Mp * nrhs);
+    HIP_CHECK(hipMemcpy2DAsync(f->y.p + Mo, sizeof(double) * M, f->gext.p + Mo, sizeof(double) * M,
+                               sizeof(double) * Mp, nrhs, hipMemcpyDeviceToDevice, s));
+    launch_lu_solve(f->App.p, Mp, Mp, f->y.p + Mo, M, nrhs, s);
+  }
+  if (f->k > 0) {
+    // z = R y, w = W^{-1} z, y -= X w
+    PhaseTimer t(f->ctx, "a7_woodbury", 4.0 * f->k * (double)M * nrhs, 16.0 * f->k * (double)M);
+    launch_gemm_tn(f->R.p, M, f->y.p, M, M, f->k, nrhs, f->z.p, f->k, false, f->part.p, s);
+    launch_small_gemm(f->W.p, f->k, f->z.p, nrhs, f->wv.p, s);
+    launch_sub_xw(f->X.p, M, M, f->k, f->wv.p, f->y.p, M, nrhs, s);
+  }
+  launch_from_ext(f->y.p, M, f->Nn, f->d_new2ext.p, dst, 2 * f->Nn, nrhs, accumulate, s);
+}
+
+void validate_selection(const rw_wall* w, const int32_t* ids, const int32_t* levels, int n_sel) {
+  if (n_sel < 0) RW_THROW(RW_EINVAL, "n_sel < 0");
+  if (n_sel > 0 && (!ids || !levels)) RW_THROW(RW_EINVAL, "null panel_ids or levels");
+  std::set<int32_t> seen;
+  for (int i = 0; i < n_sel; ++i) {
+    if (ids[i] < 0 || ids[i] >= w->P) RW_THROW(RW_EINVAL, "panel id " + std::to_string(ids[i]) + " out of range");
+    if (!seen.insert(ids[i]).second) RW_THROW(RW_EINVAL, "duplicate panel id " + std::to_string(ids[i]));
+    if (levels[i] < 0 || levels[i] > 8) RW_THROW(RW_EINVAL, "level outside [0, 8]");
+  }
+}
+
+// Algorithm 1 pre-computation for the refinement described by level_of_panel.
+void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_refined& f) {
+  rw_ctx* ctx = w->ctx;
+  hipStream_t s = ctx->stream;
+  const double t0 = wall_ms();
+  f.wall = w;
+  f.ctx = ctx;
+  f.level_of_panel = level_of_panel;
+  // ---- a1: geometry and index sets (Sec. 3.1)
+  std::unique_ptr<PhaseTimer> t_geo(new PhaseTimer(ctx, "a1_geometry"));
+  discretize(w->curve.a, w->curve.m, w->q, w->gl_s, w->gl_w, refined_panels(w->P, level_of_panel), f.disc);
+  const int q = w->q;
+  f.No = (int64_t)w->disc.nodes.size();
+  f.Nn = f.disc.n();
+  std::vector<int> k_ref, c_ref, new2ext(f.Nn), ref_kind(f.No, 0);
+  std::vector<NodeRec> pnodes;
+  for (int i = 0; i < w->P; ++i)
+    for (int j = 0; j < q; ++j) {
+      if (level_of_panel[i] >= 0) { c_ref.push_back(i * q + j); ref_kind[i * q + j] = 1; }
+      else k_ref.push_back(i * q + j);
+    }
+  for (size_t pi = 0; pi < f.disc.panels.size(); ++pi) {
+    const Panel& p = f.disc.panels[pi];
+    for (int j = 0; j < q; ++j) {
+      const int64_t n = (int64_t)pi * q + j;
+      if (p.added) {
+        new2ext[n] = (int)(f.No + (int64_t)pnodes.size());
+        pnodes.push_back(f.disc.nodes[n]);
+      } else {
+        new2ext[n] = p.ref_id * q + j;
+      }
+    }
+  }
+  f.Nk = (int64_t)k_ref.size();
+  f.Nc = (int64_t)c_ref.size();
+  f.Np = (int64_t)pnodes.size();
+  f.Next = f.No + f.Np;
+  const int64_t M = 2 * f.Next, Mo = 2 * f.No, Mp = 2 * f.Np;
+  f.d_ext.alloc(ctx, f.Next);
+  HIP_CHECK(hipMemcpyAsync(f.d_ext.p, w->d_nodes.p, sizeof(NodeRec) * f.No, hipMemcpyDeviceToDevice, s));
+  if (f.Np) HIP_CHECK(hipMemcpyAsync(f.d_ext.p + f.No, pnodes.data(), sizeof(NodeRec) * f.Np, hipMemcpyHostToDevice, s));
+  f.d_new2ext.alloc(ctx, f.Nn);
+  f.d_new2ext.upload(new2ext.data(), f.Nn, s);
+  f.d_ref_kind.alloc(ctx, f.No);
+  f.d_ref_kind.upload(ref_kind.data(), f.No, s);
+  f.d_new.alloc(ctx, f.Nn);
+  launch_gather_nodes(f.d_ext.p, f.d_new2ext.p, f.Nn, f.d_new.p, s);
+  std::vector<int> pos_k(2 * f.Nk), pos_p(2 * f.Np);
+  for (int64_t a = 0; a < f.Nk; ++a) { pos_k[2 * a] = 2 * k_ref[a]; pos_k[2 * a + 1] = 2 * k_ref[a] + 1; }
+  for (int64_t a = 0; a < f.Np; ++a) { pos_p[2 * a] = (int)(Mo + 2 * a); pos_p[2 * a + 1] = (int)(Mo + 2 * a + 1); }
+  f.d_pos_k.alloc(ctx, pos_k.size());
+  f.d_pos_k.upload(pos_k.data(), pos_k.size(), s);
+  f.d_pos_p.alloc(ctx, pos_p.size());
+  f.d_pos_p.upload(pos_p.data(), pos_p.size(), s);
+  {
+    DBuf<int> idx(ctx, std::max<size_t>(1, std::max(k_ref.size(), c_ref.size())));
+    f.d_k.alloc(ctx, f.Nk);
+    idx.upload(k_ref.data(), k_ref.size(), s);
+    launch_gather_nodes(w->d_nodes.p, idx.p, f.Nk, f.d_k.p, s);
+    HIP_CHECK(hipStreamSynchronize(s));
+    f.d_c.alloc(ctx, f.Nc);
+    idx.upload(c_ref.data(), c_ref.size(), s);
+    launch_gather_nodes(w->d_nodes.p, idx.p, f.Nc, f.d_c.p, s);
+    HIP_CHECK(hipStreamSynchronize(s));
+  }
+  f.d_p.alloc(ctx, f.Np);
+  if (f.Np) HIP_CHECK(hipMemcpyAsync(f.d_p.p, f.d_ext.p + f.No, sizeof(NodeRec) * f.Np, hipMemcpyDeviceToDevice, s));
+
+  t_geo.reset();
+  f.k_k = f.k_p = f.k = 0;
+  if (f.Nc > 0) {
+    // ---- a2: Q ~= L R by randomized row IDs of the k-rows [-A_kc A_kp] and p-rows A_pk
+    int ncols = ctx->opt.sketch_cols;
+    const double tol = w->tol;
+    std::vector<int> Jk, Jp;
+    DBuf<double> Yk, Yp, Ck, Cp, part;
+    DBuf<char> work;
+    DBuf<int> dJ(ctx, 256);
+    for (;;) {
+      const int kmax = ncols - 8;
+      Yk.alloc(ctx, (size_t)2 * f.Nk * ncols);
+      Yp.alloc(ctx, (size_t)2 * f.Np * ncols);
+      part.alloc(ctx, std::max(sketch_part_doubles(f.Nk, f.Nc + f.Np), sketch_part_doubles(f.Np, f.Nk)));
+      {
+        const double fl = 2.0 * ncols * (2.0 * f.Nk * 2.0 * (f.Nc + f.Np) + 2.0 * f.Np * 2.0 * f.Nk);
+        PhaseTimer t(ctx, "a2_sketch", fl, 8.0 * ncols * 2.0 * (f.Nk + f.Np));
+        SketchSeg sk[2] = {{f.d_c.p, f.Nc, -1.0, 0}, {f.d_p.p, f.Np, 1.0, 2 * f.Nc}};
+        launch_sketch(f.d_k.p, f.Nk, sk, 2, ncols, ctx->opt.seed, Yk.p, part.p, s);
+        SketchSeg sp[1] = {{f.d_k.p, f.Nk, 1.0, 0}};
+        launch_sketch(f.d_p.p, f.Np, sp, 1, ncols, ctx->opt.seed ^ 0xA5A5A5A5ull, Yp.p, part.p, s);
+      }
+      part.release();
+      Ck.alloc(ctx, (size_t)2 * f.Nk * kmax);
+      Cp.alloc(ctx, (size_t)2 * f.Np * kmax);
+      const int ng = std::max(256, ctx->n_cu);
+      work.alloc(ctx, std::max(rowid_work_bytes(2 * f.Nk, ncols, kmax, ng), rowid_work_bytes(2 * f.Np, ncols, kmax, ng)));
+      PhaseTimer t_id(ctx, "a2_row_id", 8.0 * ncols * 2.0 * (f.Nk + f.Np) * 40.0, 8.0 * ncols * 2.0 * (f.Nk + f.Np));
+      f.k_k = launch_rowid(ctx, Yk.p, 2 * f.Nk, ncols, tol, kmax, dJ.p, Ck.p, work.p, s);
+      Jk.resize(f.k_k);
+      if (f.k_k) dJ.download(Jk.data(), f.k_k, s);
+      f.k_p = launch_rowid(ctx, Yp.p, 2 * f.Np, ncols, tol, kmax, dJ.p + 128, Cp.p, work.p, s);
+      Jp.resize(f.k_p);
+      if (f.k_p) HIP_CHECK(hipMemcpyAsync(Jp.data(), dJ.p + 128, sizeof(int) * f.k_p, hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipStreamSynchronize(s));
+      const bool full = (f.k_k >= kmax) || (f.k_p >= kmax);
+      if (!full) break;
+      if (ncols >= 128) RW_THROW(RW_ESINGULAR, "rank of the update matrix exceeds the largest sketch (128 columns)");
+      ncols = (ncols < 64) ? 64 : (ncols < 96 ? 96 : 128);
+    }
+    f.k = f.k_k + f.k_p;
+    const int kmax = ncols - 8;
+    PhaseTimer t_lr(ctx, "a2_interp_rows", 0.0, 16.0 * f.k * (double)M);
+    f.L.alloc(ctx, (size_t)M * f.k);
+    HIP_CHECK(hipMemsetAsync(f.L.p, 0, sizeof(double) * M * f.k, s));
+    DBuf<double> inv(ctx, (size_t)128 * 128);
+    f.d_J.alloc(ctx, f.k);
+    f.d_J.upload(Jk.data(), f.k_k, s);
+    if (f.k_p) HIP_CHECK(hipMemcpyAsync(f.d_J.p + f.k_k, Jp.data(), sizeof(int) * f.k_p, hipMemcpyHostToDevice, s));
+    launch_rowid_interp(Ck.p, 2 * f.Nk, kmax, f.k_k, f.d_J.p, f.d_pos_k.p, f.L.p, M, 0, inv.p, s);
+    launch_rowid_interp(Cp.p, 2 * f.Np, kmax, f.k_p, f.d_J.p + f.k_k, f.d_pos_p.p, f.L.p, M, f.k_k, inv.p, s);
+    // R: skeleton rows of Q (k rows on k points, then p rows)
+    f.R.alloc(ctx, (size_t)f.k * M);
+    launch_r_rows(f.d_k.p, f.d_J.p, f.k_k, w->d_nodes.p, f.d_ref_kind.p, f.No, f.d_p.p, f.Np, 0, f.R.p, M, s);
+    launch_r_rows(f.d_p.p, f.d_J.p + f.k_k, f.k_p, w->d_nodes.p, f.d_ref_kind.p, f.No, f.d_p.p, f.Np, 1,
+                  f.R.p + (size_t)f.k_k * M, M, s);
+    HIP_CHECK(hipStreamSynchronize(s));
+  }
+  // ---- a3: A_pp^{-1}: dense LU for few added points, else a GPU-built HBS inverse
+  DBuf<int> dinfo(ctx, 4);
+  f.app_hbs_on = f.Np > ctx->opt.app_dense_max_nodes;
+  if (f.app_hbs_on) {
+    PhaseTimer t(ctx, "a3_app_hbs_build", 0.0, 0.0);
+    hbs_gpu_build(ctx, f.d_p.p, pnodes, w->leaf, w->tol, ctx->opt.seed ^ 0x3C6EF372FE94F82Bull, f.app_hbs);
+  } else if (f.Np > 0) {
+    f.App.alloc(ctx, (size_t)Mp * Mp);
+    {
+      PhaseTimer t(ctx, "a3_app_assemble", 0.0, 8.0 * (double)Mp * Mp);
+      launch_assemble(f.d_p.p, f.Np, f.d_p.p, f.Np, true, f.App.p, Mp, s);
+    }
+    {
+      PhaseTimer t(ctx, "a3_app_lu", 2.0 / 3.0 * (double)Mp * Mp * Mp, 0.0);
+      launch_lu_nopiv(f.App.p, Mp, Mp, dinfo.p, nullptr, s);
+    }
+    int info = 0;
+    HIP_CHECK(hipMemcpyAsync(&info, dinfo.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (info) RW_THROW(RW_ESINGULAR, "zero pivot " + std::to_string(info) + " in the LU of A_pp");
+  }
+  if (f.k > 0) {
+    // ---- a4: X = A~^{-1} L
+    f.X.alloc(ctx, (size_t)M * f.k);
+    HIP_CHECK(hipMemsetAsync(f.X.p, 0, sizeof(double) * M * f.k, s));
+    {
+      PhaseTimer t_x(ctx, "a4_X", 2.0 * w->stats.gen_entries * f.k_k + 2.0 * (double)Mp * Mp * f.k_p,
+                     8.0 * w->stats.gen_entries * ((f.k_k + 7) / 8));
+      if (f.k_k) hbs_apply(w, f.L.p, M, f.X.p, M, f.k_k, false);
+      if (f.k_p) {
+        double* xp = f.X.p + Mo + (size_t)f.k_k * M;
+        if (f.app_hbs_on) {
+          hbs_dev_apply(f.app_hbs, f.L.p + Mo + (size_t)f.k_k * M, M, xp, M, f.k_p, false);
+        } else {
+          HIP_CHECK(hipMemcpy2DAsync(xp, sizeof(double) * M, f.L.p + Mo + (size_t)f.k_k * M, sizeof(double) * M,
+                                     sizeof(double) * Mp, f.k_p, hipMemcpyDeviceToDevice, s));
+          launch_lu_solve(f.App.p, Mp, Mp, xp, M, f.k_p, s);
+        }
+      }
+    }
+    // ---- a5: W = I + R X and its inverse (FP64)
+    f.W.alloc(ctx, (size_t)2 * f.k * f.k);
+    PhaseTimer t_w(ctx, "a5_W", 2.0 * f.k * (double)f.k * M + 2.0 * (double)f.k * f.k * f.k, 16.0 * f.k * (double)M);
+    DBuf<double> part(ctx, gemm_tn_part_doubles(M, f.k, f.k));
+    launch_gemm_tn(f.R.p, M, f.X.p, M, M, f.k, f.k, f.W.p, f.k, true, part.p, s);
+    launch_small_inverse(f.W.p, f.k, dinfo.p + 1, s);
+    int info = 0;
+    HIP_CHECK(hipMemcpyAsync(&info, dinfo.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (info) RW_THROW(RW_ESINGULAR, "singular Woodbury operator W (pivot " + std::to_string(info) + ")");
+  }
+  HIP_CHECK(hipStreamSynchronize(s));
+  prof_flush(ctx);
+  f.info.n_k = f.Nk;
+  f.info.n_c = f.Nc;
+  f.info.n_p = f.Np;
+  f.info.k_k = f.k_k;
+  f.info.k_p = f.k_p;
+  f.info.k = f.k;
+  f.info.t_refine_ms = wall_ms() - t0;
+}
+
+void copy_nodes_out(const std::vector<NodeRec>& nd, double* xy, double* nrm, double* wts, int64_t* n_nodes) {
+  if (!n_nodes) RW_THROW(RW_EINVAL, "n_nodes is null");
+  const int64_t n = (int64_t)nd.size();
+  if ((xy || nrm || wts) && *n_nodes < n) {
+    *n_nodes = n;
+    RW_THROW(RW_EINVAL, "node arrays too small");
+  }
+  for (int64_t i = 0; i < n && (xy || nrm || wts); ++i) {
+    if (xy) { xy[2 * i] = nd[i].x; xy[2 * i + 1] = nd[i].y; }
+    if (nrm) { nrm[2 * i] = nd[i].nx; nrm[2 * i + 1] = nd[i].ny; }
+    if (wts) wts[i] = nd[i].w;
+  }
+  *n_nodes = n;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+const char* rw_create_error(void) { return g_create_err.c_str(); }
+
+int rw_ctx_create(rw_ctx** out, int device, void* hip_stream, size_t hbm_budget_bytes) {
+  g_create_err.clear();
+  if (!out) { g_create_err = "out is null"; return RW_EINVAL; }
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    g_create_err = "no HIP device available";
+    return RW_EDEVICE;
+  }
+  if (device < 0 || device >= ndev) { g_create_err = "device index out of range"; return RW_EINVAL; }
+  std::unique_ptr<rw_ctx> c(new rw_ctx());
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->budget = hbm_budget_bytes;
+  c->opt.ir_tol = 1e-13;
+  c->opt.ir_maxit = 6;
+  c->opt.sketch_cols = 64;
+  c->opt.seed = 0x5eedull;
+  c->opt.app_dense_max_nodes = 1024;
+  int rc = guarded(c.get(), [&]() {
+    hipDeviceProp_t prop;
+    HIP_CHECK(hipGetDeviceProperties(&prop, device));
+    c->n_cu = prop.multiProcessorCount;
+    c->sync_words = 256;
+    c->d_sync = (unsigned*)dev_alloc(c.get(), sizeof(unsigned) * c->sync_words);
+    HIP_CHECK(hipMemset(c->d_sync, 0, sizeof(unsigned) * c->sync_words));
+  });
+  if (rc != RW_OK) { g_create_err = c->err; return rc; }
+  *out = c.release();
+  return RW_OK;
+}
+
+void rw_ctx_destroy(rw_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->d_sync) dev_free(ctx, ctx->d_sync, sizeof(unsigned) * ctx->sync_words);
+  ctx_release_cache(ctx);
+  for (auto& q : ctx->pending) { (void)hipEventDestroy(q.a); (void)hipEventDestroy(q.b); }
+  for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+const char* rw_last_error(const rw_ctx* ctx) { return ctx ? ctx->err.c_str() : "null ctx"; }
+
+int rw_set_options(rw_ctx* ctx, const rw_options* opt) {
+  if (!ctx || !opt) return RW_EINVAL;
+  return guarded(ctx, [&]() {
+    if (!(opt->ir_tol >= 0) || opt->ir_maxit < 0 || opt->app_dense_max_nodes < 0)
+      RW_THROW(RW_EINVAL, "bad refinement options");
+    if (opt->sketch_cols != 32 && opt->sketch_cols != 64 && opt->sketch_cols != 96 && opt->sketch_cols != 128)
+      RW_THROW(RW_EINVAL, "sketch_cols must be 32, 64, 96 or 128");
+    ctx->opt = *opt;
+  });
+}
+
+int rw_get_options(const rw_ctx* ctx, rw_options* opt) {
+  if (!ctx || !opt) return RW_EINVAL;
+  *opt = ctx->opt;
+  return RW_OK;
+}
+
+size_t rw_ctx_bytes(const rw_ctx* ctx) { return ctx ? ctx->used : 0; }
+
+int rw_ctx_trim(rw_ctx* ctx) {
+  if (!ctx) return RW_EINVAL;
+  return guarded(ctx, [&]() {
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    ctx_release_cache(ctx);
+  });
+}
+
+int rw_profile_enable(rw_ctx* ctx, int on) {
+  if (!ctx) return RW_EINVAL;
+  return guarded(ctx, [&]() {
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    prof_flush(ctx);
+    ctx->prof = on != 0;
+  });
+}
+
+int rw_profile_reset(rw_ctx* ctx) {
+  if (!ctx) return RW_EINVAL;
+  return guarded(ctx, [&]() {
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    prof_flush(ctx);
+    ctx->phases.clear();
+  });
+}
+
+int64_t rw_profile_json(rw_ctx* ctx, char* buf, int64_t len) {
+  if (!ctx) return RW_EINVAL;
+  std::string js = "{";
+  bool first = true;
+  (void)hipStreamSynchronize(ctx->stream);
+  prof_flush(ctx);
+  for (auto& kv : ctx->phases) {
+    char tmp[512];
+    snprintf(tmp, sizeof tmp, "%s\"%s\": {\"ms\": %.6f, \"calls\": %lld, \"flops\": %.6e, \"bytes\": %.6e}",
+             first ? "" : ", ", kv.first.c_str(), kv.second.ms, (long long)kv.second.calls, kv.second.flops,
+             kv.second.bytes);
+    js += tmp;
+    first = false;
+  }
+  js += "}";
+  if (buf && len > 0) {
+    const size_t n = std::min<size_t>(js.size(), (size_t)len - 1);
+    memcpy(buf, js.data(), n);
+    buf[n] = 0;
+  }
+  return (int64_t)js.size() + 1;
+}
+
+int rw_wall_build(rw_ctx* ctx, const rw_curve* curve, int32_t n_panels, int32_t order, int32_t leaf_nodes,
+                  double id_tol, int32_t precision, rw_wall** out) {
+  if (!ctx) return RW_EINVAL;
+  return guarded(ctx, [&]() {
+    if (!out || !curve) RW_THROW(RW_EINVAL, "null argument");
+    *out = nullptr;
+    if (order < 2 || order > 32) RW_THROW(RW_EINVAL, "order outside [2, 32]");
+    if (n_panels < 2 || leaf_nodes < order || leaf_nodes % order) RW_THROW(RW_EINVAL, "bad panel / leaf sizes");
+    if (!(id_tol > 0 && id_tol < 1)) RW_THROW(RW_EINVAL, "id_tol outside (0, 1)");
+    if (precision != RW_F64 && precision != RW_F32) RW_THROW(RW_EINVAL, "unknown precision");
+    if (!(std::fabs(curve->a) < 1.0) || curve->m < 0) RW_THROW(RW_EINVAL, "curve must have |a| < 1, m >= 0");
+    std::unique_ptr<rw_wall> w(new rw_wall());
+    build_wall(ctx, *curve, n_panels, order, leaf_nodes, id_tol, precision, *w);
+    *out = w.release();
+  });
+}
+
+void rw_wall_free(rw_wall* w) {
+  if (!w) return;
+  (void)hipSetDevice(w->ctx->device);
+  delete w;
+}
+
+int rw_wall_stats_get(const rw_wall* w, rw_wall_stats* st) {
+  if (!w || !st) return RW_EINVAL;
+  *st = w->stats;
+  return RW_OK;
+}
+
+int rw_wall_nodes(const rw_wall* w, double* xy, double* nrm, double* wts, int64_t* n_nodes) {
+  if (!w) return RW_EINVAL;
+  return guarded(w->ctx, [&]() { copy_nodes_out(w->disc.nodes, xy, nrm, wts, n_nodes); });
+}
+
+int rw_hbs_apply(rw_wall* w, const double* b, int32_t nrhs, double* x) {
+  if (!w) return RW_EINVAL;
+  return guarded(w->ctx, [&]() {
+    if (nrhs <= 0 || !b || !x) RW_THROW(RW_EINVAL, "bad arguments");
+    const int64_t n2 = 2 * (int64_t)w->disc.nodes.size();
+    hbs_apply(w, b, n2, x, n2, nrhs, w->precision == RW_F32);
+    KERNEL_CHECK("hbs_apply");
+  });
+}
+
+int rw_refine(rw_wall* w, const int32_t* ids, const int32_t* levels, int32_t n_sel, rw_refined** out) {
+  if (!w) return RW_EINVAL;
+  return guarded(w->ctx, [&]() {
+    if (!out) RW_THROW(RW_EINVAL, "out is null");
+    *out = nullptr;
+    validate_selection(w, ids, levels, n_sel);
+    std::vector<int32_t> lop(w->P, -1);
+    for (int i = 0; i < n_sel; ++i) lop[ids[i]] = levels[i];
+    std::unique_ptr<rw_refined> f(new rw_refined());
+    build_refined(w, lop, *f);
+    *out = f.release();
+  });
+}
+
+int rw_coarsen(rw_refined* f, const int32_t* ids, int32_t n_sel) {
+  if (!f) return RW_EINVAL;
+  return guarded(f->ctx, [&]() {
+    if (n_sel < 0 || (n_sel > 0 && !ids)) RW_THROW(RW_EINVAL, "bad arguments");
+    std::vector<int32_t> lop = f->level_of_panel;
+    std::set<int32_t> seen;
+    for (int i = 0; i < n_sel; ++i) {
+      if (ids[i] < 0 || ids[i] >= f->wall->P || lop[ids[i]] < 0)
+        RW_THROW(RW_EINVAL, "panel " + std::to_string(ids[i]) + " is not refined");
+      if (!seen.insert(ids[i]).second) RW_THROW(RW_EINVAL, "duplicate panel id");
+      lop[ids[i]] = -1;
+    }
+    std::unique_ptr<rw_refined> g(new rw_refined());
+    build_refined(f->wall, lop, *g);
+    std::swap(*f, *g);
+  });
+}
+
+void rw_refined_free(rw_refined* f) {
+  if (!f) return;
+  (void)hipSetDevice(f->ctx->device);
+  delete f;
+}
+
+int rw_refined_info(const rw_refined* f, rw_info* info) {
+  if (!f || !info) return RW_EINVAL;
+  *info = f->info;
+  return RW_OK;
+}
+
+int rw_nodes(const rw_refined* f, double* xy, double* nrm, double* wts, int64_t* n_nodes) {
+  if (!f) return RW_EINVAL;
+  return guarded(f->ctx, [&]() { copy_nodes_out(f->disc.nodes, xy, nrm, wts, n_nodes); });
+}
+
+int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau) {
+  if (!f) return RW_EINVAL;
+  int rc = guarded(f->ctx, [&]() {
+    if (nrhs <= 0 || !g || !tau) RW_THROW(RW_EINVAL, "bad arguments");
+    const double t0 = wall_ms();
+    hipStream_t s = f->ctx->stream;
+    refined_ensure_ws(f, nrhs);
+    const int64_t n2 = 2 * f->Nn;
+    woodbury_apply(f, g, tau, nrhs, false);
+    const rw_options& o = f->ctx->opt;
+    std::vector<double> nrm(2 * nrhs);
+    int it = 0;
+    double worst = 0;
+    for (;;) {
+      {
+        PhaseTimer t(f->ctx, "a8_residual", 26.0 * (double)f->Nn * f->Nn * nrhs, 0.0);
+        launch_residual(f->d_new.p, f->Nn, g, tau, f->r.p, nrhs, f->part.p, s);
+      }
+      launch_colnorms2(f->r.p, g, n2, nrhs, f->norms.p, s);
+      HIP_CHECK(hipMemcpyAsync(nrm.data(), f->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipStreamSynchronize(s));
+      worst = 0;
+      for (int c = 0; c < nrhs; ++c) {
+        const double rel = nrm[nrhs + c] > 0 ? std::sqrt(nrm[c] / nrm[nrhs + c]) : std::sqrt(nrm[c]);
+        worst = std::max(worst, std::isfinite(rel) ? rel : INFINITY);
+      }
+      if (worst <= o.ir_tol || it >= o.ir_maxit) break;
+      woodbury_apply(f, f->r.p, tau, nrhs, true);
+      ++it;
+    }
+    prof_flush(f->ctx);
+    f->info.ir_iters = it;
+    f->info.resid = worst;
+    f->info.t_solve_ms = wall_ms() - t0;
+    if (!(worst <= o.ir_tol) && o.ir_maxit > 0)
+      RW_THROW(RW_ENOCONV, "refinement stopped at relative residual " + std::to_string(worst));
+  });
+  return rc;
+}
+
+int rw_residual(rw_refined* f, const double* g, const double* tau, int32_t nrhs, double* r) {
+  if (!f) return RW_EINVAL;
+  return guarded(f->ctx, [&]() {
+    if (nrhs <= 0 || !g || !tau || !r) RW_THROW(RW_EINVAL, "bad arguments");
+    refined_ensure_ws(f, nrhs);
+    launch_residual(f->d_new.p, f->Nn, g, tau, r, nrhs, f->part.p, f->ctx->stream);
+  });
+}
+
+int rw_stokeslet_rhs(rw_refined* f, const double* z, const double* fv, int32_t n_src, double* g) {
+  if (!f) return RW_EINVAL;
+  return guarded(f->ctx, [&]() {
+    if (n_src <= 0 || !z || !fv || !g) RW_THROW(RW_EINVAL, "bad arguments");
+    std::vector<double> zf(4 * (size_t)n_src);
+    for (int m = 0; m < n_src; ++m) {
+      zf[4 * m] = z[2 * m];
+      zf[4 * m + 1] = z[2 * m + 1];
+      zf[4 * m + 2] = fv[2 * m];
+      zf[4 * m + 3] = fv[2 * m + 1];
+    }
+    DBuf<double> d(f->ctx, zf.size());
+    d.upload(zf.data(), zf.size(), f->ctx->stream);
+    launch_stokeslet_rhs(f->d_new.p, f->Nn, d.p, n_src, g, f->ctx->stream);
+    HIP_CHECK(hipStreamSynchronize(f->ctx->stream));
+  });
+}
+
+}  // extern "C"
