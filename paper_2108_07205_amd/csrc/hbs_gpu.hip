@@ -31,6 +31,8 @@ constexpr int SK_KCAP = 88;    // largest node rank (sketch columns minus oversa
 constexpr int SK_NP = 48;      // proxy points
 constexpr int SK_EXTRA = 16;   // Gram-Schmidt steps past the tolerance rank
 constexpr double SK_RATIO = 2.0;
+constexpr int INV_LDS_N = 128; // node blocks up to this size are inverted in LDS
+constexpr int INV_LDS_BYTES = 150 * 1024;
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
@@ -67,14 +69,22 @@ __device__ __forceinline__ void a_blk(const NodeRec& t, const NodeRec& s, bool s
 // ---------------------------------------------------------------- 1. sketch
 // grid (nodes, 2): side 0 = row sketch of candr, side 1 = column sketch of candc.
 // thread t: candidate row (t & 127) of the current pass, columns 48*(t >> 7) ..
+// grid (nodes, 2, nsplit): split z handles nodes [z N / nsplit, (z+1) N / nsplit);
+// the last split also adds the proxy and nullspace entities.  Partial sums go
+// to part[z] (same layout as S), summed by node_sketch_sum_kernel.
 __global__ __launch_bounds__(256) void node_sketch_kernel(const GNode* __restrict__ gn, const int* __restrict__ candr,
                                                           const int* __restrict__ candc,
                                                           const NodeRec* __restrict__ nd, int64_t N, uint64_t seed,
-                                                          double* __restrict__ Sr, double* __restrict__ Sc) {
+                                                          int64_t part_stride, double* __restrict__ Sr,
+                                                          double* __restrict__ Sc) {
+  __shared__ NodeRec snd[256];
   const GNode g = gn[blockIdx.x];
   const int side = blockIdx.y;
+  const int z = blockIdx.z, nz = gridDim.z;
   const int* cand = (side == 0 ? candr : candc) + g.cand_off;
-  double* S = (side == 0 ? Sr : Sc) + g.cand_off * SK_R;
+  double* S = (side == 0 ? Sr : Sc) + g.cand_off * SK_R + (int64_t)z * part_stride;
+  const int64_t j_lo = (z * N) / nz, j_hi = ((z + 1) * N) / nz;
+  const bool last = (z == nz - 1);
   const int half = threadIdx.x >> 7, ri = threadIdx.x & 127;
   const double rp2 = g.rp * g.rp;
   const double wp = 2.0 * M_PI * g.rp / SK_NP;
@@ -92,17 +102,37 @@ __global__ __launch_bounds__(256) void node_sketch_kernel(const GNode* __restric
     // the proxy circle -- the proxy points (side 0: 4 entries, side 1: 2) and
     // the nullspace column / flux row (1 entry).  Each entry e with Omega row
     // `pos` is folded into the 48 accumulators by one shared loop.
-    const int64_t n_ent = N + SK_NP + 1;
+    // the proxies stand for every node outside the circle: does one exist?
     bool any_far = false;
-    for (int64_t j = 0; j < n_ent; ++j) {
+    if (last) {
+      for (int64_t j0 = 0; j0 < N && !any_far; j0 += 256) {
+        const int64_t jj = j0 + threadIdx.x;
+        int far = 0;
+        if (jj < N && !(jj >= g.n0 && jj < g.n1)) {
+          const double dx = nd[jj].x - g.cx, dy = nd[jj].y - g.cy;
+          far = dx * dx + dy * dy >= rp2;
+        }
+        any_far = __syncthreads_or(far) != 0;
+      }
+    }
+    const int64_t n_ent = last ? N + SK_NP + 1 : j_hi;
+    for (int64_t j = j_lo; j < n_ent; ++j) {
+      if (j < j_hi && ((j - j_lo) & 255) == 0) {
+        // stage the next 256 nodes of this split through LDS
+        __syncthreads();
+        const int64_t jj = j + threadIdx.x;
+        if (jj < j_hi) snd[threadIdx.x] = nd[jj];
+        __syncthreads();
+      }
+      if (j >= j_hi && j < N) { j = N - 1; continue; }   // jump to the proxies
       double e[4];
       int64_t pos0 = 0;
       int cnt = 0;
       if (j < N) {
         if (j >= g.n0 && j < g.n1) continue;
-        const NodeRec q = nd[j];
+        const NodeRec q = snd[(j - j_lo) & 255];
         const double dx = q.x - g.cx, dy = q.y - g.cy;
-        if (dx * dx + dy * dy >= rp2) { any_far = true; continue; }
+        if (dx * dx + dy * dy >= rp2) continue;
         double B[4];
         if (side == 0) {
           a_blk(a, q, false, B);                 // A(a, j)
@@ -165,80 +195,95 @@ __global__ __launch_bounds__(256) void node_sketch_kernel(const GNode* __restric
   }
 }
 
+__global__ __launch_bounds__(256) void node_sketch_sum_kernel(const double* __restrict__ part, int nsplit,
+                                                              int64_t len, int64_t stride, double* __restrict__ S) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= len) return;
+  double v = 0.0;
+  for (int z = 0; z < nsplit; ++z) v += part[i + z * stride];
+  S[i] = v;
+}
+
 // ---------------------------------------------------------------- 2. row ID
-// grid (nodes, 2); rows of the sketch in LDS; pivoted Gram-Schmidt (two passes).
-// Outputs per (node, side): piv[SK_KCAP], C (m x SK_KCAP row-major at cand_off*SK_KCAP),
-// info[0] = tolerance rank, info[1] = steps taken.
-__global__ __launch_bounds__(256) void node_id_kernel(const GNode* __restrict__ gn, const double* __restrict__ Sr,
+// (value, index) maximum over a wavefront; ties go to the lower index, index
+// -1 marks an empty slot.
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double v2 = __shfl_xor(v, off);
+    const int i2 = __shfl_xor(i, off);
+    if (i2 >= 0 && (i < 0 || v2 > v || (v2 == v && i2 < i))) { v = v2; i = i2; }
+  }
+}
+
+// grid (nodes, 2), 512 threads: sketch row i lives in the registers of
+// threads 2i and 2i+1 (48 columns each); pivoted Gram-Schmidt with two
+// projection passes.  Outputs per (node, side): piv[SK_KCAP], C (m x SK_KCAP
+// row-major at cand_off*SK_KCAP), info[0] = tolerance rank, info[1] = steps.
+__global__ __launch_bounds__(512) void node_id_kernel(const GNode* __restrict__ gn, const double* __restrict__ Sr,
                                                       const double* __restrict__ Sc, double tol2,
                                                       int* __restrict__ piv, double* __restrict__ Cr,
                                                       double* __restrict__ Cc, int* __restrict__ info) {
-  extern __shared__ double sh[];
+  __shared__ double q[SK_R];
+  __shared__ double rv[8];
+  __shared__ int ri[8];
   const GNode g = gn[blockIdx.x];
   const int side = blockIdx.y;
   const int m = g.m, tid = threadIdx.x;
+  const int i = tid >> 1, h = tid & 1;
+  const bool valid = i < m;
   const double* S = (side == 0 ? Sr : Sc) + g.cand_off * SK_R;
   double* C = (side == 0 ? Cr : Cc) + g.cand_off * SK_KCAP;
   int* pv = piv + ((int64_t)blockIdx.x * 2 + side) * SK_KCAP;
-  constexpr int LD = SK_R + 1;
-  double* Y = sh;                    // m x LD
-  double* q = Y + m * LD;            // SK_R
-  double* rn = q + SK_R;             // m
-  double* rv = rn + m;               // 256
-  int* ri = (int*)(rv + 256);        // 256
-  for (int idx = tid; idx < m * SK_R; idx += 256) Y[(idx / SK_R) * LD + idx % SK_R] = S[idx];
-  __syncthreads();
-  for (int i = tid; i < m; i += 256) {
-    double s = 0;
-    for (int c = 0; c < SK_R; ++c) s += Y[i * LD + c] * Y[i * LD + c];
-    rn[i] = s;
-  }
-  __syncthreads();
+  double y[48];
+#pragma unroll
+  for (int c = 0; c < 48; ++c) y[c] = valid ? S[(int64_t)i * SK_R + h * 48 + c] : 0.0;
+  auto row_norm = [&]() {
+    double t = 0.0;
+#pragma unroll
+    for (int c = 0; c < 48; ++c) t += y[c] * y[c];
+    return t + __shfl_xor(t, 1);
+  };
+  double nrm = row_norm();
+  bool sel = !valid;
   double n0 = 0;
   int rank = -1, step = 0;
   const int kmax = min(SK_KCAP, m);
   for (; step < kmax; ++step) {
-    double bv = -1.0;
-    int bi = -1;
-    for (int i = tid; i < m; i += 256)
-      if (rn[i] > bv || (rn[i] == bv && bi >= 0 && i < bi)) { bv = rn[i]; bi = i; }
-    rv[tid] = bv;
-    ri[tid] = bi;
+    double v = sel ? -1.0 : nrm;
+    int idx = sel ? -1 : i;
+    wave_argmax(v, idx);
+    if ((tid & 63) == 0) { rv[tid >> 6] = v; ri[tid >> 6] = idx; }
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) {
-        const double v2 = rv[tid + w];
-        const int i2 = ri[tid + w];
-        if (i2 >= 0 && (v2 > rv[tid] || (v2 == rv[tid] && (ri[tid] < 0 || i2 < ri[tid])))) { rv[tid] = v2; ri[tid] = i2; }
-      }
-      __syncthreads();
-    }
-    const double v = rv[0];
-    const int p = ri[0];
-    __syncthreads();
+    v = rv[0];
+    int p = ri[0];
+    for (int w = 1; w < 8; ++w)
+      if (ri[w] >= 0 && (p < 0 || rv[w] > v || (rv[w] == v && ri[w] < p))) { v = rv[w]; p = ri[w]; }
     if (step == 0) n0 = v;
     if (rank < 0 && !(v > tol2 * n0)) rank = step;
     if ((rank >= 0 && step >= rank + SK_EXTRA) || p < 0 || !(v > 0.0)) break;
-    const double inv = 1.0 / sqrt(v);
-    for (int c = tid; c < SK_R; c += 256) q[c] = Y[p * LD + c] * inv;
-    __syncthreads();
-    if (tid == 0) pv[step] = p;
-    for (int i = tid; i < m; i += 256) {
-      double* row = Y + i * LD;
-      double cf = 0;
-      for (int pass = 0; pass < 2; ++pass) {
-        double d = 0;
-        for (int c = 0; c < SK_R; ++c) d += row[c] * q[c];
-        for (int c = 0; c < SK_R; ++c) row[c] -= d * q[c];
-        cf += d;
-      }
-      C[(int64_t)i * SK_KCAP + step] = cf;
-      if (rn[i] >= 0.0) {
-        double s = 0;
-        for (int c = 0; c < SK_R; ++c) s += row[c] * row[c];
-        rn[i] = (i == p) ? -1.0 : s;
-      }
+    if (i == p) {
+      const double inv = 1.0 / sqrt(v);
+#pragma unroll
+      for (int c = 0; c < 48; ++c) q[h * 48 + c] = y[c] * inv;
     }
+    if (tid == 0) pv[step] = p;
+    __syncthreads();
+    const double* qh = q + h * 48;
+    double cf = 0.0;
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      double d = 0.0;
+#pragma unroll
+      for (int c = 0; c < 48; ++c) d += y[c] * qh[c];
+      d += __shfl_xor(d, 1);
+#pragma unroll
+      for (int c = 0; c < 48; ++c) y[c] -= d * qh[c];
+      cf += d;
+    }
+    if (valid && h == 0) C[(int64_t)i * SK_KCAP + step] = cf;
+    if (i == p) sel = true;
+    nrm = row_norm();
     __syncthreads();
   }
   if (tid == 0) {
@@ -296,73 +341,87 @@ __global__ __launch_bounds__(256) void node_interp_kernel(const GNode* __restric
 }
 
 // ---------------------------------------------------------------- 4. inverse
-// One workgroup: in-place Gauss-Jordan inverse with partial pivoting of
-// A (n x n, ld n) into Inv; returns false on a zero / non-finite pivot.
-__device__ bool wg_inverse(double* A, double* Inv, int n, double* rv, int* ri) {
+// One workgroup of 256 threads: in-place Gauss-Jordan inverse with partial
+// pivoting of A (n x n, ld n, n <= 256; LDS or global): the pivot row is
+// scaled, every other row is eliminated with the pivot column's entry replaced
+// by the running inverse, and the recorded row interchanges are undone as
+// column interchanges at the end.  Rows are owned by threads (two per row when
+// n <= 128), so no index division is needed.  perm: n ints of scratch; f: n
+// doubles of scratch.  Returns false on a zero / non-finite pivot.
+__device__ bool wg_inverse_inplace(double* A, int n, int* perm, double* f, double* rv, int* ri) {
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < n * n; idx += 256) Inv[idx] = ((idx % n) == (idx / n)) ? 1.0 : 0.0;
-  __syncthreads();
+  const bool two = n <= 128;
+  const int row = two ? (tid & 127) : tid;
+  const int half = two ? (tid >> 7) : 0;
+  const int cw = two ? (n + 1) / 2 : n;
+  const int c0 = half * cw, c1 = min(n, c0 + cw);
   for (int j = 0; j < n; ++j) {
-    double bv = -1.0;
-    int bi = -1;
-    for (int i = j + tid; i < n; i += 256) {
-      const double v = fabs(A[i + (int64_t)j * n]);
-      if (v > bv) { bv = v; bi = i; }
-    }
-    rv[tid] = bv;
-    ri[tid] = bi;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w && ri[tid + w] >= 0 && (rv[tid + w] > rv[tid] || (rv[tid + w] == rv[tid] && ri[tid + w] < ri[tid]))) {
-        rv[tid] = rv[tid + w];
-        ri[tid] = ri[tid + w];
+    if (tid < 64) {
+      double bv = -1.0;
+      int bi = -1;
+      for (int i = j + tid; i < n; i += 64) {
+        const double v = fabs(A[i + j * n]);
+        if (v > bv || bi < 0) { bv = v; bi = i; }
       }
-      __syncthreads();
+      wave_argmax(bv, bi);
+      if (tid == 0) { rv[0] = bv; ri[0] = bi; }
     }
-    const int p = ri[0];
-    const double pvabs = rv[0];
     __syncthreads();
-    if (p < 0 || !(pvabs > 0.0) || !isfinite(pvabs)) return false;
+    const int p = ri[0];
+    const double pabs = rv[0];
+    if (p < 0 || !(pabs > 0.0) || !isfinite(pabs)) return false;
+    if (tid == 0) perm[j] = p;
     if (p != j)
       for (int c = tid; c < n; c += 256) {
-        double t = A[j + (int64_t)c * n]; A[j + (int64_t)c * n] = A[p + (int64_t)c * n]; A[p + (int64_t)c * n] = t;
-        t = Inv[j + (int64_t)c * n]; Inv[j + (int64_t)c * n] = Inv[p + (int64_t)c * n]; Inv[p + (int64_t)c * n] = t;
+        const double t = A[j + c * n];
+        A[j + c * n] = A[p + c * n];
+        A[p + c * n] = t;
       }
     __syncthreads();
-    const double sc = 1.0 / A[j + (int64_t)j * n];
+    const double pinv = 1.0 / A[j + j * n];
+    if (tid < n) f[tid] = (tid == j) ? 0.0 : A[tid + j * n];
     __syncthreads();
-    for (int c = tid; c < n; c += 256) {
-      A[j + (int64_t)c * n] *= sc;
-      Inv[j + (int64_t)c * n] *= sc;
+    for (int c = tid; c < n; c += 256) A[j + c * n] = (c == j) ? pinv : A[j + c * n] * pinv;
+    __syncthreads();
+    if (row < n && row != j) {
+      const double fr = f[row];
+      for (int c = c0; c < c1; ++c)
+        A[row + c * n] = (c == j) ? -fr * pinv : A[row + c * n] - fr * A[j + c * n];
     }
     __syncthreads();
-    for (int idx = tid; idx < n * n; idx += 256) {
-      const int i = idx % n, c = idx / n;
-      if (i == j) continue;
-      const double f = A[i + (int64_t)j * n];
-      if (c != j) A[i + (int64_t)c * n] -= f * A[j + (int64_t)c * n];
-      Inv[i + (int64_t)c * n] -= f * Inv[j + (int64_t)c * n];
-    }
-    __syncthreads();
-    for (int i = tid; i < n; i += 256)
-      if (i != j) A[i + (int64_t)j * n] = 0.0;
+  }
+  for (int j = n - 1; j >= 0; --j) {
+    const int p = perm[j];
+    if (p != j)
+      for (int i = tid; i < n; i += 256) {
+        const double t = A[i + j * n];
+        A[i + j * n] = A[i + p * n];
+        A[i + p * n] = t;
+      }
     __syncthreads();
   }
   return true;
 }
 
-// C (m x n, ldc) = alpha op(A) op(B) + beta C, all column-major, one workgroup.
+// C (m x n, ldc) = alpha op(A) op(B) + beta C, all column-major, one
+// workgroup of 256 threads; output (i, j) walks the tile without division.
 __device__ void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda,
                         const double* B, int ldb, double beta, double* C, int ldc) {
-  for (int idx = threadIdx.x; idx < m * n; idx += 256) {
-    const int i = idx % m, j = idx / m;
-    double s = 0;
-    for (int l = 0; l < k; ++l) {
-      const double a = ta ? A[l + (int64_t)i * lda] : A[i + (int64_t)l * lda];
-      const double b = tb ? B[j + (int64_t)l * ldb] : B[l + (int64_t)j * ldb];
-      s += a * b;
+  if (m > 0 && n > 0) {
+    int i = threadIdx.x % m, j = threadIdx.x / m;
+    const int di = 256 % m, dj = 256 / m;
+    for (; j < n;) {
+      double s = 0;
+      for (int l = 0; l < k; ++l) {
+        const double a = ta ? A[l + (int64_t)i * lda] : A[i + (int64_t)l * lda];
+        const double b = tb ? B[j + (int64_t)l * ldb] : B[l + (int64_t)j * ldb];
+        s += a * b;
+      }
+      C[i + (int64_t)j * ldc] = alpha * s + (beta == 0.0 ? 0.0 : beta * C[i + (int64_t)j * ldc]);
+      i += di;
+      j += dj;
+      if (i >= m) { i -= m; ++j; }
     }
-    C[i + (int64_t)j * ldc] = alpha * s + (beta == 0.0 ? 0.0 : beta * C[i + (int64_t)j * ldc]);
   }
   __syncthreads();
 }
@@ -378,14 +437,18 @@ __global__ __launch_bounds__(256) void node_inverse_kernel(const GNode* __restri
                                                            const double* __restrict__ dhat_ch, double* __restrict__ dhat,
                                                            double* __restrict__ ws, double* __restrict__ gen,
                                                            double* __restrict__ groot, int* __restrict__ fail) {
-  __shared__ double rv[256];
-  __shared__ int ri[256];
+  __shared__ double rv[4];
+  __shared__ int ri[4];
+  __shared__ int perm[256];
+  __shared__ double fsc[256];
+  extern __shared__ double sA[];       // n x n when the node fits in LDS, then k x k
   const GNode g = gn[blockIdx.x];
   const int n = g.m, k = g.k, tid = threadIdx.x;
   const int* cr = candr + g.cand_off;
   const int* cc = candc + g.cand_off;
-  double* Dm = ws + g.ws_off;          // n x n
-  double* Inv = Dm + (int64_t)n * n;   // n x n
+  const bool in_lds = n <= INV_LDS_N;
+  double* Dm = in_lds ? sA : ws + g.ws_off;   // n x n; becomes D^-1 in place
+  double* Inv = Dm;
   // assemble D
   if (is_leaf) {
     for (int idx = tid; idx < n * n; idx += 256) {
@@ -415,7 +478,7 @@ __global__ __launch_bounds__(256) void node_inverse_kernel(const GNode* __restri
     }
   }
   __syncthreads();
-  if (!wg_inverse(Dm, Inv, n, rv, ri)) {
+  if (!wg_inverse_inplace(Dm, n, perm, fsc, rv, ri)) {
     if (tid == 0) atomicExch(fail, 1);
     return;
   }
@@ -425,14 +488,17 @@ __global__ __launch_bounds__(256) void node_inverse_kernel(const GNode* __restri
   }
   const double* Un = U + g.uv_off;
   const double* Vn = V + g.uv_off;
-  double* DinvU = Inv + (int64_t)n * n;        // n x k (after D and D^-1)
+  double* DinvU = ws + g.ws_off + (int64_t)n * n;  // n x k (after the global D slot)
   double* VtDinv = DinvU + (int64_t)n * k;     // k x n
   double* Sm = VtDinv + (int64_t)k * n;        // k x k
-  double* Si = Sm + (int64_t)k * k;            // k x k
+  // the k x k inverse goes to LDS behind D^-1 when both fit
+  double* Si = (in_lds && (n * n + k * k) * 8 <= INV_LDS_BYTES) ? sA + n * n : Sm + (int64_t)k * k;
   wg_gemm(false, false, n, k, n, 1.0, Inv, n, Un, n, 0.0, DinvU, n);
   wg_gemm(true, false, k, n, n, 1.0, Vn, n, Inv, n, 0.0, VtDinv, k);
   wg_gemm(false, false, k, k, n, 1.0, VtDinv, k, Un, n, 0.0, Sm, k);
-  if (!wg_inverse(Sm, Si, k, rv, ri)) {
+  for (int idx = tid; idx < k * k; idx += 256) Si[idx] = Sm[idx];
+  __syncthreads();
+  if (!wg_inverse_inplace(Si, k, perm, fsc, rv, ri)) {
     if (tid == 0) atomicExch(fail, 2);
     return;
   }
@@ -625,6 +691,7 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
   DBuf<double> dhA(ctx, (int64_t(1) << L) * SK_KCAP * SK_KCAP), dhB(ctx, (int64_t(1) << L) * SK_KCAP * SK_KCAP);
   DBuf<double> ws(ctx, (int64_t(1) << L) * (int64_t)mmax * mmax * 2);
   DBuf<int64_t> dpar(ctx, (size_t)(int64_t(1) << L));
+  DBuf<double> part_r, part_c;
   w.gen.alloc(ctx, gen_bound);
   HIP_CHECK(hipMemsetAsync(fail.p, 0, sizeof(int) * 4, s));
   // leaf candidate lists: all dofs of the range
@@ -656,12 +723,20 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     for (int j = 0; j < nn; ++j) { gl[j].cand_off = off; off += gl[j].m; mx = std::max(mx, gl[j].m); }
     if (mx > mmax) RW_THROW(RW_ESINGULAR, "HBS node input exceeds the sketch bound");
     dg.upload(gl.data(), nn, s);
-    hipLaunchKernelGGL(node_sketch_kernel, dim3(nn, 2), dim3(256), 0, s, dg.p, candr.p, candc.p, d_nodes, N,
-                       seed + 7919ull * l, Sr.p, Sc.p);
-    KERNEL_CHECK("node_sketch");
-    const size_t sh = sizeof(double) * ((size_t)mx * (SK_R + 1) + SK_R + mx + 256) + sizeof(int) * 256;
-    HIP_CHECK(hipFuncSetAttribute((const void*)node_id_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
-    hipLaunchKernelGGL(node_id_kernel, dim3(nn, 2), dim3(256), sh, s, dg.p, Sr.p, Sc.p, tol * tol, piv.p, Cr.p, Cc.p,
+    {
+      // split each node's entity range so every level fills the device
+      int nsplit = (int)std::min<int64_t>(64, std::max<int64_t>(1, 1024 / (2 * nn)));
+      nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, N / 64));
+      const int64_t len = off * SK_R;
+      if (part_r.n < (size_t)(len * nsplit)) { part_r.alloc(ctx, len * nsplit); part_c.alloc(ctx, len * nsplit); }
+      hipLaunchKernelGGL(node_sketch_kernel, dim3(nn, 2, nsplit), dim3(256), 0, s, dg.p, candr.p, candc.p, d_nodes, N,
+                         seed + 7919ull * l, len, part_r.p, part_c.p);
+      KERNEL_CHECK("node_sketch");
+      hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len)), dim3(256), 0, s, part_r.p, nsplit, len, len, Sr.p);
+      hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len)), dim3(256), 0, s, part_c.p, nsplit, len, len, Sc.p);
+      KERNEL_CHECK("node_sketch_sum");
+    }
+    hipLaunchKernelGGL(node_id_kernel, dim3(nn, 2), dim3(512), 0, s, dg.p, Sr.p, Sc.p, tol * tol, piv.p, Cr.p, Cc.p,
                        info.p);
     KERNEL_CHECK("node_id");
     std::vector<int> hinfo(4 * nn);
@@ -715,7 +790,9 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
       dch.upload(G[l + 1].data(), 2 * nn, s);
     }
     if (ws.n < (size_t)wso) ws.alloc(ctx, wso);
-    hipLaunchKernelGGL(node_inverse_kernel, dim3(nn), dim3(256), 0, s, dg.p, l < L ? dch.p : dg.p, l == L ? 1 : 0, 0,
+    const size_t shv = INV_LDS_BYTES;
+    HIP_CHECK(hipFuncSetAttribute((const void*)node_inverse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shv));
+    hipLaunchKernelGGL(node_inverse_kernel, dim3(nn), dim3(256), shv, s, dg.p, l < L ? dch.p : dg.p, l == L ? 1 : 0, 0,
                        candr.p, candc.p, d_nodes, Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, (double*)nullptr, fail.p);
     KERNEL_CHECK("node_inverse");
     // level descriptors for the apply
@@ -761,7 +838,8 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     DBuf<GNode> dch(ctx, 2);
     dch.upload(G[1].data(), 2, s);
     w.groot.alloc(ctx, (size_t)g.m * g.m);
-    hipLaunchKernelGGL(node_inverse_kernel, dim3(1), dim3(256), 0, s, dg.p, dch.p, 0, 1, candr.p, candc.p, d_nodes,
+    hipLaunchKernelGGL(node_inverse_kernel, dim3(1), dim3(256), (size_t)INV_LDS_BYTES, s,
+                       dg.p, dch.p, 0, 1, candr.p, candc.p, d_nodes,
                        Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, w.groot.p, fail.p);
     KERNEL_CHECK("node_inverse_root");
     w.entries += (int64_t)g.m * g.m;
