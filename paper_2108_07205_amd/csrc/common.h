@@ -83,6 +83,18 @@ struct PhaseTimer {
 };
 void prof_flush(rw_ctx* ctx);   // call after the stream has been synchronized
 
+// The ctx of the C-ABI call in progress on this host thread (set on entry),
+// so launchers can time their kernels when the ctx profiler is on.
+rw_ctx* current_ctx();
+void set_current_ctx(rw_ctx* ctx);
+
+// Kernel-level timer: like PhaseTimer, keyed "k:<kernel>", on the current ctx.
+struct KernelTimer {
+  PhaseTimer* t = nullptr;
+  KernelTimer(const char* name, double flops, double bytes);
+  ~KernelTimer();
+};
+
 // Device allocation accounted against the ctx budget.
 void* dev_alloc(rw_ctx* ctx, size_t bytes);
 void dev_free(rw_ctx* ctx, void* p, size_t bytes);

@@ -404,20 +404,32 @@ __device__ bool wg_inverse_inplace(double* A, int n, int* perm, double* f, doubl
 }
 
 // C (m x n, ldc) = alpha op(A) op(B) + beta C, all column-major, one
-// workgroup of 256 threads; output (i, j) walks the tile without division.
-__device__ void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda,
-                        const double* B, int ldb, double beta, double* C, int ldc) {
+// workgroup of 256 threads; output (i, j) walks the tile without division and
+// the inner loop keeps eight independent loads in flight.
+__device__ void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* __restrict__ A, int lda,
+                        const double* __restrict__ B, int ldb, double beta, double* __restrict__ C, int ldc) {
   if (m > 0 && n > 0) {
     int i = threadIdx.x % m, j = threadIdx.x / m;
     const int di = 256 % m, dj = 256 / m;
+    const int64_t sa = ta ? 1 : lda, sb = tb ? ldb : 1;     // stride along the inner index
     for (; j < n;) {
-      double s = 0;
-      for (int l = 0; l < k; ++l) {
-        const double a = ta ? A[l + (int64_t)i * lda] : A[i + (int64_t)l * lda];
-        const double b = tb ? B[j + (int64_t)l * ldb] : B[l + (int64_t)j * ldb];
-        s += a * b;
+      const double* a = ta ? A + (int64_t)i * lda : A + i;
+      const double* b = tb ? B + j : B + (int64_t)j * ldb;
+      double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0, s6 = 0, s7 = 0;
+      int l = 0;
+      for (; l + 8 <= k; l += 8) {
+        s0 += a[(l + 0) * sa] * b[(l + 0) * sb];
+        s1 += a[(l + 1) * sa] * b[(l + 1) * sb];
+        s2 += a[(l + 2) * sa] * b[(l + 2) * sb];
+        s3 += a[(l + 3) * sa] * b[(l + 3) * sb];
+        s4 += a[(l + 4) * sa] * b[(l + 4) * sb];
+        s5 += a[(l + 5) * sa] * b[(l + 5) * sb];
+        s6 += a[(l + 6) * sa] * b[(l + 6) * sb];
+        s7 += a[(l + 7) * sa] * b[(l + 7) * sb];
       }
-      C[i + (int64_t)j * ldc] = alpha * s + (beta == 0.0 ? 0.0 : beta * C[i + (int64_t)j * ldc]);
+      for (; l < k; ++l) s0 += a[l * sa] * b[l * sb];
+      const double sum = ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7));
+      C[i + (int64_t)j * ldc] = alpha * sum + (beta == 0.0 ? 0.0 : beta * C[i + (int64_t)j * ldc]);
       i += di;
       j += dj;
       if (i >= m) { i -= m; ++j; }
@@ -570,6 +582,10 @@ void hbs_upload(rw_ctx* ctx, const HbsInverse& H, bool with_f32, HbsDev& w) {
     d.max_k = max_k;
     d.S = in_off;
     d.K = k_off;
+    for (int j = 0; j < nn; ++j) {
+      d.up_entries += (int64_t)(nodes[j].k + nodes[j].nin) * nodes[j].nin;
+      d.e_entries += (int64_t)nodes[j].nin * nodes[j].k;
+    }
     w.S[l] = in_off;
     w.K[l] = k_off;
   }
@@ -729,16 +745,22 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
       nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, N / 64));
       const int64_t len = off * SK_R;
       if (part_r.n < (size_t)(len * nsplit)) { part_r.alloc(ctx, len * nsplit); part_c.alloc(ctx, len * nsplit); }
-      hipLaunchKernelGGL(node_sketch_kernel, dim3(nn, 2, nsplit), dim3(256), 0, s, dg.p, candr.p, candc.p, d_nodes, N,
-                         seed + 7919ull * l, len, part_r.p, part_c.p);
-      KERNEL_CHECK("node_sketch");
+      {
+        KernelTimer kt("node_sketch_kernel", 0.0, 0.0);
+        hipLaunchKernelGGL(node_sketch_kernel, dim3(nn, 2, nsplit), dim3(256), 0, s, dg.p, candr.p, candc.p, d_nodes,
+                           N, seed + 7919ull * l, len, part_r.p, part_c.p);
+        KERNEL_CHECK("node_sketch");
+      }
       hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len)), dim3(256), 0, s, part_r.p, nsplit, len, len, Sr.p);
       hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len)), dim3(256), 0, s, part_c.p, nsplit, len, len, Sc.p);
       KERNEL_CHECK("node_sketch_sum");
     }
-    hipLaunchKernelGGL(node_id_kernel, dim3(nn, 2), dim3(512), 0, s, dg.p, Sr.p, Sc.p, tol * tol, piv.p, Cr.p, Cc.p,
-                       info.p);
-    KERNEL_CHECK("node_id");
+    {
+      KernelTimer kt_id("node_id_kernel", 0.0, 0.0);
+      hipLaunchKernelGGL(node_id_kernel, dim3(nn, 2), dim3(512), 0, s, dg.p, Sr.p, Sc.p, tol * tol, piv.p, Cr.p, Cc.p,
+                         info.p);
+      KERNEL_CHECK("node_id");
+    }
     std::vector<int> hinfo(4 * nn);
     info.download(hinfo.data(), hinfo.size(), s);
     HIP_CHECK(hipStreamSynchronize(s));
@@ -792,9 +814,18 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     if (ws.n < (size_t)wso) ws.alloc(ctx, wso);
     const size_t shv = INV_LDS_BYTES;
     HIP_CHECK(hipFuncSetAttribute((const void*)node_inverse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shv));
-    hipLaunchKernelGGL(node_inverse_kernel, dim3(nn), dim3(256), shv, s, dg.p, l < L ? dch.p : dg.p, l == L ? 1 : 0, 0,
-                       candr.p, candc.p, d_nodes, Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, (double*)nullptr, fail.p);
-    KERNEL_CHECK("node_inverse");
+    double fl = 0;
+    for (int j = 0; j < nn; ++j) {
+      const double nm = gl[j].m, kk2 = gl[j].k;
+      fl += 2.0 * nm * nm * nm + 2.0 * (3.0 * nm * nm * kk2 + 3.0 * nm * kk2 * kk2) + 2.0 * kk2 * kk2 * kk2;
+    }
+    {
+      KernelTimer kt_inv("node_inverse_kernel", fl, 0.0);
+      hipLaunchKernelGGL(node_inverse_kernel, dim3(nn), dim3(256), shv, s, dg.p, l < L ? dch.p : dg.p, l == L ? 1 : 0,
+                         0, candr.p, candc.p, d_nodes, Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, (double*)nullptr,
+                         fail.p);
+      KERNEL_CHECK("node_inverse");
+    }
     // level descriptors for the apply
     std::vector<int>& li = lev_ints[l];
     std::vector<int64_t>& lo = lev_offs[l];
@@ -819,6 +850,10 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     d.max_k = max_k;
     d.S = off;
     d.K = kk;
+    for (int j = 0; j < nn; ++j) {
+      d.up_entries += (int64_t)(gl[j].k + gl[j].m) * gl[j].m;
+      d.e_entries += (int64_t)gl[j].m * gl[j].k;
+    }
     w.S[l] = off;
     w.K[l] = kk;
     HIP_CHECK(hipStreamSynchronize(s));

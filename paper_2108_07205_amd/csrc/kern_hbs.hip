@@ -116,6 +116,9 @@ void up_impl(const HbsLevelDev& L, const T* gen, const double* in, int64_t ld_in
   if (!L.nnodes || nrhs <= 0) return;
   dim3 grid(L.nnodes, (nrhs + kRB - 1) / kRB);
   const size_t sh = sizeof(double) * L.max_nin * kRB;
+  // generators streamed once per pass of kRB right-hand sides
+  const double passes = (nrhs + kRB - 1) / kRB;
+  KernelTimer kt("hbs_up_kernel", 2.0 * L.up_entries * nrhs, sizeof(T) * (double)L.up_entries * passes);
   hipLaunchKernelGGL(hbs_up_kernel<T>, grid, dim3(kThreads), sh, s, L.nin, L.k, L.in_off, L.kout_off,
                      L.up_off, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs);
   KERNEL_CHECK("hbs_up");
@@ -127,6 +130,8 @@ void down_impl(const HbsLevelDev& L, const T* gen, const double* xhat, int64_t l
   if (!L.nnodes || nrhs <= 0) return;
   dim3 grid(L.nnodes, (nrhs + kRB - 1) / kRB);
   const size_t sh = sizeof(double) * (L.max_k > 0 ? L.max_k : 1) * kRB;
+  const double passes = (nrhs + kRB - 1) / kRB;
+  KernelTimer kt("hbs_down_kernel", 2.0 * L.e_entries * nrhs, sizeof(T) * (double)L.e_entries * passes);
   hipLaunchKernelGGL(hbs_down_kernel<T>, grid, dim3(kThreads), sh, s, L.nin, L.k, L.in_off, L.kout_off,
                      L.e_off, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs);
   KERNEL_CHECK("hbs_down");

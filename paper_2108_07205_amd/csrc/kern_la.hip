@@ -588,7 +588,10 @@ int launch_rowid(rw_ctx* ctx, const double* Y, int64_t m, int ncols, double tol,
   if (!lds_rows) HIP_CHECK(hipMemcpyAsync(a.Yw, Y, sizeof(double) * m * ncols, hipMemcpyDeviceToDevice, s));
   void* args[] = {&a};
   HIP_CHECK(hipFuncSetAttribute((const void*)rowid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  HIP_CHECK(hipLaunchCooperativeKernel((const void*)rowid_kernel, dim3(G), dim3(256), args, shmem, s));
+  {
+    KernelTimer kt("rowid_kernel", 6.0 * (double)m * ncols * kmax, 0.0);
+    HIP_CHECK(hipLaunchCooperativeKernel((const void*)rowid_kernel, dim3(G), dim3(256), args, shmem, s));
+  }
   KERNEL_CHECK("rowid");
   int k = 0;
   HIP_CHECK(hipMemcpyAsync(&k, dk, sizeof(int), hipMemcpyDeviceToHost, s));

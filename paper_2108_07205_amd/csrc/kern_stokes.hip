@@ -419,6 +419,9 @@ void launch_residual(const NodeRec* nodes, int64_t n, const double* g, const dou
   const int ns = resid_splits(n, nrhs);
   double* sN = part + (size_t)ns * nrhs * 2 * n;
   dim3 grid(blocks(n, RT), (nrhs + RRB - 1) / RRB, ns);
+  // algorithmic work: 12 flops per 2x2 block (r, r^2, r.n, 1/r^2 scaling) + 6 per
+  // block and right-hand side; the division counts as one flop
+  KernelTimer kt("resid_tiles_kernel", (double)n * n * (12.0 + 6.0 * nrhs), 0.0);
   hipLaunchKernelGGL(resid_tiles_kernel, grid, dim3(RT), 0, s, nodes, n, tau, nrhs, ns, part);
   KERNEL_CHECK("resid_tiles");
   hipLaunchKernelGGL(flux_kernel, dim3(nrhs), dim3(256), 0, s, nodes, n, tau, sN);
@@ -485,6 +488,7 @@ void launch_sketch(const NodeRec* tgt, int64_t nt, const SketchSeg* segs, int ns
   // accumulators in registers without spilling
   for (int off = 0; off < ncols;) {
     const int w = (ncols - off >= 64) ? 64 : 32;
+    KernelTimer kt("sketch_kernel", 2.0 * rows * 2.0 * nsrc * w, 0.0);
     if (w == 64)
       hipLaunchKernelGGL(sketch_kernel<4>, grid, dim3(256), 0, s, tgt, nt, sa, seed, off, ns, part);
     else

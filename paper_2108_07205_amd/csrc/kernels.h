@@ -18,6 +18,8 @@ struct HbsLevelDev {
   const int64_t* kout_off = nullptr;  // node skeleton offset in the parent level's vectors
   const int64_t* up_off = nullptr;    // offset of [F*; G] ((k + nin) x nin) in the generator array
   const int64_t* e_off = nullptr;     // offset of E (nin x k)
+  int64_t up_entries = 0;             // sum over nodes of (k + nin) nin
+  int64_t e_entries = 0;              // sum over nodes of nin k
 };
 
 // up: bhat = F* b (to the parent level's vector), gb = G b (this level).

@@ -102,6 +102,19 @@ void prof_flush(rw_ctx* ctx) {
   ctx->pending.clear();
 }
 
+static thread_local rw_ctx* g_current_ctx = nullptr;
+rw_ctx* current_ctx() { return g_current_ctx; }
+void set_current_ctx(rw_ctx* ctx) { g_current_ctx = ctx; }
+
+KernelTimer::KernelTimer(const char* name, double flops, double bytes) {
+  rw_ctx* c = g_current_ctx;
+  if (c && c->prof) {
+    std::string key = std::string("k:") + name;
+    t = new PhaseTimer(c, key.c_str(), flops, bytes);
+  }
+}
+KernelTimer::~KernelTimer() { delete t; }
+
 namespace {
 thread_local std::string g_create_err;
 
@@ -112,9 +125,12 @@ int guarded(rw_ctx* ctx, F&& f) {
       ctx->err.clear();
       HIP_CHECK(hipSetDevice(ctx->device));
     }
+    set_current_ctx(ctx);
     f();
+    set_current_ctx(nullptr);
     return RW_OK;
   } catch (const RwError& e) {
+    set_current_ctx(nullptr);
     if (ctx) ctx->err = e.what();
     return e.code;
   } catch (const std::bad_alloc&) {
