@@ -131,8 +131,8 @@ int rw_profile_enable(rw_ctx* ctx, int on);
 int rw_profile_reset(rw_ctx* ctx);
 int64_t rw_profile_json(rw_ctx* ctx, char* buf, int64_t len);
 
-/* ---- reference wall (static; Sec. 3, "given a fast direct solver for the
- *      original discretization") ------------------------------------------ */
+/* ---- reference wall (static; Sec. 3.2: Algorithm 1 takes a fast direct
+ *      solver of the reference discretization as its input) ------------- */
 
 /* Discretize the curve with n_panels Gauss-Legendre panels of `order`
  * nodes, uniform in theta, and build the HBS compressed inverse A_oo^{-1}

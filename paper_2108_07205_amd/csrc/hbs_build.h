@@ -1,8 +1,8 @@
 // Static build of the HBS (hierarchically block separable) compressed
 // inverse of A_oo = -1/2 I + D + N on the reference wall.  The paper uses the
 // HBS compression and inverse of its cited fast direct solver (Gillman, Young
-// & Martinsson) as a black box "fast direct solver for the original
-// discretization" (Sec. 3.2, Algorithm 1); this is a from-scratch version of
+// & Martinsson) as the black-box solver of the reference discretization that
+// Algorithm 1 takes as input (Sec. 3.2); this is a from-scratch version of
 // that scheme for the Stokes double-layer system.
 //
 // Tree: perfect binary tree of contiguous arcs; root = level 0, leaves =

@@ -1,7 +1,7 @@
 // HBS inverse in HBM: upload of a host-built inverse, the level-sweep apply,
-// and the batched GPU build used per refinement for A_pp (Algorithm 1 step 2:
-// "build an approximate inverse of A_pp via a fast direct solver such as
-// HBS" when the added point count is large).
+// and the batched GPU build used per refinement for A_pp (Algorithm 1,
+// pre-computation step 2: an approximate inverse of A_pp from a fast direct
+// solver, used when the added node count is large).
 //
 // GPU build, per tree level (leaves to root), one workgroup per node:
 //  1. sketch: Y = M Omega (m x 96) of the node's off-diagonal block row
