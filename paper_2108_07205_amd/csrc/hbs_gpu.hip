@@ -438,6 +438,341 @@ __device__ void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, con
   __syncthreads();
 }
 
+// ------------------------------------------- 4b. register-resident node factorization
+// Fast path for node blocks of at most FN = 128 unknowns (every leaf of 64
+// nodes and every parent whose children have ranks summing to <= 128).
+// Thread t of the 256 owns row (t & 127) of the block and the 64 columns
+// 64 (t >> 7) .. + 63 in registers.  Gauss-Jordan with partial pivoting runs
+// without moving rows: step j picks pivot row p_j among the rows not yet used
+// and applies the in-place exchange update with (p_j, j), which is the
+// diagonal-pivot update of the row-permuted matrix P A.  The registers then
+// hold (P A)^-1 = A^-1 P^T with row j stored in row p_j, so
+// A^-1(j, p_c) = B(p_j, c): the result is scattered to HBM once at the end.
+constexpr int FN = 128;
+constexpr int GM_KC = 16;  // K chunk of the tiled workgroup GEMM
+
+struct GjScratch {
+  double colv[2][FN];  // column j of the current step (double-buffered)
+  double key[2][FN];   // pivot keys (see pivot_key)
+  double prow[2][FN];  // pivot row
+  int piv[FN];         // pivot row of each step
+};
+
+// Pivot key of row r with column-j entry v: |v| with its 7 lowest mantissa
+// bits replaced by 127 - r, so that the largest key is the row of largest
+// |v| (to 2^-45 relative) and, among equal magnitudes, the lowest row.  Used
+// rows get 0; non-finite entries get the largest finite magnitude, so that a
+// non-finite pivot is picked and reported.
+__device__ __forceinline__ double pivot_key(double v, int r, bool used) {
+  if (used) return 0.0;
+  const double m = isfinite(v) ? fabs(v) : 1.7976931348623157e308;
+  const unsigned long long b = ((unsigned long long)__double_as_longlong(m) & ~0x7Full) | (unsigned)(127 - r);
+  return __longlong_as_double((long long)b);
+}
+
+// 64-bit DPP move of v (lanes without a source read 0).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Maximum over the wave of non-negative doubles, by DPP row shifts and row
+// broadcasts (lane 63 ends with the maximum); returned in every lane.
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+  v = fmax(v, dpp_f64<0x111, 0xf>(v));  // row_shr:1
+  v = fmax(v, dpp_f64<0x112, 0xf>(v));  // row_shr:2
+  v = fmax(v, dpp_f64<0x114, 0xf>(v));  // row_shr:4
+  v = fmax(v, dpp_f64<0x118, 0xf>(v));  // row_shr:8
+  v = fmax(v, dpp_f64<0x142, 0xa>(v));  // row_bcast:15
+  v = fmax(v, dpp_f64<0x143, 0xc>(v));  // row_bcast:31
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+struct GemmScratch {
+  double As[GM_KC][FN + 1];
+  double Bs[GM_KC][FN + 1];
+};
+
+// In-place Gauss-Jordan inverse of the n x n block held as described above
+// (n <= FN; rows >= n and columns >= n must hold zeros).  Registers are never
+// indexed dynamically: the half of the columns that holds the current pivot
+// column j keeps it in a[0], because that half's update shifts its registers
+// down by one (a[c] <- updated a[c + 1], the new column j into a[63]).  On
+// return, register c of half h holds column 64 h + ((c + rot) & 63), myq is
+// the step at which this thread's row was the pivot (-1 for rows >= n) and
+// S.piv[j] the pivot row of step j.  Returns false (uniformly) on a zero or
+// non-finite pivot.
+__device__ bool reg_gauss_jordan(double (&a)[64], int n, GjScratch& S, int& myq, int& rot) {
+  const int tid = threadIdx.x, r = tid & (FN - 1), lane = tid & 63;
+  const int h = __builtin_amdgcn_readfirstlane(tid >> 7);
+  bool used = r >= n;
+  myq = -1;
+  for (int j = 0; j < n; ++j) {
+    const int b = j & 1;
+    const bool own = h == (j >> 6);  // wave-uniform
+    if (own) {
+      S.colv[b][r] = a[0];
+      S.key[b][r] = pivot_key(a[0], r, used);
+    }
+    __syncthreads();
+    // every wave finds the same pivot (same data, same reduction)
+    const double kmax = wave_max_nonneg(fmax(S.key[b][lane], S.key[b][lane + 64]));
+    const int p = 127 - (int)(__double_as_longlong(kmax) & 0x7F);
+    const double piv = S.colv[b][p];
+    if (!(fabs(piv) > 0.0) || !isfinite(piv)) return false;
+    if (r == p) {
+      used = true;
+      myq = j;
+#pragma unroll
+      for (int c = 0; c < 64; ++c) S.prow[b][64 * h + c] = a[c];  // register order of this half
+    }
+    if (tid == 0) S.piv[j] = p;
+    __syncthreads();
+    const double pinv = 1.0 / piv;
+    const double* pr = &S.prow[b][64 * h];
+    if (own) {
+      if (r == p) {
+#pragma unroll
+        for (int c = 0; c < 63; ++c) a[c] = a[c + 1] * pinv;
+        a[63] = pinv;
+      } else {
+        // rows >= n hold zeros and stay zero
+        const double f = S.colv[b][r] * pinv;
+#pragma unroll
+        for (int c = 0; c < 63; ++c) a[c] = a[c + 1] - f * pr[c + 1];
+        a[63] = -f;
+      }
+    } else {
+      if (r == p) {
+#pragma unroll
+        for (int c = 0; c < 64; ++c) a[c] *= pinv;
+      } else {
+        const double f = S.colv[b][r] * pinv;
+#pragma unroll
+        for (int c = 0; c < 64; ++c) a[c] -= f * pr[c];
+      }
+    }
+  }
+  rot = (h == 0 ? min(n, 64) : max(0, n - 64)) & 63;
+  return true;
+}
+
+// C (m x n, ldc) = alpha op(A) op(B) + C0 (m x n, ldc0; none when null), all
+// column-major, m, n <= FN, any K.  256 threads as a 16 x 16 grid; thread
+// (ti, tj) owns rows ti + 16 a (a < MA) and columns tj + 16 b (b < NB); K is
+// staged through LDS in chunks of GM_KC (zero-padded past m, n and K).
+template <int MA, int NB>
+__device__ void wg_gemm_tile(bool ta, bool tb, int m, int n, int K, double alpha, const double* __restrict__ A,
+                             int lda, const double* __restrict__ B, int ldb, const double* C0, int ldc0,
+                             double* C, int ldc, GemmScratch& S) {
+  constexpr int PER = GM_KC * FN / 256;  // staged elements per thread and operand
+  const int tid = threadIdx.x, ti = tid & 15, tj = tid >> 4;
+  double acc[MA][NB];
+#pragma unroll
+  for (int x = 0; x < MA; ++x)
+#pragma unroll
+    for (int y = 0; y < NB; ++y) acc[x][y] = 0.0;
+  // element u of this thread's share of a chunk: (row or column, k) pair
+  auto a_rk = [&](int u, int& row, int& kc) {
+    const int idx = tid + 256 * u;
+    if (ta) { kc = idx & (GM_KC - 1); row = idx >> 4; } else { row = idx & (FN - 1); kc = idx >> 7; }
+  };
+  auto b_ck = [&](int u, int& col, int& kb) {
+    const int idx = tid + 256 * u;
+    if (tb) { col = idx & (FN - 1); kb = idx >> 7; } else { kb = idx & (GM_KC - 1); col = idx >> 4; }
+  };
+  double pa[PER], pb[PER];
+  auto fetch = [&](int k0) {
+    const int kn = min(GM_KC, K - k0);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      int row, kc, col, kb;
+      a_rk(u, row, kc);
+      b_ck(u, col, kb);
+      pa[u] = (row < m && kc < kn) ? (ta ? A[(k0 + kc) + (int64_t)row * lda] : A[row + (int64_t)(k0 + kc) * lda]) : 0.0;
+      pb[u] = (col < n && kb < kn) ? (tb ? B[col + (int64_t)(k0 + kb) * ldb] : B[(k0 + kb) + (int64_t)col * ldb]) : 0.0;
+    }
+  };
+  if (K > 0) fetch(0);
+  for (int k0 = 0; k0 < K; k0 += GM_KC) {
+    const int kn = min(GM_KC, K - k0);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      int row, kc, col, kb;
+      a_rk(u, row, kc);
+      b_ck(u, col, kb);
+      S.As[kc][row] = pa[u];
+      S.Bs[kb][col] = pb[u];
+    }
+    __syncthreads();
+    if (k0 + GM_KC < K) fetch(k0 + GM_KC);  // in flight during this chunk's products
+    for (int kc = 0; kc < kn; ++kc) {
+      double av[MA], bv[NB];
+#pragma unroll
+      for (int x = 0; x < MA; ++x) av[x] = S.As[kc][ti + 16 * x];
+#pragma unroll
+      for (int y = 0; y < NB; ++y) bv[y] = S.Bs[kc][tj + 16 * y];
+#pragma unroll
+      for (int x = 0; x < MA; ++x)
+#pragma unroll
+        for (int y = 0; y < NB; ++y) acc[x][y] += av[x] * bv[y];
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < MA; ++x)
+#pragma unroll
+    for (int y = 0; y < NB; ++y) {
+      const int row = ti + 16 * x, col = tj + 16 * y;
+      if (row < m && col < n)
+        C[row + (int64_t)col * ldc] = alpha * acc[x][y] + (C0 ? C0[row + (int64_t)col * ldc0] : 0.0);
+    }
+  __syncthreads();
+}
+
+__device__ void wg_gemm_small(bool ta, bool tb, int m, int n, int K, double alpha, const double* A, int lda,
+                              const double* B, int ldb, const double* C0, int ldc0, double* C, int ldc,
+                              GemmScratch& S) {
+  if (m <= 0 || n <= 0) return;
+  const bool m8 = m > 64, n8 = n > 64;
+  if (!m8 && !n8) wg_gemm_tile<4, 4>(ta, tb, m, n, K, alpha, A, lda, B, ldb, C0, ldc0, C, ldc, S);
+  else if (!m8) wg_gemm_tile<4, 8>(ta, tb, m, n, K, alpha, A, lda, B, ldb, C0, ldc0, C, ldc, S);
+  else if (!n8) wg_gemm_tile<8, 4>(ta, tb, m, n, K, alpha, A, lda, B, ldb, C0, ldc0, C, ldc, S);
+  else wg_gemm_tile<8, 8>(ta, tb, m, n, K, alpha, A, lda, B, ldb, C0, ldc0, C, ldc, S);
+}
+
+// One entry of the A = -1/2 I + D + N block: row component ti of target t,
+// column component sj of source s.
+__device__ __forceinline__ double a_entry(const NodeRec& t, const NodeRec& s, bool self, int ti, int sj) {
+  if (self) return (ti == 0) ? (sj == 0 ? s.s00 : s.s01) : (sj == 0 ? s.s01 : s.s11);
+  const double rx = t.x - s.x, ry = t.y - s.y;
+  const double r2 = rx * rx + ry * ry;
+  const double cf = (rx * s.nx + ry * s.ny) * s.w * kInvPi / (r2 * r2);
+  const double rt = ti ? ry : rx, rs = sj ? ry : rx;
+  const double nt = ti ? t.ny : t.nx, ns = sj ? s.ny : s.nx;
+  return cf * rt * rs + s.w * nt * ns;
+}
+
+// grid (nodes), nodes of at most FN unknowns.  Same inputs and outputs as
+// node_inverse_kernel: D assembled straight into registers, D^-1 by the
+// register Gauss-Jordan, then with W = ws + ws_off holding
+// [D^-1 (n x n) | D^-1 U (n x k) | V* D^-1 (k x n) | V* D^-1 U (k x k)]:
+// D^ = (V* D^-1 U)^-1, E = D^-1 U D^, F* = D^ V* D^-1, G = D^-1 - E V* D^-1.
+__global__ __launch_bounds__(256) void node_factor_kernel(const GNode* __restrict__ gn, const GNode* __restrict__ gch,
+                                                          int is_leaf, int is_root, const int* __restrict__ candr,
+                                                          const int* __restrict__ candc,
+                                                          const NodeRec* __restrict__ nd, const double* __restrict__ U,
+                                                          const double* __restrict__ V,
+                                                          const double* __restrict__ dhat_ch, double* __restrict__ dhat,
+                                                          double* __restrict__ ws, double* __restrict__ gen,
+                                                          double* __restrict__ groot, int* __restrict__ fail) {
+  __shared__ GjScratch gs;
+  __shared__ GemmScratch ms;
+  const GNode g = gn[blockIdx.x];
+  const int n = g.m, k = g.k, tid = threadIdx.x, r = tid & (FN - 1);
+  const int h = __builtin_amdgcn_readfirstlane(tid >> 7);
+  const int* cr = candr + g.cand_off;
+  const int* cc = candc + g.cand_off;
+  // ---- assemble D (column-major, in the workspace slot of D^-1), then
+  // each thread takes its row segment into registers
+  double* Dw = ws + g.ws_off;
+  if (is_leaf) {
+    for (int idx = tid; idx < n * n; idx += 256) {
+      const int i = idx % n, j = idx / n;
+      const int ra = cr[i], cb = cc[j];
+      Dw[idx] = a_entry(nd[ra >> 1], nd[cb >> 1], (ra >> 1) == (cb >> 1), ra & 1, cb & 1);
+    }
+  } else {
+    const GNode ca = gch[2 * blockIdx.x], cbn = gch[2 * blockIdx.x + 1];
+    const int ka = ca.k, kb = cbn.k;
+    const double* Da = dhat_ch + ca.dhat_off;
+    const double* Db = dhat_ch + cbn.dhat_off;
+    for (int idx = tid; idx < n * n; idx += 256) {
+      const int i = idx % n, j = idx / n;
+      double v;
+      if (i < ka && j < ka) v = Da[i + j * ka];
+      else if (i >= ka && j >= ka) v = Db[(i - ka) + (j - ka) * kb];
+      else {
+        const int ra = cr[i], cb = cc[j];
+        v = a_entry(nd[ra >> 1], nd[cb >> 1], false, ra & 1, cb & 1);
+      }
+      Dw[idx] = v;
+    }
+  }
+  __syncthreads();
+  double a[64];
+#pragma unroll
+  for (int c = 0; c < 64; ++c) {
+    const int col = 64 * h + c;
+    a[c] = (r < n && col < n) ? Dw[r + (int64_t)col * n] : 0.0;
+  }
+  __syncthreads();
+  int q, rot;
+  if (!reg_gauss_jordan(a, n, gs, q, rot)) {
+    if (tid == 0) atomicExch(fail, 1);
+    return;
+  }
+  double* Dinv = is_root ? groot : ws + g.ws_off;
+  if (r < n) {
+#pragma unroll
+    for (int c = 0; c < 64; ++c) {
+      const int col = 64 * h + ((c + rot) & 63);
+      if (col < n) Dinv[q + (int64_t)gs.piv[col] * n] = a[c];
+    }
+  }
+  __syncthreads();
+  if (is_root) return;
+  double* DU = Dinv + (int64_t)n * n;
+  double* VD = DU + (int64_t)n * k;
+  double* Sm = VD + (int64_t)k * n;
+  const double* Un = U + g.uv_off;
+  const double* Vn = V + g.uv_off;
+  // op 0: D^-1 U;  op 1: V* D^-1;  op 2: V* D^-1 U  (one call site keeps the code small)
+  for (int op = 0; op < 3; ++op) {
+    const int mo = op == 0 ? n : k, no = op == 1 ? n : k;
+    const double* A = op == 0 ? Dinv : (op == 1 ? Vn : VD);
+    const double* B = op == 1 ? Dinv : Un;
+    double* C = op == 0 ? DU : (op == 1 ? VD : Sm);
+    wg_gemm_small(op == 1, false, mo, no, n, 1.0, A, op == 2 ? k : n, B, n, nullptr, 0, C, op == 0 ? n : k, ms);
+  }
+  // D^ = (V* D^-1 U)^-1, through the registers again
+#pragma unroll
+  for (int c = 0; c < 64; ++c) {
+    const int col = 64 * h + c;
+    a[c] = (r < k && col < k) ? Sm[r + (int64_t)col * k] : 0.0;
+  }
+  if (!reg_gauss_jordan(a, k, gs, q, rot)) {
+    if (tid == 0) atomicExch(fail, 2);
+    return;
+  }
+  double* Dh = dhat + g.dhat_off;
+  if (r < k) {
+#pragma unroll
+    for (int c = 0; c < 64; ++c) {
+      const int col = 64 * h + ((c + rot) & 63);
+      if (col < k) Dh[q + (int64_t)gs.piv[col] * k] = a[c];
+    }
+  }
+  __syncthreads();
+  double* up = gen + g.up_off;  // [F*; G], (k + n) x n
+  double* E = gen + g.e_off;    // n x k
+  const int rows = k + n;
+  // op 0: E = D^-1 U D^;  op 1: F* = D^ V* D^-1;  op 2: G = D^-1 - E V* D^-1
+  for (int op = 0; op < 3; ++op) {
+    const int mo = op == 1 ? k : n, no = op == 0 ? k : n;
+    const double* A = op == 0 ? DU : (op == 1 ? Dh : E);
+    const double* B = op == 0 ? Dh : VD;
+    double* C = op == 0 ? E : (op == 1 ? up : up + k);
+    wg_gemm_small(false, false, mo, no, k, op == 2 ? -1.0 : 1.0, A, op == 1 ? k : n, B, k, op == 2 ? Dinv : nullptr,
+                  n, C, op == 0 ? n : rows, ms);
+  }
+}
+
 // grid (nodes).  leaf: D = A(candr, candc); parent: children's D^ on the
 // diagonal, kernel blocks between the children's skeletons off it.
 // root (is_root): writes D^-1 to G_root only.
@@ -819,7 +1154,13 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
       const double nm = gl[j].m, kk2 = gl[j].k;
       fl += 2.0 * nm * nm * nm + 2.0 * (3.0 * nm * nm * kk2 + 3.0 * nm * kk2 * kk2) + 2.0 * kk2 * kk2 * kk2;
     }
-    {
+    if (mx <= FN) {
+      KernelTimer kt_inv("node_factor_kernel", fl, 0.0);
+      hipLaunchKernelGGL(node_factor_kernel, dim3(nn), dim3(256), 0, s, dg.p, l < L ? dch.p : dg.p, l == L ? 1 : 0,
+                         0, candr.p, candc.p, d_nodes, Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, (double*)nullptr,
+                         fail.p);
+      KERNEL_CHECK("node_factor");
+    } else {
       KernelTimer kt_inv("node_inverse_kernel", fl, 0.0);
       hipLaunchKernelGGL(node_inverse_kernel, dim3(nn), dim3(256), shv, s, dg.p, l < L ? dch.p : dg.p, l == L ? 1 : 0,
                          0, candr.p, candc.p, d_nodes, Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, (double*)nullptr,
@@ -873,9 +1214,13 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     DBuf<GNode> dch(ctx, 2);
     dch.upload(G[1].data(), 2, s);
     w.groot.alloc(ctx, (size_t)g.m * g.m);
-    hipLaunchKernelGGL(node_inverse_kernel, dim3(1), dim3(256), (size_t)INV_LDS_BYTES, s,
-                       dg.p, dch.p, 0, 1, candr.p, candc.p, d_nodes,
-                       Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, w.groot.p, fail.p);
+    if (g.m <= FN)
+      hipLaunchKernelGGL(node_factor_kernel, dim3(1), dim3(256), 0, s, dg.p, dch.p, 0, 1, candr.p, candc.p, d_nodes,
+                         Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, w.groot.p, fail.p);
+    else
+      hipLaunchKernelGGL(node_inverse_kernel, dim3(1), dim3(256), (size_t)INV_LDS_BYTES, s,
+                         dg.p, dch.p, 0, 1, candr.p, candc.p, d_nodes,
+                         Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, w.groot.p, fail.p);
     KERNEL_CHECK("node_inverse_root");
     w.entries += (int64_t)g.m * g.m;
     int hf[4];
