@@ -142,31 +142,6 @@ struct DBuf {
   size_t bytes() const { return n * sizeof(T); }
 };
 
-// One int in pinned host memory that kernels may set (plain store) and the
-// host reads after a stream synchronization.
-struct PinnedFlag {
-  int* p = nullptr;
-  PinnedFlag() = default;
-  PinnedFlag(const PinnedFlag&) = delete;
-  PinnedFlag& operator=(const PinnedFlag&) = delete;
-  PinnedFlag(PinnedFlag&& o) noexcept : p(o.p) { o.p = nullptr; }
-  PinnedFlag& operator=(PinnedFlag&& o) noexcept {
-    if (this != &o) { release(); p = o.p; o.p = nullptr; }
-    return *this;
-  }
-  ~PinnedFlag() { release(); }
-  void ensure() {
-    if (!p) {
-      HIP_CHECK(hipHostMalloc((void**)&p, sizeof(int), hipHostMallocDefault));
-      *p = 0;
-    }
-  }
-  void release() {
-    if (p) (void)hipHostFree(p);
-    p = nullptr;
-  }
-};
-
 // Run f(i) for i in [0, n) on up to `threads` host threads.
 void parallel_for(int64_t n, const std::function<void(int64_t)>& f, int threads = 0);
 

@@ -22,26 +22,8 @@ struct HbsDev {
   DBuf<double> ws;
   int ws_nrhs = 0;
   std::vector<double*> U, GB, X;
-  // fused apply: task list (type, level, node, slab), completion counters
-  // (up per node | down per node | root), ticket counter, level views
-  std::vector<int> node_base;
-  DBuf<int4> tasks;
-  int ntasks = 0, grid = 0, xs_len = 0, n_all = 0;
-  DBuf<unsigned> counters;
-  DBuf<unsigned long long> ticket;
-  DBuf<HbsApplyLevel> d_lev;
-  int lev_nrhs = 0;
-  unsigned epoch = 0;
-  unsigned long long ticket_base = 0;
-  PinnedFlag err;  // set by the device when a dependency wait times out
   int64_t n_unknowns() const { return lev.size() > 1 ? S[L] : 0; }
 };
-
-// Task list and counters of the fused apply; nin[l][j], k[l][j] per level.
-void hbs_fused_setup(HbsDev& w, const std::vector<std::vector<int>>& nin, const std::vector<std::vector<int>>& k);
-// Throws RW_EDEVICE (and resets the fused-apply state) if a device-side
-// dependency wait timed out since the last check.  Call after a stream sync.
-void hbs_check(HbsDev& w);
 
 // Pack a host-built inverse into HBM.
 void hbs_upload(rw_ctx* ctx, const HbsInverse& H, bool with_f32, HbsDev& out);

@@ -949,16 +949,9 @@ void hbs_upload(rw_ctx* ctx, const HbsInverse& H, bool with_f32, HbsDev& w) {
     d.up_off = w.d_offs.p + off_base[l] + 2 * nn;
     d.e_off = w.d_offs.p + off_base[l] + 3 * nn;
   }
+  HIP_CHECK(hipStreamSynchronize(s));
   w.entries = H.entries;
   w.max_rank = H.max_rank;
-  std::vector<std::vector<int>> nin(w.L + 1), kk(w.L + 1);
-  for (int l = 1; l <= w.L; ++l)
-    for (const HbsNodeGen& g : H.lev[l]) {
-      nin[l].push_back(g.nin);
-      kk[l].push_back(g.k);
-    }
-  hbs_fused_setup(w, nin, kk);
-  HIP_CHECK(hipStreamSynchronize(s));
 }
 
 static void hbs_ensure_ws(HbsDev& w, int nrhs) {
@@ -976,106 +969,28 @@ static void hbs_ensure_ws(HbsDev& w, int nrhs) {
   w.ws_nrhs = nrhs;
 }
 
-// Level views for the fused sweep; the vector pointers follow the workspace.
-static void hbs_fused_levels(HbsDev& w) {
-  if (w.lev_nrhs == w.ws_nrhs && w.d_lev.p) return;
-  std::vector<HbsApplyLevel> h(w.L + 1);
-  memset(h.data(), 0, sizeof(HbsApplyLevel) * h.size());
-  for (int l = 1; l <= w.L; ++l) {
-    HbsApplyLevel& v = h[l];
-    const HbsLevelDev& d = w.lev[l];
-    v.nin = d.nin;
-    v.k = d.k;
-    v.in_off = d.in_off;
-    v.kout_off = d.kout_off;
-    v.up_off = d.up_off;
-    v.e_off = d.e_off;
-    v.node_base = w.node_base[l];
-    v.in = (l == w.L) ? nullptr : w.U[l + 1];
-    v.ld_in = (l == w.L) ? 0 : w.K[l + 1];
-    v.bhat = w.U[l];
-    v.ld_bhat = w.K[l];
-    v.gb = w.GB[l];
-    v.ld_gb = w.S[l];
-    v.xin = w.X[l - 1];
-    v.ld_xin = w.S[l - 1];
-    v.out = (l == w.L) ? nullptr : w.X[l];
-    v.ld_out = (l == w.L) ? 0 : w.S[l];
-  }
-  w.d_lev.alloc(w.ctx, h.size());
-  w.d_lev.upload(h.data(), h.size(), w.ctx->stream);
-  w.lev_nrhs = w.ws_nrhs;
-}
-
-static void hbs_fused_reset(HbsDev& w) {
-  hipStream_t s = w.ctx->stream;
-  HIP_CHECK(hipMemsetAsync(w.counters.p, 0, w.counters.bytes(), s));
-  HIP_CHECK(hipMemsetAsync(w.ticket.p, 0, w.ticket.bytes(), s));
-  w.epoch = 0;
-  w.ticket_base = 0;
-}
-
-void hbs_fused_setup(HbsDev& w, const std::vector<std::vector<int>>& nin, const std::vector<std::vector<int>>& k) {
-  const int L = w.L;
-  std::vector<int4> t;
-  w.node_base.assign(L + 1, 0);
-  int nb = 0, xs = w.nroot;
-  for (int l = 1; l <= L; ++l) {
-    w.node_base[l] = nb;
-    nb += (int)nin[l].size();
-  }
-  w.n_all = nb;
-  auto slabs = [](int rows) { return (rows + 63) / 64; };
-  for (int l = L; l >= 1; --l)
-    for (int j = 0; j < (int)nin[l].size(); ++j) {
-      xs = std::max(xs, std::max(nin[l][j], k[l][j]));
-      for (int sl = 0; sl < slabs(nin[l][j] + k[l][j]); ++sl) t.push_back(make_int4(0, l, j, sl));
-    }
-  for (int sl = 0; sl < slabs(w.nroot); ++sl) t.push_back(make_int4(1, 0, 0, sl));
-  for (int l = 1; l <= L; ++l)
-    for (int j = 0; j < (int)nin[l].size(); ++j)
-      for (int sl = 0; sl < slabs(nin[l][j]); ++sl) t.push_back(make_int4(2, l, j, sl));
-  w.ntasks = (int)t.size();
-  w.xs_len = std::max(xs, 1);
-  w.grid = std::max(1, std::min(w.ntasks, 8 * std::max(1, w.ctx->n_cu)));
-  w.tasks.alloc(w.ctx, t.size());
-  w.tasks.upload(t.data(), t.size(), w.ctx->stream);
-  w.counters.alloc(w.ctx, 2 * (size_t)nb + 1);
-  w.ticket.alloc(w.ctx, 1);
-  w.err.ensure();
-  hbs_fused_reset(w);
-  w.lev_nrhs = 0;
-}
-
-void hbs_check(HbsDev& w) {
-  if (w.err.p && *w.err.p) {
-    *w.err.p = 0;
-    hbs_fused_reset(w);
-    RW_THROW(RW_EDEVICE, "HBS apply: a dependency wait timed out");
-  }
-}
-
 void hbs_dev_apply(HbsDev& w, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32) {
   if (nrhs <= 0) return;
   hbs_ensure_ws(w, nrhs);
-  hbs_fused_levels(w);
-  if (w.epoch >= (1u << 24)) hbs_fused_reset(w);  // keeps epoch * slabs far below 2^32
-  ++w.epoch;
+  hipStream_t s = w.ctx->stream;
   const bool f32 = use_f32 && w.gen32.p;
-  const double passes = nrhs == 1 ? 1.0 : (nrhs + 7) / 8;
-  const double gbytes = passes * ((f32 ? 4.0 : 8.0) * (double)(w.entries - (int64_t)w.nroot * w.nroot) +
-                                  8.0 * (double)w.nroot * w.nroot);
-  try {
-    launch_hbs_fused(w.d_lev.p, w.L, w.tasks.p, w.ntasks, w.grid, w.xs_len, w.gen.p, f32 ? w.gen32.p : nullptr,
-                     w.groot.p, w.nroot, w.U[1], w.X[0], b, ldb, x, ldx, nrhs, w.ticket.p, w.ticket_base,
-                     w.counters.p, w.counters.p + w.n_all, w.counters.p + 2 * w.n_all, w.epoch, w.err.p, gbytes,
-                     w.ctx->stream);
-  } catch (...) {
-    hbs_fused_reset(w);  // counters and tickets stay consistent with the next call
-    throw;
+  for (int l = w.L; l >= 1; --l) {
+    const double* in = (l == w.L) ? b : w.U[l + 1];
+    const int64_t ldin = (l == w.L) ? ldb : w.K[l + 1];
+    if (f32)
+      launch_hbs_up_f32(w.lev[l], w.gen32.p, in, ldin, w.U[l], w.K[l], w.GB[l], w.S[l], nrhs, s);
+    else
+      launch_hbs_up(w.lev[l], w.gen.p, in, ldin, w.U[l], w.K[l], w.GB[l], w.S[l], nrhs, s);
   }
-  // each workgroup draws exactly one ticket past the last task
-  w.ticket_base += (unsigned long long)(w.ntasks + w.grid);
+  launch_hbs_root(w.nroot, w.groot.p, w.U[1], w.K[1], w.X[0], w.S[0], nrhs, s);
+  for (int l = 1; l <= w.L; ++l) {
+    double* out = (l == w.L) ? x : w.X[l];
+    const int64_t ldout = (l == w.L) ? ldx : w.S[l];
+    if (f32)
+      launch_hbs_down_f32(w.lev[l], w.gen32.p, w.X[l - 1], w.S[l - 1], w.GB[l], w.S[l], out, ldout, nrhs, s);
+    else
+      launch_hbs_down(w.lev[l], w.gen.p, w.X[l - 1], w.S[l - 1], w.GB[l], w.S[l], out, ldout, nrhs, s);
+  }
 }
 
 // ================================================================== GPU build
@@ -1336,14 +1251,6 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     d.kout_off = w.d_offs.p + ob[l] + nn;
     d.up_off = w.d_offs.p + ob[l] + 2 * nn;
     d.e_off = w.d_offs.p + ob[l] + 3 * nn;
-  }
-  {
-    std::vector<std::vector<int>> nin(L + 1), kk(L + 1);
-    for (int l = 1; l <= L; ++l) {
-      nin[l].assign(lev_ints[l].begin(), lev_ints[l].begin() + w.lev[l].nnodes);
-      kk[l].assign(lev_ints[l].begin() + w.lev[l].nnodes, lev_ints[l].end());
-    }
-    hbs_fused_setup(w, nin, kk);
   }
   HIP_CHECK(hipStreamSynchronize(s));
 }

@@ -149,207 +149,6 @@ __global__ __launch_bounds__(kThreads) void hbs_root_kernel(int n, const double*
 }
 
 
-// ------------------------------------------------------------ fused sweep
-// Vectors passed between tasks (bhat, gb, the down outputs of levels < L)
-// are written and read with device-scope relaxed atomics, which are coherent
-// across the XCDs' L2 caches without whole-cache write-back or invalidation;
-// a task is published by a relaxed counter increment after every wave has
-// waited for its stores to complete.  Generator loads stay ordinary cached
-// loads, and each task fetches the first columns of its slab before it waits.
-constexpr int kTaskUp = 0, kTaskRoot = 1, kTaskDown = 2;
-constexpr long long kWaitTicks = 200000000LL;  // 2 s of the 100 MHz wall clock
-
-__device__ __forceinline__ int up_slabs(const HbsApplyLevel& v, int j) { return (v.k[j] + v.nin[j] + kRows - 1) / kRows; }
-__device__ __forceinline__ int down_slabs(const HbsApplyLevel& v, int j) { return (v.nin[j] + kRows - 1) / kRows; }
-
-__device__ __forceinline__ double ld_dev(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_dev(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Thread 0: wait until *c >= target.  After a timeout anywhere in the sweep
-// (err set) every later wait gives up at once, so a broken sweep still ends
-// within about one time-out.
-__device__ __forceinline__ void wait_count(unsigned* c, unsigned target, int* err) {
-  const long long t0 = wall_clock64();
-  for (unsigned it = 0; __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++it) {
-    if ((it & 1023u) == 0 && *(volatile int*)err) break;
-    if (wall_clock64() - t0 > kWaitTicks) {
-      *(volatile int*)err = 1;  // host-visible flag; the sweep still runs to its end
-      break;
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
-}
-
-// Every wave waits until its stores have completed, then thread 0 counts the
-// task as done.
-__device__ __forceinline__ void signal_done(unsigned* c) {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// One slab task: out(rows) = M(rows, :) xin for all right-hand sides in
-// chunks of RB.  The first kUnroll columns of this lane's quarter are loaded
-// before wait() returns; load(col, c) reads the input, emit(row, c, v)
-// stores one result.
-template <typename T, int RB, typename Wait, typename Load, typename Emit>
-__device__ __forceinline__ void slab_task(const T* __restrict__ M, int R, int C, int slab, int nrhs, double* xs,
-                                          double* red, Wait wait, Load load, Emit emit) {
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int row = slab * kRows + lane;
-  const int c0 = (w * C) >> 2, c1 = ((w + 1) * C) >> 2;
-  const T* mp = M + (row < R ? row : 0);
-  double m0[kUnroll];
-#pragma unroll
-  for (int u = 0; u < kUnroll; ++u) m0[u] = (row < R && c0 + u < c1) ? (double)mp[(int64_t)(c0 + u) * R] : 0.0;
-  wait();
-  for (int r0 = 0; r0 < nrhs; r0 += RB) {
-    const int nr = min(RB, nrhs - r0);
-    for (int idx = tid; idx < C * RB; idx += kThreads) {
-      const int col = idx / RB, c = idx - col * RB;
-      xs[idx] = (c < nr) ? load(col, r0 + c) : 0.0;
-    }
-    __syncthreads();
-    double acc[RB];
-#pragma unroll
-    for (int c = 0; c < RB; ++c) acc[c] = 0.0;
-    if (row < R) {
-      int col = c0;
-      if (r0 == 0 && c0 < c1) {
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-#pragma unroll
-          for (int c = 0; c < RB; ++c) acc[c] += m0[u] * xs[min(c0 + u, C - 1) * RB + c];
-        col = min(c1, c0 + kUnroll);
-      }
-      for (; col + kUnroll <= c1; col += kUnroll) {
-        double m[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) m[u] = (double)mp[(int64_t)(col + u) * R];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-#pragma unroll
-          for (int c = 0; c < RB; ++c) acc[c] += m[u] * xs[(col + u) * RB + c];
-      }
-      for (; col < c1; ++col) {
-        const double m = (double)mp[(int64_t)col * R];
-#pragma unroll
-        for (int c = 0; c < RB; ++c) acc[c] += m * xs[col * RB + c];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < RB; ++c) red[(w * RB + c) * kRows + lane] = acc[c];
-    __syncthreads();
-    if (row < R)
-      for (int c = w; c < nr; c += 4) emit(row, r0 + c, slab_sum<RB>(red, c, lane));
-    __syncthreads();
-  }
-}
-
-template <typename T, int RB>
-__global__ __launch_bounds__(kThreads) void hbs_fused_kernel(
-    const HbsApplyLevel* __restrict__ lev, int L, const int4* __restrict__ tasks, int ntasks, int xs_len,
-    const T* __restrict__ gen, const double* __restrict__ groot, int nroot, double* root_in, double* root_out,
-    const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, unsigned long long* ticket,
-    unsigned long long ticket_base, unsigned* up_done, unsigned* down_done, unsigned* root_done, unsigned epoch,
-    int* err) {
-  extern __shared__ double sm[];
-  __shared__ int s_t;
-  double* xs = sm;
-  double* red = sm + xs_len;
-  const int tid = threadIdx.x;
-  for (;;) {
-    __syncthreads();
-    if (tid == 0) s_t = (int)(atomicAdd(ticket, 1ull) - ticket_base);
-    __syncthreads();
-    const int t = s_t;
-    if (t >= ntasks) return;
-    const int4 tk = tasks[t];
-    const int l = tk.y, j = tk.z, slab = tk.w;
-    if (tk.x == kTaskUp) {
-      const HbsApplyLevel& v = lev[l];
-      const int n = v.nin[j], k = v.k[j];
-      const int64_t io = v.in_off[j], ko = v.kout_off[j];
-      double* bh = v.bhat;
-      double* gb = v.gb;
-      const int64_t ldbh = v.ld_bhat, ldgb = v.ld_gb;
-      auto emit = [&](int row, int c, double val) {
-        if (row < k) st_dev(&bh[ko + row + (int64_t)c * ldbh], val);
-        else st_dev(&gb[io + (row - k) + (int64_t)c * ldgb], val);
-      };
-      if (l == L) {
-        slab_task<T, RB>(
-            gen + v.up_off[j], k + n, n, slab, nrhs, xs, red, [] {},
-            [&](int col, int c) { return b[io + col + (int64_t)c * ldb]; }, emit);
-      } else {
-        const double* in = v.in;
-        const int64_t ldin = v.ld_in;
-        slab_task<T, RB>(
-            gen + v.up_off[j], k + n, n, slab, nrhs, xs, red,
-            [&] {
-              if (tid == 0) {
-                const HbsApplyLevel& c = lev[l + 1];
-                wait_count(&up_done[c.node_base + 2 * j], epoch * (unsigned)up_slabs(c, 2 * j), err);
-                wait_count(&up_done[c.node_base + 2 * j + 1], epoch * (unsigned)up_slabs(c, 2 * j + 1), err);
-              }
-              __syncthreads();
-            },
-            [&](int col, int c) { return ld_dev(&in[io + col + (int64_t)c * ldin]); }, emit);
-      }
-      signal_done(&up_done[v.node_base + j]);
-    } else if (tk.x == kTaskRoot) {
-      slab_task<double, RB>(
-          groot, nroot, nroot, slab, nrhs, xs, red,
-          [&] {
-            if (tid == 0) {
-              const HbsApplyLevel& c = lev[1];
-              wait_count(&up_done[c.node_base], epoch * (unsigned)up_slabs(c, 0), err);
-              wait_count(&up_done[c.node_base + 1], epoch * (unsigned)up_slabs(c, 1), err);
-            }
-            __syncthreads();
-          },
-          [&](int col, int c) { return ld_dev(&root_in[col + (int64_t)c * nroot]); },
-          [&](int row, int c, double val) { st_dev(&root_out[row + (int64_t)c * nroot], val); });
-      signal_done(root_done);
-    } else {
-      const HbsApplyLevel& v = lev[l];
-      const int n = v.nin[j], k = v.k[j];
-      const int64_t io = v.in_off[j], ko = v.kout_off[j];
-      const double* xin = v.xin;
-      const double* gb = v.gb;
-      const int64_t ldxin = v.ld_xin, ldgb = v.ld_gb;
-      auto wait = [&] {
-        if (tid == 0) {
-          if (l == 1) {
-            wait_count(root_done, epoch * (unsigned)((nroot + kRows - 1) / kRows), err);
-          } else {
-            const HbsApplyLevel& p = lev[l - 1];
-            wait_count(&down_done[p.node_base + j / 2], epoch * (unsigned)down_slabs(p, j / 2), err);
-          }
-        }
-        __syncthreads();
-      };
-      auto load = [&](int col, int c) { return ld_dev(&xin[ko + col + (int64_t)c * ldxin]); };
-      if (l == L) {
-        slab_task<T, RB>(gen + v.e_off[j], n, k, slab, nrhs, xs, red, wait, load, [&](int row, int c, double val) {
-          x[io + row + (int64_t)c * ldx] = val + ld_dev(&gb[io + row + (int64_t)c * ldgb]);
-        });
-      } else {
-        double* out = v.out;
-        const int64_t ldout = v.ld_out;
-        slab_task<T, RB>(gen + v.e_off[j], n, k, slab, nrhs, xs, red, wait, load, [&](int row, int c, double val) {
-          st_dev(&out[io + row + (int64_t)c * ldout], val + ld_dev(&gb[io + row + (int64_t)c * ldgb]));
-        });
-      }
-      signal_done(&down_done[v.node_base + j]);
-    }
-  }
-}
-
 inline size_t slab_lds(int xs_len, int rb) {
   const size_t b = sizeof(double) * ((size_t)xs_len + 4 * (size_t)rb * kRows);
   if (b > 64 * 1024) RW_THROW(RW_EINVAL, "HBS node too large for the apply kernels");
@@ -430,37 +229,4 @@ void launch_hbs_root(int nroot, const double* G, const double* in, int64_t ld_in
                        nroot, G, in, ld_in, out, ld_out, nrhs);
   }
   KERNEL_CHECK("hbs_root");
-}
-
-void launch_hbs_fused(const HbsApplyLevel* lev, int L, const int4* tasks, int ntasks, int grid, int xs_len,
-                      const double* gen, const float* gen32, const double* groot, int nroot, double* root_in,
-                      double* root_out, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
-                      unsigned long long* ticket, unsigned long long ticket_base, unsigned* up_done,
-                      unsigned* down_done, unsigned* root_done, unsigned epoch, int* err, double gen_bytes,
-                      hipStream_t s) {
-  if (ntasks <= 0 || nrhs <= 0) return;
-  const int rb = nrhs == 1 ? 1 : 8;
-  const int xl = xs_len * rb;
-  const size_t sh = slab_lds(xl, rb);
-  KernelTimer kt("hbs_fused_kernel", 0.0, gen_bytes);
-  if (gen32) {
-    if (rb == 1)
-      hipLaunchKernelGGL((hbs_fused_kernel<float, 1>), dim3(grid), dim3(kThreads), sh, s, lev, L, tasks, ntasks, xl,
-                         gen32, groot, nroot, root_in, root_out, b, ldb, x, ldx, nrhs, ticket, ticket_base, up_done,
-                         down_done, root_done, epoch, err);
-    else
-      hipLaunchKernelGGL((hbs_fused_kernel<float, 8>), dim3(grid), dim3(kThreads), sh, s, lev, L, tasks, ntasks, xl,
-                         gen32, groot, nroot, root_in, root_out, b, ldb, x, ldx, nrhs, ticket, ticket_base, up_done,
-                         down_done, root_done, epoch, err);
-  } else {
-    if (rb == 1)
-      hipLaunchKernelGGL((hbs_fused_kernel<double, 1>), dim3(grid), dim3(kThreads), sh, s, lev, L, tasks, ntasks, xl,
-                         gen, groot, nroot, root_in, root_out, b, ldb, x, ldx, nrhs, ticket, ticket_base, up_done,
-                         down_done, root_done, epoch, err);
-    else
-      hipLaunchKernelGGL((hbs_fused_kernel<double, 8>), dim3(grid), dim3(kThreads), sh, s, lev, L, tasks, ntasks, xl,
-                         gen, groot, nroot, root_in, root_out, b, ldb, x, ldx, nrhs, ticket, ticket_base, up_done,
-                         down_done, root_done, epoch, err);
-  }
-  KERNEL_CHECK("hbs_fused");
 }

@@ -27,42 +27,6 @@ void launch_hbs_up(const HbsLevelDev& L, const double* gen, const double* in, in
                    double* bhat, int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s);
 void launch_hbs_up_f32(const HbsLevelDev& L, const float* gen, const double* in, int64_t ld_in,
                        double* bhat, int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s);
-// One level of an HBS apply as seen by the fused sweep (device copy; index
-// 1..L).  Vectors are column-major with the given leading dimensions; at the
-// leaf level `in` / `out` are null and the call's b / x are used.
-struct HbsApplyLevel {
-  const int* nin;
-  const int* k;
-  const int64_t* in_off;
-  const int64_t* kout_off;
-  const int64_t* up_off;
-  const int64_t* e_off;
-  int node_base;  // first completion-counter slot of this level
-  int pad;
-  const double* in;  // up input: the child level's bhat
-  int64_t ld_in;
-  double* bhat;  // up output F* b (the parent level's input)
-  int64_t ld_bhat;
-  double* gb;  // up output G b
-  int64_t ld_gb;
-  const double* xin;  // down input: the parent level's output (the root output at level 1)
-  int64_t ld_xin;
-  double* out;  // down output
-  int64_t ld_out;
-};
-
-// Whole HBS apply in one persistent launch: workgroups draw (node, 64-row
-// slab) tasks in dependency order (up sweep leaves to level 1, root, down
-// sweep) from a ticket counter and wait for the tasks they depend on
-// through per-node completion counters.  Counters and the ticket are
-// cumulative over calls: this call's targets are epoch * slabs and its
-// tickets start at ticket_base.  err is set if a wait times out.
-void launch_hbs_fused(const HbsApplyLevel* lev, int L, const int4* tasks, int ntasks, int grid, int xs_len,
-                      const double* gen, const float* gen32, const double* groot, int nroot, double* root_in,
-                      double* root_out, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
-                      unsigned long long* ticket, unsigned long long ticket_base, unsigned* up_done,
-                      unsigned* down_done, unsigned* root_done, unsigned epoch, int* err, double gen_bytes,
-                      hipStream_t s);
 // root: out = G_root in.
 void launch_hbs_root(int nroot, const double* G, const double* in, int64_t ld_in, double* out,
                      int64_t ld_out, int nrhs, hipStream_t s);
