@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "dev_reduce.h"
 #include "hbs_dev.h"
 
 namespace {
@@ -453,45 +454,10 @@ constexpr int GM_KC = 16;  // K chunk of the tiled workgroup GEMM
 
 struct GjScratch {
   double colv[2][FN];  // column j of the current step (double-buffered)
-  double key[2][FN];   // pivot keys (see pivot_key)
+  double key[2][FN];   // pivot keys (pivot_key_bits)
   double prow[2][FN];  // pivot row
   int piv[FN];         // pivot row of each step
 };
-
-// Pivot key of row r with column-j entry v: |v| with its 7 lowest mantissa
-// bits replaced by 127 - r, so that the largest key is the row of largest
-// |v| (to 2^-45 relative) and, among equal magnitudes, the lowest row.  Used
-// rows get 0; non-finite entries get the largest finite magnitude, so that a
-// non-finite pivot is picked and reported.
-__device__ __forceinline__ double pivot_key(double v, int r, bool used) {
-  if (used) return 0.0;
-  const double m = isfinite(v) ? fabs(v) : 1.7976931348623157e308;
-  const unsigned long long b = ((unsigned long long)__double_as_longlong(m) & ~0x7Full) | (unsigned)(127 - r);
-  return __longlong_as_double((long long)b);
-}
-
-// 64-bit DPP move of v (lanes without a source read 0).
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWMASK, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-// Maximum over the wave of non-negative doubles, by DPP row shifts and row
-// broadcasts (lane 63 ends with the maximum); returned in every lane.
-__device__ __forceinline__ double wave_max_nonneg(double v) {
-  v = fmax(v, dpp_f64<0x111, 0xf>(v));  // row_shr:1
-  v = fmax(v, dpp_f64<0x112, 0xf>(v));  // row_shr:2
-  v = fmax(v, dpp_f64<0x114, 0xf>(v));  // row_shr:4
-  v = fmax(v, dpp_f64<0x118, 0xf>(v));  // row_shr:8
-  v = fmax(v, dpp_f64<0x142, 0xa>(v));  // row_bcast:15
-  v = fmax(v, dpp_f64<0x143, 0xc>(v));  // row_bcast:31
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
 
 struct GemmScratch {
   double As[GM_KC][FN + 1];
@@ -517,12 +483,12 @@ __device__ bool reg_gauss_jordan(double (&a)[64], int n, GjScratch& S, int& myq,
     const bool own = h == (j >> 6);  // wave-uniform
     if (own) {
       S.colv[b][r] = a[0];
-      S.key[b][r] = pivot_key(a[0], r, used);
+      S.key[b][r] = pivot_key_bits<7>(a[0], r, !used);
     }
     __syncthreads();
     // every wave finds the same pivot (same data, same reduction)
     const double kmax = wave_max_nonneg(fmax(S.key[b][lane], S.key[b][lane + 64]));
-    const int p = 127 - (int)(__double_as_longlong(kmax) & 0x7F);
+    const int p = pivot_key_index<7>(kmax);
     const double piv = S.colv[b][p];
     if (!(fabs(piv) > 0.0) || !isfinite(piv)) return false;
     if (r == p) {

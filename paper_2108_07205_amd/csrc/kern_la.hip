@@ -1,8 +1,9 @@
 // Dense FP64 linear algebra on gfx950 for the refinement pre-computation
 // (Algorithm 1 steps 1-4) and the Woodbury solve:
-//  * row interpolative decomposition (Definition 3.1) of a tall sketch by
-//    column-pivoted Gram-Schmidt over rows, one cooperative kernel with a
-//    grid barrier per pivot; interpolation P = C C_J^{-1};
+//  * row interpolative decomposition (Definition 3.1) of a tall sketch:
+//    skeleton rows by tournament selection (blockwise pivoted Gram-Schmidt,
+//    then among the survivors), or by one cooperative kernel with a grid
+//    barrier per pivot for wide sketches; interpolation P = C C_J^{-1};
 //  * tall-skinny products A^T B (W = I + R X, z = R y), Y -= X W;
 //  * Gauss-Jordan inverse with partial pivoting of the small Woodbury
 //    operator W (always FP64);
@@ -10,6 +11,7 @@
 //    update on the FP64 matrix cores, and blocked triangular solves.
 #include <hip/hip_cooperative_groups.h>
 
+#include "dev_reduce.h"
 #include "kernels.h"
 
 namespace cg = cooperative_groups;
@@ -157,6 +159,186 @@ __global__ __launch_bounds__(256) void rowid_kernel(RowIdArgs a) {
     k = step + 1;
   }
   if (g == 0 && tid == 0) *a.out_k = k;
+}
+
+// ------------------------------------------- row ID by tournament selection
+// For sketches of at most 64 columns.  Stage 0 cuts the rows into blocks of
+// 512; every block runs pivoted Gram-Schmidt on its rows (one row in the
+// registers of each thread) and keeps the rows whose residual norm exceeds
+// the threshold tol * (largest row norm of the whole sketch), at most kmax
+// of them.  Each later stage does the same on the concatenated selections of
+// the previous one until one block is left; its selections, in order, are
+// the skeleton rows J.  Selection needs residual norms only to choose
+// pivots, so one projection pass per pivot suffices there; the basis Q of
+// Y(J, :) and the coefficients C = Y Q^T of every row follow with full
+// accuracy, and the largest residual |y_i - C_i Q| certifies the result (the
+// caller falls back to the one-pass kernel above if a row was missed).
+constexpr int SEL_ROWS = 512;
+constexpr int SEL_NC = 64;
+
+// Largest squared row norm of Y (m x nc, row-major), as ordered bits.
+__global__ __launch_bounds__(256) void rowid_maxnorm_kernel(const double* __restrict__ Y, int64_t m, int nc,
+                                                            unsigned long long* __restrict__ out) {
+  double best = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
+    double s = 0.0;
+    for (int c = 0; c < nc; ++c) s += Y[i * nc + c] * Y[i * nc + c];
+    best = fmax(best, s);
+  }
+  best = wave_max_nonneg(best);
+  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(best));
+}
+
+__global__ __launch_bounds__(SEL_ROWS) void rowid_select_kernel(const double* __restrict__ Y, int64_t m, int nc,
+                                                                const int* __restrict__ prev_idx,
+                                                                const int* __restrict__ prev_cnt, int nprev, int kmax,
+                                                                double tol2,
+                                                                const unsigned long long* __restrict__ nrm0,
+                                                                int* __restrict__ out_idx, int* __restrict__ out_cnt) {
+  __shared__ double q[SEL_NC];
+  __shared__ double wkey[SEL_ROWS / 64];
+  __shared__ int pref[1025];
+  const int b = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const double thresh = tol2 * __longlong_as_double((long long)*nrm0);
+  // ---- candidate of this thread
+  int idx = -1;
+  if (!prev_idx) {
+    const int64_t i = (int64_t)b * SEL_ROWS + t;
+    idx = i < m ? (int)i : -1;
+  } else {
+    for (int u = t; u < nprev; u += SEL_ROWS) pref[u + 1] = prev_cnt[u];
+    __syncthreads();
+    if (t == 0) {
+      pref[0] = 0;
+      for (int u = 1; u <= nprev; ++u) pref[u] += pref[u - 1];
+    }
+    __syncthreads();
+    const int pos = b * SEL_ROWS + t;
+    if (pos < pref[nprev]) {
+      int lo = 0, hi = nprev - 1;  // last u with pref[u] <= pos
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pref[mid] <= pos) lo = mid; else hi = mid - 1;
+      }
+      idx = prev_idx[lo * kmax + (pos - pref[lo])];
+    }
+  }
+  double y[SEL_NC];
+  double rn = -1.0;
+  if (idx >= 0) {
+    rn = 0.0;
+#pragma unroll
+    for (int c = 0; c < SEL_NC; ++c) {
+      y[c] = c < nc ? Y[(int64_t)idx * nc + c] : 0.0;
+      rn += y[c] * y[c];
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < SEL_NC; ++c) y[c] = 0.0;
+  }
+  int k = 0;
+  for (; k < kmax; ++k) {
+    // ---- pivot: largest residual norm among the candidates
+    const double key = wave_max_nonneg(pivot_key_bits<9>(rn, t, rn >= 0.0));
+    if (lane == 0) wkey[w] = key;
+    __syncthreads();
+    double bk = wkey[0];
+#pragma unroll
+    for (int u = 1; u < SEL_ROWS / 64; ++u) bk = fmax(bk, wkey[u]);
+    // the pivot's squared norm (the key, to 2^-43 relative) decides the stop;
+    // every thread holds the same key, so the decision is uniform
+    if (!(bk > thresh) || !(bk >= 2.2250738585072014e-308)) break;
+    const int p = pivot_key_index<9>(bk);
+    if (t == p) {
+      const double inv = 1.0 / sqrt(rn);
+#pragma unroll
+      for (int c = 0; c < SEL_NC; ++c) q[c] = y[c] * inv;
+      out_idx[b * kmax + k] = idx;
+      rn = -1.0;
+    }
+    __syncthreads();
+    // ---- project this candidate against q (one pass) and renew its norm
+    if (rn >= 0.0) {
+      double d = 0.0;
+#pragma unroll
+      for (int c = 0; c < SEL_NC; ++c) d += y[c] * q[c];
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < SEL_NC; ++c) {
+        y[c] -= d * q[c];
+        s += y[c] * y[c];
+      }
+      rn = s;
+    }
+  }
+  if (t == 0) out_cnt[b] = k;
+}
+
+// Orthonormal rows Q (k x nc) of Y(J, :) in pivot order: classical
+// Gram-Schmidt with one reorthogonalization, one wave (thread u computes the
+// coefficient on q_u, thread c updates column c).  k <= 64.
+__global__ __launch_bounds__(64) void rowid_basis_kernel(const double* __restrict__ Y, int nc,
+                                                         const int* __restrict__ J, int k, double* __restrict__ Q) {
+  __shared__ double qs[64][SEL_NC + 1];
+  __shared__ double v[SEL_NC], d[64];
+  const int c = threadIdx.x;
+  for (int s = 0; s < k; ++s) {
+    if (c < nc) v[c] = Y[(int64_t)J[s] * nc + c];
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      if (c < s) {
+        double a = 0.0;
+        for (int u = 0; u < nc; ++u) a += v[u] * qs[c][u];
+        d[c] = a;
+      }
+      __syncthreads();
+      if (c < nc) {
+        double a = v[c];
+        for (int u = 0; u < s; ++u) a -= d[u] * qs[u][c];
+        v[c] = a;
+      }
+      __syncthreads();
+    }
+    double n2 = 0.0;
+    for (int u = 0; u < nc; ++u) n2 += v[u] * v[u];
+    const double inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+    if (c < nc) {
+      qs[s][c] = v[c] * inv;
+      Q[s * nc + c] = v[c] * inv;
+    }
+    __syncthreads();
+  }
+}
+
+// C(i, t) = <y_i, q_t> (row-major, ld kmax) for every row, and the largest
+// squared residual |y_i - C_i Q|^2 (ordered bits) in *maxres.
+__global__ __launch_bounds__(256) void rowid_coef_kernel(const double* __restrict__ Y, int64_t m, int nc,
+                                                         const double* __restrict__ Q, int k, int kmax,
+                                                         double* __restrict__ C,
+                                                         unsigned long long* __restrict__ maxres) {
+  extern __shared__ double qs[];  // k x nc
+  for (int u = threadIdx.x; u < k * nc; u += 256) qs[u] = Q[u];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double res = 0.0;
+  if (i < m) {
+    double y[SEL_NC];
+#pragma unroll
+    for (int c = 0; c < SEL_NC; ++c) y[c] = c < nc ? Y[i * nc + c] : 0.0;
+    for (int s = 0; s < k; ++s) {
+      const double* qv = qs + s * nc;
+      double d = 0.0;
+#pragma unroll
+      for (int c = 0; c < SEL_NC; ++c) d += (c < nc ? y[c] * qv[c] : 0.0);
+      C[i * kmax + s] = d;
+#pragma unroll
+      for (int c = 0; c < SEL_NC; ++c) y[c] -= (c < nc ? d * qv[c] : 0.0);
+    }
+#pragma unroll
+    for (int c = 0; c < SEL_NC; ++c) res += y[c] * y[c];
+  }
+  for (int off = 32; off > 0; off >>= 1) res = fmax(res, __shfl_xor(res, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(maxres, (unsigned long long)__double_as_longlong(res));
 }
 
 // C_J(s, t) = C(J[s], t) is lower triangular (row J[s] has no component on
@@ -550,14 +732,20 @@ __global__ __launch_bounds__(256) void trsv_diag_kernel(const double* __restrict
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-size_t rowid_work_bytes(int64_t m, int ncols, int kmax, int ngroups) {
-  (void)kmax;
-  return sizeof(double) * (size_t)(2 * ngroups) + sizeof(int64_t) * (size_t)(2 * ngroups) +
-         sizeof(double) * (size_t)(2 * ngroups) * ncols + sizeof(double) * (size_t)m * ncols + 1024;
+static size_t rowid_sel_bytes(int64_t m, int ncols, int kmax) {
+  const int64_t nb = (m + SEL_ROWS - 1) / SEL_ROWS;
+  return 2 * sizeof(unsigned long long) + 2 * sizeof(int) * (size_t)nb * (kmax + 1) +
+         sizeof(double) * (size_t)kmax * ncols + 1024;
 }
 
-int launch_rowid(rw_ctx* ctx, const double* Y, int64_t m, int ncols, double tol, int kmax, int* J, double* C,
-                 void* work, hipStream_t s) {
+size_t rowid_work_bytes(int64_t m, int ncols, int kmax, int ngroups) {
+  return sizeof(double) * (size_t)(2 * ngroups) + sizeof(int64_t) * (size_t)(2 * ngroups) +
+         sizeof(double) * (size_t)(2 * ngroups) * ncols + sizeof(double) * (size_t)m * ncols + 1024 +
+         rowid_sel_bytes(m, ncols, kmax);
+}
+
+static int rowid_cooperative(rw_ctx* ctx, const double* Y, int64_t m, int ncols, double tol, int kmax, int* J,
+                             double* C, void* work, hipStream_t s) {
   if (m <= 0) return 0;
   const int ncu = ctx->n_cu > 0 ? ctx->n_cu : 256;
   // rows per workgroup: keep them in LDS when they fit (<= 120 KiB of rows)
@@ -596,6 +784,59 @@ int launch_rowid(rw_ctx* ctx, const double* Y, int64_t m, int ncols, double tol,
   int k = 0;
   HIP_CHECK(hipMemcpyAsync(&k, dk, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
+  return k;
+}
+
+int launch_rowid(rw_ctx* ctx, const double* Y, int64_t m, int ncols, double tol, int kmax, int* J, double* C,
+                 void* work, hipStream_t s) {
+  if (m <= 0) return 0;
+  const int64_t nb0 = (m + SEL_ROWS - 1) / SEL_ROWS;
+  if (ncols > SEL_NC || kmax > 64 || nb0 > 1024) return rowid_cooperative(ctx, Y, m, ncols, tol, kmax, J, C, work, s);
+  // the selection buffers sit behind the cooperative kernel's share of `work`
+  char* w = (char*)work + (rowid_work_bytes(m, ncols, kmax, std::max(256, ctx->n_cu)) - rowid_sel_bytes(m, ncols, kmax));
+  w = (char*)(((uintptr_t)w + 255) & ~(uintptr_t)255);
+  unsigned long long* dmax = (unsigned long long*)w;  // [0] max row norm^2, [1] max residual^2
+  int* idx[2] = {(int*)(dmax + 2), (int*)(dmax + 2) + nb0 * kmax};
+  int* cnt[2] = {idx[1] + nb0 * kmax, idx[1] + nb0 * kmax + nb0};
+  double* Q = (double*)(((uintptr_t)(cnt[1] + nb0) + 15) & ~(uintptr_t)15);
+  int k = 0;
+  {
+    KernelTimer kt("rowid_select_kernel", 0.0, 0.0);
+    HIP_CHECK(hipMemsetAsync(dmax, 0, 2 * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(rowid_maxnorm_kernel, dim3((unsigned)std::min<int64_t>(1024, blocks(m))), dim3(256), 0, s, Y, m,
+                       ncols, dmax);
+    KERNEL_CHECK("rowid_maxnorm");
+    int64_t nb = nb0;
+    int cur = 0;
+    hipLaunchKernelGGL(rowid_select_kernel, dim3((unsigned)nb), dim3(SEL_ROWS), 0, s, Y, m, ncols, (const int*)nullptr,
+                       (const int*)nullptr, 0, kmax, tol * tol, dmax, idx[cur], cnt[cur]);
+    KERNEL_CHECK("rowid_select");
+    while (nb > 1) {
+      const int64_t nb2 = (nb * kmax + SEL_ROWS - 1) / SEL_ROWS;
+      hipLaunchKernelGGL(rowid_select_kernel, dim3((unsigned)nb2), dim3(SEL_ROWS), 0, s, Y, m, ncols, idx[cur], cnt[cur],
+                         (int)nb, kmax, tol * tol, dmax, idx[1 - cur], cnt[1 - cur]);
+      KERNEL_CHECK("rowid_select");
+      cur = 1 - cur;
+      nb = nb2;
+    }
+    HIP_CHECK(hipMemcpyAsync(&k, cnt[cur], sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (k > 0) {
+      HIP_CHECK(hipMemcpyAsync(J, idx[cur], sizeof(int) * k, hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(rowid_basis_kernel, dim3(1), dim3(64), 0, s, Y, ncols, J, k, Q);
+      KERNEL_CHECK("rowid_basis");
+      hipLaunchKernelGGL(rowid_coef_kernel, dim3(blocks(m)), dim3(256), sizeof(double) * k * ncols, s, Y, m, ncols, Q,
+                         k, kmax, C, dmax + 1);
+      KERNEL_CHECK("rowid_coef");
+    }
+  }
+  // certificate: every row within 10 tol of span(Y(J, :)) relative to the largest row
+  unsigned long long hm[2] = {0, 0};
+  HIP_CHECK(hipMemcpyAsync(hm, dmax, sizeof(hm), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  const double n0 = __builtin_bit_cast(double, hm[0]), res = __builtin_bit_cast(double, hm[1]);
+  // (k == kmax sends the caller to a wider sketch anyway)
+  if (k < kmax && !(res <= 100.0 * tol * tol * n0)) return rowid_cooperative(ctx, Y, m, ncols, tol, kmax, J, C, work, s);
   return k;
 }
 

@@ -198,7 +198,8 @@ struct rw_refined {
   rw_wall* wall = nullptr;
   rw_ctx* ctx = nullptr;
   std::vector<int32_t> level_of_panel;
-  Discretization disc;                 // refined discretization I_n
+  Discretization disc;                 // refined panels I_n (node records of added panels in pnodes)
+  std::vector<NodeRec> pnodes;         // added nodes I_p, in panel order
   int64_t No = 0, Nk = 0, Nc = 0, Np = 0, Nn = 0, Next = 0;
   DBuf<NodeRec> d_ext;                 // [reference nodes | added nodes]
   DBuf<NodeRec> d_new, d_k, d_c, d_p;
@@ -285,26 +286,35 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
   f.level_of_panel = level_of_panel;
   // ---- a1: geometry and index sets (Sec. 3.1)
   std::unique_ptr<PhaseTimer> t_geo(new PhaseTimer(ctx, "a1_geometry"));
-  discretize(w->curve.a, w->curve.m, w->q, w->gl_s, w->gl_w, refined_panels(w->P, level_of_panel), f.disc);
   const int q = w->q;
+  // only the added panels are new: kept nodes are the reference nodes
+  f.disc.order = q;
+  f.disc.panels = refined_panels(w->P, level_of_panel);
+  f.disc.nodes.clear();
+  {
+    std::vector<Panel> added;
+    for (const Panel& p : f.disc.panels)
+      if (p.added) added.push_back(p);
+    Discretization dp;
+    discretize(w->curve.a, w->curve.m, q, w->gl_s, w->gl_w, std::move(added), dp);
+    f.pnodes = std::move(dp.nodes);
+  }
+  const std::vector<NodeRec>& pnodes = f.pnodes;
   f.No = (int64_t)w->disc.nodes.size();
-  f.Nn = f.disc.n();
+  f.Nn = (int64_t)f.disc.panels.size() * q;
   std::vector<int> k_ref, c_ref, new2ext(f.Nn), ref_kind(f.No, 0);
-  std::vector<NodeRec> pnodes;
   for (int i = 0; i < w->P; ++i)
     for (int j = 0; j < q; ++j) {
       if (level_of_panel[i] >= 0) { c_ref.push_back(i * q + j); ref_kind[i * q + j] = 1; }
       else k_ref.push_back(i * q + j);
     }
-  for (size_t pi = 0; pi < f.disc.panels.size(); ++pi) {
-    const Panel& p = f.disc.panels[pi];
-    for (int j = 0; j < q; ++j) {
-      const int64_t n = (int64_t)pi * q + j;
-      if (p.added) {
-        new2ext[n] = (int)(f.No + (int64_t)pnodes.size());
-        pnodes.push_back(f.disc.nodes[n]);
-      } else {
-        new2ext[n] = p.ref_id * q + j;
+  {
+    int64_t np = 0;
+    for (size_t pi = 0; pi < f.disc.panels.size(); ++pi) {
+      const Panel& p = f.disc.panels[pi];
+      for (int j = 0; j < q; ++j) {
+        const int64_t n = (int64_t)pi * q + j;
+        new2ext[n] = p.added ? (int)(f.No + np++) : p.ref_id * q + j;
       }
     }
   }
@@ -330,15 +340,14 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
   f.d_pos_p.alloc(ctx, pos_p.size());
   f.d_pos_p.upload(pos_p.data(), pos_p.size(), s);
   {
-    DBuf<int> idx(ctx, std::max<size_t>(1, std::max(k_ref.size(), c_ref.size())));
+    DBuf<int> idx_k(ctx, std::max<size_t>(1, k_ref.size())), idx_c(ctx, std::max<size_t>(1, c_ref.size()));
     f.d_k.alloc(ctx, f.Nk);
-    idx.upload(k_ref.data(), k_ref.size(), s);
-    launch_gather_nodes(w->d_nodes.p, idx.p, f.Nk, f.d_k.p, s);
-    HIP_CHECK(hipStreamSynchronize(s));
+    idx_k.upload(k_ref.data(), k_ref.size(), s);
+    launch_gather_nodes(w->d_nodes.p, idx_k.p, f.Nk, f.d_k.p, s);
     f.d_c.alloc(ctx, f.Nc);
-    idx.upload(c_ref.data(), c_ref.size(), s);
-    launch_gather_nodes(w->d_nodes.p, idx.p, f.Nc, f.d_c.p, s);
-    HIP_CHECK(hipStreamSynchronize(s));
+    idx_c.upload(c_ref.data(), c_ref.size(), s);
+    launch_gather_nodes(w->d_nodes.p, idx_c.p, f.Nc, f.d_c.p, s);
+    HIP_CHECK(hipStreamSynchronize(s));  // the host index vectors go out of scope
   }
   f.d_p.alloc(ctx, f.Np);
   if (f.Np) HIP_CHECK(hipMemcpyAsync(f.d_p.p, f.d_ext.p + f.No, sizeof(NodeRec) * f.Np, hipMemcpyDeviceToDevice, s));
@@ -689,7 +698,16 @@ int rw_refined_info(const rw_refined* f, rw_info* info) {
 
 int rw_nodes(const rw_refined* f, double* xy, double* nrm, double* wts, int64_t* n_nodes) {
   if (!f) return RW_EINVAL;
-  return guarded(f->ctx, [&]() { copy_nodes_out(f->disc.nodes, xy, nrm, wts, n_nodes); });
+  return guarded(f->ctx, [&]() {
+    // refined nodes in panel order: kept panels from the reference wall, added ones from pnodes
+    const int q = f->disc.order;
+    std::vector<NodeRec> nd;
+    nd.reserve((size_t)f->Nn);
+    size_t ip = 0;
+    for (const Panel& p : f->disc.panels)
+      for (int j = 0; j < q; ++j) nd.push_back(p.added ? f->pnodes[ip++] : f->wall->disc.nodes[(size_t)p.ref_id * q + j]);
+    copy_nodes_out(nd, xy, nrm, wts, n_nodes);
+  });
 }
 
 int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau) {
