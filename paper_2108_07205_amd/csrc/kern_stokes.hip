@@ -249,102 +249,124 @@ struct SegArgs {
   int nseg;
 };
 
-__device__ __forceinline__ double omega_pm1(uint64_t seed, int64_t row, int col) {
-  uint64_t z = seed ^ ((uint64_t)row * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)(col + 1) * 0xD1B54A32D192ED03ull);
+// 64 random signs of Omega row `row`, columns 64 g .. 64 g + 63 (bit c & 63
+// of the result is column c): SplitMix64 finalizer of a counter, so Omega is
+// never stored and any kernel can regenerate any entry.
+__device__ __forceinline__ uint64_t omega_bits(uint64_t seed, int64_t row, int g) {
+  uint64_t z = seed ^ ((uint64_t)row * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)(g + 1) * 0xD1B54A32D192ED03ull);
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z = z ^ (z >> 31);
-  return (z >> 63) ? -1.0 : 1.0;
+  return z ^ (z >> 31);
 }
 
+// 1 / x for x > 0: hardware reciprocal and one Newton step (the sketch only
+// has to represent the block to well below the interpolation tolerance).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  return y * (2.0 - x * y);
+}
+
+// grid (ceil(2 nt / 64), nsplit), 256 threads.  One workgroup: 64 target rows
+// (32 nodes) x 16 NC sketch columns over its split of the sources.  Per chunk
+// of 8 source nodes (16 unknowns) the threads write the A tile (thread t: the
+// 2x2 kernel block of target node t / 8 and source node t % 8) and the
+// Omega tile (+-1) to LDS; then wave w multiplies its 16 rows by all NC
+// column blocks on the FP64 matrix cores.  LDS is double-buffered, so one
+// barrier per chunk suffices.
 template <int NC>
 __global__ __launch_bounds__(256) void sketch_kernel(const NodeRec* __restrict__ tgt, int64_t nt, SegArgs sa,
                                                      uint64_t seed, int col_off, int nsplit, double* __restrict__ out) {
   constexpr int NCOL = 16 * NC;
-  __shared__ double red[64 * NCOL];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double As[2][16][64 + 2];    // [source unknown][target row]
+  __shared__ double Bs[2][16][NCOL + 2];  // [source unknown][column]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i16 = lane & 15, k4 = lane >> 4;
-  const int64_t tb = blockIdx.x;  // 32 target nodes = 64 rows
+  const int64_t tb = blockIdx.x;
   const int z = blockIdx.y;
-  // target data of this lane's 4 row blocks
-  double tx[4], ty[4], tnc[4];
-  bool tvalid[4];
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb) {
-    const int row = rb * 16 + i16;
-    const int64_t tn = tb * 32 + (row >> 1);
-    tvalid[rb] = tn < nt;
-    const NodeRec t = tgt[tvalid[rb] ? tn : 0];
-    tx[rb] = t.x;
-    ty[rb] = t.y;
-    tnc[rb] = (row & 1) ? t.ny : t.nx;
-  }
-  const int ccomp = i16 & 1;
-  const int dcomp = k4 & 1;
+  // this thread's target node (A tile) and Omega slot (B tile)
+  const int tn = tid >> 3, sn = tid & 7;
+  const int64_t tgi = tb * 32 + tn;
+  const bool tval = tgi < nt;
+  const NodeRec tr = tgt[tval ? tgi : 0];
+  const int kb = tid >> 4, gcol = tid & 15;
   const int64_t ntot = sa.ns[0] + (sa.nseg > 1 ? sa.ns[1] : 0);
-  const int64_t npairs = (ntot + 1) / 2;
-  const int64_t pchunk = (npairs + nsplit - 1) / nsplit;
-  const int64_t p0 = z * pchunk, p1 = min(npairs, p0 + pchunk);
-  double4_t acc[4][NC];
+  const int64_t nchunk_all = (ntot + 7) / 8;
+  const int64_t per = (nchunk_all + nsplit - 1) / nsplit;
+  const int64_t c0 = z * per, c1 = min(nchunk_all, c0 + per);
+  const int grp = (col_off >> 6);
+  double4_t acc[NC];
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < NC; ++cb) acc[rb][cb] = (double4_t){0.0, 0.0, 0.0, 0.0};
-  for (int64_t p = p0 + wave; p < p1; p += 4) {
-    const int64_t gs = 2 * p + (k4 >> 1);
-    double sx = 0, sy = 0, snx = 0, sny = 0, sw = 0, sgn = 0, snd = 0;
-    int64_t orow = 0;
-    if (gs < ntot) {
-      const int sg = (gs < sa.ns[0]) ? 0 : 1;
-      const int64_t li = sg ? gs - sa.ns[0] : gs;
-      const NodeRec q = sa.src[sg][li];
-      sx = q.x; sy = q.y; snx = q.nx; sny = q.ny; sw = q.w; sgn = sa.sign[sg];
-      snd = dcomp ? q.ny : q.nx;
-      orow = sa.orow[sg] + 2 * li + dcomp;
+  for (int cb = 0; cb < NC; ++cb) acc[cb] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  auto src_of = [&](int64_t gs, int& sg, int64_t& li) {
+    sg = (gs < sa.ns[0]) ? 0 : 1;
+    li = sg ? gs - sa.ns[0] : gs;
+  };
+  for (int64_t ch = c0; ch < c1; ++ch) {
+    const int buf = (int)(ch & 1);
+    // ---- A tile: 2x2 block of (target node tn, source node sn)
+    {
+      const int64_t gs = ch * 8 + sn;
+      double b00 = 0, b01 = 0, b10 = 0, b11 = 0;
+      if (gs < ntot && tval) {
+        int sg;
+        int64_t li;
+        src_of(gs, sg, li);
+        const NodeRec q = sa.src[sg][li];
+        const double sgn = sa.sign[sg];
+        const double rx = tr.x - q.x, ry = tr.y - q.y;
+        const double r2 = rx * rx + ry * ry;
+        const double cf = sgn * q.w * kInvPi * (rx * q.nx + ry * q.ny) * rcp_nr(r2 * r2);
+        const double nw = sgn * q.w;
+        b00 = cf * rx * rx + nw * tr.nx * q.nx;
+        b01 = cf * rx * ry + nw * tr.nx * q.ny;
+        b10 = cf * ry * rx + nw * tr.ny * q.nx;
+        b11 = cf * ry * ry + nw * tr.ny * q.ny;
+      }
+      As[buf][2 * sn][2 * tn] = b00;
+      As[buf][2 * sn + 1][2 * tn] = b01;
+      As[buf][2 * sn][2 * tn + 1] = b10;
+      As[buf][2 * sn + 1][2 * tn + 1] = b11;
     }
-    double afr[4];
+    // ---- Omega tile: source unknown kb, columns gcol + 16 cb
+    {
+      const int64_t gs = ch * 8 + (kb >> 1);
+      uint64_t bits = 0;
+      bool ok = gs < ntot;
+      if (ok) {
+        int sg;
+        int64_t li;
+        src_of(gs, sg, li);
+        bits = omega_bits(seed, sa.orow[sg] + 2 * li + (kb & 1), grp);
+      }
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      const double rx = tx[rb] - sx, ry = ty[rb] - sy;
-      const double r2 = rx * rx + ry * ry;
-      const double cf = sgn * sw * kInvPi * (rx * snx + ry * sny) / (r2 * r2);
-      const double rc = ccomp ? ry : rx;
-      const double rd = dcomp ? ry : rx;
-      const double v = cf * rc * rd + sgn * sw * tnc[rb] * snd;
-      afr[rb] = (tvalid[rb] && gs < ntot) ? v : 0.0;
-    }
-#pragma unroll
-    for (int cb = 0; cb < NC; ++cb) {
-      const double bfr = (gs < ntot) ? omega_pm1(seed, orow, col_off + cb * 16 + i16) : 0.0;
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
-        acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[rb], bfr, acc[rb][cb], 0, 0, 0);
-    }
-  }
-  // reduce the four waves (deterministic order) and write this split's part
-  for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < NC; ++cb)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            // v_mfma_f64_16x16x4f64: item r of lane l holds D[l / 16 + 4 r][l % 16]
-            const int row = rb * 16 + k4 + 4 * r, col = cb * 16 + i16;
-            if (w == 0) red[row * NCOL + col] = acc[rb][cb][r];
-            else red[row * NCOL + col] += acc[rb][cb][r];
-          }
+      for (int cb = 0; cb < NC; ++cb) {
+        const int bit = ((col_off & 63) + cb * 16 + gcol) & 63;
+        Bs[buf][kb][cb * 16 + gcol] = ok ? (((bits >> bit) & 1ull) ? -1.0 : 1.0) : 0.0;
+      }
     }
     __syncthreads();
+    // ---- wave: rows 16 wave .. + 15, all column blocks, K = 16
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const double a = As[buf][ks * 4 + k4][wave * 16 + i16];
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb) {
+        const double bb = Bs[buf][ks * 4 + k4][cb * 16 + i16];
+        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[cb], 0, 0, 0);
+      }
+    }
   }
+  // ---- this split's partial sums (rows x NCOL, row-major)
   const int64_t rows_tot = 2 * nt;
   double* o = out + (int64_t)z * rows_tot * NCOL;
-  for (int idx = threadIdx.x; idx < 64 * NCOL; idx += 256) {
-    const int row = idx / NCOL, col = idx - row * NCOL;
-    const int64_t grow = tb * 64 + row;
-    if (grow < rows_tot) o[grow * NCOL + col] = red[idx];
-  }
+#pragma unroll
+  for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      // v_mfma_f64_16x16x4f64: item r of lane l holds D[l / 16 + 4 r][l % 16]
+      const int64_t grow = tb * 64 + wave * 16 + k4 + 4 * r;
+      if (grow < rows_tot) o[grow * NCOL + cb * 16 + i16] = acc[cb][r];
+    }
 }
 
 // Y(:, col_off .. col_off + w) = sum over splits of part[z] (rows x w, row-major)
