@@ -196,6 +196,228 @@ __global__ __launch_bounds__(256) void node_sketch_kernel(const GNode* __restric
   }
 }
 
+// MFMA form of the node sketch (same Y = M Omega, same entities and Omega
+// rows), for nodes of at most 64 RBW candidate rows.  grid (nodes, 2).
+// Near nodes are found pass by pass (2048 nodes per pass, compacted in index
+// order by a block prefix sum, so the summation order is fixed); entity
+// columns are taken 16 at a time: the threads write the A tile (thread t:
+// column t % 16, rows t / 16 + 16 u) and the +-1 Omega tile to LDS, then wave
+// w accumulates its row blocks w, w + 4, ... times the six 16-column blocks
+// of the sketch on the FP64 matrix cores.
+typedef double double4_t __attribute__((ext_vector_type(4)));
+constexpr int NSK_PASS = 2048;
+
+// 96 signs of Omega row pos (bit c of (lo, hi) is column c).
+__device__ __forceinline__ void sketch_signs(uint64_t base, int64_t pos, uint64_t& lo, uint64_t& hi) {
+  const uint64_t key = base ^ ((uint64_t)pos * 0xD1B54A32D192ED03ull);
+  lo = mix64(key);
+  hi = mix64(key ^ 0x5851F42D4C957F2Dull);
+}
+
+template <int RBW>
+__global__ __launch_bounds__(256) void node_sketch_mfma_kernel(const GNode* __restrict__ gn,
+                                                               const int* __restrict__ candr,
+                                                               const int* __restrict__ candc,
+                                                               const NodeRec* __restrict__ nd, int64_t N,
+                                                               uint64_t seed, int64_t part_stride,
+                                                               double* __restrict__ Sr, double* __restrict__ Sc) {
+  constexpr int MR = 64 * RBW;  // row capacity
+  __shared__ NodeRec rn[MR];
+  __shared__ int rc[MR];
+  __shared__ int nlist[NSK_PASS];
+  __shared__ int wsum[257];
+  __shared__ double As[16][MR + 2];
+  __shared__ double Bs[16][SK_R + 2];
+  const GNode g = gn[blockIdx.x];
+  const int side = blockIdx.y, m = g.m;
+  const int z = blockIdx.z, nz = gridDim.z;
+  const int64_t j_lo = (z * N) / nz, j_hi = ((z + 1) * N) / nz;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i16 = lane & 15, k4 = lane >> 4;
+  const int* cand = (side == 0 ? candr : candc) + g.cand_off;
+  double* S = (side == 0 ? Sr : Sc) + g.cand_off * SK_R + (int64_t)z * part_stride;
+  const double rp2 = g.rp * g.rp;
+  const double wp = 2.0 * M_PI * g.rp / SK_NP;
+  const uint64_t base = seed * 0x9E3779B97F4A7C15ull;
+  for (int i = tid; i < m; i += 256) {
+    const int dof = cand[i];
+    rn[i] = nd[dof >> 1];
+    rc[i] = dof & 1;
+  }
+  double4_t acc[RBW][6];
+#pragma unroll
+  for (int u = 0; u < RBW; ++u)
+#pragma unroll
+    for (int cb = 0; cb < 6; ++cb) acc[u][cb] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  const int nrb = (m + 15) >> 4;
+  int buf_any_far = 0;
+  // one chunk of 16 entity columns: kind 0 = near node dofs (nlist[c0 / 2 ..]),
+  // 1 = proxy columns c0 .., 2 = the nullspace column
+  auto chunk = [&](int kind, int c0, int ncols) {
+    const int col = tid & 15;
+    const bool cval = col < ncols;
+    // entity of this column
+    NodeRec q{};
+    int comp = 0, pl = 0, kd = 0;
+    int64_t pos = 0;
+    double px = 0, py = 0, ux = 0, uy = 0;
+    if (cval) {
+      if (kind == 0) {
+        const int j = nlist[(c0 + col) >> 1];
+        comp = (c0 + col) & 1;
+        q = nd[j];
+        pos = 2 * (int64_t)j + comp;
+      } else if (kind == 1) {
+        const int u = c0 + col;
+        const int per = side == 0 ? 4 : 2;
+        pl = u / per;
+        kd = u - pl * per;
+        const double th = 2.0 * M_PI * pl / SK_NP;
+        ux = cos(th);
+        uy = sin(th);
+        px = g.cx + g.rp * ux;
+        py = g.cy + g.rp * uy;
+        pos = 2 * N + 4 * (int64_t)pl + kd;
+      } else {
+        pos = 2 * N + 4 * (int64_t)SK_NP;
+      }
+    }
+    for (int i = tid >> 4; i < nrb * 16; i += 16) {
+      double v = 0.0;
+      if (cval && i < m) {
+        const NodeRec& a = rn[i];
+        const int ca = rc[i];
+        if (kind == 0) {
+          double B[4];
+          if (side == 0) {
+            a_blk(a, q, false, B);  // A(a, j)
+            v = B[ca * 2 + comp];
+          } else {
+            a_blk(q, a, false, B);  // A(j, a)
+            v = B[comp * 2 + ca];
+          }
+        } else if (kind == 1) {
+          if (side == 0) {
+            const double rx = a.x - px, ry = a.y - py, r2 = rx * rx + ry * ry;
+            const double rcv = ca ? ry : rx;
+            if (kd < 2) {  // Stokeslet, source component kd
+              v = ((ca == kd) ? -0.125 * kInvPi * log(r2) : 0.0) + 0.25 * kInvPi / r2 * rcv * (kd ? ry : rx);
+            } else {       // double layer with the radial normal
+              const double cf = (rx * ux + ry * uy) * kInvPi / (r2 * r2) * wp;
+              v = cf * rcv * (kd == 3 ? ry : rx);
+            }
+          } else {
+            const double rx = px - a.x, ry = py - a.y, r2 = rx * rx + ry * ry;
+            const double cf = (rx * a.nx + ry * a.ny) * a.w * kInvPi / (r2 * r2);
+            v = cf * (kd ? ry : rx) * (ca ? ry : rx);
+          }
+        } else {
+          v = (side == 0) ? (ca ? a.ny : a.nx) : a.w * (ca ? a.ny : a.nx);
+        }
+      }
+      As[col][i] = v;
+    }
+    {
+      const int bc = tid >> 4, gcol = tid & 15;  // column bc of the chunk, sketch columns gcol + 16 cb
+      uint64_t lo = 0, hi = 0;
+      const bool ok = bc < ncols;
+      if (ok) {
+        int64_t bpos;
+        if (kind == 0) bpos = 2 * (int64_t)nlist[(c0 + bc) >> 1] + ((c0 + bc) & 1);
+        else if (kind == 1) {
+          const int per = side == 0 ? 4 : 2;
+          const int u = c0 + bc, l = u / per;
+          bpos = 2 * N + 4 * (int64_t)l + (u - l * per);
+        } else bpos = 2 * N + 4 * (int64_t)SK_NP;
+        sketch_signs(base, bpos, lo, hi);
+      }
+#pragma unroll
+      for (int cb = 0; cb < 6; ++cb) {
+        const int c = cb * 16 + gcol;
+        const uint64_t bit = c < 64 ? (lo >> c) & 1ull : (hi >> (c - 64)) & 1ull;
+        Bs[bc][c] = ok ? (bit ? -1.0 : 1.0) : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      double bv[6];
+#pragma unroll
+      for (int cb = 0; cb < 6; ++cb) bv[cb] = Bs[ks * 4 + k4][cb * 16 + i16];
+#pragma unroll
+      for (int u = 0; u < RBW; ++u) {
+        const int rb = wave + 4 * u;
+        if (rb < nrb) {
+          const double a = As[ks * 4 + k4][rb * 16 + i16];
+#pragma unroll
+          for (int cb = 0; cb < 6; ++cb) acc[u][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[cb], acc[u][cb], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  };
+  // ---- near nodes of this split's node range, pass by pass
+  for (int64_t p0 = j_lo; p0 < j_hi; p0 += NSK_PASS) {
+    const int64_t p1 = min(j_hi, p0 + NSK_PASS);
+    const int per = NSK_PASS / 256;
+    int cntl = 0, farl = 0;
+    int loc[NSK_PASS / 256];
+#pragma unroll
+    for (int u = 0; u < NSK_PASS / 256; ++u) {
+      const int64_t j = p0 + tid * per + u;
+      loc[u] = 0;
+      if (j < p1 && !(j >= g.n0 && j < g.n1)) {
+        const double dx = nd[j].x - g.cx, dy = nd[j].y - g.cy;
+        if (dx * dx + dy * dy < rp2) { loc[u] = 1; ++cntl; } else farl = 1;
+      }
+    }
+    wsum[tid + 1] = cntl;
+    buf_any_far |= __syncthreads_or(farl);
+    if (tid == 0) {
+      wsum[0] = 0;
+      for (int u = 1; u <= 256; ++u) wsum[u] += wsum[u - 1];
+    }
+    __syncthreads();
+    int o = wsum[tid];
+#pragma unroll
+    for (int u = 0; u < NSK_PASS / 256; ++u)
+      if (loc[u]) nlist[o++] = (int)(p0 + tid * per + u);
+    const int nnear = wsum[256];
+    __syncthreads();
+    for (int c0 = 0; c0 < 2 * nnear; c0 += 16) chunk(0, c0, min(16, 2 * nnear - c0));
+  }
+  // ---- proxies and the nullspace column stand for the far nodes, if any
+  // (the last split; it checks every node for one outside the circle)
+  if (z == nz - 1) {
+    int farl = 0;
+    for (int64_t j = tid; j < N && !farl; j += 256)
+      if (!(j >= g.n0 && j < g.n1)) {
+        const double dx = nd[j].x - g.cx, dy = nd[j].y - g.cy;
+        farl = dx * dx + dy * dy >= rp2;
+      }
+    buf_any_far = __syncthreads_or(farl);
+  } else {
+    buf_any_far = 0;
+  }
+  if (buf_any_far) {
+    const int npc = SK_NP * (side == 0 ? 4 : 2);
+    for (int c0 = 0; c0 < npc; c0 += 16) chunk(1, c0, min(16, npc - c0));
+    chunk(2, 0, 1);
+  }
+  // ---- write the sketch rows (m x SK_R, row-major)
+#pragma unroll
+  for (int u = 0; u < RBW; ++u) {
+    const int rb = wave + 4 * u;
+#pragma unroll
+    for (int cb = 0; cb < 6; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // v_mfma_f64_16x16x4f64: item r of lane l holds D[l / 16 + 4 r][l % 16]
+        const int row = rb * 16 + k4 + 4 * r;
+        if (rb < nrb && row < m) S[(int64_t)row * SK_R + cb * 16 + i16] = acc[u][cb][r];
+      }
+  }
+}
+
 __global__ __launch_bounds__(256) void node_sketch_sum_kernel(const double* __restrict__ part, int nsplit,
                                                               int64_t len, int64_t stride, double* __restrict__ S) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1040,7 +1262,34 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     for (int j = 0; j < nn; ++j) { gl[j].cand_off = off; off += gl[j].m; mx = std::max(mx, gl[j].m); }
     if (mx > mmax) RW_THROW(RW_ESINGULAR, "HBS node input exceeds the sketch bound");
     dg.upload(gl.data(), nn, s);
-    {
+    if (mx <= 192) {
+      // split each node's near nodes by index range so every level fills the device
+      int nsplit = (int)std::min<int64_t>(64, std::max<int64_t>(1, 1024 / (2 * nn)));
+      nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, N / 64));
+      const int64_t len = off * SK_R;
+      double* outr = Sr.p;
+      double* outc = Sc.p;
+      if (nsplit > 1) {
+        if (part_r.n < (size_t)(len * nsplit)) { part_r.alloc(ctx, len * nsplit); part_c.alloc(ctx, len * nsplit); }
+        outr = part_r.p;
+        outc = part_c.p;
+      }
+      {
+        KernelTimer kt("node_sketch_kernel", 0.0, 0.0);
+        if (mx <= 128)
+          hipLaunchKernelGGL(node_sketch_mfma_kernel<2>, dim3(nn, 2, nsplit), dim3(256), 0, s, dg.p, candr.p, candc.p,
+                             d_nodes, N, seed + 7919ull * l, len, outr, outc);
+        else
+          hipLaunchKernelGGL(node_sketch_mfma_kernel<3>, dim3(nn, 2, nsplit), dim3(256), 0, s, dg.p, candr.p, candc.p,
+                             d_nodes, N, seed + 7919ull * l, len, outr, outc);
+        KERNEL_CHECK("node_sketch");
+      }
+      if (nsplit > 1) {
+        hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len)), dim3(256), 0, s, part_r.p, nsplit, len, len, Sr.p);
+        hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len)), dim3(256), 0, s, part_c.p, nsplit, len, len, Sc.p);
+        KERNEL_CHECK("node_sketch_sum");
+      }
+    } else {
       // split each node's entity range so every level fills the device
       int nsplit = (int)std::min<int64_t>(64, std::max<int64_t>(1, 1024 / (2 * nn)));
       nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, N / 64));
