@@ -686,6 +686,95 @@ struct GemmScratch {
   double Bs[GM_KC][FN + 1];
 };
 
+// ---- 64-wide register Gauss-Jordan: lane l owns row l of the block, wave h
+// the 16 columns 16 h .. 16 h + 15 (a[16]).  Same scheme as the 128-wide one
+// below (pivot column kept in a[0] of its owner wave by shifting that wave's
+// registers, pivot rows found among unused rows, (P A)^-1 stored in place),
+// but a step moves only a quarter of the data through LDS and the pivot
+// search stays inside the owner wave.
+constexpr int GN = 64;
+
+struct Gj64Scratch {
+  double colv[2][GN];
+  double prow[2][GN];
+  double key[2];
+  int piv[GN];
+};
+
+__device__ bool reg_gj64(double (&a)[16], int n, Gj64Scratch& S, int& myq, int& rot) {
+  const int tid = threadIdx.x, r = tid & 63;
+  const int h = __builtin_amdgcn_readfirstlane(tid >> 6);
+  bool used = r >= n;
+  myq = -1;
+  for (int j = 0; j < n; ++j) {
+    const int b = j & 1;
+    const bool own = h == (j >> 4);  // wave-uniform
+    if (own) {
+      S.colv[b][r] = a[0];
+      const double k = wave_max_nonneg(pivot_key_bits<6>(a[0], r, !used));
+      if (r == 0) S.key[b] = k;
+    }
+    __syncthreads();
+    const int p = pivot_key_index<6>(S.key[b]);
+    const double piv = S.colv[b][p];
+    if (!(fabs(piv) > 0.0) || !isfinite(piv)) return false;
+    if (r == p) {
+      used = true;
+      myq = j;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) S.prow[b][16 * h + c] = a[c];
+    }
+    if (tid == 0) S.piv[j] = p;
+    __syncthreads();
+    const double pinv = 1.0 / piv;
+    const double* pr = &S.prow[b][16 * h];
+    if (own) {
+      if (r == p) {
+#pragma unroll
+        for (int c = 0; c < 15; ++c) a[c] = a[c + 1] * pinv;
+        a[15] = pinv;
+      } else {
+        const double f = S.colv[b][r] * pinv;
+#pragma unroll
+        for (int c = 0; c < 15; ++c) a[c] = a[c + 1] - f * pr[c + 1];
+        a[15] = -f;
+      }
+    } else {
+      if (r == p) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) a[c] *= pinv;
+      } else {
+        const double f = S.colv[b][r] * pinv;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) a[c] -= f * pr[c];
+      }
+    }
+  }
+  rot = min(max(n - 16 * h, 0), 16) & 15;
+  return true;
+}
+
+// Registers of reg_gj64 from / to a column-major n x n block (ld).
+__device__ __forceinline__ void gj64_load(const double* M, int ld, int n, double (&a)[16]) {
+  const int r = threadIdx.x & 63, h = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int col = 16 * h + c;
+    a[c] = (r < n && col < n) ? M[r + (int64_t)col * ld] : 0.0;
+  }
+}
+__device__ __forceinline__ void gj64_store(const double (&a)[16], int n, int q, int rot, const int* piv, double* M,
+                                           int ld) {
+  const int r = threadIdx.x & 63, h = threadIdx.x >> 6;
+  if (r < n) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int col = 16 * h + ((c + rot) & 15);
+      if (col < n) M[q + (int64_t)piv[col] * ld] = a[c];
+    }
+  }
+}
+
 // In-place Gauss-Jordan inverse of the n x n block held as described above
 // (n <= FN; rows >= n and columns >= n must hold zeros).  Registers are never
 // indexed dynamically: the half of the columns that holds the current pivot
@@ -860,6 +949,7 @@ __global__ __launch_bounds__(256) void node_factor_kernel(const GNode* __restric
                                                           double* __restrict__ ws, double* __restrict__ gen,
                                                           double* __restrict__ groot, int* __restrict__ fail) {
   __shared__ GjScratch gs;
+  __shared__ Gj64Scratch g64;
   __shared__ GemmScratch ms;
   const GNode g = gn[blockIdx.x];
   const int n = g.m, k = g.k, tid = threadIdx.x, r = tid & (FN - 1);
@@ -893,24 +983,82 @@ __global__ __launch_bounds__(256) void node_factor_kernel(const GNode* __restric
     }
   }
   __syncthreads();
-  double a[64];
-#pragma unroll
-  for (int c = 0; c < 64; ++c) {
-    const int col = 64 * h + c;
-    a[c] = (r < n && col < n) ? Dw[r + (int64_t)col * n] : 0.0;
-  }
-  __syncthreads();
+  double* Dinv = is_root ? groot : ws + g.ws_off;  // Dinv == Dw except at the root
   int q, rot;
-  if (!reg_gauss_jordan(a, n, gs, q, rot)) {
-    if (tid == 0) atomicExch(fail, 1);
-    return;
-  }
-  double* Dinv = is_root ? groot : ws + g.ws_off;
-  if (r < n) {
+  // split of the 2 x 2 block inverse: the children's skeletons for a parent
+  const int n1 = is_leaf ? (n + 1) / 2 : gch[2 * blockIdx.x].k, n2 = n - n1;
+  if (n <= GN) {
+    double a16[16];
+    gj64_load(Dw, n, n, a16);
+    if (!reg_gj64(a16, n, g64, q, rot)) {
+      if (tid == 0) atomicExch(fail, 1);
+      return;
+    }
+    gj64_store(a16, n, q, rot, g64.piv, Dinv, n);
+  } else if (n1 > 0 && n2 > 0 && n1 <= GN && n2 <= GN) {
+    // D = [[A, B], [C, E]]: A^-1 and the Schur complement E - C A^-1 B
+    // inverted in registers, the rest by workgroup GEMMs
+    double* Ai = ws + g.ws_off + (int64_t)n * n;  // n1 x n1
+    double* Xb = Ai + (int64_t)n1 * n1;            // n1 x n2: A^-1 B
+    double* Yb = Xb + (int64_t)n1 * n2;            // n2 x n1: C A^-1
+    double* Si = Yb + (int64_t)n2 * n1;            // n2 x n2: (E - C A^-1 B)^-1
+    double* Tb = Si + (int64_t)n2 * n2;            // n1 x n2: A^-1 B Si
+    const double* Bb = Dw + (int64_t)n1 * n;
+    const double* Cb = Dw + n1;
+    const double* Eb = Dw + n1 + (int64_t)n1 * n;
+    {
+      double a16[16];
+      gj64_load(Dw, n, n1, a16);
+      if (!reg_gj64(a16, n1, g64, q, rot)) {
+        if (tid == 0) atomicExch(fail, 1);
+        return;
+      }
+      gj64_store(a16, n1, q, rot, g64.piv, Ai, n1);
+    }
+    __syncthreads();
+    wg_gemm_small(false, false, n1, n2, n1, 1.0, Ai, n1, Bb, n, nullptr, 0, Xb, n1, ms);
+    wg_gemm_small(false, false, n2, n1, n1, 1.0, Cb, n, Ai, n1, nullptr, 0, Yb, n2, ms);
+    wg_gemm_small(false, false, n2, n2, n1, -1.0, Cb, n, Xb, n1, Eb, n, Si, n2, ms);
+    {
+      double a16[16];
+      gj64_load(Si, n2, n2, a16);
+      if (!reg_gj64(a16, n2, g64, q, rot)) {
+        if (tid == 0) atomicExch(fail, 1);
+        return;
+      }
+      gj64_store(a16, n2, q, rot, g64.piv, Si, n2);
+    }
+    __syncthreads();
+    // D^-1 = [[A^-1 + T Y, -T], [-Si Y, Si]], T = X Si (the blocks of D are
+    // no longer read, so D^-1 may overwrite them)
+    wg_gemm_small(false, false, n1, n2, n2, 1.0, Xb, n1, Si, n2, nullptr, 0, Tb, n1, ms);
+    wg_gemm_small(false, false, n1, n1, n2, 1.0, Tb, n1, Yb, n2, Ai, n1, Dinv, n, ms);
+    wg_gemm_small(false, false, n2, n1, n2, -1.0, Si, n2, Yb, n2, nullptr, 0, Dinv + n1, n, ms);
+    for (int idx = tid; idx < n1 * n2; idx += 256) {
+      const int i = idx % n1, jj = idx / n1;
+      Dinv[i + (int64_t)(n1 + jj) * n] = -Tb[i + (int64_t)jj * n1];
+    }
+    for (int idx = tid; idx < n2 * n2; idx += 256) {
+      const int i = idx % n2, jj = idx / n2;
+      Dinv[n1 + i + (int64_t)(n1 + jj) * n] = Si[i + (int64_t)jj * n2];
+    }
+  } else {
+    double a[64];
 #pragma unroll
     for (int c = 0; c < 64; ++c) {
-      const int col = 64 * h + ((c + rot) & 63);
-      if (col < n) Dinv[q + (int64_t)gs.piv[col] * n] = a[c];
+      const int col = 64 * h + c;
+      a[c] = (r < n && col < n) ? Dw[r + (int64_t)col * n] : 0.0;
+    }
+    if (!reg_gauss_jordan(a, n, gs, q, rot)) {
+      if (tid == 0) atomicExch(fail, 1);
+      return;
+    }
+    if (r < n) {
+#pragma unroll
+      for (int c = 0; c < 64; ++c) {
+        const int col = 64 * h + ((c + rot) & 63);
+        if (col < n) Dinv[q + (int64_t)gs.piv[col] * n] = a[c];
+      }
     }
   }
   __syncthreads();
@@ -929,21 +1077,32 @@ __global__ __launch_bounds__(256) void node_factor_kernel(const GNode* __restric
     wg_gemm_small(op == 1, false, mo, no, n, 1.0, A, op == 2 ? k : n, B, n, nullptr, 0, C, op == 0 ? n : k, ms);
   }
   // D^ = (V* D^-1 U)^-1, through the registers again
-#pragma unroll
-  for (int c = 0; c < 64; ++c) {
-    const int col = 64 * h + c;
-    a[c] = (r < k && col < k) ? Sm[r + (int64_t)col * k] : 0.0;
-  }
-  if (!reg_gauss_jordan(a, k, gs, q, rot)) {
-    if (tid == 0) atomicExch(fail, 2);
-    return;
-  }
   double* Dh = dhat + g.dhat_off;
-  if (r < k) {
+  if (k <= GN) {
+    double a16[16];
+    gj64_load(Sm, k, k, a16);
+    if (!reg_gj64(a16, k, g64, q, rot)) {
+      if (tid == 0) atomicExch(fail, 2);
+      return;
+    }
+    gj64_store(a16, k, q, rot, g64.piv, Dh, k);
+  } else {
+    double a[64];
 #pragma unroll
     for (int c = 0; c < 64; ++c) {
-      const int col = 64 * h + ((c + rot) & 63);
-      if (col < k) Dh[q + (int64_t)gs.piv[col] * k] = a[c];
+      const int col = 64 * h + c;
+      a[c] = (r < k && col < k) ? Sm[r + (int64_t)col * k] : 0.0;
+    }
+    if (!reg_gauss_jordan(a, k, gs, q, rot)) {
+      if (tid == 0) atomicExch(fail, 2);
+      return;
+    }
+    if (r < k) {
+#pragma unroll
+      for (int c = 0; c < 64; ++c) {
+        const int col = 64 * h + ((c + rot) & 63);
+        if (col < k) Dh[q + (int64_t)gs.piv[col] * k] = a[c];
+      }
     }
   }
   __syncthreads();
@@ -1328,7 +1487,7 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
       g.dhat_off = dho;
       dho += (int64_t)k * k;
       g.ws_off = wso;
-      wso += 2 * (int64_t)g.m * g.m + 2 * (int64_t)g.m * k + 2 * (int64_t)k * k;
+      wso += 3 * (int64_t)g.m * g.m + 2 * (int64_t)g.m * k + 2 * (int64_t)k * k;
       g.up_off = gen_used;
       gen_used += (int64_t)(k + g.m) * g.m;
       g.e_off = gen_used;
