@@ -40,9 +40,9 @@ METRIC = "refined-wall solves/sec at N=16k pts, rel err ≤1e-8 vs FP64 oracle; 
 # FP64 matrix (MFMA) 78.6 TFLOP/s; FP64 vector ALU 78.6 TFLOP/s
 PEAK = {"hbm": (8000.0, "GB/s"), "mfma": (78.6, "TFLOP/s"), "alu": (78.6, "TFLOP/s")}
 KERNEL_BOUND = {
-    "sketch_kernel": "mfma", "gemm_nn_sub_kernel": "mfma",
-    "resid_tiles_kernel": "alu", "node_inverse_kernel": "alu", "rowid_kernel": "alu",
-    "node_sketch_kernel": "alu", "node_id_kernel": "alu",
+    "sketch_kernel": "mfma", "gemm_nn_sub_kernel": "mfma", "node_sketch_kernel": "mfma",
+    "resid_tiles_kernel": "alu", "node_inverse_kernel": "alu", "node_factor_kernel": "alu",
+    "rowid_kernel": "alu", "rowid_select_kernel": "alu", "node_id_kernel": "alu",
     "hbs_up_kernel": "hbm", "hbs_down_kernel": "hbm",
 }
 
@@ -123,8 +123,8 @@ def roofline(phases: dict):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without the phase events")
     args = ap.parse_args()

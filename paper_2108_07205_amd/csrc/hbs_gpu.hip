@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "dev_gj.h"
 #include "dev_reduce.h"
 #include "hbs_dev.h"
 
@@ -449,7 +450,6 @@ __global__ __launch_bounds__(512) void node_id_kernel(const GNode* __restrict__ 
                                                       double* __restrict__ Cc, int* __restrict__ info) {
   __shared__ double q[SK_R];
   __shared__ double rv[8];
-  __shared__ int ri[8];
   const GNode g = gn[blockIdx.x];
   const int side = blockIdx.y;
   const int m = g.m, tid = threadIdx.x;
@@ -473,35 +473,38 @@ __global__ __launch_bounds__(512) void node_id_kernel(const GNode* __restrict__ 
   int rank = -1, step = 0;
   const int kmax = min(SK_KCAP, m);
   for (; step < kmax; ++step) {
-    double v = sel ? -1.0 : nrm;
-    int idx = sel ? -1 : i;
-    wave_argmax(v, idx);
-    if ((tid & 63) == 0) { rv[tid >> 6] = v; ri[tid >> 6] = idx; }
+    // pivot: DPP maximum of the keys of the unselected rows (the key carries
+    // the squared norm to 2^-43 relative, enough for the rank decision)
+    const double key = wave_max_nonneg(pivot_key_bits<9>(nrm, i, !sel));
+    if ((tid & 63) == 0) rv[tid >> 6] = key;
     __syncthreads();
-    v = rv[0];
-    int p = ri[0];
-    for (int w = 1; w < 8; ++w)
-      if (ri[w] >= 0 && (p < 0 || rv[w] > v || (rv[w] == v && ri[w] < p))) { v = rv[w]; p = ri[w]; }
+    double v = rv[0];
+#pragma unroll
+    for (int w = 1; w < 8; ++w) v = fmax(v, rv[w]);
+    const int p = v > 0.0 ? pivot_key_index<9>(v) : -1;
     if (step == 0) n0 = v;
     if (rank < 0 && !(v > tol2 * n0)) rank = step;
-    if ((rank >= 0 && step >= rank + SK_EXTRA) || p < 0 || !(v > 0.0)) break;
+    if ((rank >= 0 && step >= rank + SK_EXTRA) || p < 0 || !(v >= 2.2250738585072014e-308)) break;
     if (i == p) {
-      const double inv = 1.0 / sqrt(v);
+      const double inv = 1.0 / sqrt(nrm);
 #pragma unroll
       for (int c = 0; c < 48; ++c) q[h * 48 + c] = y[c] * inv;
     }
     if (tid == 0) pv[step] = p;
     __syncthreads();
-    const double* qh = q + h * 48;
+    // this thread's half of q in registers, then two projection passes
+    double qr[48];
+#pragma unroll
+    for (int c = 0; c < 48; ++c) qr[c] = q[h * 48 + c];
     double cf = 0.0;
 #pragma unroll
     for (int pass = 0; pass < 2; ++pass) {
       double d = 0.0;
 #pragma unroll
-      for (int c = 0; c < 48; ++c) d += y[c] * qh[c];
+      for (int c = 0; c < 48; ++c) d += y[c] * qr[c];
       d += __shfl_xor(d, 1);
 #pragma unroll
-      for (int c = 0; c < 48; ++c) y[c] -= d * qh[c];
+      for (int c = 0; c < 48; ++c) y[c] -= d * qr[c];
       cf += d;
     }
     if (valid && h == 0) C[(int64_t)i * SK_KCAP + step] = cf;
@@ -685,95 +688,6 @@ struct GemmScratch {
   double As[GM_KC][FN + 1];
   double Bs[GM_KC][FN + 1];
 };
-
-// ---- 64-wide register Gauss-Jordan: lane l owns row l of the block, wave h
-// the 16 columns 16 h .. 16 h + 15 (a[16]).  Same scheme as the 128-wide one
-// below (pivot column kept in a[0] of its owner wave by shifting that wave's
-// registers, pivot rows found among unused rows, (P A)^-1 stored in place),
-// but a step moves only a quarter of the data through LDS and the pivot
-// search stays inside the owner wave.
-constexpr int GN = 64;
-
-struct Gj64Scratch {
-  double colv[2][GN];
-  double prow[2][GN];
-  double key[2];
-  int piv[GN];
-};
-
-__device__ bool reg_gj64(double (&a)[16], int n, Gj64Scratch& S, int& myq, int& rot) {
-  const int tid = threadIdx.x, r = tid & 63;
-  const int h = __builtin_amdgcn_readfirstlane(tid >> 6);
-  bool used = r >= n;
-  myq = -1;
-  for (int j = 0; j < n; ++j) {
-    const int b = j & 1;
-    const bool own = h == (j >> 4);  // wave-uniform
-    if (own) {
-      S.colv[b][r] = a[0];
-      const double k = wave_max_nonneg(pivot_key_bits<6>(a[0], r, !used));
-      if (r == 0) S.key[b] = k;
-    }
-    __syncthreads();
-    const int p = pivot_key_index<6>(S.key[b]);
-    const double piv = S.colv[b][p];
-    if (!(fabs(piv) > 0.0) || !isfinite(piv)) return false;
-    if (r == p) {
-      used = true;
-      myq = j;
-#pragma unroll
-      for (int c = 0; c < 16; ++c) S.prow[b][16 * h + c] = a[c];
-    }
-    if (tid == 0) S.piv[j] = p;
-    __syncthreads();
-    const double pinv = 1.0 / piv;
-    const double* pr = &S.prow[b][16 * h];
-    if (own) {
-      if (r == p) {
-#pragma unroll
-        for (int c = 0; c < 15; ++c) a[c] = a[c + 1] * pinv;
-        a[15] = pinv;
-      } else {
-        const double f = S.colv[b][r] * pinv;
-#pragma unroll
-        for (int c = 0; c < 15; ++c) a[c] = a[c + 1] - f * pr[c + 1];
-        a[15] = -f;
-      }
-    } else {
-      if (r == p) {
-#pragma unroll
-        for (int c = 0; c < 16; ++c) a[c] *= pinv;
-      } else {
-        const double f = S.colv[b][r] * pinv;
-#pragma unroll
-        for (int c = 0; c < 16; ++c) a[c] -= f * pr[c];
-      }
-    }
-  }
-  rot = min(max(n - 16 * h, 0), 16) & 15;
-  return true;
-}
-
-// Registers of reg_gj64 from / to a column-major n x n block (ld).
-__device__ __forceinline__ void gj64_load(const double* M, int ld, int n, double (&a)[16]) {
-  const int r = threadIdx.x & 63, h = threadIdx.x >> 6;
-#pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    const int col = 16 * h + c;
-    a[c] = (r < n && col < n) ? M[r + (int64_t)col * ld] : 0.0;
-  }
-}
-__device__ __forceinline__ void gj64_store(const double (&a)[16], int n, int q, int rot, const int* piv, double* M,
-                                           int ld) {
-  const int r = threadIdx.x & 63, h = threadIdx.x >> 6;
-  if (r < n) {
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      const int col = 16 * h + ((c + rot) & 15);
-      if (col < n) M[q + (int64_t)piv[col] * ld] = a[c];
-    }
-  }
-}
 
 // In-place Gauss-Jordan inverse of the n x n block held as described above
 // (n <= FN; rows >= n and columns >= n must hold zeros).  Registers are never

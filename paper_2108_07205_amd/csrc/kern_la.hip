@@ -11,6 +11,7 @@
 //    update on the FP64 matrix cores, and blocked triangular solves.
 #include <hip/hip_cooperative_groups.h>
 
+#include "dev_gj.h"
 #include "dev_reduce.h"
 #include "kernels.h"
 
@@ -474,6 +475,20 @@ __global__ __launch_bounds__(256) void sub_xw_kernel(const double* __restrict__ 
 // ================================================================ small inverse
 // Gauss-Jordan with partial pivoting, one workgroup, matrix in global memory
 // (k x k, ld = k), inverse built in `inv` then copied back.
+// In-place inverse of W (k x k, k <= 64) by the register Gauss-Jordan.
+__global__ __launch_bounds__(256) void small_inverse64_kernel(double* __restrict__ A, int k, int* __restrict__ info) {
+  __shared__ Gj64Scratch S;
+  double a[16];
+  int q, rot;
+  gj64_load(A, k, k, a);
+  if (!reg_gj64(a, k, S, q, rot)) {
+    if (threadIdx.x == 0) *info = 1;
+    return;
+  }
+  gj64_store(a, k, q, rot, S.piv, A, k);
+  if (threadIdx.x == 0) *info = 0;
+}
+
 __global__ __launch_bounds__(256) void small_inverse_kernel(double* __restrict__ A, double* __restrict__ inv, int k,
                                                             int* __restrict__ info) {
   __shared__ double rv[256];
@@ -884,8 +899,11 @@ void launch_sub_xw(const double* X, int64_t ldx, int64_t M, int k, const double*
 }
 
 void launch_small_inverse(double* W, int k, int* info, hipStream_t s) {
-  // the inverse is built in the k*k doubles that follow W
-  hipLaunchKernelGGL(small_inverse_kernel, dim3(1), dim3(256), 0, s, W, W + (size_t)k * k, k, info);
+  // in place for k <= 64; else built in the k*k doubles that follow W
+  if (k <= GN)
+    hipLaunchKernelGGL(small_inverse64_kernel, dim3(1), dim3(256), 0, s, W, k, info);
+  else
+    hipLaunchKernelGGL(small_inverse_kernel, dim3(1), dim3(256), 0, s, W, W + (size_t)k * k, k, info);
   KERNEL_CHECK("small_inverse");
 }
 
