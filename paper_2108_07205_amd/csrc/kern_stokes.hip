@@ -32,52 +32,65 @@ int resid_splits(int64_t n, int nrhs) {
   return (int)(s < 1 ? 1 : s);
 }
 
+// 1 / x (x > 0) to within an ulp or two: hardware reciprocal and two Newton
+// steps (cheaper than the correctly rounded division).
+__device__ __forceinline__ double rcp_nr2(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * (2.0 - x * y);
+  return y * (2.0 - x * y);
+}
+
+// grid (ceil(n / RT), ceil(nrhs / RB), nsplit).  Thread: one target node;
+// sources of this split staged RT at a time in LDS as (x, y), (n w / pi) and
+// (tau_x, tau_y) pairs.
+template <int RB>
 __global__ __launch_bounds__(RT) void resid_tiles_kernel(const NodeRec* __restrict__ nd, int64_t n,
                                                          const double* __restrict__ tau, int nrhs, int nsplit,
                                                          double* __restrict__ part) {
-  __shared__ double sx[RT], sy[RT], snx[RT], sny[RT], stx[RRB][RT], sty[RRB][RT];
+  __shared__ double2 sp[RT], sn[RT], st[RB][RT];
   const int64_t t = (int64_t)blockIdx.x * RT + threadIdx.x;
-  const int r0 = blockIdx.y * RRB;
-  const int nr = min(RRB, nrhs - r0);
+  const int r0 = blockIdx.y * RB;
+  const int nr = min(RB, nrhs - r0);
   const int z = blockIdx.z;
   const int64_t chunk = (n + nsplit - 1) / nsplit;
   const int64_t s0 = z * chunk, s1 = min(n, s0 + chunk);
   const int64_t ld = 2 * n;
   double xi = 0, yi = 0;
   if (t < n) { xi = nd[t].x; yi = nd[t].y; }
-  double ax[RRB], ay[RRB];
+  double ax[RB], ay[RB];
 #pragma unroll
-  for (int c = 0; c < RRB; ++c) { ax[c] = 0; ay[c] = 0; }
+  for (int c = 0; c < RB; ++c) { ax[c] = 0; ay[c] = 0; }
   for (int64_t b0 = s0; b0 < s1; b0 += RT) {
     const int64_t sj = b0 + threadIdx.x;
     __syncthreads();
     if (sj < s1) {
       const NodeRec q = nd[sj];
-      sx[threadIdx.x] = q.x;
-      sy[threadIdx.x] = q.y;
-      snx[threadIdx.x] = q.nx * q.w * kInvPi;
-      sny[threadIdx.x] = q.ny * q.w * kInvPi;
+      sp[threadIdx.x] = make_double2(q.x, q.y);
+      sn[threadIdx.x] = make_double2(q.nx * q.w * kInvPi, q.ny * q.w * kInvPi);
 #pragma unroll
-      for (int c = 0; c < RRB; ++c) {
-        stx[c][threadIdx.x] = (c < nr) ? tau[2 * sj + (int64_t)(r0 + c) * ld] : 0.0;
-        sty[c][threadIdx.x] = (c < nr) ? tau[2 * sj + 1 + (int64_t)(r0 + c) * ld] : 0.0;
-      }
+      for (int c = 0; c < RB; ++c)
+        st[c][threadIdx.x] = (c < nr) ? make_double2(tau[2 * sj + (int64_t)(r0 + c) * ld],
+                                                     tau[2 * sj + 1 + (int64_t)(r0 + c) * ld])
+                                      : make_double2(0.0, 0.0);
     } else {
-      sx[threadIdx.x] = 1e300; sy[threadIdx.x] = 1e300;  // far away; zero weight
-      snx[threadIdx.x] = 0; sny[threadIdx.x] = 0;
+      sp[threadIdx.x] = make_double2(1e300, 1e300);  // far away; zero weight
+      sn[threadIdx.x] = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int c = 0; c < RRB; ++c) { stx[c][threadIdx.x] = 0; sty[c][threadIdx.x] = 0; }
+      for (int c = 0; c < RB; ++c) st[c][threadIdx.x] = make_double2(0.0, 0.0);
     }
     __syncthreads();
     const int cnt = (int)min<int64_t>(RT, s1 - b0);
+#pragma unroll 4
     for (int s = 0; s < cnt; ++s) {
-      const double rx = xi - sx[s], ry = yi - sy[s];
+      const double2 p = sp[s], nw = sn[s];
+      const double rx = xi - p.x, ry = yi - p.y;
       const double r2 = rx * rx + ry * ry;
-      const double inv = r2 > 0.0 ? 1.0 / r2 : 0.0;  // r = 0 only on the diagonal
-      const double cf = (rx * snx[s] + ry * sny[s]) * inv * inv;
+      const double inv = r2 > 0.0 ? rcp_nr2(r2) : 0.0;  // r = 0 only on the diagonal
+      const double cf = (rx * nw.x + ry * nw.y) * inv * inv;
 #pragma unroll
-      for (int c = 0; c < RRB; ++c) {
-        const double d = cf * (rx * stx[c][s] + ry * sty[c][s]);
+      for (int c = 0; c < RB; ++c) {
+        const double2 tv = st[c][s];
+        const double d = cf * (rx * tv.x + ry * tv.y);
         ax[c] += d * rx;
         ay[c] += d * ry;
       }
@@ -440,12 +453,18 @@ void launch_residual(const NodeRec* nodes, int64_t n, const double* g, const dou
   if (n <= 0 || nrhs <= 0) return;
   const int ns = resid_splits(n, nrhs);
   double* sN = part + (size_t)ns * nrhs * 2 * n;
-  dim3 grid(blocks(n, RT), (nrhs + RRB - 1) / RRB, ns);
   // algorithmic work: 12 flops per 2x2 block (r, r^2, r.n, 1/r^2 scaling) + 6 per
   // block and right-hand side; the division counts as one flop
-  KernelTimer kt("resid_tiles_kernel", (double)n * n * (12.0 + 6.0 * nrhs), 0.0);
-  hipLaunchKernelGGL(resid_tiles_kernel, grid, dim3(RT), 0, s, nodes, n, tau, nrhs, ns, part);
-  KERNEL_CHECK("resid_tiles");
+  {
+    KernelTimer kt("resid_tiles_kernel", (double)n * n * (12.0 + 6.0 * nrhs), 0.0);
+    if (nrhs == 1)
+      hipLaunchKernelGGL(resid_tiles_kernel<1>, dim3(blocks(n, RT), 1, ns), dim3(RT), 0, s, nodes, n, tau, nrhs, ns,
+                         part);
+    else
+      hipLaunchKernelGGL(resid_tiles_kernel<RRB>, dim3(blocks(n, RT), (nrhs + RRB - 1) / RRB, ns), dim3(RT), 0, s,
+                         nodes, n, tau, nrhs, ns, part);
+    KERNEL_CHECK("resid_tiles");
+  }
   hipLaunchKernelGGL(flux_kernel, dim3(nrhs), dim3(256), 0, s, nodes, n, tau, sN);
   KERNEL_CHECK("flux");
   hipLaunchKernelGGL(resid_finalize_kernel, dim3(blocks(n), nrhs), dim3(256), 0, s, nodes, n, g, tau, nrhs, ns,
