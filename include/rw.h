@@ -188,6 +188,22 @@ int rw_nodes(const rw_refined* ref, double* xy_host, double* normals_host,
  * RW_ENOCONV (result written, residual above tolerance), RW_EDEVICE. */
 int rw_solve(rw_refined* ref, const double* g_dev, int32_t nrhs, double* tau_dev);
 
+/* Several refinements of one wall in one call (Algorithm 1 solve steps for
+ * each; Sec. 3.2: every refinement reuses the same reference inverse).  The
+ * A_oo^{-1} applies of all instances are stacked into one multi-RHS apply per
+ * sweep, so the reference generators are streamed once for the whole batch;
+ * each instance then takes refinement corrections until its own columns
+ * meet ir_tol (or ir_maxit).  inst: n_inst distinct handles refined from the
+ * same wall (library-owned); g_dev[i], tau_dev[i]: 2*N_n(i) x nrhs[i]
+ * column-major device arrays (caller-owned, g and tau may not alias);
+ * info_host: NULL or n_inst entries that receive each instance's rw_info.
+ * The stream is synchronized before return.  Errors: RW_EINVAL (null or
+ * repeated handles, handles of different walls, nrhs <= 0), RW_ENOMEM,
+ * RW_ENOCONV (all results written; at least one instance stopped above the
+ * tolerance), RW_EDEVICE. */
+int rw_solve_batch(rw_refined* const* inst, int32_t n_inst, const double* const* g_dev,
+                   const int32_t* nrhs, double* const* tau_dev, rw_info* info_host);
+
 /* r = g - A_nn tau on the refined discretization (exact Nystrom operator,
  * entries generated on the fly).  Shapes as rw_solve. */
 int rw_residual(rw_refined* ref, const double* g_dev, const double* tau_dev,

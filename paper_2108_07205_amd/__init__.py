@@ -96,6 +96,7 @@ _SIGS = {
     "rw_refined_info": (ctypes.c_int, [_P, ctypes.POINTER(rw_info)]),
     "rw_nodes": (ctypes.c_int, [_P, _DP, _DP, _DP, _I64P]),
     "rw_solve": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
+    "rw_solve_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
     "rw_residual": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P]),
     "rw_stokeslet_rhs": (ctypes.c_int, [_P, _DP, _DP, ctypes.c_int32, _P]),
 }
@@ -290,6 +291,29 @@ def rw_solve(ctx, ref, g, tau, n_unknowns: int, check: bool = True):
     return rc
 
 
+def rw_solve_batch(ctx, refs, gs, taus, n_unknowns, check: bool = True):
+    """Marshal lists of handles and (nrhs_i, 2 N_n(i)) float64 device tensors
+    into pointer arrays for the C call; returns (rc, [info dict per instance])."""
+    n = len(refs)
+    if not (len(gs) == len(taus) == len(n_unknowns) == n) or n == 0:
+        raise ValueError("refs, gs, taus and n_unknowns must have the same non-zero length")
+    hs = (_P * n)(*refs)
+    pg = (_P * n)()
+    pt = (_P * n)()
+    nr = (ctypes.c_int32 * n)()
+    for i in range(n):
+        pg[i], ng = _dev_ptr(gs[i], "g", n_unknowns[i])
+        pt[i], nt = _dev_ptr(taus[i], "tau", n_unknowns[i])
+        if ng != nt:
+            raise ValueError(f"g and tau column counts differ for instance {i}")
+        nr[i] = ng
+    infos = (rw_info * n)()
+    rc = load_library().rw_solve_batch(hs, n, pg, nr, pt, infos)
+    if check:
+        _check(rc, ctx)
+    return rc, [{f: getattr(inf, f) for f, _ in rw_info._fields_} for inf in infos]
+
+
 def rw_residual(ctx, ref, g, tau, r, n_unknowns: int):
     pg, ng = _dev_ptr(g, "g", n_unknowns)
     pt, _ = _dev_ptr(tau, "tau", n_unknowns)
@@ -371,6 +395,15 @@ class Wall:
 
     def refine(self, panel_ids, levels) -> "Refined":
         return Refined(self, panel_ids, levels)
+
+    def solve_batch(self, refs, gs, check: bool = True):
+        """tau_i = A_nn(i)^{-1} g_i for refinements `refs` of this wall in one
+        call (rw_solve_batch); returns ([tau_i], [info_i])."""
+        import torch
+        taus = [torch.empty_like(g) for g in gs]
+        _, infos = rw_solve_batch(self.ctx.h, [r.h for r in refs], gs, taus, [r.n_unknowns for r in refs],
+                                  check=check)
+        return taus, infos
 
     def close(self):
         if self.h:

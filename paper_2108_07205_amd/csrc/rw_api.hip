@@ -154,6 +154,7 @@ struct rw_wall {
   DBuf<NodeRec> d_nodes;
   HbsDev hbs;                             // A_oo^{-1}
   rw_wall_stats stats{};
+  DBuf<double> bat_in, bat_out;           // rw_solve_batch: stacked A_oo^{-1} inputs / outputs
 };
 
 namespace {
@@ -234,18 +235,26 @@ void refined_ensure_ws(rw_refined* f, int nrhs) {
   f->ws_nrhs = nrhs;
 }
 
-// dst (2 N_n x nrhs) = (A~ + L R)^{-1} src via eq. (wood); accumulate: dst += ...
-void woodbury_apply(rw_refined* f, const double* src, double* dst, int nrhs, bool accumulate) {
+// Woodbury apply in stages so that several instances can share the apply of
+// the reference inverse: in: src -> gext (extended order); the A_oo^{-1}
+// block of y = A~^{-1} gext (ref_apply); out: the A_pp^{-1} block of y, the
+// correction y -= X W^{-1} R y and dst (+)= y in refined order.
+void woodbury_in(rw_refined* f, const double* src, int nrhs) {
+  const int64_t M = 2 * f->Next;
+  launch_to_ext(src, 2 * f->Nn, f->Nn, f->d_new2ext.p, f->gext.p, M, M, nrhs, f->ctx->stream);
+}
+
+void woodbury_ref_apply(rw_refined* f, int nrhs) {
   rw_wall* w = f->wall;
+  const int64_t M = 2 * f->Next;
+  const double gb = (w->precision == RW_F32 ? 4.0 : 8.0) * w->stats.gen_entries;
+  PhaseTimer t(f->ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * nrhs, gb * ((nrhs + 7) / 8));
+  hbs_apply(w, f->gext.p, M, f->y.p, M, nrhs, w->precision == RW_F32);
+}
+
+void woodbury_out(rw_refined* f, double* dst, int nrhs, bool accumulate) {
   hipStream_t s = f->ctx->stream;
   const int64_t M = 2 * f->Next, Mo = 2 * f->No, Mp = 2 * f->Np;
-  launch_to_ext(src, 2 * f->Nn, f->Nn, f->d_new2ext.p, f->gext.p, M, M, nrhs, s);
-  // y = A~^{-1} g_ext: reference HBS inverse on the o-part, LU of A_pp on the p-part
-  {
-    const double gb = (w->precision == RW_F32 ? 4.0 : 8.0) * w->stats.gen_entries;
-    PhaseTimer t(f->ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * nrhs, gb * ((nrhs + 7) / 8));
-    hbs_apply(w, f->gext.p, M, f->y.p, M, nrhs, w->precision == RW_F32);
-  }
   if (f->Np > 0 && f->app_hbs_on) {
     PhaseTimer t(f->ctx, "a6_app_solve", 2.0 * f->app_hbs.entries * nrhs, 8.0 * f->app_hbs.entries * ((nrhs + 7) / 8));
     hbs_dev_apply(f->app_hbs, f->gext.p + Mo, M, f->y.p + Mo, M, nrhs, false);
@@ -263,6 +272,13 @@ void woodbury_apply(rw_refined* f, const double* src, double* dst, int nrhs, boo
     launch_sub_xw(f->X.p, M, M, f->k, f->wv.p, f->y.p, M, nrhs, s);
   }
   launch_from_ext(f->y.p, M, f->Nn, f->d_new2ext.p, dst, 2 * f->Nn, nrhs, accumulate, s);
+}
+
+// dst (2 N_n x nrhs) = (A~ + L R)^{-1} src via eq. (wood); accumulate: dst += ...
+void woodbury_apply(rw_refined* f, const double* src, double* dst, int nrhs, bool accumulate) {
+  woodbury_in(f, src, nrhs);
+  woodbury_ref_apply(f, nrhs);
+  woodbury_out(f, dst, nrhs, accumulate);
 }
 
 void validate_selection(const rw_wall* w, const int32_t* ids, const int32_t* levels, int n_sel) {
@@ -748,6 +764,122 @@ int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau) {
       RW_THROW(RW_ENOCONV, "refinement stopped at relative residual " + std::to_string(worst));
   });
   return rc;
+}
+
+namespace {
+
+// One Woodbury apply for several instances of one wall: their reference-mesh
+// parts are stacked into one multi-RHS apply of A_oo^{-1} (the generators are
+// streamed once for all of them), the rest runs per instance.
+void batch_woodbury(rw_wall* w, const std::vector<rw_refined*>& fs, const std::vector<const double*>& src,
+                    const std::vector<double*>& dst, const std::vector<int>& nr, bool accumulate) {
+  hipStream_t s = w->ctx->stream;
+  const int64_t Mo = 2 * (int64_t)w->disc.nodes.size();
+  int64_t C = 0;
+  for (size_t i = 0; i < fs.size(); ++i) {
+    woodbury_in(fs[i], src[i], nr[i]);
+    C += nr[i];
+  }
+  w->bat_in.ensure(w->ctx, (size_t)(Mo * C));
+  w->bat_out.ensure(w->ctx, (size_t)(Mo * C));
+  int64_t c0 = 0;
+  for (size_t i = 0; i < fs.size(); ++i) {
+    const int64_t M = 2 * fs[i]->Next;
+    HIP_CHECK(hipMemcpy2DAsync(w->bat_in.p + c0 * Mo, sizeof(double) * Mo, fs[i]->gext.p, sizeof(double) * M,
+                               sizeof(double) * Mo, nr[i], hipMemcpyDeviceToDevice, s));
+    c0 += nr[i];
+  }
+  {
+    const double gb = (w->precision == RW_F32 ? 4.0 : 8.0) * w->stats.gen_entries;
+    PhaseTimer t(w->ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * C, gb * ((C + 7) / 8));
+    hbs_apply(w, w->bat_in.p, Mo, w->bat_out.p, Mo, (int)C, w->precision == RW_F32);
+  }
+  c0 = 0;
+  for (size_t i = 0; i < fs.size(); ++i) {
+    const int64_t M = 2 * fs[i]->Next;
+    HIP_CHECK(hipMemcpy2DAsync(fs[i]->y.p, sizeof(double) * M, w->bat_out.p + c0 * Mo, sizeof(double) * Mo,
+                               sizeof(double) * Mo, nr[i], hipMemcpyDeviceToDevice, s));
+    c0 += nr[i];
+    woodbury_out(fs[i], dst[i], nr[i], accumulate);
+  }
+}
+
+}  // namespace
+
+int rw_solve_batch(rw_refined* const* inst, int32_t n_inst, const double* const* g, const int32_t* nrhs,
+                   double* const* tau, rw_info* info) {
+  if (!inst || n_inst <= 0 || !inst[0]) return RW_EINVAL;
+  rw_refined* f0 = inst[0];
+  return guarded(f0->ctx, [&]() {
+    if (!g || !nrhs || !tau) RW_THROW(RW_EINVAL, "null array argument");
+    rw_wall* w = f0->wall;
+    std::set<const rw_refined*> seen;
+    for (int i = 0; i < n_inst; ++i) {
+      if (!inst[i] || inst[i]->wall != w) RW_THROW(RW_EINVAL, "instances must be refinements of one wall");
+      if (!seen.insert(inst[i]).second) RW_THROW(RW_EINVAL, "an instance appears twice");
+      if (nrhs[i] <= 0 || !g[i] || !tau[i]) RW_THROW(RW_EINVAL, "bad arguments of instance " + std::to_string(i));
+    }
+    const double t0 = wall_ms();
+    hipStream_t s = f0->ctx->stream;
+    const rw_options& o = f0->ctx->opt;
+    std::vector<rw_refined*> fs(inst, inst + n_inst);
+    std::vector<int> nr(nrhs, nrhs + n_inst);
+    for (int i = 0; i < n_inst; ++i) refined_ensure_ws(fs[i], nr[i]);
+    batch_woodbury(w, fs, std::vector<const double*>(g, g + n_inst), std::vector<double*>(tau, tau + n_inst), nr,
+                   false);
+    std::vector<int> it(n_inst, 0);
+    std::vector<double> worst(n_inst, 0.0);
+    std::vector<std::vector<double>> nrm(n_inst);
+    for (int i = 0; i < n_inst; ++i) nrm[i].resize(2 * nr[i]);
+    std::vector<char> active(n_inst, 1);
+    for (;;) {
+      for (int i = 0; i < n_inst; ++i) {
+        if (!active[i]) continue;
+        rw_refined* f = fs[i];
+        {
+          PhaseTimer t(f->ctx, "a8_residual", 26.0 * (double)f->Nn * f->Nn * nr[i], 0.0);
+          launch_residual(f->d_new.p, f->Nn, g[i], tau[i], f->r.p, nr[i], f->part.p, s);
+        }
+        launch_colnorms2(f->r.p, g[i], 2 * f->Nn, nr[i], f->norms.p, s);
+        HIP_CHECK(hipMemcpyAsync(nrm[i].data(), f->norms.p, sizeof(double) * 2 * nr[i], hipMemcpyDeviceToHost, s));
+      }
+      HIP_CHECK(hipStreamSynchronize(s));
+      std::vector<rw_refined*> fa;
+      std::vector<const double*> sa;
+      std::vector<double*> da;
+      std::vector<int> na;
+      for (int i = 0; i < n_inst; ++i) {
+        if (!active[i]) continue;
+        worst[i] = 0;
+        for (int c = 0; c < nr[i]; ++c) {
+          const double rel = nrm[i][nr[i] + c] > 0 ? std::sqrt(nrm[i][c] / nrm[i][nr[i] + c]) : std::sqrt(nrm[i][c]);
+          worst[i] = std::max(worst[i], std::isfinite(rel) ? rel : INFINITY);
+        }
+        if (worst[i] <= o.ir_tol || it[i] >= o.ir_maxit) {
+          active[i] = 0;
+          continue;
+        }
+        fa.push_back(fs[i]);
+        sa.push_back(fs[i]->r.p);
+        da.push_back(tau[i]);
+        na.push_back(nr[i]);
+        ++it[i];
+      }
+      if (fa.empty()) break;
+      batch_woodbury(w, fa, sa, da, na, true);
+    }
+    prof_flush(f0->ctx);
+    const double tms = wall_ms() - t0;
+    bool conv = true;
+    for (int i = 0; i < n_inst; ++i) {
+      fs[i]->info.ir_iters = it[i];
+      fs[i]->info.resid = worst[i];
+      fs[i]->info.t_solve_ms = tms;
+      if (info) info[i] = fs[i]->info;
+      if (!(worst[i] <= o.ir_tol) && o.ir_maxit > 0) conv = false;
+    }
+    if (!conv) RW_THROW(RW_ENOCONV, "refinement stopped above the tolerance for at least one instance");
+  });
 }
 
 int rw_residual(rw_refined* f, const double* g, const double* tau, int32_t nrhs, double* r) {
