@@ -136,6 +136,41 @@ def test_woodbury_only_accuracy_and_refinement_gain(ctx, wall64):
     ref.close()
 
 
+def test_mixed_precision_generators(ctx, wall64):
+    """FP32 reference generators (the mixed-precision mode): the Woodbury
+    solve alone carries the FP32 rounding of A_oo^{-1} (relative error well
+    above the FP64 one, below ~1e-4 with kappa ~ 3e2), and the FP64 refinement
+    on the exact residual recovers the FP64 accuracy (<= 1e-10 of the oracle,
+    the metric's bar is 1e-8)."""
+    p = W.config1(seed=4, nrhs=2)
+    sets = _oracle_sets(p)
+    A = K.nystrom_matrix(sets.new)
+    gs = np.stack([K.rhs_vector(sets.new, st.z, st.f) for st in p.rhs])
+    t_or = np.stack([S.solve_refined(A, g) for g in gs])
+    _say("mixed precision: FP32 wall 64 panels")
+    w32 = rw.Wall(ctx, 64, precision=rw.RW_F32)
+    ref32 = w32.refine(p.refinement.panel_ids, p.refinement.levels)
+    ctx.set_options(ir_maxit=0)
+    try:
+        t0 = ref32.solve(_dev(gs)).cpu().numpy()
+    finally:
+        ctx.set_options(ir_maxit=6)
+    e0 = relerr(t0, t_or)
+    t1 = ref32.solve(_dev(gs)).cpu().numpy()
+    e1 = relerr(t1, t_or)
+    inf = ref32.info()
+    _say(f"  woodbury-only err={e0:.2e}, after {inf['ir_iters']} corrections err={e1:.2e}")
+    assert 1e-11 < e0 < 1e-4
+    assert inf["ir_iters"] >= 1
+    assert e1 <= 1e-10
+    # the FP64 wall gives the same refined solution
+    ref64 = wall64.refine(p.refinement.panel_ids, p.refinement.levels)
+    assert relerr(ref64.solve(_dev(gs)).cpu().numpy(), t1) <= 1e-10
+    ref64.close()
+    ref32.close()
+    w32.close()
+
+
 def test_residual_and_multi_rhs(ctx, wall64):
     p = W.config1(seed=5, nrhs=3)
     sets = _oracle_sets(p)
