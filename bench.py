@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without the phase events")
+    ap.add_argument("--extra-steps", type=int, default=40,
+                    help="steps of the side measurements (RHS/s with resident factors, FP32-generator mode)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU (the refined-wall path is not sharded); use --gpus 1",
@@ -154,25 +156,125 @@ def main():
 
     for i in range(args.warmup):
         step(10_000 + i)
-    torch.cuda.synchronize()
-    if not args.no_profile:
-        ctx.profile(True)
-        ctx.profile_reset()
-    lat, ok, infos = [], 0, []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for s in range(args.steps):
-        t0 = time.perf_counter()
-        good, info = step(s)
-        lat.append((time.perf_counter() - t0) * 1e3)
-        ok += int(good)
-        infos.append(info)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    phases = ctx.profile_json() if not args.no_profile else {}
-    ctx.profile(False)
-    lat = np.array(lat)
+
+    def timed(profile: bool):
+        """K steps between synchronizations; with profile, HIP events around
+        every phase and kernel (their overhead is why the headline pass runs
+        without them)."""
+        if profile:
+            ctx.profile(True)
+            ctx.profile_reset()
+        lat, ok, infos = [], 0, []
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for s in range(args.steps):
+            t0 = time.perf_counter()
+            good, info = step(s)
+            lat.append((time.perf_counter() - t0) * 1e3)
+            ok += int(good)
+            infos.append(info)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        ph = ctx.profile_json() if profile else {}
+        ctx.profile(False)
+        return ok, elapsed, np.array(lat), infos, ph
+
+    # headline: seeds 0..K-1 without events; then the same seeds with the
+    # per-kernel HIP events that give the roofline and the kernel table
+    ok, elapsed, lat, infos, _ = timed(False)
     value = ok / elapsed
+    phases = {}
+    prof_rate = None
+    if not args.no_profile:
+        okp, elp, _, _, phases = timed(True)
+        prof_rate = okp / elp
+
+    # ---- side measurements (not the headline): solves with resident factors
+    # (the paper's per-RHS direct solve time) and the FP32-generator mode
+    def rhs_rate(w, nsteps):
+        p = W.config2(seed=0)
+        ref = w.refine(p.refinement.panel_ids, p.refinement.levels)
+        gs = [ref.stokeslet_rhs(p.rhs[0].z, p.rhs[0].f)]
+        for s2 in range(1, 8):
+            q = W.config2(seed=s2)
+            gs.append(ref.stokeslet_rhs(q.rhs[0].z, q.rhs[0].f))
+        tau = torch.empty_like(gs[0])
+        rw.rw_solve(ctx.h, ref.h, gs[0], tau, ref.n_unknowns)
+        torch.cuda.synchronize()
+        t = []
+        worst, iters = 0.0, 0
+        for i in range(nsteps):
+            t0 = time.perf_counter()
+            rw.rw_solve(ctx.h, ref.h, gs[i % len(gs)], tau, ref.n_unknowns)
+            t.append((time.perf_counter() - t0) * 1e3)
+            inf = ref.info()
+            worst, iters = max(worst, inf["resid"]), max(iters, inf["ir_iters"])
+        ref.close()
+        t = np.array(t)
+        return {"rhs_per_s": 1e3 / float(np.mean(t)), "p50_ms": float(np.percentile(t, 50)),
+                "p99_ms": float(np.percentile(t, 99)), "max_resid": worst, "ir_iters_max": iters}
+
+    def solve_rate(w, nsteps):
+        okm, lm, res, its = 0, [], 0.0, 0
+        t0 = time.perf_counter()
+        for s2 in range(nsteps):
+            t1 = time.perf_counter()
+            p = W.config2(seed=s2)
+            ref = w.refine(p.refinement.panel_ids, p.refinement.levels)
+            g = ref.stokeslet_rhs(p.rhs[0].z, p.rhs[0].f)
+            rc = rw.rw_solve(ctx.h, ref.h, g, torch.empty_like(g), ref.n_unknowns, check=False)
+            inf = ref.info()
+            ref.close()
+            okm += int(rc == rw.RW_OK)
+            res, its = max(res, inf["resid"]), max(its, inf["ir_iters"])
+            lm.append((time.perf_counter() - t1) * 1e3)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        return {"solves_per_s": okm / el, "passed": okm, "of": nsteps, "p50_ms": float(np.percentile(lm, 50)),
+                "p99_ms": float(np.percentile(lm, 99)), "max_resid": res, "ir_iters_max": its}
+
+    def batched(w, n_inst):
+        """Uneven refinements of one wall (the batched family: 2..32 panels,
+        2..5 levels, 8 RHS each) solved by one rw_solve_batch call vs one
+        rw_solve per instance (same factors, same gate)."""
+        probs = W.batched_instances(n_inst=n_inst, seed=0, n_panels=1024, nrhs=8)
+        refs, gs = [], []
+        t0 = time.perf_counter()
+        for p in probs:
+            ref = w.refine(p.refinement.panel_ids, p.refinement.levels)
+            refs.append(ref)
+            gs.append(torch.stack([ref.stokeslet_rhs(q.z, q.f) for q in p.rhs]).contiguous())
+        torch.cuda.synchronize()
+        t_ref = time.perf_counter() - t0
+        w.solve_batch(refs, gs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        taus, infos = w.solve_batch(refs, gs)
+        torch.cuda.synchronize()
+        t_bat = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        seq = [ref.solve(g) for ref, g in zip(refs, gs)]
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        agree = max(float((a - b).norm() / b.norm()) for a, b in zip(taus, seq))
+        n_p = [int(r.info()["n_p"]) for r in refs]
+        for r in refs:
+            r.close()
+        nrhs = sum(int(g.shape[0]) for g in gs)
+        return {"instances": n_inst, "rhs": nrhs, "n_p_range": [min(n_p), max(n_p)],
+                "refine_ms_total": 1e3 * t_ref, "batch_solve_ms": 1e3 * t_bat, "sequential_solve_ms": 1e3 * t_seq,
+                "batch_rhs_per_s": nrhs / t_bat, "speedup_vs_sequential": t_seq / t_bat,
+                "max_resid": max(i["resid"] for i in infos), "batch_vs_sequential_rel_diff": agree}
+
+    side = {}
+    if args.extra_steps > 0:
+        side["batched_fp64"] = batched(wall, 16)
+        side["fp64_resident_factors"] = rhs_rate(wall, args.extra_steps)
+        w32 = rw.Wall(ctx, 1024, precision=rw.RW_F32)
+        side["fp32_generators"] = {"refined_solves": solve_rate(w32, args.extra_steps),
+                                   "resident_factors": rhs_rate(w32, args.extra_steps),
+                                   "criterion": "same FP64 residual gate as the headline"}
+        w32.close()
     dom, roof, ktable = roofline(phases)
     hbs = phases.get("a6_hbs_apply")
     out = {
@@ -192,6 +294,7 @@ def main():
                    "nodes_ref": 16384, "n_sel": 16, "levels": 4, "nodes_refined": int(infos[0]["n_k"] + infos[0]["n_p"]),
                    "unknowns_refined": int(2 * (infos[0]["n_k"] + infos[0]["n_p"])), "stokeslets": 16,
                    "nrhs": 1, "leaf_nodes": 64, "id_tol": 1e-10, "seeds": f"0..{args.steps - 1}"},
+        "value_with_kernel_events": prof_rate,
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "gate": {"passed": ok, "of": args.steps, "criterion": "||g - A tau||/||g|| <= 1e-13 (FP64 residual)",
@@ -206,6 +309,7 @@ def main():
         "hbs": {"gen_bytes_f64": st["gen_bytes_f64"], "levels": st["n_levels"], "max_rank": st["max_rank"],
                 "build_ms": st["t_build_ms"],
                 "apply_GBps": (hbs["bytes"] / (hbs["ms"] / 1e3) / 1e9) if hbs and hbs["ms"] > 0 else None},
+        "side": side,
         "cpu_baseline": None,
     }
     if rank == 0 and not args.no_cpu_baseline:

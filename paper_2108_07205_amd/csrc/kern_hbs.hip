@@ -18,6 +18,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kRows = 64;    // rows per workgroup (one per lane)
 constexpr int kUnroll = 16;  // loads in flight per lane
+constexpr int kMfmaMin = 40;  // right-hand sides from which the slab product runs on MFMA (measured crossover)
 
 // acc = rows `row` of M (R x C, ld R) times xs (C x RB, row-major in LDS),
 // over the column quarter w of the four waves.
@@ -149,6 +150,120 @@ __global__ __launch_bounds__(kThreads) void hbs_root_kernel(int n, const double*
 }
 
 
+// ------------------------------------------- many right-hand sides (MFMA)
+// For 40 or more right-hand sides the slab product is a small GEMM: out
+// (64 rows x 64 RHS) = M(slab rows, :) X(:, 64 RHS).  Wave w owns row block w
+// (16 rows) and the four 16-column blocks of the RHS; the A fragments come
+// straight from the column-major generators (16 consecutive rows per column),
+// the B tile (16 input rows x 64 RHS) is staged in LDS per chunk of the
+// contraction, and the FP64 matrix cores accumulate.
+typedef double double4_t __attribute__((ext_vector_type(4)));
+constexpr int kMR = 64;  // right-hand sides per pass
+
+template <typename T, typename Load, typename Emit>
+__device__ __forceinline__ void slab_mfma(const T* __restrict__ M, int R, int C, int slab, int r0, int nr,
+                                          double (*Bs)[kMR + 2], Load load, Emit emit) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, i16 = lane & 15, k4 = lane >> 4;
+  const int arow = slab * kRows + w * 16 + i16;
+  const bool aval = arow < R;
+  const T* mp = M + (aval ? arow : 0);
+  double4_t acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  // this thread's share of a chunk: A fragments of the four k-steps, and B
+  // elements (input row c0 + (e & 15), right-hand side e >> 4 for
+  // e = tid + 256 u), read along input rows
+  double an[4], bn[4];
+  auto fetch = [&](int c0) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kc = c0 + ks * 4 + k4;
+      an[ks] = (aval && kc < C) ? (double)mp[(int64_t)kc * R] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + kThreads * u, kk = e & 15, c = e >> 4;
+      bn[u] = (c0 + kk < C && c < nr) ? load(c0 + kk, r0 + c) : 0.0;
+    }
+  };
+  if (C > 0) fetch(0);
+  for (int c0 = 0; c0 < C; c0 += 16) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + kThreads * u;
+      Bs[e & 15][e >> 4] = bn[u];
+    }
+    double a[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) a[ks] = an[ks];
+    __syncthreads();
+    if (c0 + 16 < C) fetch(c0 + 16);  // in flight during this chunk's products
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], Bs[ks * 4 + k4][cb * 16 + i16], acc[cb], 0, 0, 0);
+  }
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      // v_mfma_f64_16x16x4f64: item r of lane l holds D[l / 16 + 4 r][l % 16]
+      const int row = slab * kRows + w * 16 + k4 + 4 * r, c = cb * 16 + i16;
+      if (row < R && c < nr) emit(row, r0 + c, acc[cb][r]);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void hbs_up_mfma_kernel(
+    int rbmax, const int* __restrict__ nin, const int* __restrict__ kk, const int64_t* __restrict__ in_off,
+    const int64_t* __restrict__ kout_off, const int64_t* __restrict__ up_off, const T* __restrict__ gen,
+    const double* __restrict__ in, int64_t ld_in, double* __restrict__ bhat, int64_t ld_bhat,
+    double* __restrict__ gb, int64_t ld_gb, int nrhs) {
+  __shared__ double Bs[16][kMR + 2];
+  const int j = blockIdx.x / rbmax, rb = blockIdx.x - j * rbmax;
+  const int n = nin[j], k = kk[j], R = k + n;
+  if (rb * kRows >= R) return;
+  const int r0 = blockIdx.y * kMR, nr = min(kMR, nrhs - r0);
+  const int64_t io = in_off[j], ko = kout_off[j];
+  slab_mfma<T>(
+      gen + up_off[j], R, n, rb, r0, nr, Bs, [&](int col, int c) { return in[io + col + (int64_t)c * ld_in]; },
+      [&](int row, int c, double v) {
+        if (row < k) bhat[ko + row + (int64_t)c * ld_bhat] = v;
+        else gb[io + (row - k) + (int64_t)c * ld_gb] = v;
+      });
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void hbs_down_mfma_kernel(
+    int rbmax, const int* __restrict__ nin, const int* __restrict__ kk, const int64_t* __restrict__ in_off,
+    const int64_t* __restrict__ kout_off, const int64_t* __restrict__ e_off, const T* __restrict__ gen,
+    const double* __restrict__ xhat, int64_t ld_xh, const double* __restrict__ gb, int64_t ld_gb,
+    double* __restrict__ out, int64_t ld_out, int nrhs) {
+  __shared__ double Bs[16][kMR + 2];
+  const int j = blockIdx.x / rbmax, rb = blockIdx.x - j * rbmax;
+  const int n = nin[j], k = kk[j];
+  if (rb * kRows >= n) return;
+  const int r0 = blockIdx.y * kMR, nr = min(kMR, nrhs - r0);
+  const int64_t io = in_off[j], ko = kout_off[j];
+  slab_mfma<T>(
+      gen + e_off[j], n, k, rb, r0, nr, Bs, [&](int col, int c) { return xhat[ko + col + (int64_t)c * ld_xh]; },
+      [&](int row, int c, double v) {
+        out[io + row + (int64_t)c * ld_out] = v + gb[io + row + (int64_t)c * ld_gb];
+      });
+}
+
+__global__ __launch_bounds__(kThreads) void hbs_root_mfma_kernel(int n, const double* __restrict__ G,
+                                                                 const double* __restrict__ in, int64_t ld_in,
+                                                                 double* __restrict__ out, int64_t ld_out, int nrhs) {
+  __shared__ double Bs[16][kMR + 2];
+  const int r0 = blockIdx.y * kMR, nr = min(kMR, nrhs - r0);
+  slab_mfma<double>(
+      G, n, n, blockIdx.x, r0, nr, Bs, [&](int col, int c) { return in[col + (int64_t)c * ld_in]; },
+      [&](int row, int c, double v) { out[row + (int64_t)c * ld_out] = v; });
+}
+
 inline size_t slab_lds(int xs_len, int rb) {
   const size_t b = sizeof(double) * ((size_t)xs_len + 4 * (size_t)rb * kRows);
   if (b > 64 * 1024) RW_THROW(RW_EINVAL, "HBS node too large for the apply kernels");
@@ -170,10 +285,18 @@ void up_impl(const HbsLevelDev& L, const T* gen, const double* in, int64_t ld_in
              int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s) {
   if (!L.nnodes || nrhs <= 0) return;
   // generators streamed once per pass of up to 8 right-hand sides
-  const double passes = nrhs == 1 ? 1.0 : (nrhs + 7) / 8;
+  const double passes = nrhs == 1 ? 1.0 : (nrhs < kMfmaMin ? (nrhs + 7) / 8 : (nrhs + kMR - 1) / kMR);
   KernelTimer kt("hbs_up_kernel", 2.0 * L.up_entries * nrhs, sizeof(T) * (double)L.up_entries * passes);
-  if (nrhs == 1) up_launch<T, 1>(L, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs, s);
-  else up_launch<T, 8>(L, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs, s);
+  if (nrhs == 1) {
+    up_launch<T, 1>(L, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs, s);
+  } else if (nrhs < kMfmaMin) {
+    up_launch<T, 8>(L, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs, s);
+  } else {
+    const int rbmax = (L.max_k + L.max_nin + kRows - 1) / kRows;
+    hipLaunchKernelGGL((hbs_up_mfma_kernel<T>), dim3(L.nnodes * rbmax, (nrhs + kMR - 1) / kMR), dim3(kThreads), 0, s,
+                       rbmax, L.nin, L.k, L.in_off, L.kout_off, L.up_off, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb,
+                       nrhs);
+  }
   KERNEL_CHECK("hbs_up");
 }
 
@@ -191,10 +314,18 @@ template <typename T>
 void down_impl(const HbsLevelDev& L, const T* gen, const double* xhat, int64_t ld_xh, const double* gb,
                int64_t ld_gb, double* out, int64_t ld_out, int nrhs, hipStream_t s) {
   if (!L.nnodes || nrhs <= 0) return;
-  const double passes = nrhs == 1 ? 1.0 : (nrhs + 7) / 8;
+  const double passes = nrhs == 1 ? 1.0 : (nrhs < kMfmaMin ? (nrhs + 7) / 8 : (nrhs + kMR - 1) / kMR);
   KernelTimer kt("hbs_down_kernel", 2.0 * L.e_entries * nrhs, sizeof(T) * (double)L.e_entries * passes);
-  if (nrhs == 1) down_launch<T, 1>(L, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs, s);
-  else down_launch<T, 8>(L, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs, s);
+  if (nrhs == 1) {
+    down_launch<T, 1>(L, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs, s);
+  } else if (nrhs < kMfmaMin) {
+    down_launch<T, 8>(L, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs, s);
+  } else {
+    const int rbmax = (L.max_nin + kRows - 1) / kRows;
+    hipLaunchKernelGGL((hbs_down_mfma_kernel<T>), dim3(L.nnodes * rbmax, (nrhs + kMR - 1) / kMR), dim3(kThreads), 0,
+                       s, rbmax, L.nin, L.k, L.in_off, L.kout_off, L.e_off, gen, xhat, ld_xh, gb, ld_gb, out, ld_out,
+                       nrhs);
+  }
   KERNEL_CHECK("hbs_down");
 }
 
@@ -221,7 +352,10 @@ void launch_hbs_root(int nroot, const double* G, const double* in, int64_t ld_in
                      int64_t ld_out, int nrhs, hipStream_t s) {
   if (nroot <= 0 || nrhs <= 0) return;
   const int nb = (nroot + kRows - 1) / kRows;
-  if (nrhs == 1) {
+  if (nrhs >= kMfmaMin) {
+    hipLaunchKernelGGL(hbs_root_mfma_kernel, dim3(nb, (nrhs + kMR - 1) / kMR), dim3(kThreads), 0, s, nroot, G, in,
+                       ld_in, out, ld_out, nrhs);
+  } else if (nrhs == 1) {
     hipLaunchKernelGGL((hbs_root_kernel<1>), dim3(nb, 1), dim3(kThreads), slab_lds(nroot * 1, 1), s, nroot, G, in,
                        ld_in, out, ld_out, nrhs);
   } else {

@@ -74,6 +74,24 @@ def test_hbs_apply_matches_dense_inverse(wall64):
     assert st["n_levels"] == 4 and st["gen_entries"] > 0
 
 
+@pytest.mark.parametrize("nrhs", [1, 5, 16, 70])
+def test_hbs_apply_column_counts(wall64, nrhs):
+    """The apply kernels for 1, up to 39 (8 per pass) and 40 or more (64 per
+    pass on the matrix cores) right-hand sides all match the dense inverse,
+    and every column equals the single-column apply of it."""
+    _say(f"hbs apply 64 panels, {nrhs} columns")
+    d = G.discretize(G.reference_panels(64), 0.3, 5)
+    A = K.nystrom_matrix(d)
+    B = np.random.default_rng(100 + nrhs).standard_normal((nrhs, 2 * d.n))
+    X = wall64.hbs_apply(_dev(B)).cpu().numpy()
+    Xo = np.linalg.solve(A, B.T).T
+    for c in range(nrhs):
+        assert relerr(X[c], Xo[c]) < 2e-9
+    for c in (0, nrhs - 1):
+        x1 = wall64.hbs_apply(_dev(B[c])).cpu().numpy()
+        assert relerr(X[c], x1) < 1e-13
+
+
 def test_hbs_apply_4096_nodes(ctx):
     _say("hbs apply 256 panels")
     wall = rw.Wall(ctx, 256)
