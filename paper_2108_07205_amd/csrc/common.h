@@ -5,7 +5,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
+#include <exception>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -51,11 +53,18 @@ struct PhaseStat {
   double bytes = 0.0;   // algorithmic HBM bytes
 };
 
+struct AuxWorker;
+
 struct rw_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  size_t budget = 0;   // 0 = unlimited
-  size_t used = 0;     // bytes held (in use + cached)
+  size_t budget = 0;   // 0 = unlimited (an aux ctx checks it against both ctxs' bytes)
+  std::atomic<size_t> used{0};   // bytes held (in use + cached); written by the thread that drives this ctx
+  // helper ctx on its own stream whose work one host worker thread runs
+  // beside this ctx's inside a call (aux_fork / aux_join); owner: set on the helper
+  rw_ctx* aux = nullptr;
+  rw_ctx* owner = nullptr;
+  AuxWorker* worker = nullptr;
   std::string err;
   rw_options opt{};
   int n_cu = 0;
@@ -64,6 +73,11 @@ struct rw_ctx {
   // caching allocator: freed blocks are kept by size for reuse
   std::multimap<size_t, void*> cache;
   size_t cached = 0;
+  // second stream for work that runs beside `stream` inside one call
+  // (non-blocking, default priority; created on first use) and the
+  // timing-free events that order the two
+  hipStream_t side = nullptr;
+  std::vector<hipEvent_t> order_events;
   // phase profiler (HIP events on `stream`)
   bool prof = false;
   struct Pending { std::string name; hipEvent_t a, b; double flops, bytes; };
@@ -74,11 +88,13 @@ struct rw_ctx {
 
 // Records a HIP event pair around a phase when the ctx profiler is on; the
 // elapsed time is folded into ctx->phases at the next prof_flush().
+// st: the stream the phase runs on (default: ctx->stream).
 struct PhaseTimer {
   rw_ctx* ctx;
   rw_ctx::Pending p{};
   bool on;
-  PhaseTimer(rw_ctx* c, const char* name, double flops = 0.0, double bytes = 0.0);
+  hipStream_t st;
+  PhaseTimer(rw_ctx* c, const char* name, double flops = 0.0, double bytes = 0.0, hipStream_t stream = nullptr);
   ~PhaseTimer();
 };
 void prof_flush(rw_ctx* ctx);   // call after the stream has been synchronized
@@ -91,8 +107,31 @@ void set_current_ctx(rw_ctx* ctx);
 // Kernel-level timer: like PhaseTimer, keyed "k:<kernel>", on the current ctx.
 struct KernelTimer {
   PhaseTimer* t = nullptr;
-  KernelTimer(const char* name, double flops, double bytes);
+  KernelTimer(const char* name, double flops, double bytes, hipStream_t stream = nullptr);
   ~KernelTimer();
+};
+
+// The ctx's second stream, and its i-th ordering event (both created on
+// first use and kept until the ctx is destroyed).
+hipStream_t ctx_side_stream(rw_ctx* ctx);
+hipEvent_t ctx_order_event(rw_ctx* ctx, int i);
+// `waiter` waits for everything enqueued on `src` so far (event i).
+void stream_after(rw_ctx* ctx, hipStream_t waiter, hipStream_t src, int i);
+
+// Run fn(aux) on the helper ctx's worker thread, its stream ordered after
+// everything enqueued on ctx->stream so far; aux_join waits for it, orders
+// ctx->stream after the helper's stream and rethrows fn's error.  Between
+// the two, the caller's thread may use ctx but not the helper, and fn may
+// use the helper but not ctx.  AuxTask joins (ignoring errors) if the caller
+// leaves early.
+void aux_fork(rw_ctx* ctx, std::function<void(rw_ctx*)> fn);
+void aux_join(rw_ctx* ctx);
+struct AuxTask {
+  rw_ctx* ctx = nullptr;
+  bool active = false;
+  void fork(rw_ctx* c, std::function<void(rw_ctx*)> fn) { aux_fork(c, std::move(fn)); ctx = c; active = true; }
+  void join() { if (active) { active = false; aux_join(ctx); } }
+  ~AuxTask() { if (active) { active = false; try { aux_join(ctx); } catch (...) {} } }
 };
 
 // Device allocation accounted against the ctx budget.

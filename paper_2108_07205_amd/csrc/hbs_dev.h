@@ -27,8 +27,11 @@ struct HbsDev {
 
 // Pack a host-built inverse into HBM.
 void hbs_upload(rw_ctx* ctx, const HbsInverse& H, bool with_f32, HbsDev& out);
-// x = A^{-1} b (b, x: n x nrhs column-major with leading dimensions ldb, ldx).
-void hbs_dev_apply(HbsDev& h, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32);
+// x = A^{-1} b (b, x: n x nrhs column-major with leading dimensions ldb, ldx),
+// enqueued on stream s (the caller's; the generators may have been built on
+// another stream of the same device, ordered before s by the caller).
+void hbs_dev_apply(HbsDev& h, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32,
+                   hipStream_t s);
 
 // GPU build of the HBS inverse of the Nystrom matrix of one node set
 // (contiguous arcs, balanced binary tree with leaves of at most leaf_max

@@ -1230,10 +1230,10 @@ static void hbs_ensure_ws(HbsDev& w, int nrhs) {
   w.ws_nrhs = nrhs;
 }
 
-void hbs_dev_apply(HbsDev& w, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32) {
+void hbs_dev_apply(HbsDev& w, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32,
+                   hipStream_t s) {
   if (nrhs <= 0) return;
   hbs_ensure_ws(w, nrhs);
-  hipStream_t s = w.ctx->stream;
   const bool f32 = use_f32 && w.gen32.p;
   for (int l = w.L; l >= 1; --l) {
     const double* in = (l == w.L) ? b : w.U[l + 1];
@@ -1285,36 +1285,61 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
       if (l == L) g.m = (int)(2 * (g.n1 - g.n0));
     }
   }
-  // ---- buffers sized by the bounds m <= max(2 leaf_max, 2 SK_KCAP), k <= SK_KCAP
+  // ---- buffers sized by the bounds m <= max(2 leaf_max, 2 SK_KCAP), k <= SK_KCAP.
+  // The node factorizations of level l run on the side stream while the
+  // main stream goes on with the sketches and IDs of level l - 1, so every
+  // buffer that a factorization reads (node records, candidate lists, U, V)
+  // has a region per level; the sketch and ID buffers serve one level at a
+  // time on the main stream.
   const int mmax = std::max(2 * leaf_max + 2, 2 * SK_KCAP);
-  int64_t cap_total = 0, gen_bound = 0;
-  for (int l = 1; l <= L; ++l) {
+  std::vector<int64_t> cand_base(L + 1), uv_base(L + 1, 0);
+  int64_t cand_total = 0, uv_total = 0, cap_max = 0, gen_bound = 0, ws_bound = 0;
+  for (int l = 0; l <= L; ++l) {
     const int64_t nn = int64_t(1) << l;
     const int64_t mb = (l == L) ? 2 * ((N + nn - 1) / nn) : 2 * SK_KCAP;
-    cap_total = std::max(cap_total, nn * mb);
+    cand_base[l] = cand_total;
+    cand_total += nn * mb;
+    if (l == 0) continue;
+    uv_base[l] = uv_total;
+    uv_total += nn * mb * SK_KCAP;
+    cap_max = std::max(cap_max, nn * mb);
     gen_bound += nn * ((SK_KCAP + mb) * mb + mb * SK_KCAP);
+    ws_bound = std::max(ws_bound, nn * (3 * mb * mb + 2 * mb * SK_KCAP + 2 * SK_KCAP * SK_KCAP));
   }
-  DBuf<GNode> dg(ctx, (size_t)(int64_t(2) << L));
-  DBuf<int> candr(ctx, cap_total), candc(ctx, cap_total), pcandr(ctx, cap_total), pcandc(ctx, cap_total);
-  DBuf<double> Sr(ctx, cap_total * SK_R), Sc(ctx, cap_total * SK_R);
-  DBuf<double> Cr(ctx, cap_total * SK_KCAP), Cc(ctx, cap_total * SK_KCAP);
+  ws_bound = std::max<int64_t>(ws_bound, 3 * (int64_t)mmax * mmax);
+  DBuf<GNode> dg(ctx, (size_t)(int64_t(2) << L));   // level l at [2^l, 2^(l+1))
+  DBuf<int> candr(ctx, cand_total), candc(ctx, cand_total);
+  DBuf<double> Sr(ctx, cap_max * SK_R), Sc(ctx, cap_max * SK_R);
+  DBuf<double> Cr(ctx, cap_max * SK_KCAP), Cc(ctx, cap_max * SK_KCAP);
   DBuf<int> piv(ctx, (size_t)(int64_t(2) << L) * SK_KCAP), info(ctx, (size_t)(int64_t(4) << L)), fail(ctx, 4);
-  DBuf<double> Ub(ctx, cap_total * SK_KCAP), Vb(ctx, cap_total * SK_KCAP);
+  DBuf<double> Ub(ctx, uv_total), Vb(ctx, uv_total);
   DBuf<double> dhA(ctx, (int64_t(1) << L) * SK_KCAP * SK_KCAP), dhB(ctx, (int64_t(1) << L) * SK_KCAP * SK_KCAP);
-  DBuf<double> ws(ctx, (int64_t(1) << L) * (int64_t)mmax * mmax * 2);
-  DBuf<int64_t> dpar(ctx, (size_t)(int64_t(1) << L));
+  DBuf<double> ws(ctx, ws_bound);
+  DBuf<int64_t> dpar(ctx, (size_t)(int64_t(2) << L));  // level l at [2^l, 2^(l+1))
   DBuf<double> part_r, part_c;
   w.gen.alloc(ctx, gen_bound);
   HIP_CHECK(hipMemsetAsync(fail.p, 0, sizeof(int) * 4, s));
   // leaf candidate lists: all dofs of the range
-  {
-    std::vector<int> c;
-    c.reserve(2 * N);
-    for (int64_t d = 0; d < 2 * N; ++d) c.push_back((int)d);
-    candr.upload(c.data(), c.size(), s);
-    candc.upload(c.data(), c.size(), s);
-    HIP_CHECK(hipStreamSynchronize(s));
-  }
+  std::vector<int> leaf_cand;
+  leaf_cand.reserve(2 * N);
+  for (int64_t d = 0; d < 2 * N; ++d) leaf_cand.push_back((int)d);
+  HIP_CHECK(hipMemcpyAsync(candr.p + cand_base[L], leaf_cand.data(), sizeof(int) * leaf_cand.size(),
+                           hipMemcpyHostToDevice, s));
+  HIP_CHECK(hipMemcpyAsync(candc.p + cand_base[L], leaf_cand.data(), sizeof(int) * leaf_cand.size(),
+                           hipMemcpyHostToDevice, s));
+  // the factor chain starts after everything enqueued so far; whatever way
+  // this function ends, later work on the main stream waits for it
+  const hipStream_t sf = ctx_side_stream(ctx);
+  stream_after(ctx, sf, s, 0);
+  struct SideJoin {
+    rw_ctx* c;
+    hipStream_t main, side;
+    ~SideJoin() {
+      hipEvent_t e = nullptr;
+      try { e = ctx_order_event(c, 2); } catch (...) { return; }
+      if (hipEventRecord(e, side) == hipSuccess) (void)hipStreamWaitEvent(main, e, 0);
+    }
+  } side_join{ctx, s, sf};
   w.ctx = ctx;
   w.L = L;
   w.lev.assign(L + 1, HbsLevelDev());
@@ -1322,65 +1347,57 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
   w.K.assign(L + 2, 0);
   std::vector<std::vector<int>> lev_ints(L + 1);
   std::vector<std::vector<int64_t>> lev_offs(L + 1);
+  std::vector<std::vector<int64_t>> ppos(L + 1);   // host sources of the dpar uploads
   int64_t gen_used = 0;
   w.entries = 0;
   w.max_rank = 0;
   double* dh_child = dhB.p;
   double* dh_cur = dhA.p;
+  const size_t shi = sizeof(double) * SK_KCAP * SK_KCAP;
+  HIP_CHECK(hipFuncSetAttribute((const void*)node_interp_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shi));
+  const size_t shv = INV_LDS_BYTES;
+  HIP_CHECK(hipFuncSetAttribute((const void*)node_inverse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shv));
   for (int l = L; l >= 1; --l) {
     const int nn = 1 << l;
     std::vector<GNode>& gl = G[l];
+    GNode* dgl = dg.p + nn;
+    int* cr = candr.p + cand_base[l];
+    int* cc = candc.p + cand_base[l];
     int64_t off = 0;
     int mx = 0;
     for (int j = 0; j < nn; ++j) { gl[j].cand_off = off; off += gl[j].m; mx = std::max(mx, gl[j].m); }
     if (mx > mmax) RW_THROW(RW_ESINGULAR, "HBS node input exceeds the sketch bound");
-    dg.upload(gl.data(), nn, s);
-    if (mx <= 192) {
-      // split each node's near nodes by index range so every level fills the device
-      int nsplit = (int)std::min<int64_t>(64, std::max<int64_t>(1, 1024 / (2 * nn)));
-      nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, N / 64));
-      const int64_t len = off * SK_R;
-      double* outr = Sr.p;
-      double* outc = Sc.p;
-      if (nsplit > 1) {
-        if (part_r.n < (size_t)(len * nsplit)) { part_r.alloc(ctx, len * nsplit); part_c.alloc(ctx, len * nsplit); }
-        outr = part_r.p;
-        outc = part_c.p;
-      }
-      {
-        KernelTimer kt("node_sketch_kernel", 0.0, 0.0);
-        if (mx <= 128)
-          hipLaunchKernelGGL(node_sketch_mfma_kernel<2>, dim3(nn, 2, nsplit), dim3(256), 0, s, dg.p, candr.p, candc.p,
-                             d_nodes, N, seed + 7919ull * l, len, outr, outc);
-        else
-          hipLaunchKernelGGL(node_sketch_mfma_kernel<3>, dim3(nn, 2, nsplit), dim3(256), 0, s, dg.p, candr.p, candc.p,
-                             d_nodes, N, seed + 7919ull * l, len, outr, outc);
-        KERNEL_CHECK("node_sketch");
-      }
-      if (nsplit > 1) {
-        hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len)), dim3(256), 0, s, part_r.p, nsplit, len, len, Sr.p);
-        hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len)), dim3(256), 0, s, part_c.p, nsplit, len, len, Sc.p);
-        KERNEL_CHECK("node_sketch_sum");
-      }
-    } else {
-      // split each node's entity range so every level fills the device
-      int nsplit = (int)std::min<int64_t>(64, std::max<int64_t>(1, 1024 / (2 * nn)));
-      nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, N / 64));
-      const int64_t len = off * SK_R;
+    HIP_CHECK(hipMemcpyAsync(dgl, gl.data(), sizeof(GNode) * nn, hipMemcpyHostToDevice, s));
+    // split each node's near nodes (entity range) so every level fills the device
+    int nsplit = (int)std::min<int64_t>(64, std::max<int64_t>(1, 1024 / (2 * nn)));
+    nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, N / 64));
+    const int64_t len = off * SK_R;
+    const bool mfma_sketch = mx <= 192;
+    if (nsplit > 1 || !mfma_sketch)
       if (part_r.n < (size_t)(len * nsplit)) { part_r.alloc(ctx, len * nsplit); part_c.alloc(ctx, len * nsplit); }
-      {
-        KernelTimer kt("node_sketch_kernel", 0.0, 0.0);
-        hipLaunchKernelGGL(node_sketch_kernel, dim3(nn, 2, nsplit), dim3(256), 0, s, dg.p, candr.p, candc.p, d_nodes,
-                           N, seed + 7919ull * l, len, part_r.p, part_c.p);
-        KERNEL_CHECK("node_sketch");
-      }
+    double* outr = (nsplit > 1 || !mfma_sketch) ? part_r.p : Sr.p;
+    double* outc = (nsplit > 1 || !mfma_sketch) ? part_c.p : Sc.p;
+    {
+      KernelTimer kt("node_sketch_kernel", 0.0, 0.0);
+      if (mx <= 128)
+        hipLaunchKernelGGL(node_sketch_mfma_kernel<2>, dim3(nn, 2, nsplit), dim3(256), 0, s, dgl, cr, cc, d_nodes, N,
+                           seed + 7919ull * l, len, outr, outc);
+      else if (mfma_sketch)
+        hipLaunchKernelGGL(node_sketch_mfma_kernel<3>, dim3(nn, 2, nsplit), dim3(256), 0, s, dgl, cr, cc, d_nodes, N,
+                           seed + 7919ull * l, len, outr, outc);
+      else
+        hipLaunchKernelGGL(node_sketch_kernel, dim3(nn, 2, nsplit), dim3(256), 0, s, dgl, cr, cc, d_nodes, N,
+                           seed + 7919ull * l, len, outr, outc);
+      KERNEL_CHECK("node_sketch");
+    }
+    if (nsplit > 1 || !mfma_sketch) {
       hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len)), dim3(256), 0, s, part_r.p, nsplit, len, len, Sr.p);
       hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len)), dim3(256), 0, s, part_c.p, nsplit, len, len, Sc.p);
       KERNEL_CHECK("node_sketch_sum");
     }
     {
       KernelTimer kt_id("node_id_kernel", 0.0, 0.0);
-      hipLaunchKernelGGL(node_id_kernel, dim3(nn, 2), dim3(512), 0, s, dg.p, Sr.p, Sc.p, tol * tol, piv.p, Cr.p, Cc.p,
+      hipLaunchKernelGGL(node_id_kernel, dim3(nn, 2), dim3(512), 0, s, dgl, Sr.p, Sc.p, tol * tol, piv.p, Cr.p, Cc.p,
                          info.p);
       KERNEL_CHECK("node_id");
     }
@@ -1410,49 +1427,45 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
       w.entries += 2 * (int64_t)g.m * k + (int64_t)g.m * g.m;
     }
     if (gen_used > (int64_t)w.gen.n) RW_THROW(RW_ESINGULAR, "HBS generator bound exceeded");
+    if (wso > (int64_t)ws.n) RW_THROW(RW_ESINGULAR, "HBS factor workspace bound exceeded");
     // parent candidate sizes and positions of each child's skeleton in them
-    std::vector<int64_t> ppos(nn);
-    if (l >= 1) {
+    ppos[l].assign(nn, 0);
+    {
       int64_t po = 0;
       for (int pj = 0; pj < nn / 2; ++pj) {
-        ppos[2 * pj] = po;
-        ppos[2 * pj + 1] = po + gl[2 * pj].k;
+        ppos[l][2 * pj] = po;
+        ppos[l][2 * pj + 1] = po + gl[2 * pj].k;
         G[l - 1][pj].m = gl[2 * pj].k + gl[2 * pj + 1].k;
         po += G[l - 1][pj].m;
       }
-      dpar.upload(ppos.data(), nn, s);
+      HIP_CHECK(hipMemcpyAsync(dpar.p + nn, ppos[l].data(), sizeof(int64_t) * nn, hipMemcpyHostToDevice, s));
     }
-    dg.upload(gl.data(), nn, s);
-    const size_t shi = sizeof(double) * SK_KCAP * SK_KCAP;
-    HIP_CHECK(hipFuncSetAttribute((const void*)node_interp_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shi));
-    hipLaunchKernelGGL(node_interp_kernel, dim3(nn, 2), dim3(256), shi, s, dg.p, candr.p, candc.p, piv.p, Cr.p, Cc.p,
-                       Ub.p, Vb.p, dpar.p, pcandr.p, pcandc.p);
+    HIP_CHECK(hipMemcpyAsync(dgl, gl.data(), sizeof(GNode) * nn, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(node_interp_kernel, dim3(nn, 2), dim3(256), shi, s, dgl, cr, cc, piv.p, Cr.p,
+                       Cc.p, Ub.p + uv_base[l], Vb.p + uv_base[l], dpar.p + nn, candr.p + cand_base[l - 1],
+                       candc.p + cand_base[l - 1]);
     KERNEL_CHECK("node_interp");
-    // children (level l + 1) descriptors for the parent assembly
-    DBuf<GNode> dch;
-    if (l < L) {
-      dch.alloc(ctx, (size_t)(2 * nn));
-      dch.upload(G[l + 1].data(), 2 * nn, s);
-    }
-    if (ws.n < (size_t)wso) ws.alloc(ctx, wso);
-    const size_t shv = INV_LDS_BYTES;
-    HIP_CHECK(hipFuncSetAttribute((const void*)node_inverse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shv));
+    // ---- node factorizations of this level on the side stream, once the
+    // interpolation matrices are in; the children's D^ come from the
+    // previous launch on the same stream
+    stream_after(ctx, sf, s, 1);
     double fl = 0;
     for (int j = 0; j < nn; ++j) {
       const double nm = gl[j].m, kk2 = gl[j].k;
       fl += 2.0 * nm * nm * nm + 2.0 * (3.0 * nm * nm * kk2 + 3.0 * nm * kk2 * kk2) + 2.0 * kk2 * kk2 * kk2;
     }
+    const GNode* dch = (l < L) ? dg.p + 2 * nn : dgl;
     if (mx <= FN) {
-      KernelTimer kt_inv("node_factor_kernel", fl, 0.0);
-      hipLaunchKernelGGL(node_factor_kernel, dim3(nn), dim3(256), 0, s, dg.p, l < L ? dch.p : dg.p, l == L ? 1 : 0,
-                         0, candr.p, candc.p, d_nodes, Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, (double*)nullptr,
+      KernelTimer kt_inv("node_factor_kernel", fl, 0.0, sf);
+      hipLaunchKernelGGL(node_factor_kernel, dim3(nn), dim3(256), 0, sf, dgl, dch, l == L ? 1 : 0, 0, cr, cc, d_nodes,
+                         Ub.p + uv_base[l], Vb.p + uv_base[l], dh_child, dh_cur, ws.p, w.gen.p, (double*)nullptr,
                          fail.p);
       KERNEL_CHECK("node_factor");
     } else {
-      KernelTimer kt_inv("node_inverse_kernel", fl, 0.0);
-      hipLaunchKernelGGL(node_inverse_kernel, dim3(nn), dim3(256), shv, s, dg.p, l < L ? dch.p : dg.p, l == L ? 1 : 0,
-                         0, candr.p, candc.p, d_nodes, Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, (double*)nullptr,
-                         fail.p);
+      KernelTimer kt_inv("node_inverse_kernel", fl, 0.0, sf);
+      hipLaunchKernelGGL(node_inverse_kernel, dim3(nn), dim3(256), shv, sf, dgl, dch, l == L ? 1 : 0, 0, cr, cc,
+                         d_nodes, Ub.p + uv_base[l], Vb.p + uv_base[l], dh_child, dh_cur, ws.p, w.gen.p,
+                         (double*)nullptr, fail.p);
       KERNEL_CHECK("node_inverse");
     }
     // level descriptors for the apply
@@ -1485,12 +1498,9 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     }
     w.S[l] = off;
     w.K[l] = kk;
-    HIP_CHECK(hipStreamSynchronize(s));
-    std::swap(candr, pcandr);
-    std::swap(candc, pcandc);
     std::swap(dh_child, dh_cur);
   }
-  // ---- root
+  // ---- root (side stream, after its record is uploaded)
   {
     GNode& g = G[0][0];
     g.cand_off = 0;
@@ -1498,18 +1508,21 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     g.ws_off = 0;
     w.nroot = g.m;
     w.S[0] = g.m;
-    dg.upload(&g, 1, s);
-    DBuf<GNode> dch(ctx, 2);
-    dch.upload(G[1].data(), 2, s);
+    HIP_CHECK(hipMemcpyAsync(dg.p + 1, &g, sizeof(GNode), hipMemcpyHostToDevice, s));
     w.groot.alloc(ctx, (size_t)g.m * g.m);
-    if (g.m <= FN)
-      hipLaunchKernelGGL(node_factor_kernel, dim3(1), dim3(256), 0, s, dg.p, dch.p, 0, 1, candr.p, candc.p, d_nodes,
+    stream_after(ctx, sf, s, 1);
+    int* cr = candr.p + cand_base[0];
+    int* cc = candc.p + cand_base[0];
+    if (g.m <= FN) {
+      const double nm = g.m;
+      KernelTimer kt_root("node_factor_kernel", 2.0 * nm * nm * nm, 0.0, sf);
+      hipLaunchKernelGGL(node_factor_kernel, dim3(1), dim3(256), 0, sf, dg.p + 1, dg.p + 2, 0, 1, cr, cc, d_nodes,
                          Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, w.groot.p, fail.p);
-    else
-      hipLaunchKernelGGL(node_inverse_kernel, dim3(1), dim3(256), (size_t)INV_LDS_BYTES, s,
-                         dg.p, dch.p, 0, 1, candr.p, candc.p, d_nodes,
+    } else
+      hipLaunchKernelGGL(node_inverse_kernel, dim3(1), dim3(256), shv, sf, dg.p + 1, dg.p + 2, 0, 1, cr, cc, d_nodes,
                          Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, w.groot.p, fail.p);
     KERNEL_CHECK("node_inverse_root");
+    stream_after(ctx, s, sf, 2);
     w.entries += (int64_t)g.m * g.m;
     int hf[4];
     fail.download(hf, 4, s);

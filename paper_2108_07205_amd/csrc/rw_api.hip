@@ -3,8 +3,10 @@
 // Woodbury solve with FP64 iterative refinement.
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <set>
 
 #include "geometry.h"
@@ -14,6 +16,12 @@
 // Caching allocator: a freed block goes back to ctx->cache and is reused by a
 // later request of the same or a slightly smaller size, so the per-step
 // refine / solve cycle does not call hipMalloc or hipFree once warm.
+// Bytes held by ctx and by the ctx that shares its budget (owner or helper).
+static size_t budget_used(const rw_ctx* ctx) {
+  const rw_ctx* other = ctx->owner ? ctx->owner : ctx->aux;
+  return ctx->used.load() + (other ? other->used.load() : 0);
+}
+
 void* dev_alloc(rw_ctx* ctx, size_t bytes) {
   bytes = (bytes + 255) & ~size_t(255);
   auto it = ctx->cache.lower_bound(bytes);
@@ -23,20 +31,20 @@ void* dev_alloc(rw_ctx* ctx, size_t bytes) {
     ctx->cache.erase(it);
     return p;
   }
-  if (ctx->budget && ctx->used + bytes > ctx->budget) {
+  if (ctx->budget && budget_used(ctx) + bytes > ctx->budget) {
     // release cached blocks before giving up
-    for (auto& kv : ctx->cache) { (void)hipFree(kv.second); ctx->used -= std::min(ctx->used, kv.first); }
+    for (auto& kv : ctx->cache) { (void)hipFree(kv.second); ctx->used -= std::min(ctx->used.load(), kv.first); }
     ctx->cache.clear();
     ctx->cached = 0;
-    if (ctx->used + bytes > ctx->budget)
-      RW_THROW(RW_ENOMEM, "HBM budget exceeded: need " + std::to_string(ctx->used + bytes) + " bytes, budget " +
+    if (budget_used(ctx) + bytes > ctx->budget)
+      RW_THROW(RW_ENOMEM, "HBM budget exceeded: need " + std::to_string(budget_used(ctx) + bytes) + " bytes, budget " +
                               std::to_string(ctx->budget));
   }
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    for (auto& kv : ctx->cache) { (void)hipFree(kv.second); ctx->used -= std::min(ctx->used, kv.first); }
+    for (auto& kv : ctx->cache) { (void)hipFree(kv.second); ctx->used -= std::min(ctx->used.load(), kv.first); }
     ctx->cache.clear();
     ctx->cached = 0;
     e = hipMalloc(&p, bytes);
@@ -61,13 +69,14 @@ void dev_free(rw_ctx* ctx, void* p, size_t bytes) {
 static void ctx_release_cache(rw_ctx* ctx) {
   for (auto& kv : ctx->cache) {
     (void)hipFree(kv.second);
-    ctx->used -= std::min(ctx->used, kv.first);
+    ctx->used -= std::min(ctx->used.load(), kv.first);
   }
   ctx->cache.clear();
   ctx->cached = 0;
 }
 
-PhaseTimer::PhaseTimer(rw_ctx* c, const char* name, double flops, double bytes) : ctx(c), on(c && c->prof) {
+PhaseTimer::PhaseTimer(rw_ctx* c, const char* name, double flops, double bytes, hipStream_t stream)
+    : ctx(c), on(c && c->prof), st(stream ? stream : (c ? c->stream : nullptr)) {
   if (!on) return;
   p.name = name;
   p.flops = flops;
@@ -78,15 +87,27 @@ PhaseTimer::PhaseTimer(rw_ctx* c, const char* name, double flops, double bytes) 
     else HIP_CHECK(hipEventCreate(&e));
     (i == 0 ? p.a : p.b) = e;
   }
-  HIP_CHECK(hipEventRecord(p.a, ctx->stream));
+  HIP_CHECK(hipEventRecord(p.a, st));
 }
 
 PhaseTimer::~PhaseTimer() {
   if (!on) return;
-  if (hipEventRecord(p.b, ctx->stream) == hipSuccess) ctx->pending.push_back(p);
+  if (hipEventRecord(p.b, st) == hipSuccess) ctx->pending.push_back(p);
 }
 
 void prof_flush(rw_ctx* ctx) {
+  if (ctx->aux) {
+    // the helper's phases (its worker is idle whenever the owner flushes)
+    prof_flush(ctx->aux);
+    for (auto& kv : ctx->aux->phases) {
+      PhaseStat& st = ctx->phases[kv.first];
+      st.ms += kv.second.ms;
+      st.calls += kv.second.calls;
+      st.flops += kv.second.flops;
+      st.bytes += kv.second.bytes;
+    }
+    ctx->aux->phases.clear();
+  }
   for (auto& q : ctx->pending) {
     float ms = 0.f;
     if (hipEventSynchronize(q.b) == hipSuccess && hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
@@ -106,14 +127,140 @@ static thread_local rw_ctx* g_current_ctx = nullptr;
 rw_ctx* current_ctx() { return g_current_ctx; }
 void set_current_ctx(rw_ctx* ctx) { g_current_ctx = ctx; }
 
-KernelTimer::KernelTimer(const char* name, double flops, double bytes) {
+KernelTimer::KernelTimer(const char* name, double flops, double bytes, hipStream_t stream) {
   rw_ctx* c = g_current_ctx;
   if (c && c->prof) {
     std::string key = std::string("k:") + name;
-    t = new PhaseTimer(c, key.c_str(), flops, bytes);
+    t = new PhaseTimer(c, key.c_str(), flops, bytes, stream);
   }
 }
 KernelTimer::~KernelTimer() { delete t; }
+
+hipStream_t ctx_side_stream(rw_ctx* ctx) {
+  if (!ctx->side) HIP_CHECK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+  return ctx->side;
+}
+
+hipEvent_t ctx_order_event(rw_ctx* ctx, int i) {
+  while ((int)ctx->order_events.size() <= i) {
+    hipEvent_t e;
+    HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->order_events.push_back(e);
+  }
+  return ctx->order_events[i];
+}
+
+void stream_after(rw_ctx* ctx, hipStream_t waiter, hipStream_t src, int i) {
+  hipEvent_t e = ctx_order_event(ctx, i);
+  HIP_CHECK(hipEventRecord(e, src));
+  HIP_CHECK(hipStreamWaitEvent(waiter, e, 0));
+}
+
+// ------------------------------------------------------------ helper ctx
+struct AuxWorker {
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::function<void()> job;
+  bool has_job = false, busy = false, stop = false;
+  std::exception_ptr err;
+};
+
+static void aux_loop(rw_ctx* aux, AuxWorker* wk) {
+  for (;;) {
+    std::function<void()> job;
+    {
+      std::unique_lock<std::mutex> lk(wk->mu);
+      wk->cv.wait(lk, [&] { return wk->has_job || wk->stop; });
+      if (!wk->has_job) return;
+      job = std::move(wk->job);
+      wk->has_job = false;
+    }
+    std::exception_ptr e;
+    set_current_ctx(aux);
+    try {
+      HIP_CHECK(hipSetDevice(aux->device));
+      job();
+    } catch (...) {
+      e = std::current_exception();
+    }
+    set_current_ctx(nullptr);
+    {
+      std::lock_guard<std::mutex> lk(wk->mu);
+      wk->err = e;
+      wk->busy = false;
+    }
+    wk->cv.notify_all();
+  }
+}
+
+static rw_ctx* ctx_aux(rw_ctx* ctx) {
+  if (ctx->aux) return ctx->aux;
+  std::unique_ptr<rw_ctx> a(new rw_ctx());
+  a->device = ctx->device;
+  a->budget = ctx->budget;
+  a->owner = ctx;
+  a->n_cu = ctx->n_cu;
+  HIP_CHECK(hipStreamCreateWithFlags(&a->stream, hipStreamNonBlocking));
+  std::unique_ptr<AuxWorker> wk(new AuxWorker());
+  wk->th = std::thread(aux_loop, a.get(), wk.get());
+  ctx->worker = wk.release();
+  ctx->aux = a.release();
+  return ctx->aux;
+}
+
+void aux_fork(rw_ctx* ctx, std::function<void(rw_ctx*)> fn) {
+  rw_ctx* a = ctx_aux(ctx);
+  a->opt = ctx->opt;
+  a->prof = ctx->prof;
+  stream_after(ctx, a->stream, ctx->stream, 3);
+  AuxWorker* wk = ctx->worker;
+  {
+    std::lock_guard<std::mutex> lk(wk->mu);
+    wk->job = [fn, a]() { fn(a); };
+    wk->has_job = true;
+    wk->busy = true;
+  }
+  wk->cv.notify_all();
+}
+
+void aux_join(rw_ctx* ctx) {
+  AuxWorker* wk = ctx->worker;
+  if (!wk) return;
+  std::exception_ptr e;
+  {
+    std::unique_lock<std::mutex> lk(wk->mu);
+    wk->cv.wait(lk, [&] { return !wk->busy; });
+    e = wk->err;
+    wk->err = nullptr;
+  }
+  stream_after(ctx, ctx->stream, ctx->aux->stream, 4);
+  if (e) std::rethrow_exception(e);
+}
+
+static void ctx_destroy_aux(rw_ctx* ctx) {
+  if (ctx->worker) {
+    {
+      std::lock_guard<std::mutex> lk(ctx->worker->mu);
+      ctx->worker->stop = true;
+    }
+    ctx->worker->cv.notify_all();
+    ctx->worker->th.join();
+    delete ctx->worker;
+    ctx->worker = nullptr;
+  }
+  if (rw_ctx* a = ctx->aux) {
+    (void)hipStreamSynchronize(a->stream);
+    ctx_release_cache(a);
+    for (auto& q : a->pending) { (void)hipEventDestroy(q.a); (void)hipEventDestroy(q.b); }
+    for (auto e : a->event_pool) (void)hipEventDestroy(e);
+    for (auto e : a->order_events) (void)hipEventDestroy(e);
+    if (a->side) (void)hipStreamDestroy(a->side);
+    (void)hipStreamDestroy(a->stream);
+    delete a;
+    ctx->aux = nullptr;
+  }
+}
 
 namespace {
 thread_local std::string g_create_err;
@@ -160,7 +307,7 @@ struct rw_wall {
 namespace {
 
 void hbs_apply(rw_wall* w, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32) {
-  hbs_dev_apply(w->hbs, b, ldb, x, ldx, nrhs, use_f32);
+  hbs_dev_apply(w->hbs, b, ldb, x, ldx, nrhs, use_f32, w->ctx->stream);
 }
 
 void build_wall(rw_ctx* ctx, const rw_curve& cv, int P, int q, int leaf, double tol, int precision, rw_wall& w) {
@@ -257,7 +404,7 @@ void woodbury_out(rw_refined* f, double* dst, int nrhs, bool accumulate) {
   const int64_t M = 2 * f->Next, Mo = 2 * f->No, Mp = 2 * f->Np;
   if (f->Np > 0 && f->app_hbs_on) {
     PhaseTimer t(f->ctx, "a6_app_solve", 2.0 * f->app_hbs.entries * nrhs, 8.0 * f->app_hbs.entries * ((nrhs + 7) / 8));
-    hbs_dev_apply(f->app_hbs, f->gext.p + Mo, M, f->y.p + Mo, M, nrhs, false);
+    hbs_dev_apply(f->app_hbs, f->gext.p + Mo, M, f->y.p + Mo, M, nrhs, false, s);
   } else if (f->Np > 0) {
     PhaseTimer t(f->ctx, "a6_app_solve", 2.0 * (double)Mp * Mp * nrhs, 8.0 * (double)Mp * Mp * nrhs);
     HIP_CHECK(hipMemcpy2DAsync(f->y.p + Mo, sizeof(double) * M, f->gext.p + Mo, sizeof(double) * M,
@@ -290,6 +437,32 @@ void validate_selection(const rw_wall* w, const int32_t* ids, const int32_t* lev
     if (!seen.insert(ids[i]).second) RW_THROW(RW_EINVAL, "duplicate panel id " + std::to_string(ids[i]));
     if (levels[i] < 0 || levels[i] > 8) RW_THROW(RW_EINVAL, "level outside [0, 8]");
   }
+}
+
+// Algorithm 1, pre-computation step 2: an inverse of A_pp on ctx ax (its
+// own stream): dense LU for few added points, else the GPU-built HBS inverse.
+void build_app_inverse(rw_wall* w, rw_refined& f, uint64_t seed, rw_ctx* ax) {
+  hipStream_t s = ax->stream;
+  const int64_t Mp = 2 * f.Np;
+  if (f.app_hbs_on) {
+    PhaseTimer t(ax, "a3_app_hbs_build", 0.0, 0.0);
+    hbs_gpu_build(ax, f.d_p.p, f.pnodes, w->leaf, w->tol, seed, f.app_hbs);
+    return;
+  }
+  DBuf<int> dinfo(ax, 1);
+  f.App.alloc(ax, (size_t)Mp * Mp);
+  {
+    PhaseTimer t(ax, "a3_app_assemble", 0.0, 8.0 * (double)Mp * Mp);
+    launch_assemble(f.d_p.p, f.Np, f.d_p.p, f.Np, true, f.App.p, Mp, s);
+  }
+  {
+    PhaseTimer t(ax, "a3_app_lu", 2.0 / 3.0 * (double)Mp * Mp * Mp, 0.0);
+    launch_lu_nopiv(f.App.p, Mp, Mp, dinfo.p, nullptr, s);
+  }
+  int info = 0;
+  HIP_CHECK(hipMemcpyAsync(&info, dinfo.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  if (info) RW_THROW(RW_ESINGULAR, "zero pivot " + std::to_string(info) + " in the LU of A_pp");
 }
 
 // Algorithm 1 pre-computation for the refinement described by level_of_panel.
@@ -369,6 +542,14 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
   if (f.Np) HIP_CHECK(hipMemcpyAsync(f.d_p.p, f.d_ext.p + f.No, sizeof(NodeRec) * f.Np, hipMemcpyDeviceToDevice, s));
 
   t_geo.reset();
+  // ---- a3: A_pp^{-1} (dense LU for few added points, else a GPU-built HBS
+  // inverse) on the helper ctx, beside the compression of Q on this stream
+  f.app_hbs_on = f.Np > ctx->opt.app_dense_max_nodes;
+  AuxTask a3;
+  if (f.Np > 0) {
+    const uint64_t seed = ctx->opt.seed ^ 0x3C6EF372FE94F82Bull;
+    a3.fork(ctx, [&f, w, seed](rw_ctx* ax) { build_app_inverse(w, f, seed, ax); });
+  }
   f.k_k = f.k_p = f.k = 0;
   if (f.Nc > 0) {
     // ---- a2: Q ~= L R by randomized row IDs of the k-rows [-A_kc A_kp] and p-rows A_pk
@@ -427,44 +608,28 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
                   f.R.p + (size_t)f.k_k * M, M, s);
     HIP_CHECK(hipStreamSynchronize(s));
   }
-  // ---- a3: A_pp^{-1}: dense LU for few added points, else a GPU-built HBS inverse
   DBuf<int> dinfo(ctx, 4);
-  f.app_hbs_on = f.Np > ctx->opt.app_dense_max_nodes;
-  if (f.app_hbs_on) {
-    PhaseTimer t(ctx, "a3_app_hbs_build", 0.0, 0.0);
-    hbs_gpu_build(ctx, f.d_p.p, pnodes, w->leaf, w->tol, ctx->opt.seed ^ 0x3C6EF372FE94F82Bull, f.app_hbs);
-  } else if (f.Np > 0) {
-    f.App.alloc(ctx, (size_t)Mp * Mp);
-    {
-      PhaseTimer t(ctx, "a3_app_assemble", 0.0, 8.0 * (double)Mp * Mp);
-      launch_assemble(f.d_p.p, f.Np, f.d_p.p, f.Np, true, f.App.p, Mp, s);
-    }
-    {
-      PhaseTimer t(ctx, "a3_app_lu", 2.0 / 3.0 * (double)Mp * Mp * Mp, 0.0);
-      launch_lu_nopiv(f.App.p, Mp, Mp, dinfo.p, nullptr, s);
-    }
-    int info = 0;
-    HIP_CHECK(hipMemcpyAsync(&info, dinfo.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
-    if (info) RW_THROW(RW_ESINGULAR, "zero pivot " + std::to_string(info) + " in the LU of A_pp");
-  }
   if (f.k > 0) {
-    // ---- a4: X = A~^{-1} L
+    // ---- a4: X = A~^{-1} L; the A_oo^{-1} block needs only the reference inverse
     f.X.alloc(ctx, (size_t)M * f.k);
     HIP_CHECK(hipMemsetAsync(f.X.p, 0, sizeof(double) * M * f.k, s));
-    {
-      PhaseTimer t_x(ctx, "a4_X", 2.0 * w->stats.gen_entries * f.k_k + 2.0 * (double)Mp * Mp * f.k_p,
-                     8.0 * w->stats.gen_entries * ((f.k_k + 7) / 8));
-      if (f.k_k) hbs_apply(w, f.L.p, M, f.X.p, M, f.k_k, false);
-      if (f.k_p) {
-        double* xp = f.X.p + Mo + (size_t)f.k_k * M;
-        if (f.app_hbs_on) {
-          hbs_dev_apply(f.app_hbs, f.L.p + Mo + (size_t)f.k_k * M, M, xp, M, f.k_p, false);
-        } else {
-          HIP_CHECK(hipMemcpy2DAsync(xp, sizeof(double) * M, f.L.p + Mo + (size_t)f.k_k * M, sizeof(double) * M,
-                                     sizeof(double) * Mp, f.k_p, hipMemcpyDeviceToDevice, s));
-          launch_lu_solve(f.App.p, Mp, Mp, xp, M, f.k_p, s);
-        }
+    if (f.k_k) {
+      PhaseTimer t_x(ctx, "a4_X", 2.0 * w->stats.gen_entries * f.k_k, 8.0 * w->stats.gen_entries * ((f.k_k + 7) / 8));
+      hbs_apply(w, f.L.p, M, f.X.p, M, f.k_k, false);
+    }
+  }
+  a3.join();
+  if (f.k > 0) {
+    if (f.k_p) {
+      double* xp = f.X.p + Mo + (size_t)f.k_k * M;
+      if (f.app_hbs_on) {
+        PhaseTimer t_x(ctx, "a4_Xp", 2.0 * f.app_hbs.entries * f.k_p, 8.0 * f.app_hbs.entries * ((f.k_p + 7) / 8));
+        hbs_dev_apply(f.app_hbs, f.L.p + Mo + (size_t)f.k_k * M, M, xp, M, f.k_p, false, s);
+      } else {
+        PhaseTimer t_x(ctx, "a4_Xp", 2.0 * (double)Mp * Mp * f.k_p, 8.0 * (double)Mp * Mp);
+        HIP_CHECK(hipMemcpy2DAsync(xp, sizeof(double) * M, f.L.p + Mo + (size_t)f.k_k * M, sizeof(double) * M,
+                                   sizeof(double) * Mp, f.k_p, hipMemcpyDeviceToDevice, s));
+        launch_lu_solve(f.App.p, Mp, Mp, xp, M, f.k_p, s);
       }
     }
     // ---- a5: W = I + R X and its inverse (FP64)
@@ -547,10 +712,13 @@ int rw_ctx_create(rw_ctx** out, int device, void* hip_stream, size_t hbm_budget_
 void rw_ctx_destroy(rw_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
+  ctx_destroy_aux(ctx);
   if (ctx->d_sync) dev_free(ctx, ctx->d_sync, sizeof(unsigned) * ctx->sync_words);
   ctx_release_cache(ctx);
   for (auto& q : ctx->pending) { (void)hipEventDestroy(q.a); (void)hipEventDestroy(q.b); }
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  for (auto e : ctx->order_events) (void)hipEventDestroy(e);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   delete ctx;
 }
 
@@ -573,13 +741,17 @@ int rw_get_options(const rw_ctx* ctx, rw_options* opt) {
   return RW_OK;
 }
 
-size_t rw_ctx_bytes(const rw_ctx* ctx) { return ctx ? ctx->used : 0; }
+size_t rw_ctx_bytes(const rw_ctx* ctx) { return ctx ? budget_used(ctx) : 0; }
 
 int rw_ctx_trim(rw_ctx* ctx) {
   if (!ctx) return RW_EINVAL;
   return guarded(ctx, [&]() {
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
     ctx_release_cache(ctx);
+    if (ctx->aux) {
+      HIP_CHECK(hipStreamSynchronize(ctx->aux->stream));
+      ctx_release_cache(ctx->aux);
+    }
   });
 }
 
