@@ -75,6 +75,10 @@ typedef struct {
   uint64_t seed;             /* seed of the sketching matrix (counter-based, reproducible) [0x5eed] */
   int32_t app_dense_max_nodes; /* A_pp^{-1} by dense LU up to this many added nodes, else by an HBS
                                   inverse built on the GPU (Algorithm 1 step 2) [1024] */
+  int32_t far_field;         /* 1: split the kept nodes at a circle around the refined arc (Sec. 3.3)
+                                and sketch the far part of Q through multipole / local expansions,
+                                the near part exactly (used when at most half the kept nodes are
+                                near); 0: sketch the whole blocks of Q exactly [1] */
 } rw_options;
 
 /* Counts and timings reported by rw_refine / rw_solve. */
@@ -85,6 +89,8 @@ typedef struct {
   double resid;              /* max over columns of ||g - A_nn tau|| / ||g|| after the last rw_solve */
   double t_refine_ms;        /* wall time of the last rw_refine / rw_coarsen (host clock) */
   double t_solve_ms;         /* wall time of the last rw_solve */
+  int64_t n_near;            /* kept nodes sketched exactly by the far-field split, -1 if Q's blocks
+                                were sketched exactly as a whole */
 } rw_info;
 
 /* Reference-wall statistics reported by rw_wall_stats. */

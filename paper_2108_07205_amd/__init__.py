@@ -50,14 +50,14 @@ class rw_curve(ctypes.Structure):
 class rw_options(ctypes.Structure):
     _fields_ = [("ir_tol", ctypes.c_double), ("ir_maxit", ctypes.c_int32),
                 ("sketch_cols", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("app_dense_max_nodes", ctypes.c_int32)]
+                ("app_dense_max_nodes", ctypes.c_int32), ("far_field", ctypes.c_int32)]
 
 
 class rw_info(ctypes.Structure):
     _fields_ = [("n_k", ctypes.c_int64), ("n_c", ctypes.c_int64), ("n_p", ctypes.c_int64),
                 ("k_k", ctypes.c_int32), ("k_p", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("ir_iters", ctypes.c_int32), ("resid", ctypes.c_double),
-                ("t_refine_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
+                ("t_refine_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double), ("n_near", ctypes.c_int64)]
 
 
 class rw_wall_stats(ctypes.Structure):
@@ -163,7 +163,8 @@ def rw_ctx_destroy(ctx):
     load_library().rw_ctx_destroy(ctx)
 
 
-def rw_set_options(ctx, ir_tol=None, ir_maxit=None, sketch_cols=None, seed=None, app_dense_max_nodes=None):
+def rw_set_options(ctx, ir_tol=None, ir_maxit=None, sketch_cols=None, seed=None, app_dense_max_nodes=None,
+                   far_field=None):
     lib = load_library()
     o = rw_options()
     _check(lib.rw_get_options(ctx, ctypes.byref(o)), ctx)
@@ -177,6 +178,8 @@ def rw_set_options(ctx, ir_tol=None, ir_maxit=None, sketch_cols=None, seed=None,
         o.seed = seed
     if app_dense_max_nodes is not None:
         o.app_dense_max_nodes = app_dense_max_nodes
+    if far_field is not None:
+        o.far_field = int(bool(far_field))
     _check(lib.rw_set_options(ctx, ctypes.byref(o)), ctx)
 
 

@@ -78,6 +78,9 @@ struct rw_ctx {
   // timing-free events that order the two
   hipStream_t side = nullptr;
   std::vector<hipEvent_t> order_events;
+  // pinned host staging for small per-call transfers (grow-only)
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
   // phase profiler (HIP events on `stream`)
   bool prof = false;
   struct Pending { std::string name; hipEvent_t a, b; double flops, bytes; };
@@ -115,6 +118,9 @@ struct KernelTimer {
 // first use and kept until the ctx is destroyed).
 hipStream_t ctx_side_stream(rw_ctx* ctx);
 hipEvent_t ctx_order_event(rw_ctx* ctx, int i);
+// Pinned host staging of at least `bytes` (grow-only; growing first waits
+// for the ctx's streams, so no copy from the old buffer is still in flight).
+void* ctx_pinned(rw_ctx* ctx, size_t bytes);
 // `waiter` waits for everything enqueued on `src` so far (event i).
 void stream_after(rw_ctx* ctx, hipStream_t waiter, hipStream_t src, int i);
 

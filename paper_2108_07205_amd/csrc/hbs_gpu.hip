@@ -444,12 +444,15 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
 // threads 2i and 2i+1 (48 columns each); pivoted Gram-Schmidt with two
 // projection passes.  Outputs per (node, side): piv[SK_KCAP], C (m x SK_KCAP
 // row-major at cand_off*SK_KCAP), info[0] = tolerance rank, info[1] = steps.
+// The pivot keys and the pivot vector alternate between two LDS slots, so a
+// step needs two barriers: a slot is written again two steps later, after
+// every thread has passed the first barrier of the step in between.
 __global__ __launch_bounds__(512) void node_id_kernel(const GNode* __restrict__ gn, const double* __restrict__ Sr,
                                                       const double* __restrict__ Sc, double tol2,
                                                       int* __restrict__ piv, double* __restrict__ Cr,
                                                       double* __restrict__ Cc, int* __restrict__ info) {
-  __shared__ double q[SK_R];
-  __shared__ double rv[8];
+  __shared__ double q[2][SK_R];
+  __shared__ double rv[2][8];
   const GNode g = gn[blockIdx.x];
   const int side = blockIdx.y;
   const int m = g.m, tid = threadIdx.x;
@@ -473,14 +476,15 @@ __global__ __launch_bounds__(512) void node_id_kernel(const GNode* __restrict__ 
   int rank = -1, step = 0;
   const int kmax = min(SK_KCAP, m);
   for (; step < kmax; ++step) {
+    const int b = step & 1;
     // pivot: DPP maximum of the keys of the unselected rows (the key carries
     // the squared norm to 2^-43 relative, enough for the rank decision)
     const double key = wave_max_nonneg(pivot_key_bits<9>(nrm, i, !sel));
-    if ((tid & 63) == 0) rv[tid >> 6] = key;
+    if ((tid & 63) == 0) rv[b][tid >> 6] = key;
     __syncthreads();
-    double v = rv[0];
+    double v = rv[b][0];
 #pragma unroll
-    for (int w = 1; w < 8; ++w) v = fmax(v, rv[w]);
+    for (int w = 1; w < 8; ++w) v = fmax(v, rv[b][w]);
     const int p = v > 0.0 ? pivot_key_index<9>(v) : -1;
     if (step == 0) n0 = v;
     if (rank < 0 && !(v > tol2 * n0)) rank = step;
@@ -488,14 +492,14 @@ __global__ __launch_bounds__(512) void node_id_kernel(const GNode* __restrict__ 
     if (i == p) {
       const double inv = 1.0 / sqrt(nrm);
 #pragma unroll
-      for (int c = 0; c < 48; ++c) q[h * 48 + c] = y[c] * inv;
+      for (int c = 0; c < 48; ++c) q[b][h * 48 + c] = y[c] * inv;
     }
     if (tid == 0) pv[step] = p;
     __syncthreads();
     // this thread's half of q in registers, then two projection passes
     double qr[48];
 #pragma unroll
-    for (int c = 0; c < 48; ++c) qr[c] = q[h * 48 + c];
+    for (int c = 0; c < 48; ++c) qr[c] = q[b][h * 48 + c];
     double cf = 0.0;
 #pragma unroll
     for (int pass = 0; pass < 2; ++pass) {
@@ -510,7 +514,6 @@ __global__ __launch_bounds__(512) void node_id_kernel(const GNode* __restrict__ 
     if (valid && h == 0) C[(int64_t)i * SK_KCAP + step] = cf;
     if (i == p) sel = true;
     nrm = row_norm();
-    __syncthreads();
   }
   if (tid == 0) {
     info[(blockIdx.x * 2 + side) * 2] = rank < 0 ? step : rank;
@@ -520,49 +523,70 @@ __global__ __launch_bounds__(512) void node_id_kernel(const GNode* __restrict__ 
 
 // ---------------------------------------------------------------- 3. interpolation
 // grid (nodes, 2).  P = C(:, 0:k) C_J^{-1} -> U (side 0) or V (side 1), m x k
-// column-major; the skeleton dofs go to the parent's candidate list.
+// column-major; the skeleton dofs go to the parent's candidate list.  C_J
+// (the pivot rows of the Gram-Schmidt coefficients) is lower triangular: its
+// rows are staged in LDS, its inverse is formed there by forward
+// substitution (thread t: column t), and the product is taken in items of
+// one row of C times four columns of the inverse.
+constexpr int INTERP_NC = 4;
 __global__ __launch_bounds__(256) void node_interp_kernel(const GNode* __restrict__ gn, const int* __restrict__ candr,
                                                           const int* __restrict__ candc, const int* __restrict__ piv,
                                                           const double* __restrict__ Cr, const double* __restrict__ Cc,
                                                           double* __restrict__ U, double* __restrict__ V,
                                                           const int64_t* __restrict__ par_pos,
                                                           int* __restrict__ pcandr, int* __restrict__ pcandc) {
-  extern __shared__ double iv[];  // k x k: iv[s * k + t] = Inv(s, t)
+  extern __shared__ double lds[];  // cj[s * k + u] = C_J(s, u); iv[u * k + t] = Inv(u, t)
   const GNode g = gn[blockIdx.x];
   const int side = blockIdx.y;
   const int k = g.k, m = g.m, tid = threadIdx.x;
   const int* pv = piv + ((int64_t)blockIdx.x * 2 + side) * SK_KCAP;
   const double* C = (side == 0 ? Cr : Cc) + g.cand_off * SK_KCAP;
   double* P = (side == 0 ? U : V) + g.uv_off;
-  for (int idx = tid; idx < k * k; idx += 256) iv[idx] = 0.0;
+  double* cj = lds;
+  double* iv = lds + k * k;
+  for (int idx = tid; idx < k * k; idx += 256) {
+    const int srow = idx / k, u = idx - srow * k;
+    cj[idx] = (u <= srow) ? C[(int64_t)pv[srow] * SK_KCAP + u] : 0.0;
+    iv[idx] = 0.0;
+  }
   __syncthreads();
   if (tid < k) {
     const int t = tid;
-    for (int s = t; s < k; ++s) {
-      const double* cs = C + (int64_t)pv[s] * SK_KCAP;
-      double v = (s == t) ? 1.0 : 0.0;
-      for (int u = t; u < s; ++u) v -= cs[u] * iv[u * k + t];
-      iv[s * k + t] = v / cs[s];
+    for (int srow = t; srow < k; ++srow) {
+      const double* cs = cj + srow * k;
+      double v = (srow == t) ? 1.0 : 0.0;
+      for (int u = t; u < srow; ++u) v -= cs[u] * iv[u * k + t];
+      iv[srow * k + t] = v / cs[srow];
     }
   }
   __syncthreads();
-  for (int i = tid; i < m; i += 256) {
+  const int nb = (k + INTERP_NC - 1) / INTERP_NC;
+  for (int item = tid; item < m * nb; item += 256) {
+    const int i = item % m, t0 = (item / m) * INTERP_NC;
     const double* ci = C + (int64_t)i * SK_KCAP;
-    for (int t = 0; t < k; ++t) {
-      double v = 0;
-      for (int s = t; s < k; ++s) v += ci[s] * iv[s * k + t];
-      P[i + (int64_t)t * m] = v;
+    double v[INTERP_NC];
+#pragma unroll
+    for (int c = 0; c < INTERP_NC; ++c) v[c] = 0.0;
+    for (int srow = t0; srow < k; ++srow) {
+      const double a = ci[srow];
+      const double* ir = iv + srow * k + t0;
+#pragma unroll
+      for (int c = 0; c < INTERP_NC; ++c)
+        if (t0 + c < k) v[c] += a * ir[c];
     }
+#pragma unroll
+    for (int c = 0; c < INTERP_NC; ++c)
+      if (t0 + c < k) P[i + (int64_t)(t0 + c) * m] = v[c];
   }
   __syncthreads();
-  for (int s = tid; s < k; s += 256) {
-    const int p = pv[s];
-    for (int t = 0; t < k; ++t) P[p + (int64_t)t * m] = (t == s) ? 1.0 : 0.0;
+  for (int srow = tid; srow < k; srow += 256) {
+    const int p = pv[srow];
+    for (int t = 0; t < k; ++t) P[p + (int64_t)t * m] = (t == srow) ? 1.0 : 0.0;
   }
   if (par_pos) {
     const int* cand = (side == 0 ? candr : candc) + g.cand_off;
     int* pc = (side == 0 ? pcandr : pcandc) + par_pos[blockIdx.x];
-    for (int s = tid; s < k; s += 256) pc[s] = cand[pv[s]];
+    for (int srow = tid; srow < k; srow += 256) pc[srow] = cand[pv[srow]];
   }
 }
 
@@ -1347,13 +1371,19 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
   w.K.assign(L + 2, 0);
   std::vector<std::vector<int>> lev_ints(L + 1);
   std::vector<std::vector<int64_t>> lev_offs(L + 1);
-  std::vector<std::vector<int64_t>> ppos(L + 1);   // host sources of the dpar uploads
+  // pinned staging: node records (level l at [2^l, 2^(l+1))), parent
+  // positions (same layout) and the ID ranks of one level
+  char* pin = (char*)ctx_pinned(ctx, (sizeof(GNode) + sizeof(int64_t)) * (size_t)(int64_t(2) << L) +
+                                         sizeof(int) * (size_t)(int64_t(4) << L));
+  GNode* hG = (GNode*)pin;
+  int64_t* hP = (int64_t*)(pin + sizeof(GNode) * (size_t)(int64_t(2) << L));
+  int* hI = (int*)(hP + (int64_t(2) << L));
   int64_t gen_used = 0;
   w.entries = 0;
   w.max_rank = 0;
   double* dh_child = dhB.p;
   double* dh_cur = dhA.p;
-  const size_t shi = sizeof(double) * SK_KCAP * SK_KCAP;
+  const size_t shi = 2 * sizeof(double) * SK_KCAP * SK_KCAP;
   HIP_CHECK(hipFuncSetAttribute((const void*)node_interp_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shi));
   const size_t shv = INV_LDS_BYTES;
   HIP_CHECK(hipFuncSetAttribute((const void*)node_inverse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shv));
@@ -1367,7 +1397,8 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     int mx = 0;
     for (int j = 0; j < nn; ++j) { gl[j].cand_off = off; off += gl[j].m; mx = std::max(mx, gl[j].m); }
     if (mx > mmax) RW_THROW(RW_ESINGULAR, "HBS node input exceeds the sketch bound");
-    HIP_CHECK(hipMemcpyAsync(dgl, gl.data(), sizeof(GNode) * nn, hipMemcpyHostToDevice, s));
+    memcpy(hG + nn, gl.data(), sizeof(GNode) * nn);
+    HIP_CHECK(hipMemcpyAsync(dgl, hG + nn, sizeof(GNode) * nn, hipMemcpyHostToDevice, s));
     // split each node's near nodes (entity range) so every level fills the device
     int nsplit = (int)std::min<int64_t>(64, std::max<int64_t>(1, 1024 / (2 * nn)));
     nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, N / 64));
@@ -1401,8 +1432,8 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
                          info.p);
       KERNEL_CHECK("node_id");
     }
-    std::vector<int> hinfo(4 * nn);
-    info.download(hinfo.data(), hinfo.size(), s);
+    const int* hinfo = hI;
+    info.download(hI, 4 * (size_t)nn, s);
     HIP_CHECK(hipStreamSynchronize(s));
     // ranks and offsets
     int64_t uv = 0, dho = 0, wso = 0;
@@ -1429,18 +1460,19 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     if (gen_used > (int64_t)w.gen.n) RW_THROW(RW_ESINGULAR, "HBS generator bound exceeded");
     if (wso > (int64_t)ws.n) RW_THROW(RW_ESINGULAR, "HBS factor workspace bound exceeded");
     // parent candidate sizes and positions of each child's skeleton in them
-    ppos[l].assign(nn, 0);
     {
+      int64_t* pp = hP + nn;
       int64_t po = 0;
       for (int pj = 0; pj < nn / 2; ++pj) {
-        ppos[l][2 * pj] = po;
-        ppos[l][2 * pj + 1] = po + gl[2 * pj].k;
+        pp[2 * pj] = po;
+        pp[2 * pj + 1] = po + gl[2 * pj].k;
         G[l - 1][pj].m = gl[2 * pj].k + gl[2 * pj + 1].k;
         po += G[l - 1][pj].m;
       }
-      HIP_CHECK(hipMemcpyAsync(dpar.p + nn, ppos[l].data(), sizeof(int64_t) * nn, hipMemcpyHostToDevice, s));
+      HIP_CHECK(hipMemcpyAsync(dpar.p + nn, pp, sizeof(int64_t) * nn, hipMemcpyHostToDevice, s));
     }
-    HIP_CHECK(hipMemcpyAsync(dgl, gl.data(), sizeof(GNode) * nn, hipMemcpyHostToDevice, s));
+    memcpy(hG + nn, gl.data(), sizeof(GNode) * nn);
+    HIP_CHECK(hipMemcpyAsync(dgl, hG + nn, sizeof(GNode) * nn, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(node_interp_kernel, dim3(nn, 2), dim3(256), shi, s, dgl, cr, cc, piv.p, Cr.p,
                        Cc.p, Ub.p + uv_base[l], Vb.p + uv_base[l], dpar.p + nn, candr.p + cand_base[l - 1],
                        candc.p + cand_base[l - 1]);
@@ -1508,7 +1540,8 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     g.ws_off = 0;
     w.nroot = g.m;
     w.S[0] = g.m;
-    HIP_CHECK(hipMemcpyAsync(dg.p + 1, &g, sizeof(GNode), hipMemcpyHostToDevice, s));
+    hG[1] = g;
+    HIP_CHECK(hipMemcpyAsync(dg.p + 1, hG + 1, sizeof(GNode), hipMemcpyHostToDevice, s));
     w.groot.alloc(ctx, (size_t)g.m * g.m);
     stream_after(ctx, sf, s, 1);
     int* cr = candr.p + cand_base[0];

@@ -67,6 +67,23 @@ size_t sketch_part_doubles(int64_t nt, int64_t nsrc);  // workspace of launch_sk
 void launch_sketch(const NodeRec* tgt, int64_t nt, const SketchSeg* segs, int nseg, int ncols,
                    uint64_t seed, double* Y, double* part, hipStream_t s);
 
+// Far field of the Q sketches by expansions about the center c of a circle
+// of radius rho around the refined arc: rows 2 pos[i], 2 pos[i] + 1 of Y
+// (row-major, ncols) (+)= the sketch of the sources in segs evaluated at
+// tgt[i] (pos = nullptr: pos[i] = i), with the same Omega as launch_sketch
+// (same seed and Omega row offsets).  local = false: multipole expansion of
+// sources within rho, targets beyond FAR_RATIO rho; local = true: local
+// expansion of sources beyond FAR_RATIO rho, targets within rho.
+// part: far_part_elems(ncols, nsplit), coef: far_part_elems(ncols, 1).
+constexpr int FAR_P = 40;           // expansion terms
+constexpr double FAR_RATIO = 2.5;   // near / far split radius over rho
+size_t far_part_elems(int ncols, int nsplit);
+void launch_far_sketch(const SketchSeg* segs, int nseg, const NodeRec* tgt, int64_t nt, const int* pos, bool local,
+                       double cx, double cy, double rho, int ncols, uint64_t seed, bool accumulate, double* Y,
+                       double2* part, int nsplit, double2* coef, hipStream_t s);
+// Y rows 2 pos[i], 2 pos[i] + 1 <- rows 2 i, 2 i + 1 of Yc (row-major, ncols)
+void launch_scatter_rows(const double* Yc, int64_t n, const int* pos, int ncols, double* Y, hipStream_t s);
+
 // gather / scatter between refined order and extended order
 void launch_to_ext(const double* g, int64_t ld_g, int64_t n_new, const int* new2ext, double* ext,
                    int64_t ld_ext, int64_t n_ext_dofs, int nrhs, hipStream_t s);

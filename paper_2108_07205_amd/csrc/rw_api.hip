@@ -150,6 +150,21 @@ hipEvent_t ctx_order_event(rw_ctx* ctx, int i) {
   return ctx->order_events[i];
 }
 
+void* ctx_pinned(rw_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->pinned_bytes) return ctx->pinned;
+  if (ctx->pinned) {
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    if (ctx->side) HIP_CHECK(hipStreamSynchronize(ctx->side));
+    (void)hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+  }
+  bytes = std::max<size_t>(bytes, 64 * 1024);
+  HIP_CHECK(hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault));
+  ctx->pinned_bytes = bytes;
+  return ctx->pinned;
+}
+
 void stream_after(rw_ctx* ctx, hipStream_t waiter, hipStream_t src, int i) {
   hipEvent_t e = ctx_order_event(ctx, i);
   HIP_CHECK(hipEventRecord(e, src));
@@ -256,6 +271,7 @@ static void ctx_destroy_aux(rw_ctx* ctx) {
     for (auto e : a->event_pool) (void)hipEventDestroy(e);
     for (auto e : a->order_events) (void)hipEventDestroy(e);
     if (a->side) (void)hipStreamDestroy(a->side);
+    if (a->pinned) (void)hipHostFree(a->pinned);
     (void)hipStreamDestroy(a->stream);
     delete a;
     ctx->aux = nullptr;
@@ -551,26 +567,95 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
     a3.fork(ctx, [&f, w, seed](rw_ctx* ax) { build_app_inverse(w, f, seed, ax); });
   }
   f.k_k = f.k_p = f.k = 0;
+  f.info.n_near = -1;
   if (f.Nc > 0) {
     // ---- a2: Q ~= L R by randomized row IDs of the k-rows [-A_kc A_kp] and p-rows A_pk
     int ncols = ctx->opt.sketch_cols;
     const double tol = w->tol;
     std::vector<int> Jk, Jp;
-    DBuf<double> Yk, Yp, Ck, Cp, part;
+    DBuf<double> Yk, Yp, Ck, Cp, part, Ynear;
+    DBuf<double2> fpart, fcoef;
     DBuf<char> work;
     DBuf<int> dJ(ctx, 256);
+    // Sec. 3.3: a circle of radius rho about the refined arc Gamma_r (its
+    // cut and added nodes) splits the kept nodes into near (within
+    // FAR_RATIO rho: exact entries) and far (expansions about the center)
+    const std::vector<NodeRec>& rn = w->disc.nodes;
+    double bx0 = 1e300, bx1 = -1e300, by0 = 1e300, by1 = -1e300;
+    auto bbox = [&](const NodeRec& q) {
+      bx0 = std::min(bx0, q.x); bx1 = std::max(bx1, q.x);
+      by0 = std::min(by0, q.y); by1 = std::max(by1, q.y);
+    };
+    for (int i : c_ref) bbox(rn[i]);
+    for (const NodeRec& q : pnodes) bbox(q);
+    const double fcx = 0.5 * (bx0 + bx1), fcy = 0.5 * (by0 + by1);
+    double rho = 0.0;
+    for (int i : c_ref) rho = std::max(rho, std::hypot(rn[i].x - fcx, rn[i].y - fcy));
+    for (const NodeRec& q : pnodes) rho = std::max(rho, std::hypot(q.x - fcx, q.y - fcy));
+    std::vector<int> near_a, far_a, near_ref, far_ref;
+    for (int64_t a = 0; a < f.Nk; ++a) {
+      const NodeRec& q = rn[k_ref[a]];
+      const bool nr = std::hypot(q.x - fcx, q.y - fcy) < FAR_RATIO * rho;
+      (nr ? near_a : far_a).push_back((int)a);
+      (nr ? near_ref : far_ref).push_back(k_ref[a]);
+    }
+    const bool far_on = ctx->opt.far_field != 0 && rho > 0.0 && f.Np > 0 && 2 * (int64_t)near_a.size() <= f.Nk;
+    const int64_t n_near = (int64_t)near_a.size(), n_far = (int64_t)far_a.size();
+    DBuf<NodeRec> d_near, d_far;
+    DBuf<int> d_near_pos, d_far_pos, d_idx;
+    if (far_on) {
+      f.info.n_near = n_near;
+      d_near.alloc(ctx, std::max<int64_t>(1, n_near));
+      d_far.alloc(ctx, std::max<int64_t>(1, n_far));
+      d_near_pos.alloc(ctx, std::max<int64_t>(1, n_near));
+      d_far_pos.alloc(ctx, std::max<int64_t>(1, n_far));
+      d_idx.alloc(ctx, std::max<int64_t>(1, f.Nk));
+      d_near_pos.upload(near_a.data(), n_near, s);
+      d_far_pos.upload(far_a.data(), n_far, s);
+      d_idx.upload(near_ref.data(), n_near, s);
+      if (n_far) HIP_CHECK(hipMemcpyAsync(d_idx.p + n_near, far_ref.data(), sizeof(int) * n_far, hipMemcpyHostToDevice, s));
+      launch_gather_nodes(w->d_nodes.p, d_idx.p, n_near, d_near.p, s);
+      launch_gather_nodes(w->d_nodes.p, d_idx.p + n_near, n_far, d_far.p, s);
+      HIP_CHECK(hipStreamSynchronize(s));  // the host index vectors stay valid until the copies are done
+    }
     for (;;) {
       const int kmax = ncols - 8;
       Yk.alloc(ctx, (size_t)2 * f.Nk * ncols);
       Yp.alloc(ctx, (size_t)2 * f.Np * ncols);
-      part.alloc(ctx, std::max(sketch_part_doubles(f.Nk, f.Nc + f.Np), sketch_part_doubles(f.Np, f.Nk)));
-      {
+      SketchSeg sk[2] = {{f.d_c.p, f.Nc, -1.0, 0}, {f.d_p.p, f.Np, 1.0, 2 * f.Nc}};
+      const uint64_t seed_k = ctx->opt.seed, seed_p = ctx->opt.seed ^ 0xA5A5A5A5ull;
+      if (far_on) {
+        // k-rows: far rows by the multipole expansion of the arc's sources,
+        // near rows exactly (compact, then scattered); p-rows: the near kept
+        // sources exactly, the far ones by a local expansion (Omega rows of
+        // the near list after those of all kept nodes, so none repeats)
+        const int ns_k = (int)std::min<int64_t>(256, std::max<int64_t>(1, (f.Nc + f.Np) / 128));
+        const int ns_p = (int)std::min<int64_t>(256, std::max<int64_t>(1, n_far / 128));
+        part.alloc(ctx, std::max<size_t>(1, std::max(sketch_part_doubles(n_near, f.Nc + f.Np),
+                                                     sketch_part_doubles(f.Np, n_near))));
+        Ynear.alloc(ctx, (size_t)std::max<int64_t>(1, 2 * n_near * ncols));
+        fpart.alloc(ctx, far_part_elems(ncols, std::max(ns_k, ns_p)));
+        fcoef.alloc(ctx, far_part_elems(ncols, 1));
+        const double fl = 2.0 * ncols * (2.0 * n_near * 2.0 * (f.Nc + f.Np) + 2.0 * f.Np * 2.0 * n_near) +
+                          8.0 * 4.0 * FAR_P * ncols * ((f.Nc + f.Np) + n_far + n_far + f.Np);
+        PhaseTimer t(ctx, "a2_sketch", fl, 8.0 * ncols * 2.0 * (f.Nk + f.Np));
+        launch_far_sketch(sk, 2, d_far.p, n_far, d_far_pos.p, false, fcx, fcy, rho, ncols, seed_k, false, Yk.p,
+                          fpart.p, ns_k, fcoef.p, s);
+        launch_sketch(d_near.p, n_near, sk, 2, ncols, seed_k, Ynear.p, part.p, s);
+        launch_scatter_rows(Ynear.p, n_near, d_near_pos.p, ncols, Yk.p, s);
+        SketchSeg spn[1] = {{d_near.p, n_near, 1.0, 2 * f.Nk}};
+        launch_sketch(f.d_p.p, f.Np, spn, 1, ncols, seed_p, Yp.p, part.p, s);
+        SketchSeg spf[1] = {{d_far.p, n_far, 1.0, 0}};
+        if (n_far)
+          launch_far_sketch(spf, 1, f.d_p.p, f.Np, nullptr, true, fcx, fcy, rho, ncols, seed_p, true, Yp.p, fpart.p,
+                            ns_p, fcoef.p, s);
+      } else {
+        part.alloc(ctx, std::max(sketch_part_doubles(f.Nk, f.Nc + f.Np), sketch_part_doubles(f.Np, f.Nk)));
         const double fl = 2.0 * ncols * (2.0 * f.Nk * 2.0 * (f.Nc + f.Np) + 2.0 * f.Np * 2.0 * f.Nk);
         PhaseTimer t(ctx, "a2_sketch", fl, 8.0 * ncols * 2.0 * (f.Nk + f.Np));
-        SketchSeg sk[2] = {{f.d_c.p, f.Nc, -1.0, 0}, {f.d_p.p, f.Np, 1.0, 2 * f.Nc}};
-        launch_sketch(f.d_k.p, f.Nk, sk, 2, ncols, ctx->opt.seed, Yk.p, part.p, s);
+        launch_sketch(f.d_k.p, f.Nk, sk, 2, ncols, seed_k, Yk.p, part.p, s);
         SketchSeg sp[1] = {{f.d_k.p, f.Nk, 1.0, 0}};
-        launch_sketch(f.d_p.p, f.Np, sp, 1, ncols, ctx->opt.seed ^ 0xA5A5A5A5ull, Yp.p, part.p, s);
+        launch_sketch(f.d_p.p, f.Np, sp, 1, ncols, seed_p, Yp.p, part.p, s);
       }
       part.release();
       Ck.alloc(ctx, (size_t)2 * f.Nk * kmax);
@@ -696,6 +781,7 @@ int rw_ctx_create(rw_ctx** out, int device, void* hip_stream, size_t hbm_budget_
   c->opt.sketch_cols = 64;
   c->opt.seed = 0x5eedull;
   c->opt.app_dense_max_nodes = 1024;
+  c->opt.far_field = 1;
   int rc = guarded(c.get(), [&]() {
     hipDeviceProp_t prop;
     HIP_CHECK(hipGetDeviceProperties(&prop, device));
@@ -719,6 +805,7 @@ void rw_ctx_destroy(rw_ctx* ctx) {
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
   for (auto e : ctx->order_events) (void)hipEventDestroy(e);
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
 }
 

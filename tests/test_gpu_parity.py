@@ -154,6 +154,42 @@ def test_woodbury_only_accuracy_and_refinement_gain(ctx, wall64):
     ref.close()
 
 
+@pytest.mark.parametrize("seed", [1, 4])
+def test_far_field_split_matches_exact_sketch(ctx, wall64, seed):
+    """Sec. 3.3 split: the kept nodes beyond the circle around the refined arc
+    enter the Q sketches through multipole / local expansions.  The Woodbury
+    solve alone must be as accurate as with the exactly sketched blocks (a
+    missing or wrong expansion term would leave the row IDs blind to part of
+    Q's range), and the refined solutions must agree with the oracle."""
+    p = W.config1(seed=seed)
+    sets = _oracle_sets(p)
+    st = p.rhs[0]
+    g_or = K.rhs_vector(sets.new, st.z, st.f)
+    tau_or = S.solve_refined(K.nystrom_matrix(sets.new), g_or)
+    out = {}
+    try:
+        for far in (1, 0):
+            ctx.set_options(far_field=far, ir_maxit=0)
+            ref = wall64.refine(p.refinement.panel_ids, p.refinement.levels)
+            inf = ref.info()
+            tau0 = ref.solve(_dev(g_or)).cpu().numpy()
+            ctx.set_options(ir_maxit=6)
+            tau1 = ref.solve(_dev(g_or)).cpu().numpy()
+            out[far] = (inf, relerr(tau0, tau_or), relerr(tau1, tau_or))
+            _say(f"  far_field={far}: n_near={inf['n_near']} k={inf['k']} woodbury-only err={out[far][1]:.2e} "
+                 f"refined err={out[far][2]:.2e}")
+            ref.close()
+    finally:
+        ctx.set_options(far_field=1, ir_maxit=6)
+    on, off = out[1], out[0]
+    assert 0 <= on[0]["n_near"] <= on[0]["n_k"] // 2
+    assert off[0]["n_near"] == -1
+    assert abs(on[0]["k"] - off[0]["k"]) <= 6
+    assert on[1] < 1e-6 and off[1] < 1e-6
+    assert on[1] < 10 * off[1] + 1e-9
+    assert on[2] <= 1e-10 and off[2] <= 1e-10
+
+
 def test_mixed_precision_generators(ctx, wall64):
     """FP32 reference generators (the mixed-precision mode): the Woodbury
     solve alone carries the FP32 rounding of A_oo^{-1} (relative error well
@@ -316,9 +352,11 @@ def test_config2_full_size_sampled(ctx):
          f"{st['gen_bytes_f64'] / 1e6:.1f} MB generators")
     ref = wall.refine(p.refinement.panel_ids, p.refinement.levels)
     inf = ref.info()
-    _say(f"  refine {inf['t_refine_ms']:.1f} ms, k={inf['k']} n_k={inf['n_k']} n_p={inf['n_p']}")
+    _say(f"  refine {inf['t_refine_ms']:.1f} ms, k={inf['k']} n_k={inf['n_k']} n_p={inf['n_p']} "
+         f"n_near={inf['n_near']}")
     sets = _oracle_sets(p)
     assert inf["n_p"] == 4096 and inf["n_k"] == 16128
+    assert 0 <= inf["n_near"] <= inf["n_k"] // 2   # the far-field split is taken at full size
     s0 = p.rhs[0]
     g = ref.stokeslet_rhs(s0.z, s0.f)
     tau = ref.solve(g)
