@@ -42,6 +42,7 @@ PEAK = {"hbm": (8000.0, "GB/s"), "mfma": (78.6, "TFLOP/s"), "alu": (78.6, "TFLOP
 KERNEL_BOUND = {
     "sketch_kernel": "mfma", "gemm_nn_sub_kernel": "mfma", "node_sketch_kernel": "mfma",
     "resid_tiles_kernel": "alu", "node_inverse_kernel": "alu", "node_factor_kernel": "alu",
+    "node_factor_bordered_kernel": "alu", "far_coef_kernel": "alu", "far_eval_kernel": "alu",
     "rowid_kernel": "alu", "rowid_select_kernel": "alu", "node_id_kernel": "alu",
     "hbs_up_kernel": "hbm", "hbs_down_kernel": "hbm",
 }

@@ -11,16 +11,24 @@
 // registers down by one in each of its updates (the new column j goes to
 // a[15]); the result is (P A)^-1, row j stored in row p_j, so
 // A^-1(j, p_c) = B(p_j, c), which gj64_store writes out.  The pivot search
-// stays inside the owner wave (DPP maximum of pivot keys), and a step moves
-// one 64-value pivot row through LDS.
+// stays inside the owner wave (DPP maximum of pivot keys); the owner's
+// column goes through LDS, and every wave reads its segment of the pivot row
+// from its own lane p (readlane), so a step needs one barrier: the column
+// and key slots alternate, and a slot is rewritten two steps later, after
+// every wave has passed the barrier of the step in between.
 constexpr int GN = 64;
 
 struct Gj64Scratch {
   double colv[2][GN];
-  double prow[2][GN];
   double key[2];
   int piv[GN];
 };
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane), hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
 __device__ inline bool reg_gj64(double (&a)[16], int n, Gj64Scratch& S, int& myq, int& rot) {
   const int tid = threadIdx.x, r = tid & 63;
@@ -36,26 +44,28 @@ __device__ inline bool reg_gj64(double (&a)[16], int n, Gj64Scratch& S, int& myq
       if (r == 0) S.key[b] = k;
     }
     __syncthreads();
-    const int p = pivot_key_index<6>(S.key[b]);
+    const int p = __builtin_amdgcn_readfirstlane(pivot_key_index<6>(S.key[b]));
     const double piv = S.colv[b][p];
-    if (!(fabs(piv) > 0.0) || !isfinite(piv)) return false;
+    if (!(fabs(piv) > 0.0) || !isfinite(piv)) {
+      __syncthreads();
+      return false;
+    }
+    if (tid == 0) S.piv[j] = p;
+    const double pinv = 1.0 / piv;
+    const double f = S.colv[b][r] * pinv;
+    double pr[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) pr[c] = readlane_f64(a[c], p);
     if (r == p) {
       used = true;
       myq = j;
-#pragma unroll
-      for (int c = 0; c < 16; ++c) S.prow[b][16 * h + c] = a[c];
     }
-    if (tid == 0) S.piv[j] = p;
-    __syncthreads();
-    const double pinv = 1.0 / piv;
-    const double* pr = &S.prow[b][16 * h];
     if (own) {
       if (r == p) {
 #pragma unroll
         for (int c = 0; c < 15; ++c) a[c] = a[c + 1] * pinv;
         a[15] = pinv;
       } else {
-        const double f = S.colv[b][r] * pinv;
 #pragma unroll
         for (int c = 0; c < 15; ++c) a[c] = a[c + 1] - f * pr[c + 1];
         a[15] = -f;
@@ -65,12 +75,12 @@ __device__ inline bool reg_gj64(double (&a)[16], int n, Gj64Scratch& S, int& myq
 #pragma unroll
         for (int c = 0; c < 16; ++c) a[c] *= pinv;
       } else {
-        const double f = S.colv[b][r] * pinv;
 #pragma unroll
         for (int c = 0; c < 16; ++c) a[c] -= f * pr[c];
       }
     }
   }
+  __syncthreads();   // S.piv complete for gj64_store
   rot = min(max(n - 16 * h, 0), 16) & 15;
   return true;
 }

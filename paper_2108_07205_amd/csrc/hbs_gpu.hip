@@ -19,6 +19,7 @@
 //     D^_b]]), D^ = (V* D^-1 U)^-1, E = D^-1 U D^, F* = D^ V* D^-1,
 //     G = D^-1 - D^-1 U D^ V* D^-1; the root stores G_root = D_root^-1.
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 #include "dev_gj.h"
@@ -78,9 +79,10 @@ __global__ __launch_bounds__(256) void node_sketch_kernel(const GNode* __restric
                                                           const int* __restrict__ candc,
                                                           const NodeRec* __restrict__ nd, int64_t N, uint64_t seed,
                                                           int64_t part_stride, double* __restrict__ Sr,
-                                                          double* __restrict__ Sc) {
+                                                          double* __restrict__ Sc, int mlo, int mhi) {
   __shared__ NodeRec snd[256];
   const GNode g = gn[blockIdx.x];
+  if (g.m <= mlo || g.m > mhi) return;   // node handled by another launch
   const int side = blockIdx.y;
   const int z = blockIdx.z, nz = gridDim.z;
   const int* cand = (side == 0 ? candr : candc) + g.cand_off;
@@ -221,7 +223,8 @@ __global__ __launch_bounds__(256) void node_sketch_mfma_kernel(const GNode* __re
                                                                const int* __restrict__ candc,
                                                                const NodeRec* __restrict__ nd, int64_t N,
                                                                uint64_t seed, int64_t part_stride,
-                                                               double* __restrict__ Sr, double* __restrict__ Sc) {
+                                                               double* __restrict__ Sr, double* __restrict__ Sc,
+                                                               int mlo, int mhi) {
   constexpr int MR = 64 * RBW;  // row capacity
   __shared__ NodeRec rn[MR];
   __shared__ int rc[MR];
@@ -230,6 +233,7 @@ __global__ __launch_bounds__(256) void node_sketch_mfma_kernel(const GNode* __re
   __shared__ double As[16][MR + 2];
   __shared__ double Bs[16][SK_R + 2];
   const GNode g = gn[blockIdx.x];
+  if (g.m <= mlo || g.m > mhi) return;   // node handled by another launch
   const int side = blockIdx.y, m = g.m;
   const int z = blockIdx.z, nz = gridDim.z;
   const int64_t j_lo = (z * N) / nz, j_hi = ((z + 1) * N) / nz;
@@ -518,6 +522,72 @@ __global__ __launch_bounds__(512) void node_id_kernel(const GNode* __restrict__ 
   if (tid == 0) {
     info[(blockIdx.x * 2 + side) * 2] = rank < 0 ? step : rank;
     info[(blockIdx.x * 2 + side) * 2 + 1] = step;
+  }
+}
+
+// ---------------------------------------------------------------- 2b. level plan
+// grid 1, one wave: the ID ranks of level l (info: row rank, row steps,
+// column rank, column steps per node) give each node's rank k (the larger
+// tolerance rank, at most the smaller step count) and, by prefix sums in
+// node order, its U / V, D^, workspace and generator offsets; the skeleton
+// positions in the parent's candidate list (ppos); the parent level's
+// candidate counts m and offsets.  cnt[0] (generator entries used) advances
+// by the level's total.  fail[1]: a rank reached the sketch size; fail[2]:
+// an offset passed its buffer bound.
+__device__ __forceinline__ long long wave_incl_scan(long long v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const long long u = __shfl_up(v, o);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(64) void level_plan_kernel(GNode* __restrict__ gl, int nn, const int* __restrict__ info,
+                                                        GNode* __restrict__ gpar, int64_t* __restrict__ ppos,
+                                                        int64_t* __restrict__ cnt, int64_t gen_cap, int64_t ws_cap,
+                                                        int* __restrict__ fail) {
+  const int lane = threadIdx.x;
+  long long base[5] = {0, 0, 0, (long long)cnt[0], 0};   // U/V, D^, workspace, generators, skeleton positions
+  for (int j0 = 0; j0 < nn; j0 += 64) {
+    const int j = j0 + lane;
+    const bool v = j < nn;
+    long long m = 0, k = 0;
+    if (v) {
+      m = gl[j].m;
+      const int kr = info[4 * j], sr = info[4 * j + 1], kc = info[4 * j + 2], sc = info[4 * j + 3];
+      k = min(max(kr, kc), min(sr, sc));
+      if (max(kr, kc) >= SK_KCAP) fail[1] = 1;
+    }
+    const long long q[5] = {m * k, k * k, 3 * m * m + 2 * m * k + 2 * k * k, (k + m) * m + m * k, k};
+    long long ex[5], tot[5];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+      const long long in = wave_incl_scan(q[t], lane);
+      ex[t] = base[t] + in - q[t];
+      tot[t] = __shfl(in, 63);
+    }
+    const long long k_next = __shfl_down(k, 1);
+    if (v) {
+      GNode& g = gl[j];
+      g.k = (int)k;
+      g.uv_off = ex[0];
+      g.dhat_off = ex[1];
+      g.ws_off = ex[2];
+      g.up_off = ex[3];
+      g.e_off = ex[3] + (k + m) * m;
+      ppos[j] = ex[4];
+      if ((j & 1) == 0) {
+        gpar[j >> 1].m = (int)(k + k_next);
+        gpar[j >> 1].cand_off = ex[4];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 5; ++t) base[t] += tot[t];
+  }
+  if (lane == 0) {
+    cnt[0] = base[3];
+    if (base[3] > gen_cap || base[2] > ws_cap) fail[2] = 1;
   }
 }
 
@@ -873,6 +943,233 @@ __device__ __forceinline__ double a_entry(const NodeRec& t, const NodeRec& s, bo
   return cf * rt * rs + s.w * nt * ns;
 }
 
+// ------------------------------------------------- 4a. bordered factorization
+// One Gauss-Jordan inversion per node of the bordered matrix
+//   M = [[D, U], [V*, 0]]   ((n + k) x (n + k)),
+// whose inverse, by the block inverse with Schur complement -V* D^-1 U, is
+//   M^-1 = [[G, E], [F*, -D^]]
+// with D^ = (V* D^-1 U)^-1, E = D^-1 U D^, F* = D^ V* D^-1 and
+// G = D^-1 - D^-1 U D^ V* D^-1: every generator of the node in one pass,
+// without D^-1 or the products ever leaving the registers.  The root (k = 0)
+// gets D^-1 = G_root.
+// grid (nodes), 512 threads (8 waves); n + k <= BT.  Lane l holds rows
+// l, l + 64, l + 128 (sub-rows s), wave w the 24 columns 24 w .. 24 w + 23
+// (a[s][c]).  Pivoting as in reg_gj64: step j takes column j, whose owner
+// wave keeps it in a[.][0] by shifting its registers; rows are never moved,
+// so the result is (P M)^-1 with row j stored in row p_j.  One barrier per
+// step: the owner publishes column j and the pivot key through alternating
+// LDS slots, and every wave reads its part of pivot row p from lane p % 64.
+constexpr int BT = 192;        // largest bordered size
+constexpr int BWV = 12;        // waves
+constexpr int BC = BT / BWV;   // columns per wave
+constexpr int BS = BT / 64;    // sub-rows per lane
+static_assert(BC == 16 && BS == 3, "the column switches and pivot-row branches below are written for 16 x 3");
+
+struct BorderScratch {
+  double pan[2][BT][BC + 1];   // transformed panel of the block (alternating slots)
+  double rows[BWV][BC][BC];    // per wave: its columns of the block's pivot rows
+  double pinv[BT];             // 1 / pivot of each step
+  int piv[BT];                 // pivot row of each step
+  int bad;                     // a panel met a zero or non-finite pivot
+};
+
+__global__ __launch_bounds__(BWV * 64) void node_factor_bordered_kernel(
+    const GNode* __restrict__ gn, const GNode* __restrict__ gch, int is_leaf, int is_root,
+    const int* __restrict__ candr, const int* __restrict__ candc, const NodeRec* __restrict__ nd,
+    const double* __restrict__ U, const double* __restrict__ V, const double* __restrict__ dhat_ch,
+    double* __restrict__ dhat, double* __restrict__ ws, double* __restrict__ gen, double* __restrict__ groot,
+    int* __restrict__ fail) {
+  __shared__ BorderScratch S;
+  const GNode g = gn[blockIdx.x];
+  const int n = g.m, k = is_root ? 0 : g.k, T = n + k;
+  if (T > BT) return;   // node taken by the block-inverse kernels
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int* cr = candr + g.cand_off;
+  const int* cc = candc + g.cand_off;
+  const double* Un = U + g.uv_off;
+  const double* Vn = V + g.uv_off;
+  int ka = 0, kb = 0;
+  const double *Da = nullptr, *Db = nullptr;
+  if (!is_leaf) {
+    const GNode ca = gch[2 * blockIdx.x], cbn = gch[2 * blockIdx.x + 1];
+    ka = ca.k;
+    kb = cbn.k;
+    Da = dhat_ch + ca.dhat_off;
+    Db = dhat_ch + cbn.dhat_off;
+  }
+  // ---- M assembled in the node's workspace slot, then into the registers
+  double* Mw = ws + g.ws_off;
+  for (int idx = tid; idx < T * T; idx += BWV * 64) {
+    const int row = idx % T, col = idx / T;
+    double v = 0.0;
+    if (row < n && col < n) {
+      if (!is_leaf && row < ka && col < ka) v = Da[row + col * ka];
+      else if (!is_leaf && row >= ka && col >= ka) v = Db[(row - ka) + (col - ka) * kb];
+      else {
+        const int ra = cr[row], cb = cc[col];
+        v = a_entry(nd[ra >> 1], nd[cb >> 1], is_leaf && (ra >> 1) == (cb >> 1), ra & 1, cb & 1);
+      }
+    } else if (row < n) {
+      v = Un[row + (int64_t)(col - n) * n];
+    } else if (col < n) {
+      v = Vn[col + (int64_t)(row - n) * n];
+    }
+    Mw[idx] = v;
+  }
+  __threadfence_block();
+  __syncthreads();
+  double a[BS][BC];
+#pragma unroll
+  for (int sr = 0; sr < BS; ++sr) {
+    const int row = lane + 64 * sr;
+#pragma unroll
+    for (int c = 0; c < BC; ++c) {
+      const int col = BC * w + c;
+      a[sr][c] = (row < T && col < T) ? Mw[row + col * T] : 0.0;
+    }
+  }
+  // Blocked Gauss-Jordan: block bj is the 16 columns of wave bj.  That wave
+  // runs the 16 steps on its own columns alone (pivot search by DPP, pivot
+  // row by readlane: no barrier), the new inverse column replacing the
+  // eliminated one in place; its columns then hold E(:, I), the block's
+  // row operations E = E_15 ... E_0 restricted to the pivot rows I.  After
+  // one barrier every other wave applies them to its columns,
+  //   A <- A + (E(:, I) - I(:, I)) A(I, :),
+  // a rank-16 update.  Pivot rows are not scaled during the sweep (a later
+  // elimination with an unscaled pivot row gives the same result for the
+  // other rows, and the pivot row stays piv times its scaled form), so each
+  // row is divided by its own pivot once at the end.
+  if (tid == 0) S.bad = 0;
+  bool used[BS];
+  int myq[BS];
+  double rinv[BS];
+#pragma unroll
+  for (int sr = 0; sr < BS; ++sr) {
+    used[sr] = lane + 64 * sr >= T;
+    myq[sr] = -1;
+    rinv[sr] = 0.0;
+  }
+  const int nbk = (T + BC - 1) / BC;
+  for (int bj = 0; bj < nbk; ++bj) {
+    const int j0 = bj * BC, nb = min(BC, T - j0), slot = bj & 1;
+    if (w == bj) {
+      // ---- panel: nb steps on this wave's columns
+      bool ok = true;
+#pragma unroll
+      for (int c = 0; c < BC; ++c) {
+        if (c < nb && ok) {
+          double kmax = 0.0;
+#pragma unroll
+          for (int sr = 0; sr < BS; ++sr)
+            kmax = fmax(kmax, pivot_key_bits<8>(a[sr][c], lane + 64 * sr, !used[sr]));
+          kmax = wave_max_nonneg(kmax);
+          const int p = __builtin_amdgcn_readfirstlane(pivot_key_index<8>(kmax));
+          const int ps = p >> 6, pl = p & 63;
+          double pr[BC];
+#pragma unroll
+          for (int cc = 0; cc < BC; ++cc)
+            pr[cc] = readlane_f64(ps == 0 ? a[0][cc] : (ps == 1 ? a[1][cc] : a[2][cc]), pl);
+          const double piv = pr[c];
+          if (!(fabs(piv) > 0.0) || !isfinite(piv)) {
+            ok = false;
+            if (lane == 0) S.bad = 1;
+          } else {
+            const double pinv = 1.0 / piv;
+            if (lane == 0) {
+              S.piv[j0 + c] = p;
+              S.pinv[j0 + c] = pinv;
+            }
+#pragma unroll
+            for (int sr = 0; sr < BS; ++sr) {
+              const bool isp = lane + 64 * sr == p;
+              const double f = isp ? 0.0 : a[sr][c] * pinv;
+              if (isp) used[sr] = true;
+#pragma unroll
+              for (int cc = 0; cc < BC; ++cc) a[sr][cc] -= f * pr[cc];
+              a[sr][c] = isp ? 1.0 : -f;
+            }
+          }
+        }
+      }
+      // publish the transformed panel E(:, I) of the block
+#pragma unroll
+      for (int sr = 0; sr < BS; ++sr)
+#pragma unroll
+        for (int cc = 0; cc < BC; ++cc) S.pan[slot][lane + 64 * sr][cc] = a[sr][cc];
+    }
+    __syncthreads();
+    if (S.bad) {
+      if (tid == 0) atomicExch(fail, 1);
+      return;   // uniform
+    }
+    // the block's pivot rows: used, step and 1 / pivot of this lane's rows
+    int tt[BS];
+#pragma unroll
+    for (int sr = 0; sr < BS; ++sr) tt[sr] = -1;
+    for (int t = 0; t < nb; ++t) {
+      const int pt = S.piv[j0 + t];
+#pragma unroll
+      for (int sr = 0; sr < BS; ++sr)
+        if (lane + 64 * sr == pt) {
+          tt[sr] = t;
+          used[sr] = true;
+          myq[sr] = j0 + t;
+          rinv[sr] = S.pinv[j0 + t];
+        }
+    }
+    if (w != bj) {
+      // this wave's columns of the pivot rows, before the update
+#pragma unroll
+      for (int sr = 0; sr < BS; ++sr)
+        if (tt[sr] >= 0) {
+#pragma unroll
+          for (int cc = 0; cc < BC; ++cc) S.rows[w][tt[sr]][cc] = a[sr][cc];
+        }
+      __builtin_amdgcn_wave_barrier();
+      for (int t = 0; t < nb; ++t) {
+        double rt[BC];
+#pragma unroll
+        for (int cc = 0; cc < BC; ++cc) rt[cc] = S.rows[w][t][cc];
+#pragma unroll
+        for (int sr = 0; sr < BS; ++sr) {
+          const double cf = S.pan[slot][lane + 64 * sr][t] - (tt[sr] == t ? 1.0 : 0.0);
+#pragma unroll
+          for (int cc = 0; cc < BC; ++cc) a[sr][cc] += cf * rt[cc];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+#pragma unroll
+  for (int sr = 0; sr < BS; ++sr)
+#pragma unroll
+    for (int c = 0; c < BC; ++c) a[sr][c] *= rinv[sr];
+  __syncthreads();   // S.piv complete
+  // ---- M^-1(q, piv[col]) = a: route the blocks to G_root or [F*; G], E, D^
+  double* up = gen + g.up_off;
+  double* E = gen + g.e_off;
+  double* Dh = dhat + g.dhat_off;
+  const int ld_up = k + n;
+#pragma unroll
+  for (int sr = 0; sr < BS; ++sr) {
+    const int i = myq[sr];
+    if (lane + 64 * sr >= T || i < 0) continue;
+#pragma unroll
+    for (int c = 0; c < BC; ++c) {
+      const int col = BC * w + c;
+      if (col >= T) continue;
+      const int jo = S.piv[col];
+      const double v = a[sr][c];
+      if (is_root) groot[i + (int64_t)jo * n] = v;
+      else if (i < n && jo < n) up[(k + i) + (int64_t)jo * ld_up] = v;
+      else if (jo < n) up[(i - n) + (int64_t)jo * ld_up] = v;
+      else if (i < n) E[i + (int64_t)(jo - n) * n] = v;
+      else Dh[(i - n) + (int64_t)(jo - n) * k] = -v;
+    }
+  }
+}
+
 // grid (nodes), nodes of at most FN unknowns.  Same inputs and outputs as
 // node_inverse_kernel: D assembled straight into registers, D^-1 by the
 // register Gauss-Jordan, then with W = ws + ws_off holding
@@ -885,11 +1182,14 @@ __global__ __launch_bounds__(256) void node_factor_kernel(const GNode* __restric
                                                           const double* __restrict__ V,
                                                           const double* __restrict__ dhat_ch, double* __restrict__ dhat,
                                                           double* __restrict__ ws, double* __restrict__ gen,
-                                                          double* __restrict__ groot, int* __restrict__ fail) {
+                                                          double* __restrict__ groot, int* __restrict__ fail,
+                                                          int mlo, int mhi) {
   __shared__ GjScratch gs;
   __shared__ Gj64Scratch g64;
   __shared__ GemmScratch ms;
   const GNode g = gn[blockIdx.x];
+  if (g.m <= mlo || g.m > mhi) return;   // node handled by another launch
+  if (g.m + (is_root ? 0 : g.k) <= BT) return;   // taken by the bordered factorization
   const int n = g.m, k = g.k, tid = threadIdx.x, r = tid & (FN - 1);
   const int h = __builtin_amdgcn_readfirstlane(tid >> 7);
   const int* cr = candr + g.cand_off;
@@ -1068,13 +1368,16 @@ __global__ __launch_bounds__(256) void node_inverse_kernel(const GNode* __restri
                                                            const double* __restrict__ V,
                                                            const double* __restrict__ dhat_ch, double* __restrict__ dhat,
                                                            double* __restrict__ ws, double* __restrict__ gen,
-                                                           double* __restrict__ groot, int* __restrict__ fail) {
+                                                           double* __restrict__ groot, int* __restrict__ fail,
+                                                           int mlo, int mhi) {
   __shared__ double rv[4];
   __shared__ int ri[4];
   __shared__ int perm[256];
   __shared__ double fsc[256];
   extern __shared__ double sA[];       // n x n when the node fits in LDS, then k x k
   const GNode g = gn[blockIdx.x];
+  if (g.m <= mlo || g.m > mhi) return;   // node handled by another launch
+  if (g.m + (is_root ? 0 : g.k) <= BT) return;   // taken by the bordered factorization
   const int n = g.m, k = g.k, tid = threadIdx.x;
   const int* cr = candr + g.cand_off;
   const int* cc = candc + g.cand_off;
@@ -1336,21 +1639,43 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
   DBuf<double> Sr(ctx, cap_max * SK_R), Sc(ctx, cap_max * SK_R);
   DBuf<double> Cr(ctx, cap_max * SK_KCAP), Cc(ctx, cap_max * SK_KCAP);
   DBuf<int> piv(ctx, (size_t)(int64_t(2) << L) * SK_KCAP), info(ctx, (size_t)(int64_t(4) << L)), fail(ctx, 4);
+  DBuf<int64_t> cnt(ctx, 2);
   DBuf<double> Ub(ctx, uv_total), Vb(ctx, uv_total);
   DBuf<double> dhA(ctx, (int64_t(1) << L) * SK_KCAP * SK_KCAP), dhB(ctx, (int64_t(1) << L) * SK_KCAP * SK_KCAP);
   DBuf<double> ws(ctx, ws_bound);
   DBuf<int64_t> dpar(ctx, (size_t)(int64_t(2) << L));  // level l at [2^l, 2^(l+1))
-  DBuf<double> part_r, part_c;
+  // sketch partial sums: the largest (candidates x split count) of any level
+  auto level_split = [&](int64_t nn) {
+    int ns = (int)std::min<int64_t>(64, std::max<int64_t>(1, 1024 / (2 * nn)));
+    return (int)std::min<int64_t>(ns, std::max<int64_t>(1, N / 64));
+  };
+  int64_t part_len = 0;
+  for (int l = 1; l <= L; ++l) {
+    const int64_t nn = int64_t(1) << l;
+    const int64_t mb = (l == L) ? 2 * ((N + nn - 1) / nn) : 2 * SK_KCAP;
+    part_len = std::max(part_len, nn * mb * SK_R * level_split(nn));
+  }
+  DBuf<double> part_r(ctx, part_len), part_c(ctx, part_len);
   w.gen.alloc(ctx, gen_bound);
+  w.groot.alloc(ctx, (size_t)(2 * SK_KCAP) * (2 * SK_KCAP));
   HIP_CHECK(hipMemsetAsync(fail.p, 0, sizeof(int) * 4, s));
-  // leaf candidate lists: all dofs of the range
-  std::vector<int> leaf_cand;
-  leaf_cand.reserve(2 * N);
-  for (int64_t d = 0; d < 2 * N; ++d) leaf_cand.push_back((int)d);
-  HIP_CHECK(hipMemcpyAsync(candr.p + cand_base[L], leaf_cand.data(), sizeof(int) * leaf_cand.size(),
-                           hipMemcpyHostToDevice, s));
-  HIP_CHECK(hipMemcpyAsync(candc.p + cand_base[L], leaf_cand.data(), sizeof(int) * leaf_cand.size(),
-                           hipMemcpyHostToDevice, s));
+  HIP_CHECK(hipMemsetAsync(cnt.p, 0, sizeof(int64_t) * 2, s));
+  // pinned staging: node records (level l at [2^l, 2^(l+1))) and the leaf candidate lists
+  char* pin = (char*)ctx_pinned(ctx, sizeof(GNode) * (size_t)(int64_t(2) << L) + sizeof(int) * (size_t)(2 * N));
+  GNode* hG = (GNode*)pin;
+  int* hC = (int*)(pin + sizeof(GNode) * (size_t)(int64_t(2) << L));
+  // leaf records carry their counts and offsets; a parent's are set on the
+  // device from its children's ranks (level_plan_kernel)
+  {
+    int64_t off = 0;
+    for (GNode& g : G[L]) { g.cand_off = off; off += g.m; }
+    for (int l = 0; l <= L; ++l) memcpy(hG + (int64_t(1) << l), G[l].data(), sizeof(GNode) * G[l].size());
+    memset(hG, 0, sizeof(GNode));
+    HIP_CHECK(hipMemcpyAsync(dg.p, hG, sizeof(GNode) * (size_t)(int64_t(2) << L), hipMemcpyHostToDevice, s));
+    for (int64_t d = 0; d < 2 * N; ++d) hC[d] = (int)d;
+    HIP_CHECK(hipMemcpyAsync(candr.p + cand_base[L], hC, sizeof(int) * 2 * N, hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(candc.p + cand_base[L], hC, sizeof(int) * 2 * N, hipMemcpyHostToDevice, s));
+  }
   // the factor chain starts after everything enqueued so far; whatever way
   // this function ends, later work on the main stream waits for it
   const hipStream_t sf = ctx_side_stream(ctx);
@@ -1369,62 +1694,83 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
   w.lev.assign(L + 1, HbsLevelDev());
   w.S.assign(L + 2, 0);
   w.K.assign(L + 2, 0);
-  std::vector<std::vector<int>> lev_ints(L + 1);
-  std::vector<std::vector<int64_t>> lev_offs(L + 1);
-  // pinned staging: node records (level l at [2^l, 2^(l+1))), parent
-  // positions (same layout) and the ID ranks of one level
-  char* pin = (char*)ctx_pinned(ctx, (sizeof(GNode) + sizeof(int64_t)) * (size_t)(int64_t(2) << L) +
-                                         sizeof(int) * (size_t)(int64_t(4) << L));
-  GNode* hG = (GNode*)pin;
-  int64_t* hP = (int64_t*)(pin + sizeof(GNode) * (size_t)(int64_t(2) << L));
-  int* hI = (int*)(hP + (int64_t(2) << L));
-  int64_t gen_used = 0;
-  w.entries = 0;
-  w.max_rank = 0;
   double* dh_child = dhB.p;
   double* dh_cur = dhA.p;
   const size_t shi = 2 * sizeof(double) * SK_KCAP * SK_KCAP;
   HIP_CHECK(hipFuncSetAttribute((const void*)node_interp_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shi));
   const size_t shv = INV_LDS_BYTES;
   HIP_CHECK(hipFuncSetAttribute((const void*)node_inverse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shv));
+  constexpr int MANY = 1 << 30;
+  // profiler entries of the factor launches (their flops are known once the ranks are read back)
+  std::vector<size_t> fac_entry(L + 1, SIZE_MAX);
+  auto factor_launch = [&](const GNode* gn, const GNode* gch, int nn, int is_leaf, int is_root, const int* cr,
+                           const int* cc, const double* U, const double* V, double* groot, int mx_known, int lvl) {
+    // nodes with n + k <= BT: bordered Gauss-Jordan; the others: block
+    // inverse in registers (n <= FN) or LDS Gauss-Jordan
+    {
+      KernelTimer kt("node_factor_bordered_kernel", 0.0, 0.0, sf);
+      hipLaunchKernelGGL(node_factor_bordered_kernel, dim3(nn), dim3(BWV * 64), 0, sf, gn, gch, is_leaf, is_root, cr, cc,
+                         d_nodes, U, V, dh_child, dh_cur, ws.p, w.gen.p, groot, fail.p);
+      KERNEL_CHECK("node_factor_bordered");
+    }
+    if (ctx->prof && !ctx->pending.empty()) fac_entry[lvl] = ctx->pending.size() - 1;
+    const bool small = mx_known < 0 || mx_known <= FN;
+    const bool large = mx_known < 0 || mx_known > FN;
+    if (small) {
+      KernelTimer kt("node_factor_kernel", 0.0, 0.0, sf);
+      hipLaunchKernelGGL(node_factor_kernel, dim3(nn), dim3(256), 0, sf, gn, gch, is_leaf, is_root, cr, cc, d_nodes,
+                         U, V, dh_child, dh_cur, ws.p, w.gen.p, groot, fail.p, 0, FN);
+      KERNEL_CHECK("node_factor");
+    }
+    if (large) {
+      KernelTimer kt("node_inverse_kernel", 0.0, 0.0, sf);
+      hipLaunchKernelGGL(node_inverse_kernel, dim3(nn), dim3(256), shv, sf, gn, gch, is_leaf, is_root, cr, cc, d_nodes,
+                         U, V, dh_child, dh_cur, ws.p, w.gen.p, groot, fail.p, FN, MANY);
+      KERNEL_CHECK("node_inverse");
+    }
+  };
   for (int l = L; l >= 1; --l) {
     const int nn = 1 << l;
-    std::vector<GNode>& gl = G[l];
+    const bool leaf = l == L;
     GNode* dgl = dg.p + nn;
     int* cr = candr.p + cand_base[l];
     int* cc = candc.p + cand_base[l];
-    int64_t off = 0;
+    // host-known sizes at the leaves; bounds above them
     int mx = 0;
-    for (int j = 0; j < nn; ++j) { gl[j].cand_off = off; off += gl[j].m; mx = std::max(mx, gl[j].m); }
-    if (mx > mmax) RW_THROW(RW_ESINGULAR, "HBS node input exceeds the sketch bound");
-    memcpy(hG + nn, gl.data(), sizeof(GNode) * nn);
-    HIP_CHECK(hipMemcpyAsync(dgl, hG + nn, sizeof(GNode) * nn, hipMemcpyHostToDevice, s));
-    // split each node's near nodes (entity range) so every level fills the device
-    int nsplit = (int)std::min<int64_t>(64, std::max<int64_t>(1, 1024 / (2 * nn)));
-    nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, N / 64));
+    int64_t off = 0;
+    if (leaf) {
+      for (const GNode& g : G[L]) { off += g.m; mx = std::max(mx, g.m); }
+      if (mx > mmax) RW_THROW(RW_ESINGULAR, "HBS node input exceeds the sketch bound");
+    } else {
+      off = (int64_t)nn * 2 * SK_KCAP;
+    }
+    const int nsplit = level_split(nn);
     const int64_t len = off * SK_R;
-    const bool mfma_sketch = mx <= 192;
-    if (nsplit > 1 || !mfma_sketch)
-      if (part_r.n < (size_t)(len * nsplit)) { part_r.alloc(ctx, len * nsplit); part_c.alloc(ctx, len * nsplit); }
-    double* outr = (nsplit > 1 || !mfma_sketch) ? part_r.p : Sr.p;
-    double* outc = (nsplit > 1 || !mfma_sketch) ? part_c.p : Sc.p;
     {
       KernelTimer kt("node_sketch_kernel", 0.0, 0.0);
-      if (mx <= 128)
-        hipLaunchKernelGGL(node_sketch_mfma_kernel<2>, dim3(nn, 2, nsplit), dim3(256), 0, s, dgl, cr, cc, d_nodes, N,
-                           seed + 7919ull * l, len, outr, outc);
-      else if (mfma_sketch)
-        hipLaunchKernelGGL(node_sketch_mfma_kernel<3>, dim3(nn, 2, nsplit), dim3(256), 0, s, dgl, cr, cc, d_nodes, N,
-                           seed + 7919ull * l, len, outr, outc);
-      else
-        hipLaunchKernelGGL(node_sketch_kernel, dim3(nn, 2, nsplit), dim3(256), 0, s, dgl, cr, cc, d_nodes, N,
-                           seed + 7919ull * l, len, outr, outc);
+      const dim3 grid(nn, 2, nsplit);
+      const bool direct = nsplit == 1;
+      double* outr = direct ? Sr.p : part_r.p;
+      double* outc = direct ? Sc.p : part_c.p;
+      const uint64_t sd = seed + 7919ull * l;
+      if (leaf && mx > 192) {
+        hipLaunchKernelGGL(node_sketch_kernel, grid, dim3(256), 0, s, dgl, cr, cc, d_nodes, N, sd, len, part_r.p,
+                           part_c.p, 0, MANY);
+      } else {
+        if (!leaf || mx <= 128)
+          hipLaunchKernelGGL(node_sketch_mfma_kernel<2>, grid, dim3(256), 0, s, dgl, cr, cc, d_nodes, N, sd, len,
+                             outr, outc, 0, 128);
+        if (!leaf || mx > 128)
+          hipLaunchKernelGGL(node_sketch_mfma_kernel<3>, grid, dim3(256), 0, s, dgl, cr, cc, d_nodes, N, sd, len,
+                             outr, outc, 128, 192);
+      }
       KERNEL_CHECK("node_sketch");
-    }
-    if (nsplit > 1 || !mfma_sketch) {
-      hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len)), dim3(256), 0, s, part_r.p, nsplit, len, len, Sr.p);
-      hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len)), dim3(256), 0, s, part_c.p, nsplit, len, len, Sc.p);
-      KERNEL_CHECK("node_sketch_sum");
+      if (!direct || (leaf && mx > 192)) {
+        const int nz = nsplit;
+        hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len)), dim3(256), 0, s, part_r.p, nz, len, len, Sr.p);
+        hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len)), dim3(256), 0, s, part_c.p, nz, len, len, Sc.p);
+        KERNEL_CHECK("node_sketch_sum");
+      }
     }
     {
       KernelTimer kt_id("node_id_kernel", 0.0, 0.0);
@@ -1432,136 +1778,85 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
                          info.p);
       KERNEL_CHECK("node_id");
     }
-    const int* hinfo = hI;
-    info.download(hI, 4 * (size_t)nn, s);
-    HIP_CHECK(hipStreamSynchronize(s));
-    // ranks and offsets
-    int64_t uv = 0, dho = 0, wso = 0;
-    for (int j = 0; j < nn; ++j) {
-      const int kr = hinfo[4 * j], sr = hinfo[4 * j + 1], kc = hinfo[4 * j + 2], sc = hinfo[4 * j + 3];
-      int k = std::max(kr, kc);
-      k = std::min(k, std::min(sr, sc));
-      if (std::max(kr, kc) >= SK_KCAP) RW_THROW(RW_ESINGULAR, "HBS node rank reached the sketch size");
-      GNode& g = gl[j];
-      g.k = k;
-      g.uv_off = uv;
-      uv += (int64_t)g.m * k;
-      g.dhat_off = dho;
-      dho += (int64_t)k * k;
-      g.ws_off = wso;
-      wso += 3 * (int64_t)g.m * g.m + 2 * (int64_t)g.m * k + 2 * (int64_t)k * k;
-      g.up_off = gen_used;
-      gen_used += (int64_t)(k + g.m) * g.m;
-      g.e_off = gen_used;
-      gen_used += (int64_t)g.m * k;
-      w.max_rank = std::max(w.max_rank, k);
-      w.entries += 2 * (int64_t)g.m * k + (int64_t)g.m * g.m;
-    }
-    if (gen_used > (int64_t)w.gen.n) RW_THROW(RW_ESINGULAR, "HBS generator bound exceeded");
-    if (wso > (int64_t)ws.n) RW_THROW(RW_ESINGULAR, "HBS factor workspace bound exceeded");
-    // parent candidate sizes and positions of each child's skeleton in them
-    {
-      int64_t* pp = hP + nn;
-      int64_t po = 0;
-      for (int pj = 0; pj < nn / 2; ++pj) {
-        pp[2 * pj] = po;
-        pp[2 * pj + 1] = po + gl[2 * pj].k;
-        G[l - 1][pj].m = gl[2 * pj].k + gl[2 * pj + 1].k;
-        po += G[l - 1][pj].m;
-      }
-      HIP_CHECK(hipMemcpyAsync(dpar.p + nn, pp, sizeof(int64_t) * nn, hipMemcpyHostToDevice, s));
-    }
-    memcpy(hG + nn, gl.data(), sizeof(GNode) * nn);
-    HIP_CHECK(hipMemcpyAsync(dgl, hG + nn, sizeof(GNode) * nn, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(node_interp_kernel, dim3(nn, 2), dim3(256), shi, s, dgl, cr, cc, piv.p, Cr.p,
-                       Cc.p, Ub.p + uv_base[l], Vb.p + uv_base[l], dpar.p + nn, candr.p + cand_base[l - 1],
+    hipLaunchKernelGGL(level_plan_kernel, dim3(1), dim3(64), 0, s, dgl, nn, info.p, dg.p + nn / 2, dpar.p + nn, cnt.p,
+                       (int64_t)w.gen.n, (int64_t)ws.n, fail.p);
+    KERNEL_CHECK("level_plan");
+    hipLaunchKernelGGL(node_interp_kernel, dim3(nn, 2), dim3(256), shi, s, dgl, cr, cc, piv.p, Cr.p, Cc.p,
+                       Ub.p + uv_base[l], Vb.p + uv_base[l], dpar.p + nn, candr.p + cand_base[l - 1],
                        candc.p + cand_base[l - 1]);
     KERNEL_CHECK("node_interp");
     // ---- node factorizations of this level on the side stream, once the
     // interpolation matrices are in; the children's D^ come from the
     // previous launch on the same stream
     stream_after(ctx, sf, s, 1);
-    double fl = 0;
-    for (int j = 0; j < nn; ++j) {
-      const double nm = gl[j].m, kk2 = gl[j].k;
-      fl += 2.0 * nm * nm * nm + 2.0 * (3.0 * nm * nm * kk2 + 3.0 * nm * kk2 * kk2) + 2.0 * kk2 * kk2 * kk2;
-    }
-    const GNode* dch = (l < L) ? dg.p + 2 * nn : dgl;
-    if (mx <= FN) {
-      KernelTimer kt_inv("node_factor_kernel", fl, 0.0, sf);
-      hipLaunchKernelGGL(node_factor_kernel, dim3(nn), dim3(256), 0, sf, dgl, dch, l == L ? 1 : 0, 0, cr, cc, d_nodes,
-                         Ub.p + uv_base[l], Vb.p + uv_base[l], dh_child, dh_cur, ws.p, w.gen.p, (double*)nullptr,
-                         fail.p);
-      KERNEL_CHECK("node_factor");
-    } else {
-      KernelTimer kt_inv("node_inverse_kernel", fl, 0.0, sf);
-      hipLaunchKernelGGL(node_inverse_kernel, dim3(nn), dim3(256), shv, sf, dgl, dch, l == L ? 1 : 0, 0, cr, cc,
-                         d_nodes, Ub.p + uv_base[l], Vb.p + uv_base[l], dh_child, dh_cur, ws.p, w.gen.p,
-                         (double*)nullptr, fail.p);
-      KERNEL_CHECK("node_inverse");
-    }
-    // level descriptors for the apply
+    const GNode* dch = leaf ? dgl : dg.p + 2 * nn;
+    factor_launch(dgl, dch, nn, leaf ? 1 : 0, 0, cr, cc, Ub.p + uv_base[l], Vb.p + uv_base[l], (double*)nullptr,
+                  leaf ? mx : -1, l);
+    std::swap(dh_child, dh_cur);
+  }
+  // ---- root (side stream; its record was completed by the level-1 plan)
+  factor_launch(dg.p + 1, dg.p + 2, 1, 0, 1, candr.p + cand_base[0], candc.p + cand_base[0], Ub.p, Vb.p, w.groot.p,
+                -1, 0);
+  stream_after(ctx, s, sf, 2);
+  // ---- read back the node records, the generator count and the flags
+  int64_t hcnt[2];
+  int hf[4];
+  HIP_CHECK(hipMemcpyAsync(hG, dg.p, sizeof(GNode) * (size_t)(int64_t(2) << L), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(hcnt, cnt.p, sizeof hcnt, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(hf, fail.p, sizeof hf, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  if (hf[1]) RW_THROW(RW_ESINGULAR, "HBS node rank reached the sketch size");
+  if (hf[2]) RW_THROW(RW_ESINGULAR, "HBS generator bound exceeded");
+  if (hf[0]) RW_THROW(RW_ESINGULAR, "singular block in the GPU HBS build (" + std::to_string(hf[0]) + ")");
+  // ---- level descriptors for the apply, statistics, factor flops
+  std::vector<std::vector<int>> lev_ints(L + 1);
+  std::vector<std::vector<int64_t>> lev_offs(L + 1);
+  w.entries = 0;
+  w.max_rank = 0;
+  for (int l = L; l >= 1; --l) {
+    const int nn = 1 << l;
+    const GNode* gl = hG + nn;
     std::vector<int>& li = lev_ints[l];
     std::vector<int64_t>& lo = lev_offs[l];
     li.resize(2 * nn);
     lo.resize(4 * nn);
-    int64_t kk = 0;
+    int64_t kk = 0, off = 0;
     int max_nin = 0, max_k = 0;
-    for (int j = 0; j < nn; ++j) {
-      li[j] = gl[j].m;
-      li[nn + j] = gl[j].k;
-      lo[j] = gl[j].cand_off;
-      lo[nn + j] = kk;
-      kk += gl[j].k;
-      lo[2 * nn + j] = gl[j].up_off;
-      lo[3 * nn + j] = gl[j].e_off;
-      max_nin = std::max(max_nin, gl[j].m);
-      max_k = std::max(max_k, gl[j].k);
-    }
+    double fl = 0.0;
     HbsLevelDev& d = w.lev[l];
+    for (int j = 0; j < nn; ++j) {
+      const GNode& g = gl[j];
+      li[j] = g.m;
+      li[nn + j] = g.k;
+      lo[j] = g.cand_off;
+      lo[nn + j] = kk;
+      kk += g.k;
+      off += g.m;
+      lo[2 * nn + j] = g.up_off;
+      lo[3 * nn + j] = g.e_off;
+      max_nin = std::max(max_nin, g.m);
+      max_k = std::max(max_k, g.k);
+      d.up_entries += (int64_t)(g.k + g.m) * g.m;
+      d.e_entries += (int64_t)g.m * g.k;
+      w.entries += 2 * (int64_t)g.m * g.k + (int64_t)g.m * g.m;
+      const double nm = g.m, kk2 = g.k;
+      fl += 2.0 * nm * nm * nm + 2.0 * (3.0 * nm * nm * kk2 + 3.0 * nm * kk2 * kk2) + 2.0 * kk2 * kk2 * kk2;
+    }
+    w.max_rank = std::max(w.max_rank, max_k);
     d.nnodes = nn;
     d.max_nin = max_nin;
     d.max_k = max_k;
     d.S = off;
     d.K = kk;
-    for (int j = 0; j < nn; ++j) {
-      d.up_entries += (int64_t)(gl[j].k + gl[j].m) * gl[j].m;
-      d.e_entries += (int64_t)gl[j].m * gl[j].k;
-    }
     w.S[l] = off;
     w.K[l] = kk;
-    std::swap(dh_child, dh_cur);
+    if (fac_entry[l] != SIZE_MAX && fac_entry[l] < ctx->pending.size()) ctx->pending[fac_entry[l]].flops = fl;
   }
-  // ---- root (side stream, after its record is uploaded)
-  {
-    GNode& g = G[0][0];
-    g.cand_off = 0;
-    g.k = 0;
-    g.ws_off = 0;
-    w.nroot = g.m;
-    w.S[0] = g.m;
-    hG[1] = g;
-    HIP_CHECK(hipMemcpyAsync(dg.p + 1, hG + 1, sizeof(GNode), hipMemcpyHostToDevice, s));
-    w.groot.alloc(ctx, (size_t)g.m * g.m);
-    stream_after(ctx, sf, s, 1);
-    int* cr = candr.p + cand_base[0];
-    int* cc = candc.p + cand_base[0];
-    if (g.m <= FN) {
-      const double nm = g.m;
-      KernelTimer kt_root("node_factor_kernel", 2.0 * nm * nm * nm, 0.0, sf);
-      hipLaunchKernelGGL(node_factor_kernel, dim3(1), dim3(256), 0, sf, dg.p + 1, dg.p + 2, 0, 1, cr, cc, d_nodes,
-                         Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, w.groot.p, fail.p);
-    } else
-      hipLaunchKernelGGL(node_inverse_kernel, dim3(1), dim3(256), shv, sf, dg.p + 1, dg.p + 2, 0, 1, cr, cc, d_nodes,
-                         Ub.p, Vb.p, dh_child, dh_cur, ws.p, w.gen.p, w.groot.p, fail.p);
-    KERNEL_CHECK("node_inverse_root");
-    stream_after(ctx, s, sf, 2);
-    w.entries += (int64_t)g.m * g.m;
-    int hf[4];
-    fail.download(hf, 4, s);
-    HIP_CHECK(hipStreamSynchronize(s));
-    if (hf[0]) RW_THROW(RW_ESINGULAR, "singular block in the GPU HBS build (" + std::to_string(hf[0]) + ")");
-  }
+  w.nroot = hG[1].m;
+  w.S[0] = hG[1].m;
+  w.entries += (int64_t)w.nroot * w.nroot;
+  if (fac_entry[0] != SIZE_MAX && fac_entry[0] < ctx->pending.size())
+    ctx->pending[fac_entry[0]].flops = 2.0 * (double)w.nroot * w.nroot * w.nroot;
   // ---- pack level descriptors
   std::vector<int> ints;
   std::vector<int64_t> offs;

@@ -391,53 +391,61 @@ __global__ void rowid_unit_rows_kernel(int k, const int* __restrict__ J, const i
 }
 
 // ================================================================ A^T B
+// Split over row ranges (one workgroup each); per 48 x 48 output tile every
+// thread keeps a 3 x 3 block (rows ti + 16 x, columns tj + 16 y) in
+// registers while chunks of 32 rows of A and B pass through LDS.
 constexpr int TN_CH = 32;  // rows per LDS chunk
-constexpr int TN_ACC = 32; // outputs per thread per pass
+constexpr int TN_T = 48;   // output tile edge
 
 __global__ __launch_bounds__(256) void gemm_tn_part_kernel(const double* __restrict__ A, int64_t lda,
                                                            const double* __restrict__ B, int64_t ldb, int64_t M,
                                                            int ka, int kb, int64_t rows_per,
                                                            double* __restrict__ part) {
-  extern __shared__ double sm[];
-  double* As = sm;                 // TN_CH x ka
-  double* Bs = sm + TN_CH * ka;    // TN_CH x kb
+  __shared__ double As[TN_CH][TN_T + 1];
+  __shared__ double Bs[TN_CH][TN_T + 1];
+  const int tid = threadIdx.x, ti = tid & 15, tj = tid >> 4;
   const int64_t e0 = (int64_t)blockIdx.x * rows_per;
   const int64_t e1 = min(M, e0 + rows_per);
   const int nout = ka * kb;
   double* pb = part + (int64_t)blockIdx.x * nout;
-  for (int base = 0; base < nout; base += 256 * TN_ACC) {
-    double acc[TN_ACC];
+  for (int ia0 = 0; ia0 < ka; ia0 += TN_T)
+    for (int ib0 = 0; ib0 < kb; ib0 += TN_T) {
+      double acc[3][3];
 #pragma unroll
-    for (int u = 0; u < TN_ACC; ++u) acc[u] = 0.0;
-    for (int64_t c0 = e0; c0 < e1; c0 += TN_CH) {
-      const int cnt = (int)min<int64_t>(TN_CH, e1 - c0);
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < TN_CH * ka; idx += 256) {
-        const int col = idx / TN_CH, r = idx - col * TN_CH;
-        As[r * ka + col] = (r < cnt) ? A[c0 + r + (int64_t)col * lda] : 0.0;
-      }
-      for (int idx = threadIdx.x; idx < TN_CH * kb; idx += 256) {
-        const int col = idx / TN_CH, r = idx - col * TN_CH;
-        Bs[r * kb + col] = (r < cnt) ? B[c0 + r + (int64_t)col * ldb] : 0.0;
-      }
-      __syncthreads();
+      for (int x = 0; x < 3; ++x)
 #pragma unroll
-      for (int u = 0; u < TN_ACC; ++u) {
-        const int o = base + u * 256 + threadIdx.x;
-        if (o < nout) {
-          const int ia = o % ka, ib = o / ka;
-          double s = acc[u];
-          for (int r = 0; r < TN_CH; ++r) s += As[r * ka + ia] * Bs[r * kb + ib];
-          acc[u] = s;
+        for (int y = 0; y < 3; ++y) acc[x][y] = 0.0;
+      for (int64_t c0 = e0; c0 < e1; c0 += TN_CH) {
+        const int cnt = (int)min<int64_t>(TN_CH, e1 - c0);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < TN_CH * TN_T / 256; ++u) {
+          const int idx = tid + 256 * u, r = idx & (TN_CH - 1), c = idx / TN_CH;
+          As[r][c] = (r < cnt && ia0 + c < ka) ? A[c0 + r + (int64_t)(ia0 + c) * lda] : 0.0;
+          Bs[r][c] = (r < cnt && ib0 + c < kb) ? B[c0 + r + (int64_t)(ib0 + c) * ldb] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int r = 0; r < TN_CH; ++r) {
+          double av[3], bv[3];
+#pragma unroll
+          for (int x = 0; x < 3; ++x) av[x] = As[r][ti + 16 * x];
+#pragma unroll
+          for (int y = 0; y < 3; ++y) bv[y] = Bs[r][tj + 16 * y];
+#pragma unroll
+          for (int x = 0; x < 3; ++x)
+#pragma unroll
+            for (int y = 0; y < 3; ++y) acc[x][y] += av[x] * bv[y];
         }
       }
-    }
 #pragma unroll
-    for (int u = 0; u < TN_ACC; ++u) {
-      const int o = base + u * 256 + threadIdx.x;
-      if (o < nout) pb[o] = acc[u];
+      for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y) {
+          const int ia = ia0 + ti + 16 * x, ib = ib0 + tj + 16 * y;
+          if (ia < ka && ib < kb) pb[ia + ib * ka] = acc[x][y];
+        }
     }
-  }
 }
 
 __global__ __launch_bounds__(256) void gemm_tn_reduce_kernel(const double* __restrict__ part, int nparts, int ka,
@@ -452,7 +460,7 @@ __global__ __launch_bounds__(256) void gemm_tn_reduce_kernel(const double* __res
 }
 
 int gemm_tn_nparts(int64_t M) {
-  int64_t p = (M + 511) / 512;
+  int64_t p = (M + 255) / 256;
   return (int)(p < 1 ? 1 : (p > 256 ? 256 : p));
 }
 
@@ -878,9 +886,7 @@ void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, 
   if (ka <= 0 || kb <= 0) return;
   const int np = gemm_tn_nparts(M);
   const int64_t rows_per = (M + np - 1) / np;
-  const size_t sh = sizeof(double) * TN_CH * (ka + kb);
-  HIP_CHECK(hipFuncSetAttribute((const void*)gemm_tn_part_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
-  hipLaunchKernelGGL(gemm_tn_part_kernel, dim3(np), dim3(256), sh, s, A, lda, B, ldb, M, ka, kb, rows_per, part);
+  hipLaunchKernelGGL(gemm_tn_part_kernel, dim3(np), dim3(256), 0, s, A, lda, B, ldb, M, ka, kb, rows_per, part);
   KERNEL_CHECK("gemm_tn_part");
   hipLaunchKernelGGL(gemm_tn_reduce_kernel, dim3(blocks((int64_t)ka * kb)), dim3(256), 0, s, part, np, ka, kb, C, ldc,
                      add_identity ? 1 : 0);

@@ -121,6 +121,79 @@ __global__ __launch_bounds__(256) void flux_kernel(const NodeRec* __restrict__ n
   if (threadIdx.x == 0) sN[c] = red[0];
 }
 
+// One right-hand side: the sources packed as (x, y, n_x w / pi, n_y w / pi,
+// tau_x, tau_y, 0, 0), so that a source index that is the same in every lane
+// turns into scalar loads of one 64-byte record per source: the kernel's
+// inner loop then reads no LDS and runs at the FP64 instruction rate.
+constexpr int RPK = 8;   // doubles per packed source
+__global__ __launch_bounds__(256) void resid_pack_kernel(const NodeRec* __restrict__ nd, int64_t n,
+                                                         const double* __restrict__ tau, double* __restrict__ pk) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  const NodeRec q = nd[j];
+  double* o = pk + j * RPK;
+  o[0] = q.x;
+  o[1] = q.y;
+  o[2] = q.nx * q.w * kInvPi;
+  o[3] = q.ny * q.w * kInvPi;
+  o[4] = tau[2 * j];
+  o[5] = tau[2 * j + 1];
+  o[6] = 0.0;
+  o[7] = 0.0;
+}
+
+// grid (ceil(n / 256), 1, nsplit): thread = target, sources of the split in
+// order (the same index in every lane).
+__global__ __launch_bounds__(256) void resid_scalar_kernel(const NodeRec* __restrict__ nd, int64_t n,
+                                                           const double* __restrict__ pk, int nsplit,
+                                                           double* __restrict__ part) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int z = blockIdx.z;
+  const int64_t chunk = (n + nsplit - 1) / nsplit;
+  const int64_t s0 = z * chunk, s1 = min(n, s0 + chunk);
+  double xi = 0, yi = 0;
+  if (t < n) { xi = nd[t].x; yi = nd[t].y; }
+  double ax = 0.0, ay = 0.0;
+  // r = 0 only on the diagonal, where the clamp keeps 1 / r^4 finite and
+  // the zero r . n makes the term vanish
+  auto term = [&](const double* q, double rx, double ry, double inv) {
+    const double cf = (rx * q[2] + ry * q[3]) * inv * inv;
+    const double d = cf * (rx * q[4] + ry * q[5]);
+    ax += d * rx;
+    ay += d * ry;
+  };
+  int64_t sj = s0;
+  // four sources per reciprocal: 1 / (a b c d) and products give the four
+  // 1 / r^2 (r^2 within [1e-150, ~1e2], so the product stays in range)
+  for (; sj + 4 <= s1; sj += 4) {
+    const double* q0 = pk + sj * RPK;
+    const double* q1 = q0 + RPK;
+    const double* q2 = q1 + RPK;
+    const double* q3 = q2 + RPK;
+    const double x0 = xi - q0[0], y0 = yi - q0[1], x1 = xi - q1[0], y1 = yi - q1[1];
+    const double x2 = xi - q2[0], y2 = yi - q2[1], x3 = xi - q3[0], y3 = yi - q3[1];
+    const double a = fmax(x0 * x0 + y0 * y0, 1e-150), b = fmax(x1 * x1 + y1 * y1, 1e-150);
+    const double c = fmax(x2 * x2 + y2 * y2, 1e-150), d = fmax(x3 * x3 + y3 * y3, 1e-150);
+    const double ab = a * b, cd = c * d;
+    const double y = rcp_nr2(ab * cd);
+    const double yab = y * cd, ycd = y * ab;
+    term(q0, x0, y0, b * yab);
+    term(q1, x1, y1, a * yab);
+    term(q2, x2, y2, d * ycd);
+    term(q3, x3, y3, c * ycd);
+  }
+  for (; sj < s1; ++sj) {
+    const double* q = pk + sj * RPK;
+    const double rx = xi - q[0], ry = yi - q[1];
+    term(q, rx, ry, rcp_nr2(fmax(rx * rx + ry * ry, 1e-150)));
+  }
+  if (t < n) {
+    double* p = part + (int64_t)z * 2 * n;
+    p[2 * t] = ax;
+    p[2 * t + 1] = ay;
+  }
+}
+
 __global__ __launch_bounds__(256) void resid_finalize_kernel(const NodeRec* __restrict__ nd, int64_t n,
                                                              const double* __restrict__ g,
                                                              const double* __restrict__ tau, int nrhs, int nsplit,
@@ -445,7 +518,7 @@ inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) /
 }  // namespace
 
 size_t resid_part_doubles(int64_t n, int nrhs) {
-  return (size_t)resid_splits(n, nrhs) * nrhs * 2 * n + 64 + nrhs;
+  return (size_t)resid_splits(n, nrhs) * nrhs * 2 * n + 64 + nrhs + (nrhs == 1 ? (size_t)RPK * n : 0);
 }
 
 void launch_residual(const NodeRec* nodes, int64_t n, const double* g, const double* tau, double* r, int nrhs,
@@ -457,10 +530,11 @@ void launch_residual(const NodeRec* nodes, int64_t n, const double* g, const dou
   // block and right-hand side; the division counts as one flop
   {
     KernelTimer kt("resid_tiles_kernel", (double)n * n * (12.0 + 6.0 * nrhs), 0.0);
-    if (nrhs == 1)
-      hipLaunchKernelGGL(resid_tiles_kernel<1>, dim3(blocks(n, RT), 1, ns), dim3(RT), 0, s, nodes, n, tau, nrhs, ns,
-                         part);
-    else
+    if (nrhs == 1) {
+      double* pk = sN + 64 + nrhs;
+      hipLaunchKernelGGL(resid_pack_kernel, dim3(blocks(n)), dim3(256), 0, s, nodes, n, tau, pk);
+      hipLaunchKernelGGL(resid_scalar_kernel, dim3(blocks(n), 1, ns), dim3(256), 0, s, nodes, n, pk, ns, part);
+    } else
       hipLaunchKernelGGL(resid_tiles_kernel<RRB>, dim3(blocks(n, RT), (nrhs + RRB - 1) / RRB, ns), dim3(RT), 0, s,
                          nodes, n, tau, nrhs, ns, part);
     KERNEL_CHECK("resid_tiles");
