@@ -48,6 +48,39 @@ KERNEL_BOUND = {
 }
 
 
+# HBM traffic per launch from two rocprofv3 counter passes of this bench
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged over the kernel's
+# dispatches), each scaled by what the counter reads for a plain 1 GiB device
+# copy.  Valid only while the kernel's sources hash to the value they had when
+# the counters were taken; otherwise the roofline reports traffic as null.
+MEASURED_TRAFFIC = {
+    "node_factor_bordered_kernel": {
+        "fetch_kib": 2630.6, "write_kib": 6428.7, "fetch_scale": 1.9999, "write_scale": 1.0000,
+        "sources": ["paper_2108_07205_amd/csrc/hbs_gpu.hip", "paper_2108_07205_amd/csrc/dev_gj.h",
+                    "paper_2108_07205_amd/csrc/dev_reduce.h", "paper_2108_07205_amd/csrc/hbs_dev.h",
+                    "paper_2108_07205_amd/csrc/common.h"],
+        "sha256": "015b8537e5558de6d7357ee07135fd790e91a7097509785fd7ea81d61ae47aa6",
+        "summary": "profiles/star1024_refine16x4_hbm_traffic.md",
+    },
+}
+
+
+def measured_traffic(kernel: str):
+    """Scaled HBM bytes per launch of `kernel`, or None when no counters were
+    taken for it or its sources changed since."""
+    import hashlib
+    m = MEASURED_TRAFFIC.get(kernel)
+    if not m:
+        return None
+    h = hashlib.sha256()
+    for f in m["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != m["sha256"]:
+        return None
+    return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
+
+
 def cpu_baseline(budget_s: float = 20.0) -> dict:
     """The FP64 oracle (dense assembly + LU, as it stands) on the host cores,
     on a bounded sample of one config-2 refined-wall solve, extrapolated to
@@ -116,7 +149,8 @@ def roofline(phases: dict):
     ph = kern[name]
     bound, peak, unit, ach = rate(name, ph)
     return name, {"kernel": name, "bound": bound, "achieved": ach, "peak": peak, "unit": unit,
-                  "frac": (ach / peak) if ach is not None else None, "traffic": None,
+                  "frac": (ach / peak) if ach is not None else None, "traffic": measured_traffic(name),
+                  "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                   "avg_launch_ms": ph["ms"] / max(1, ph["calls"]), "launches": ph["calls"],
                   "algorithmic_per_launch": (ph["bytes"] if bound == "hbm" else ph["flops"]) / max(1, ph["calls"])}, table
 
