@@ -236,7 +236,6 @@ __global__ __launch_bounds__(256) void node_sketch_mfma_kernel(const GNode* __re
   if (g.m <= mlo || g.m > mhi) return;   // node handled by another launch
   const int side = blockIdx.y, m = g.m;
   const int z = blockIdx.z, nz = gridDim.z;
-  const int64_t j_lo = (z * N) / nz, j_hi = ((z + 1) * N) / nz;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i16 = lane & 15, k4 = lane >> 4;
   const int* cand = (side == 0 ? candr : candc) + g.cand_off;
   double* S = (side == 0 ? Sr : Sc) + g.cand_off * SK_R + (int64_t)z * part_stride;
@@ -254,7 +253,6 @@ __global__ __launch_bounds__(256) void node_sketch_mfma_kernel(const GNode* __re
 #pragma unroll
     for (int cb = 0; cb < 6; ++cb) acc[u][cb] = (double4_t){0.0, 0.0, 0.0, 0.0};
   const int nrb = (m + 15) >> 4;
-  int buf_any_far = 0;
   // one chunk of 16 entity columns: kind 0 = near node dofs (nlist[c0 / 2 ..]),
   // 1 = proxy columns c0 .., 2 = the nullspace column
   auto chunk = [&](int kind, int c0, int ncols) {
@@ -360,9 +358,13 @@ __global__ __launch_bounds__(256) void node_sketch_mfma_kernel(const GNode* __re
     }
     __syncthreads();
   };
-  // ---- near nodes of this split's node range, pass by pass
-  for (int64_t p0 = j_lo; p0 < j_hi; p0 += NSK_PASS) {
-    const int64_t p1 = min(j_hi, p0 + NSK_PASS);
+  // ---- near nodes of the whole arc, pass by pass; the 16-column chunks of
+  // each pass's near list, then the proxy chunks and the nullspace column,
+  // are dealt round-robin over the splits, so every split does the same work
+  int chunk_no = 0;   // running chunk number (near chunks of all passes, then the far chunks)
+  int farl_any = 0;
+  for (int64_t p0 = 0; p0 < N; p0 += NSK_PASS) {
+    const int64_t p1 = min(N, p0 + NSK_PASS);
     const int per = NSK_PASS / 256;
     int cntl = 0, farl = 0;
     int loc[NSK_PASS / 256];
@@ -375,38 +377,35 @@ __global__ __launch_bounds__(256) void node_sketch_mfma_kernel(const GNode* __re
         if (dx * dx + dy * dy < rp2) { loc[u] = 1; ++cntl; } else farl = 1;
       }
     }
-    wsum[tid + 1] = cntl;
-    buf_any_far |= __syncthreads_or(farl);
-    if (tid == 0) {
-      wsum[0] = 0;
-      for (int u = 1; u <= 256; ++u) wsum[u] += wsum[u - 1];
+    // exclusive prefix of the per-thread counts: wave scan, then the 4 wave totals
+    int incl = cntl;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o);
+      if (lane >= o) incl += v;
     }
-    __syncthreads();
-    int o = wsum[tid];
+    if (lane == 63) wsum[wave] = incl;
+    farl_any |= __syncthreads_or(farl);
+    int wbase = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < 4; ++w2) wbase += (w2 < wave) ? wsum[w2] : 0;
+    const int nnear = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    int o = wbase + incl - cntl;
 #pragma unroll
     for (int u = 0; u < NSK_PASS / 256; ++u)
       if (loc[u]) nlist[o++] = (int)(p0 + tid * per + u);
-    const int nnear = wsum[256];
     __syncthreads();
-    for (int c0 = 0; c0 < 2 * nnear; c0 += 16) chunk(0, c0, min(16, 2 * nnear - c0));
+    for (int c0 = 0; c0 < 2 * nnear; c0 += 16, ++chunk_no)
+      if (chunk_no % nz == z) chunk(0, c0, min(16, 2 * nnear - c0));
+    __syncthreads();   // nlist and wsum are rewritten by the next pass
   }
   // ---- proxies and the nullspace column stand for the far nodes, if any
-  // (the last split; it checks every node for one outside the circle)
-  if (z == nz - 1) {
-    int farl = 0;
-    for (int64_t j = tid; j < N && !farl; j += 256)
-      if (!(j >= g.n0 && j < g.n1)) {
-        const double dx = nd[j].x - g.cx, dy = nd[j].y - g.cy;
-        farl = dx * dx + dy * dy >= rp2;
-      }
-    buf_any_far = __syncthreads_or(farl);
-  } else {
-    buf_any_far = 0;
-  }
-  if (buf_any_far) {
+  if (farl_any) {
     const int npc = SK_NP * (side == 0 ? 4 : 2);
-    for (int c0 = 0; c0 < npc; c0 += 16) chunk(1, c0, min(16, npc - c0));
-    chunk(2, 0, 1);
+    for (int c0 = 0; c0 < npc; c0 += 16, ++chunk_no)
+      if (chunk_no % nz == z) chunk(1, c0, min(16, npc - c0));
+    if (chunk_no % nz == z) chunk(2, 0, 1);
+    ++chunk_no;
   }
   // ---- write the sketch rows (m x SK_R, row-major)
 #pragma unroll
@@ -423,13 +422,17 @@ __global__ __launch_bounds__(256) void node_sketch_mfma_kernel(const GNode* __re
   }
 }
 
-__global__ __launch_bounds__(256) void node_sketch_sum_kernel(const double* __restrict__ part, int nsplit,
-                                                              int64_t len, int64_t stride, double* __restrict__ S) {
+// grid (ceil(len / 256), 2): y = 0 sums the row-sketch partials, y = 1 the column ones.
+__global__ __launch_bounds__(256) void node_sketch_sum_kernel(const double* __restrict__ part_r,
+                                                              const double* __restrict__ part_c, int nsplit,
+                                                              int64_t len, int64_t stride, double* __restrict__ Sr,
+                                                              double* __restrict__ Sc) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= len) return;
+  const double* part = blockIdx.y ? part_c : part_r;
   double v = 0.0;
   for (int z = 0; z < nsplit; ++z) v += part[i + z * stride];
-  S[i] = v;
+  (blockIdx.y ? Sc : Sr)[i] = v;
 }
 
 // ---------------------------------------------------------------- 2. row ID
@@ -451,13 +454,19 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
 // The pivot keys and the pivot vector alternate between two LDS slots, so a
 // step needs two barriers: a slot is written again two steps later, after
 // every thread has passed the first barrier of the step in between.
-__global__ __launch_bounds__(512) void node_id_kernel(const GNode* __restrict__ gn, const double* __restrict__ Sr,
-                                                      const double* __restrict__ Sc, double tol2,
-                                                      int* __restrict__ piv, double* __restrict__ Cr,
-                                                      double* __restrict__ Cc, int* __restrict__ info) {
+// NT threads hold up to NT / 2 rows; nodes outside (mlo, mhi] are left to
+// the launch of the other size.
+template <int NT>
+__global__ __launch_bounds__(NT) void node_id_kernel(const GNode* __restrict__ gn, const double* __restrict__ Sr,
+                                                     const double* __restrict__ Sc, double tol2,
+                                                     int* __restrict__ piv, double* __restrict__ Cr,
+                                                     double* __restrict__ Cc, int* __restrict__ info, int mlo,
+                                                     int mhi) {
+  constexpr int NW = NT / 64;
   __shared__ double q[2][SK_R];
-  __shared__ double rv[2][8];
+  __shared__ double rv[2][NW];
   const GNode g = gn[blockIdx.x];
+  if (g.m <= mlo || g.m > mhi) return;
   const int side = blockIdx.y;
   const int m = g.m, tid = threadIdx.x;
   const int i = tid >> 1, h = tid & 1;
@@ -488,7 +497,7 @@ __global__ __launch_bounds__(512) void node_id_kernel(const GNode* __restrict__ 
     __syncthreads();
     double v = rv[b][0];
 #pragma unroll
-    for (int w = 1; w < 8; ++w) v = fmax(v, rv[b][w]);
+    for (int w = 1; w < NW; ++w) v = fmax(v, rv[b][w]);
     const int p = v > 0.0 ? pivot_key_index<9>(v) : -1;
     if (step == 0) n0 = v;
     if (rank < 0 && !(v > tol2 * n0)) rank = step;
@@ -598,13 +607,15 @@ __global__ __launch_bounds__(64) void level_plan_kernel(GNode* __restrict__ gl, 
 // rows are staged in LDS, its inverse is formed there by forward
 // substitution (thread t: column t), and the product is taken in items of
 // one row of C times four columns of the inverse.
-constexpr int INTERP_NC = 4;
-__global__ __launch_bounds__(256) void node_interp_kernel(const GNode* __restrict__ gn, const int* __restrict__ candr,
-                                                          const int* __restrict__ candc, const int* __restrict__ piv,
-                                                          const double* __restrict__ Cr, const double* __restrict__ Cc,
-                                                          double* __restrict__ U, double* __restrict__ V,
-                                                          const int64_t* __restrict__ par_pos,
-                                                          int* __restrict__ pcandr, int* __restrict__ pcandc) {
+__global__ __launch_bounds__(256) void node_interp_kernel(const GNode* __restrict__ gn,
+                                                              const int* __restrict__ candr,
+                                                              const int* __restrict__ candc,
+                                                              const int* __restrict__ piv,
+                                                              const double* __restrict__ Cr,
+                                                              const double* __restrict__ Cc, double* __restrict__ U,
+                                                              double* __restrict__ V,
+                                                              const int64_t* __restrict__ par_pos,
+                                                              int* __restrict__ pcandr, int* __restrict__ pcandc) {
   extern __shared__ double lds[];  // cj[s * k + u] = C_J(s, u); iv[u * k + t] = Inv(u, t)
   const GNode g = gn[blockIdx.x];
   const int side = blockIdx.y;
@@ -630,22 +641,23 @@ __global__ __launch_bounds__(256) void node_interp_kernel(const GNode* __restric
     }
   }
   __syncthreads();
-  const int nb = (k + INTERP_NC - 1) / INTERP_NC;
+  constexpr int NCB = 4;
+  const int nb = (k + NCB - 1) / NCB;
   for (int item = tid; item < m * nb; item += 256) {
-    const int i = item % m, t0 = (item / m) * INTERP_NC;
+    const int i = item % m, t0 = (item / m) * NCB;
     const double* ci = C + (int64_t)i * SK_KCAP;
-    double v[INTERP_NC];
+    double v[NCB];
 #pragma unroll
-    for (int c = 0; c < INTERP_NC; ++c) v[c] = 0.0;
+    for (int c = 0; c < NCB; ++c) v[c] = 0.0;
     for (int srow = t0; srow < k; ++srow) {
       const double a = ci[srow];
       const double* ir = iv + srow * k + t0;
 #pragma unroll
-      for (int c = 0; c < INTERP_NC; ++c)
+      for (int c = 0; c < NCB; ++c)
         if (t0 + c < k) v[c] += a * ir[c];
     }
 #pragma unroll
-    for (int c = 0; c < INTERP_NC; ++c)
+    for (int c = 0; c < NCB; ++c)
       if (t0 + c < k) P[i + (int64_t)(t0 + c) * m] = v[c];
   }
   __syncthreads();
@@ -1749,9 +1761,8 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     {
       KernelTimer kt("node_sketch_kernel", 0.0, 0.0);
       const dim3 grid(nn, 2, nsplit);
-      const bool direct = nsplit == 1;
-      double* outr = direct ? Sr.p : part_r.p;
-      double* outc = direct ? Sc.p : part_c.p;
+      double* outr = part_r.p;
+      double* outc = part_c.p;
       const uint64_t sd = seed + 7919ull * l;
       if (leaf && mx > 192) {
         hipLaunchKernelGGL(node_sketch_kernel, grid, dim3(256), 0, s, dgl, cr, cc, d_nodes, N, sd, len, part_r.p,
@@ -1765,17 +1776,19 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
                              outr, outc, 128, 192);
       }
       KERNEL_CHECK("node_sketch");
-      if (!direct || (leaf && mx > 192)) {
-        const int nz = nsplit;
-        hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len)), dim3(256), 0, s, part_r.p, nz, len, len, Sr.p);
-        hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len)), dim3(256), 0, s, part_c.p, nz, len, len, Sc.p);
-        KERNEL_CHECK("node_sketch_sum");
-      }
+      hipLaunchKernelGGL(node_sketch_sum_kernel, dim3(nblk(len), 2), dim3(256), 0, s, part_r.p, part_c.p, nsplit, len,
+                         len, Sr.p, Sc.p);
+      KERNEL_CHECK("node_sketch_sum");
     }
     {
+      // nodes of at most 128 candidates on 256 threads (two per row), larger ones on 512
       KernelTimer kt_id("node_id_kernel", 0.0, 0.0);
-      hipLaunchKernelGGL(node_id_kernel, dim3(nn, 2), dim3(512), 0, s, dgl, Sr.p, Sc.p, tol * tol, piv.p, Cr.p, Cc.p,
-                         info.p);
+      if (!leaf || mx <= 128)
+        hipLaunchKernelGGL(node_id_kernel<256>, dim3(nn, 2), dim3(256), 0, s, dgl, Sr.p, Sc.p, tol * tol, piv.p, Cr.p,
+                           Cc.p, info.p, 0, 128);
+      if (!leaf || mx > 128)
+        hipLaunchKernelGGL(node_id_kernel<512>, dim3(nn, 2), dim3(512), 0, s, dgl, Sr.p, Sc.p, tol * tol, piv.p, Cr.p,
+                           Cc.p, info.p, 128, 256);
       KERNEL_CHECK("node_id");
     }
     hipLaunchKernelGGL(level_plan_kernel, dim3(1), dim3(64), 0, s, dgl, nn, info.p, dg.p + nn / 2, dpar.p + nn, cnt.p,

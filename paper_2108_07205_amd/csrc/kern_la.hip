@@ -278,11 +278,16 @@ __global__ __launch_bounds__(SEL_ROWS) void rowid_select_kernel(const double* __
 // Orthonormal rows Q (k x nc) of Y(J, :) in pivot order: classical
 // Gram-Schmidt with one reorthogonalization, one wave (thread u computes the
 // coefficient on q_u, thread c updates column c).  k <= 64.
+// The selected rows J (idx[0..*kp)) are copied to Jout and orthonormalized
+// in order into Q (k x nc, row-major); k is read on the device.
 __global__ __launch_bounds__(64) void rowid_basis_kernel(const double* __restrict__ Y, int nc,
-                                                         const int* __restrict__ J, int k, double* __restrict__ Q) {
+                                                         const int* __restrict__ J, const int* __restrict__ kp,
+                                                         int* __restrict__ Jout, double* __restrict__ Q) {
   __shared__ double qs[64][SEL_NC + 1];
   __shared__ double v[SEL_NC], d[64];
   const int c = threadIdx.x;
+  const int k = *kp;
+  if (c < k) Jout[c] = J[c];
   for (int s = 0; s < k; ++s) {
     if (c < nc) v[c] = Y[(int64_t)J[s] * nc + c];
     __syncthreads();
@@ -314,10 +319,12 @@ __global__ __launch_bounds__(64) void rowid_basis_kernel(const double* __restric
 // C(i, t) = <y_i, q_t> (row-major, ld kmax) for every row, and the largest
 // squared residual |y_i - C_i Q|^2 (ordered bits) in *maxres.
 __global__ __launch_bounds__(256) void rowid_coef_kernel(const double* __restrict__ Y, int64_t m, int nc,
-                                                         const double* __restrict__ Q, int k, int kmax,
-                                                         double* __restrict__ C,
+                                                         const double* __restrict__ Q, const int* __restrict__ kp,
+                                                         int kmax, double* __restrict__ C,
                                                          unsigned long long* __restrict__ maxres) {
   extern __shared__ double qs[];  // k x nc
+  const int k = *kp;
+  if (k == 0) return;
   for (int u = threadIdx.x; u < k * nc; u += 256) qs[u] = Q[u];
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -810,11 +817,10 @@ static int rowid_cooperative(rw_ctx* ctx, const double* Y, int64_t m, int ncols,
   return k;
 }
 
-int launch_rowid(rw_ctx* ctx, const double* Y, int64_t m, int ncols, double tol, int kmax, int* J, double* C,
-                 void* work, hipStream_t s) {
-  if (m <= 0) return 0;
+bool launch_rowid_enqueue(rw_ctx* ctx, const double* Y, int64_t m, int ncols, double tol, int kmax, int* J,
+                          double* C, void* work, int* res_k, unsigned long long* res_m, hipStream_t s) {
   const int64_t nb0 = (m + SEL_ROWS - 1) / SEL_ROWS;
-  if (ncols > SEL_NC || kmax > 64 || nb0 > 1024) return rowid_cooperative(ctx, Y, m, ncols, tol, kmax, J, C, work, s);
+  if (m <= 0 || ncols > SEL_NC || kmax > 64 || nb0 > 1024) return false;
   // the selection buffers sit behind the cooperative kernel's share of `work`
   char* w = (char*)work + (rowid_work_bytes(m, ncols, kmax, std::max(256, ctx->n_cu)) - rowid_sel_bytes(m, ncols, kmax));
   w = (char*)(((uintptr_t)w + 255) & ~(uintptr_t)255);
@@ -822,45 +828,62 @@ int launch_rowid(rw_ctx* ctx, const double* Y, int64_t m, int ncols, double tol,
   int* idx[2] = {(int*)(dmax + 2), (int*)(dmax + 2) + nb0 * kmax};
   int* cnt[2] = {idx[1] + nb0 * kmax, idx[1] + nb0 * kmax + nb0};
   double* Q = (double*)(((uintptr_t)(cnt[1] + nb0) + 15) & ~(uintptr_t)15);
-  int k = 0;
-  {
-    KernelTimer kt("rowid_select_kernel", 0.0, 0.0);
-    HIP_CHECK(hipMemsetAsync(dmax, 0, 2 * sizeof(unsigned long long), s));
-    hipLaunchKernelGGL(rowid_maxnorm_kernel, dim3((unsigned)std::min<int64_t>(1024, blocks(m))), dim3(256), 0, s, Y, m,
-                       ncols, dmax);
-    KERNEL_CHECK("rowid_maxnorm");
-    int64_t nb = nb0;
-    int cur = 0;
-    hipLaunchKernelGGL(rowid_select_kernel, dim3((unsigned)nb), dim3(SEL_ROWS), 0, s, Y, m, ncols, (const int*)nullptr,
-                       (const int*)nullptr, 0, kmax, tol * tol, dmax, idx[cur], cnt[cur]);
+  KernelTimer kt("rowid_select_kernel", 0.0, 0.0);
+  HIP_CHECK(hipMemsetAsync(dmax, 0, 2 * sizeof(unsigned long long), s));
+  hipLaunchKernelGGL(rowid_maxnorm_kernel, dim3((unsigned)std::min<int64_t>(1024, blocks(m))), dim3(256), 0, s, Y, m,
+                     ncols, dmax);
+  KERNEL_CHECK("rowid_maxnorm");
+  int64_t nb = nb0;
+  int cur = 0;
+  hipLaunchKernelGGL(rowid_select_kernel, dim3((unsigned)nb), dim3(SEL_ROWS), 0, s, Y, m, ncols, (const int*)nullptr,
+                     (const int*)nullptr, 0, kmax, tol * tol, dmax, idx[cur], cnt[cur]);
+  KERNEL_CHECK("rowid_select");
+  while (nb > 1) {
+    const int64_t nb2 = (nb * kmax + SEL_ROWS - 1) / SEL_ROWS;
+    hipLaunchKernelGGL(rowid_select_kernel, dim3((unsigned)nb2), dim3(SEL_ROWS), 0, s, Y, m, ncols, idx[cur], cnt[cur],
+                       (int)nb, kmax, tol * tol, dmax, idx[1 - cur], cnt[1 - cur]);
     KERNEL_CHECK("rowid_select");
-    while (nb > 1) {
-      const int64_t nb2 = (nb * kmax + SEL_ROWS - 1) / SEL_ROWS;
-      hipLaunchKernelGGL(rowid_select_kernel, dim3((unsigned)nb2), dim3(SEL_ROWS), 0, s, Y, m, ncols, idx[cur], cnt[cur],
-                         (int)nb, kmax, tol * tol, dmax, idx[1 - cur], cnt[1 - cur]);
-      KERNEL_CHECK("rowid_select");
-      cur = 1 - cur;
-      nb = nb2;
-    }
-    HIP_CHECK(hipMemcpyAsync(&k, cnt[cur], sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
-    if (k > 0) {
-      HIP_CHECK(hipMemcpyAsync(J, idx[cur], sizeof(int) * k, hipMemcpyDeviceToDevice, s));
-      hipLaunchKernelGGL(rowid_basis_kernel, dim3(1), dim3(64), 0, s, Y, ncols, J, k, Q);
-      KERNEL_CHECK("rowid_basis");
-      hipLaunchKernelGGL(rowid_coef_kernel, dim3(blocks(m)), dim3(256), sizeof(double) * k * ncols, s, Y, m, ncols, Q,
-                         k, kmax, C, dmax + 1);
-      KERNEL_CHECK("rowid_coef");
-    }
+    cur = 1 - cur;
+    nb = nb2;
   }
-  // certificate: every row within 10 tol of span(Y(J, :)) relative to the largest row
-  unsigned long long hm[2] = {0, 0};
-  HIP_CHECK(hipMemcpyAsync(hm, dmax, sizeof(hm), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
+  // basis and coefficients read the selected count on the device
+  hipLaunchKernelGGL(rowid_basis_kernel, dim3(1), dim3(64), 0, s, Y, ncols, idx[cur], cnt[cur], J, Q);
+  KERNEL_CHECK("rowid_basis");
+  hipLaunchKernelGGL(rowid_coef_kernel, dim3(blocks(m)), dim3(256), sizeof(double) * kmax * ncols, s, Y, m, ncols, Q,
+                     cnt[cur], kmax, C, dmax + 1);
+  KERNEL_CHECK("rowid_coef");
+  HIP_CHECK(hipMemcpyAsync(res_k, cnt[cur], sizeof(int), hipMemcpyDeviceToDevice, s));
+  HIP_CHECK(hipMemcpyAsync(res_m, dmax, 2 * sizeof(unsigned long long), hipMemcpyDeviceToDevice, s));
+  return true;
+}
+
+bool rowid_certified(int k, int kmax, double tol, const unsigned long long* hm) {
+  // every row within 10 tol of span(Y(J, :)) relative to the largest row;
+  // k == kmax sends the caller to a wider sketch anyway
   const double n0 = __builtin_bit_cast(double, hm[0]), res = __builtin_bit_cast(double, hm[1]);
-  // (k == kmax sends the caller to a wider sketch anyway)
-  if (k < kmax && !(res <= 100.0 * tol * tol * n0)) return rowid_cooperative(ctx, Y, m, ncols, tol, kmax, J, C, work, s);
+  return k >= kmax || res <= 100.0 * tol * tol * n0;
+}
+
+int launch_rowid(rw_ctx* ctx, const double* Y, int64_t m, int ncols, double tol, int kmax, int* J, double* C,
+                 void* work, hipStream_t s) {
+  if (m <= 0) return 0;
+  DBuf<char> res(ctx, 256);
+  int* rk = (int*)res.p;
+  unsigned long long* rm = (unsigned long long*)(res.p + 64);
+  if (!launch_rowid_enqueue(ctx, Y, m, ncols, tol, kmax, J, C, work, rk, rm, s))
+    return rowid_cooperative(ctx, Y, m, ncols, tol, kmax, J, C, work, s);
+  int k = 0;
+  unsigned long long hm[2] = {0, 0};
+  HIP_CHECK(hipMemcpyAsync(&k, rk, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(hm, rm, sizeof(hm), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  if (!rowid_certified(k, kmax, tol, hm)) return rowid_cooperative(ctx, Y, m, ncols, tol, kmax, J, C, work, s);
   return k;
+}
+
+int launch_rowid_fallback(rw_ctx* ctx, const double* Y, int64_t m, int ncols, double tol, int kmax, int* J, double* C,
+                          void* work, hipStream_t s) {
+  return rowid_cooperative(ctx, Y, m, ncols, tol, kmax, J, C, work, s);
 }
 
 void launch_rowid_interp(const double* C, int64_t m, int kmax, int k, const int* J, const int* pos, double* L,

@@ -101,6 +101,17 @@ struct RowIdResult {
 size_t rowid_work_bytes(int64_t m, int ncols, int kmax, int ngroups);
 int launch_rowid(rw_ctx* ctx, const double* Y, int64_t m, int ncols, double tol, int kmax, int* J,
                  double* C, void* work, hipStream_t s);   // returns k (synchronizes)
+// The same without synchronizing: the tournament selection, basis and
+// coefficients are enqueued, and k (int) and the squared largest row norm and
+// residual (2 x u64, ordered bits) land in res_k / res_m (device).  Returns
+// false, enqueueing nothing, where only the cooperative form applies.  Once
+// the caller has read the results back, rowid_certified tells whether they
+// stand; if not, launch_rowid_fallback redoes the ID (synchronizing).
+bool launch_rowid_enqueue(rw_ctx* ctx, const double* Y, int64_t m, int ncols, double tol, int kmax, int* J,
+                          double* C, void* work, int* res_k, unsigned long long* res_m, hipStream_t s);
+bool rowid_certified(int k, int kmax, double tol, const unsigned long long* hm);
+int launch_rowid_fallback(rw_ctx* ctx, const double* Y, int64_t m, int ncols, double tol, int kmax, int* J, double* C,
+                          void* work, hipStream_t s);
 void launch_rowid_interp(const double* C, int64_t m, int kmax, int k, const int* J, const int* pos,
                          double* L, int64_t ldL, int col0, double* inv_work /* k*k doubles */, hipStream_t s);
 // C_out = A^T B for tall A (M x ka), B (M x kb), column-major; beta: C_out = beta*C_out + ...

@@ -528,31 +528,46 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
   f.Np = (int64_t)pnodes.size();
   f.Next = f.No + f.Np;
   const int64_t M = 2 * f.Next, Mo = 2 * f.No, Mp = 2 * f.Np;
+  // host arrays go to the device through the ctx's pinned staging buffer
+  // (one region per array), so the copies are asynchronous and the host
+  // vectors may go out of scope at once; the buffer is next reused by a
+  // later call, after this one has synchronized its stream
+  const size_t stage_bytes = sizeof(NodeRec) * f.Np +
+                             sizeof(int) * (f.Nn + f.No + 3 * f.Nk + 2 * f.Np + f.Nc + 4 * f.Nk) + 16 * 256;
+  char* stage_base = (char*)ctx_pinned(ctx, stage_bytes);
+  size_t stage_off = 0;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (!bytes) return;
+    char* st = stage_base + stage_off;
+    stage_off = (stage_off + bytes + 255) & ~size_t(255);
+    if (stage_off > stage_bytes) RW_THROW(RW_EDEVICE, "pinned staging overflow");
+    memcpy(st, src, bytes);
+    HIP_CHECK(hipMemcpyAsync(dst, st, bytes, hipMemcpyHostToDevice, s));
+  };
   f.d_ext.alloc(ctx, f.Next);
   HIP_CHECK(hipMemcpyAsync(f.d_ext.p, w->d_nodes.p, sizeof(NodeRec) * f.No, hipMemcpyDeviceToDevice, s));
-  if (f.Np) HIP_CHECK(hipMemcpyAsync(f.d_ext.p + f.No, pnodes.data(), sizeof(NodeRec) * f.Np, hipMemcpyHostToDevice, s));
+  up(f.d_ext.p + f.No, pnodes.data(), sizeof(NodeRec) * f.Np);
   f.d_new2ext.alloc(ctx, f.Nn);
-  f.d_new2ext.upload(new2ext.data(), f.Nn, s);
+  up(f.d_new2ext.p, new2ext.data(), sizeof(int) * f.Nn);
   f.d_ref_kind.alloc(ctx, f.No);
-  f.d_ref_kind.upload(ref_kind.data(), f.No, s);
+  up(f.d_ref_kind.p, ref_kind.data(), sizeof(int) * f.No);
   f.d_new.alloc(ctx, f.Nn);
   launch_gather_nodes(f.d_ext.p, f.d_new2ext.p, f.Nn, f.d_new.p, s);
   std::vector<int> pos_k(2 * f.Nk), pos_p(2 * f.Np);
   for (int64_t a = 0; a < f.Nk; ++a) { pos_k[2 * a] = 2 * k_ref[a]; pos_k[2 * a + 1] = 2 * k_ref[a] + 1; }
   for (int64_t a = 0; a < f.Np; ++a) { pos_p[2 * a] = (int)(Mo + 2 * a); pos_p[2 * a + 1] = (int)(Mo + 2 * a + 1); }
   f.d_pos_k.alloc(ctx, pos_k.size());
-  f.d_pos_k.upload(pos_k.data(), pos_k.size(), s);
+  up(f.d_pos_k.p, pos_k.data(), sizeof(int) * pos_k.size());
   f.d_pos_p.alloc(ctx, pos_p.size());
-  f.d_pos_p.upload(pos_p.data(), pos_p.size(), s);
+  up(f.d_pos_p.p, pos_p.data(), sizeof(int) * pos_p.size());
   {
     DBuf<int> idx_k(ctx, std::max<size_t>(1, k_ref.size())), idx_c(ctx, std::max<size_t>(1, c_ref.size()));
     f.d_k.alloc(ctx, f.Nk);
-    idx_k.upload(k_ref.data(), k_ref.size(), s);
+    up(idx_k.p, k_ref.data(), sizeof(int) * k_ref.size());
     launch_gather_nodes(w->d_nodes.p, idx_k.p, f.Nk, f.d_k.p, s);
     f.d_c.alloc(ctx, f.Nc);
-    idx_c.upload(c_ref.data(), c_ref.size(), s);
+    up(idx_c.p, c_ref.data(), sizeof(int) * c_ref.size());
     launch_gather_nodes(w->d_nodes.p, idx_c.p, f.Nc, f.d_c.p, s);
-    HIP_CHECK(hipStreamSynchronize(s));  // the host index vectors go out of scope
   }
   f.d_p.alloc(ctx, f.Np);
   if (f.Np) HIP_CHECK(hipMemcpyAsync(f.d_p.p, f.d_ext.p + f.No, sizeof(NodeRec) * f.Np, hipMemcpyDeviceToDevice, s));
@@ -572,7 +587,7 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
     // ---- a2: Q ~= L R by randomized row IDs of the k-rows [-A_kc A_kp] and p-rows A_pk
     int ncols = ctx->opt.sketch_cols;
     const double tol = w->tol;
-    std::vector<int> Jk, Jp;
+    DBuf<char> dres(ctx, 256);   // ranks and certificates of the two row IDs
     DBuf<double> Yk, Yp, Ck, Cp, part, Ynear;
     DBuf<double2> fpart, fcoef;
     DBuf<char> work;
@@ -610,13 +625,12 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
       d_near_pos.alloc(ctx, std::max<int64_t>(1, n_near));
       d_far_pos.alloc(ctx, std::max<int64_t>(1, n_far));
       d_idx.alloc(ctx, std::max<int64_t>(1, f.Nk));
-      d_near_pos.upload(near_a.data(), n_near, s);
-      d_far_pos.upload(far_a.data(), n_far, s);
-      d_idx.upload(near_ref.data(), n_near, s);
-      if (n_far) HIP_CHECK(hipMemcpyAsync(d_idx.p + n_near, far_ref.data(), sizeof(int) * n_far, hipMemcpyHostToDevice, s));
+      up(d_near_pos.p, near_a.data(), sizeof(int) * n_near);
+      up(d_far_pos.p, far_a.data(), sizeof(int) * n_far);
+      up(d_idx.p, near_ref.data(), sizeof(int) * n_near);
+      up(d_idx.p + n_near, far_ref.data(), sizeof(int) * n_far);
       launch_gather_nodes(w->d_nodes.p, d_idx.p, n_near, d_near.p, s);
       launch_gather_nodes(w->d_nodes.p, d_idx.p + n_near, n_far, d_far.p, s);
-      HIP_CHECK(hipStreamSynchronize(s));  // the host index vectors stay valid until the copies are done
     }
     for (;;) {
       const int kmax = ncols - 8;
@@ -629,8 +643,8 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
         // near rows exactly (compact, then scattered); p-rows: the near kept
         // sources exactly, the far ones by a local expansion (Omega rows of
         // the near list after those of all kept nodes, so none repeats)
-        const int ns_k = (int)std::min<int64_t>(256, std::max<int64_t>(1, (f.Nc + f.Np) / 128));
-        const int ns_p = (int)std::min<int64_t>(256, std::max<int64_t>(1, n_far / 128));
+        const int ns_k = (int)std::min<int64_t>(256, std::max<int64_t>(1, (f.Nc + f.Np) / 32));
+        const int ns_p = (int)std::min<int64_t>(256, std::max<int64_t>(1, n_far / 32));
         part.alloc(ctx, std::max<size_t>(1, std::max(sketch_part_doubles(n_near, f.Nc + f.Np),
                                                      sketch_part_doubles(f.Np, n_near))));
         Ynear.alloc(ctx, (size_t)std::max<int64_t>(1, 2 * n_near * ncols));
@@ -663,13 +677,25 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
       const int ng = std::max(256, ctx->n_cu);
       work.alloc(ctx, std::max(rowid_work_bytes(2 * f.Nk, ncols, kmax, ng), rowid_work_bytes(2 * f.Np, ncols, kmax, ng)));
       PhaseTimer t_id(ctx, "a2_row_id", 8.0 * ncols * 2.0 * (f.Nk + f.Np) * 40.0, 8.0 * ncols * 2.0 * (f.Nk + f.Np));
-      f.k_k = launch_rowid(ctx, Yk.p, 2 * f.Nk, ncols, tol, kmax, dJ.p, Ck.p, work.p, s);
-      Jk.resize(f.k_k);
-      if (f.k_k) dJ.download(Jk.data(), f.k_k, s);
-      f.k_p = launch_rowid(ctx, Yp.p, 2 * f.Np, ncols, tol, kmax, dJ.p + 128, Cp.p, work.p, s);
-      Jp.resize(f.k_p);
-      if (f.k_p) HIP_CHECK(hipMemcpyAsync(Jp.data(), dJ.p + 128, sizeof(int) * f.k_p, hipMemcpyDeviceToHost, s));
+      // both row IDs enqueued, one read-back of their ranks and certificates
+      // (the shared `work` is free again once a job's results are copied out)
+      int* rk = (int*)dres.p;
+      unsigned long long* rm = (unsigned long long*)(dres.p + 64);
+      const bool qk = f.Nk > 0 && launch_rowid_enqueue(ctx, Yk.p, 2 * f.Nk, ncols, tol, kmax, dJ.p, Ck.p, work.p, rk,
+                                                       rm, s);
+      const bool qp = f.Np > 0 && launch_rowid_enqueue(ctx, Yp.p, 2 * f.Np, ncols, tol, kmax, dJ.p + 128, Cp.p, work.p,
+                                                       rk + 1, rm + 2, s);
+      int hk[2] = {0, 0};
+      unsigned long long hm[4] = {0, 0, 0, 0};
+      HIP_CHECK(hipMemcpyAsync(hk, rk, sizeof(hk), hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipMemcpyAsync(hm, rm, sizeof(hm), hipMemcpyDeviceToHost, s));
       HIP_CHECK(hipStreamSynchronize(s));
+      f.k_k = qk ? hk[0] : 0;
+      f.k_p = qp ? hk[1] : 0;
+      if (f.Nk > 0 && (!qk || !rowid_certified(f.k_k, kmax, tol, hm)))
+        f.k_k = launch_rowid_fallback(ctx, Yk.p, 2 * f.Nk, ncols, tol, kmax, dJ.p, Ck.p, work.p, s);
+      if (f.Np > 0 && (!qp || !rowid_certified(f.k_p, kmax, tol, hm + 2)))
+        f.k_p = launch_rowid_fallback(ctx, Yp.p, 2 * f.Np, ncols, tol, kmax, dJ.p + 128, Cp.p, work.p, s);
       const bool full = (f.k_k >= kmax) || (f.k_p >= kmax);
       if (!full) break;
       if (ncols >= 128) RW_THROW(RW_ESINGULAR, "rank of the update matrix exceeds the largest sketch (128 columns)");
@@ -682,8 +708,8 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
     HIP_CHECK(hipMemsetAsync(f.L.p, 0, sizeof(double) * M * f.k, s));
     DBuf<double> inv(ctx, (size_t)128 * 128);
     f.d_J.alloc(ctx, f.k);
-    f.d_J.upload(Jk.data(), f.k_k, s);
-    if (f.k_p) HIP_CHECK(hipMemcpyAsync(f.d_J.p + f.k_k, Jp.data(), sizeof(int) * f.k_p, hipMemcpyHostToDevice, s));
+    if (f.k_k) HIP_CHECK(hipMemcpyAsync(f.d_J.p, dJ.p, sizeof(int) * f.k_k, hipMemcpyDeviceToDevice, s));
+    if (f.k_p) HIP_CHECK(hipMemcpyAsync(f.d_J.p + f.k_k, dJ.p + 128, sizeof(int) * f.k_p, hipMemcpyDeviceToDevice, s));
     launch_rowid_interp(Ck.p, 2 * f.Nk, kmax, f.k_k, f.d_J.p, f.d_pos_k.p, f.L.p, M, 0, inv.p, s);
     launch_rowid_interp(Cp.p, 2 * f.Np, kmax, f.k_p, f.d_J.p + f.k_k, f.d_pos_p.p, f.L.p, M, f.k_k, inv.p, s);
     // R: skeleton rows of Q (k rows on k points, then p rows)
@@ -691,7 +717,6 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
     launch_r_rows(f.d_k.p, f.d_J.p, f.k_k, w->d_nodes.p, f.d_ref_kind.p, f.No, f.d_p.p, f.Np, 0, f.R.p, M, s);
     launch_r_rows(f.d_p.p, f.d_J.p + f.k_k, f.k_p, w->d_nodes.p, f.d_ref_kind.p, f.No, f.d_p.p, f.Np, 1,
                   f.R.p + (size_t)f.k_k * M, M, s);
-    HIP_CHECK(hipStreamSynchronize(s));
   }
   DBuf<int> dinfo(ctx, 4);
   if (f.k > 0) {
