@@ -23,6 +23,14 @@ constexpr int RT = 128;  // targets per block
 constexpr int RRB = 4;   // right-hand sides per pass
 
 int resid_splits(int64_t n, int nrhs) {
+  if (nrhs == 1) {
+    // scalar-broadcast kernel: 256 targets per workgroup; about 8 waves per SIMD
+    const int64_t tb = (n + 255) / 256;
+    int64_t s = (2048 + tb - 1) / tb;
+    s = s < 1 ? 1 : (s > 64 ? 64 : s);
+    const int64_t maxs = (n + 63) / 64;   // at least 64 sources per split
+    return (int)(s > maxs ? maxs : s);
+  }
   const int64_t tb = (n + RT - 1) / RT;
   const int64_t chunks = (nrhs + RRB - 1) / RRB;
   int64_t s = (2048 + tb * chunks - 1) / (tb * chunks);
