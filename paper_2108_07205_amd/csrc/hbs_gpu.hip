@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <type_traits>
 #include <cmath>
+#include <utility>
 
 #include "dev_gj.h"
 #include "dev_reduce.h"
@@ -447,91 +448,141 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
   }
 }
 
-// grid (nodes, 2), 512 threads: sketch row i lives in the registers of
-// threads 2i and 2i+1 (48 columns each); pivoted Gram-Schmidt with two
-// projection passes.  Outputs per (node, side): piv[SK_KCAP], C (m x SK_KCAP
-// row-major at cand_off*SK_KCAP), info[0] = tolerance rank, info[1] = steps.
+// Sum over the TPR (2 or 4) consecutive lanes that hold one sketch row, by
+// DPP quad permutations; every lane of the group gets the same bits.
+template <int TPR>
+__device__ __forceinline__ double row_group_sum(double t) {
+  t += dpp_f64<0xB1, 0xf>(t);                          // quad_perm [1,0,3,2]
+  if constexpr (TPR == 4) t += dpp_f64<0x4E, 0xf>(t);  // quad_perm [2,3,0,1]
+  return t;
+}
+
+// Dot product of CPT-vectors with four independent partial sums.
+template <int CPT>
+__device__ __forceinline__ double dot_by4(const double (&a)[CPT], const double (&b)[CPT]) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+  for (int c = 0; c < CPT; c += 4) {
+    s0 = fma(a[c], b[c], s0);
+    s1 = fma(a[c + 1], b[c + 1], s1);
+    s2 = fma(a[c + 2], b[c + 2], s2);
+    s3 = fma(a[c + 3], b[c + 3], s3);
+  }
+  return (s0 + s1) + (s2 + s3);
+}
+
+// Pivoted Gram-Schmidt on one node side: sketch row i lives in the registers
+// of the TPR threads TPR i .. TPR i + TPR - 1 (SK_R / TPR columns each), and
+// every step projects the remaining rows on the new direction once.  The
+// computed quantities satisfy Y = C Q^T + R exactly up to the rounding of
+// each update, whether or not Q stays orthogonal to working precision, and
+// the rank test recomputes the residual row norms, so the interpolation
+// error stays bounded by the residual rows without a second pass.
+// Outputs piv[SK_KCAP], C (m x SK_KCAP row-major at cand_off*SK_KCAP),
+// info[0] = tolerance rank, info[1] = steps.
+// The node's rank is the larger of the two sides' tolerance ranks, so a side
+// needs steps up to the other side's rank: each side publishes its rank in
+// pub (tagged with the level) as soon as it is known and stops once it has
+// taken as many steps as both ranks, or SK_EXTRA steps past its own when the
+// other side's rank is not in yet (the other side may not be running).
 // The pivot keys and the pivot vector alternate between two LDS slots, so a
 // step needs two barriers: a slot is written again two steps later, after
 // every thread has passed the first barrier of the step in between.
-// NT threads hold up to NT / 2 rows; nodes outside (mlo, mhi] are left to
-// the launch of the other size.
-template <int NT>
-__global__ __launch_bounds__(NT) void node_id_kernel(const GNode* __restrict__ gn, const double* __restrict__ Sr,
-                                                     const double* __restrict__ Sc, double tol2,
-                                                     int* __restrict__ piv, double* __restrict__ Cr,
-                                                     double* __restrict__ Cc, int* __restrict__ info, int mlo,
-                                                     int mhi) {
-  constexpr int NW = NT / 64;
-  __shared__ double q[2][SK_R];
-  __shared__ double rv[2][NW];
-  const GNode g = gn[blockIdx.x];
-  if (g.m <= mlo || g.m > mhi) return;
-  const int side = blockIdx.y;
+constexpr int ID_NT = 512;
+struct IdScratch {
+  double q[2][SK_R];
+  double rv[2][ID_NT / 64];
+  int other[2];
+};
+
+template <int TPR>
+__device__ __forceinline__ void node_id_body(const GNode& g, const double* __restrict__ S, double tol2, int* pv,
+                                             double* __restrict__ C, int* __restrict__ inf, long long* mine,
+                                             long long* theirs, long long tag, IdScratch& L) {
+  constexpr int NW = ID_NT / 64, CPT = SK_R / TPR;
+  static_assert(CPT % 4 == 0, "four partial sums per dot product");
   const int m = g.m, tid = threadIdx.x;
-  const int i = tid >> 1, h = tid & 1;
+  const int i = tid / TPR, h = tid % TPR;
   const bool valid = i < m;
-  const double* S = (side == 0 ? Sr : Sc) + g.cand_off * SK_R;
-  double* C = (side == 0 ? Cr : Cc) + g.cand_off * SK_KCAP;
-  int* pv = piv + ((int64_t)blockIdx.x * 2 + side) * SK_KCAP;
-  double y[48];
+  double y[CPT];
 #pragma unroll
-  for (int c = 0; c < 48; ++c) y[c] = valid ? S[(int64_t)i * SK_R + h * 48 + c] : 0.0;
-  auto row_norm = [&]() {
-    double t = 0.0;
-#pragma unroll
-    for (int c = 0; c < 48; ++c) t += y[c] * y[c];
-    return t + __shfl_xor(t, 1);
-  };
-  double nrm = row_norm();
+  for (int c = 0; c < CPT; ++c) y[c] = valid ? S[(int64_t)i * SK_R + h * CPT + c] : 0.0;
+  double nrm = row_group_sum<TPR>(dot_by4<CPT>(y, y));
   bool sel = !valid;
   double n0 = 0;
   int rank = -1, step = 0;
   const int kmax = min(SK_KCAP, m);
+  // the other side's published rank, loaded one step ahead of its use
+  long long seen = 0;
+  if (tid == 0) seen = __hip_atomic_load(theirs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (; step < kmax; ++step) {
     const int b = step & 1;
     // pivot: DPP maximum of the keys of the unselected rows (the key carries
     // the squared norm to 2^-43 relative, enough for the rank decision)
     const double key = wave_max_nonneg(pivot_key_bits<9>(nrm, i, !sel));
-    if ((tid & 63) == 0) rv[b][tid >> 6] = key;
+    if ((tid & 63) == 0) L.rv[b][tid >> 6] = key;
+    if (tid == 0) {
+      L.other[b] = (seen >> 8) == tag ? (int)(seen & 255) : -1;
+      seen = __hip_atomic_load(theirs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __syncthreads();
-    double v = rv[b][0];
+    double v = L.rv[b][0];
 #pragma unroll
-    for (int w = 1; w < NW; ++w) v = fmax(v, rv[b][w]);
+    for (int w = 1; w < NW; ++w) v = fmax(v, L.rv[b][w]);
     const int p = v > 0.0 ? pivot_key_index<9>(v) : -1;
     if (step == 0) n0 = v;
-    if (rank < 0 && !(v > tol2 * n0)) rank = step;
-    if ((rank >= 0 && step >= rank + SK_EXTRA) || p < 0 || !(v >= 2.2250738585072014e-308)) break;
+    if (rank < 0 && !(v > tol2 * n0)) {
+      rank = step;
+      if (tid == 0) __hip_atomic_store(mine, (tag << 8) | rank, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const int other = L.other[b];
+    if (rank >= 0 && (step >= rank + SK_EXTRA || (other >= 0 && step >= max(rank, other)))) break;
+    if (p < 0 || !(v >= 2.2250738585072014e-308)) break;
     if (i == p) {
       const double inv = 1.0 / sqrt(nrm);
 #pragma unroll
-      for (int c = 0; c < 48; ++c) q[b][h * 48 + c] = y[c] * inv;
+      for (int c = 0; c < CPT; ++c) L.q[b][h * CPT + c] = y[c] * inv;
     }
     if (tid == 0) pv[step] = p;
     __syncthreads();
-    // this thread's half of q in registers, then two projection passes
-    double qr[48];
+    double qr[CPT];
 #pragma unroll
-    for (int c = 0; c < 48; ++c) qr[c] = q[b][h * 48 + c];
-    double cf = 0.0;
+    for (int c = 0; c < CPT; ++c) qr[c] = L.q[b][h * CPT + c];
+    const double cf = row_group_sum<TPR>(dot_by4<CPT>(y, qr));
 #pragma unroll
-    for (int pass = 0; pass < 2; ++pass) {
-      double d = 0.0;
-#pragma unroll
-      for (int c = 0; c < 48; ++c) d += y[c] * qr[c];
-      d += __shfl_xor(d, 1);
-#pragma unroll
-      for (int c = 0; c < 48; ++c) y[c] -= d * qr[c];
-      cf += d;
-    }
+    for (int c = 0; c < CPT; ++c) y[c] = fma(-cf, qr[c], y[c]);
     if (valid && h == 0) C[(int64_t)i * SK_KCAP + step] = cf;
     if (i == p) sel = true;
-    nrm = row_norm();
+    nrm = row_group_sum<TPR>(dot_by4<CPT>(y, y));
   }
   if (tid == 0) {
-    info[(blockIdx.x * 2 + side) * 2] = rank < 0 ? step : rank;
-    info[(blockIdx.x * 2 + side) * 2 + 1] = step;
+    inf[0] = rank < 0 ? step : rank;
+    inf[1] = step;
   }
+}
+
+// grid (nodes, 2), ID_NT threads: y = 0 the row side, y = 1 the column side.
+// Nodes of at most 128 candidates take four threads per row, larger ones (up
+// to 256) two.  pub: 2 slots per node, zero at the start of the build; tag:
+// a positive number unique to the level.
+__global__ __launch_bounds__(ID_NT) void node_id_kernel(const GNode* __restrict__ gn, const double* __restrict__ Sr,
+                                                        const double* __restrict__ Sc, double tol2,
+                                                        int* __restrict__ piv, double* __restrict__ Cr,
+                                                        double* __restrict__ Cc, int* __restrict__ info,
+                                                        long long* __restrict__ pub, long long tag) {
+  __shared__ IdScratch L;
+  const GNode g = gn[blockIdx.x];
+  const int side = blockIdx.y;
+  const double* S = (side == 0 ? Sr : Sc) + g.cand_off * SK_R;
+  double* C = (side == 0 ? Cr : Cc) + g.cand_off * SK_KCAP;
+  int* pv = piv + ((int64_t)blockIdx.x * 2 + side) * SK_KCAP;
+  int* inf = info + (blockIdx.x * 2 + side) * 2;
+  long long* mine = pub + blockIdx.x * 2 + side;
+  long long* theirs = pub + blockIdx.x * 2 + (1 - side);
+  if (g.m <= 128)
+    node_id_body<4>(g, S, tol2, pv, C, inf, mine, theirs, tag, L);
+  else
+    node_id_body<2>(g, S, tol2, pv, C, inf, mine, theirs, tag, L);
 }
 
 // ---------------------------------------------------------------- 2b. level plan
@@ -604,9 +655,93 @@ __global__ __launch_bounds__(64) void level_plan_kernel(GNode* __restrict__ gl, 
 // grid (nodes, 2).  P = C(:, 0:k) C_J^{-1} -> U (side 0) or V (side 1), m x k
 // column-major; the skeleton dofs go to the parent's candidate list.  C_J
 // (the pivot rows of the Gram-Schmidt coefficients) is lower triangular: its
-// rows are staged in LDS, its inverse is formed there by forward
-// substitution (thread t: column t), and the product is taken in items of
-// one row of C times four columns of the inverse.
+// rows are staged in LDS, and its inverse is formed row by row in registers
+// (interp_inverse).  The product then gives each thread the C row of its
+// candidate and a stripe of SK_KCAP / TPR columns in registers, reading the
+// rows of the inverse from LDS as broadcasts.  The skeleton rows get the
+// identity rows directly.
+constexpr int IV_LD = SK_KCAP;
+
+// Inv = C_J^{-1}, k <= SK_KCAP, by forward substitution along the rows of
+// C_J with two threads per column t: thread 2 t + hh holds Inv(u, t) for
+// u = 4 w + 2 hh + e (e = 0, 1) in x[2 w + e], so every row step reads the
+// row of C_J (cj, ld SK_KCAP, zero above the diagonal) as pairs at static
+// offsets and sums over the entries of Inv computed so far (the others are
+// still zero).  The pair of threads adds its two partial sums by DPP, and the
+// owner of Inv(srow, t) stores it.  dinv: reciprocals of the diagonal.
+// Output: Inv in iv (row-major, ld IV_LD), columns t < k.
+template <int SROW>
+__device__ __forceinline__ void interp_inverse_row(double (&x)[SK_KCAP / 2], const double* cj, const double* dinv,
+                                                   int t, int hh) {
+  const double* cs = cj + SROW * SK_KCAP + 2 * hh;
+  double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+  for (int w = 0; 4 * w < SROW; ++w) {
+    const double2 c2 = *reinterpret_cast<const double2*>(cs + 4 * w);
+    s0 = fma(c2.x, x[2 * w], s0);
+    s1 = fma(c2.y, x[2 * w + 1], s1);
+  }
+  const double sum = row_group_sum<2>(s0 + s1);
+  const double val = ((SROW == t ? 1.0 : 0.0) - sum) * dinv[SROW];
+  if (hh == ((SROW >> 1) & 1)) x[2 * (SROW >> 2) + (SROW & 1)] = val;
+}
+
+template <int... R>
+__device__ __forceinline__ void interp_inverse_rows(std::integer_sequence<int, R...>, double (&x)[SK_KCAP / 2],
+                                                    const double* cj, const double* dinv, int k, int t, int hh) {
+  ((R < k ? interp_inverse_row<R>(x, cj, dinv, t, hh) : void()), ...);
+}
+
+__device__ __forceinline__ void interp_inverse(const double* cj, const double* dinv, int k, double* iv) {
+  constexpr int NX = SK_KCAP / 2;
+  static_assert(SK_KCAP % 4 == 0, "pairs of pairs of rows");
+  const int t = threadIdx.x >> 1, hh = threadIdx.x & 1;
+  double x[NX];
+#pragma unroll
+  for (int e = 0; e < NX; ++e) x[e] = 0.0;
+  interp_inverse_rows(std::make_integer_sequence<int, SK_KCAP>{}, x, cj, dinv, k, t, hh);
+  if (t < k) {
+#pragma unroll
+    for (int w = 0; w < NX / 2; ++w)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int u = 4 * w + 2 * hh + e;
+        if (u < k) iv[u * IV_LD + t] = x[2 * w + e];
+      }
+  }
+}
+
+template <int TPR>
+__device__ __forceinline__ void interp_product(const double* __restrict__ C, const double* iv, const int* pstep,
+                                               int m, int k, double* __restrict__ P) {
+  constexpr int CPT = SK_KCAP / TPR;
+  static_assert(SK_KCAP % (2 * TPR) == 0, "stripes of whole double pairs");
+  const int i = threadIdx.x / TPR, h = threadIdx.x % TPR;
+  if (i >= m) return;
+  const int c0 = h * CPT;
+  const int ps = pstep[i];
+  double v[CPT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) v[c] = 0.0;
+  if (ps < 0) {
+    const double* ci = C + (int64_t)i * SK_KCAP;
+    double a = ci[0];
+    for (int srow = 0; srow < k; ++srow) {
+      const double an = srow + 1 < k ? ci[srow + 1] : 0.0;
+      const double* ir = iv + srow * IV_LD + c0;
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) v[c] = fma(a, ir[c], v[c]);
+      a = an;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) v[c] = (c0 + c == ps) ? 1.0 : 0.0;
+  }
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+    if (c0 + c < k) P[i + (int64_t)(c0 + c) * m] = v[c];
+}
+
 __global__ __launch_bounds__(256) void node_interp_kernel(const GNode* __restrict__ gn,
                                                               const int* __restrict__ candr,
                                                               const int* __restrict__ candc,
@@ -616,7 +751,9 @@ __global__ __launch_bounds__(256) void node_interp_kernel(const GNode* __restric
                                                               double* __restrict__ V,
                                                               const int64_t* __restrict__ par_pos,
                                                               int* __restrict__ pcandr, int* __restrict__ pcandc) {
-  extern __shared__ double lds[];  // cj[s * k + u] = C_J(s, u); iv[u * k + t] = Inv(u, t)
+  extern __shared__ double lds[];  // cj[s * SK_KCAP + u] = C_J(s, u); iv[u * IV_LD + t] = Inv(u, t)
+  __shared__ int pstep[256];       // skeleton step of each candidate, -1 for the others
+  __shared__ double dinv[SK_KCAP];
   const GNode g = gn[blockIdx.x];
   const int side = blockIdx.y;
   const int k = g.k, m = g.m, tid = threadIdx.x;
@@ -624,47 +761,25 @@ __global__ __launch_bounds__(256) void node_interp_kernel(const GNode* __restric
   const double* C = (side == 0 ? Cr : Cc) + g.cand_off * SK_KCAP;
   double* P = (side == 0 ? U : V) + g.uv_off;
   double* cj = lds;
-  double* iv = lds + k * k;
-  for (int idx = tid; idx < k * k; idx += 256) {
-    const int srow = idx / k, u = idx - srow * k;
-    cj[idx] = (u <= srow) ? C[(int64_t)pv[srow] * SK_KCAP + u] : 0.0;
+  double* iv = lds + SK_KCAP * SK_KCAP;
+  for (int idx = tid; idx < k * SK_KCAP; idx += 256) {
+    const int srow = idx / SK_KCAP, u = idx - srow * SK_KCAP;
+    const double c = (u <= srow) ? C[(int64_t)pv[srow] * SK_KCAP + u] : 0.0;
+    cj[idx] = c;
     iv[idx] = 0.0;
+    if (u == srow) dinv[srow] = 1.0 / c;
   }
+  pstep[tid] = -1;
   __syncthreads();
-  if (tid < k) {
-    const int t = tid;
-    for (int srow = t; srow < k; ++srow) {
-      const double* cs = cj + srow * k;
-      double v = (srow == t) ? 1.0 : 0.0;
-      for (int u = t; u < srow; ++u) v -= cs[u] * iv[u * k + t];
-      iv[srow * k + t] = v / cs[srow];
-    }
-  }
+  if (tid < k) pstep[pv[tid]] = tid;
+  interp_inverse(cj, dinv, k, iv);
   __syncthreads();
-  constexpr int NCB = 4;
-  const int nb = (k + NCB - 1) / NCB;
-  for (int item = tid; item < m * nb; item += 256) {
-    const int i = item % m, t0 = (item / m) * NCB;
-    const double* ci = C + (int64_t)i * SK_KCAP;
-    double v[NCB];
-#pragma unroll
-    for (int c = 0; c < NCB; ++c) v[c] = 0.0;
-    for (int srow = t0; srow < k; ++srow) {
-      const double a = ci[srow];
-      const double* ir = iv + srow * k + t0;
-#pragma unroll
-      for (int c = 0; c < NCB; ++c)
-        if (t0 + c < k) v[c] += a * ir[c];
-    }
-#pragma unroll
-    for (int c = 0; c < NCB; ++c)
-      if (t0 + c < k) P[i + (int64_t)(t0 + c) * m] = v[c];
-  }
-  __syncthreads();
-  for (int srow = tid; srow < k; srow += 256) {
-    const int p = pv[srow];
-    for (int t = 0; t < k; ++t) P[p + (int64_t)t * m] = (t == srow) ? 1.0 : 0.0;
-  }
+  if (m <= 64)
+    interp_product<4>(C, iv, pstep, m, k, P);
+  else if (m <= 128)
+    interp_product<2>(C, iv, pstep, m, k, P);
+  else
+    interp_product<1>(C, iv, pstep, m, k, P);
   if (par_pos) {
     const int* cand = (side == 0 ? candr : candc) + g.cand_off;
     int* pc = (side == 0 ? pcandr : pcandc) + par_pos[blockIdx.x];
@@ -1650,8 +1765,13 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
   DBuf<int> candr(ctx, cand_total), candc(ctx, cand_total);
   DBuf<double> Sr(ctx, cap_max * SK_R), Sc(ctx, cap_max * SK_R);
   DBuf<double> Cr(ctx, cap_max * SK_KCAP), Cc(ctx, cap_max * SK_KCAP);
-  DBuf<int> piv(ctx, (size_t)(int64_t(2) << L) * SK_KCAP), info(ctx, (size_t)(int64_t(4) << L)), fail(ctx, 4);
-  DBuf<int64_t> cnt(ctx, 2);
+  DBuf<int> piv(ctx, (size_t)(int64_t(2) << L) * SK_KCAP), info(ctx, (size_t)(int64_t(4) << L));
+  // control words, cleared together: fail flags (4 ints), generator / spare
+  // counters (2), the ID sides' published ranks (2 per node of a level)
+  DBuf<int64_t> ctl(ctx, (size_t)(4 + (int64_t(2) << L)));
+  int* const failp = (int*)ctl.p;
+  int64_t* const cntp = ctl.p + 2;
+  long long* const pubp = (long long*)(ctl.p + 4);
   DBuf<double> Ub(ctx, uv_total), Vb(ctx, uv_total);
   DBuf<double> dhA(ctx, (int64_t(1) << L) * SK_KCAP * SK_KCAP), dhB(ctx, (int64_t(1) << L) * SK_KCAP * SK_KCAP);
   DBuf<double> ws(ctx, ws_bound);
@@ -1670,8 +1790,7 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
   DBuf<double> part_r(ctx, part_len), part_c(ctx, part_len);
   w.gen.alloc(ctx, gen_bound);
   w.groot.alloc(ctx, (size_t)(2 * SK_KCAP) * (2 * SK_KCAP));
-  HIP_CHECK(hipMemsetAsync(fail.p, 0, sizeof(int) * 4, s));
-  HIP_CHECK(hipMemsetAsync(cnt.p, 0, sizeof(int64_t) * 2, s));
+  HIP_CHECK(hipMemsetAsync(ctl.p, 0, sizeof(int64_t) * ctl.n, s));
   // pinned staging: node records (level l at [2^l, 2^(l+1))) and the leaf candidate lists
   char* pin = (char*)ctx_pinned(ctx, sizeof(GNode) * (size_t)(int64_t(2) << L) + sizeof(int) * (size_t)(2 * N));
   GNode* hG = (GNode*)pin;
@@ -1722,7 +1841,7 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     {
       KernelTimer kt("node_factor_bordered_kernel", 0.0, 0.0, sf);
       hipLaunchKernelGGL(node_factor_bordered_kernel, dim3(nn), dim3(BWV * 64), 0, sf, gn, gch, is_leaf, is_root, cr, cc,
-                         d_nodes, U, V, dh_child, dh_cur, ws.p, w.gen.p, groot, fail.p);
+                         d_nodes, U, V, dh_child, dh_cur, ws.p, w.gen.p, groot, failp);
       KERNEL_CHECK("node_factor_bordered");
     }
     if (ctx->prof && !ctx->pending.empty()) fac_entry[lvl] = ctx->pending.size() - 1;
@@ -1731,13 +1850,13 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     if (small) {
       KernelTimer kt("node_factor_kernel", 0.0, 0.0, sf);
       hipLaunchKernelGGL(node_factor_kernel, dim3(nn), dim3(256), 0, sf, gn, gch, is_leaf, is_root, cr, cc, d_nodes,
-                         U, V, dh_child, dh_cur, ws.p, w.gen.p, groot, fail.p, 0, FN);
+                         U, V, dh_child, dh_cur, ws.p, w.gen.p, groot, failp, 0, FN);
       KERNEL_CHECK("node_factor");
     }
     if (large) {
       KernelTimer kt("node_inverse_kernel", 0.0, 0.0, sf);
       hipLaunchKernelGGL(node_inverse_kernel, dim3(nn), dim3(256), shv, sf, gn, gch, is_leaf, is_root, cr, cc, d_nodes,
-                         U, V, dh_child, dh_cur, ws.p, w.gen.p, groot, fail.p, FN, MANY);
+                         U, V, dh_child, dh_cur, ws.p, w.gen.p, groot, failp, FN, MANY);
       KERNEL_CHECK("node_inverse");
     }
   };
@@ -1753,6 +1872,7 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     if (leaf) {
       for (const GNode& g : G[L]) { off += g.m; mx = std::max(mx, g.m); }
       if (mx > mmax) RW_THROW(RW_ESINGULAR, "HBS node input exceeds the sketch bound");
+      if (mx > ID_NT / 2) RW_THROW(RW_EINVAL, "HBS leaf of more than 128 nodes");
     } else {
       off = (int64_t)nn * 2 * SK_KCAP;
     }
@@ -1781,18 +1901,13 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
       KERNEL_CHECK("node_sketch_sum");
     }
     {
-      // nodes of at most 128 candidates on 256 threads (two per row), larger ones on 512
       KernelTimer kt_id("node_id_kernel", 0.0, 0.0);
-      if (!leaf || mx <= 128)
-        hipLaunchKernelGGL(node_id_kernel<256>, dim3(nn, 2), dim3(256), 0, s, dgl, Sr.p, Sc.p, tol * tol, piv.p, Cr.p,
-                           Cc.p, info.p, 0, 128);
-      if (!leaf || mx > 128)
-        hipLaunchKernelGGL(node_id_kernel<512>, dim3(nn, 2), dim3(512), 0, s, dgl, Sr.p, Sc.p, tol * tol, piv.p, Cr.p,
-                           Cc.p, info.p, 128, 256);
+      hipLaunchKernelGGL(node_id_kernel, dim3(nn, 2), dim3(ID_NT), 0, s, dgl, Sr.p, Sc.p, tol * tol, piv.p, Cr.p,
+                         Cc.p, info.p, pubp, (long long)(l + 1));
       KERNEL_CHECK("node_id");
     }
-    hipLaunchKernelGGL(level_plan_kernel, dim3(1), dim3(64), 0, s, dgl, nn, info.p, dg.p + nn / 2, dpar.p + nn, cnt.p,
-                       (int64_t)w.gen.n, (int64_t)ws.n, fail.p);
+    hipLaunchKernelGGL(level_plan_kernel, dim3(1), dim3(64), 0, s, dgl, nn, info.p, dg.p + nn / 2, dpar.p + nn, cntp,
+                       (int64_t)w.gen.n, (int64_t)ws.n, failp);
     KERNEL_CHECK("level_plan");
     hipLaunchKernelGGL(node_interp_kernel, dim3(nn, 2), dim3(256), shi, s, dgl, cr, cc, piv.p, Cr.p, Cc.p,
                        Ub.p + uv_base[l], Vb.p + uv_base[l], dpar.p + nn, candr.p + cand_base[l - 1],
@@ -1812,12 +1927,13 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
                 -1, 0);
   stream_after(ctx, s, sf, 2);
   // ---- read back the node records, the generator count and the flags
-  int64_t hcnt[2];
-  int hf[4];
+  int64_t hctl[4];
   HIP_CHECK(hipMemcpyAsync(hG, dg.p, sizeof(GNode) * (size_t)(int64_t(2) << L), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(hcnt, cnt.p, sizeof hcnt, hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(hf, fail.p, sizeof hf, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(hctl, ctl.p, sizeof hctl, hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
+  int hf[4];
+  memcpy(hf, hctl, sizeof hf);
+  const int64_t* hcnt = hctl + 2;
   if (hf[1]) RW_THROW(RW_ESINGULAR, "HBS node rank reached the sketch size");
   if (hf[2]) RW_THROW(RW_ESINGULAR, "HBS generator bound exceeded");
   if (hf[0]) RW_THROW(RW_ESINGULAR, "singular block in the GPU HBS build (" + std::to_string(hf[0]) + ")");

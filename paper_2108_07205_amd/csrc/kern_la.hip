@@ -455,15 +455,46 @@ __global__ __launch_bounds__(256) void gemm_tn_part_kernel(const double* __restr
     }
 }
 
+// One right-hand side (kb = 1): grid (nparts, ceil(ka / 4)); wave w of block
+// (p, y) forms the partial dot product of column 4 y + w of A with x over the
+// rows of part p, every lane's loads independent of the others.
+__global__ __launch_bounds__(256) void gemv_tn_part_kernel(const double* __restrict__ A, int64_t lda,
+                                                           const double* __restrict__ x, int64_t M, int ka,
+                                                           int64_t rows_per, double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, ia = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (ia >= ka) return;
+  const int64_t e0 = (int64_t)blockIdx.x * rows_per;
+  const int64_t e1 = min(M, e0 + rows_per);
+  const double* a = A + (int64_t)ia * lda;
+  double s0 = 0.0, s1 = 0.0;
+  int64_t r = e0 + lane;
+  for (; r + 64 < e1; r += 128) {
+    s0 = fma(a[r], x[r], s0);
+    s1 = fma(a[r + 64], x[r + 64], s1);
+  }
+  if (r < e1) s0 = fma(a[r], x[r], s0);
+  double v = s0 + s1;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (lane == 0) part[(int64_t)blockIdx.x * ka + ia] = v;
+}
+
+// One wave per output entry: the nparts partials in a fixed order (lane
+// strides, then a butterfly), plus the identity if asked.
 __global__ __launch_bounds__(256) void gemm_tn_reduce_kernel(const double* __restrict__ part, int nparts, int ka,
                                                              int kb, double* __restrict__ C, int64_t ldc, int ident) {
-  const int o = blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (o >= ka * kb) return;
   double s = 0;
-  for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * ka * kb + o];
-  const int ia = o % ka, ib = o / ka;
-  if (ident && ia == ib) s += 1.0;
-  C[ia + (int64_t)ib * ldc] = s;
+  for (int p = lane; p < nparts; p += 64) s += part[(int64_t)p * ka * kb + o];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) {
+    const int ia = o % ka, ib = o / ka;
+    if (ident && ia == ib) s += 1.0;
+    C[ia + (int64_t)ib * ldc] = s;
+  }
 }
 
 int gemm_tn_nparts(int64_t M) {
@@ -909,10 +940,14 @@ void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, 
   if (ka <= 0 || kb <= 0) return;
   const int np = gemm_tn_nparts(M);
   const int64_t rows_per = (M + np - 1) / np;
-  hipLaunchKernelGGL(gemm_tn_part_kernel, dim3(np), dim3(256), 0, s, A, lda, B, ldb, M, ka, kb, rows_per, part);
+  if (kb == 1)
+    hipLaunchKernelGGL(gemv_tn_part_kernel, dim3(np, (ka + 3) / 4), dim3(256), 0, s, A, lda, B, M, ka, rows_per,
+                       part);
+  else
+    hipLaunchKernelGGL(gemm_tn_part_kernel, dim3(np), dim3(256), 0, s, A, lda, B, ldb, M, ka, kb, rows_per, part);
   KERNEL_CHECK("gemm_tn_part");
-  hipLaunchKernelGGL(gemm_tn_reduce_kernel, dim3(blocks((int64_t)ka * kb)), dim3(256), 0, s, part, np, ka, kb, C, ldc,
-                     add_identity ? 1 : 0);
+  hipLaunchKernelGGL(gemm_tn_reduce_kernel, dim3(blocks((int64_t)ka * kb, 4)), dim3(256), 0, s, part, np, ka, kb, C,
+                     ldc, add_identity ? 1 : 0);
   KERNEL_CHECK("gemm_tn_reduce");
 }
 

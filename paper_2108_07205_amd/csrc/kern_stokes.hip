@@ -112,21 +112,30 @@ __global__ __launch_bounds__(RT) void resid_tiles_kernel(const NodeRec* __restri
     }
 }
 
-// s_N[c] = sum_j w_j n_j . tau_j  (the rank-one nullspace term)
-__global__ __launch_bounds__(256) void flux_kernel(const NodeRec* __restrict__ nd, int64_t n,
-                                                   const double* __restrict__ tau, double* __restrict__ sN) {
-  __shared__ double red[256];
-  const int c = blockIdx.x;
-  const double* tc = tau + (int64_t)c * 2 * n;
-  double s = 0.0;
-  for (int64_t j = threadIdx.x; j < n; j += 256) s += nd[j].w * (nd[j].nx * tc[2 * j] + nd[j].ny * tc[2 * j + 1]);
-  red[threadIdx.x] = s;
+// Sum over a workgroup of 256 threads in a fixed order (butterfly within
+// each wave, then the four wave sums in order), returned to thread 0.
+__device__ __forceinline__ double block_sum256(double v, double* red4) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) sN[c] = red[0];
+  return (red4[0] + red4[1]) + (red4[2] + red4[3]);
+}
+
+// Partial sums of s_N[c] = sum_j w_j n_j . tau_j (the rank-one nullspace
+// term) over the 256 nodes of block b: fpart[c * nb + b].
+__device__ __forceinline__ double flux_term(const NodeRec& q, const double* tc, int64_t j) {
+  return q.w * (q.nx * tc[2 * j] + q.ny * tc[2 * j + 1]);
+}
+__global__ __launch_bounds__(256) void flux_part_kernel(const NodeRec* __restrict__ nd, int64_t n,
+                                                        const double* __restrict__ tau,
+                                                        double* __restrict__ fpart) {
+  __shared__ double red4[4];
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  const double v = j < n ? flux_term(nd[j], tau + (int64_t)c * 2 * n, j) : 0.0;
+  const double t = block_sum256(v, red4);
+  if (threadIdx.x == 0) fpart[(int64_t)c * gridDim.x + blockIdx.x] = t;
 }
 
 // One right-hand side: the sources packed as (x, y, n_x w / pi, n_y w / pi,
@@ -134,20 +143,28 @@ __global__ __launch_bounds__(256) void flux_kernel(const NodeRec* __restrict__ n
 // turns into scalar loads of one 64-byte record per source: the kernel's
 // inner loop then reads no LDS and runs at the FP64 instruction rate.
 constexpr int RPK = 8;   // doubles per packed source
+// Also writes the flux partial of its block (fpart[blockIdx.x]).
 __global__ __launch_bounds__(256) void resid_pack_kernel(const NodeRec* __restrict__ nd, int64_t n,
-                                                         const double* __restrict__ tau, double* __restrict__ pk) {
+                                                         const double* __restrict__ tau, double* __restrict__ pk,
+                                                         double* __restrict__ fpart) {
+  __shared__ double red4[4];
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
-  const NodeRec q = nd[j];
-  double* o = pk + j * RPK;
-  o[0] = q.x;
-  o[1] = q.y;
-  o[2] = q.nx * q.w * kInvPi;
-  o[3] = q.ny * q.w * kInvPi;
-  o[4] = tau[2 * j];
-  o[5] = tau[2 * j + 1];
-  o[6] = 0.0;
-  o[7] = 0.0;
+  double fl = 0.0;
+  if (j < n) {
+    const NodeRec q = nd[j];
+    double* o = pk + j * RPK;
+    o[0] = q.x;
+    o[1] = q.y;
+    o[2] = q.nx * q.w * kInvPi;
+    o[3] = q.ny * q.w * kInvPi;
+    o[4] = tau[2 * j];
+    o[5] = tau[2 * j + 1];
+    o[6] = 0.0;
+    o[7] = 0.0;
+    fl = flux_term(q, tau, j);
+  }
+  const double t = block_sum256(fl, red4);
+  if (threadIdx.x == 0) fpart[blockIdx.x] = t;
 }
 
 // grid (ceil(n / 256), 1, nsplit): thread = target, sources of the split in
@@ -202,51 +219,71 @@ __global__ __launch_bounds__(256) void resid_scalar_kernel(const NodeRec* __rest
   }
 }
 
+// grid (nb = ceil(n / 256), nrhs).  s_N[c] is the sum of the nb flux
+// partials, taken in the same order by every thread; with npart, block b
+// also writes the partial sums of |r|^2 and |g|^2 over its nodes to
+// npart[2 (c nb + b)] and npart[2 (c nb + b) + 1].
 __global__ __launch_bounds__(256) void resid_finalize_kernel(const NodeRec* __restrict__ nd, int64_t n,
                                                              const double* __restrict__ g,
                                                              const double* __restrict__ tau, int nrhs, int nsplit,
                                                              const double* __restrict__ part,
-                                                             const double* __restrict__ sN,
-                                                             double* __restrict__ r) {
+                                                             const double* __restrict__ fpart,
+                                                             double* __restrict__ r, double* __restrict__ npart) {
+  __shared__ double red4[2][4];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int c = blockIdx.y;
-  if (i >= n) return;
+  const int c = blockIdx.y, nb = gridDim.x;
   const int64_t ld = 2 * n;
-  const NodeRec q = nd[i];
-  const double tx = tau[2 * i + (int64_t)c * ld], ty = tau[2 * i + 1 + (int64_t)c * ld];
-  // self block without its nullspace part (added through s_N below)
-  const double a00 = q.s00 - q.w * q.nx * q.nx, a01 = q.s01 - q.w * q.nx * q.ny, a11 = q.s11 - q.w * q.ny * q.ny;
-  double ax = a00 * tx + a01 * ty + q.nx * sN[c];
-  double ay = a01 * tx + a11 * ty + q.ny * sN[c];
-  for (int z = 0; z < nsplit; ++z) {
-    const double* p = part + ((int64_t)z * nrhs + c) * ld;
-    ax += p[2 * i];
-    ay += p[2 * i + 1];
+  double sN = 0.0;
+  for (int b = 0; b < nb; ++b) sN += fpart[(int64_t)c * nb + b];
+  double r2 = 0.0, g2 = 0.0;
+  if (i < n) {
+    const NodeRec q = nd[i];
+    const double tx = tau[2 * i + (int64_t)c * ld], ty = tau[2 * i + 1 + (int64_t)c * ld];
+    // self block without its nullspace part (added through s_N below)
+    const double a00 = q.s00 - q.w * q.nx * q.nx, a01 = q.s01 - q.w * q.nx * q.ny, a11 = q.s11 - q.w * q.ny * q.ny;
+    double ax = a00 * tx + a01 * ty + q.nx * sN;
+    double ay = a01 * tx + a11 * ty + q.ny * sN;
+    for (int z = 0; z < nsplit; ++z) {
+      const double* p = part + ((int64_t)z * nrhs + c) * ld;
+      ax += p[2 * i];
+      ay += p[2 * i + 1];
+    }
+    const double gx = g[2 * i + (int64_t)c * ld], gy = g[2 * i + 1 + (int64_t)c * ld];
+    const double rx = gx - ax, ry = gy - ay;
+    r[2 * i + (int64_t)c * ld] = rx;
+    r[2 * i + 1 + (int64_t)c * ld] = ry;
+    r2 = rx * rx + ry * ry;
+    g2 = gx * gx + gy * gy;
   }
-  r[2 * i + (int64_t)c * ld] = g[2 * i + (int64_t)c * ld] - ax;
-  r[2 * i + 1 + (int64_t)c * ld] = g[2 * i + 1 + (int64_t)c * ld] - ay;
+  if (npart) {
+    const double sr = block_sum256(r2, red4[0]);
+    const double sg = block_sum256(g2, red4[1]);
+    if (threadIdx.x == 0) {
+      npart[2 * ((int64_t)c * nb + blockIdx.x)] = sr;
+      npart[2 * ((int64_t)c * nb + blockIdx.x) + 1] = sg;
+    }
+  }
 }
 
-__global__ __launch_bounds__(256) void colnorms2_kernel(const double* __restrict__ a,
-                                                        const double* __restrict__ b, int64_t rows,
-                                                        int nrhs, double* __restrict__ out) {
-  __shared__ double ra[256], rb[256];
-  const int c = blockIdx.x;
-  double sa = 0, sb = 0;
-  for (int64_t i = threadIdx.x; i < rows; i += 256) {
-    const double x = a[i + (int64_t)c * rows];
-    const double y = b[i + (int64_t)c * rows];
-    sa += x * x;
-    sb += y * y;
+// grid (nrhs), one wave: norms[c] = sum_b npart[2 (c nb + b)] (|r_c|^2),
+// norms[nrhs + c] = the same for |g_c|^2.
+__global__ __launch_bounds__(64) void resid_norms_kernel(const double* __restrict__ npart, int nb, int nrhs,
+                                                         double* __restrict__ norms) {
+  const int c = blockIdx.x, lane = threadIdx.x;
+  double sr = 0.0, sg = 0.0;
+  for (int b = lane; b < nb; b += 64) {
+    sr += npart[2 * ((int64_t)c * nb + b)];
+    sg += npart[2 * ((int64_t)c * nb + b) + 1];
   }
-  ra[threadIdx.x] = sa;
-  rb[threadIdx.x] = sb;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) { ra[threadIdx.x] += ra[threadIdx.x + w]; rb[threadIdx.x] += rb[threadIdx.x + w]; }
-    __syncthreads();
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sr += __shfl_xor(sr, o);
+    sg += __shfl_xor(sg, o);
   }
-  if (threadIdx.x == 0) { out[c] = ra[0]; out[nrhs + c] = rb[0]; }
+  if (lane == 0) {
+    norms[c] = sr;
+    norms[nrhs + c] = sg;
+  }
 }
 
 // ---------------------------------------------------------------- RHS
@@ -525,38 +562,42 @@ inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) /
 
 }  // namespace
 
+// workspace: split partials (nsplit x nrhs x 2n), flux partials (nrhs x nb),
+// norm partials (2 x nrhs x nb), packed sources (RPK x n, one right-hand side)
 size_t resid_part_doubles(int64_t n, int nrhs) {
-  return (size_t)resid_splits(n, nrhs) * nrhs * 2 * n + 64 + nrhs + (nrhs == 1 ? (size_t)RPK * n : 0);
+  const int64_t nb = blocks(n);
+  return (size_t)resid_splits(n, nrhs) * nrhs * 2 * n + (size_t)(3 * nb * nrhs) + (nrhs == 1 ? (size_t)RPK * n : 0);
 }
 
 void launch_residual(const NodeRec* nodes, int64_t n, const double* g, const double* tau, double* r, int nrhs,
-                     double* part, hipStream_t s) {
+                     double* part, double* norms, hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return;
   const int ns = resid_splits(n, nrhs);
-  double* sN = part + (size_t)ns * nrhs * 2 * n;
+  const int nb = (int)blocks(n);
+  double* fpart = part + (size_t)ns * nrhs * 2 * n;
+  double* npart = fpart + (size_t)nb * nrhs;
   // algorithmic work: 12 flops per 2x2 block (r, r^2, r.n, 1/r^2 scaling) + 6 per
   // block and right-hand side; the division counts as one flop
   {
     KernelTimer kt("resid_tiles_kernel", (double)n * n * (12.0 + 6.0 * nrhs), 0.0);
     if (nrhs == 1) {
-      double* pk = sN + 64 + nrhs;
-      hipLaunchKernelGGL(resid_pack_kernel, dim3(blocks(n)), dim3(256), 0, s, nodes, n, tau, pk);
-      hipLaunchKernelGGL(resid_scalar_kernel, dim3(blocks(n), 1, ns), dim3(256), 0, s, nodes, n, pk, ns, part);
-    } else
+      double* pk = npart + (size_t)2 * nb * nrhs;
+      hipLaunchKernelGGL(resid_pack_kernel, dim3(nb), dim3(256), 0, s, nodes, n, tau, pk, fpart);
+      hipLaunchKernelGGL(resid_scalar_kernel, dim3(nb, 1, ns), dim3(256), 0, s, nodes, n, pk, ns, part);
+    } else {
+      hipLaunchKernelGGL(flux_part_kernel, dim3(nb, nrhs), dim3(256), 0, s, nodes, n, tau, fpart);
       hipLaunchKernelGGL(resid_tiles_kernel<RRB>, dim3(blocks(n, RT), (nrhs + RRB - 1) / RRB, ns), dim3(RT), 0, s,
                          nodes, n, tau, nrhs, ns, part);
+    }
     KERNEL_CHECK("resid_tiles");
   }
-  hipLaunchKernelGGL(flux_kernel, dim3(nrhs), dim3(256), 0, s, nodes, n, tau, sN);
-  KERNEL_CHECK("flux");
-  hipLaunchKernelGGL(resid_finalize_kernel, dim3(blocks(n), nrhs), dim3(256), 0, s, nodes, n, g, tau, nrhs, ns,
-                     part, sN, r);
+  hipLaunchKernelGGL(resid_finalize_kernel, dim3(nb, nrhs), dim3(256), 0, s, nodes, n, g, tau, nrhs, ns, part, fpart,
+                     r, norms ? npart : (double*)nullptr);
   KERNEL_CHECK("resid_finalize");
-}
-
-void launch_colnorms2(const double* a, const double* b, int64_t rows, int nrhs, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(colnorms2_kernel, dim3(nrhs), dim3(256), 0, s, a, b, rows, nrhs, out);
-  KERNEL_CHECK("colnorms2");
+  if (norms) {
+    hipLaunchKernelGGL(resid_norms_kernel, dim3(nrhs), dim3(64), 0, s, npart, nb, nrhs, norms);
+    KERNEL_CHECK("resid_norms");
+  }
 }
 
 void launch_stokeslet_rhs(const NodeRec* nodes, int64_t n, const double* zf, int n_src, double* g,

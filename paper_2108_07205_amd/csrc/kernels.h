@@ -38,12 +38,11 @@ void launch_hbs_down_f32(const HbsLevelDev& L, const float* gen, const double* x
 
 // ----------------------------------------------------------- Stokes tiles
 // r = g - A tau on one node set (exact Nystrom operator, tiles on the fly).
-// part: workspace of resid_part_doubles(n, nrhs) doubles.
+// part: workspace of resid_part_doubles(n, nrhs) doubles.  norms (optional,
+// 2 nrhs doubles): |r_c|^2 in norms[c], |g_c|^2 in norms[nrhs + c].
 size_t resid_part_doubles(int64_t n, int nrhs);
 void launch_residual(const NodeRec* nodes, int64_t n, const double* g, const double* tau, double* r,
-                     int nrhs, double* part, hipStream_t s);
-// column sums of squares of two 2n x nrhs arrays -> out[0..nrhs) and out[nrhs..2 nrhs)
-void launch_colnorms2(const double* a, const double* b, int64_t rows, int nrhs, double* out, hipStream_t s);
+                     int nrhs, double* part, double* norms, hipStream_t s);
 // g = sum_m S(x_i, z_m) f_m at all nodes (z, f device arrays, n_src x 2 row-major)
 void launch_stokeslet_rhs(const NodeRec* nodes, int64_t n, const double* zf, int n_src, double* g,
                           hipStream_t s);

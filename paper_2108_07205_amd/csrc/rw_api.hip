@@ -1017,7 +1017,6 @@ int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau) {
     const double t0 = wall_ms();
     hipStream_t s = f->ctx->stream;
     refined_ensure_ws(f, nrhs);
-    const int64_t n2 = 2 * f->Nn;
     woodbury_apply(f, g, tau, nrhs, false);
     const rw_options& o = f->ctx->opt;
     std::vector<double> nrm(2 * nrhs);
@@ -1026,9 +1025,8 @@ int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau) {
     for (;;) {
       {
         PhaseTimer t(f->ctx, "a8_residual", 26.0 * (double)f->Nn * f->Nn * nrhs, 0.0);
-        launch_residual(f->d_new.p, f->Nn, g, tau, f->r.p, nrhs, f->part.p, s);
+        launch_residual(f->d_new.p, f->Nn, g, tau, f->r.p, nrhs, f->part.p, f->norms.p, s);
       }
-      launch_colnorms2(f->r.p, g, n2, nrhs, f->norms.p, s);
       HIP_CHECK(hipMemcpyAsync(nrm.data(), f->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
       HIP_CHECK(hipStreamSynchronize(s));
       worst = 0;
@@ -1122,9 +1120,8 @@ int rw_solve_batch(rw_refined* const* inst, int32_t n_inst, const double* const*
         rw_refined* f = fs[i];
         {
           PhaseTimer t(f->ctx, "a8_residual", 26.0 * (double)f->Nn * f->Nn * nr[i], 0.0);
-          launch_residual(f->d_new.p, f->Nn, g[i], tau[i], f->r.p, nr[i], f->part.p, s);
+          launch_residual(f->d_new.p, f->Nn, g[i], tau[i], f->r.p, nr[i], f->part.p, f->norms.p, s);
         }
-        launch_colnorms2(f->r.p, g[i], 2 * f->Nn, nr[i], f->norms.p, s);
         HIP_CHECK(hipMemcpyAsync(nrm[i].data(), f->norms.p, sizeof(double) * 2 * nr[i], hipMemcpyDeviceToHost, s));
       }
       HIP_CHECK(hipStreamSynchronize(s));
@@ -1171,7 +1168,7 @@ int rw_residual(rw_refined* f, const double* g, const double* tau, int32_t nrhs,
   return guarded(f->ctx, [&]() {
     if (nrhs <= 0 || !g || !tau || !r) RW_THROW(RW_EINVAL, "bad arguments");
     refined_ensure_ws(f, nrhs);
-    launch_residual(f->d_new.p, f->Nn, g, tau, r, nrhs, f->part.p, f->ctx->stream);
+    launch_residual(f->d_new.p, f->Nn, g, tau, r, nrhs, f->part.p, nullptr, f->ctx->stream);
   });
 }
 
