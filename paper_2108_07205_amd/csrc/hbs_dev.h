@@ -16,12 +16,21 @@ struct HbsDev {
   DBuf<double> gen;              // packed generators: [F*; G] ((k + nin) x nin) and E (nin x k) per node
   DBuf<float> gen32;             // FP32 copy (optional)
   DBuf<double> groot;            // G_root (nroot x nroot)
+  const int* d_nroot = nullptr;  // GPU build: the root size on the device (nroot is then a bound)
   int64_t entries = 0;           // sum of |E| + |F| + |G| + |G_root|
   int max_rank = 0;
   // apply workspace
   DBuf<double> ws;
   int ws_nrhs = 0;
   std::vector<double*> U, GB, X;
+  // GPU build: node records and flags read back without a wait, checked by
+  // hbs_gpu_finish (records: pinned host memory of the building context)
+  struct Finish {
+    bool pending = false;
+    const void* rec = nullptr;
+    const int64_t* ctl = nullptr;
+    std::vector<size_t> fac_entry;
+  } fin;
   int64_t n_unknowns() const { return lev.size() > 1 ? S[L] : 0; }
 };
 
@@ -36,7 +45,13 @@ void hbs_dev_apply(HbsDev& h, const double* b, int64_t ldb, double* x, int64_t l
 // GPU build of the HBS inverse of the Nystrom matrix of one node set
 // (contiguous arcs, balanced binary tree with leaves of at most leaf_max
 // nodes).  d_nodes: device copy of h_nodes.  Same generator layout as
-// hbs_upload.  Throws RW_ESINGULAR on a singular node block or a rank that
-// exceeds the node sketch.
+// hbs_upload; the level descriptors are written on the device, the host
+// keeps bounds of the sizes (nroot, S, K, max_nin, max_k), and nothing waits
+// for the device: the apply can be enqueued at once on the same stream (or
+// after it).  hbs_gpu_finish, called once the stream has been synchronized,
+// throws RW_ESINGULAR on a singular node block or a rank that exceeds the
+// node sketch (the descriptors are then empty, so applies enqueued before
+// give zeros) and fills the statistics.
 void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRec>& h_nodes, int leaf_max,
                    double tol, uint64_t seed, HbsDev& out);
+void hbs_gpu_finish(HbsDev& w);

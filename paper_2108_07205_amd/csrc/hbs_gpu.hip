@@ -651,6 +651,36 @@ __global__ __launch_bounds__(64) void level_plan_kernel(GNode* __restrict__ gl, 
   }
 }
 
+// ---------------------------------------------------------------- 2c. apply descriptors
+// Once per build, over the node records 1 .. 2^(L+1) - 1 (level l at
+// [2^l, 2^(l+1))): level l's input sizes and ranks go to ints[2^(l+1) - 4 ..]
+// (nin, then k), its input offsets, skeleton offsets (ppos), [F*; G] and E
+// offsets to offs[2^(l+2) - 8 ..]; the root size to ints[2^(L+2) - 4].  A
+// failed build leaves every size zero, so that applies do nothing.
+__global__ __launch_bounds__(256) void apply_desc_kernel(const GNode* __restrict__ dg,
+                                                         const int64_t* __restrict__ ppos, int L,
+                                                         const int* __restrict__ fail, int* __restrict__ ints,
+                                                         int64_t* __restrict__ offs) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x + 1;
+  if (g >= (int64_t(2) << L)) return;
+  const bool bad = (fail[0] | fail[1] | fail[2]) != 0;
+  const GNode r = dg[g];
+  if (g == 1) {
+    ints[(int64_t(4) << L) - 4] = bad ? 0 : r.m;
+    return;
+  }
+  const int l = 63 - __clzll((unsigned long long)g);
+  const int64_t nn = int64_t(1) << l, j = g - nn;
+  int* ii = ints + 2 * nn - 4;
+  int64_t* oo = offs + 4 * nn - 8;
+  ii[j] = bad ? 0 : r.m;
+  ii[nn + j] = bad ? 0 : r.k;
+  oo[j] = r.cand_off;
+  oo[nn + j] = ppos[g];
+  oo[2 * nn + j] = r.up_off;
+  oo[3 * nn + j] = r.e_off;
+}
+
 // ---------------------------------------------------------------- 3. interpolation
 // grid (nodes, 2).  P = C(:, 0:k) C_J^{-1} -> U (side 0) or V (side 1), m x k
 // column-major; the skeleton dofs go to the parent's candidate list.  C_J
@@ -1697,7 +1727,7 @@ void hbs_dev_apply(HbsDev& w, const double* b, int64_t ldb, double* x, int64_t l
     else
       launch_hbs_up(w.lev[l], w.gen.p, in, ldin, w.U[l], w.K[l], w.GB[l], w.S[l], nrhs, s);
   }
-  launch_hbs_root(w.nroot, w.groot.p, w.U[1], w.K[1], w.X[0], w.S[0], nrhs, s);
+  launch_hbs_root(w.nroot, w.d_nroot, w.groot.p, w.U[1], w.K[1], w.X[0], w.S[0], nrhs, s);
   for (int l = 1; l <= w.L; ++l) {
     double* out = (l == w.L) ? x : w.X[l];
     const int64_t ldout = (l == w.L) ? ldx : w.S[l];
@@ -1706,6 +1736,42 @@ void hbs_dev_apply(HbsDev& w, const double* b, int64_t ldb, double* x, int64_t l
     else
       launch_hbs_down(w.lev[l], w.gen.p, w.X[l - 1], w.S[l - 1], w.GB[l], w.S[l], out, ldout, nrhs, s);
   }
+}
+
+void hbs_gpu_finish(HbsDev& w) {
+  if (!w.fin.pending) return;
+  w.fin.pending = false;
+  const GNode* hG = (const GNode*)w.fin.rec;
+  int hf[4];
+  memcpy(hf, w.fin.ctl, sizeof hf);
+  if (hf[1]) RW_THROW(RW_ESINGULAR, "HBS node rank reached the sketch size");
+  if (hf[2]) RW_THROW(RW_ESINGULAR, "HBS generator bound exceeded");
+  if (hf[0]) RW_THROW(RW_ESINGULAR, "singular block in the GPU HBS build (" + std::to_string(hf[0]) + ")");
+  rw_ctx* ctx = w.ctx;
+  w.entries = 0;
+  w.max_rank = 0;
+  for (int l = w.L; l >= 1; --l) {
+    const int nn = 1 << l;
+    const GNode* gl = hG + nn;
+    HbsLevelDev& d = w.lev[l];
+    d.up_entries = d.e_entries = 0;
+    double fl = 0.0;
+    for (int j = 0; j < nn; ++j) {
+      const GNode& g = gl[j];
+      d.up_entries += (int64_t)(g.k + g.m) * g.m;
+      d.e_entries += (int64_t)g.m * g.k;
+      w.entries += 2 * (int64_t)g.m * g.k + (int64_t)g.m * g.m;
+      w.max_rank = std::max(w.max_rank, g.k);
+      const double nm = g.m, kk2 = g.k;
+      fl += 2.0 * nm * nm * nm + 2.0 * (3.0 * nm * nm * kk2 + 3.0 * nm * kk2 * kk2) + 2.0 * kk2 * kk2 * kk2;
+    }
+    const size_t fe = w.fin.fac_entry[l];
+    if (fe != SIZE_MAX && fe < ctx->pending.size()) ctx->pending[fe].flops = fl;
+  }
+  const double nr = hG[1].m;
+  w.entries += (int64_t)(nr * nr);
+  const size_t fe = w.fin.fac_entry[0];
+  if (fe != SIZE_MAX && fe < ctx->pending.size()) ctx->pending[fe].flops = 2.0 * nr * nr * nr;
 }
 
 // ================================================================== GPU build
@@ -1792,9 +1858,11 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
   w.groot.alloc(ctx, (size_t)(2 * SK_KCAP) * (2 * SK_KCAP));
   HIP_CHECK(hipMemsetAsync(ctl.p, 0, sizeof(int64_t) * ctl.n, s));
   // pinned staging: node records (level l at [2^l, 2^(l+1))) and the leaf candidate lists
-  char* pin = (char*)ctx_pinned(ctx, sizeof(GNode) * (size_t)(int64_t(2) << L) + sizeof(int) * (size_t)(2 * N));
+  char* pin = (char*)ctx_pinned(ctx, sizeof(GNode) * (size_t)(int64_t(2) << L) + sizeof(int64_t) * 4 +
+                                          sizeof(int) * (size_t)(2 * N));
   GNode* hG = (GNode*)pin;
-  int* hC = (int*)(pin + sizeof(GNode) * (size_t)(int64_t(2) << L));
+  int64_t* hCtl = (int64_t*)(pin + sizeof(GNode) * (size_t)(int64_t(2) << L));
+  int* hC = (int*)(hCtl + 4);
   // leaf records carry their counts and offsets; a parent's are set on the
   // device from its children's ranks (level_plan_kernel)
   {
@@ -1860,6 +1928,8 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
       KERNEL_CHECK("node_inverse");
     }
   };
+  int mx_leaf = 0;
+  for (const GNode& g : G[L]) mx_leaf = std::max(mx_leaf, g.m);
   for (int l = L; l >= 1; --l) {
     const int nn = 1 << l;
     const bool leaf = l == L;
@@ -1926,89 +1996,40 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
   factor_launch(dg.p + 1, dg.p + 2, 1, 0, 1, candr.p + cand_base[0], candc.p + cand_base[0], Ub.p, Vb.p, w.groot.p,
                 -1, 0);
   stream_after(ctx, s, sf, 2);
-  // ---- read back the node records, the generator count and the flags
-  int64_t hctl[4];
-  HIP_CHECK(hipMemcpyAsync(hG, dg.p, sizeof(GNode) * (size_t)(int64_t(2) << L), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(hctl, ctl.p, sizeof hctl, hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
-  int hf[4];
-  memcpy(hf, hctl, sizeof hf);
-  const int64_t* hcnt = hctl + 2;
-  if (hf[1]) RW_THROW(RW_ESINGULAR, "HBS node rank reached the sketch size");
-  if (hf[2]) RW_THROW(RW_ESINGULAR, "HBS generator bound exceeded");
-  if (hf[0]) RW_THROW(RW_ESINGULAR, "singular block in the GPU HBS build (" + std::to_string(hf[0]) + ")");
-  // ---- level descriptors for the apply, statistics, factor flops
-  std::vector<std::vector<int>> lev_ints(L + 1);
-  std::vector<std::vector<int64_t>> lev_offs(L + 1);
+  // ---- apply descriptors on the device; the host keeps bounds of the
+  // sizes, and the records and flags are read back without a wait
+  w.d_ints.alloc(ctx, (size_t)((int64_t(4) << L) - 3));
+  w.d_offs.alloc(ctx, (size_t)((int64_t(8) << L) - 8));
+  hipLaunchKernelGGL(apply_desc_kernel, dim3(nblk((int64_t(2) << L) - 1)), dim3(256), 0, s, dg.p, dpar.p, L, failp,
+                     w.d_ints.p, w.d_offs.p);
+  KERNEL_CHECK("apply_desc");
+  for (int l = 1; l <= L; ++l) {
+    const int64_t nn = int64_t(1) << l;
+    HbsLevelDev& d = w.lev[l];
+    d.nnodes = (int)nn;
+    d.max_nin = l == L ? mx_leaf : 2 * SK_KCAP;
+    d.max_k = SK_KCAP;
+    d.S = l == L ? 2 * N : nn * 2 * SK_KCAP;
+    d.K = nn * SK_KCAP;
+    d.up_entries = d.e_entries = 0;
+    w.S[l] = d.S;
+    w.K[l] = d.K;
+    d.nin = w.d_ints.p + 2 * nn - 4;
+    d.k = d.nin + nn;
+    d.in_off = w.d_offs.p + 4 * nn - 8;
+    d.kout_off = d.in_off + nn;
+    d.up_off = d.in_off + 2 * nn;
+    d.e_off = d.in_off + 3 * nn;
+  }
+  w.nroot = 2 * SK_KCAP;
+  w.S[0] = w.nroot;
+  w.d_nroot = w.d_ints.p + (int64_t(4) << L) - 4;
   w.entries = 0;
   w.max_rank = 0;
-  for (int l = L; l >= 1; --l) {
-    const int nn = 1 << l;
-    const GNode* gl = hG + nn;
-    std::vector<int>& li = lev_ints[l];
-    std::vector<int64_t>& lo = lev_offs[l];
-    li.resize(2 * nn);
-    lo.resize(4 * nn);
-    int64_t kk = 0, off = 0;
-    int max_nin = 0, max_k = 0;
-    double fl = 0.0;
-    HbsLevelDev& d = w.lev[l];
-    for (int j = 0; j < nn; ++j) {
-      const GNode& g = gl[j];
-      li[j] = g.m;
-      li[nn + j] = g.k;
-      lo[j] = g.cand_off;
-      lo[nn + j] = kk;
-      kk += g.k;
-      off += g.m;
-      lo[2 * nn + j] = g.up_off;
-      lo[3 * nn + j] = g.e_off;
-      max_nin = std::max(max_nin, g.m);
-      max_k = std::max(max_k, g.k);
-      d.up_entries += (int64_t)(g.k + g.m) * g.m;
-      d.e_entries += (int64_t)g.m * g.k;
-      w.entries += 2 * (int64_t)g.m * g.k + (int64_t)g.m * g.m;
-      const double nm = g.m, kk2 = g.k;
-      fl += 2.0 * nm * nm * nm + 2.0 * (3.0 * nm * nm * kk2 + 3.0 * nm * kk2 * kk2) + 2.0 * kk2 * kk2 * kk2;
-    }
-    w.max_rank = std::max(w.max_rank, max_k);
-    d.nnodes = nn;
-    d.max_nin = max_nin;
-    d.max_k = max_k;
-    d.S = off;
-    d.K = kk;
-    w.S[l] = off;
-    w.K[l] = kk;
-    if (fac_entry[l] != SIZE_MAX && fac_entry[l] < ctx->pending.size()) ctx->pending[fac_entry[l]].flops = fl;
-  }
-  w.nroot = hG[1].m;
-  w.S[0] = hG[1].m;
-  w.entries += (int64_t)w.nroot * w.nroot;
-  if (fac_entry[0] != SIZE_MAX && fac_entry[0] < ctx->pending.size())
-    ctx->pending[fac_entry[0]].flops = 2.0 * (double)w.nroot * w.nroot * w.nroot;
-  // ---- pack level descriptors
-  std::vector<int> ints;
-  std::vector<int64_t> offs;
-  std::vector<size_t> ib(L + 1), ob(L + 1);
-  for (int l = 1; l <= L; ++l) {
-    ib[l] = ints.size();
-    ob[l] = offs.size();
-    ints.insert(ints.end(), lev_ints[l].begin(), lev_ints[l].end());
-    offs.insert(offs.end(), lev_offs[l].begin(), lev_offs[l].end());
-  }
-  w.d_ints.alloc(ctx, ints.size());
-  w.d_ints.upload(ints.data(), ints.size(), s);
-  w.d_offs.alloc(ctx, offs.size());
-  w.d_offs.upload(offs.data(), offs.size(), s);
-  for (int l = 1; l <= L; ++l) {
-    HbsLevelDev& d = w.lev[l];
-    const int nn = d.nnodes;
-    d.nin = w.d_ints.p + ib[l];
-    d.k = w.d_ints.p + ib[l] + nn;
-    d.in_off = w.d_offs.p + ob[l];
-    d.kout_off = w.d_offs.p + ob[l] + nn;
-    d.up_off = w.d_offs.p + ob[l] + 2 * nn;
-    d.e_off = w.d_offs.p + ob[l] + 3 * nn;
-  }
-  HIP_CHECK(hipStreamSynchronize(s));
+  HIP_CHECK(hipMemcpyAsync(hG, dg.p, sizeof(GNode) * (size_t)(int64_t(2) << L), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(hCtl, ctl.p, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, s));
+  w.fin.pending = true;
+  w.fin.rec = hG;
+  w.fin.ctl = hCtl;
+  w.fin.fac_entry = fac_entry;
 }

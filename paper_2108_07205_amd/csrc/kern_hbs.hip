@@ -124,16 +124,20 @@ __global__ __launch_bounds__(kThreads) void hbs_down_kernel(
           slab_sum<RB>(red, c, lane) + gb[io + row + (int64_t)(r0 + c) * ld_gb];
 }
 
-// grid (ceil(n / 64), ceil(nrhs / RB)).  out = G_root in.
+// grid (ceil(nmax / 64), ceil(nrhs / RB)).  out = G_root in; the root size
+// is n_dev[0] when n_dev is given (at most nmax), else nmax.
 template <int RB>
-__global__ __launch_bounds__(kThreads) void hbs_root_kernel(int n, const double* __restrict__ G,
+__global__ __launch_bounds__(kThreads) void hbs_root_kernel(int nmax, const int* __restrict__ n_dev,
+                                                            const double* __restrict__ G,
                                                             const double* __restrict__ in, int64_t ld_in,
                                                             double* __restrict__ out, int64_t ld_out, int nrhs) {
   extern __shared__ double sm[];
+  const int n = n_dev ? min(*n_dev, nmax) : nmax;
+  if (blockIdx.x * kRows >= n) return;  // whole workgroup
   const int r0 = blockIdx.y * RB, nr = min(RB, nrhs - r0);
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   double* xs = sm;
-  double* red = sm + n * RB;
+  double* red = sm + nmax * RB;
   for (int idx = tid; idx < n * RB; idx += kThreads) {
     const int col = idx / RB, c = idx - col * RB;
     xs[idx] = (c < nr) ? in[col + (int64_t)(r0 + c) * ld_in] : 0.0;
@@ -254,10 +258,13 @@ __global__ __launch_bounds__(kThreads) void hbs_down_mfma_kernel(
       });
 }
 
-__global__ __launch_bounds__(kThreads) void hbs_root_mfma_kernel(int n, const double* __restrict__ G,
+__global__ __launch_bounds__(kThreads) void hbs_root_mfma_kernel(int nmax, const int* __restrict__ n_dev,
+                                                                 const double* __restrict__ G,
                                                                  const double* __restrict__ in, int64_t ld_in,
                                                                  double* __restrict__ out, int64_t ld_out, int nrhs) {
   __shared__ double Bs[16][kMR + 2];
+  const int n = n_dev ? min(*n_dev, nmax) : nmax;
+  if (blockIdx.x * kRows >= n) return;
   const int r0 = blockIdx.y * kMR, nr = min(kMR, nrhs - r0);
   slab_mfma<double>(
       G, n, n, blockIdx.x, r0, nr, Bs, [&](int col, int c) { return in[col + (int64_t)c * ld_in]; },
@@ -286,7 +293,7 @@ void up_impl(const HbsLevelDev& L, const T* gen, const double* in, int64_t ld_in
   if (!L.nnodes || nrhs <= 0) return;
   // generators streamed once per pass of up to 8 right-hand sides
   const double passes = nrhs == 1 ? 1.0 : (nrhs < kMfmaMin ? (nrhs + 7) / 8 : (nrhs + kMR - 1) / kMR);
-  KernelTimer kt("hbs_up_kernel", 2.0 * L.up_entries * nrhs, sizeof(T) * (double)L.up_entries * passes);
+  KernelTimer kt("hbs_up_kernel", 2.0 * L.up_entries * nrhs, sizeof(T) * (double)L.up_entries * passes, s);
   if (nrhs == 1) {
     up_launch<T, 1>(L, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs, s);
   } else if (nrhs < kMfmaMin) {
@@ -315,7 +322,7 @@ void down_impl(const HbsLevelDev& L, const T* gen, const double* xhat, int64_t l
                int64_t ld_gb, double* out, int64_t ld_out, int nrhs, hipStream_t s) {
   if (!L.nnodes || nrhs <= 0) return;
   const double passes = nrhs == 1 ? 1.0 : (nrhs < kMfmaMin ? (nrhs + 7) / 8 : (nrhs + kMR - 1) / kMR);
-  KernelTimer kt("hbs_down_kernel", 2.0 * L.e_entries * nrhs, sizeof(T) * (double)L.e_entries * passes);
+  KernelTimer kt("hbs_down_kernel", 2.0 * L.e_entries * nrhs, sizeof(T) * (double)L.e_entries * passes, s);
   if (nrhs == 1) {
     down_launch<T, 1>(L, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs, s);
   } else if (nrhs < kMfmaMin) {
@@ -348,19 +355,19 @@ void launch_hbs_down_f32(const HbsLevelDev& L, const float* gen, const double* x
                          hipStream_t s) {
   down_impl<float>(L, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs, s);
 }
-void launch_hbs_root(int nroot, const double* G, const double* in, int64_t ld_in, double* out,
+void launch_hbs_root(int nroot, const int* d_nroot, const double* G, const double* in, int64_t ld_in, double* out,
                      int64_t ld_out, int nrhs, hipStream_t s) {
   if (nroot <= 0 || nrhs <= 0) return;
   const int nb = (nroot + kRows - 1) / kRows;
   if (nrhs >= kMfmaMin) {
-    hipLaunchKernelGGL(hbs_root_mfma_kernel, dim3(nb, (nrhs + kMR - 1) / kMR), dim3(kThreads), 0, s, nroot, G, in,
-                       ld_in, out, ld_out, nrhs);
+    hipLaunchKernelGGL(hbs_root_mfma_kernel, dim3(nb, (nrhs + kMR - 1) / kMR), dim3(kThreads), 0, s, nroot, d_nroot,
+                       G, in, ld_in, out, ld_out, nrhs);
   } else if (nrhs == 1) {
-    hipLaunchKernelGGL((hbs_root_kernel<1>), dim3(nb, 1), dim3(kThreads), slab_lds(nroot * 1, 1), s, nroot, G, in,
-                       ld_in, out, ld_out, nrhs);
+    hipLaunchKernelGGL((hbs_root_kernel<1>), dim3(nb, 1), dim3(kThreads), slab_lds(nroot * 1, 1), s, nroot, d_nroot,
+                       G, in, ld_in, out, ld_out, nrhs);
   } else {
     hipLaunchKernelGGL((hbs_root_kernel<8>), dim3(nb, (nrhs + 7) / 8), dim3(kThreads), slab_lds(nroot * 8, 8), s,
-                       nroot, G, in, ld_in, out, ld_out, nrhs);
+                       nroot, d_nroot, G, in, ld_in, out, ld_out, nrhs);
   }
   KERNEL_CHECK("hbs_root");
 }

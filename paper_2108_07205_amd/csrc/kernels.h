@@ -27,8 +27,9 @@ void launch_hbs_up(const HbsLevelDev& L, const double* gen, const double* in, in
                    double* bhat, int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s);
 void launch_hbs_up_f32(const HbsLevelDev& L, const float* gen, const double* in, int64_t ld_in,
                        double* bhat, int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s);
-// root: out = G_root in.
-void launch_hbs_root(int nroot, const double* G, const double* in, int64_t ld_in, double* out,
+// root: out = G_root in (nroot x nroot, ld nroot); with d_nroot the size is
+// read on the device (at most nroot).
+void launch_hbs_root(int nroot, const int* d_nroot, const double* G, const double* in, int64_t ld_in, double* out,
                      int64_t ld_out, int nrhs, hipStream_t s);
 // down: out = E xhat + gb.
 void launch_hbs_down(const HbsLevelDev& L, const double* gen, const double* xhat, int64_t ld_xh,

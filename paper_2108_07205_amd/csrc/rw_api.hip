@@ -415,12 +415,21 @@ void woodbury_ref_apply(rw_refined* f, int nrhs) {
   hbs_apply(w, f->gext.p, M, f->y.p, M, nrhs, w->precision == RW_F32);
 }
 
-void woodbury_out(rw_refined* f, double* dst, int nrhs, bool accumulate) {
+// The A_pp^{-1} block of y on stream s.
+void woodbury_app_apply(rw_refined* f, int nrhs, hipStream_t s) {
+  const int64_t M = 2 * f->Next, Mo = 2 * f->No;
+  PhaseTimer t(f->ctx, "a6_app_solve", 2.0 * f->app_hbs.entries * nrhs, 8.0 * f->app_hbs.entries * ((nrhs + 7) / 8),
+               s);
+  hbs_dev_apply(f->app_hbs, f->gext.p + Mo, M, f->y.p + Mo, M, nrhs, false, s);
+}
+
+// app_done: the A_pp^{-1} block of y is already in (woodbury_app_apply).
+void woodbury_out(rw_refined* f, double* dst, int nrhs, bool accumulate, bool app_done = false) {
   hipStream_t s = f->ctx->stream;
   const int64_t M = 2 * f->Next, Mo = 2 * f->No, Mp = 2 * f->Np;
-  if (f->Np > 0 && f->app_hbs_on) {
-    PhaseTimer t(f->ctx, "a6_app_solve", 2.0 * f->app_hbs.entries * nrhs, 8.0 * f->app_hbs.entries * ((nrhs + 7) / 8));
-    hbs_dev_apply(f->app_hbs, f->gext.p + Mo, M, f->y.p + Mo, M, nrhs, false, s);
+  if (app_done) {
+  } else if (f->Np > 0 && f->app_hbs_on) {
+    woodbury_app_apply(f, nrhs, s);
   } else if (f->Np > 0) {
     PhaseTimer t(f->ctx, "a6_app_solve", 2.0 * (double)Mp * Mp * nrhs, 8.0 * (double)Mp * Mp * nrhs);
     HIP_CHECK(hipMemcpy2DAsync(f->y.p + Mo, sizeof(double) * M, f->gext.p + Mo, sizeof(double) * M,
@@ -438,10 +447,22 @@ void woodbury_out(rw_refined* f, double* dst, int nrhs, bool accumulate) {
 }
 
 // dst (2 N_n x nrhs) = (A~ + L R)^{-1} src via eq. (wood); accumulate: dst += ...
+// A~ is block diagonal, so the A_pp^{-1} block (GPU-built HBS) runs on the
+// side stream while the reference inverse runs on the main one.
 void woodbury_apply(rw_refined* f, const double* src, double* dst, int nrhs, bool accumulate) {
   woodbury_in(f, src, nrhs);
-  woodbury_ref_apply(f, nrhs);
-  woodbury_out(f, dst, nrhs, accumulate);
+  const bool fork = f->Np > 0 && f->app_hbs_on;
+  if (fork) {
+    rw_ctx* ctx = f->ctx;
+    const hipStream_t side = ctx_side_stream(ctx);
+    stream_after(ctx, side, ctx->stream, 5);
+    woodbury_app_apply(f, nrhs, side);
+    woodbury_ref_apply(f, nrhs);
+    stream_after(ctx, ctx->stream, side, 6);
+  } else {
+    woodbury_ref_apply(f, nrhs);
+  }
+  woodbury_out(f, dst, nrhs, accumulate, fork);
 }
 
 void validate_selection(const rw_wall* w, const int32_t* ids, const int32_t* levels, int n_sel) {
@@ -754,6 +775,9 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
     if (info) RW_THROW(RW_ESINGULAR, "singular Woodbury operator W (pivot " + std::to_string(info) + ")");
   }
   HIP_CHECK(hipStreamSynchronize(s));
+  // the A_pp build's flags and statistics (read back on its stream, which
+  // the main stream has waited for)
+  if (f.app_hbs_on) hbs_gpu_finish(f.app_hbs);
   prof_flush(ctx);
   f.info.n_k = f.Nk;
   f.info.n_c = f.Nc;
