@@ -11,6 +11,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <unordered_map>
 #include <stdexcept>
 #include <string>
 #include <thread>
@@ -72,15 +73,20 @@ struct rw_ctx {
   size_t sync_words = 0;
   // caching allocator: freed blocks are kept by size for reuse
   std::multimap<size_t, void*> cache;
+  std::unordered_map<void*, size_t> live;   // block sizes of the allocations in use
   size_t cached = 0;
   // second stream for work that runs beside `stream` inside one call
   // (non-blocking, default priority; created on first use) and the
   // timing-free events that order the two
   hipStream_t side = nullptr;
   std::vector<hipEvent_t> order_events;
-  // pinned host staging for small per-call transfers (grow-only)
+  // pinned host staging for small per-call transfers (grow-only), and a
+  // separate pinned area for small read-backs (a pageable one would keep
+  // the HIP runtime busy, and the ctx's other thread waiting, until the copy)
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
+  void* rb = nullptr;
+  size_t rb_bytes = 0;
   // phase profiler (HIP events on `stream`)
   bool prof = false;
   struct Pending { std::string name; hipEvent_t a, b; double flops, bytes; };
@@ -121,6 +127,9 @@ hipEvent_t ctx_order_event(rw_ctx* ctx, int i);
 // Pinned host staging of at least `bytes` (grow-only; growing first waits
 // for the ctx's streams, so no copy from the old buffer is still in flight).
 void* ctx_pinned(rw_ctx* ctx, size_t bytes);
+// Pinned read-back area of at least `bytes` (grow-only; its contents are
+// valid until the next call that reads back on this ctx).
+void* ctx_readback(rw_ctx* ctx, size_t bytes);
 // `waiter` waits for everything enqueued on `src` so far (event i).
 void stream_after(rw_ctx* ctx, hipStream_t waiter, hipStream_t src, int i);
 

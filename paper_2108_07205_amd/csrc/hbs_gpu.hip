@@ -1842,9 +1842,13 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
   DBuf<double> dhA(ctx, (int64_t(1) << L) * SK_KCAP * SK_KCAP), dhB(ctx, (int64_t(1) << L) * SK_KCAP * SK_KCAP);
   DBuf<double> ws(ctx, ws_bound);
   DBuf<int64_t> dpar(ctx, (size_t)(int64_t(2) << L));  // level l at [2^l, 2^(l+1))
-  // sketch partial sums: the largest (candidates x split count) of any level
+  // sketch partial sums: the largest (candidates x split count) of any level.
+  // About 384 workgroups per level (1.5 per compute unit): all of them
+  // resident beside the concurrent row-ID and factor kernels, each with
+  // several chunks to spread its fixed cost (candidate records, near-node
+  // scan, partial rows) over
   auto level_split = [&](int64_t nn) {
-    int ns = (int)std::min<int64_t>(64, std::max<int64_t>(1, 1024 / (2 * nn)));
+    int ns = (int)std::min<int64_t>(64, std::max<int64_t>(1, 384 / (2 * nn)));
     return (int)std::min<int64_t>(ns, std::max<int64_t>(1, N / 64));
   };
   int64_t part_len = 0;

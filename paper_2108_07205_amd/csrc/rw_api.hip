@@ -14,20 +14,33 @@
 
 // ======================================================================== ctx
 // Caching allocator: a freed block goes back to ctx->cache and is reused by a
-// later request of the same or a slightly smaller size, so the per-step
-// refine / solve cycle does not call hipMalloc or hipFree once warm.
+// later request of at most its size and at least half of it, so the
+// per-step refine / solve cycle does not call hipMalloc or hipFree once warm
+// (hipMalloc also holds up kernel launches from the ctx's other thread).
+// Requests are rounded up to size classes (256-byte multiples up to 64 KiB,
+// then four classes per octave), so that the sizes of successive
+// refinements, which differ by some percent, fall on the same few blocks.
 // Bytes held by ctx and by the ctx that shares its budget (owner or helper).
 static size_t budget_used(const rw_ctx* ctx) {
   const rw_ctx* other = ctx->owner ? ctx->owner : ctx->aux;
   return ctx->used.load() + (other ? other->used.load() : 0);
 }
 
+static size_t size_class(size_t b) {
+  b = (b + 255) & ~size_t(255);
+  if (b <= 65536) return b;
+  const int e = 63 - __builtin_clzll((unsigned long long)b);
+  const size_t base = size_t(1) << e, step = base / 4;
+  return base + (b - base + step - 1) / step * step;
+}
+
 void* dev_alloc(rw_ctx* ctx, size_t bytes) {
-  bytes = (bytes + 255) & ~size_t(255);
+  bytes = size_class(bytes);
   auto it = ctx->cache.lower_bound(bytes);
-  if (it != ctx->cache.end() && it->first <= bytes + bytes / 4 + 4096) {
+  if (it != ctx->cache.end() && it->first <= 2 * bytes) {
     void* p = it->second;
     ctx->cached -= it->first;
+    ctx->live[p] = it->first;
     ctx->cache.erase(it);
     return p;
   }
@@ -54,14 +67,22 @@ void* dev_alloc(rw_ctx* ctx, size_t bytes) {
     }
   }
   ctx->used += bytes;
+  ctx->live[p] = bytes;
   return p;
 }
 
-// Blocks return to the cache; the caller's stream order makes reuse safe
-// (all library work on a ctx is issued on its one stream).
+// Blocks return to the cache at their full size; the callers' stream order
+// makes reuse safe (work on a ctx's second stream is joined back into its
+// main stream before the buffers it uses are released).
 void dev_free(rw_ctx* ctx, void* p, size_t bytes) {
   if (!p) return;
-  bytes = (bytes + 255) & ~size_t(255);
+  auto it = ctx->live.find(p);
+  if (it != ctx->live.end()) {
+    bytes = it->second;
+    ctx->live.erase(it);
+  } else {
+    bytes = size_class(bytes);
+  }
   ctx->cache.emplace(bytes, p);
   ctx->cached += bytes;
 }
@@ -163,6 +184,20 @@ void* ctx_pinned(rw_ctx* ctx, size_t bytes) {
   HIP_CHECK(hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault));
   ctx->pinned_bytes = bytes;
   return ctx->pinned;
+}
+
+void* ctx_readback(rw_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->rb_bytes) return ctx->rb;
+  if (ctx->rb) {
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    (void)hipHostFree(ctx->rb);
+    ctx->rb = nullptr;
+    ctx->rb_bytes = 0;
+  }
+  bytes = std::max<size_t>(bytes, 4096);
+  HIP_CHECK(hipHostMalloc(&ctx->rb, bytes, hipHostMallocDefault));
+  ctx->rb_bytes = bytes;
+  return ctx->rb;
 }
 
 void stream_after(rw_ctx* ctx, hipStream_t waiter, hipStream_t src, int i) {
@@ -272,6 +307,7 @@ static void ctx_destroy_aux(rw_ctx* ctx) {
     for (auto e : a->order_events) (void)hipEventDestroy(e);
     if (a->side) (void)hipStreamDestroy(a->side);
     if (a->pinned) (void)hipHostFree(a->pinned);
+    if (a->rb) (void)hipHostFree(a->rb);
     (void)hipStreamDestroy(a->stream);
     delete a;
     ctx->aux = nullptr;
@@ -706,10 +742,11 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
                                                        rm, s);
       const bool qp = f.Np > 0 && launch_rowid_enqueue(ctx, Yp.p, 2 * f.Np, ncols, tol, kmax, dJ.p + 128, Cp.p, work.p,
                                                        rk + 1, rm + 2, s);
-      int hk[2] = {0, 0};
-      unsigned long long hm[4] = {0, 0, 0, 0};
-      HIP_CHECK(hipMemcpyAsync(hk, rk, sizeof(hk), hipMemcpyDeviceToHost, s));
-      HIP_CHECK(hipMemcpyAsync(hm, rm, sizeof(hm), hipMemcpyDeviceToHost, s));
+      char* rbk = (char*)ctx_readback(ctx, 64 + 4 * sizeof(unsigned long long));
+      int* hk = (int*)rbk;
+      unsigned long long* hm = (unsigned long long*)(rbk + 64);
+      HIP_CHECK(hipMemcpyAsync(hk, rk, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipMemcpyAsync(hm, rm, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
       HIP_CHECK(hipStreamSynchronize(s));
       f.k_k = qk ? hk[0] : 0;
       f.k_p = qp ? hk[1] : 0;
@@ -769,9 +806,10 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
     DBuf<double> part(ctx, gemm_tn_part_doubles(M, f.k, f.k));
     launch_gemm_tn(f.R.p, M, f.X.p, M, M, f.k, f.k, f.W.p, f.k, true, part.p, s);
     launch_small_inverse(f.W.p, f.k, dinfo.p + 1, s);
-    int info = 0;
-    HIP_CHECK(hipMemcpyAsync(&info, dinfo.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    int* hinfo = (int*)ctx_readback(ctx, sizeof(int));
+    HIP_CHECK(hipMemcpyAsync(hinfo, dinfo.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
+    const int info = *hinfo;
     if (info) RW_THROW(RW_ESINGULAR, "singular Woodbury operator W (pivot " + std::to_string(info) + ")");
   }
   HIP_CHECK(hipStreamSynchronize(s));
@@ -855,6 +893,7 @@ void rw_ctx_destroy(rw_ctx* ctx) {
   for (auto e : ctx->order_events) (void)hipEventDestroy(e);
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->rb) (void)hipHostFree(ctx->rb);
   delete ctx;
 }
 
@@ -1051,8 +1090,10 @@ int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau) {
         PhaseTimer t(f->ctx, "a8_residual", 26.0 * (double)f->Nn * f->Nn * nrhs, 0.0);
         launch_residual(f->d_new.p, f->Nn, g, tau, f->r.p, nrhs, f->part.p, f->norms.p, s);
       }
-      HIP_CHECK(hipMemcpyAsync(nrm.data(), f->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
+      double* hn = (double*)ctx_readback(f->ctx, sizeof(double) * 2 * nrhs);
+      HIP_CHECK(hipMemcpyAsync(hn, f->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
       HIP_CHECK(hipStreamSynchronize(s));
+      std::copy(hn, hn + 2 * nrhs, nrm.begin());
       worst = 0;
       for (int c = 0; c < nrhs; ++c) {
         const double rel = nrm[nrhs + c] > 0 ? std::sqrt(nrm[c] / nrm[nrhs + c]) : std::sqrt(nrm[c]);
