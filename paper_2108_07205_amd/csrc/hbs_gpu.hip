@@ -70,6 +70,46 @@ __device__ __forceinline__ void a_blk(const NodeRec& t, const NodeRec& s, bool s
   B[3] = cf * ry * ry + s.w * t.ny * s.ny;
 }
 
+// ---------------------------------------------------------------- 0. proxy circles
+// One workgroup per node record g = 1 .. 2^(L+1) - 1 (level l at
+// [2^l, 2^(l+1))): the centroid (cx, cy) of the node's points [n0, n1) and
+// the proxy radius rp = SK_RATIO max |x_i - c|, by block sums and maxima in
+// a fixed order.
+__global__ __launch_bounds__(256) void node_geom_kernel(GNode* __restrict__ dg, const NodeRec* __restrict__ nd) {
+  __shared__ double red[3][4];
+  GNode& g = dg[blockIdx.x + 1];
+  const int64_t n0 = g.n0, n1 = g.n1;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double sx = 0.0, sy = 0.0;
+  for (int64_t i = n0 + tid; i < n1; i += 256) {
+    sx += nd[i].x;
+    sy += nd[i].y;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sx += __shfl_xor(sx, o);
+    sy += __shfl_xor(sy, o);
+  }
+  if (lane == 0) { red[0][w] = sx; red[1][w] = sy; }
+  __syncthreads();
+  const double inv = 1.0 / (double)(n1 - n0);
+  const double cx = ((red[0][0] + red[0][1]) + (red[0][2] + red[0][3])) * inv;
+  const double cy = ((red[1][0] + red[1][1]) + (red[1][2] + red[1][3])) * inv;
+  double r2 = 0.0;
+  for (int64_t i = n0 + tid; i < n1; i += 256) {
+    const double dx = nd[i].x - cx, dy = nd[i].y - cy;
+    r2 = fmax(r2, dx * dx + dy * dy);
+  }
+  r2 = wave_max_nonneg(r2);
+  if (lane == 0) red[2][w] = r2;
+  __syncthreads();
+  if (tid == 0) {
+    g.cx = cx;
+    g.cy = cy;
+    g.rp = SK_RATIO * sqrt(fmax(fmax(red[2][0], red[2][1]), fmax(red[2][2], red[2][3])));
+  }
+}
+
 // ---------------------------------------------------------------- 1. sketch
 // grid (nodes, 2): side 0 = row sketch of candr, side 1 = column sketch of candc.
 // thread t: candidate row (t & 127) of the current pass, columns 48*(t >> 7) ..
@@ -1793,15 +1833,6 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
       memset(&g, 0, sizeof g);
       g.n0 = (j * N) >> l;
       g.n1 = ((j + 1) * N) >> l;
-      double cx = 0, cy = 0;
-      for (int64_t i = g.n0; i < g.n1; ++i) { cx += hn[i].x; cy += hn[i].y; }
-      cx /= double(g.n1 - g.n0);
-      cy /= double(g.n1 - g.n0);
-      double R = 0;
-      for (int64_t i = g.n0; i < g.n1; ++i) R = std::max(R, std::hypot(hn[i].x - cx, hn[i].y - cy));
-      g.cx = cx;
-      g.cy = cy;
-      g.rp = SK_RATIO * R;
       if (l == L) g.m = (int)(2 * (g.n1 - g.n0));
     }
   }
@@ -1875,6 +1906,8 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     for (int l = 0; l <= L; ++l) memcpy(hG + (int64_t(1) << l), G[l].data(), sizeof(GNode) * G[l].size());
     memset(hG, 0, sizeof(GNode));
     HIP_CHECK(hipMemcpyAsync(dg.p, hG, sizeof(GNode) * (size_t)(int64_t(2) << L), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(node_geom_kernel, dim3((unsigned)((int64_t(2) << L) - 1)), dim3(256), 0, s, dg.p, d_nodes);
+    KERNEL_CHECK("node_geom");
     for (int64_t d = 0; d < 2 * N; ++d) hC[d] = (int)d;
     HIP_CHECK(hipMemcpyAsync(candr.p + cand_base[L], hC, sizeof(int) * 2 * N, hipMemcpyHostToDevice, s));
     HIP_CHECK(hipMemcpyAsync(candc.p + cand_base[L], hC, sizeof(int) * 2 * N, hipMemcpyHostToDevice, s));

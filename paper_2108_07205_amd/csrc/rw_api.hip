@@ -661,13 +661,19 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
     for (int i : c_ref) bbox(rn[i]);
     for (const NodeRec& q : pnodes) bbox(q);
     const double fcx = 0.5 * (bx0 + bx1), fcy = 0.5 * (by0 + by1);
-    double rho = 0.0;
-    for (int i : c_ref) rho = std::max(rho, std::hypot(rn[i].x - fcx, rn[i].y - fcy));
-    for (const NodeRec& q : pnodes) rho = std::max(rho, std::hypot(q.x - fcx, q.y - fcy));
+    auto d2 = [&](const NodeRec& q) { return (q.x - fcx) * (q.x - fcx) + (q.y - fcy) * (q.y - fcy); };
+    double rho2 = 0.0;
+    for (int i : c_ref) rho2 = std::max(rho2, d2(rn[i]));
+    for (const NodeRec& q : pnodes) rho2 = std::max(rho2, d2(q));
+    const double rho = std::sqrt(rho2), near2 = FAR_RATIO * FAR_RATIO * rho2;
     std::vector<int> near_a, far_a, near_ref, far_ref;
+    near_a.reserve(f.Nk);
+    far_a.reserve(f.Nk);
+    near_ref.reserve(f.Nk);
+    far_ref.reserve(f.Nk);
     for (int64_t a = 0; a < f.Nk; ++a) {
       const NodeRec& q = rn[k_ref[a]];
-      const bool nr = std::hypot(q.x - fcx, q.y - fcy) < FAR_RATIO * rho;
+      const bool nr = d2(q) < near2;
       (nr ? near_a : far_a).push_back((int)a);
       (nr ? near_ref : far_ref).push_back(k_ref[a]);
     }
