@@ -332,6 +332,7 @@ def main():
         "value_with_kernel_events": prof_rate,
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
+        "slowest_steps_ms": {str(int(i)): round(float(lat[i]), 3) for i in np.argsort(lat)[::-1][:5]},
         "gate": {"passed": ok, "of": args.steps, "criterion": "||g - A tau||/||g|| <= 1e-13 (FP64 residual)",
                  "max_resid": float(max(i["resid"] for i in infos)),
                  "k_range": [int(min(i["k"] for i in infos)), int(max(i["k"] for i in infos))],

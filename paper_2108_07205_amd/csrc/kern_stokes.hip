@@ -21,11 +21,12 @@ constexpr double kInvPi = 0.31830988618379067154;
 // ---------------------------------------------------------------- residual
 constexpr int RT = 128;  // targets per block
 constexpr int RRB = 4;   // right-hand sides per pass
+constexpr int RT1 = 2;   // targets per thread of the one-right-hand-side kernel
 
 int resid_splits(int64_t n, int nrhs) {
   if (nrhs == 1) {
-    // scalar-broadcast kernel: 256 targets per workgroup; about 8 waves per SIMD
-    const int64_t tb = (n + 255) / 256;
+    // scalar-broadcast kernel: 256 RT1 targets per workgroup; about 8 waves per SIMD
+    const int64_t tb = (n + 256 * RT1 - 1) / (256 * RT1);
     int64_t s = (2048 + tb - 1) / tb;
     s = s < 1 ? 1 : (s > 64 ? 64 : s);
     const int64_t maxs = (n + 63) / 64;   // at least 64 sources per split
@@ -167,25 +168,31 @@ __global__ __launch_bounds__(256) void resid_pack_kernel(const NodeRec* __restri
   if (threadIdx.x == 0) fpart[blockIdx.x] = t;
 }
 
-// grid (ceil(n / 256), 1, nsplit): thread = target, sources of the split in
-// order (the same index in every lane).
+// grid (ceil(n / (256 RT1)), 1, nsplit): thread = RT1 targets (256 apart),
+// sources of the split in order (the same index in every lane, so each
+// source record is one scalar load shared by the RT1 targets).
 __global__ __launch_bounds__(256) void resid_scalar_kernel(const NodeRec* __restrict__ nd, int64_t n,
                                                            const double* __restrict__ pk, int nsplit,
                                                            double* __restrict__ part) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t t0 = (int64_t)blockIdx.x * 256 * RT1 + threadIdx.x;
   const int z = blockIdx.z;
   const int64_t chunk = (n + nsplit - 1) / nsplit;
   const int64_t s0 = z * chunk, s1 = min(n, s0 + chunk);
-  double xi = 0, yi = 0;
-  if (t < n) { xi = nd[t].x; yi = nd[t].y; }
-  double ax = 0.0, ay = 0.0;
+  double xi[RT1], yi[RT1], ax[RT1], ay[RT1];
+#pragma unroll
+  for (int u = 0; u < RT1; ++u) {
+    const int64_t t = t0 + 256 * u;
+    xi[u] = t < n ? nd[t].x : 0.0;
+    yi[u] = t < n ? nd[t].y : 0.0;
+    ax[u] = ay[u] = 0.0;
+  }
   // r = 0 only on the diagonal, where the clamp keeps 1 / r^4 finite and
   // the zero r . n makes the term vanish
-  auto term = [&](const double* q, double rx, double ry, double inv) {
+  auto term = [&](int u, const double* q, double rx, double ry, double inv) {
     const double cf = (rx * q[2] + ry * q[3]) * inv * inv;
     const double d = cf * (rx * q[4] + ry * q[5]);
-    ax += d * rx;
-    ay += d * ry;
+    ax[u] += d * rx;
+    ay[u] += d * ry;
   };
   int64_t sj = s0;
   // four sources per reciprocal: 1 / (a b c d) and products give the four
@@ -195,27 +202,37 @@ __global__ __launch_bounds__(256) void resid_scalar_kernel(const NodeRec* __rest
     const double* q1 = q0 + RPK;
     const double* q2 = q1 + RPK;
     const double* q3 = q2 + RPK;
-    const double x0 = xi - q0[0], y0 = yi - q0[1], x1 = xi - q1[0], y1 = yi - q1[1];
-    const double x2 = xi - q2[0], y2 = yi - q2[1], x3 = xi - q3[0], y3 = yi - q3[1];
-    const double a = fmax(x0 * x0 + y0 * y0, 1e-150), b = fmax(x1 * x1 + y1 * y1, 1e-150);
-    const double c = fmax(x2 * x2 + y2 * y2, 1e-150), d = fmax(x3 * x3 + y3 * y3, 1e-150);
-    const double ab = a * b, cd = c * d;
-    const double y = rcp_nr2(ab * cd);
-    const double yab = y * cd, ycd = y * ab;
-    term(q0, x0, y0, b * yab);
-    term(q1, x1, y1, a * yab);
-    term(q2, x2, y2, d * ycd);
-    term(q3, x3, y3, c * ycd);
+#pragma unroll
+    for (int u = 0; u < RT1; ++u) {
+      const double x0 = xi[u] - q0[0], y0 = yi[u] - q0[1], x1 = xi[u] - q1[0], y1 = yi[u] - q1[1];
+      const double x2 = xi[u] - q2[0], y2 = yi[u] - q2[1], x3 = xi[u] - q3[0], y3 = yi[u] - q3[1];
+      const double a = fmax(x0 * x0 + y0 * y0, 1e-150), b = fmax(x1 * x1 + y1 * y1, 1e-150);
+      const double c = fmax(x2 * x2 + y2 * y2, 1e-150), d = fmax(x3 * x3 + y3 * y3, 1e-150);
+      const double ab = a * b, cd = c * d;
+      const double y = rcp_nr2(ab * cd);
+      const double yab = y * cd, ycd = y * ab;
+      term(u, q0, x0, y0, b * yab);
+      term(u, q1, x1, y1, a * yab);
+      term(u, q2, x2, y2, d * ycd);
+      term(u, q3, x3, y3, c * ycd);
+    }
   }
   for (; sj < s1; ++sj) {
     const double* q = pk + sj * RPK;
-    const double rx = xi - q[0], ry = yi - q[1];
-    term(q, rx, ry, rcp_nr2(fmax(rx * rx + ry * ry, 1e-150)));
+#pragma unroll
+    for (int u = 0; u < RT1; ++u) {
+      const double rx = xi[u] - q[0], ry = yi[u] - q[1];
+      term(u, q, rx, ry, rcp_nr2(fmax(rx * rx + ry * ry, 1e-150)));
+    }
   }
-  if (t < n) {
-    double* p = part + (int64_t)z * 2 * n;
-    p[2 * t] = ax;
-    p[2 * t + 1] = ay;
+  double* p = part + (int64_t)z * 2 * n;
+#pragma unroll
+  for (int u = 0; u < RT1; ++u) {
+    const int64_t t = t0 + 256 * u;
+    if (t < n) {
+      p[2 * t] = ax[u];
+      p[2 * t + 1] = ay[u];
+    }
   }
 }
 
@@ -583,7 +600,8 @@ void launch_residual(const NodeRec* nodes, int64_t n, const double* g, const dou
     if (nrhs == 1) {
       double* pk = npart + (size_t)2 * nb * nrhs;
       hipLaunchKernelGGL(resid_pack_kernel, dim3(nb), dim3(256), 0, s, nodes, n, tau, pk, fpart);
-      hipLaunchKernelGGL(resid_scalar_kernel, dim3(nb, 1, ns), dim3(256), 0, s, nodes, n, pk, ns, part);
+      hipLaunchKernelGGL(resid_scalar_kernel, dim3(blocks(n, 256 * RT1), 1, ns), dim3(256), 0, s, nodes, n, pk, ns,
+                         part);
     } else {
       hipLaunchKernelGGL(flux_part_kernel, dim3(nb, nrhs), dim3(256), 0, s, nodes, n, tau, fpart);
       hipLaunchKernelGGL(resid_tiles_kernel<RRB>, dim3(blocks(n, RT), (nrhs + RRB - 1) / RRB, ns), dim3(RT), 0, s,
