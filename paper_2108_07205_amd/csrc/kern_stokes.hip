@@ -21,7 +21,7 @@ constexpr double kInvPi = 0.31830988618379067154;
 // ---------------------------------------------------------------- residual
 constexpr int RT = 128;  // targets per block
 constexpr int RRB = 4;   // right-hand sides per pass
-constexpr int RT1 = 2;   // targets per thread of the one-right-hand-side kernel
+constexpr int RT1 = 4;   // targets per thread of the one-right-hand-side kernel
 
 int resid_splits(int64_t n, int nrhs) {
   if (nrhs == 1) {
