@@ -195,6 +195,11 @@ def main():
         ref.close()
         return rc == rw.RW_OK, info
 
+    # Python's cyclic garbage collector stays off from the warmup through the
+    # timed passes (as timeit does), so that no collection lands in a step
+    # and the GPU is not left idle between the warmup and the timed region
+    gc.collect()
+    gc.disable()
     for i in range(args.warmup):
         step(10_000 + i)
 
@@ -206,10 +211,6 @@ def main():
             ctx.profile(True)
             ctx.profile_reset()
         lat, ok, infos = [], 0, []
-        # Python's cyclic garbage collector stays off in the timed loop (as
-        # timeit does), so that a collection pass does not land in a step
-        gc.collect()
-        gc.disable()
         torch.cuda.synchronize()
         t_start = time.perf_counter()
         for s in range(args.steps):
@@ -220,7 +221,6 @@ def main():
             infos.append(info)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
-        gc.enable()
         ph = ctx.profile_json() if profile else {}
         ctx.profile(False)
         return ok, elapsed, np.array(lat), infos, ph
@@ -234,6 +234,8 @@ def main():
     if not args.no_profile:
         okp, elp, _, _, phases = timed(True)
         prof_rate = okp / elp
+
+    gc.enable()
 
     # ---- side measurements (not the headline): solves with resident factors
     # (the paper's per-RHS direct solve time) and the FP32-generator mode

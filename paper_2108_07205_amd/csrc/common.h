@@ -127,6 +127,9 @@ hipEvent_t ctx_order_event(rw_ctx* ctx, int i);
 // Pinned host staging of at least `bytes` (grow-only; growing first waits
 // for the ctx's streams, so no copy from the old buffer is still in flight).
 void* ctx_pinned(rw_ctx* ctx, size_t bytes);
+// Allow kernel fn at least `bytes` of dynamic LDS on the current device
+// (hipFuncSetAttribute once per kernel, device and larger size).
+void func_lds_at_least(const void* fn, int bytes);
 // Pinned read-back area of at least `bytes` (grow-only; its contents are
 // valid until the next call that reads back on this ctx).
 void* ctx_readback(rw_ctx* ctx, size_t bytes);

@@ -1933,9 +1933,9 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
   double* dh_child = dhB.p;
   double* dh_cur = dhA.p;
   const size_t shi = 2 * sizeof(double) * SK_KCAP * SK_KCAP;
-  HIP_CHECK(hipFuncSetAttribute((const void*)node_interp_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shi));
+  func_lds_at_least((const void*)node_interp_kernel, (int)shi);
   const size_t shv = INV_LDS_BYTES;
-  HIP_CHECK(hipFuncSetAttribute((const void*)node_inverse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shv));
+  func_lds_at_least((const void*)node_inverse_kernel, (int)shv);
   constexpr int MANY = 1 << 30;
   // profiler entries of the factor launches (their flops are known once the ranks are read back)
   std::vector<size_t> fac_entry(L + 1, SIZE_MAX);
@@ -1950,8 +1950,10 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
       KERNEL_CHECK("node_factor_bordered");
     }
     if (ctx->prof && !ctx->pending.empty()) fac_entry[lvl] = ctx->pending.size() - 1;
-    const bool small = mx_known < 0 || mx_known <= FN;
-    const bool large = mx_known < 0 || mx_known > FN;
+    // the root block (n = k_1 + k_2 <= 2 SK_KCAP) always fits the bordered kernel
+    static_assert(2 * SK_KCAP <= BT, "the root block fits the bordered factorization");
+    const bool small = !is_root && (mx_known < 0 || mx_known <= FN);
+    const bool large = !is_root && (mx_known < 0 || mx_known > FN);
     if (small) {
       KernelTimer kt("node_factor_kernel", 0.0, 0.0, sf);
       hipLaunchKernelGGL(node_factor_kernel, dim3(nn), dim3(256), 0, sf, gn, gch, is_leaf, is_root, cr, cc, d_nodes,

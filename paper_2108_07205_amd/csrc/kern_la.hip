@@ -497,9 +497,12 @@ __global__ __launch_bounds__(256) void gemm_tn_reduce_kernel(const double* __res
   }
 }
 
+// Row ranges of 64 rows (two LDS chunks), up to 1024 of them: the products
+// here are short and wide (M ~ 10^4 - 10^5 rows, k < 100 columns), so the
+// part count sets the parallelism; the reduction reads nparts k^2 partials.
 int gemm_tn_nparts(int64_t M) {
-  int64_t p = (M + 255) / 256;
-  return (int)(p < 1 ? 1 : (p > 256 ? 256 : p));
+  int64_t p = (M + 63) / 64;
+  return (int)(p < 1 ? 1 : (p > 1024 ? 1024 : p));
 }
 
 // ================================================================ Y -= X W
@@ -836,7 +839,7 @@ static int rowid_cooperative(rw_ctx* ctx, const double* Y, int64_t m, int ncols,
   a.out_k = dk;
   if (!lds_rows) HIP_CHECK(hipMemcpyAsync(a.Yw, Y, sizeof(double) * m * ncols, hipMemcpyDeviceToDevice, s));
   void* args[] = {&a};
-  HIP_CHECK(hipFuncSetAttribute((const void*)rowid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  func_lds_at_least((const void*)rowid_kernel, (int)shmem);
   {
     KernelTimer kt("rowid_kernel", 6.0 * (double)m * ncols * kmax, 0.0);
     HIP_CHECK(hipLaunchCooperativeKernel((const void*)rowid_kernel, dim3(G), dim3(256), args, shmem, s));
@@ -922,8 +925,8 @@ void launch_rowid_interp(const double* C, int64_t m, int kmax, int k, const int*
   if (k <= 0 || m <= 0) return;
   if (k > 128) RW_THROW(RW_EINVAL, "row ID rank above 128");
   const size_t sh = sizeof(double) * k * k;
-  HIP_CHECK(hipFuncSetAttribute((const void*)cj_inv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
-  HIP_CHECK(hipFuncSetAttribute((const void*)rowid_interp_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+  func_lds_at_least((const void*)cj_inv_kernel, (int)sh);
+  func_lds_at_least((const void*)rowid_interp_kernel, (int)sh);
   hipLaunchKernelGGL(cj_inv_kernel, dim3(1), dim3(128), sh, s, C, kmax, k, J, inv_work);
   KERNEL_CHECK("cj_inv");
   hipLaunchKernelGGL(rowid_interp_kernel, dim3(blocks(m)), dim3(256), sh, s, C, m, kmax, k, inv_work, pos, L, ldL,
@@ -956,7 +959,7 @@ void launch_sub_xw(const double* X, int64_t ldx, int64_t M, int k, const double*
   if (k <= 0 || M <= 0) return;
   const size_t sh = sizeof(double) * k * nrhs;
   if (sh > 150 * 1024) RW_THROW(RW_EINVAL, "too many right-hand sides for one Woodbury pass");
-  HIP_CHECK(hipFuncSetAttribute((const void*)sub_xw_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+  func_lds_at_least((const void*)sub_xw_kernel, (int)sh);
   hipLaunchKernelGGL(sub_xw_kernel, dim3(blocks(M)), dim3(256), sizeof(double) * k * nrhs, s, X, ldx, M, k, W, Y, ldy,
                      nrhs);
   KERNEL_CHECK("sub_xw");

@@ -173,6 +173,7 @@ hipEvent_t ctx_order_event(rw_ctx* ctx, int i) {
 
 void* ctx_pinned(rw_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->pinned_bytes) return ctx->pinned;
+  const size_t old_bytes = ctx->pinned_bytes;
   if (ctx->pinned) {
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
     if (ctx->side) HIP_CHECK(hipStreamSynchronize(ctx->side));
@@ -180,10 +181,24 @@ void* ctx_pinned(rw_ctx* ctx, size_t bytes) {
     ctx->pinned = nullptr;
     ctx->pinned_bytes = 0;
   }
-  bytes = std::max<size_t>(bytes, 64 * 1024);
+  // pinning pages is slow (milliseconds for megabytes): start at 4 MiB and
+  // at least double, so that growth is rare
+  bytes = std::max<size_t>({bytes, size_t(4) << 20, 2 * old_bytes});
   HIP_CHECK(hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault));
   ctx->pinned_bytes = bytes;
   return ctx->pinned;
+}
+
+void func_lds_at_least(const void* fn, int bytes) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int> done;
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  int& cur = done[{fn, dev}];
+  if (bytes <= cur) return;
+  HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  cur = bytes;
 }
 
 void* ctx_readback(rw_ctx* ctx, size_t bytes) {
