@@ -56,11 +56,11 @@ KERNEL_BOUND = {
 # the counters were taken; otherwise the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
     "node_factor_bordered_kernel": {
-        "fetch_kib": 2630.6, "write_kib": 6428.7, "fetch_scale": 1.9999, "write_scale": 1.0000,
+        "fetch_kib": 2626.6, "write_kib": 6422.2, "fetch_scale": 1.9999, "write_scale": 1.0000,
         "sources": ["paper_2108_07205_amd/csrc/hbs_gpu.hip", "paper_2108_07205_amd/csrc/dev_gj.h",
                     "paper_2108_07205_amd/csrc/dev_reduce.h", "paper_2108_07205_amd/csrc/hbs_dev.h",
                     "paper_2108_07205_amd/csrc/common.h"],
-        "sha256": "015b8537e5558de6d7357ee07135fd790e91a7097509785fd7ea81d61ae47aa6",
+        "sha256": "0b51f908f1dd80fa657ee984c8c50693cc23ab09220e6c0b5aa86cd8b0c3f321",
         "summary": "profiles/star1024_refine16x4_hbm_traffic.md",
     },
 }
