@@ -252,6 +252,28 @@ def test_residual_and_multi_rhs(ctx, wall64):
     ref.close()
 
 
+@pytest.mark.parametrize("ids,levels", [((3,), (1,)), ((3, 20, 40, 50), (6, 6, 6, 6))])
+def test_residual_one_rhs_ragged(ctx, wall64, ids, levels):
+    """The one-right-hand-side residual kernel (several targets per thread,
+    four sources per reciprocal) against the oracle's dense product at node
+    counts (1040, 5056) whose target blocks and source splits leave ragged
+    tails (a partial block of targets, split lengths not divisible by 4)."""
+    p = W.small_problem(n_panels=64, ids=ids, levels=levels, n_stokeslets=4, nrhs=1)
+    sets = _oracle_sets(p)
+    ref = wall64.refine(p.refinement.panel_ids, p.refinement.levels)
+    assert ref.n_nodes == sets.new.x.shape[0]
+    A = K.nystrom_matrix(sets.new)
+    g = K.rhs_vector(sets.new, p.rhs[0].z, p.rhs[0].f)
+    x = sets.new.x
+    t = np.stack([np.sin(2 * x[:, 0] + 0.3), np.cos(3 * x[:, 1] - 0.7)], 1).reshape(-1)
+    r = ref.residual(_dev(g), _dev(t)).cpu().numpy()
+    r_or = g - A @ t
+    _say(f"  residual 1 rhs n={ref.n_nodes}: max diff {np.max(np.abs(r - r_or)) / np.max(np.abs(r_or)):.2e}")
+    # same bound as the several-RHS residual check (independent discretizations)
+    assert np.max(np.abs(r - r_or)) < 1e-11 * np.max(np.abs(r_or))
+    ref.close()
+
+
 def test_unrefined_and_level_zero(ctx, wall64):
     d = G.discretize(G.reference_panels(64), 0.3, 5)
     A = K.nystrom_matrix(d)
