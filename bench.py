@@ -60,7 +60,7 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_2108_07205_amd/csrc/hbs_gpu.hip", "paper_2108_07205_amd/csrc/dev_gj.h",
                     "paper_2108_07205_amd/csrc/dev_reduce.h", "paper_2108_07205_amd/csrc/hbs_dev.h",
                     "paper_2108_07205_amd/csrc/common.h"],
-        "sha256": "0b51f908f1dd80fa657ee984c8c50693cc23ab09220e6c0b5aa86cd8b0c3f321",
+        "sha256": "196341712d7c6aa6fb8e2449d3f412de64ce294d666c45a95a1563f13997039d",
         "summary": "profiles/star1024_refine16x4_hbm_traffic.md",
     },
 }

@@ -11,8 +11,9 @@
 //     columns / double-layer rows) plus the rank-one nullspace column / flux
 //     row; Omega = +-1 from a counter-based hash.  Entries are generated on the
 //     fly, never stored.
-//  2. row ID of each sketch by pivoted Gram-Schmidt over rows in LDS; the
-//     node rank is the larger of the two tolerance ranks.
+//  2. row ID of each sketch by pivoted Gram-Schmidt over rows held in
+//     registers (one projection per step); the node rank is the larger of
+//     the two tolerance ranks.
 //  3. interpolation matrices U, V and the skeleton lists (the parent's
 //     candidate rows / columns).
 //  4. node inverse: D (leaf block, or [[D^_a, A(Jr_a, Jc_b)], [A(Jr_b, Jc_a),
