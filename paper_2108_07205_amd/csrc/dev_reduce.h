@@ -28,6 +28,15 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// 1 / x for a finite, normal, nonzero x to within an ulp or two: hardware
+// reciprocal and two Newton steps (a shorter dependency chain than the
+// correctly rounded division).
+__device__ __forceinline__ double recip_nr2(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * (2.0 - x * y);
+  return y * (2.0 - x * y);
+}
+
 // Pivot key: the non-negative magnitude v with its `bits` lowest mantissa
 // bits replaced by (2^bits - 1 - i), so that the largest key belongs to the
 // largest v (to 2^(bits-52) relative) and, among equal magnitudes, to the

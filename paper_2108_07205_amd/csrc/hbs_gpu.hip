@@ -1264,16 +1264,25 @@ __global__ __launch_bounds__(BWV * 64) void node_factor_bordered_kernel(
           kmax = wave_max_nonneg(kmax);
           const int p = __builtin_amdgcn_readfirstlane(pivot_key_index<8>(kmax));
           const int ps = p >> 6, pl = p & 63;
+          // pivot row by readlane from its (wave-uniform) row slot: one
+          // branch instead of a register select per column
           double pr[BC];
+          if (ps == 0) {
 #pragma unroll
-          for (int cc = 0; cc < BC; ++cc)
-            pr[cc] = readlane_f64(ps == 0 ? a[0][cc] : (ps == 1 ? a[1][cc] : a[2][cc]), pl);
+            for (int cc = 0; cc < BC; ++cc) pr[cc] = readlane_f64(a[0][cc], pl);
+          } else if (ps == 1) {
+#pragma unroll
+            for (int cc = 0; cc < BC; ++cc) pr[cc] = readlane_f64(a[1][cc], pl);
+          } else {
+#pragma unroll
+            for (int cc = 0; cc < BC; ++cc) pr[cc] = readlane_f64(a[2][cc], pl);
+          }
           const double piv = pr[c];
-          if (!(fabs(piv) > 0.0) || !isfinite(piv)) {
+          if (!(fabs(piv) >= 2.2250738585072014e-308) || !isfinite(piv)) {
             ok = false;
             if (lane == 0) S.bad = 1;
           } else {
-            const double pinv = 1.0 / piv;
+            const double pinv = recip_nr2(piv);
             if (lane == 0) {
               S.piv[j0 + c] = p;
               S.pinv[j0 + c] = pinv;
@@ -1295,6 +1304,7 @@ __global__ __launch_bounds__(BWV * 64) void node_factor_bordered_kernel(
       for (int sr = 0; sr < BS; ++sr)
 #pragma unroll
         for (int cc = 0; cc < BC; ++cc) S.pan[slot][lane + 64 * sr][cc] = a[sr][cc];
+      __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();
     if (S.bad) {
@@ -1316,6 +1326,10 @@ __global__ __launch_bounds__(BWV * 64) void node_factor_bordered_kernel(
           rinv[sr] = S.pinv[j0 + t];
         }
     }
+    // the next panel's wave updates its columns and factors them while the
+    // others update theirs: it issues first on its SIMD, since the next
+    // barrier waits for it
+    if (w == bj + 1) __builtin_amdgcn_s_setprio(3);
     if (w != bj) {
       // this wave's columns of the pivot rows, before the update
 #pragma unroll
