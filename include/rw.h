@@ -189,6 +189,8 @@ int rw_nodes(const rw_refined* ref, double* xy_host, double* normals_host,
 /* tau = A_nn^{-1} g for nrhs right-hand sides: Woodbury solve (eq. wood)
  * then iterative refinement with the exact refined Nystrom residual until
  * ||g - A_nn tau|| / ||g|| <= ir_tol (per column) or ir_maxit corrections.
+ * With ir_maxit >= 1 the first correction is always taken (it is enqueued
+ * before the first residual is read back).
  * g_dev, tau_dev: 2*N_n x nrhs column-major, may not alias.  The stream is
  * synchronized before return.  Errors: RW_EINVAL, RW_ENOMEM,
  * RW_ENOCONV (result written, residual above tolerance), RW_EDEVICE. */

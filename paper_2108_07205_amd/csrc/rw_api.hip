@@ -1103,26 +1103,32 @@ int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau) {
     refined_ensure_ws(f, nrhs);
     woodbury_apply(f, g, tau, nrhs, false);
     const rw_options& o = f->ctx->opt;
-    std::vector<double> nrm(2 * nrhs);
     int it = 0;
     double worst = 0;
+    double* hn = (double*)ctx_readback(f->ctx, sizeof(double) * 2 * nrhs);
+    auto residual = [&]() {
+      PhaseTimer t(f->ctx, "a8_residual", 26.0 * (double)f->Nn * f->Nn * nrhs, 0.0);
+      launch_residual(f->d_new.p, f->Nn, g, tau, f->r.p, nrhs, f->part.p, f->norms.p, s);
+    };
+    auto correct = [&]() {
+      woodbury_apply(f, f->r.p, tau, nrhs, true);
+      ++it;
+      residual();
+    };
+    residual();
+    // the Woodbury solution takes at least one correction when refinement is
+    // on: it is enqueued with its residual before anything is read back
+    if (o.ir_maxit > 0) correct();
     for (;;) {
-      {
-        PhaseTimer t(f->ctx, "a8_residual", 26.0 * (double)f->Nn * f->Nn * nrhs, 0.0);
-        launch_residual(f->d_new.p, f->Nn, g, tau, f->r.p, nrhs, f->part.p, f->norms.p, s);
-      }
-      double* hn = (double*)ctx_readback(f->ctx, sizeof(double) * 2 * nrhs);
       HIP_CHECK(hipMemcpyAsync(hn, f->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
       HIP_CHECK(hipStreamSynchronize(s));
-      std::copy(hn, hn + 2 * nrhs, nrm.begin());
       worst = 0;
       for (int c = 0; c < nrhs; ++c) {
-        const double rel = nrm[nrhs + c] > 0 ? std::sqrt(nrm[c] / nrm[nrhs + c]) : std::sqrt(nrm[c]);
+        const double rel = hn[nrhs + c] > 0 ? std::sqrt(hn[c] / hn[nrhs + c]) : std::sqrt(hn[c]);
         worst = std::max(worst, std::isfinite(rel) ? rel : INFINITY);
       }
       if (worst <= o.ir_tol || it >= o.ir_maxit) break;
-      woodbury_apply(f, f->r.p, tau, nrhs, true);
-      ++it;
+      correct();
     }
     prof_flush(f->ctx);
     f->info.ir_iters = it;
