@@ -56,11 +56,11 @@ KERNEL_BOUND = {
 # the counters were taken; otherwise the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
     "node_factor_bordered_kernel": {
-        "fetch_kib": 2626.6, "write_kib": 6422.2, "fetch_scale": 1.9999, "write_scale": 1.0000,
+        "fetch_kib": 2643.3, "write_kib": 6439.2, "fetch_scale": 1.9999, "write_scale": 1.0000,
         "sources": ["paper_2108_07205_amd/csrc/hbs_gpu.hip", "paper_2108_07205_amd/csrc/dev_gj.h",
                     "paper_2108_07205_amd/csrc/dev_reduce.h", "paper_2108_07205_amd/csrc/hbs_dev.h",
                     "paper_2108_07205_amd/csrc/common.h"],
-        "sha256": "196341712d7c6aa6fb8e2449d3f412de64ce294d666c45a95a1563f13997039d",
+        "sha256": "0fc3c5081c90d2abad5ea21ec4633d1ce68c3eda726cd1aa3c5a78d695237d4b",
         "summary": "profiles/star1024_refine16x4_hbm_traffic.md",
     },
 }
