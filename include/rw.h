@@ -87,7 +87,8 @@ typedef struct {
   int32_t k_k, k_p, k;       /* ranks of the k-row and p-row IDs of Q, k = k_k + k_p */
   int32_t ir_iters;          /* refinement corrections applied by the last rw_solve */
   double resid;              /* max over columns of ||g - A_nn tau|| / ||g|| after the last rw_solve */
-  double t_refine_ms;        /* wall time of the last rw_refine / rw_coarsen (host clock) */
+  double t_refine_ms;        /* host time of the last rw_refine / rw_coarsen (until it returned,
+                                which is before its last device work ends) */
   double t_solve_ms;         /* wall time of the last rw_solve */
   int64_t n_near;            /* kept nodes sketched exactly by the far-field split, -1 if Q's blocks
                                 were sketched exactly as a whole */
@@ -170,7 +171,17 @@ int rw_hbs_apply(rw_wall* wall, const double* b_dev, int32_t nrhs, double* x_dev
  * extended system), then build Q ~= L R, A_pp^{-1}, X = A~^{-1} L and the LU
  * of W = I + R X.  n_sel = 0 gives the unrefined wall (k = 0).
  * Errors: RW_EINVAL (ids out of [0, n_panels), duplicates, levels outside
- * [0, 8]), RW_ENOMEM, RW_ESINGULAR, RW_EDEVICE. */
+ * [0, 8]), RW_ENOMEM, RW_ESINGULAR, RW_EDEVICE.
+ * Asynchrony: the call returns once the last part of the pre-computation
+ * (the A_pp^{-1} build's top levels, X and W) is enqueued on the ctx's
+ * stream, so that the caller can enqueue the solve behind it.  The checks
+ * that read device results (a zero pivot in W or in an HBS node block, an
+ * HBS rank reaching the sketch size) are then made by the first of
+ * rw_solve, rw_solve_batch or rw_residual on the handle, or by the next
+ * rw_refine / rw_coarsen on the ctx; a failure found there is returned by
+ * that handle's rw_solve / rw_solve_batch / rw_residual (RW_ESINGULAR) from
+ * then on.  With the ctx profiler on, rw_refine waits and reports it
+ * itself.  rw_refined_free waits for the handle's device work. */
 int rw_refine(rw_wall* wall, const int32_t* panel_ids_host, const int32_t* levels_host,
               int32_t n_sel, rw_refined** out);
 /* Coarsen: give panel_ids_host[i] back its reference discretization and
@@ -193,7 +204,8 @@ int rw_nodes(const rw_refined* ref, double* xy_host, double* normals_host,
  * before the first residual is read back).
  * g_dev, tau_dev: 2*N_n x nrhs column-major, may not alias.  The stream is
  * synchronized before return.  Errors: RW_EINVAL, RW_ENOMEM,
- * RW_ENOCONV (result written, residual above tolerance), RW_EDEVICE. */
+ * RW_ENOCONV (result written, residual above tolerance), RW_ESINGULAR (the
+ * refinement's deferred checks failed; tau is not a solution), RW_EDEVICE. */
 int rw_solve(rw_refined* ref, const double* g_dev, int32_t nrhs, double* tau_dev);
 
 /* Several refinements of one wall in one call (Algorithm 1 solve steps for
@@ -208,18 +220,22 @@ int rw_solve(rw_refined* ref, const double* g_dev, int32_t nrhs, double* tau_dev
  * The stream is synchronized before return.  Errors: RW_EINVAL (null or
  * repeated handles, handles of different walls, nrhs <= 0), RW_ENOMEM,
  * RW_ENOCONV (all results written; at least one instance stopped above the
- * tolerance), RW_EDEVICE. */
+ * tolerance), RW_ESINGULAR (an instance's deferred refinement checks
+ * failed), RW_EDEVICE. */
 int rw_solve_batch(rw_refined* const* inst, int32_t n_inst, const double* const* g_dev,
                    const int32_t* nrhs, double* const* tau_dev, rw_info* info_host);
 
 /* r = g - A_nn tau on the refined discretization (exact Nystrom operator,
- * entries generated on the fly).  Shapes as rw_solve. */
+ * entries generated on the fly).  Shapes as rw_solve.  Enqueued on the ctx's
+ * stream (not synchronized).  Errors: RW_EINVAL, RW_ENOMEM, RW_ESINGULAR
+ * (the refinement's deferred checks failed), RW_EDEVICE. */
 int rw_residual(rw_refined* ref, const double* g_dev, const double* tau_dev,
                 int32_t nrhs, double* r_dev);
 
 /* Boundary data of exterior Stokeslets (eq. stokeslet, mu = 1) at the refined
  * nodes: g(x_i) = sum_m S(x_i, z_m) f_m.  z_host, f_host: n_src x 2 row-major
- * (host).  g_dev: 2*N_n (one column).  Errors: RW_EINVAL, RW_EDEVICE. */
+ * (host; copied before return).  g_dev: 2*N_n (one column), written on the
+ * ctx's stream (not synchronized).  Errors: RW_EINVAL, RW_EDEVICE. */
 int rw_stokeslet_rhs(rw_refined* ref, const double* z_host, const double* f_host,
                      int32_t n_src, double* g_dev);
 

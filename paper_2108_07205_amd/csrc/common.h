@@ -87,6 +87,15 @@ struct rw_ctx {
   size_t pinned_bytes = 0;
   void* rb = nullptr;
   size_t rb_bytes = 0;
+  // event after the last enqueued copy out of `pinned` (ctx_pinned waits
+  // for it before handing the buffer out again)
+  hipEvent_t pinned_ev = nullptr;
+  bool pinned_ev_set = false;
+  // the refinement whose end rw_refine did not wait for (at most one per
+  // ctx; its device-side checks are still to be read), and the pinned word
+  // its W pivot flag comes back to
+  rw_refined* unsettled = nullptr;
+  int* defer_pin = nullptr;
   // phase profiler (HIP events on `stream`)
   bool prof = false;
   struct Pending { std::string name; hipEvent_t a, b; double flops, bytes; };
@@ -126,7 +135,12 @@ hipStream_t ctx_side_stream(rw_ctx* ctx);
 hipEvent_t ctx_order_event(rw_ctx* ctx, int i);
 // Pinned host staging of at least `bytes` (grow-only; growing first waits
 // for the ctx's streams, so no copy from the old buffer is still in flight).
+// It first waits for the copies marked by ctx_pinned_used, so that the
+// host may overwrite the buffer.
 void* ctx_pinned(rw_ctx* ctx, size_t bytes);
+// Marks the copies enqueued on `s` so far as the last users of the staging
+// buffer (the next ctx_pinned waits for them).
+void ctx_pinned_used(rw_ctx* ctx, hipStream_t s);
 // Allow kernel fn at least `bytes` of dynamic LDS on the current device
 // (hipFuncSetAttribute once per kernel, device and larger size).
 void func_lds_at_least(const void* fn, int bytes);

@@ -1150,13 +1150,11 @@ __device__ __forceinline__ double a_entry(const NodeRec& t, const NodeRec& s, bo
 // G = D^-1 - D^-1 U D^ V* D^-1: every generator of the node in one pass,
 // without D^-1 or the products ever leaving the registers.  The root (k = 0)
 // gets D^-1 = G_root.
-// grid (nodes), 512 threads (8 waves); n + k <= BT.  Lane l holds rows
-// l, l + 64, l + 128 (sub-rows s), wave w the 24 columns 24 w .. 24 w + 23
-// (a[s][c]).  Pivoting as in reg_gj64: step j takes column j, whose owner
-// wave keeps it in a[.][0] by shifting its registers; rows are never moved,
-// so the result is (P M)^-1 with row j stored in row p_j.  One barrier per
-// step: the owner publishes column j and the pivot key through alternating
-// LDS slots, and every wave reads its part of pivot row p from lane p % 64.
+// grid (nodes), BWV * 64 threads; n + k <= BT.  Lane l holds rows l, l + 64,
+// l + 128 (sub-rows s), wave w the BC columns BC w .. BC w + BC - 1
+// (a[s][c]).  Partial pivoting by rows, which are never moved, so the result
+// is (P M)^-1 with row j stored in row p_j; the column steps are blocked by
+// the BC columns of a wave (the scheme is described at the sweep below).
 constexpr int BT = 192;        // largest bordered size
 constexpr int BWV = 12;        // waves
 constexpr int BC = BT / BWV;   // columns per wave
@@ -1326,11 +1324,8 @@ __global__ __launch_bounds__(BWV * 64) void node_factor_bordered_kernel(
           rinv[sr] = S.pinv[j0 + t];
         }
     }
-    // the next panel's wave updates its columns and factors them while the
-    // others update theirs: it issues first on its SIMD, since the next
-    // barrier waits for it
-    if (w == bj + 1) __builtin_amdgcn_s_setprio(3);
-    if (w != bj) {
+    // rank-nb update of this wave's columns by the block's row operations
+    auto update = [&]() __attribute__((always_inline)) {
       // this wave's columns of the pivot rows, before the update
 #pragma unroll
       for (int sr = 0; sr < BS; ++sr)
@@ -1351,7 +1346,18 @@ __global__ __launch_bounds__(BWV * 64) void node_factor_bordered_kernel(
         }
       }
       __builtin_amdgcn_wave_barrier();
+    };
+    // The update is bound by the LDS reads of the pivot rows (broadcast to
+    // every lane) when all waves run it at once, so the next panel's wave
+    // runs it alone, at raised priority, and then factors its panel while
+    // the other waves update theirs (the panel steps read no LDS).  Waves
+    // whose columns all lie beyond T have nothing to update.
+    if (w == bj + 1) {
+      __builtin_amdgcn_s_setprio(3);
+      update();
     }
+    __syncthreads();
+    if (w != bj && w != bj + 1 && BC * w < T) update();
   }
 #pragma unroll
   for (int sr = 0; sr < BS; ++sr)

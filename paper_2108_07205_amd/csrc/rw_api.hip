@@ -172,6 +172,10 @@ hipEvent_t ctx_order_event(rw_ctx* ctx, int i) {
 }
 
 void* ctx_pinned(rw_ctx* ctx, size_t bytes) {
+  if (ctx->pinned_ev_set) {
+    HIP_CHECK(hipEventSynchronize(ctx->pinned_ev));
+    ctx->pinned_ev_set = false;
+  }
   if (bytes <= ctx->pinned_bytes) return ctx->pinned;
   const size_t old_bytes = ctx->pinned_bytes;
   if (ctx->pinned) {
@@ -187,6 +191,12 @@ void* ctx_pinned(rw_ctx* ctx, size_t bytes) {
   HIP_CHECK(hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault));
   ctx->pinned_bytes = bytes;
   return ctx->pinned;
+}
+
+void ctx_pinned_used(rw_ctx* ctx, hipStream_t s) {
+  if (!ctx->pinned_ev) HIP_CHECK(hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming));
+  HIP_CHECK(hipEventRecord(ctx->pinned_ev, s));
+  ctx->pinned_ev_set = true;
 }
 
 void func_lds_at_least(const void* fn, int bytes) {
@@ -357,6 +367,22 @@ int guarded(rw_ctx* ctx, F&& f) {
 }
 }  // namespace
 
+// Event handle that moves with its owner and is destroyed with it.
+struct OwnedEvent {
+  hipEvent_t e = nullptr;
+  OwnedEvent() = default;
+  OwnedEvent(const OwnedEvent&) = delete;
+  OwnedEvent& operator=(const OwnedEvent&) = delete;
+  OwnedEvent(OwnedEvent&& o) noexcept : e(o.e) { o.e = nullptr; }
+  OwnedEvent& operator=(OwnedEvent&& o) noexcept {
+    std::swap(e, o.e);
+    return *this;
+  }
+  ~OwnedEvent() {
+    if (e) (void)hipEventDestroy(e);
+  }
+};
+
 // ======================================================================= wall
 struct rw_wall {
   rw_ctx* ctx = nullptr;
@@ -429,9 +455,37 @@ struct rw_refined {
   DBuf<double> gext, y, z, wv, r, tmp, part, norms;
   int ws_nrhs = 0;
   rw_info info{};
+  // rw_refine returns once the device work is enqueued: `done` marks its
+  // end, `pending` that its device-side checks (W pivot flag, A_pp build
+  // flags) are still to be read; their outcome then sticks to the handle
+  OwnedEvent done;
+  bool pending = false;
+  int fail_rc = RW_OK;
+  std::string fail_msg;
 };
 
 namespace {
+
+// Reads the device-side outcome of a refinement whose end rw_refine did not
+// wait for: waits for its device work (at once if the stream has been
+// synchronized past it), then checks the W pivot flag and the A_pp build's
+// flags.  A failure sticks to the handle; it is thrown unless `quiet`.
+void refined_settle(rw_refined* f, bool quiet = false) {
+  if (f->pending) {
+    f->pending = false;
+    if (f->ctx->unsettled == f) f->ctx->unsettled = nullptr;
+    try {
+      HIP_CHECK(hipEventSynchronize(f->done.e));
+      const int info = *f->ctx->defer_pin;
+      if (info) RW_THROW(RW_ESINGULAR, "singular Woodbury operator W (pivot " + std::to_string(info) + ")");
+      if (f->app_hbs_on) hbs_gpu_finish(f->app_hbs);
+    } catch (const RwError& e) {
+      f->fail_rc = e.code;
+      f->fail_msg = e.what();
+    }
+  }
+  if (f->fail_rc != RW_OK && !quiet) RW_THROW(f->fail_rc, f->fail_msg);
+}
 
 void refined_ensure_ws(rw_refined* f, int nrhs) {
   if (nrhs <= f->ws_nrhs) return;
@@ -558,6 +612,10 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
   rw_ctx* ctx = w->ctx;
   hipStream_t s = ctx->stream;
   const double t0 = wall_ms();
+  // the previous refinement's checks are read first: its read-back word and
+  // pinned staging are reused below (its outcome stays with its handle)
+  if (ctx->unsettled) refined_settle(ctx->unsettled, true);
+  if (!ctx->defer_pin) HIP_CHECK(hipHostMalloc((void**)&ctx->defer_pin, 64, hipHostMallocDefault));
   f.wall = w;
   f.ctx = ctx;
   f.level_of_panel = level_of_panel;
@@ -602,8 +660,8 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
   const int64_t M = 2 * f.Next, Mo = 2 * f.No, Mp = 2 * f.Np;
   // host arrays go to the device through the ctx's pinned staging buffer
   // (one region per array), so the copies are asynchronous and the host
-  // vectors may go out of scope at once; the buffer is next reused by a
-  // later call, after this one has synchronized its stream
+  // vectors may go out of scope at once; the buffer is next handed out once
+  // these copies have run (ctx_pinned_used)
   const size_t stage_bytes = sizeof(NodeRec) * f.Np +
                              sizeof(int) * (f.Nn + f.No + 3 * f.Nk + 2 * f.Np + f.Nc + 4 * f.Nk) + 16 * 256;
   char* stage_base = (char*)ctx_pinned(ctx, stage_bytes);
@@ -641,6 +699,7 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
     up(idx_c.p, c_ref.data(), sizeof(int) * c_ref.size());
     launch_gather_nodes(w->d_nodes.p, idx_c.p, f.Nc, f.d_c.p, s);
   }
+  ctx_pinned_used(ctx, s);
   f.d_p.alloc(ctx, f.Np);
   if (f.Np) HIP_CHECK(hipMemcpyAsync(f.d_p.p, f.d_ext.p + f.No, sizeof(NodeRec) * f.Np, hipMemcpyDeviceToDevice, s));
 
@@ -827,17 +886,21 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
     DBuf<double> part(ctx, gemm_tn_part_doubles(M, f.k, f.k));
     launch_gemm_tn(f.R.p, M, f.X.p, M, M, f.k, f.k, f.W.p, f.k, true, part.p, s);
     launch_small_inverse(f.W.p, f.k, dinfo.p + 1, s);
-    int* hinfo = (int*)ctx_readback(ctx, sizeof(int));
-    HIP_CHECK(hipMemcpyAsync(hinfo, dinfo.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
-    const int info = *hinfo;
-    if (info) RW_THROW(RW_ESINGULAR, "singular Woodbury operator W (pivot " + std::to_string(info) + ")");
+    HIP_CHECK(hipMemcpyAsync(ctx->defer_pin, dinfo.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  } else {
+    *ctx->defer_pin = 0;
   }
-  HIP_CHECK(hipStreamSynchronize(s));
-  // the A_pp build's flags and statistics (read back on its stream, which
-  // the main stream has waited for)
-  if (f.app_hbs_on) hbs_gpu_finish(f.app_hbs);
-  prof_flush(ctx);
+  // the W pivot flag and the A_pp build's flags and statistics (read back on
+  // its stream, which the main stream has waited for) are checked once the
+  // stream has passed this event: here under the profiler, otherwise by the
+  // next call that uses the handle or the next refinement on this ctx
+  if (!f.done.e) HIP_CHECK(hipEventCreateWithFlags(&f.done.e, hipEventDisableTiming));
+  HIP_CHECK(hipEventRecord(f.done.e, s));
+  f.pending = true;
+  if (ctx->prof) {
+    refined_settle(&f);
+    prof_flush(ctx);
+  }
   f.info.n_k = f.Nk;
   f.info.n_c = f.Nc;
   f.info.n_p = f.Np;
@@ -845,6 +908,7 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
   f.info.k_p = f.k_p;
   f.info.k = f.k;
   f.info.t_refine_ms = wall_ms() - t0;
+  if (f.pending) ctx->unsettled = &f;
 }
 
 void copy_nodes_out(const std::vector<NodeRec>& nd, double* xy, double* nrm, double* wts, int64_t* n_nodes) {
@@ -915,6 +979,8 @@ void rw_ctx_destroy(rw_ctx* ctx) {
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->rb) (void)hipHostFree(ctx->rb);
+  if (ctx->pinned_ev) (void)hipEventDestroy(ctx->pinned_ev);
+  if (ctx->defer_pin) (void)hipHostFree(ctx->defer_pin);
   delete ctx;
 }
 
@@ -1065,12 +1131,14 @@ int rw_coarsen(rw_refined* f, const int32_t* ids, int32_t n_sel) {
     std::unique_ptr<rw_refined> g(new rw_refined());
     build_refined(f->wall, lop, *g);
     std::swap(*f, *g);
+    if (f->ctx->unsettled == g.get()) f->ctx->unsettled = f;
   });
 }
 
 void rw_refined_free(rw_refined* f) {
   if (!f) return;
   (void)hipSetDevice(f->ctx->device);
+  refined_settle(f, true);
   delete f;
 }
 
@@ -1098,6 +1166,7 @@ int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau) {
   if (!f) return RW_EINVAL;
   int rc = guarded(f->ctx, [&]() {
     if (nrhs <= 0 || !g || !tau) RW_THROW(RW_EINVAL, "bad arguments");
+    if (f->fail_rc != RW_OK) RW_THROW(f->fail_rc, f->fail_msg);
     const double t0 = wall_ms();
     hipStream_t s = f->ctx->stream;
     refined_ensure_ws(f, nrhs);
@@ -1122,6 +1191,8 @@ int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau) {
     for (;;) {
       HIP_CHECK(hipMemcpyAsync(hn, f->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
       HIP_CHECK(hipStreamSynchronize(s));
+      // the refinement's own checks, if rw_refine returned before its end
+      refined_settle(f);
       worst = 0;
       for (int c = 0; c < nrhs; ++c) {
         const double rel = hn[nrhs + c] > 0 ? std::sqrt(hn[c] / hn[nrhs + c]) : std::sqrt(hn[c]);
@@ -1198,6 +1269,7 @@ int rw_solve_batch(rw_refined* const* inst, int32_t n_inst, const double* const*
     const rw_options& o = f0->ctx->opt;
     std::vector<rw_refined*> fs(inst, inst + n_inst);
     std::vector<int> nr(nrhs, nrhs + n_inst);
+    for (int i = 0; i < n_inst; ++i) refined_settle(fs[i]);
     for (int i = 0; i < n_inst; ++i) refined_ensure_ws(fs[i], nr[i]);
     batch_woodbury(w, fs, std::vector<const double*>(g, g + n_inst), std::vector<double*>(tau, tau + n_inst), nr,
                    false);
@@ -1259,6 +1331,7 @@ int rw_residual(rw_refined* f, const double* g, const double* tau, int32_t nrhs,
   if (!f) return RW_EINVAL;
   return guarded(f->ctx, [&]() {
     if (nrhs <= 0 || !g || !tau || !r) RW_THROW(RW_EINVAL, "bad arguments");
+    refined_settle(f);
     refined_ensure_ws(f, nrhs);
     launch_residual(f->d_new.p, f->Nn, g, tau, r, nrhs, f->part.p, nullptr, f->ctx->stream);
   });
@@ -1275,10 +1348,15 @@ int rw_stokeslet_rhs(rw_refined* f, const double* z, const double* fv, int32_t n
       zf[4 * m + 2] = fv[2 * m];
       zf[4 * m + 3] = fv[2 * m + 1];
     }
+    // through the pinned staging buffer: an upload from pageable memory would
+    // wait for the work already on the stream (a refinement still running)
+    hipStream_t s = f->ctx->stream;
+    double* hz = (double*)ctx_pinned(f->ctx, sizeof(double) * zf.size());
+    memcpy(hz, zf.data(), sizeof(double) * zf.size());
     DBuf<double> d(f->ctx, zf.size());
-    d.upload(zf.data(), zf.size(), f->ctx->stream);
-    launch_stokeslet_rhs(f->d_new.p, f->Nn, d.p, n_src, g, f->ctx->stream);
-    HIP_CHECK(hipStreamSynchronize(f->ctx->stream));
+    HIP_CHECK(hipMemcpyAsync(d.p, hz, sizeof(double) * zf.size(), hipMemcpyHostToDevice, s));
+    ctx_pinned_used(f->ctx, s);
+    launch_stokeslet_rhs(f->d_new.p, f->Nn, d.p, n_src, g, s);
   });
 }
 

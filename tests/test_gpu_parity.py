@@ -309,6 +309,40 @@ def test_coarsen(ctx, wall64):
     ref.close()
 
 
+def test_refinements_in_flight(ctx, wall64):
+    """rw_refine returns before its last device work ends: a later refinement
+    reads the earlier one's checks, either handle can then be solved, a
+    handle freed unsolved waits for its own work, and a pending handle can be
+    coarsened (A_pp^{-1} by the GPU-built HBS inverse, whose flags are among
+    the deferred checks)."""
+    ps = [W.config1(seed=s) for s in (0, 1)]
+    ctx.set_options(app_dense_max_nodes=0)
+    try:
+        a = wall64.refine(ps[0].refinement.panel_ids, ps[0].refinement.levels)
+        b = wall64.refine(ps[1].refinement.panel_ids, ps[1].refinement.levels)
+        c = wall64.refine(ps[0].refinement.panel_ids, ps[0].refinement.levels)
+        c.close()
+        for ref, p in ((b, ps[1]), (a, ps[0])):
+            st = p.rhs[0]
+            tau = ref.solve(ref.stokeslet_rhs(st.z, st.f)).cpu().numpy()
+            sets = _oracle_sets(p)
+            g_or = K.rhs_vector(sets.new, st.z, st.f)
+            e = relerr(tau, S.solve_refined(K.nystrom_matrix(sets.new), g_or))
+            _say(f"  in flight seed={p.seed}: k={ref.info()['k']} err={e:.2e}")
+            assert e <= 1e-10
+        a.close()
+        b.close()
+        d = wall64.refine([5, 6, 7], [2, 3, 1])
+        d.coarsen([6])
+        sets = G.refine(64, [5, 7], [2, 1], 0.3, 5)
+        st = W.stokeslets(np.random.default_rng(4), 8)
+        g = K.rhs_vector(sets.new, st.z, st.f)
+        assert relerr(d.solve(_dev(g)).cpu().numpy(), np.linalg.solve(K.nystrom_matrix(sets.new), g)) <= 1e-10
+        d.close()
+    finally:
+        ctx.set_options(app_dense_max_nodes=1024)
+
+
 def test_solve_batch_matches_single_and_oracle(ctx, wall64):
     """rw_solve_batch on uneven refinements of one wall (contiguous panel
     blocks around different positions, 1..4 levels, 1..3 right-hand sides
