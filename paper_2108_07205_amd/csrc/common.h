@@ -152,17 +152,18 @@ void stream_after(rw_ctx* ctx, hipStream_t waiter, hipStream_t src, int i);
 
 // Run fn(aux) on the helper ctx's worker thread, its stream ordered after
 // everything enqueued on ctx->stream so far; aux_join waits for it, orders
-// ctx->stream after the helper's stream and rethrows fn's error.  Between
+// `into` (default ctx->stream) after the helper's stream and rethrows fn's
+// error.  Between
 // the two, the caller's thread may use ctx but not the helper, and fn may
 // use the helper but not ctx.  AuxTask joins (ignoring errors) if the caller
 // leaves early.
 void aux_fork(rw_ctx* ctx, std::function<void(rw_ctx*)> fn);
-void aux_join(rw_ctx* ctx);
+void aux_join(rw_ctx* ctx, hipStream_t into = nullptr);
 struct AuxTask {
   rw_ctx* ctx = nullptr;
   bool active = false;
   void fork(rw_ctx* c, std::function<void(rw_ctx*)> fn) { aux_fork(c, std::move(fn)); ctx = c; active = true; }
-  void join() { if (active) { active = false; aux_join(ctx); } }
+  void join(hipStream_t into = nullptr) { if (active) { active = false; aux_join(ctx, into); } }
   ~AuxTask() { if (active) { active = false; try { aux_join(ctx); } catch (...) {} } }
 };
 

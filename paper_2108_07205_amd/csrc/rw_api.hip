@@ -299,7 +299,7 @@ void aux_fork(rw_ctx* ctx, std::function<void(rw_ctx*)> fn) {
   wk->cv.notify_all();
 }
 
-void aux_join(rw_ctx* ctx) {
+void aux_join(rw_ctx* ctx, hipStream_t into) {
   AuxWorker* wk = ctx->worker;
   if (!wk) return;
   std::exception_ptr e;
@@ -309,7 +309,7 @@ void aux_join(rw_ctx* ctx) {
     e = wk->err;
     wk->err = nullptr;
   }
-  stream_after(ctx, ctx->stream, ctx->aux->stream, 4);
+  stream_after(ctx, into ? into : ctx->stream, ctx->aux->stream, 4);
   if (e) std::rethrow_exception(e);
 }
 
@@ -460,6 +460,8 @@ struct rw_refined {
   // flags) are still to be read; their outcome then sticks to the handle
   OwnedEvent done;
   bool pending = false;
+  DBuf<int> dinfo;                     // W pivot flag (device)
+  DBuf<double> wpart;                  // split partial sums of R X
   int fail_rc = RW_OK;
   std::string fail_msg;
 };
@@ -532,6 +534,9 @@ void woodbury_app_apply(rw_refined* f, int nrhs, hipStream_t s) {
 void woodbury_out(rw_refined* f, double* dst, int nrhs, bool accumulate, bool app_done = false) {
   hipStream_t s = f->ctx->stream;
   const int64_t M = 2 * f->Next, Mo = 2 * f->No, Mp = 2 * f->Np;
+  // the refinement's last products (X, W, A_pp^{-1}) come from the side
+  // stream: with app_done the stream has joined it already
+  if (!app_done) HIP_CHECK(hipStreamWaitEvent(s, f->done.e, 0));
   if (app_done) {
   } else if (f->Np > 0 && f->app_hbs_on) {
     woodbury_app_apply(f, nrhs, s);
@@ -856,7 +861,6 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
     launch_r_rows(f.d_p.p, f.d_J.p + f.k_k, f.k_p, w->d_nodes.p, f.d_ref_kind.p, f.No, f.d_p.p, f.Np, 1,
                   f.R.p + (size_t)f.k_k * M, M, s);
   }
-  DBuf<int> dinfo(ctx, 4);
   if (f.k > 0) {
     // ---- a4: X = A~^{-1} L; the A_oo^{-1} block needs only the reference inverse
     f.X.alloc(ctx, (size_t)M * f.k);
@@ -866,36 +870,53 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
       hbs_apply(w, f.L.p, M, f.X.p, M, f.k_k, false);
     }
   }
-  a3.join();
+  // ---- the rest (A_pp^{-1} block of X, W and its inverse) runs on the side
+  // stream, behind this stream's work so far and the A_pp build, so that the
+  // main stream is free for the solve's A_oo^{-1} apply meanwhile; the solve
+  // joins the side stream before the Woodbury correction
+  if (f.k > 0) {
+    f.W.alloc(ctx, (size_t)2 * f.k * f.k);
+    f.wpart.alloc(ctx, gemm_tn_part_doubles(M, f.k, f.k));
+    f.dinfo.alloc(ctx, 4);
+  }
+  const hipStream_t st = ctx_side_stream(ctx);
+  struct SideDrain {   // on an error below, no side-stream work outlives the handle's buffers
+    hipStream_t st;
+    bool armed = true;
+    ~SideDrain() { if (armed) (void)hipStreamSynchronize(st); }
+  } drain{st};
+  stream_after(ctx, st, s, 7);
+  a3.join(st);
   if (f.k > 0) {
     if (f.k_p) {
       double* xp = f.X.p + Mo + (size_t)f.k_k * M;
       if (f.app_hbs_on) {
-        PhaseTimer t_x(ctx, "a4_Xp", 2.0 * f.app_hbs.entries * f.k_p, 8.0 * f.app_hbs.entries * ((f.k_p + 7) / 8));
-        hbs_dev_apply(f.app_hbs, f.L.p + Mo + (size_t)f.k_k * M, M, xp, M, f.k_p, false, s);
+        PhaseTimer t_x(ctx, "a4_Xp", 2.0 * f.app_hbs.entries * f.k_p, 8.0 * f.app_hbs.entries * ((f.k_p + 7) / 8),
+                       st);
+        hbs_dev_apply(f.app_hbs, f.L.p + Mo + (size_t)f.k_k * M, M, xp, M, f.k_p, false, st);
       } else {
-        PhaseTimer t_x(ctx, "a4_Xp", 2.0 * (double)Mp * Mp * f.k_p, 8.0 * (double)Mp * Mp);
+        PhaseTimer t_x(ctx, "a4_Xp", 2.0 * (double)Mp * Mp * f.k_p, 8.0 * (double)Mp * Mp, st);
         HIP_CHECK(hipMemcpy2DAsync(xp, sizeof(double) * M, f.L.p + Mo + (size_t)f.k_k * M, sizeof(double) * M,
-                                   sizeof(double) * Mp, f.k_p, hipMemcpyDeviceToDevice, s));
-        launch_lu_solve(f.App.p, Mp, Mp, xp, M, f.k_p, s);
+                                   sizeof(double) * Mp, f.k_p, hipMemcpyDeviceToDevice, st));
+        launch_lu_solve(f.App.p, Mp, Mp, xp, M, f.k_p, st);
       }
     }
     // ---- a5: W = I + R X and its inverse (FP64)
-    f.W.alloc(ctx, (size_t)2 * f.k * f.k);
-    PhaseTimer t_w(ctx, "a5_W", 2.0 * f.k * (double)f.k * M + 2.0 * (double)f.k * f.k * f.k, 16.0 * f.k * (double)M);
-    DBuf<double> part(ctx, gemm_tn_part_doubles(M, f.k, f.k));
-    launch_gemm_tn(f.R.p, M, f.X.p, M, M, f.k, f.k, f.W.p, f.k, true, part.p, s);
-    launch_small_inverse(f.W.p, f.k, dinfo.p + 1, s);
-    HIP_CHECK(hipMemcpyAsync(ctx->defer_pin, dinfo.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    PhaseTimer t_w(ctx, "a5_W", 2.0 * f.k * (double)f.k * M + 2.0 * (double)f.k * f.k * f.k, 16.0 * f.k * (double)M,
+                   st);
+    launch_gemm_tn(f.R.p, M, f.X.p, M, M, f.k, f.k, f.W.p, f.k, true, f.wpart.p, st);
+    launch_small_inverse(f.W.p, f.k, f.dinfo.p + 1, st);
+    HIP_CHECK(hipMemcpyAsync(ctx->defer_pin, f.dinfo.p + 1, sizeof(int), hipMemcpyDeviceToHost, st));
   } else {
     *ctx->defer_pin = 0;
   }
   // the W pivot flag and the A_pp build's flags and statistics (read back on
-  // its stream, which the main stream has waited for) are checked once the
-  // stream has passed this event: here under the profiler, otherwise by the
-  // next call that uses the handle or the next refinement on this ctx
+  // the helper's stream, which the side stream has waited for) are checked
+  // once the side stream has passed this event: here under the profiler,
+  // otherwise by the next call that uses the handle or the next refinement
   if (!f.done.e) HIP_CHECK(hipEventCreateWithFlags(&f.done.e, hipEventDisableTiming));
-  HIP_CHECK(hipEventRecord(f.done.e, s));
+  HIP_CHECK(hipEventRecord(f.done.e, st));
+  drain.armed = false;
   f.pending = true;
   if (ctx->prof) {
     refined_settle(&f);
