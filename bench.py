@@ -56,11 +56,11 @@ KERNEL_BOUND = {
 # the counters were taken; otherwise the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
     "node_factor_bordered_kernel": {
-        "fetch_kib": 2643.3, "write_kib": 6439.2, "fetch_scale": 1.9999, "write_scale": 1.0000,
+        "fetch_kib": 2644.8, "write_kib": 6433.8, "fetch_scale": 1.9999, "write_scale": 1.0000,
         "sources": ["paper_2108_07205_amd/csrc/hbs_gpu.hip", "paper_2108_07205_amd/csrc/dev_gj.h",
                     "paper_2108_07205_amd/csrc/dev_reduce.h", "paper_2108_07205_amd/csrc/hbs_dev.h",
                     "paper_2108_07205_amd/csrc/common.h"],
-        "sha256": "0fc3c5081c90d2abad5ea21ec4633d1ce68c3eda726cd1aa3c5a78d695237d4b",
+        "sha256": "edb18a1da6304bd5db38b705cf895f5b82b5ec35bd2e255e4f205fc738a99d36",
         "summary": "profiles/star1024_refine16x4_hbm_traffic.md",
     },
 }
