@@ -20,17 +20,36 @@ constexpr int kRows = 64;    // rows per workgroup (one per lane)
 constexpr int kUnroll = 16;  // loads in flight per lane
 constexpr int kMfmaMin = 40;  // right-hand sides from which the slab product runs on MFMA (measured crossover)
 
+// The first kUnroll entries of row `row` in the column quarter w of M (R x
+// C, ld R), loaded before the input slice is staged so that the two loads'
+// latencies overlap (slab_gemv takes them as its first chunk).
+template <typename T>
+__device__ __forceinline__ void slab_prefetch(const T* __restrict__ M, int R, int C, int row, int w,
+                                              double (&m0)[kUnroll]) {
+  const int c0 = (w * C) >> 2, c1 = ((w + 1) * C) >> 2;
+  if (row >= R || c0 + kUnroll > c1) return;
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) m0[u] = (double)M[row + (int64_t)(c0 + u) * R];
+}
+
 // acc = rows `row` of M (R x C, ld R) times xs (C x RB, row-major in LDS),
-// over the column quarter w of the four waves.
+// over the column quarter w of the four waves; m0: slab_prefetch's chunk.
 template <typename T, int RB>
 __device__ __forceinline__ void slab_gemv(const T* __restrict__ M, int R, int C, int row, const double* xs, int w,
-                                          double (&acc)[RB]) {
+                                          const double (&m0)[kUnroll], double (&acc)[RB]) {
 #pragma unroll
   for (int c = 0; c < RB; ++c) acc[c] = 0.0;
   if (row >= R) return;
   const int c0 = (w * C) >> 2, c1 = ((w + 1) * C) >> 2;
   const T* mp = M + row;
   int col = c0;
+  if (col + kUnroll <= c1) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+      for (int c = 0; c < RB; ++c) acc[c] += m0[u] * xs[(col + u) * RB + c];
+    col += kUnroll;
+  }
   for (; col + kUnroll <= c1; col += kUnroll) {
     double m[kUnroll];
 #pragma unroll
@@ -70,14 +89,17 @@ __global__ __launch_bounds__(kThreads) void hbs_up_kernel(
   double* xs = sm;
   double* red = sm + xs_len;
   const int64_t io = in_off[j];
+  const int row = rb * kRows + lane;
+  const T* Mj = gen + up_off[j];
+  double m0[kUnroll];
+  slab_prefetch<T>(Mj, R, n, row, w, m0);
   for (int idx = tid; idx < n * RB; idx += kThreads) {
     const int col = idx / RB, c = idx - col * RB;
     xs[idx] = (c < nr) ? in[io + col + (int64_t)(r0 + c) * ld_in] : 0.0;
   }
   __syncthreads();
-  const int row = rb * kRows + lane;
   double acc[RB];
-  slab_gemv<T, RB>(gen + up_off[j], R, n, row, xs, w, acc);
+  slab_gemv<T, RB>(Mj, R, n, row, xs, w, m0, acc);
 #pragma unroll
   for (int c = 0; c < RB; ++c) red[(w * RB + c) * kRows + lane] = acc[c];
   __syncthreads();
@@ -107,14 +129,17 @@ __global__ __launch_bounds__(kThreads) void hbs_down_kernel(
   double* xs = sm;
   double* red = sm + xs_len;
   const int64_t io = in_off[j], ko = kout_off[j];
+  const int row = rb * kRows + lane;
+  const T* Ej = gen + e_off[j];
+  double m0[kUnroll];
+  slab_prefetch<T>(Ej, n, k, row, w, m0);
   for (int idx = tid; idx < k * RB; idx += kThreads) {
     const int col = idx / RB, c = idx - col * RB;
     xs[idx] = (c < nr) ? xhat[ko + col + (int64_t)(r0 + c) * ld_xh] : 0.0;
   }
   __syncthreads();
-  const int row = rb * kRows + lane;
   double acc[RB];
-  slab_gemv<T, RB>(gen + e_off[j], n, k, row, xs, w, acc);
+  slab_gemv<T, RB>(Ej, n, k, row, xs, w, m0, acc);
 #pragma unroll
   for (int c = 0; c < RB; ++c) red[(w * RB + c) * kRows + lane] = acc[c];
   __syncthreads();
@@ -138,14 +163,16 @@ __global__ __launch_bounds__(kThreads) void hbs_root_kernel(int nmax, const int*
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   double* xs = sm;
   double* red = sm + nmax * RB;
+  const int row = blockIdx.x * kRows + lane;
+  double m0[kUnroll];
+  slab_prefetch<double>(G, n, n, row, w, m0);
   for (int idx = tid; idx < n * RB; idx += kThreads) {
     const int col = idx / RB, c = idx - col * RB;
     xs[idx] = (c < nr) ? in[col + (int64_t)(r0 + c) * ld_in] : 0.0;
   }
   __syncthreads();
-  const int row = blockIdx.x * kRows + lane;
   double acc[RB];
-  slab_gemv<double, RB>(G, n, n, row, xs, w, acc);
+  slab_gemv<double, RB>(G, n, n, row, xs, w, m0, acc);
 #pragma unroll
   for (int c = 0; c < RB; ++c) red[(w * RB + c) * kRows + lane] = acc[c];
   __syncthreads();
