@@ -1252,14 +1252,19 @@ __global__ __launch_bounds__(BWV * 64) void node_factor_bordered_kernel(
     if (w == bj) {
       // ---- panel: nb steps on this wave's columns
       bool ok = true;
+      // pivot key of the step's column: the first one here, the next one
+      // inside each step, right after that column is eliminated, so that its
+      // search overlaps the step's other column updates
+      auto col_key = [&](int c) __attribute__((always_inline)) {
+        double km = 0.0;
+#pragma unroll
+        for (int sr = 0; sr < BS; ++sr) km = fmax(km, pivot_key_bits<8>(a[sr][c], lane + 64 * sr, !used[sr]));
+        return wave_max_nonneg(km);
+      };
+      double kmax = col_key(0);
 #pragma unroll
       for (int c = 0; c < BC; ++c) {
         if (c < nb && ok) {
-          double kmax = 0.0;
-#pragma unroll
-          for (int sr = 0; sr < BS; ++sr)
-            kmax = fmax(kmax, pivot_key_bits<8>(a[sr][c], lane + 64 * sr, !used[sr]));
-          kmax = wave_max_nonneg(kmax);
           const int p = __builtin_amdgcn_readfirstlane(pivot_key_index<8>(kmax));
           const int ps = p >> 6, pl = p & 63;
           // pivot row by readlane from its (wave-uniform) row slot: one
@@ -1281,19 +1286,30 @@ __global__ __launch_bounds__(BWV * 64) void node_factor_bordered_kernel(
             if (lane == 0) S.bad = 1;
           } else {
             const double pinv = recip_nr2(piv);
-            if (lane == 0) {
-              S.piv[j0 + c] = p;
-              S.pinv[j0 + c] = pinv;
+            bool isp[BS];
+            double f[BS];
+#pragma unroll
+            for (int sr = 0; sr < BS; ++sr) {
+              isp[sr] = lane + 64 * sr == p;
+              f[sr] = isp[sr] ? 0.0 : a[sr][c] * pinv;
+              used[sr] = used[sr] || isp[sr];
+            }
+            if (c + 1 < BC) {
+#pragma unroll
+              for (int sr = 0; sr < BS; ++sr) a[sr][c + 1] -= f[sr] * pr[c + 1];
+              kmax = col_key(c + 1);
             }
 #pragma unroll
             for (int sr = 0; sr < BS; ++sr) {
-              const bool isp = lane + 64 * sr == p;
-              const double f = isp ? 0.0 : a[sr][c] * pinv;
-              if (isp) used[sr] = true;
 #pragma unroll
-              for (int cc = 0; cc < BC; ++cc) a[sr][cc] -= f * pr[cc];
-              a[sr][c] = isp ? 1.0 : -f;
+              for (int cc = 0; cc < BC; ++cc)
+                if (cc != c + 1) a[sr][cc] -= f[sr] * pr[cc];
+              a[sr][c] = isp[sr] ? 1.0 : -f[sr];
             }
+            // wave-uniform values: every lane stores the same words (no
+            // branch, so the step stays one block for the scheduler)
+            S.piv[j0 + c] = p;
+            S.pinv[j0 + c] = pinv;
           }
         }
       }
