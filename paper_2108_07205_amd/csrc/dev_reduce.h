@@ -42,10 +42,18 @@ __device__ __forceinline__ double recip_nr2(double x) {
 // largest v (to 2^(bits-52) relative) and, among equal magnitudes, to the
 // lowest index i < 2^bits.  Unusable entries get 0; non-finite magnitudes
 // get the largest finite double, so that they are picked (and reported).
-// (Branch-free: the key is always formed and then selected, so that a
-// caller's straight-line code stays one block the scheduler can interleave.)
 template <int BITS>
 __device__ __forceinline__ double pivot_key_bits(double v, int i, bool usable) {
+  if (!usable) return 0.0;
+  const double m = isfinite(v) ? fabs(v) : 1.7976931348623157e308;
+  constexpr unsigned long long mask = (1ull << BITS) - 1;
+  const unsigned long long b = ((unsigned long long)__double_as_longlong(m) & ~mask) | (unsigned)(mask - i);
+  return __longlong_as_double((long long)b);
+}
+// The same key, branch-free (formed, then selected), for callers whose
+// straight-line step should stay one block the scheduler can interleave.
+template <int BITS>
+__device__ __forceinline__ double pivot_key_bits_sel(double v, int i, bool usable) {
   const double m = isfinite(v) ? fabs(v) : 1.7976931348623157e308;
   constexpr unsigned long long mask = (1ull << BITS) - 1;
   const unsigned long long b = ((unsigned long long)__double_as_longlong(m) & ~mask) | (unsigned)(mask - i);

@@ -1258,7 +1258,7 @@ __global__ __launch_bounds__(BWV * 64) void node_factor_bordered_kernel(
       auto col_key = [&](int c) __attribute__((always_inline)) {
         double km = 0.0;
 #pragma unroll
-        for (int sr = 0; sr < BS; ++sr) km = fmax(km, pivot_key_bits<8>(a[sr][c], lane + 64 * sr, !used[sr]));
+        for (int sr = 0; sr < BS; ++sr) km = fmax(km, pivot_key_bits_sel<8>(a[sr][c], lane + 64 * sr, !used[sr]));
         return wave_max_nonneg(km);
       };
       double kmax = col_key(0);
@@ -1350,16 +1350,36 @@ __global__ __launch_bounds__(BWV * 64) void node_factor_bordered_kernel(
           for (int cc = 0; cc < BC; ++cc) S.rows[w][tt[sr]][cc] = a[sr][cc];
         }
       __builtin_amdgcn_wave_barrier();
+      // software-pipelined over half rows of 8 columns: the LDS reads of the
+      // next half (and of the next step's coefficients) are issued before
+      // the current half's FMAs, so that one wave running alone does not
+      // wait for each read
+      constexpr int H = BC / 2;
+      auto coef = [&](int t, double (&cf)[BS]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int sr = 0; sr < BS; ++sr) cf[sr] = S.pan[slot][lane + 64 * sr][t] - (tt[sr] == t ? 1.0 : 0.0);
+      };
+      double r0[H], r1[H], cf[BS], cfn[BS];
+#pragma unroll
+      for (int x = 0; x < H; ++x) r0[x] = S.rows[w][0][x];
+      coef(0, cf);
       for (int t = 0; t < nb; ++t) {
-        double rt[BC];
 #pragma unroll
-        for (int cc = 0; cc < BC; ++cc) rt[cc] = S.rows[w][t][cc];
+        for (int x = 0; x < H; ++x) r1[x] = S.rows[w][t][H + x];
 #pragma unroll
-        for (int sr = 0; sr < BS; ++sr) {
-          const double cf = S.pan[slot][lane + 64 * sr][t] - (tt[sr] == t ? 1.0 : 0.0);
+        for (int sr = 0; sr < BS; ++sr)
 #pragma unroll
-          for (int cc = 0; cc < BC; ++cc) a[sr][cc] += cf * rt[cc];
-        }
+          for (int x = 0; x < H; ++x) a[sr][x] += cf[sr] * r0[x];
+        const int tn = min(t + 1, nb - 1);
+#pragma unroll
+        for (int x = 0; x < H; ++x) r0[x] = S.rows[w][tn][x];
+        coef(tn, cfn);
+#pragma unroll
+        for (int sr = 0; sr < BS; ++sr)
+#pragma unroll
+          for (int x = 0; x < H; ++x) a[sr][H + x] += cf[sr] * r1[x];
+#pragma unroll
+        for (int sr = 0; sr < BS; ++sr) cf[sr] = cfn[sr];
       }
       __builtin_amdgcn_wave_barrier();
     };
