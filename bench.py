@@ -56,11 +56,11 @@ KERNEL_BOUND = {
 # the counters were taken; otherwise the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
     "node_factor_bordered_kernel": {
-        "fetch_kib": 2644.8, "write_kib": 6433.8, "fetch_scale": 1.9999, "write_scale": 1.0000,
+        "fetch_kib": 2652.9, "write_kib": 6427.2, "fetch_scale": 1.9999, "write_scale": 1.0000,
         "sources": ["paper_2108_07205_amd/csrc/hbs_gpu.hip", "paper_2108_07205_amd/csrc/dev_gj.h",
                     "paper_2108_07205_amd/csrc/dev_reduce.h", "paper_2108_07205_amd/csrc/hbs_dev.h",
                     "paper_2108_07205_amd/csrc/common.h"],
-        "sha256": "edb18a1da6304bd5db38b705cf895f5b82b5ec35bd2e255e4f205fc738a99d36",
+        "sha256": "fbb2a5d11584f0a8eec0a9ce2cf4849932ab75acafaabbbf77db308acb365ed3",
         "summary": "profiles/star1024_refine16x4_hbm_traffic.md",
     },
 }
