@@ -484,6 +484,9 @@ void refined_settle(rw_refined* f, bool quiet = false) {
     } catch (const RwError& e) {
       f->fail_rc = e.code;
       f->fail_msg = e.what();
+    } catch (...) {   // (also reached from rw_refined_free, which must not throw)
+      f->fail_rc = RW_EDEVICE;
+      f->fail_msg = "reading the refinement's device-side checks failed";
     }
   }
   if (f->fail_rc != RW_OK && !quiet) RW_THROW(f->fail_rc, f->fail_msg);
