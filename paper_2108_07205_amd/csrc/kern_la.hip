@@ -521,6 +521,36 @@ __global__ __launch_bounds__(256) void sub_xw_kernel(const double* __restrict__ 
   }
 }
 
+// y -= X (W^-1 z) in one launch: every block stages W^-1 (k x k) and z in
+// LDS, forms w = W^-1 z there (the same sums as small_gemm_kernel), then
+// subtracts X w from its rows as sub_xw_kernel does.
+__global__ __launch_bounds__(256) void woodbury_sub_kernel(const double* __restrict__ X, int64_t ldx, int64_t M, int k,
+                                                           const double* __restrict__ Wi,
+                                                           const double* __restrict__ z, double* __restrict__ Y,
+                                                           int64_t ldy, int nrhs) {
+  extern __shared__ double sm[];
+  double* sW = sm;               // k x k
+  double* sz = sW + k * k;       // k x nrhs
+  double* ws = sz + k * nrhs;    // k x nrhs
+  for (int idx = threadIdx.x; idx < k * k; idx += 256) sW[idx] = Wi[idx];
+  for (int idx = threadIdx.x; idx < k * nrhs; idx += 256) sz[idx] = z[idx];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < k * nrhs; idx += 256) {
+    const int i = idx % k, c = idx / k;
+    double s = 0;
+    for (int j = 0; j < k; ++j) s += sW[i + j * k] * sz[j + c * k];
+    ws[idx] = s;
+  }
+  __syncthreads();
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= M) return;
+  for (int c = 0; c < nrhs; ++c) {
+    double s = 0;
+    for (int j = 0; j < k; ++j) s += X[e + (int64_t)j * ldx] * ws[j + c * k];
+    Y[e + (int64_t)c * ldy] -= s;
+  }
+}
+
 // ================================================================ small inverse
 // Gauss-Jordan with partial pivoting, one workgroup, matrix in global memory
 // (k x k, ld = k), inverse built in `inv` then copied back.
@@ -963,6 +993,17 @@ void launch_sub_xw(const double* X, int64_t ldx, int64_t M, int k, const double*
   hipLaunchKernelGGL(sub_xw_kernel, dim3(blocks(M)), dim3(256), sizeof(double) * k * nrhs, s, X, ldx, M, k, W, Y, ldy,
                      nrhs);
   KERNEL_CHECK("sub_xw");
+}
+
+bool launch_woodbury_sub(const double* X, int64_t ldx, int64_t M, int k, const double* Winv, const double* z,
+                         double* Y, int64_t ldy, int nrhs, hipStream_t s) {
+  if (k <= 0 || M <= 0) return true;
+  const size_t sh = sizeof(double) * ((size_t)k * k + 2 * (size_t)k * nrhs);
+  if (sh > 150 * 1024) return false;
+  func_lds_at_least((const void*)woodbury_sub_kernel, (int)sh);
+  hipLaunchKernelGGL(woodbury_sub_kernel, dim3(blocks(M)), dim3(256), sh, s, X, ldx, M, k, Winv, z, Y, ldy, nrhs);
+  KERNEL_CHECK("woodbury_sub");
+  return true;
 }
 
 void launch_small_inverse(double* W, int k, int* info, hipStream_t s) {

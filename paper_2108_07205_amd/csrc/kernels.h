@@ -126,6 +126,10 @@ void launch_sub_xw(const double* X, int64_t ldx, int64_t M, int k, const double*
 void launch_small_inverse(double* W, int k, int* info, hipStream_t s);
 // out = Winv z (k x k times k x nrhs)
 void launch_small_gemm(const double* Winv, int k, const double* z, int nrhs, double* out, hipStream_t s);
+// Y = Y - X (Winv z) in one launch (Winv: k x k, z: k x nrhs, both col-major
+// ld = k); false, with nothing launched, when W^-1 and z do not fit in LDS.
+bool launch_woodbury_sub(const double* X, int64_t ldx, int64_t M, int k, const double* Winv, const double* z,
+                         double* Y, int64_t ldy, int nrhs, hipStream_t s);
 
 // unpivoted blocked LU of an n x n matrix (ld), in place; *info = first tiny pivot + 1
 void launch_lu_nopiv(double* A, int64_t n, int64_t ld, int* info, double* work, hipStream_t s);

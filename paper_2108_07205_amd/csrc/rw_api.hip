@@ -553,8 +553,10 @@ void woodbury_out(rw_refined* f, double* dst, int nrhs, bool accumulate, bool ap
     // z = R y, w = W^{-1} z, y -= X w
     PhaseTimer t(f->ctx, "a7_woodbury", 4.0 * f->k * (double)M * nrhs, 16.0 * f->k * (double)M);
     launch_gemm_tn(f->R.p, M, f->y.p, M, M, f->k, nrhs, f->z.p, f->k, false, f->part.p, s);
-    launch_small_gemm(f->W.p, f->k, f->z.p, nrhs, f->wv.p, s);
-    launch_sub_xw(f->X.p, M, M, f->k, f->wv.p, f->y.p, M, nrhs, s);
+    if (!launch_woodbury_sub(f->X.p, M, M, f->k, f->W.p, f->z.p, f->y.p, M, nrhs, s)) {
+      launch_small_gemm(f->W.p, f->k, f->z.p, nrhs, f->wv.p, s);
+      launch_sub_xw(f->X.p, M, M, f->k, f->wv.p, f->y.p, M, nrhs, s);
+    }
   }
   launch_from_ext(f->y.p, M, f->Nn, f->d_new2ext.p, dst, 2 * f->Nn, nrhs, accumulate, s);
 }
