@@ -472,9 +472,16 @@ __global__ __launch_bounds__(256) void node_sketch_sum_kernel(const double* __re
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= len) return;
   const double* part = blockIdx.y ? part_c : part_r;
-  double v = 0.0;
-  for (int z = 0; z < nsplit; ++z) v += part[i + z * stride];
-  (blockIdx.y ? Sc : Sr)[i] = v;
+  // four independent sums (z mod 4), so that four loads are in flight at a
+  // time, combined in a fixed order
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  int z = 0;
+  for (; z + 4 <= nsplit; z += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] += part[i + (int64_t)(z + u) * stride];
+  }
+  for (int u = 0; z < nsplit; ++z, ++u) v[u] += part[i + (int64_t)z * stride];
+  (blockIdx.y ? Sc : Sr)[i] = (v[0] + v[1]) + (v[2] + v[3]);
 }
 
 // ---------------------------------------------------------------- 2. row ID

@@ -169,13 +169,24 @@ __global__ __launch_bounds__(256) void far_coef_sum_kernel(const double2* __rest
                                                            double2* __restrict__ coef) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= len) return;
-  double re = 0.0, im = 0.0;
-  for (int z = 0; z < nsplit; ++z) {
-    const double2 v = part[(int64_t)z * len + i];
-    re += v.x;
-    im += v.y;
+  // four independent sums (z mod 4), so that four loads are in flight at a
+  // time, combined in a fixed order
+  double re[4] = {0.0, 0.0, 0.0, 0.0}, im[4] = {0.0, 0.0, 0.0, 0.0};
+  int z = 0;
+  for (; z + 4 <= nsplit; z += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double2 v = part[(int64_t)(z + u) * len + i];
+      re[u] += v.x;
+      im[u] += v.y;
+    }
   }
-  coef[i] = make_double2(re, im);
+  for (int u = 0; z < nsplit; ++z, ++u) {
+    const double2 v = part[(int64_t)z * len + i];
+    re[u] += v.x;
+    im[u] += v.y;
+  }
+  coef[i] = make_double2((re[0] + re[1]) + (re[2] + re[3]), (im[0] + im[1]) + (im[2] + im[3]));
 }
 
 // grid (ceil(nt / 256), ncols / 16), 256 threads: thread = target node,
