@@ -276,15 +276,16 @@ __global__ __launch_bounds__(256) void resid_finalize_kernel(const NodeRec* __re
     const double a00 = q.s00 - q.w * q.nx * q.nx, a01 = q.s01 - q.w * q.nx * q.ny, a11 = q.s11 - q.w * q.ny * q.ny;
     double ax = a00 * tx + a01 * ty + q.nx * sN;
     double ay = a01 * tx + a11 * ty + q.ny * sN;
-    // split partials in eight independent sums (z mod 8), so that eight
-    // loads are in flight at a time, combined in a fixed order
-    double sx[8] = {}, sy[8] = {};
+    // split partials in RSUM independent sums (z mod RSUM), so that RSUM
+    // loads are in flight at a time, combined pairwise in a fixed order
+    constexpr int RSUM = 16;
+    double sx[RSUM] = {}, sy[RSUM] = {};
     const double2* p2 = reinterpret_cast<const double2*>(part + (int64_t)c * ld) + i;
     const int64_t zst = (int64_t)nrhs * n;   // split stride in double2
     int z = 0;
-    for (; z + 8 <= nsplit; z += 8) {
+    for (; z + RSUM <= nsplit; z += RSUM) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < RSUM; ++u) {
         const double2 v = p2[(int64_t)(z + u) * zst];
         sx[u] += v.x;
         sy[u] += v.y;
@@ -295,8 +296,15 @@ __global__ __launch_bounds__(256) void resid_finalize_kernel(const NodeRec* __re
       sx[u] += v.x;
       sy[u] += v.y;
     }
-    ax += ((sx[0] + sx[1]) + (sx[2] + sx[3])) + ((sx[4] + sx[5]) + (sx[6] + sx[7]));
-    ay += ((sy[0] + sy[1]) + (sy[2] + sy[3])) + ((sy[4] + sy[5]) + (sy[6] + sy[7]));
+#pragma unroll
+    for (int h = RSUM / 2; h > 0; h >>= 1)
+#pragma unroll
+      for (int u = 0; u < h; ++u) {
+        sx[u] += sx[u + h];
+        sy[u] += sy[u + h];
+      }
+    ax += sx[0];
+    ay += sy[0];
     const double gx = g[2 * i + (int64_t)c * ld], gy = g[2 * i + 1 + (int64_t)c * ld];
     const double rx = gx - ax, ry = gy - ay;
     r[2 * i + (int64_t)c * ld] = rx;
@@ -555,8 +563,16 @@ __global__ __launch_bounds__(256) void sum_parts_kernel(const double* __restrict
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t len = rows * w;
   if (i >= len) return;
-  double s = 0.0;
-  for (int z = 0; z < nsplit; ++z) s += part[(int64_t)z * len + i];
+  // four independent sums (z mod 4), so that four loads are in flight at a
+  // time, combined in a fixed order
+  double sv[4] = {0.0, 0.0, 0.0, 0.0};
+  int z = 0;
+  for (; z + 4 <= nsplit; z += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sv[u] += part[(int64_t)(z + u) * len + i];
+  }
+  for (int u = 0; z < nsplit; ++z, ++u) sv[u] += part[(int64_t)z * len + i];
+  const double s = (sv[0] + sv[1]) + (sv[2] + sv[3]);
   const int64_t r = i / w;
   const int c = (int)(i - r * w);
   Y[r * ldY + col_off + c] = s;
