@@ -56,11 +56,11 @@ KERNEL_BOUND = {
 # the counters were taken; otherwise the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
     "node_factor_bordered_kernel": {
-        "fetch_kib": 2652.9, "write_kib": 6427.2, "fetch_scale": 1.9999, "write_scale": 1.0000,
+        "fetch_kib": 2654.0, "write_kib": 6433.5, "fetch_scale": 1.9999, "write_scale": 1.0000,
         "sources": ["paper_2108_07205_amd/csrc/hbs_gpu.hip", "paper_2108_07205_amd/csrc/dev_gj.h",
                     "paper_2108_07205_amd/csrc/dev_reduce.h", "paper_2108_07205_amd/csrc/hbs_dev.h",
                     "paper_2108_07205_amd/csrc/common.h"],
-        "sha256": "fbb2a5d11584f0a8eec0a9ce2cf4849932ab75acafaabbbf77db308acb365ed3",
+        "sha256": "f1fa1b9e4aefe3ec3897e5f96cf123868a118bd0421a900f37f7cb37392abc14",
         "summary": "profiles/star1024_refine16x4_hbm_traffic.md",
     },
 }
