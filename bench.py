@@ -18,7 +18,7 @@ reference inverse (the paper's T_static) is built once before timing.  A step
 counts toward the rate only if its solve meets the residual certificate
 (||g - A tau|| / ||g|| <= 1e-13 with kappa ~ 4e2, i.e. error <~ 1e-10).
 
-Prints ONE JSON line.  --gpus > 1 is refused: this build runs on one GPU.
+Prints ONE JSON line.  --gpus > 1 is refused: the refined-wall path runs on one GPU.
 """
 from __future__ import annotations
 
@@ -167,7 +167,7 @@ def main():
                     help="steps of the side measurements (RHS/s with resident factors, FP32-generator mode)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU (the refined-wall path is not sharded); use --gpus 1",
+        print("bench.py: the refined-wall path runs on one GPU (it is not sharded); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     import torch
