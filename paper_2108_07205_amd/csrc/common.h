@@ -79,6 +79,7 @@ struct rw_ctx {
   // (non-blocking, default priority; created on first use) and the
   // timing-free events that order the two
   hipStream_t side = nullptr;
+  hipStream_t side2 = nullptr;   // a third one, used beside `side` (created on first use)
   std::vector<hipEvent_t> order_events;
   // pinned host staging for small per-call transfers (grow-only), and a
   // separate pinned area for small read-backs (a pageable one would keep
@@ -132,6 +133,7 @@ struct KernelTimer {
 // The ctx's second stream, and its i-th ordering event (both created on
 // first use and kept until the ctx is destroyed).
 hipStream_t ctx_side_stream(rw_ctx* ctx);
+hipStream_t ctx_side2_stream(rw_ctx* ctx);
 hipEvent_t ctx_order_event(rw_ctx* ctx, int i);
 // Pinned host staging of at least `bytes` (grow-only; growing first waits
 // for the ctx's streams, so no copy from the old buffer is still in flight).

@@ -1980,15 +1980,19 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
   // this function ends, later work on the main stream waits for it
   const hipStream_t sf = ctx_side_stream(ctx);
   stream_after(ctx, sf, s, 0);
+  // the block-inverse fallbacks of a level run on a third stream beside the
+  // level's bordered factorization (they take disjoint nodes)
+  const hipStream_t sf2 = ctx_side2_stream(ctx);
   struct SideJoin {
     rw_ctx* c;
-    hipStream_t main, side;
+    hipStream_t main, side, side2;
     ~SideJoin() {
-      hipEvent_t e = nullptr;
-      try { e = ctx_order_event(c, 2); } catch (...) { return; }
+      hipEvent_t e = nullptr, e2 = nullptr;
+      try { e = ctx_order_event(c, 2); e2 = ctx_order_event(c, 10); } catch (...) { return; }
+      if (hipEventRecord(e2, side2) == hipSuccess) (void)hipStreamWaitEvent(main, e2, 0);
       if (hipEventRecord(e, side) == hipSuccess) (void)hipStreamWaitEvent(main, e, 0);
     }
-  } side_join{ctx, s, sf};
+  } side_join{ctx, s, sf, sf2};
   w.ctx = ctx;
   w.L = L;
   w.lev.assign(L + 1, HbsLevelDev());
@@ -2006,7 +2010,12 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
   auto factor_launch = [&](const GNode* gn, const GNode* gch, int nn, int is_leaf, int is_root, const int* cr,
                            const int* cc, const double* U, const double* V, double* groot, int mx_known, int lvl) {
     // nodes with n + k <= BT: bordered Gauss-Jordan; the others: block
-    // inverse in registers (n <= FN) or LDS Gauss-Jordan
+    // inverse in registers (n <= FN) or LDS Gauss-Jordan, on sf2 beside it:
+    // sf2 starts from sf's point before this launch (the level's inputs and
+    // the children's D^), and sf's later work waits for it
+    const bool small = !is_root && (mx_known < 0 || mx_known <= FN);
+    const bool large = !is_root && (mx_known < 0 || mx_known > FN);
+    if (small || large) stream_after(ctx, sf2, sf, 8);
     {
       KernelTimer kt("node_factor_bordered_kernel", 0.0, 0.0, sf);
       hipLaunchKernelGGL(node_factor_bordered_kernel, dim3(nn), dim3(BWV * 64), 0, sf, gn, gch, is_leaf, is_root, cr, cc,
@@ -2016,20 +2025,19 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
     if (ctx->prof && !ctx->pending.empty()) fac_entry[lvl] = ctx->pending.size() - 1;
     // the root block (n = k_1 + k_2 <= 2 SK_KCAP) always fits the bordered kernel
     static_assert(2 * SK_KCAP <= BT, "the root block fits the bordered factorization");
-    const bool small = !is_root && (mx_known < 0 || mx_known <= FN);
-    const bool large = !is_root && (mx_known < 0 || mx_known > FN);
     if (small) {
-      KernelTimer kt("node_factor_kernel", 0.0, 0.0, sf);
-      hipLaunchKernelGGL(node_factor_kernel, dim3(nn), dim3(256), 0, sf, gn, gch, is_leaf, is_root, cr, cc, d_nodes,
+      KernelTimer kt("node_factor_kernel", 0.0, 0.0, sf2);
+      hipLaunchKernelGGL(node_factor_kernel, dim3(nn), dim3(256), 0, sf2, gn, gch, is_leaf, is_root, cr, cc, d_nodes,
                          U, V, dh_child, dh_cur, ws.p, w.gen.p, groot, failp, 0, FN);
       KERNEL_CHECK("node_factor");
     }
     if (large) {
-      KernelTimer kt("node_inverse_kernel", 0.0, 0.0, sf);
-      hipLaunchKernelGGL(node_inverse_kernel, dim3(nn), dim3(256), shv, sf, gn, gch, is_leaf, is_root, cr, cc, d_nodes,
+      KernelTimer kt("node_inverse_kernel", 0.0, 0.0, sf2);
+      hipLaunchKernelGGL(node_inverse_kernel, dim3(nn), dim3(256), shv, sf2, gn, gch, is_leaf, is_root, cr, cc, d_nodes,
                          U, V, dh_child, dh_cur, ws.p, w.gen.p, groot, failp, FN, MANY);
       KERNEL_CHECK("node_inverse");
     }
+    if (small || large) stream_after(ctx, sf, sf2, 9);
   };
   int mx_leaf = 0;
   for (const GNode& g : G[L]) mx_leaf = std::max(mx_leaf, g.m);

@@ -162,6 +162,11 @@ hipStream_t ctx_side_stream(rw_ctx* ctx) {
   return ctx->side;
 }
 
+hipStream_t ctx_side2_stream(rw_ctx* ctx) {
+  if (!ctx->side2) HIP_CHECK(hipStreamCreateWithFlags(&ctx->side2, hipStreamNonBlocking));
+  return ctx->side2;
+}
+
 hipEvent_t ctx_order_event(rw_ctx* ctx, int i) {
   while ((int)ctx->order_events.size() <= i) {
     hipEvent_t e;
@@ -331,6 +336,7 @@ static void ctx_destroy_aux(rw_ctx* ctx) {
     for (auto e : a->event_pool) (void)hipEventDestroy(e);
     for (auto e : a->order_events) (void)hipEventDestroy(e);
     if (a->side) (void)hipStreamDestroy(a->side);
+    if (a->side2) (void)hipStreamDestroy(a->side2);
     if (a->pinned) (void)hipHostFree(a->pinned);
     if (a->rb) (void)hipHostFree(a->rb);
     (void)hipStreamDestroy(a->stream);
@@ -1003,6 +1009,7 @@ void rw_ctx_destroy(rw_ctx* ctx) {
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
   for (auto e : ctx->order_events) (void)hipEventDestroy(e);
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  if (ctx->side2) (void)hipStreamDestroy(ctx->side2);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->rb) (void)hipHostFree(ctx->rb);
   if (ctx->pinned_ev) (void)hipEventDestroy(ctx->pinned_ev);
