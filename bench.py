@@ -56,11 +56,11 @@ KERNEL_BOUND = {
 # the counters were taken; otherwise the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
     "node_factor_bordered_kernel": {
-        "fetch_kib": 2654.0, "write_kib": 6433.5, "fetch_scale": 1.9999, "write_scale": 1.0000,
+        "fetch_kib": 2654.0, "write_kib": 6432.3, "fetch_scale": 1.9999, "write_scale": 1.0000,
         "sources": ["paper_2108_07205_amd/csrc/hbs_gpu.hip", "paper_2108_07205_amd/csrc/dev_gj.h",
                     "paper_2108_07205_amd/csrc/dev_reduce.h", "paper_2108_07205_amd/csrc/hbs_dev.h",
                     "paper_2108_07205_amd/csrc/common.h"],
-        "sha256": "f1fa1b9e4aefe3ec3897e5f96cf123868a118bd0421a900f37f7cb37392abc14",
+        "sha256": "7ecf603c65c54b025fc61d28c7feef22b4ca4a6c56df90d2b69333353e7ec0c9",
         "summary": "profiles/star1024_refine16x4_hbm_traffic.md",
     },
 }
