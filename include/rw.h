@@ -173,8 +173,10 @@ int rw_hbs_apply(rw_wall* wall, const double* b_dev, int32_t nrhs, double* x_dev
  * Errors: RW_EINVAL (ids out of [0, n_panels), duplicates, levels outside
  * [0, 8]), RW_ENOMEM, RW_ESINGULAR, RW_EDEVICE.
  * Asynchrony: the call returns once the last part of the pre-computation
- * (the A_pp^{-1} build's top levels, X and W) is enqueued on the ctx's
- * stream, so that the caller can enqueue the solve behind it.  The checks
+ * (the A_pp^{-1} build's top levels, X and W) is enqueued, on a second
+ * stream of the ctx that the later calls on the handle wait for; work the
+ * caller enqueues on the ctx's stream meanwhile (Stokeslet data, the solve)
+ * can start beside it.  The checks
  * that read device results (a zero pivot in W or in an HBS node block, an
  * HBS rank reaching the sketch size) are then made by the first of
  * rw_solve, rw_solve_batch or rw_residual on the handle, or by the next
