@@ -1,12 +1,18 @@
-"""Write tests/golden/*.txt from the FP64 oracle only (dense assembly + LU).
+"""Write the full-size golden solutions under tests/golden from the FP64
+oracle only (dense assembly + LU of the refined Nystrom system).
 
-config2_seed0_tau_sample.txt: the 1024-panel wall with 16 panels refined 4
-levels (40448 unknowns), Stokeslet data of seed 0; the oracle's tau_n is
-stored at 4096 seeded sample indices plus its 2-norm and max-norm, so the GPU
-test can check the full-size solve without the 13 GB dense solve.
+For every case of ``workloads.golden_cases()`` (1024-panel wall, 16384
+reference nodes; 16 panels x 4 levels at two seeds, 16 panels x 4 levels
+across theta = 0, 4 panels x 6 levels) the oracle's full tau_n (Stokeslet
+data of the case's first right-hand side) is stored as ``<case>_tau.npy``
+(float64, 2 N_n values, node-major interleaved) and its provenance
+(refinement, sizes, norms, assembly and LU times, BLAS threads) in
+``golden_meta.json``.  Nothing here calls the HIP library.
 
-Run:  python tests/golden/make_golden.py   (about 5 minutes, ~30 GB RAM)
+Run:  python tests/golden/make_golden.py [case ...]
+(about 5 minutes and 30 GB of RAM per case on 8 cores)
 """
+import json
 import os
 import sys
 import time
@@ -20,10 +26,18 @@ import workloads as W  # noqa: E402
 from oracle import geometry as G, kernels as K, solve as S  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+META = os.path.join(HERE, "golden_meta.json")
 
 
-def config2_sample(seed: int = 0, nsample: int = 4096):
-    p = W.config2(seed=seed)
+def _threads() -> int:
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        return -1
+
+
+def solve_case(name: str, p: W.Problem) -> dict:
     sets = G.refine(p.n_panels, p.refinement.panel_ids, p.refinement.levels, p.curve.a, p.curve.m)
     st = p.rhs[0]
     g = K.rhs_vector(sets.new, st.z, st.f)
@@ -32,20 +46,29 @@ def config2_sample(seed: int = 0, nsample: int = 4096):
     t1 = time.time()
     tau = S.solve_refined(A, g)
     t2 = time.time()
+    # backward error of the LU solve, from the same matrix
+    res = float(np.linalg.norm(g - A @ tau) / np.linalg.norm(g))
     del A
-    rng = np.random.default_rng(12345)
-    idx = np.unique(np.concatenate([rng.choice(tau.size, nsample - 512, replace=False),
-                                    np.sort(rng.choice(2 * sets.p_in_new, 256, replace=False)),
-                                    np.sort(rng.choice(2 * sets.p_in_new + 1, 256, replace=False))]))
-    out = os.path.join(HERE, f"config2_seed{seed}_tau_sample.txt")
-    with open(out, "w") as fh:
-        fh.write(f"# oracle tau_n for workloads.config2(seed={seed}): dense FP64 assembly + LU\n")
-        fh.write(f"# n_unknowns {tau.size} norm2 {np.linalg.norm(tau):.17e} normmax {np.max(np.abs(tau)):.17e}\n")
-        fh.write(f"# assembly {t1 - t0:.1f} s, LU solve {t2 - t1:.1f} s\n")
-        for i in idx:
-            fh.write(f"{int(i)} {tau[i]:.17e}\n")
-    print(f"wrote {out}: {idx.size} samples, assembly {t1 - t0:.1f} s, solve {t2 - t1:.1f} s")
+    np.save(os.path.join(HERE, f"{name}_tau.npy"), tau)
+    return {"n_panels": p.n_panels, "panel_ids": list(p.refinement.panel_ids),
+            "levels": list(p.refinement.levels), "seed": p.seed,
+            "n_nodes": int(sets.new.n), "n_p": int(sets.p_in_new.size),
+            "norm2": float(np.linalg.norm(tau)), "normmax": float(np.max(np.abs(tau))),
+            "lu_backward_error": res, "assembly_s": round(t1 - t0, 1), "lu_s": round(t2 - t1, 1),
+            "blas_threads": _threads(), "host_cpus": os.cpu_count()}
+
+
+def main(names):
+    cases = W.golden_cases()
+    meta = json.load(open(META)) if os.path.exists(META) else {}
+    for name in names or list(cases):
+        m = solve_case(name, cases[name])
+        meta[name] = m
+        with open(META, "w") as fh:
+            json.dump(meta, fh, indent=1, sort_keys=True)
+        print(f"{name}: {m['n_nodes']} nodes, assembly {m['assembly_s']} s, LU {m['lu_s']} s, "
+              f"backward error {m['lu_backward_error']:.2e}", flush=True)
 
 
 if __name__ == "__main__":
-    config2_sample(0)
+    main(sys.argv[1:])

@@ -108,3 +108,38 @@ def test_nystrom_rows_match_full_matrix(star64):
     sub = K.nystrom_rows(star64, rows)
     idx = np.stack([2 * rows, 2 * rows + 1], 1).reshape(-1)
     assert np.array_equal(sub, A[idx])
+
+
+def test_residual_rows_closed_forms():
+    """residual_rows(rows, tau, g) = g - A tau on the given rows, pinned by
+    closed forms of the operator (not by re-forming the same rows):
+    * rigid motions v (a constant vector, the rotation (-y, x)): the
+      double-layer kernel is the Stokeslet's stress, which a rigid motion
+      does not feel, so D v = -1/2 v on the curve; N v = n int v.n ds = 0
+      (zero flux); hence A v = -v and the residual is g + v;
+    * on a circle of radius R the normal field spans the nullspace of
+      -1/2 I + D and N n = n int |n|^2 ds = 2 pi R n, so the residual is
+      g - 2 pi R n.
+    The rows are unsorted and span several 512-row chunks; g is random, so a
+    wrong gather of g, a dropped term, a sign error or a transposed operand
+    fails."""
+    d = G.discretize(G.reference_panels(96), 0.3, 5)
+    rng = np.random.default_rng(5)
+    rows = rng.permutation(d.n)[:1100]
+    g = rng.standard_normal(2 * d.n)
+    gr = g.reshape(-1, 2)[rows]
+    c = np.array([0.7, -1.3])
+    r_c = K.residual_rows(d, rows, np.tile(c, d.n), g).reshape(-1, 2)
+    assert np.max(np.abs(r_c - (gr + c))) < 1e-11
+    rot = np.stack([-d.x[:, 1], d.x[:, 0]], axis=1)
+    r_rot = K.residual_rows(d, rows, rot.reshape(-1), g).reshape(-1, 2)
+    assert np.max(np.abs(r_rot - (gr + rot[rows]))) < 1e-11
+    R = 1.0
+    dc = G.discretize(G.reference_panels(12), 0.0, 5)
+    gc = rng.standard_normal(2 * dc.n)
+    rc_rows = rng.permutation(dc.n)[:150]
+    r_n = K.residual_rows(dc, rc_rows, dc.normal.reshape(-1), gc).reshape(-1, 2)
+    assert np.max(np.abs(r_n - (gc.reshape(-1, 2)[rc_rows] - 2 * math.pi * R * dc.normal[rc_rows]))) < 1e-12
+    # and the residual of the dense solution vanishes on the same rows
+    tau = S.solve_refined(K.nystrom_matrix(d), g)
+    assert np.max(np.abs(K.residual_rows(d, rows, tau, g))) < 1e-12 * np.max(np.abs(g))

@@ -193,3 +193,23 @@ def small_problem(n_panels: int = 16, ids: Sequence[int] = (3,), levels: Sequenc
     ref = Refinement(tuple(int(i) for i in ids), tuple(int(l) for l in levels))
     rhs = [stokeslets(rng, n_stokeslets) for _ in range(nrhs)]
     return Problem(curve, n_panels, order, leaf_nodes, ref, rhs, seed, "small")
+
+
+def golden_cases() -> dict:
+    """Full-size refinements whose dense-oracle solutions are stored under
+    tests/golden (1024-panel wall, 16384 reference nodes):
+
+    * ``config2_seed0``, ``config2_seed7``: the headline family (16 panels
+      nearest a point at 1e-3, 4 levels);
+    * ``wrap_16x4``: 16 consecutive panels across theta = 0 (1021..1023,
+      0..12), 4 levels, Stokeslets of seed 3;
+    * ``near4x6``: the 4 panels nearest a seeded point at 1e-3, 6 levels
+      (64 children each)."""
+    wrap_ids = [1021, 1022, 1023] + list(range(13))
+    return {
+        "config2_seed0": config2(seed=0),
+        "config2_seed7": config2(seed=7),
+        "wrap_16x4": small_problem(n_panels=1024, ids=wrap_ids, levels=[4] * 16,
+                                   n_stokeslets=16, seed=3),
+        "near4x6": near_point_problem("star1024_refine4x6", 1024, 4, 6, 1e-3, 16, 1, seed=5),
+    }
