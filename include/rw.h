@@ -57,8 +57,10 @@ enum rw_status {
 };
 
 /* Storage precision of the reference HBS generators used by the solve
- * (the FP64 copy is always kept for the iterative-refinement path). */
-enum rw_precision { RW_F64 = 0, RW_F32 = 1 };
+ * (the FP64 copy is always kept for the iterative-refinement path).
+ * RW_BF16 is reserved: rw_wall_build rejects it with RW_EINVAL until BF16
+ * generators are built. */
+enum rw_precision { RW_F64 = 0, RW_F32 = 1, RW_BF16 = 2 };
 
 /* Star curve gamma(theta) = (1 + a cos(m theta)) (cos theta, sin theta),
  * theta in [0, 2 pi), counter-clockwise (a = 0: unit circle). */
@@ -79,6 +81,9 @@ typedef struct {
                                 and sketch the far part of Q through multipole / local expansions,
                                 the near part exactly (used when at most half the kept nodes are
                                 near); 0: sketch the whole blocks of Q exactly [1] */
+  int32_t test_singular;     /* test hook, 0 in normal use [0]: 1 = zero the first column of W = I + R X
+                                before its inversion, 2 = zero the first column of a dense A_pp before
+                                its LU; the library's own pivot checks then report RW_ESINGULAR */
 } rw_options;
 
 /* Counts and timings reported by rw_refine / rw_solve. */
@@ -92,7 +97,20 @@ typedef struct {
   double t_solve_ms;         /* wall time of the last rw_solve */
   int64_t n_near;            /* kept nodes sketched exactly by the far-field split, -1 if Q's blocks
                                 were sketched exactly as a whole */
+  int64_t app_entries;       /* generator entries of the GPU-built HBS inverse of A_pp (0 for the dense
+                                LU or no added nodes); set once the refinement's device-side checks
+                                have been read (by the first rw_solve / rw_residual on the handle) */
+  int32_t app_max_rank;      /* largest node rank of that HBS inverse (0 as above) */
 } rw_info;
+
+/* Outcome of one rw_solve (Algorithm 1 solve steps + refinement). */
+typedef struct {
+  int32_t ir_iters;          /* refinement corrections applied */
+  int32_t k;                 /* rank k = k_k + k_p of the Woodbury update used */
+  double resid;              /* max over columns of ||g - A_nn tau|| / ||g|| on return */
+  double resid_direct;       /* the same for the plain Woodbury solution (before any correction) */
+  double t_solve_ms;         /* wall time of the call */
+} rw_solve_info;
 
 /* Reference-wall statistics reported by rw_wall_stats. */
 typedef struct {
@@ -170,6 +188,9 @@ int rw_hbs_apply(rw_wall* wall, const double* b_dev, int32_t nrhs, double* x_dev
  * children (levels[i] = 0 keeps the panel but still routes it through the
  * extended system), then build Q ~= L R, A_pp^{-1}, X = A~^{-1} L and the LU
  * of W = I + R X.  n_sel = 0 gives the unrefined wall (k = 0).
+ * q_tol: relative tolerance of the row IDs of Q's k-rows and p-rows
+ * (Definition 3.1; Secs. 3.3-3.4), in (0, 1); q_tol <= 0 takes the wall's
+ * id_tol.  The HBS inverse of A_pp (large refinements) uses the wall's id_tol.
  * Errors: RW_EINVAL (ids out of [0, n_panels), duplicates, levels outside
  * [0, 8]), RW_ENOMEM, RW_ESINGULAR, RW_EDEVICE.
  * Asynchrony: the call returns once the last part of the pre-computation
@@ -185,9 +206,9 @@ int rw_hbs_apply(rw_wall* wall, const double* b_dev, int32_t nrhs, double* x_dev
  * then on.  With the ctx profiler on, rw_refine waits and reports it
  * itself.  rw_refined_free waits for the handle's device work. */
 int rw_refine(rw_wall* wall, const int32_t* panel_ids_host, const int32_t* levels_host,
-              int32_t n_sel, rw_refined** out);
+              int32_t n_sel, double q_tol, rw_refined** out);
 /* Coarsen: give panel_ids_host[i] back its reference discretization and
- * redo the pre-computation for the remaining refinement (coarsening all
+ * redo the pre-computation (with the handle's q_tol) for the remaining refinement (coarsening all
  * refined panels returns the reference problem).  Ids that are not refined
  * are an error (RW_EINVAL).  On error the handle is unchanged. */
 int rw_coarsen(rw_refined* ref, const int32_t* panel_ids_host, int32_t n_sel);
@@ -204,11 +225,14 @@ int rw_nodes(const rw_refined* ref, double* xy_host, double* normals_host,
  * ||g - A_nn tau|| / ||g|| <= ir_tol (per column) or ir_maxit corrections.
  * With ir_maxit >= 1 the first correction is always taken (it is enqueued
  * before the first residual is read back).
- * g_dev, tau_dev: 2*N_n x nrhs column-major, may not alias.  The stream is
- * synchronized before return.  Errors: RW_EINVAL, RW_ENOMEM,
- * RW_ENOCONV (result written, residual above tolerance), RW_ESINGULAR (the
- * refinement's deferred checks failed; tau is not a solution), RW_EDEVICE. */
-int rw_solve(rw_refined* ref, const double* g_dev, int32_t nrhs, double* tau_dev);
+ * g_dev, tau_dev: 2*N_n x nrhs column-major, may not alias.  info_host: NULL
+ * or a caller-owned rw_solve_info that receives the outcome (also on
+ * RW_ENOCONV).  The stream is synchronized before return.  Errors:
+ * RW_EINVAL, RW_ENOMEM, RW_ENOCONV (result written, residual above
+ * tolerance), RW_ESINGULAR (the refinement's deferred checks failed; tau is
+ * not a solution), RW_EDEVICE. */
+int rw_solve(rw_refined* ref, const double* g_dev, int32_t nrhs, double* tau_dev,
+             rw_solve_info* info_host);
 
 /* Several refinements of one wall in one call (Algorithm 1 solve steps for
  * each; Sec. 3.2: every refinement reuses the same reference inverse).  The

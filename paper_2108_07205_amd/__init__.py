@@ -25,6 +25,7 @@ __all__ = [
     "rw_refined_free", "rw_refined_info", "rw_nodes", "rw_solve", "rw_residual", "rw_stokeslet_rhs",
     "rw_ctx_trim", "rw_profile_enable", "rw_profile_reset", "rw_profile_json",
     "RW_OK", "RW_EINVAL", "RW_ENOMEM", "RW_ESINGULAR", "RW_ENOCONV", "RW_EDEVICE", "RW_F64", "RW_F32",
+    "RW_BF16", "rw_solve_batch",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -32,7 +33,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librw.so")
 
 RW_OK, RW_EINVAL, RW_ENOMEM, RW_ESINGULAR, RW_ENOCONV, RW_EDEVICE = 0, -1, -2, -3, -4, -5
-RW_F64, RW_F32 = 0, 1
+RW_F64, RW_F32, RW_BF16 = 0, 1, 2
 _CODES = {RW_EINVAL: "RW_EINVAL", RW_ENOMEM: "RW_ENOMEM", RW_ESINGULAR: "RW_ESINGULAR",
           RW_ENOCONV: "RW_ENOCONV", RW_EDEVICE: "RW_EDEVICE"}
 
@@ -50,14 +51,21 @@ class rw_curve(ctypes.Structure):
 class rw_options(ctypes.Structure):
     _fields_ = [("ir_tol", ctypes.c_double), ("ir_maxit", ctypes.c_int32),
                 ("sketch_cols", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("app_dense_max_nodes", ctypes.c_int32), ("far_field", ctypes.c_int32)]
+                ("app_dense_max_nodes", ctypes.c_int32), ("far_field", ctypes.c_int32),
+                ("test_singular", ctypes.c_int32)]
 
 
 class rw_info(ctypes.Structure):
     _fields_ = [("n_k", ctypes.c_int64), ("n_c", ctypes.c_int64), ("n_p", ctypes.c_int64),
                 ("k_k", ctypes.c_int32), ("k_p", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("ir_iters", ctypes.c_int32), ("resid", ctypes.c_double),
-                ("t_refine_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double), ("n_near", ctypes.c_int64)]
+                ("t_refine_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double), ("n_near", ctypes.c_int64),
+                ("app_entries", ctypes.c_int64), ("app_max_rank", ctypes.c_int32)]
+
+
+class rw_solve_info(ctypes.Structure):
+    _fields_ = [("ir_iters", ctypes.c_int32), ("k", ctypes.c_int32), ("resid", ctypes.c_double),
+                ("resid_direct", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
 
 
 class rw_wall_stats(ctypes.Structure):
@@ -90,12 +98,12 @@ _SIGS = {
     "rw_wall_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(rw_wall_stats)]),
     "rw_wall_nodes": (ctypes.c_int, [_P, _DP, _DP, _DP, _I64P]),
     "rw_hbs_apply": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
-    "rw_refine": (ctypes.c_int, [_P, _I32P, _I32P, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "rw_refine": (ctypes.c_int, [_P, _I32P, _I32P, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_P)]),
     "rw_coarsen": (ctypes.c_int, [_P, _I32P, ctypes.c_int32]),
     "rw_refined_free": (None, [_P]),
     "rw_refined_info": (ctypes.c_int, [_P, ctypes.POINTER(rw_info)]),
     "rw_nodes": (ctypes.c_int, [_P, _DP, _DP, _DP, _I64P]),
-    "rw_solve": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
+    "rw_solve": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.POINTER(rw_solve_info)]),
     "rw_solve_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
     "rw_residual": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P]),
     "rw_stokeslet_rhs": (ctypes.c_int, [_P, _DP, _DP, ctypes.c_int32, _P]),
@@ -164,7 +172,7 @@ def rw_ctx_destroy(ctx):
 
 
 def rw_set_options(ctx, ir_tol=None, ir_maxit=None, sketch_cols=None, seed=None, app_dense_max_nodes=None,
-                   far_field=None):
+                   far_field=None, test_singular=None):
     lib = load_library()
     o = rw_options()
     _check(lib.rw_get_options(ctx, ctypes.byref(o)), ctx)
@@ -180,6 +188,8 @@ def rw_set_options(ctx, ir_tol=None, ir_maxit=None, sketch_cols=None, seed=None,
         o.app_dense_max_nodes = app_dense_max_nodes
     if far_field is not None:
         o.far_field = int(bool(far_field))
+    if test_singular is not None:
+        o.test_singular = int(test_singular)
     _check(lib.rw_set_options(ctx, ctypes.byref(o)), ctx)
 
 
@@ -253,14 +263,14 @@ def rw_hbs_apply(ctx, wall, b, x, n_unknowns: int):
     _check(load_library().rw_hbs_apply(wall, pb, nb, px), ctx)
 
 
-def rw_refine(ctx, wall, panel_ids: Sequence[int], levels: Sequence[int]):
+def rw_refine(ctx, wall, panel_ids: Sequence[int], levels: Sequence[int], q_tol: float = 0.0):
     ids = np.ascontiguousarray(panel_ids, dtype=np.int32)
     lev = np.ascontiguousarray(levels, dtype=np.int32)
     if ids.shape != lev.shape:
         raise ValueError("panel_ids and levels differ in length")
     out = _P()
     _check(load_library().rw_refine(wall, ids.ctypes.data_as(_I32P), lev.ctypes.data_as(_I32P), ids.size,
-                                    ctypes.byref(out)), ctx)
+                                    q_tol, ctypes.byref(out)), ctx)
     return out
 
 
@@ -283,12 +293,16 @@ def rw_nodes(ctx, ref):
     return _nodes(load_library().rw_nodes, ctx, ref)
 
 
-def rw_solve(ctx, ref, g, tau, n_unknowns: int, check: bool = True):
+def rw_solve(ctx, ref, g, tau, n_unknowns: int, check: bool = True, info: dict = None):
+    """rc of rw_solve; when `info` is a dict it receives the rw_solve_info fields."""
     pg, ng = _dev_ptr(g, "g", n_unknowns)
     pt, nt = _dev_ptr(tau, "tau", n_unknowns)
     if ng != nt:
         raise ValueError("g and tau column counts differ")
-    rc = load_library().rw_solve(ref, pg, ng, pt)
+    si = rw_solve_info()
+    rc = load_library().rw_solve(ref, pg, ng, pt, ctypes.byref(si))
+    if info is not None:
+        info.update({f: getattr(si, f) for f, _ in rw_solve_info._fields_})
     if check:
         _check(rc, ctx)
     return rc
@@ -396,8 +410,8 @@ class Wall:
         rw_hbs_apply(self.ctx.h, self.h, b, x, 2 * self.n_nodes)
         return x
 
-    def refine(self, panel_ids, levels) -> "Refined":
-        return Refined(self, panel_ids, levels)
+    def refine(self, panel_ids, levels, q_tol: float = 0.0) -> "Refined":
+        return Refined(self, panel_ids, levels, q_tol)
 
     def solve_batch(self, refs, gs, check: bool = True):
         """tau_i = A_nn(i)^{-1} g_i for refinements `refs` of this wall in one
@@ -423,10 +437,10 @@ class Wall:
 class Refined:
     """A locally refined discretization with its Algorithm-1 factors."""
 
-    def __init__(self, wall: Wall, panel_ids, levels):
+    def __init__(self, wall: Wall, panel_ids, levels, q_tol: float = 0.0):
         self.wall = wall
         self.ctx = wall.ctx
-        self.h = rw_refine(self.ctx.h, wall.h, panel_ids, levels)
+        self.h = rw_refine(self.ctx.h, wall.h, panel_ids, levels, q_tol)
         self._refresh()
 
     def _refresh(self):
@@ -453,10 +467,10 @@ class Refined:
         rw_stokeslet_rhs(self.ctx.h, self.h, z, f, g, self.n_unknowns)
         return g
 
-    def solve(self, g, check: bool = True):
+    def solve(self, g, check: bool = True, info: dict = None):
         import torch
         tau = torch.empty_like(g)
-        rw_solve(self.ctx.h, self.h, g, tau, self.n_unknowns, check=check)
+        rw_solve(self.ctx.h, self.h, g, tau, self.n_unknowns, check=check, info=info)
         return tau
 
     def residual(self, g, tau):

@@ -34,6 +34,11 @@ struct HbsDev {
   int64_t n_unknowns() const { return lev.size() > 1 ? S[L] : 0; }
 };
 
+// Passes over the generators that one apply of nrhs right-hand sides makes
+// (8 columns per pass on the vector path, 64 from 40 columns on the matrix
+// cores): the algorithmic generator bytes are passes * entries * width.
+double hbs_gen_passes(int nrhs);
+
 // Pack a host-built inverse into HBM.
 void hbs_upload(rw_ctx* ctx, const HbsInverse& H, bool with_f32, HbsDev& out);
 // x = A^{-1} b (b, x: n x nrhs column-major with leading dimensions ldb, ldx),

@@ -34,7 +34,6 @@ constexpr double kInvPi = 0.31830988618379067154;
 constexpr int SK_R = 96;       // sketch columns per node
 constexpr int SK_KCAP = 88;    // largest node rank (sketch columns minus oversampling)
 constexpr int SK_NP = 48;      // proxy points
-constexpr int SK_EXTRA = 16;   // Gram-Schmidt steps past the tolerance rank
 constexpr double SK_RATIO = 2.0;
 constexpr int INV_LDS_N = 128; // node blocks up to this size are inverted in LDS
 constexpr int INV_LDS_BYTES = 150 * 1024;
@@ -531,8 +530,9 @@ __device__ __forceinline__ double dot_by4(const double (&a)[CPT], const double (
 // The node's rank is the larger of the two sides' tolerance ranks, so a side
 // needs steps up to the other side's rank: each side publishes its rank in
 // pub (tagged with the level) as soon as it is known and stops once it has
-// taken as many steps as both ranks, or SK_EXTRA steps past its own when the
-// other side's rank is not in yet (the other side may not be running).
+// taken as many steps as both ranks.  While the other side's rank is not in
+// (that side may not be running yet) it goes on, up to kmax steps, so the
+// node's rank never depends on the order in which the two sides run.
 // The pivot keys and the pivot vector alternate between two LDS slots, so a
 // step needs two barriers: a slot is written again two steps later, after
 // every thread has passed the first barrier of the step in between.
@@ -584,7 +584,7 @@ __device__ __forceinline__ void node_id_body(const GNode& g, const double* __res
       if (tid == 0) __hip_atomic_store(mine, (tag << 8) | rank, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     const int other = L.other[b];
-    if (rank >= 0 && (step >= rank + SK_EXTRA || (other >= 0 && step >= max(rank, other)))) break;
+    if (rank >= 0 && other >= 0 && step >= max(rank, other)) break;
     if (p < 0 || !(v >= 2.2250738585072014e-308)) break;
     if (i == p) {
       const double inv = 1.0 / sqrt(nrm);
@@ -640,7 +640,9 @@ __global__ __launch_bounds__(ID_NT) void node_id_kernel(const GNode* __restrict_
 // node order, its U / V, D^, workspace and generator offsets; the skeleton
 // positions in the parent's candidate list (ppos); the parent level's
 // candidate counts m and offsets.  cnt[0] (generator entries used) advances
-// by the level's total.  fail[1]: a rank reached the sketch size; fail[2]:
+// by the level's total.  fail[1]: a rank reached the sketch size, or a side
+// stopped before the larger tolerance rank (cannot happen: each side runs
+// until it has seen both ranks, or to the end of its candidates); fail[2]:
 // an offset passed its buffer bound.
 __device__ __forceinline__ long long wave_incl_scan(long long v, int lane) {
 #pragma unroll
@@ -665,7 +667,7 @@ __global__ __launch_bounds__(64) void level_plan_kernel(GNode* __restrict__ gl, 
       m = gl[j].m;
       const int kr = info[4 * j], sr = info[4 * j + 1], kc = info[4 * j + 2], sc = info[4 * j + 3];
       k = min(max(kr, kc), min(sr, sc));
-      if (max(kr, kc) >= SK_KCAP) fail[1] = 1;
+      if (max(kr, kc) >= SK_KCAP || k < max(kr, kc)) fail[1] = 1;
     }
     const long long q[5] = {m * k, k * k, 3 * m * m + 2 * m * k + 2 * k * k, (k + m) * m + m * k, k};
     long long ex[5], tot[5];
@@ -1866,8 +1868,11 @@ void hbs_gpu_finish(HbsDev& w) {
       d.e_entries += (int64_t)g.m * g.k;
       w.entries += 2 * (int64_t)g.m * g.k + (int64_t)g.m * g.m;
       w.max_rank = std::max(w.max_rank, g.k);
+      // flops credited to the bordered kernel: only the nodes it factors
+      // (larger ones go to the block-inverse kernels)
       const double nm = g.m, kk2 = g.k;
-      fl += 2.0 * nm * nm * nm + 2.0 * (3.0 * nm * nm * kk2 + 3.0 * nm * kk2 * kk2) + 2.0 * kk2 * kk2 * kk2;
+      if (g.m + g.k <= BT)
+        fl += 2.0 * nm * nm * nm + 2.0 * (3.0 * nm * nm * kk2 + 3.0 * nm * kk2 * kk2) + 2.0 * kk2 * kk2 * kk2;
     }
     const size_t fe = w.fin.fac_entry[l];
     if (fe != SIZE_MAX && fe < ctx->pending.size()) ctx->pending[fe].flops = fl;

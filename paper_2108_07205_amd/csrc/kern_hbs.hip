@@ -12,6 +12,7 @@
 // the four partial sums are added through LDS.  Up to 8 right-hand sides
 // share one pass over the generators.
 #include "kernels.h"
+#include "hbs_dev.h"
 
 namespace {
 
@@ -319,7 +320,7 @@ void up_impl(const HbsLevelDev& L, const T* gen, const double* in, int64_t ld_in
              int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s) {
   if (!L.nnodes || nrhs <= 0) return;
   // generators streamed once per pass of up to 8 right-hand sides
-  const double passes = nrhs == 1 ? 1.0 : (nrhs < kMfmaMin ? (nrhs + 7) / 8 : (nrhs + kMR - 1) / kMR);
+  const double passes = hbs_gen_passes(nrhs);
   KernelTimer kt("hbs_up_kernel", 2.0 * L.up_entries * nrhs, sizeof(T) * (double)L.up_entries * passes, s);
   if (nrhs == 1) {
     up_launch<T, 1>(L, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs, s);
@@ -348,7 +349,7 @@ template <typename T>
 void down_impl(const HbsLevelDev& L, const T* gen, const double* xhat, int64_t ld_xh, const double* gb,
                int64_t ld_gb, double* out, int64_t ld_out, int nrhs, hipStream_t s) {
   if (!L.nnodes || nrhs <= 0) return;
-  const double passes = nrhs == 1 ? 1.0 : (nrhs < kMfmaMin ? (nrhs + 7) / 8 : (nrhs + kMR - 1) / kMR);
+  const double passes = hbs_gen_passes(nrhs);
   KernelTimer kt("hbs_down_kernel", 2.0 * L.e_entries * nrhs, sizeof(T) * (double)L.e_entries * passes, s);
   if (nrhs == 1) {
     down_launch<T, 1>(L, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs, s);
@@ -364,6 +365,11 @@ void down_impl(const HbsLevelDev& L, const T* gen, const double* xhat, int64_t l
 }
 
 }  // namespace
+
+double hbs_gen_passes(int nrhs) {
+  if (nrhs <= 1) return 1.0;
+  return nrhs < kMfmaMin ? (double)((nrhs + 7) / 8) : (double)((nrhs + kMR - 1) / kMR);
+}
 
 void launch_hbs_up(const HbsLevelDev& L, const double* gen, const double* in, int64_t ld_in, double* bhat,
                    int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s) {

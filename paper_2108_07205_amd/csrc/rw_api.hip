@@ -445,6 +445,7 @@ struct rw_refined {
   rw_wall* wall = nullptr;
   rw_ctx* ctx = nullptr;
   std::vector<int32_t> level_of_panel;
+  double q_tol = 1e-10;                // row-ID tolerance of Q (rw_refine's q_tol or the wall's id_tol)
   Discretization disc;                 // refined panels I_n (node records of added panels in pnodes)
   std::vector<NodeRec> pnodes;         // added nodes I_p, in panel order
   int64_t No = 0, Nk = 0, Nc = 0, Np = 0, Nn = 0, Next = 0;
@@ -486,7 +487,11 @@ void refined_settle(rw_refined* f, bool quiet = false) {
       HIP_CHECK(hipEventSynchronize(f->done.e));
       const int info = *f->ctx->defer_pin;
       if (info) RW_THROW(RW_ESINGULAR, "singular Woodbury operator W (pivot " + std::to_string(info) + ")");
-      if (f->app_hbs_on) hbs_gpu_finish(f->app_hbs);
+      if (f->app_hbs_on) {
+        hbs_gpu_finish(f->app_hbs);
+        f->info.app_entries = f->app_hbs.entries;
+        f->info.app_max_rank = f->app_hbs.max_rank;
+      }
     } catch (const RwError& e) {
       f->fail_rc = e.code;
       f->fail_msg = e.what();
@@ -527,14 +532,14 @@ void woodbury_ref_apply(rw_refined* f, int nrhs) {
   rw_wall* w = f->wall;
   const int64_t M = 2 * f->Next;
   const double gb = (w->precision == RW_F32 ? 4.0 : 8.0) * w->stats.gen_entries;
-  PhaseTimer t(f->ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * nrhs, gb * ((nrhs + 7) / 8));
+  PhaseTimer t(f->ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * nrhs, gb * hbs_gen_passes(nrhs));
   hbs_apply(w, f->gext.p, M, f->y.p, M, nrhs, w->precision == RW_F32);
 }
 
 // The A_pp^{-1} block of y on stream s.
 void woodbury_app_apply(rw_refined* f, int nrhs, hipStream_t s) {
   const int64_t M = 2 * f->Next, Mo = 2 * f->No;
-  PhaseTimer t(f->ctx, "a6_app_solve", 2.0 * f->app_hbs.entries * nrhs, 8.0 * f->app_hbs.entries * ((nrhs + 7) / 8),
+  PhaseTimer t(f->ctx, "a6_app_solve", 2.0 * f->app_hbs.entries * nrhs, 8.0 * f->app_hbs.entries * hbs_gen_passes(nrhs),
                s);
   hbs_dev_apply(f->app_hbs, f->gext.p + Mo, M, f->y.p + Mo, M, nrhs, false, s);
 }
@@ -613,6 +618,8 @@ void build_app_inverse(rw_wall* w, rw_refined& f, uint64_t seed, rw_ctx* ax) {
     PhaseTimer t(ax, "a3_app_assemble", 0.0, 8.0 * (double)Mp * Mp);
     launch_assemble(f.d_p.p, f.Np, f.d_p.p, f.Np, true, f.App.p, Mp, s);
   }
+  // test hook: a zero first column, which the LU's pivot check must report
+  if (w->ctx->opt.test_singular == 2) HIP_CHECK(hipMemsetAsync(f.App.p, 0, sizeof(double) * Mp, s));
   {
     PhaseTimer t(ax, "a3_app_lu", 2.0 / 3.0 * (double)Mp * Mp * Mp, 0.0);
     launch_lu_nopiv(f.App.p, Mp, Mp, dinfo.p, nullptr, s);
@@ -733,7 +740,7 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
   if (f.Nc > 0) {
     // ---- a2: Q ~= L R by randomized row IDs of the k-rows [-A_kc A_kp] and p-rows A_pk
     int ncols = ctx->opt.sketch_cols;
-    const double tol = w->tol;
+    const double tol = f.q_tol;
     DBuf<char> dres(ctx, 256);   // ranks and certificates of the two row IDs
     DBuf<double> Yk, Yp, Ck, Cp, part, Ynear;
     DBuf<double2> fpart, fcoef;
@@ -877,7 +884,7 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
     f.X.alloc(ctx, (size_t)M * f.k);
     HIP_CHECK(hipMemsetAsync(f.X.p, 0, sizeof(double) * M * f.k, s));
     if (f.k_k) {
-      PhaseTimer t_x(ctx, "a4_X", 2.0 * w->stats.gen_entries * f.k_k, 8.0 * w->stats.gen_entries * ((f.k_k + 7) / 8));
+      PhaseTimer t_x(ctx, "a4_X", 2.0 * w->stats.gen_entries * f.k_k, 8.0 * w->stats.gen_entries * hbs_gen_passes(f.k_k));
       hbs_apply(w, f.L.p, M, f.X.p, M, f.k_k, false);
     }
   }
@@ -902,7 +909,7 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
     if (f.k_p) {
       double* xp = f.X.p + Mo + (size_t)f.k_k * M;
       if (f.app_hbs_on) {
-        PhaseTimer t_x(ctx, "a4_Xp", 2.0 * f.app_hbs.entries * f.k_p, 8.0 * f.app_hbs.entries * ((f.k_p + 7) / 8),
+        PhaseTimer t_x(ctx, "a4_Xp", 2.0 * f.app_hbs.entries * f.k_p, 8.0 * f.app_hbs.entries * hbs_gen_passes(f.k_p),
                        st);
         hbs_dev_apply(f.app_hbs, f.L.p + Mo + (size_t)f.k_k * M, M, xp, M, f.k_p, false, st);
       } else {
@@ -916,6 +923,8 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
     PhaseTimer t_w(ctx, "a5_W", 2.0 * f.k * (double)f.k * M + 2.0 * (double)f.k * f.k * f.k, 16.0 * f.k * (double)M,
                    st);
     launch_gemm_tn(f.R.p, M, f.X.p, M, M, f.k, f.k, f.W.p, f.k, true, f.wpart.p, st);
+    // test hook: a zero first column, which the inversion's pivot check must report
+    if (ctx->opt.test_singular == 1) HIP_CHECK(hipMemsetAsync(f.W.p, 0, sizeof(double) * f.k, st));
     launch_small_inverse(f.W.p, f.k, f.dinfo.p + 1, st);
     HIP_CHECK(hipMemcpyAsync(ctx->defer_pin, f.dinfo.p + 1, sizeof(int), hipMemcpyDeviceToHost, st));
   } else {
@@ -986,6 +995,7 @@ int rw_ctx_create(rw_ctx** out, int device, void* hip_stream, size_t hbm_budget_
   c->opt.seed = 0x5eedull;
   c->opt.app_dense_max_nodes = 1024;
   c->opt.far_field = 1;
+  c->opt.test_singular = 0;
   int rc = guarded(c.get(), [&]() {
     hipDeviceProp_t prop;
     HIP_CHECK(hipGetDeviceProperties(&prop, device));
@@ -1024,6 +1034,7 @@ int rw_set_options(rw_ctx* ctx, const rw_options* opt) {
   return guarded(ctx, [&]() {
     if (!(opt->ir_tol >= 0) || opt->ir_maxit < 0 || opt->app_dense_max_nodes < 0)
       RW_THROW(RW_EINVAL, "bad refinement options");
+    if (opt->test_singular < 0 || opt->test_singular > 2) RW_THROW(RW_EINVAL, "test_singular outside 0..2");
     if (opt->sketch_cols != 32 && opt->sketch_cols != 64 && opt->sketch_cols != 96 && opt->sketch_cols != 128)
       RW_THROW(RW_EINVAL, "sketch_cols must be 32, 64, 96 or 128");
     ctx->opt = *opt;
@@ -1100,6 +1111,7 @@ int rw_wall_build(rw_ctx* ctx, const rw_curve* curve, int32_t n_panels, int32_t 
     if (order < 2 || order > 32) RW_THROW(RW_EINVAL, "order outside [2, 32]");
     if (n_panels < 2 || leaf_nodes < order || leaf_nodes % order) RW_THROW(RW_EINVAL, "bad panel / leaf sizes");
     if (!(id_tol > 0 && id_tol < 1)) RW_THROW(RW_EINVAL, "id_tol outside (0, 1)");
+    if (precision == RW_BF16) RW_THROW(RW_EINVAL, "RW_BF16 generators are reserved (not built)");
     if (precision != RW_F64 && precision != RW_F32) RW_THROW(RW_EINVAL, "unknown precision");
     if (!(std::fabs(curve->a) < 1.0) || curve->m < 0) RW_THROW(RW_EINVAL, "curve must have |a| < 1, m >= 0");
     std::unique_ptr<rw_wall> w(new rw_wall());
@@ -1135,15 +1147,18 @@ int rw_hbs_apply(rw_wall* w, const double* b, int32_t nrhs, double* x) {
   });
 }
 
-int rw_refine(rw_wall* w, const int32_t* ids, const int32_t* levels, int32_t n_sel, rw_refined** out) {
+int rw_refine(rw_wall* w, const int32_t* ids, const int32_t* levels, int32_t n_sel, double q_tol,
+              rw_refined** out) {
   if (!w) return RW_EINVAL;
   return guarded(w->ctx, [&]() {
     if (!out) RW_THROW(RW_EINVAL, "out is null");
     *out = nullptr;
     validate_selection(w, ids, levels, n_sel);
+    if (!(q_tol < 1.0) || std::isnan(q_tol)) RW_THROW(RW_EINVAL, "q_tol must be below 1 (<= 0: the wall's id_tol)");
     std::vector<int32_t> lop(w->P, -1);
     for (int i = 0; i < n_sel; ++i) lop[ids[i]] = levels[i];
     std::unique_ptr<rw_refined> f(new rw_refined());
+    f->q_tol = q_tol > 0 ? q_tol : w->tol;
     build_refined(w, lop, *f);
     *out = f.release();
   });
@@ -1162,6 +1177,7 @@ int rw_coarsen(rw_refined* f, const int32_t* ids, int32_t n_sel) {
       lop[ids[i]] = -1;
     }
     std::unique_ptr<rw_refined> g(new rw_refined());
+    g->q_tol = f->q_tol;
     build_refined(f->wall, lop, *g);
     std::swap(*f, *g);
     if (f->ctx->unsettled == g.get()) f->ctx->unsettled = f;
@@ -1195,8 +1211,9 @@ int rw_nodes(const rw_refined* f, double* xy, double* nrm, double* wts, int64_t*
   });
 }
 
-int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau) {
+int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau, rw_solve_info* sinfo) {
   if (!f) return RW_EINVAL;
+  if (sinfo) *sinfo = rw_solve_info{};
   int rc = guarded(f->ctx, [&]() {
     if (nrhs <= 0 || !g || !tau) RW_THROW(RW_EINVAL, "bad arguments");
     if (f->fail_rc != RW_OK) RW_THROW(f->fail_rc, f->fail_msg);
@@ -1207,7 +1224,9 @@ int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau) {
     const rw_options& o = f->ctx->opt;
     int it = 0;
     double worst = 0;
-    double* hn = (double*)ctx_readback(f->ctx, sizeof(double) * 2 * nrhs);
+    // read-back area: the latest norms, then those of the direct solution
+    double* hn = (double*)ctx_readback(f->ctx, sizeof(double) * 4 * nrhs);
+    double* hn0 = hn + 2 * nrhs;
     auto residual = [&]() {
       PhaseTimer t(f->ctx, "a8_residual", 26.0 * (double)f->Nn * f->Nn * nrhs, 0.0);
       launch_residual(f->d_new.p, f->Nn, g, tau, f->r.p, nrhs, f->part.p, f->norms.p, s);
@@ -1218,6 +1237,8 @@ int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau) {
       residual();
     };
     residual();
+    // norms of the direct solution, copied out before a correction overwrites them
+    HIP_CHECK(hipMemcpyAsync(hn0, f->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
     // the Woodbury solution takes at least one correction when refinement is
     // on: it is enqueued with its residual before anything is read back
     if (o.ir_maxit > 0) correct();
@@ -1238,6 +1259,18 @@ int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau) {
     f->info.ir_iters = it;
     f->info.resid = worst;
     f->info.t_solve_ms = wall_ms() - t0;
+    if (sinfo) {
+      double w0 = 0;
+      for (int c = 0; c < nrhs; ++c) {
+        const double rel = hn0[nrhs + c] > 0 ? std::sqrt(hn0[c] / hn0[nrhs + c]) : std::sqrt(hn0[c]);
+        w0 = std::max(w0, std::isfinite(rel) ? rel : INFINITY);
+      }
+      sinfo->ir_iters = it;
+      sinfo->k = f->k;
+      sinfo->resid = worst;
+      sinfo->resid_direct = w0;
+      sinfo->t_solve_ms = f->info.t_solve_ms;
+    }
     if (!(worst <= o.ir_tol) && o.ir_maxit > 0)
       RW_THROW(RW_ENOCONV, "refinement stopped at relative residual " + std::to_string(worst));
   });
@@ -1269,7 +1302,7 @@ void batch_woodbury(rw_wall* w, const std::vector<rw_refined*>& fs, const std::v
   }
   {
     const double gb = (w->precision == RW_F32 ? 4.0 : 8.0) * w->stats.gen_entries;
-    PhaseTimer t(w->ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * C, gb * ((C + 7) / 8));
+    PhaseTimer t(w->ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * C, gb * hbs_gen_passes((int)C));
     hbs_apply(w, w->bat_in.p, Mo, w->bat_out.p, Mo, (int)C, w->precision == RW_F32);
   }
   c0 = 0;

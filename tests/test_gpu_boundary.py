@@ -1,0 +1,159 @@
+"""C-ABI boundary behaviour on the GPU: error paths forced from the host
+(RW_ENOCONV, RW_ESINGULAR through the library's own pivot checks), the
+row-ID tolerance q_tol of rw_refine, the rw_solve_info out-parameter, the
+reserved RW_BF16 precision, and run-to-run determinism of the GPU-built
+A_pp HBS inverse (Algorithm 1, pre-computation step 2)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import geometry as G, kernels as K, solve as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2108_07205_amd as rw  # noqa: E402
+
+
+def _say(msg):
+    print(f"[gpu-boundary] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = rw.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def wall64(ctx):
+    w = rw.Wall(ctx, 64)
+    yield w
+    w.close()
+
+
+def _oracle(p):
+    sets = G.refine(p.n_panels, p.refinement.panel_ids, p.refinement.levels, p.curve.a, p.curve.m)
+    st = p.rhs[0]
+    g = K.rhs_vector(sets.new, st.z, st.f)
+    return g, S.solve_refined(K.nystrom_matrix(sets.new), g)
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def test_enoconv_result_written(ctx, wall64):
+    """ir_maxit = 1 with an unreachable ir_tol: RW_ENOCONV, the info filled
+    and tau written (one correction past the Woodbury solution)."""
+    p = W.config1(seed=0)
+    g, tau_or = _oracle(p)
+    ref = wall64.refine(p.refinement.panel_ids, p.refinement.levels)
+    ctx.set_options(ir_maxit=1, ir_tol=1e-30)
+    try:
+        tau = torch.empty(ref.n_unknowns, dtype=torch.float64, device="cuda")
+        info = {}
+        rc = rw.rw_solve(ctx.h, ref.h, _dev(g), tau, ref.n_unknowns, check=False, info=info)
+    finally:
+        ctx.set_options(ir_maxit=6, ir_tol=1e-13)
+    _say(f"enoconv: rc={rc} info={info}")
+    assert rc == rw.RW_ENOCONV
+    assert info["ir_iters"] == 1 and info["k"] == ref.info()["k"]
+    assert 0 < info["resid"] < info["resid_direct"]
+    err = np.linalg.norm(tau.cpu().numpy() - tau_or) / np.linalg.norm(tau_or)
+    assert err < 1e-10
+    ref.close()
+
+
+def test_esingular_from_w(ctx, wall64):
+    """A zeroed first column of W = I + R X (test hook): the Gauss-Jordan's
+    pivot check flags it and the handle's solve returns RW_ESINGULAR."""
+    p = W.config1(seed=1)
+    g, _ = _oracle(p)
+    ctx.set_options(test_singular=1)
+    try:
+        ref = wall64.refine(p.refinement.panel_ids, p.refinement.levels)
+    finally:
+        ctx.set_options(test_singular=0)
+    tau = torch.empty(ref.n_unknowns, dtype=torch.float64, device="cuda")
+    rc = rw.rw_solve(ctx.h, ref.h, _dev(g), tau, ref.n_unknowns, check=False)
+    _say(f"esingular W: rc={rc}")
+    assert rc == rw.RW_ESINGULAR
+    assert rw.rw_solve(ctx.h, ref.h, _dev(g), tau, ref.n_unknowns, check=False) == rw.RW_ESINGULAR
+    ref.close()
+    # the context is still usable
+    ref = wall64.refine(p.refinement.panel_ids, p.refinement.levels)
+    ref.solve(_dev(g))
+    ref.close()
+
+
+def test_esingular_from_dense_app(ctx, wall64):
+    """A zeroed first column of the dense A_pp (test hook): its LU's pivot
+    check fails rw_refine with RW_ESINGULAR and leaves no handle."""
+    p = W.config1(seed=2)
+    ctx.set_options(test_singular=2)
+    try:
+        with pytest.raises(rw.RwError) as ei:
+            wall64.refine(p.refinement.panel_ids, p.refinement.levels)
+    finally:
+        ctx.set_options(test_singular=0)
+    _say(f"esingular A_pp: {ei.value}")
+    assert ei.value.code == rw.RW_ESINGULAR
+    ref = wall64.refine(p.refinement.panel_ids, p.refinement.levels)
+    ref.close()
+
+
+def test_q_tol_controls_rank(ctx, wall64):
+    """A looser q_tol gives a smaller Woodbury rank k; refinement still
+    reaches the FP64 bar against the oracle.  q_tol >= 1 is rejected."""
+    p = W.config1(seed=0)
+    g, tau_or = _oracle(p)
+    r1 = wall64.refine(p.refinement.panel_ids, p.refinement.levels)
+    r2 = wall64.refine(p.refinement.panel_ids, p.refinement.levels, q_tol=1e-6)
+    k1, k2 = r1.info()["k"], r2.info()["k"]
+    info = {}
+    tau = r2.solve(_dev(g), info=info).cpu().numpy()
+    err = np.linalg.norm(tau - tau_or) / np.linalg.norm(tau_or)
+    _say(f"q_tol: k(1e-10)={k1} k(1e-6)={k2} ir={info['ir_iters']} err={err:.2e}")
+    assert 0 < k2 < k1
+    assert err < 1e-10
+    r1.close()
+    r2.close()
+    with pytest.raises(rw.RwError) as ei:
+        wall64.refine(p.refinement.panel_ids, p.refinement.levels, q_tol=1.5)
+    assert ei.value.code == rw.RW_EINVAL
+
+
+def test_bf16_reserved(ctx):
+    with pytest.raises(rw.RwError) as ei:
+        rw.Wall(ctx, 64, precision=rw.RW_BF16)
+    assert ei.value.code == rw.RW_EINVAL
+
+
+@pytest.mark.parametrize("n_panels,maker", [(64, "config1"), (1024, "config2")])
+def test_app_hbs_build_is_deterministic(ctx, n_panels, maker):
+    """The GPU-built A_pp HBS inverse of one refinement has the same node
+    ranks and generator count on every build (both sides of each node ID run
+    until both tolerance ranks are known)."""
+    wall = rw.Wall(ctx, n_panels)
+    p = getattr(W, maker)(seed=3)
+    g = None
+    ctx.set_options(app_dense_max_nodes=0)
+    try:
+        seen = []
+        for rep in range(3):
+            ref = wall.refine(p.refinement.panel_ids, p.refinement.levels)
+            if g is None:
+                g = ref.stokeslet_rhs(p.rhs[0].z, p.rhs[0].f)
+            ref.solve(g)
+            inf = ref.info()
+            seen.append((inf["app_entries"], inf["app_max_rank"], inf["k"]))
+            ref.close()
+    finally:
+        ctx.set_options(app_dense_max_nodes=1024)
+    _say(f"app HBS {maker}: (entries, max rank, k) = {seen}")
+    assert seen[0][0] > 0
+    assert seen[0] == seen[1] == seen[2]
+    wall.close()
