@@ -15,8 +15,14 @@ one right-hand side):
           residual (Algorithm 1 solve steps).
 Step s uses seed s for the refinement point and the Stokeslets.  The static
 reference inverse (the paper's T_static) is built once before timing.  A step
-counts toward the rate only if its solve meets the residual certificate
-(||g - A tau|| / ||g|| <= 1e-13 with kappa ~ 4e2, i.e. error <~ 1e-10).
+counts toward the rate only if (1) its solve met the library's own FP64
+residual (||g - A tau|| / ||g|| <= 1e-13) and (2) after the timed region, the
+FP64 oracle's residual of its tau, formed by the oracle on its own
+discretization at 264 sampled rows (200 seeded + every 64th added node), is
+at most 1.6e-11 relative: with kappa_est = 6e2 (twice the condition number
+measured on this curve) that bounds the error against the oracle's solution
+by 1e-8, the metric's gate.  Seeds whose full oracle solution is stored
+(tests/golden) are also compared element by element.
 
 Prints ONE JSON line.  --gpus > 1 is refused: the refined-wall path runs on one GPU.
 """
@@ -82,43 +88,116 @@ def measured_traffic(kernel: str):
     return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
 
 
-def cpu_baseline(budget_s: float = 20.0) -> dict:
-    """The FP64 oracle (dense assembly + LU, as it stands) on the host cores,
-    on a bounded sample of one config-2 refined-wall solve, extrapolated to
-    solves/s: assembly of a row slab scaled by rows, LU solve of a smaller
-    dense system of the same operator family scaled by n^3."""
+KAPPA_EST = 6e2          # twice the condition number measured on this curve
+ORACLE_RESID_GATE = 1e-8 / KAPPA_EST
+
+
+def _oracle_check(job):
+    """Worker (separate process, oracle only): relative oracle residual of one
+    seed's tau at sampled rows, and the element-wise difference from the
+    stored full oracle solution when there is one."""
+    seed, tau = job
+    import workloads as W
+    from oracle import geometry as G, kernels as K
+    p = W.config2(seed=seed)
+    sets = G.refine(p.n_panels, p.refinement.panel_ids, p.refinement.levels, p.curve.a, p.curve.m)
+    st = p.rhs[0]
+    g = K.rhs_vector(sets.new, st.z, st.f)
+    rng = np.random.default_rng(1000 + seed)
+    rows = np.unique(np.concatenate([rng.choice(sets.new.n, 200, replace=False), sets.p_in_new[::64]]))
+    r = K.residual_rows(sets.new, rows, tau, g)
+    gs = g.reshape(-1, 2)[rows].reshape(-1)
+    out = {"seed": seed, "resid": float(np.linalg.norm(r) / np.linalg.norm(gs)), "rows": int(rows.size)}
+    gold = os.path.join(ROOT, "tests", "golden", f"config2_seed{seed}_tau.npy")
+    if os.path.exists(gold):
+        t_or = np.load(gold, allow_pickle=False)
+        out["golden_rel2"] = float(np.linalg.norm(tau - t_or) / np.linalg.norm(t_or))
+    return out
+
+
+def oracle_gate(taus: dict) -> dict:
+    """Check every timed seed's tau with the FP64 oracle on the host cores
+    (a pool of spawned processes that import only oracle/ and workloads/)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    jobs = sorted(taus.items())
+    nw = max(1, min(16, (os.cpu_count() or 2) // 2, len(jobs)))
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=nw, mp_context=mp.get_context("spawn")) as ex:
+        res = list(ex.map(_oracle_check, jobs, chunksize=max(1, len(jobs) // (4 * nw))))
+    ok = {r["seed"]: r["resid"] <= ORACLE_RESID_GATE and r.get("golden_rel2", 0.0) <= 1e-10 for r in res}
+    gold = {str(r["seed"]): r["golden_rel2"] for r in res if "golden_rel2" in r}
+    return {"ok": ok, "max_resid": max(r["resid"] for r in res), "rows_per_seed": res[0]["rows"],
+            "golden_rel2": gold, "workers": nw, "seconds": round(time.perf_counter() - t0, 1)}
+
+
+def _blas_threads() -> int:
+    from threadpoolctl import threadpool_info
+    return max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+
+
+def cpu_baseline() -> dict:
+    """The FP64 oracle (dense assembly + LU with one refinement step, as it
+    stands) timed on the host cores on a bounded sample of one refined-wall
+    solve of the headline workload (20224 nodes, 40448 unknowns):
+    * assembly: 1024 of the 20224 node rows, scaled by rows (every row costs
+      the same);
+    * LU solve: the oracle's dense solve of the same operator at 6144 and
+      10240 unknowns, fitted by t = c n^3 and extrapolated to 40448;
+    both with the BLAS thread pool at all host threads and the LU again at
+    1 thread (threads read inside this process through threadpoolctl)."""
     import workloads as W
     from oracle import geometry as G, kernels as K, solve as S
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+    from threadpoolctl import threadpool_limits
     p = W.config2(seed=0)
     sets = G.refine(p.n_panels, p.refinement.panel_ids, p.refinement.levels, p.curve.a, p.curve.m)
     n_nodes = sets.new.n
+    n_full = 2 * n_nodes
     rows = 1024
     t0 = time.perf_counter()
     K.nystrom_rows(sets.new, np.arange(rows))
     t_slab = time.perf_counter() - t0
     t_asm = t_slab * n_nodes / rows
-    # LU sample: the oracle's dense solve on a 256-panel wall (8192 unknowns)
-    d = G.discretize(G.reference_panels(256), p.curve.a, p.curve.m)
-    A = K.nystrom_matrix(d)
-    g = np.ones(A.shape[0])
-    t0 = time.perf_counter()
-    S.solve_refined(A, g)
-    t_lu_s = time.perf_counter() - t0
-    n_full = 2 * n_nodes
-    t_lu = t_lu_s * (n_full / A.shape[0]) ** 3
+
+    def lu_time(n_panels: int, threads=None) -> tuple:
+        d = G.discretize(G.reference_panels(n_panels), p.curve.a, p.curve.m)
+        A = K.nystrom_matrix(d)
+        g = np.ones(A.shape[0])
+        if threads is None:
+            t0 = time.perf_counter()
+            S.solve_refined(A, g)
+            return A.shape[0], time.perf_counter() - t0, _blas_threads()
+        with threadpool_limits(threads, user_api="blas"):
+            used = _blas_threads()
+            t0 = time.perf_counter()
+            S.solve_refined(A, g)
+            return A.shape[0], time.perf_counter() - t0, used
+
+    n1, t1, th_all = lu_time(192)
+    n2, t2, _ = lu_time(320)
+    # least-squares c in t = c n^3 over the two sizes
+    c = (t1 * n1 ** 3 + t2 * n2 ** 3) / (n1 ** 6 + n2 ** 6)
+    t_lu = c * n_full ** 3
+    n1s, t1s, th_one = lu_time(192, threads=1)
+    t_lu1 = t1s * (n_full / n1s) ** 3
     total = t_asm + t_lu
+    meta_path = os.path.join(ROOT, "tests", "golden", "golden_meta.json")
+    measured = None
+    if os.path.exists(meta_path):
+        m = json.load(open(meta_path)).get("config2_seed0")
+        if m:
+            measured = {"assembly_s": m["assembly_s"], "lu_s": m["lu_s"], "blas_threads": m["blas_threads"],
+                        "host_cpus": m["host_cpus"], "what": "full-size oracle run that wrote the golden solution"}
     return {
-        "value": 1.0 / total, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-        "sample": (f"dense Nystrom assembly of {rows} of {n_nodes} refined node rows ({t_slab:.2f} s, scaled "
-                   f"by rows) + numpy.linalg.solve of an {A.shape[0]}x{A.shape[0]} system of the same "
-                   f"operator ({t_lu_s:.2f} s, scaled by (n/{A.shape[0]})^3 to n={n_full}); "
-                   f"extrapolated full solve {total:.1f} s"),
-        "host_cpus": os.cpu_count(),
+        "value": 1.0 / total, "unit": "solves/s", "cores": int(th_all), "kind": "oracle",
+        "sample": (f"assembly of {rows} of {n_nodes} node rows ({t_slab:.2f} s, scaled by rows to {t_asm:.1f} s); "
+                   f"oracle LU solve at n={n1} ({t1:.2f} s) and n={n2} ({t2:.2f} s), t = c n^3 fitted and "
+                   f"extrapolated to n={n_full} ({t_lu:.1f} s); full solve {total:.1f} s"),
+        "assembly_s": t_asm, "lu_s": t_lu, "lu_fit_sizes": [n1, n2], "lu_fit_s": [t1, t2],
+        "one_thread": {"lu_s": t_lu1, "solves_per_s": 1.0 / (t_asm + t_lu1), "threads": int(th_one),
+                       "sample": f"LU at n={n1s} on 1 BLAS thread ({t1s:.2f} s) scaled by n^3; the assembly "
+                                 f"(NumPy element-wise work) runs on one thread in both cases"},
+        "host_cpus": os.cpu_count(), "full_size_reference_run": measured,
     }
 
 
@@ -163,6 +242,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without the phase events")
+    ap.add_argument("--hbs-apply-only", action="store_true",
+                    help="only the one-RHS reference-inverse apply, warm and cold (for kernel traces)")
     ap.add_argument("--extra-steps", type=int, default=40,
                     help="steps of the side measurements (RHS/s with resident factors, FP32-generator mode)")
     args = ap.parse_args()
@@ -180,19 +261,75 @@ def main():
     st = wall.stats()
     stream = torch.cuda.current_stream()
 
+    def hbs_apply_rates(w, reps: int = 40):
+        """One-RHS apply of the reference inverse A_oo^{-1} (the a6 kernel
+        sweep) timed by HIP events on the ctx stream: warm (generators left
+        in the 256 MB Infinity Cache by the previous rep) and cold (a 1 GiB
+        scratch buffer written before each rep), against 8 TB/s and against
+        a measured device copy (1 GiB, read + write)."""
+        n = 2 * w.n_nodes
+        stw = w.stats()
+        alg = float(stw["gen_bytes_f64"] + 8 * 2 * n)   # generators + read b + write x
+        b = torch.randn(n, dtype=torch.float64, device="cuda")
+        x = torch.empty_like(b)
+        scratch = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+
+        def one(cold: bool) -> float:
+            if cold:
+                scratch.fill_(float(np.random.rand()))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rw.rw_hbs_apply(ctx.h, w.h, b, x, n)
+            e1.record()
+            e1.synchronize()
+            return e0.elapsed_time(e1) * 1e3
+
+        for _ in range(5):
+            one(False)
+        warm = float(np.median([one(False) for _ in range(reps)]))
+        cold = float(np.median([one(True) for _ in range(reps)]))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        scratch.copy_(src)
+        e0.record()
+        for _ in range(5):
+            scratch.copy_(src)
+        e1.record()
+        e1.synchronize()
+        copy_gbps = 5 * 2 * scratch.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del scratch, src
+        out = {"algorithmic_bytes": alg, "warm_us": warm, "cold_us": cold, "copy_peak_GBps": copy_gbps}
+        for k in ("warm", "cold"):
+            gbps = alg / (out[f"{k}_us"] * 1e-6) / 1e9
+            out[f"{k}_GBps"] = gbps
+            out[f"{k}_frac_of_8TBps"] = gbps / PEAK["hbm"][0]
+            out[f"{k}_frac_of_copy"] = gbps / copy_gbps
+        return out
+
+    if args.hbs_apply_only:
+        print(json.dumps({"hbs_apply_1rhs": hbs_apply_rates(wall), "levels": st["n_levels"],
+                          "gen_bytes_f64": st["gen_bytes_f64"]}), flush=True)
+        wall.close()
+        ctx.close()
+        return
+
     # the synthetic inputs (refined panel lists and Stokeslet sources) are
     # generated before the timed region, like data already at hand
     problems = {s: W.config2(seed=s) for s in range(args.steps)}
     problems.update({10_000 + i: W.config2(seed=10_000 + i) for i in range(args.warmup)})
+
+    taus = {}
 
     def step(seed: int):
         p = problems[seed]
         ref = wall.refine(p.refinement.panel_ids, p.refinement.levels)
         s0 = p.rhs[0]
         g = ref.stokeslet_rhs(s0.z, s0.f)
-        rc = rw.rw_solve(ctx.h, ref.h, g, torch.empty_like(g), ref.n_unknowns, check=False)
+        tau = torch.empty_like(g)
+        rc = rw.rw_solve(ctx.h, ref.h, g, tau, ref.n_unknowns, check=False)
         info = ref.info()
         ref.close()
+        taus[seed] = tau       # kept for the oracle check after the timed region
         return rc == rw.RW_OK, info
 
     # Python's cyclic garbage collector stays off from the warmup through the
@@ -210,14 +347,14 @@ def main():
         if profile:
             ctx.profile(True)
             ctx.profile_reset()
-        lat, ok, infos = [], 0, []
+        lat, ok, infos = [], [], []
         torch.cuda.synchronize()
         t_start = time.perf_counter()
         for s in range(args.steps):
             t0 = time.perf_counter()
             good, info = step(s)
             lat.append((time.perf_counter() - t0) * 1e3)
-            ok += int(good)
+            ok.append(good)
             infos.append(info)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
@@ -227,13 +364,18 @@ def main():
 
     # headline: seeds 0..K-1 without events; then the same seeds with the
     # per-kernel HIP events that give the roofline and the kernel table
-    ok, elapsed, lat, infos, _ = timed(False)
+    ok_lib, elapsed, lat, infos, _ = timed(False)
+    # the oracle's check of every timed seed (host cores, after the timed region)
+    ogate = oracle_gate({s: t.cpu().numpy() for s, t in taus.items()})
+    taus.clear()
+    ok = sum(int(good and ogate["ok"][s]) for s, good in enumerate(ok_lib))
     value = ok / elapsed
     phases = {}
     prof_rate = None
     if not args.no_profile:
         okp, elp, _, _, phases = timed(True)
-        prof_rate = okp / elp
+        taus.clear()
+        prof_rate = sum(okp) / elp
 
     gc.enable()
 
@@ -314,7 +456,7 @@ def main():
                 "batch_rhs_per_s": nrhs / t_bat, "speedup_vs_sequential": t_seq / t_bat,
                 "max_resid": max(i["resid"] for i in infos), "batch_vs_sequential_rel_diff": agree}
 
-    side = {}
+    side = {"hbs_apply_1rhs": hbs_apply_rates(wall)}
     if args.extra_steps > 0:
         side["batched_fp64"] = batched(wall, 16)
         side["fp64_resident_factors"] = rhs_rate(wall, args.extra_steps)
@@ -346,7 +488,15 @@ def main():
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "slowest_steps_ms": {str(int(i)): round(float(lat[i]), 3) for i in np.argsort(lat)[::-1][:5]},
-        "gate": {"passed": ok, "of": args.steps, "criterion": "||g - A tau||/||g|| <= 1e-13 (FP64 residual)",
+        "gate": {"passed": ok, "of": args.steps,
+                 "criterion": (f"library FP64 residual ||g - A tau||/||g|| <= 1e-13, and the FP64 oracle's residual "
+                               f"of tau on its own discretization at {ogate['rows_per_seed']} sampled rows <= "
+                               f"{ORACLE_RESID_GATE:.2e} relative (kappa_est {KAPPA_EST:.0f}: error vs the oracle "
+                               f"<= 1e-8); seeds with a stored full oracle solution: ||tau - tau_oracle||_2 / "
+                               f"||tau_oracle||_2 <= 1e-10"),
+                 "passed_library_residual": int(sum(ok_lib)),
+                 "oracle_max_resid": ogate["max_resid"], "oracle_golden_rel2": ogate["golden_rel2"],
+                 "oracle_check_s": ogate["seconds"], "oracle_workers": ogate["workers"],
                  "max_resid": float(max(i["resid"] for i in infos)),
                  "k_range": [int(min(i["k"] for i in infos)), int(max(i["k"] for i in infos))],
                  "ir_iters_max": int(max(i["ir_iters"] for i in infos))},
