@@ -17,12 +17,14 @@ Step s uses seed s for the refinement point and the Stokeslets.  The static
 reference inverse (the paper's T_static) is built once before timing.  A step
 counts toward the rate only if (1) its solve met the library's own FP64
 residual (||g - A tau|| / ||g|| <= 1e-13) and (2) after the timed region, the
-FP64 oracle's residual of its tau, formed by the oracle on its own
-discretization at 264 sampled rows (200 seeded + every 64th added node), is
-at most 1.6e-11 relative: with kappa_est = 6e2 (twice the condition number
-measured on this curve) that bounds the error against the oracle's solution
-by 1e-8, the metric's gate.  Seeds whose full oracle solution is stored
-(tests/golden) are also compared element by element.
+FP64 oracle's residual r of its tau, formed by the oracle on its own
+discretization at 264 sampled rows (200 seeded + every 64th added node),
+bounds the error against the oracle's solution by at most 1e-8 (the
+metric's gate): ||tau - tau_or|| / ||tau|| <= ||A^{-1}|| ||r|| / ||tau||, with
+||r|| estimated from the sampled rows (||r_s|| / ||g_s|| times ||g||) and
+||A^{-1}|| <= 100 (largest measured on refined walls of this curve: 42).
+Seeds whose full oracle solution is stored (tests/golden) are also compared
+element by element.
 
 Prints ONE JSON line.  --gpus > 1 is refused: the refined-wall path runs on one GPU.
 """
@@ -88,8 +90,11 @@ def measured_traffic(kernel: str):
     return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
 
 
-KAPPA_EST = 6e2          # twice the condition number measured on this curve
-ORACLE_RESID_GATE = 1e-8 / KAPPA_EST
+# ||A^{-1}||_2 of the refined Nystrom matrices of this curve: 27 (unrefined),
+# 31-42 on refined walls (smallest singular value 0.024-0.037); twice the
+# largest, rounded up
+INV_NORM_EST = 100.0
+ERROR_GATE = 1e-8
 
 
 def _oracle_check(job):
@@ -107,7 +112,9 @@ def _oracle_check(job):
     rows = np.unique(np.concatenate([rng.choice(sets.new.n, 200, replace=False), sets.p_in_new[::64]]))
     r = K.residual_rows(sets.new, rows, tau, g)
     gs = g.reshape(-1, 2)[rows].reshape(-1)
-    out = {"seed": seed, "resid": float(np.linalg.norm(r) / np.linalg.norm(gs)), "rows": int(rows.size)}
+    rel = float(np.linalg.norm(r) / np.linalg.norm(gs))
+    bound = INV_NORM_EST * rel * float(np.linalg.norm(g) / np.linalg.norm(tau))
+    out = {"seed": seed, "resid": rel, "bound": bound, "rows": int(rows.size)}
     gold = os.path.join(ROOT, "tests", "golden", f"config2_seed{seed}_tau.npy")
     if os.path.exists(gold):
         t_or = np.load(gold, allow_pickle=False)
@@ -125,9 +132,10 @@ def oracle_gate(taus: dict) -> dict:
     t0 = time.perf_counter()
     with cf.ProcessPoolExecutor(max_workers=nw, mp_context=mp.get_context("spawn")) as ex:
         res = list(ex.map(_oracle_check, jobs, chunksize=max(1, len(jobs) // (4 * nw))))
-    ok = {r["seed"]: r["resid"] <= ORACLE_RESID_GATE and r.get("golden_rel2", 0.0) <= 1e-10 for r in res}
+    ok = {r["seed"]: r["bound"] <= ERROR_GATE and r.get("golden_rel2", 0.0) <= 1e-10 for r in res}
     gold = {str(r["seed"]): r["golden_rel2"] for r in res if "golden_rel2" in r}
-    return {"ok": ok, "max_resid": max(r["resid"] for r in res), "rows_per_seed": res[0]["rows"],
+    return {"ok": ok, "max_resid": max(r["resid"] for r in res), "max_bound": max(r["bound"] for r in res),
+            "rows_per_seed": res[0]["rows"],
             "golden_rel2": gold, "workers": nw, "seconds": round(time.perf_counter() - t0, 1)}
 
 
@@ -489,13 +497,14 @@ def main():
         "p99_ms": float(np.percentile(lat, 99)),
         "slowest_steps_ms": {str(int(i)): round(float(lat[i]), 3) for i in np.argsort(lat)[::-1][:5]},
         "gate": {"passed": ok, "of": args.steps,
-                 "criterion": (f"library FP64 residual ||g - A tau||/||g|| <= 1e-13, and the FP64 oracle's residual "
-                               f"of tau on its own discretization at {ogate['rows_per_seed']} sampled rows <= "
-                               f"{ORACLE_RESID_GATE:.2e} relative (kappa_est {KAPPA_EST:.0f}: error vs the oracle "
-                               f"<= 1e-8); seeds with a stored full oracle solution: ||tau - tau_oracle||_2 / "
+                 "criterion": (f"library FP64 residual ||g - A tau||/||g|| <= 1e-13, and the error bound vs the FP64 "
+                               f"oracle ||A^-1|| ||r|| / ||tau|| <= {ERROR_GATE:g} with r the oracle's residual of tau "
+                               f"on its own discretization ({ogate['rows_per_seed']} sampled rows) and ||A^-1|| <= "
+                               f"{INV_NORM_EST:g}; seeds with a stored full oracle solution: ||tau - tau_oracle||_2 / "
                                f"||tau_oracle||_2 <= 1e-10"),
                  "passed_library_residual": int(sum(ok_lib)),
-                 "oracle_max_resid": ogate["max_resid"], "oracle_golden_rel2": ogate["golden_rel2"],
+                 "oracle_max_resid": ogate["max_resid"], "oracle_max_error_bound": ogate["max_bound"],
+                 "oracle_golden_rel2": ogate["golden_rel2"],
                  "oracle_check_s": ogate["seconds"], "oracle_workers": ogate["workers"],
                  "max_resid": float(max(i["resid"] for i in infos)),
                  "k_range": [int(min(i["k"] for i in infos)), int(max(i["k"] for i in infos))],

@@ -81,6 +81,9 @@ typedef struct {
                                 and sketch the far part of Q through multipole / local expansions,
                                 the near part exactly (used when at most half the kept nodes are
                                 near); 0: sketch the whole blocks of Q exactly [1] */
+  int32_t hbs_merge;         /* binary tree levels merged into one level of the reference HBS tree built
+                                by the next rw_wall_build, 1..4 (1: binary tree; 2: four children per
+                                node): fewer dependent level sweeps per apply [2] */
   int32_t test_singular;     /* test hook, 0 in normal use [0]: 1 = zero the first column of W = I + R X
                                 before its inversion, 2 = zero the first column of a dense A_pp before
                                 its LU; the library's own pivot checks then report RW_ESINGULAR */
@@ -115,7 +118,7 @@ typedef struct {
 /* Reference-wall statistics reported by rw_wall_stats. */
 typedef struct {
   int64_t n_nodes;           /* N_o */
-  int32_t n_levels;          /* tree depth (root = level 0, leaves = level n_levels) */
+  int32_t n_levels;          /* tree levels below the root (root = level 0, leaves = level n_levels) */
   int32_t max_rank;          /* largest skeleton size of any tree node */
   int64_t gen_entries;       /* sum over nodes of |E| + |F| + |G| (the generators one apply reads) */
   int64_t gen_bytes_f64;     /* 8 * gen_entries */

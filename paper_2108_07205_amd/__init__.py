@@ -52,7 +52,7 @@ class rw_options(ctypes.Structure):
     _fields_ = [("ir_tol", ctypes.c_double), ("ir_maxit", ctypes.c_int32),
                 ("sketch_cols", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("app_dense_max_nodes", ctypes.c_int32), ("far_field", ctypes.c_int32),
-                ("test_singular", ctypes.c_int32)]
+                ("hbs_merge", ctypes.c_int32), ("test_singular", ctypes.c_int32)]
 
 
 class rw_info(ctypes.Structure):
@@ -172,7 +172,7 @@ def rw_ctx_destroy(ctx):
 
 
 def rw_set_options(ctx, ir_tol=None, ir_maxit=None, sketch_cols=None, seed=None, app_dense_max_nodes=None,
-                   far_field=None, test_singular=None):
+                   far_field=None, test_singular=None, hbs_merge=None):
     lib = load_library()
     o = rw_options()
     _check(lib.rw_get_options(ctx, ctypes.byref(o)), ctx)
@@ -190,6 +190,8 @@ def rw_set_options(ctx, ir_tol=None, ir_maxit=None, sketch_cols=None, seed=None,
         o.far_field = int(bool(far_field))
     if test_singular is not None:
         o.test_singular = int(test_singular)
+    if hbs_merge is not None:
+        o.hbs_merge = int(hbs_merge)
     _check(lib.rw_set_options(ctx, ctypes.byref(o)), ctx)
 
 

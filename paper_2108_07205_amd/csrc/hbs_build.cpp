@@ -176,71 +176,89 @@ void hbs_build_inverse(const std::vector<NodeRec>& nd, const HbsParams& prm, Hbs
   while ((int64_t(1) << L) < nleaf) ++L;
   if ((int64_t(1) << L) != nleaf || nleaf * prm.leaf_nodes != N || L < 1)
     RW_THROW(RW_EINVAL, "HBS tree needs N / leaf_nodes to be a power of two >= 2");
+  if (prm.merge < 1 || prm.merge > 4) RW_THROW(RW_EINVAL, "HBS merge outside [1, 4]");
+  // tree levels t = 0 (root) .. T (leaves) at binary depths dep[t]: a node
+  // at level t covers N / 2^dep[t] nodes and has 2^(dep[t+1] - dep[t])
+  // children, contiguous in node order
+  std::vector<int> dep;
+  for (int d = L;; d = std::max(0, d - prm.merge)) {
+    dep.push_back(d);
+    if (d == 0) break;
+  }
+  std::reverse(dep.begin(), dep.end());
+  const int T = (int)dep.size() - 1;
   out = HbsInverse();
-  out.L = L;
-  out.lev.resize(L + 1);
-  std::vector<std::vector<CNode>> cn(L + 1);
+  out.L = T;
+  out.lev.resize(T + 1);
+  std::vector<std::vector<CNode>> cn(T + 1);
+  auto nchild = [&](int t) { return t < T ? (1 << (dep[t + 1] - dep[t])) : 0; };
 
   // ---- compression, leaves to level 1
-  for (int l = L; l >= 1; --l) {
-    const int64_t cnt = int64_t(1) << l, sz = N / cnt;
-    cn[l].resize(cnt);
+  for (int t = T; t >= 1; --t) {
+    const int64_t cnt = int64_t(1) << dep[t], sz = N / cnt;
+    const int B = nchild(t);
+    cn[t].resize(cnt);
     parallel_for(cnt, [&](int64_t j) {
-      CNode& c = cn[l][j];
+      CNode& c = cn[t][j];
       c.n0 = j * sz;
       c.n1 = (j + 1) * sz;
-      if (l == L) {
+      if (t == T) {
         for (int64_t d = 2 * c.n0; d < 2 * c.n1; ++d) c.candr.push_back((int)d);
         c.candc = c.candr;
       } else {
-        const CNode& a = cn[l + 1][2 * j];
-        const CNode& b = cn[l + 1][2 * j + 1];
-        c.candr = a.Jr;
-        c.candr.insert(c.candr.end(), b.Jr.begin(), b.Jr.end());
-        c.candc = a.Jc;
-        c.candc.insert(c.candc.end(), b.Jc.begin(), b.Jc.end());
+        for (int b = 0; b < B; ++b) {
+          const CNode& ch = cn[t + 1][B * j + b];
+          c.candr.insert(c.candr.end(), ch.Jr.begin(), ch.Jr.end());
+          c.candc.insert(c.candc.end(), ch.Jc.begin(), ch.Jc.end());
+        }
       }
       compress_node(nd, prm, c);
     }, prm.threads);
   }
 
   // ---- inverse, leaves to root
-  std::vector<std::vector<std::vector<double>>> Dhat(L + 1);
-  for (int l = L; l >= 0; --l) {
-    const int64_t cnt = int64_t(1) << l;
-    if (l >= 1) out.lev[l].resize(cnt);
-    Dhat[l].resize(cnt);
+  std::vector<std::vector<std::vector<double>>> Dhat(T + 1);
+  for (int t = T; t >= 0; --t) {
+    const int64_t cnt = int64_t(1) << dep[t];
+    const int B = nchild(t);
+    if (t >= 1) out.lev[t].resize(cnt);
+    Dhat[t].resize(cnt);
     parallel_for(cnt, [&](int64_t j) {
       std::vector<double> Dm;
       int n;
-      if (l == L) {
-        const CNode& c = cn[l][j];
+      if (t == T) {
+        const CNode& c = cn[t][j];
         n = (int)c.candr.size();
         a_sub(nd, c.candr, c.candc, Dm);
       } else {
-        const CNode& a = cn[l + 1][2 * j];
-        const CNode& b = cn[l + 1][2 * j + 1];
-        const int ka = a.k, kb = b.k;
-        n = ka + kb;
+        // children's D^ on the diagonal, A(J_r(a), J_c(b)) off it
+        std::vector<int> off(B + 1, 0);
+        for (int b = 0; b < B; ++b) off[b + 1] = off[b] + cn[t + 1][B * j + b].k;
+        n = off[B];
         Dm.assign((size_t)n * n, 0.0);
-        const std::vector<double>& Da = Dhat[l + 1][2 * j];
-        const std::vector<double>& Db = Dhat[l + 1][2 * j + 1];
-        for (int c = 0; c < ka; ++c)
-          for (int r = 0; r < ka; ++r) Dm[r + (size_t)c * n] = Da[r + (size_t)c * ka];
-        for (int c = 0; c < kb; ++c)
-          for (int r = 0; r < kb; ++r) Dm[ka + r + (size_t)(ka + c) * n] = Db[r + (size_t)c * kb];
-        for (int c = 0; c < kb; ++c)
-          for (int r = 0; r < ka; ++r) Dm[r + (size_t)(ka + c) * n] = a_entry(nd, a.Jr[r], b.Jc[c]);
-        for (int c = 0; c < ka; ++c)
-          for (int r = 0; r < kb; ++r) Dm[ka + r + (size_t)c * n] = a_entry(nd, b.Jr[r], a.Jc[c]);
+        for (int a = 0; a < B; ++a) {
+          const CNode& ca = cn[t + 1][B * j + a];
+          for (int b = 0; b < B; ++b) {
+            const CNode& cb = cn[t + 1][B * j + b];
+            if (a == b) {
+              const std::vector<double>& Da = Dhat[t + 1][B * j + a];
+              for (int c = 0; c < ca.k; ++c)
+                for (int r = 0; r < ca.k; ++r) Dm[off[a] + r + (size_t)(off[a] + c) * n] = Da[r + (size_t)c * ca.k];
+            } else {
+              for (int c = 0; c < cb.k; ++c)
+                for (int r = 0; r < ca.k; ++r)
+                  Dm[off[a] + r + (size_t)(off[b] + c) * n] = a_entry(nd, ca.Jr[r], cb.Jc[c]);
+            }
+          }
+        }
       }
       if (hinv(n, Dm.data(), n)) RW_THROW(RW_ESINGULAR, "singular diagonal block in the HBS inverse");
-      if (l == 0) {
+      if (t == 0) {
         out.nroot = n;
         out.Groot = std::move(Dm);
         return;
       }
-      const CNode& c = cn[l][j];
+      const CNode& c = cn[t][j];
       const int k = c.k;
       // DinvU (n x k), VtDinv (k x n)
       std::vector<double> DinvU((size_t)n * k), VtDinv((size_t)k * n), S((size_t)k * k);
@@ -248,7 +266,7 @@ void hbs_build_inverse(const std::vector<NodeRec>& nd, const HbsParams& prm, Hbs
       hgemm('T', 'N', k, n, n, 1.0, c.V.data(), n, Dm.data(), n, 0.0, VtDinv.data(), k);
       hgemm('N', 'N', k, k, n, 1.0, VtDinv.data(), k, c.U.data(), n, 0.0, S.data(), k);
       if (k > 0 && hinv(k, S.data(), k)) RW_THROW(RW_ESINGULAR, "singular V* D^-1 U in the HBS inverse");
-      HbsNodeGen& g = out.lev[l][j];
+      HbsNodeGen& g = out.lev[t][j];
       g.nin = n;
       g.k = k;
       g.E.assign((size_t)n * k, 0.0);
@@ -257,13 +275,13 @@ void hbs_build_inverse(const std::vector<NodeRec>& nd, const HbsParams& prm, Hbs
       hgemm('N', 'N', k, n, k, 1.0, S.data(), k, VtDinv.data(), k, 0.0, g.Ft.data(), k);
       g.G = Dm;
       hgemm('N', 'N', n, n, k, -1.0, g.E.data(), n, VtDinv.data(), k, 1.0, g.G.data(), n);
-      Dhat[l][j] = std::move(S);
+      Dhat[t][j] = std::move(S);
     }, prm.threads);
   }
   out.max_rank = 0;
   out.entries = (int64_t)out.nroot * out.nroot;
-  for (int l = 1; l <= L; ++l)
-    for (auto& g : out.lev[l]) {
+  for (int t = 1; t <= T; ++t)
+    for (auto& g : out.lev[t]) {
       out.max_rank = std::max(out.max_rank, g.k);
       out.entries += (int64_t)g.E.size() + (int64_t)g.Ft.size() + (int64_t)g.G.size();
     }

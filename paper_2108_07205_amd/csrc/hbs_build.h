@@ -5,9 +5,13 @@
 // Algorithm 1 takes as input (Sec. 3.2); this is a from-scratch version of
 // that scheme for the Stokes double-layer system.
 //
-// Tree: perfect binary tree of contiguous arcs; root = level 0, leaves =
-// level L.  Per non-root node tau with input size n (2 * leaf nodes at the
-// leaves, the children's skeleton sizes above) and skeleton size k:
+// Tree of contiguous arcs; root = level 0, leaves = level L.  The arcs are
+// those of a perfect binary tree, and each tree level takes `merge` binary
+// levels at once (merge = 1: binary tree; 2: four children per node; the
+// level nearest the root takes what is left), so an apply has fewer
+// dependent level sweeps.  Per non-root node tau with input size n (2 * leaf
+// nodes at the leaves, the children's skeleton sizes above) and skeleton
+// size k:
 //   E (n x k), F* (k x n), G (n x n);  root: G_root = D_root^{-1}.
 // Apply of A_oo^{-1} b: upward b^ = F* b and g = G b per node (children's
 // b^ concatenated form the parent's input), x_root = G_root b_root, downward
@@ -41,6 +45,7 @@ struct HbsParams {
   int n_proxy = 48;          // proxy points per circle
   double proxy_ratio = 2.0;  // proxy radius / node radius
   int threads = 0;
+  int merge = 1;             // binary levels per tree level (1..4)
 };
 
 // Throws RwError(RW_ESINGULAR) on a singular node block.

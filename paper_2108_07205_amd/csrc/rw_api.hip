@@ -423,6 +423,7 @@ void build_wall(rw_ctx* ctx, const rw_curve& cv, int P, int q, int leaf, double 
   HbsParams prm;
   prm.leaf_nodes = leaf;
   prm.tol = tol;
+  prm.merge = ctx->opt.hbs_merge;
   HbsInverse H;
   hbs_build_inverse(w.disc.nodes, prm, H);
   hipStream_t s = ctx->stream;
@@ -996,6 +997,7 @@ int rw_ctx_create(rw_ctx** out, int device, void* hip_stream, size_t hbm_budget_
   c->opt.app_dense_max_nodes = 1024;
   c->opt.far_field = 1;
   c->opt.test_singular = 0;
+  c->opt.hbs_merge = 2;
   int rc = guarded(c.get(), [&]() {
     hipDeviceProp_t prop;
     HIP_CHECK(hipGetDeviceProperties(&prop, device));
@@ -1035,6 +1037,7 @@ int rw_set_options(rw_ctx* ctx, const rw_options* opt) {
     if (!(opt->ir_tol >= 0) || opt->ir_maxit < 0 || opt->app_dense_max_nodes < 0)
       RW_THROW(RW_EINVAL, "bad refinement options");
     if (opt->test_singular < 0 || opt->test_singular > 2) RW_THROW(RW_EINVAL, "test_singular outside 0..2");
+    if (opt->hbs_merge < 1 || opt->hbs_merge > 4) RW_THROW(RW_EINVAL, "hbs_merge outside 1..4");
     if (opt->sketch_cols != 32 && opt->sketch_cols != 64 && opt->sketch_cols != 96 && opt->sketch_cols != 128)
       RW_THROW(RW_EINVAL, "sketch_cols must be 32, 64, 96 or 128");
     ctx->opt = *opt;

@@ -60,18 +60,27 @@ def test_reference_nodes_match_oracle(wall64):
     assert np.max(np.abs(w - d.w) / d.w) < 1e-13
 
 
-def test_hbs_apply_matches_dense_inverse(wall64):
-    _say("hbs apply 64 panels, 3 columns")
+@pytest.mark.parametrize("merge", [1, 2, 3])
+def test_hbs_apply_matches_dense_inverse(ctx, merge):
+    """Reference HBS inverse with 1, 2 or 3 binary levels per tree level
+    (2, 4 or 8 children per node) against the dense inverse."""
+    _say(f"hbs apply 64 panels, 3 columns, merge {merge}")
+    ctx.set_options(hbs_merge=merge)
+    try:
+        wall = rw.Wall(ctx, 64)
+    finally:
+        ctx.set_options(hbs_merge=2)
     d = G.discretize(G.reference_panels(64), 0.3, 5)
     A = K.nystrom_matrix(d)
     rng = np.random.default_rng(11)
     B = rng.standard_normal((3, 2 * d.n))
-    X = wall64.hbs_apply(_dev(B)).cpu().numpy()
+    X = wall.hbs_apply(_dev(B)).cpu().numpy()
     Xo = np.linalg.solve(A, B.T).T
     for c in range(3):
         assert relerr(X[c], Xo[c]) < 2e-9
-    st = wall64.stats()
-    assert st["n_levels"] == 4 and st["gen_entries"] > 0
+    st = wall.stats()
+    assert st["n_levels"] == -(-4 // merge) and st["gen_entries"] > 0
+    wall.close()
 
 
 @pytest.mark.parametrize("nrhs", [1, 5, 16, 70])
