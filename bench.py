@@ -272,9 +272,12 @@ def main():
     def hbs_apply_rates(w, reps: int = 40):
         """One-RHS apply of the reference inverse A_oo^{-1} (the a6 kernel
         sweep) timed by HIP events on the ctx stream: warm (generators left
-        in the 256 MB Infinity Cache by the previous rep) and cold (a 1 GiB
-        scratch buffer written before each rep), against 8 TB/s and against
-        a measured device copy (1 GiB, read + write)."""
+        in the 256 MB Infinity Cache by the previous rep), cold (a 1 GiB
+        buffer read before each rep, which leaves the cache holding clean
+        lines of other data) and cold after a 1 GiB write (the cache then
+        holds dirty lines that must be written back as the apply reads),
+        against 8 TB/s and against a measured device copy (1 GiB, read +
+        write)."""
         n = 2 * w.n_nodes
         stw = w.stats()
         alg = float(stw["gen_bytes_f64"] + 8 * 2 * n)   # generators + read b + write x
@@ -283,8 +286,10 @@ def main():
         scratch = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
 
-        def one(cold: bool) -> float:
-            if cold:
+        def one(cold) -> float:
+            if cold == "read":
+                scratch.sum()
+            elif cold == "write":
                 scratch.fill_(float(np.random.rand()))
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
@@ -296,7 +301,8 @@ def main():
         for _ in range(5):
             one(False)
         warm = float(np.median([one(False) for _ in range(reps)]))
-        cold = float(np.median([one(True) for _ in range(reps)]))
+        cold = float(np.median([one("read") for _ in range(reps)]))
+        cold_w = float(np.median([one("write") for _ in range(reps)]))
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         scratch.copy_(src)
         e0.record()
@@ -306,8 +312,9 @@ def main():
         e1.synchronize()
         copy_gbps = 5 * 2 * scratch.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
         del scratch, src
-        out = {"algorithmic_bytes": alg, "warm_us": warm, "cold_us": cold, "copy_peak_GBps": copy_gbps}
-        for k in ("warm", "cold"):
+        out = {"algorithmic_bytes": alg, "warm_us": warm, "cold_us": cold, "cold_dirty_us": cold_w,
+               "copy_peak_GBps": copy_gbps}
+        for k in ("warm", "cold", "cold_dirty"):
             gbps = alg / (out[f"{k}_us"] * 1e-6) / 1e9
             out[f"{k}_GBps"] = gbps
             out[f"{k}_frac_of_8TBps"] = gbps / PEAK["hbm"][0]

@@ -21,7 +21,8 @@ import numpy as np
 __all__ = [
     "RwError", "load_library", "Context", "Wall", "Refined",
     "rw_ctx_create", "rw_ctx_destroy", "rw_set_options", "rw_get_options", "rw_wall_build",
-    "rw_wall_free", "rw_wall_stats_get", "rw_wall_nodes", "rw_hbs_apply", "rw_refine", "rw_coarsen",
+    "rw_wall_free", "rw_wall_stats_get", "rw_wall_nodes", "rw_hbs_apply", "rw_refine",
+    "rw_coarsen",
     "rw_refined_free", "rw_refined_info", "rw_nodes", "rw_solve", "rw_residual", "rw_stokeslet_rhs",
     "rw_ctx_trim", "rw_profile_enable", "rw_profile_reset", "rw_profile_json",
     "RW_OK", "RW_EINVAL", "RW_ENOMEM", "RW_ESINGULAR", "RW_ENOCONV", "RW_EDEVICE", "RW_F64", "RW_F32",

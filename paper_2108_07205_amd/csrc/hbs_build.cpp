@@ -286,3 +286,44 @@ void hbs_build_inverse(const std::vector<NodeRec>& nd, const HbsParams& prm, Hbs
       out.entries += (int64_t)g.E.size() + (int64_t)g.Ft.size() + (int64_t)g.G.size();
     }
 }
+
+bool hbs_fold_top(HbsInverse& H, int max_root) {
+  if (H.L < 2) return false;
+  const std::vector<HbsNodeGen>& top = H.lev[1];
+  int n = 0;
+  for (const HbsNodeGen& g : top) n += g.nin;
+  if (n > max_root) return false;
+  // T = blockdiag(E_1) G_root blockdiag(F*_1) + blockdiag(G_1): the map from
+  // the inputs of the level-1 nodes to their down-sweep outputs
+  const int nr = H.nroot;
+  std::vector<double> GF((size_t)nr * n, 0.0);   // G_root blockdiag(F*_1): nr x n
+  {
+    int c0 = 0, k0 = 0;
+    for (const HbsNodeGen& g : top) {
+      // columns c0 .. c0 + nin of GF = G_root(:, k0 .. k0 + k) F*_j
+      hgemm('N', 'N', nr, g.nin, g.k, 1.0, H.Groot.data() + (size_t)k0 * nr, nr, g.Ft.data(), g.k, 0.0,
+            GF.data() + (size_t)c0 * nr, nr);
+      c0 += g.nin;
+      k0 += g.k;
+    }
+  }
+  std::vector<double> T((size_t)n * n, 0.0);
+  {
+    int r0 = 0, k0 = 0;
+    for (const HbsNodeGen& g : top) {
+      // rows r0 .. r0 + nin of T = E_j GF(k0 .. k0 + k, :)
+      hgemm('N', 'N', g.nin, n, g.k, 1.0, g.E.data(), g.nin, GF.data() + k0, nr, 0.0, T.data() + r0, n);
+      for (int c = 0; c < g.nin; ++c)
+        for (int r = 0; r < g.nin; ++r) T[r0 + r + (size_t)(r0 + c) * n] += g.G[r + (size_t)c * g.nin];
+      r0 += g.nin;
+      k0 += g.k;
+    }
+  }
+  for (const HbsNodeGen& g : top) H.entries -= (int64_t)(g.E.size() + g.Ft.size() + g.G.size());
+  H.entries += (int64_t)n * n - (int64_t)nr * nr;
+  H.Groot = std::move(T);
+  H.nroot = n;
+  H.lev.erase(H.lev.begin() + 1);
+  H.L -= 1;
+  return true;
+}

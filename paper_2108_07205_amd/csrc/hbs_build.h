@@ -50,3 +50,11 @@ struct HbsParams {
 
 // Throws RwError(RW_ESINGULAR) on a singular node block.
 void hbs_build_inverse(const std::vector<NodeRec>& nodes, const HbsParams& prm, HbsInverse& out);
+
+// Folds tree level 1 into the root: the new root block is the map
+// blockdiag(E_1) G_root blockdiag(F*_1) + blockdiag(G_1) from the level-1
+// nodes' inputs to their down-sweep outputs (the same operator, one dense
+// block), so an apply has two dependent sweeps less.  Only when the new
+// root has at most max_root rows and the tree has at least two levels;
+// returns whether it folded.
+bool hbs_fold_top(HbsInverse& H, int max_root);

@@ -23,6 +23,8 @@ struct HbsDev {
   DBuf<double> ws;
   int ws_nrhs = 0;
   std::vector<double*> U, GB, X;
+  // one-RHS apply: its split partial vectors (hbs_ws1_plan) in ws1
+  DBuf<double> ws1;
   // GPU build: node records and flags read back without a wait, checked by
   // hbs_gpu_finish (records: pinned host memory of the building context)
   struct Finish {
@@ -33,6 +35,24 @@ struct HbsDev {
   } fin;
   int64_t n_unknowns() const { return lev.size() > 1 ? S[L] : 0; }
 };
+
+// Partial vectors of a one-RHS apply laid out from `base` (U1: bhat, GB1:
+// G b, X1: down outputs, X1[0] the root's) with the split counts of each
+// level; fixed-size, so that planning allocates nothing.
+constexpr int HBS_MAX_LEVELS = 32;
+struct HbsWs1 {
+  double* U1[HBS_MAX_LEVELS + 1];
+  double* GB1[HBS_MAX_LEVELS + 1];
+  double* X1[HBS_MAX_LEVELS + 1];
+  int nsu[HBS_MAX_LEVELS + 2];
+  int nsd[HBS_MAX_LEVELS + 1];
+  int nsr;
+};
+// Doubles the plan needs; with base != nullptr also fills ws.
+int64_t hbs_ws1_plan(const HbsDev& w, double* base, HbsWs1& ws);
+// One-RHS apply x = A^{-1} b with the partial vectors at `base` (at least
+// hbs_ws1_plan doubles); allocates nothing.
+void hbs_dev_apply1_at(const HbsDev& w, const double* b, double* x, bool use_f32, double* base, hipStream_t s);
 
 // Passes over the generators that one apply of nrhs right-hand sides makes
 // (8 columns per pass on the vector path, 64 from 40 columns on the matrix

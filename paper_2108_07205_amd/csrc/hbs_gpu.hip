@@ -1820,9 +1820,65 @@ static void hbs_ensure_ws(HbsDev& w, int nrhs) {
   w.ws_nrhs = nrhs;
 }
 
+int64_t hbs_ws1_plan(const HbsDev& w, double* base, HbsWs1& ws) {
+  const int L = w.L;
+  if (L > HBS_MAX_LEVELS) RW_THROW(RW_EINVAL, "HBS tree deeper than the one-RHS plan supports");
+  for (int l = 0; l <= L + 1; ++l) ws.nsu[l] = 1;
+  for (int l = 0; l <= L; ++l) ws.nsd[l] = 1;
+  for (int l = 1; l <= L; ++l) {
+    ws.nsu[l] = hbs_split_count(w.lev[l].max_nin);
+    ws.nsd[l] = hbs_split_count(w.lev[l].max_k);
+  }
+  ws.nsr = hbs_split_count(w.nroot);
+  int64_t off = 0;
+  auto take = [&](int64_t n) {
+    double* q = base ? base + off : nullptr;
+    off += n;
+    return q;
+  };
+  ws.X1[0] = take((int64_t)ws.nsr * w.S[0]);
+  for (int l = 1; l <= L; ++l) {
+    ws.U1[l] = take((int64_t)ws.nsu[l] * w.K[l]);
+    ws.GB1[l] = take((int64_t)ws.nsu[l] * w.S[l]);
+    ws.X1[l] = take((int64_t)ws.nsd[l] * w.S[l]);
+  }
+  return off;
+}
+
+// One right-hand side: level sweeps of split products whose partial vectors
+// are summed by the next kernel (see kern_hbs.hip).  Every partial vector is
+// written before it is read, so `base` needs no clearing.
+void hbs_dev_apply1_at(const HbsDev& w, const double* b, double* x, bool use_f32, double* base, hipStream_t s) {
+  HbsWs1 ws;
+  hbs_ws1_plan(w, base, ws);
+  const int L = w.L;
+  const float* g32 = use_f32 ? w.gen32.p : nullptr;
+  for (int l = L; l >= 1; --l) {
+    const bool leaf = l == L;
+    launch_hbs_up1(w.lev[l], w.gen.p, g32, leaf ? b : ws.U1[l + 1], leaf ? 0 : w.K[l + 1], leaf ? 1 : ws.nsu[l + 1],
+                   ws.U1[l], w.K[l], ws.GB1[l], w.S[l], s);
+  }
+  launch_hbs_root1(w.nroot, w.d_nroot, w.groot.p, ws.U1[1], w.K[1], ws.nsu[1], ws.X1[0], w.S[0], s);
+  for (int l = 1; l <= L; ++l) {
+    const int xnp = l == 1 ? ws.nsr : ws.nsd[l - 1];
+    const bool direct = l == L && ws.nsd[L] == 1;
+    launch_hbs_down1(w.lev[l], w.gen.p, g32, ws.X1[l - 1], w.S[l - 1], xnp, ws.GB1[l], w.S[l], ws.nsu[l],
+                     direct ? x : ws.X1[l], w.S[l], s);
+  }
+  if (ws.nsd[L] > 1) launch_parts_reduce(ws.X1[L], w.S[L], ws.nsd[L], w.S[L], x, s);
+}
+
 void hbs_dev_apply(HbsDev& w, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32,
                    hipStream_t s) {
   if (nrhs <= 0) return;
+  if (nrhs == 1) {
+    if (!w.ws1.p) {
+      HbsWs1 ws;
+      w.ws1.alloc(w.ctx, (size_t)std::max<int64_t>(1, hbs_ws1_plan(w, nullptr, ws)));
+    }
+    hbs_dev_apply1_at(w, b, x, use_f32 && w.gen32.p, w.ws1.p, s);
+    return;
+  }
   hbs_ensure_ws(w, nrhs);
   const bool f32 = use_f32 && w.gen32.p;
   for (int l = w.L; l >= 1; --l) {

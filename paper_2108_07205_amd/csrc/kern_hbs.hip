@@ -299,6 +299,151 @@ __global__ __launch_bounds__(kThreads) void hbs_root_mfma_kernel(int nmax, const
       [&](int row, int c, double v) { out[row + (int64_t)c * ld_out] = v; });
 }
 
+// ------------------------------------------ one right-hand side (split)
+// With one right-hand side every level is a batch of small GEMVs whose time
+// is the latency of the loads, not their bytes.  Each workgroup therefore
+// takes one slab of 64 rows and one split of at most kSplit columns of a
+// node's block: lane l owns row l, wave w columns 16 w .. 16 w + 15 of the
+// split, so every lane issues its loads in one round.  The split's partial
+// product goes to a partial vector of its own; the kernel that consumes the
+// vector sums the partials while it stages its input, so no separate
+// reduction runs and no atomics are needed.  A partial vector is written
+// for every split of every row of every node (zeros where a node has fewer
+// columns than the level's splits), so the consumer can sum them all.
+constexpr int kSplit = 64;
+
+// Partial vectors: part p of element i at base[p * stride + i].
+struct Parts {
+  const double* base;
+  int64_t stride;
+  int np;
+};
+
+// Sum of the partials of element i: up to 16 loads issued at once (one
+// memory round trip), then a fixed-order sum.
+__device__ __forceinline__ double parts_sum(const Parts& P, int64_t i) {
+  double t[16];
+#pragma unroll
+  for (int p = 0; p < 16; ++p) t[p] = p < P.np ? P.base[(int64_t)p * P.stride + i] : 0.0;
+  double v = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7])) +
+             (((t[8] + t[9]) + (t[10] + t[11])) + ((t[12] + t[13]) + (t[14] + t[15])));
+  for (int p = 16; p < P.np; ++p) v += P.base[(int64_t)p * P.stride + i];
+  return v;
+}
+
+// Loads of this lane (row `row` of M, R x C, ld R; columns of wave w in the
+// split starting at c0), issued before the input is staged.
+template <typename T>
+__device__ __forceinline__ void split_load(const T* __restrict__ M, int R, int C, int row, int c0, int w,
+                                           double (&m)[16]) {
+  const int cw = c0 + 16 * w;
+  const bool rv = row < R;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) m[u] = (rv && cw + u < C) ? (double)M[row + (int64_t)(cw + u) * R] : 0.0;
+}
+
+// This wave's part of the dot product (four independent sums), the four
+// waves' parts added through LDS; every lane of wave 0 returns its row's sum.
+__device__ __forceinline__ double split_dot(const double (&m)[16], const double* xs, int w, double* red) {
+  const int lane = threadIdx.x & 63;
+  const double* x = xs + 16 * w;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+  for (int u = 0; u < 16; u += 4) {
+    a0 = fma(m[u], x[u], a0);
+    a1 = fma(m[u + 1], x[u + 1], a1);
+    a2 = fma(m[u + 2], x[u + 2], a2);
+    a3 = fma(m[u + 3], x[u + 3], a3);
+  }
+  red[w * 64 + lane] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  return (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+}
+
+// grid (nodes * rbmax * ns).  [bhat; gb] partials = [F*; G](:, split) b(split).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void hbs_up1_kernel(int rbmax, int ns, const int* __restrict__ nin,
+                                                           const int* __restrict__ kk,
+                                                           const int64_t* __restrict__ in_off,
+                                                           const int64_t* __restrict__ kout_off,
+                                                           const int64_t* __restrict__ up_off,
+                                                           const T* __restrict__ gen, Parts in, double* __restrict__ bhat,
+                                                           int64_t bstride, double* __restrict__ gb,
+                                                           int64_t gstride) {
+  __shared__ double xs[kSplit];
+  __shared__ double red[4 * 64];
+  const int b = blockIdx.x;
+  const int j = b / (rbmax * ns), rem = b - j * rbmax * ns, rb = rem / ns, sp = rem - rb * ns;
+  const int n = nin[j], k = kk[j], R = k + n;
+  if (rb * kRows >= R) return;  // whole workgroup
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int row = rb * kRows + lane, c0 = sp * kSplit;
+  double m[16];
+  split_load<T>(gen + up_off[j], R, n, row, c0, w, m);
+  const int64_t io = in_off[j];
+  if (tid < kSplit) xs[tid] = c0 + tid < n ? parts_sum(in, io + c0 + tid) : 0.0;
+  __syncthreads();
+  const double v = split_dot(m, xs, w, red);
+  if (w == 0 && row < R) {
+    if (row < k) bhat[(int64_t)sp * bstride + kout_off[j] + row] = v;
+    else gb[(int64_t)sp * gstride + io + (row - k)] = v;
+  }
+}
+
+// grid (nodes * rbmax * ns).  out partials = E(:, split) xhat(split) (+ gb in split 0).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void hbs_down1_kernel(int rbmax, int ns, const int* __restrict__ nin,
+                                                             const int* __restrict__ kk,
+                                                             const int64_t* __restrict__ in_off,
+                                                             const int64_t* __restrict__ kout_off,
+                                                             const int64_t* __restrict__ e_off,
+                                                             const T* __restrict__ gen, Parts xhat, Parts gb,
+                                                             double* __restrict__ out, int64_t ostride) {
+  __shared__ double xs[kSplit];
+  __shared__ double red[4 * 64];
+  const int b = blockIdx.x;
+  const int j = b / (rbmax * ns), rem = b - j * rbmax * ns, rb = rem / ns, sp = rem - rb * ns;
+  const int n = nin[j], k = kk[j];
+  if (rb * kRows >= n) return;  // whole workgroup
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int row = rb * kRows + lane, c0 = sp * kSplit;
+  double m[16];
+  split_load<T>(gen + e_off[j], n, k, row, c0, w, m);
+  const int64_t io = in_off[j];
+  double g = 0.0;
+  if (sp == 0 && w == 0 && row < n) g = parts_sum(gb, io + row);
+  if (tid < kSplit) xs[tid] = c0 + tid < k ? parts_sum(xhat, kout_off[j] + c0 + tid) : 0.0;
+  __syncthreads();
+  const double v = split_dot(m, xs, w, red);
+  if (w == 0 && row < n) out[(int64_t)sp * ostride + io + row] = v + g;
+}
+
+// grid (rbmax * ns).  out partials = G_root(:, split) in(split); the root
+// size is n_dev[0] when n_dev is given (at most nmax), else nmax.
+__global__ __launch_bounds__(kThreads) void hbs_root1_kernel(int nmax, int ns, const int* __restrict__ n_dev,
+                                                             const double* __restrict__ G, Parts in,
+                                                             double* __restrict__ out, int64_t ostride) {
+  __shared__ double xs[kSplit];
+  __shared__ double red[4 * 64];
+  const int n = n_dev ? min(*n_dev, nmax) : nmax;
+  const int rb = blockIdx.x / ns, sp = blockIdx.x - rb * ns;
+  if (rb * kRows >= n) return;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int row = rb * kRows + lane, c0 = sp * kSplit;
+  double m[16];
+  split_load<double>(G, n, n, row, c0, w, m);
+  if (tid < kSplit) xs[tid] = c0 + tid < n ? parts_sum(in, c0 + tid) : 0.0;
+  __syncthreads();
+  const double v = split_dot(m, xs, w, red);
+  if (w == 0 && row < n) out[(int64_t)sp * ostride + row] = v;
+}
+
+// x = sum of the partials (a leaf level whose E has more than kSplit columns).
+__global__ __launch_bounds__(kThreads) void parts_reduce_kernel(Parts in, int64_t n, double* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) x[i] = parts_sum(in, i);
+}
+
 inline size_t slab_lds(int xs_len, int rb) {
   const size_t b = sizeof(double) * ((size_t)xs_len + 4 * (size_t)rb * kRows);
   if (b > 64 * 1024) RW_THROW(RW_EINVAL, "HBS node too large for the apply kernels");
@@ -365,6 +510,58 @@ void down_impl(const HbsLevelDev& L, const T* gen, const double* xhat, int64_t l
 }
 
 }  // namespace
+
+int hbs_split_count(int ncols) { return ncols <= 0 ? 1 : (ncols + kSplit - 1) / kSplit; }
+
+namespace {
+template <typename T>
+void up1_impl(const HbsLevelDev& L, const T* gen, const double* in, int64_t in_stride, int in_np, double* bhat,
+              int64_t bstride, double* gb, int64_t gstride, hipStream_t s) {
+  if (!L.nnodes) return;
+  const int rbmax = (L.max_k + L.max_nin + kRows - 1) / kRows, ns = hbs_split_count(L.max_nin);
+  KernelTimer kt("hbs_up_kernel", 2.0 * L.up_entries, sizeof(T) * (double)L.up_entries, s);
+  hipLaunchKernelGGL((hbs_up1_kernel<T>), dim3(L.nnodes * rbmax * ns), dim3(kThreads), 0, s, rbmax, ns, L.nin, L.k,
+                     L.in_off, L.kout_off, L.up_off, gen, Parts{in, in_stride, in_np}, bhat, bstride, gb, gstride);
+  KERNEL_CHECK("hbs_up1");
+}
+template <typename T>
+void down1_impl(const HbsLevelDev& L, const T* gen, const double* xh, int64_t xstride, int xnp, const double* gb,
+                int64_t gstride, int gnp, double* out, int64_t ostride, hipStream_t s) {
+  if (!L.nnodes) return;
+  const int rbmax = (L.max_nin + kRows - 1) / kRows, ns = hbs_split_count(L.max_k);
+  KernelTimer kt("hbs_down_kernel", 2.0 * L.e_entries, sizeof(T) * (double)L.e_entries, s);
+  hipLaunchKernelGGL((hbs_down1_kernel<T>), dim3(L.nnodes * rbmax * ns), dim3(kThreads), 0, s, rbmax, ns, L.nin,
+                     L.k, L.in_off, L.kout_off, L.e_off, gen, Parts{xh, xstride, xnp}, Parts{gb, gstride, gnp}, out,
+                     ostride);
+  KERNEL_CHECK("hbs_down1");
+}
+}  // namespace
+
+void launch_hbs_up1(const HbsLevelDev& L, const double* gen, const float* gen32, const double* in, int64_t in_stride,
+                    int in_np, double* bhat, int64_t bstride, double* gb, int64_t gstride, hipStream_t s) {
+  if (gen32) up1_impl<float>(L, gen32, in, in_stride, in_np, bhat, bstride, gb, gstride, s);
+  else up1_impl<double>(L, gen, in, in_stride, in_np, bhat, bstride, gb, gstride, s);
+}
+void launch_hbs_down1(const HbsLevelDev& L, const double* gen, const float* gen32, const double* xh, int64_t xstride,
+                      int xnp, const double* gb, int64_t gstride, int gnp, double* out, int64_t ostride,
+                      hipStream_t s) {
+  if (gen32) down1_impl<float>(L, gen32, xh, xstride, xnp, gb, gstride, gnp, out, ostride, s);
+  else down1_impl<double>(L, gen, xh, xstride, xnp, gb, gstride, gnp, out, ostride, s);
+}
+void launch_hbs_root1(int nroot, const int* d_nroot, const double* G, const double* in, int64_t in_stride, int in_np,
+                      double* out, int64_t ostride, hipStream_t s) {
+  if (nroot <= 0) return;
+  const int rbmax = (nroot + kRows - 1) / kRows, ns = hbs_split_count(nroot);
+  hipLaunchKernelGGL(hbs_root1_kernel, dim3(rbmax * ns), dim3(kThreads), 0, s, nroot, ns, d_nroot, G,
+                     Parts{in, in_stride, in_np}, out, ostride);
+  KERNEL_CHECK("hbs_root1");
+}
+void launch_parts_reduce(const double* in, int64_t stride, int np, int64_t n, double* x, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(parts_reduce_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                     Parts{in, stride, np}, n, x);
+  KERNEL_CHECK("parts_reduce");
+}
 
 double hbs_gen_passes(int nrhs) {
   if (nrhs <= 1) return 1.0;

@@ -37,6 +37,21 @@ void launch_hbs_down(const HbsLevelDev& L, const double* gen, const double* xhat
 void launch_hbs_down_f32(const HbsLevelDev& L, const float* gen, const double* xhat, int64_t ld_xh,
                          const double* gb, int64_t ld_gb, double* out, int64_t ld_out, int nrhs, hipStream_t s);
 
+// One right-hand side: every level's block products split over column
+// ranges of hbs_split_count(columns) workgroups, each writing a partial
+// vector (part p of element i at base[p * stride + i]); a consumer sums
+// the np partials of its input while staging it.  gen32 (if not null) is
+// the FP32 copy of the generators.
+int hbs_split_count(int ncols);
+void launch_hbs_up1(const HbsLevelDev& L, const double* gen, const float* gen32, const double* in, int64_t in_stride,
+                    int in_np, double* bhat, int64_t bstride, double* gb, int64_t gstride, hipStream_t s);
+void launch_hbs_down1(const HbsLevelDev& L, const double* gen, const float* gen32, const double* xh, int64_t xstride,
+                      int xnp, const double* gb, int64_t gstride, int gnp, double* out, int64_t ostride,
+                      hipStream_t s);
+void launch_hbs_root1(int nroot, const int* d_nroot, const double* G, const double* in, int64_t in_stride, int in_np,
+                      double* out, int64_t ostride, hipStream_t s);
+void launch_parts_reduce(const double* in, int64_t stride, int np, int64_t n, double* x, hipStream_t s);
+
 // ----------------------------------------------------------- Stokes tiles
 // r = g - A tau on one node set (exact Nystrom operator, tiles on the fly).
 // part: workspace of resid_part_doubles(n, nrhs) doubles.  norms (optional,

@@ -426,14 +426,16 @@ void build_wall(rw_ctx* ctx, const rw_curve& cv, int P, int q, int leaf, double 
   prm.merge = ctx->opt.hbs_merge;
   HbsInverse H;
   hbs_build_inverse(w.disc.nodes, prm, H);
+  const int tree_levels = H.L, tree_max_rank = H.max_rank;
+  hbs_fold_top(H, 768);   // root block of at most 768 rows (4.7 MB): the 8-RHS root kernel stages it in 64 KB of LDS
   hipStream_t s = ctx->stream;
   w.d_nodes.alloc(ctx, w.disc.nodes.size());
   w.d_nodes.upload(w.disc.nodes.data(), w.disc.nodes.size(), s);
   hbs_upload(ctx, H, precision == RW_F32, w.hbs);
   HIP_CHECK(hipStreamSynchronize(s));
   w.stats.n_nodes = (int64_t)w.disc.nodes.size();
-  w.stats.n_levels = w.hbs.L;
-  w.stats.max_rank = H.max_rank;
+  w.stats.n_levels = tree_levels;
+  w.stats.max_rank = tree_max_rank;
   w.stats.gen_entries = H.entries;
   w.stats.gen_bytes_f64 = 8 * H.entries;
   w.stats.t_build_ms = wall_ms() - t0;
