@@ -185,6 +185,20 @@ int rw_wall_nodes(const rw_wall* wall, double* xy_host, double* normals_host,
  * Errors: RW_EINVAL (nrhs <= 0), RW_ENOMEM, RW_EDEVICE. */
 int rw_hbs_apply(rw_wall* wall, const double* b_dev, int32_t nrhs, double* x_dev);
 
+/* One-RHS x = A_oo^{-1} b, as rw_hbs_apply with nrhs = 1, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): no hipMalloc, hipFree or
+ * other allocating call.  Its partial vectors live in a file-scope device
+ * array of 2^21 doubles (16 MiB) that each device holds until the process
+ * ends; walls whose apply needs more are rejected with RW_EINVAL.  Every
+ * call on a device shares that array (each call writes every partial before
+ * reading it, so nothing needs clearing), so calls that overlap on one GPU
+ * (several ctxs or streams) race: order them.  b_dev, x_dev: 2*N_o doubles
+ * (one column), may not alias; enqueued on the ctx stream, not synchronized,
+ * no profiler events.  Errors: RW_EINVAL (null arrays, wall too large),
+ * RW_EDEVICE. */
+int rw_hbs_apply_noalloc(rw_wall* wall, const double* b_dev, double* x_dev);
+
 /* ---- refinement (per time step; Algorithm 1 pre-computation) ------------ */
 
 /* Refine reference panels panel_ids[i] into 2^levels[i] equal-theta

@@ -21,7 +21,7 @@ import numpy as np
 __all__ = [
     "RwError", "load_library", "Context", "Wall", "Refined",
     "rw_ctx_create", "rw_ctx_destroy", "rw_set_options", "rw_get_options", "rw_wall_build",
-    "rw_wall_free", "rw_wall_stats_get", "rw_wall_nodes", "rw_hbs_apply", "rw_refine",
+    "rw_wall_free", "rw_wall_stats_get", "rw_wall_nodes", "rw_hbs_apply", "rw_hbs_apply_noalloc", "rw_refine",
     "rw_coarsen",
     "rw_refined_free", "rw_refined_info", "rw_nodes", "rw_solve", "rw_residual", "rw_stokeslet_rhs",
     "rw_ctx_trim", "rw_profile_enable", "rw_profile_reset", "rw_profile_json",
@@ -99,6 +99,7 @@ _SIGS = {
     "rw_wall_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(rw_wall_stats)]),
     "rw_wall_nodes": (ctypes.c_int, [_P, _DP, _DP, _DP, _I64P]),
     "rw_hbs_apply": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
+    "rw_hbs_apply_noalloc": (ctypes.c_int, [_P, _P, _P]),
     "rw_refine": (ctypes.c_int, [_P, _I32P, _I32P, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_P)]),
     "rw_coarsen": (ctypes.c_int, [_P, _I32P, ctypes.c_int32]),
     "rw_refined_free": (None, [_P]),
@@ -264,6 +265,14 @@ def rw_hbs_apply(ctx, wall, b, x, n_unknowns: int):
     if nb != nx:
         raise ValueError("b and x column counts differ")
     _check(load_library().rw_hbs_apply(wall, pb, nb, px), ctx)
+
+
+def rw_hbs_apply_noalloc(ctx, wall, b, x, n_unknowns: int):
+    pb, nb = _dev_ptr(b, "b", n_unknowns)
+    px, nx = _dev_ptr(x, "x", n_unknowns)
+    if nb != 1 or nx != 1:
+        raise ValueError("rw_hbs_apply_noalloc takes one column")
+    _check(load_library().rw_hbs_apply_noalloc(wall, pb, px), ctx)
 
 
 def rw_refine(ctx, wall, panel_ids: Sequence[int], levels: Sequence[int], q_tol: float = 0.0):

@@ -345,6 +345,31 @@ static void ctx_destroy_aux(rw_ctx* ctx) {
   }
 }
 
+// ------------------------------------------------ no-allocation scratch
+// Device memory of rw_hbs_apply_noalloc: a file-scope array that each device
+// holds from the library's load until the process ends.  Host code never
+// uses the array's name as an address: rw_ctx_create looks up each device's
+// copy once (hipGetSymbolAddress, with that device current) and keeps it.
+constexpr int64_t NOALLOC_DOUBLES = int64_t(1) << 21;   // 16 MiB
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+static std::mutex g_scratch_mu;
+
+// Address of this device's copy of `scratch` (device current); looked up once.
+static double* noalloc_scratch(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) RW_THROW(RW_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    double* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      RW_THROW(RW_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+
 namespace {
 thread_local std::string g_create_err;
 
@@ -1007,6 +1032,7 @@ int rw_ctx_create(rw_ctx** out, int device, void* hip_stream, size_t hbm_budget_
     c->sync_words = 256;
     c->d_sync = (unsigned*)dev_alloc(c.get(), sizeof(unsigned) * c->sync_words);
     HIP_CHECK(hipMemset(c->d_sync, 0, sizeof(unsigned) * c->sync_words));
+    noalloc_scratch(device);   // this device's copy of the no-allocation scratch
   });
   if (rc != RW_OK) { g_create_err = c->err; return rc; }
   *out = c.release();
@@ -1150,6 +1176,32 @@ int rw_hbs_apply(rw_wall* w, const double* b, int32_t nrhs, double* x) {
     hbs_apply(w, b, n2, x, n2, nrhs, w->precision == RW_F32);
     KERNEL_CHECK("hbs_apply");
   });
+}
+
+int rw_hbs_apply_noalloc(rw_wall* w, const double* b, double* x) {
+  if (!w) return RW_EINVAL;
+  rw_ctx* ctx = w->ctx;
+  ctx->err.clear();
+  try {
+    if (!b || !x) RW_THROW(RW_EINVAL, "null b or x");
+    HIP_CHECK(hipSetDevice(ctx->device));
+    HbsWs1 plan;
+    const int64_t need = hbs_ws1_plan(w->hbs, nullptr, plan);
+    if (need > NOALLOC_DOUBLES)
+      RW_THROW(RW_EINVAL, "the wall's one-RHS apply needs " + std::to_string(need) + " scratch doubles, above the " +
+                              std::to_string(NOALLOC_DOUBLES) + " of rw_hbs_apply_noalloc");
+    double* base = g_scratch_ptr[ctx->device];
+    if (!base) RW_THROW(RW_EDEVICE, "no-allocation scratch not set up for this device");
+    hbs_dev_apply1_at(w->hbs, b, x, w->precision == RW_F32, base, ctx->stream);
+    KERNEL_CHECK("hbs_apply_noalloc");
+    return RW_OK;
+  } catch (const RwError& e) {
+    ctx->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    ctx->err = e.what();
+    return RW_EDEVICE;
+  }
 }
 
 int rw_refine(rw_wall* w, const int32_t* ids, const int32_t* levels, int32_t n_sel, double q_tol,
