@@ -64,11 +64,11 @@ KERNEL_BOUND = {
 # the counters were taken; otherwise the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
     "node_factor_bordered_kernel": {
-        "fetch_kib": 2654.0, "write_kib": 6432.3, "fetch_scale": 1.9999, "write_scale": 1.0000,
+        "fetch_kib": 1251.5, "write_kib": 3298.2, "fetch_scale": 1.9999, "write_scale": 1.0000,
         "sources": ["paper_2108_07205_amd/csrc/hbs_gpu.hip", "paper_2108_07205_amd/csrc/dev_gj.h",
                     "paper_2108_07205_amd/csrc/dev_reduce.h", "paper_2108_07205_amd/csrc/hbs_dev.h",
                     "paper_2108_07205_amd/csrc/common.h"],
-        "sha256": "7ecf603c65c54b025fc61d28c7feef22b4ca4a6c56df90d2b69333353e7ec0c9",
+        "sha256": "3bd0fc8d777d53203b6454f4fc5ca78648f8e7c9495e208b4391faeaf3e6cfda",
         "summary": "profiles/star1024_refine16x4_hbm_traffic.md",
     },
 }
@@ -240,6 +240,7 @@ def roofline(phases: dict):
                   "frac": (ach / peak) if ach is not None else None, "traffic": measured_traffic(name),
                   "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                   "avg_launch_ms": ph["ms"] / max(1, ph["calls"]), "launches": ph["calls"],
+                  "algorithmic_bytes_per_launch": ph["bytes"] / max(1, ph["calls"]),
                   "algorithmic_per_launch": (ph["bytes"] if bound == "hbm" else ph["flops"]) / max(1, ph["calls"])}, table
 
 
@@ -250,6 +251,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without the phase events")
+    ap.add_argument("--no-oracle-check", action="store_true",
+                    help="skip the oracle's check of the timed seeds (profiler runs; the line then says so)")
     ap.add_argument("--hbs-apply-only", action="store_true",
                     help="only the one-RHS reference-inverse apply, warm and cold (for kernel traces)")
     ap.add_argument("--extra-steps", type=int, default=40,
@@ -381,7 +384,11 @@ def main():
     # per-kernel HIP events that give the roofline and the kernel table
     ok_lib, elapsed, lat, infos, _ = timed(False)
     # the oracle's check of every timed seed (host cores, after the timed region)
-    ogate = oracle_gate({s: t.cpu().numpy() for s, t in taus.items()})
+    if args.no_oracle_check:
+        ogate = {"ok": {s: True for s in taus}, "max_resid": None, "max_bound": None, "rows_per_seed": 0,
+                 "golden_rel2": {}, "workers": 0, "seconds": 0.0, "skipped": True}
+    else:
+        ogate = oracle_gate({s: t.cpu().numpy() for s, t in taus.items()})
     taus.clear()
     ok = sum(int(good and ogate["ok"][s]) for s, good in enumerate(ok_lib))
     value = ok / elapsed
@@ -513,6 +520,7 @@ def main():
                  "oracle_max_resid": ogate["max_resid"], "oracle_max_error_bound": ogate["max_bound"],
                  "oracle_golden_rel2": ogate["golden_rel2"],
                  "oracle_check_s": ogate["seconds"], "oracle_workers": ogate["workers"],
+                 "oracle_check_skipped": bool(ogate.get("skipped", False)),
                  "max_resid": float(max(i["resid"] for i in infos)),
                  "k_range": [int(min(i["k"] for i in infos)), int(max(i["k"] for i in infos))],
                  "ir_iters_max": int(max(i["ir_iters"] for i in infos))},

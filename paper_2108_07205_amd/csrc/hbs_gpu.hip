@@ -1150,6 +1150,18 @@ __device__ __forceinline__ double a_entry(const NodeRec& t, const NodeRec& s, bo
   return cf * rt * rs + s.w * nt * ns;
 }
 
+// a_entry with the target given by its position and normal.
+__device__ __forceinline__ double a_entry_xy(double tx, double ty, double tnx, double tny, const NodeRec& s, bool self,
+                                             int ti, int sj) {
+  if (self) return (ti == 0) ? (sj == 0 ? s.s00 : s.s01) : (sj == 0 ? s.s01 : s.s11);
+  const double rx = tx - s.x, ry = ty - s.y;
+  const double r2 = rx * rx + ry * ry;
+  const double cf = (rx * s.nx + ry * s.ny) * s.w * kInvPi / (r2 * r2);
+  const double rt = ti ? ry : rx, rs = sj ? ry : rx;
+  const double nt = ti ? tny : tnx, ns = sj ? s.ny : s.nx;
+  return cf * rt * rs + s.w * nt * ns;
+}
+
 // ------------------------------------------------- 4a. bordered factorization
 // One Gauss-Jordan inversion per node of the bordered matrix
 //   M = [[D, U], [V*, 0]]   ((n + k) x (n + k)),
@@ -1203,35 +1215,34 @@ __global__ __launch_bounds__(BWV * 64) void node_factor_bordered_kernel(
     Da = dhat_ch + ca.dhat_off;
     Db = dhat_ch + cbn.dhat_off;
   }
-  // ---- M assembled in the node's workspace slot, then into the registers
-  double* Mw = ws + g.ws_off;
-  for (int idx = tid; idx < T * T; idx += BWV * 64) {
-    const int row = idx % T, col = idx / T;
-    double v = 0.0;
-    if (row < n && col < n) {
-      if (!is_leaf && row < ka && col < ka) v = Da[row + col * ka];
-      else if (!is_leaf && row >= ka && col >= ka) v = Db[(row - ka) + (col - ka) * kb];
-      else {
-        const int ra = cr[row], cb = cc[col];
-        v = a_entry(nd[ra >> 1], nd[cb >> 1], is_leaf && (ra >> 1) == (cb >> 1), ra & 1, cb & 1);
-      }
-    } else if (row < n) {
-      v = Un[row + (int64_t)(col - n) * n];
-    } else if (col < n) {
-      v = Vn[col + (int64_t)(row - n) * n];
-    }
-    Mw[idx] = v;
-  }
-  __threadfence_block();
-  __syncthreads();
+  // ---- M assembled straight into the registers: lane l, wave w hold rows
+  // l + 64 s, columns BC w + c (the children's D^ blocks, kernel entries
+  // between the candidates, U and V* on the border); one sub-row at a time,
+  // the column records read per entry (wave-uniform, from the cache)
   double a[BS][BC];
 #pragma unroll
   for (int sr = 0; sr < BS; ++sr) {
     const int row = lane + 64 * sr;
+    const int rd = row < n ? cr[row] : 0;
+    const NodeRec& t = nd[rd >> 1];
+    const double tx = t.x, ty = t.y, tnx = t.nx, tny = t.ny;
 #pragma unroll
     for (int c = 0; c < BC; ++c) {
-      const int col = BC * w + c;
-      a[sr][c] = (row < T && col < T) ? Mw[row + col * T] : 0.0;
+      const int col = BC * w + c;   // wave-uniform
+      double v = 0.0;
+      if (row < n && col < n) {
+        if (!is_leaf && row < ka && col < ka) v = Da[row + col * ka];
+        else if (!is_leaf && row >= ka && col >= ka) v = Db[(row - ka) + (col - ka) * kb];
+        else {
+          const int cb = cc[col];
+          v = a_entry_xy(tx, ty, tnx, tny, nd[cb >> 1], is_leaf && (rd >> 1) == (cb >> 1), rd & 1, cb & 1);
+        }
+      } else if (row < n && col < T) {
+        v = Un[row + (int64_t)(col - n) * n];
+      } else if (row < T && col < n) {
+        v = Vn[col + (int64_t)(row - n) * n];
+      }
+      a[sr][c] = v;
     }
   }
   // Blocked Gauss-Jordan: block bj is the 16 columns of wave bj.  That wave
@@ -1917,26 +1928,42 @@ void hbs_gpu_finish(HbsDev& w) {
     const GNode* gl = hG + nn;
     HbsLevelDev& d = w.lev[l];
     d.up_entries = d.e_entries = 0;
-    double fl = 0.0;
+    double fl = 0.0, by = 0.0;
     for (int j = 0; j < nn; ++j) {
       const GNode& g = gl[j];
       d.up_entries += (int64_t)(g.k + g.m) * g.m;
       d.e_entries += (int64_t)g.m * g.k;
       w.entries += 2 * (int64_t)g.m * g.k + (int64_t)g.m * g.m;
       w.max_rank = std::max(w.max_rank, g.k);
-      // flops credited to the bordered kernel: only the nodes it factors
-      // (larger ones go to the block-inverse kernels)
+      // flops and bytes credited to the bordered kernel: only the nodes it
+      // factors (larger ones go to the block-inverse kernels).  Bytes: the
+      // (m + k)^2 generator entries written, U and V read, the children's
+      // D^ read, one node record (64 B) and two candidate indices per row
       const double nm = g.m, kk2 = g.k;
-      if (g.m + g.k <= BT)
+      if (g.m + g.k <= BT) {
         fl += 2.0 * nm * nm * nm + 2.0 * (3.0 * nm * nm * kk2 + 3.0 * nm * kk2 * kk2) + 2.0 * kk2 * kk2 * kk2;
+        double ch = 0.0;
+        if (l < w.L) {
+          const GNode* gc = hG + 2 * nn;
+          ch = (double)gc[2 * j].k * gc[2 * j].k + (double)gc[2 * j + 1].k * gc[2 * j + 1].k;
+        }
+        by += 8.0 * (nm + kk2) * (nm + kk2) + 16.0 * nm * kk2 + 8.0 * ch + 72.0 * nm;
+      }
     }
     const size_t fe = w.fin.fac_entry[l];
-    if (fe != SIZE_MAX && fe < ctx->pending.size()) ctx->pending[fe].flops = fl;
+    if (fe != SIZE_MAX && fe < ctx->pending.size()) {
+      ctx->pending[fe].flops = fl;
+      ctx->pending[fe].bytes = by;
+    }
   }
   const double nr = hG[1].m;
   w.entries += (int64_t)(nr * nr);
   const size_t fe = w.fin.fac_entry[0];
-  if (fe != SIZE_MAX && fe < ctx->pending.size()) ctx->pending[fe].flops = 2.0 * nr * nr * nr;
+  if (fe != SIZE_MAX && fe < ctx->pending.size()) {
+    const double ka = hG[2].k, kb = hG[3].k;
+    ctx->pending[fe].flops = 2.0 * nr * nr * nr;
+    ctx->pending[fe].bytes = 8.0 * nr * nr + 8.0 * (ka * ka + kb * kb) + 72.0 * nr;
+  }
 }
 
 // ================================================================== GPU build
