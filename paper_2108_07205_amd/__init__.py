@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -26,7 +27,7 @@ __all__ = [
     "rw_refined_free", "rw_refined_info", "rw_nodes", "rw_solve", "rw_residual", "rw_stokeslet_rhs",
     "rw_ctx_trim", "rw_profile_enable", "rw_profile_reset", "rw_profile_json",
     "RW_OK", "RW_EINVAL", "RW_ENOMEM", "RW_ESINGULAR", "RW_ENOCONV", "RW_EDEVICE", "RW_F64", "RW_F32",
-    "RW_BF16", "rw_solve_batch",
+    "RW_BF16", "RW_SOLVE_IR", "RW_SOLVE_GMRES", "rw_solve_batch",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -35,6 +36,7 @@ LIB_PATH = os.path.join(HERE, "librw.so")
 
 RW_OK, RW_EINVAL, RW_ENOMEM, RW_ESINGULAR, RW_ENOCONV, RW_EDEVICE = 0, -1, -2, -3, -4, -5
 RW_F64, RW_F32, RW_BF16 = 0, 1, 2
+RW_SOLVE_IR, RW_SOLVE_GMRES = 0, 1
 _CODES = {RW_EINVAL: "RW_EINVAL", RW_ENOMEM: "RW_ENOMEM", RW_ESINGULAR: "RW_ESINGULAR",
           RW_ENOCONV: "RW_ENOCONV", RW_EDEVICE: "RW_EDEVICE"}
 
@@ -53,7 +55,8 @@ class rw_options(ctypes.Structure):
     _fields_ = [("ir_tol", ctypes.c_double), ("ir_maxit", ctypes.c_int32),
                 ("sketch_cols", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("app_dense_max_nodes", ctypes.c_int32), ("far_field", ctypes.c_int32),
-                ("hbs_merge", ctypes.c_int32), ("test_singular", ctypes.c_int32)]
+                ("hbs_merge", ctypes.c_int32), ("solver", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
+                ("gmres_precond", ctypes.c_int32), ("test_singular", ctypes.c_int32)]
 
 
 class rw_info(ctypes.Structure):
@@ -174,7 +177,8 @@ def rw_ctx_destroy(ctx):
 
 
 def rw_set_options(ctx, ir_tol=None, ir_maxit=None, sketch_cols=None, seed=None, app_dense_max_nodes=None,
-                   far_field=None, test_singular=None, hbs_merge=None):
+                   far_field=None, test_singular=None, hbs_merge=None, solver=None, gmres_restart=None,
+                   gmres_precond=None):
     lib = load_library()
     o = rw_options()
     _check(lib.rw_get_options(ctx, ctypes.byref(o)), ctx)
@@ -194,6 +198,12 @@ def rw_set_options(ctx, ir_tol=None, ir_maxit=None, sketch_cols=None, seed=None,
         o.test_singular = int(test_singular)
     if hbs_merge is not None:
         o.hbs_merge = int(hbs_merge)
+    if solver is not None:
+        o.solver = int(solver)
+    if gmres_restart is not None:
+        o.gmres_restart = int(gmres_restart)
+    if gmres_precond is not None:
+        o.gmres_precond = int(gmres_precond)
     _check(lib.rw_set_options(ctx, ctypes.byref(o)), ctx)
 
 
@@ -359,10 +369,14 @@ def rw_stokeslet_rhs(ctx, ref, z, f, g, n_unknowns: int):
 
 # ----------------------------------------------------------------- classes
 class Context:
-    """A device + stream + HBM budget; owns nothing but scratch flags."""
+    """A device + stream + HBM budget.  Closing it first closes the walls made
+    on it (and their refinements): the C ABI requires a ctx to outlive its
+    walls and a wall its refinements."""
 
     def __init__(self, device: int = 0, stream: Optional[int] = None, hbm_budget_bytes: int = 0, **opts):
         self.device = device
+        self.h = None
+        self._children = weakref.WeakSet()
         self.h = rw_ctx_create(device, stream, hbm_budget_bytes)
         if opts:
             rw_set_options(self.h, **opts)
@@ -390,6 +404,8 @@ class Context:
 
     def close(self):
         if self.h:
+            for w in list(self._children):
+                w.close()
             rw_ctx_destroy(self.h)
             self.h = None
 
@@ -406,7 +422,12 @@ class Wall:
     def __init__(self, ctx: Context, n_panels: int, order: int = 16, leaf_nodes: int = 64,
                  id_tol: float = 1e-10, precision: int = RW_F64, a: float = 0.3, m: int = 5):
         self.ctx = ctx
+        self.h = None
+        self._children = weakref.WeakSet()
+        if not ctx.h:
+            raise RwError(RW_EINVAL, "context is closed")
         self.h = rw_wall_build(ctx.h, n_panels, order, leaf_nodes, id_tol, precision, a, m)
+        ctx._children.add(self)
         self.n_nodes = n_panels * order
         self.n_panels = n_panels
 
@@ -436,7 +457,10 @@ class Wall:
 
     def close(self):
         if self.h:
-            rw_wall_free(self.h)
+            for r in list(self._children):
+                r.close()
+            if self.ctx.h:
+                rw_wall_free(self.h)
             self.h = None
 
     def __del__(self):
@@ -452,7 +476,11 @@ class Refined:
     def __init__(self, wall: Wall, panel_ids, levels, q_tol: float = 0.0):
         self.wall = wall
         self.ctx = wall.ctx
+        self.h = None
+        if not wall.h:
+            raise RwError(RW_EINVAL, "wall is closed")
         self.h = rw_refine(self.ctx.h, wall.h, panel_ids, levels, q_tol)
+        wall._children.add(self)
         self._refresh()
 
     def _refresh(self):
@@ -493,7 +521,8 @@ class Refined:
 
     def close(self):
         if self.h:
-            rw_refined_free(self.h)
+            if self.wall.h and self.ctx.h:
+                rw_refined_free(self.h)
             self.h = None
 
     def __del__(self):
