@@ -62,6 +62,12 @@ enum rw_status {
  * generators are built. */
 enum rw_precision { RW_F64 = 0, RW_F32 = 1, RW_BF16 = 2 };
 
+/* Solver of rw_solve after the refinement's factors are built. */
+enum rw_solver {
+  RW_SOLVE_IR = 0,    /* Richardson refinement: tau += M^{-1} (g - A_nn tau), M^{-1} the Woodbury solve */
+  RW_SOLVE_GMRES = 1  /* GMRES on the exact A_nn, right-preconditioned by the Woodbury solve (Sec. 4) */
+};
+
 /* Star curve gamma(theta) = (1 + a cos(m theta)) (cos theta, sin theta),
  * theta in [0, 2 pi), counter-clockwise (a = 0: unit circle). */
 typedef struct {
@@ -84,6 +90,11 @@ typedef struct {
   int32_t hbs_merge;         /* binary tree levels merged into one level of the reference HBS tree built
                                 by the next rw_wall_build, 1..4 (1: binary tree; 2: four children per
                                 node): fewer dependent level sweeps per apply [2] */
+  int32_t solver;            /* RW_SOLVE_IR or RW_SOLVE_GMRES [RW_SOLVE_IR]; with GMRES, ir_maxit caps the
+                                Krylov iterations over all restarts and ir_tol is the same residual test */
+  int32_t gmres_restart;     /* GMRES: Krylov dimension before a restart, 1..256 [30] */
+  int32_t gmres_precond;     /* GMRES: 1 = preconditioned by the Woodbury solve (Sec. 4, eq.
+                                left_precond_general applied on the right), 0 = plain GMRES on A_nn [1] */
   int32_t test_singular;     /* test hook, 0 in normal use [0]: 1 = zero the first column of W = I + R X
                                 before its inversion, 2 = zero the first column of a dense A_pp before
                                 its LU; the library's own pivot checks then report RW_ESINGULAR */
@@ -108,10 +119,12 @@ typedef struct {
 
 /* Outcome of one rw_solve (Algorithm 1 solve steps + refinement). */
 typedef struct {
-  int32_t ir_iters;          /* refinement corrections applied */
+  int32_t ir_iters;          /* refinement corrections applied (RW_SOLVE_IR) or Krylov iterations over all
+                                restarts, summed over the columns (RW_SOLVE_GMRES) */
   int32_t k;                 /* rank k = k_k + k_p of the Woodbury update used */
   double resid;              /* max over columns of ||g - A_nn tau|| / ||g|| on return */
-  double resid_direct;       /* the same for the plain Woodbury solution (before any correction) */
+  double resid_direct;       /* the same for the plain Woodbury solution (before any correction; with
+                                RW_SOLVE_GMRES after the first Krylov step) */
   double t_solve_ms;         /* wall time of the call */
 } rw_solve_info;
 
@@ -241,7 +254,12 @@ int rw_nodes(const rw_refined* ref, double* xy_host, double* normals_host,
  * then iterative refinement with the exact refined Nystrom residual until
  * ||g - A_nn tau|| / ||g|| <= ir_tol (per column) or ir_maxit corrections.
  * With ir_maxit >= 1 the first correction is always taken (it is enqueued
- * before the first residual is read back).
+ * before the first residual is read back).  With solver = RW_SOLVE_GMRES:
+ * restarted GMRES per column from tau = 0 on the exact A_nn (its products by
+ * the residual kernel), right-preconditioned by the Woodbury solve unless
+ * gmres_precond = 0, modified Gram-Schmidt applied twice per step, until the
+ * same residual test or ir_maxit iterations; the residual is recomputed at
+ * each restart and at the end.
  * g_dev, tau_dev: 2*N_n x nrhs column-major, may not alias.  info_host: NULL
  * or a caller-owned rw_solve_info that receives the outcome (also on
  * RW_ENOCONV).  The stream is synchronized before return.  Errors:

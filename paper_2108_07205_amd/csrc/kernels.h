@@ -136,6 +136,10 @@ void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, 
 // Y = Y - X W (X: M x k col-major, W: k x nrhs col-major ld=k)
 void launch_sub_xw(const double* X, int64_t ldx, int64_t M, int k, const double* W, double* Y,
                    int64_t ldy, int nrhs, hipStream_t s);
+// Krylov vectors: v = w / sqrt(nrm2[0]) (nrm2 on the device; w, v may alias),
+// y = a x.
+void launch_scale_rsqrt(const double* w, int64_t n, const double* nrm2, double* v, hipStream_t s);
+void launch_scale_copy(const double* x, int64_t n, double a, double* y, hipStream_t s);
 // in-place inverse of a small k x k matrix (Gauss-Jordan, partial pivoting);
 // writes 0 / pivot index + 1 to *info (device int)
 void launch_small_inverse(double* W, int k, int* info, hipStream_t s);

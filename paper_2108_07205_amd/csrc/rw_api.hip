@@ -497,6 +497,11 @@ struct rw_refined {
   bool pending = false;
   DBuf<int> dinfo;                     // W pivot flag (device)
   DBuf<double> wpart;                  // split partial sums of R X
+  // GMRES workspace (rw_solve with RW_SOLVE_GMRES): Arnoldi basis V (N x
+  // (m + 1)), preconditioned directions Z (N x m), the new vector, a zero
+  // vector, Gram-Schmidt coefficients and norms, partial sums, y
+  DBuf<double> gv, gz, gw, gzero, gh, gpart, gy;
+  int gm = 0;
   int fail_rc = RW_OK;
   std::string fail_msg;
 };
@@ -980,6 +985,149 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
   if (f.pending) ctx->unsettled = &f;
 }
 
+// ------------------------------------------------------------------ GMRES
+// Restarted GMRES on the exact refined operator A_nn for one column (Sec. 4:
+// the Woodbury solve of the extended system is the preconditioner; here it
+// is applied on the right, so the residual GMRES minimizes is the true
+// ||g - A_nn tau||).  Products A z come from the residual kernel (g = 0);
+// Gram-Schmidt is applied twice per step (classical, on the device), and the
+// host reads back one Hessenberg column per step for the Givens rotations.
+// Returns the iterations taken; *rel: the final ||g - A tau|| / ||g||,
+// *rel1: the residual estimate after the first step.
+void gmres_ensure_ws(rw_refined* f, int m) {
+  if (m <= f->gm) return;
+  rw_ctx* ctx = f->ctx;
+  const int64_t N = 2 * f->Nn;
+  f->gv.alloc(ctx, (size_t)N * (m + 1));
+  f->gz.alloc(ctx, (size_t)N * m);
+  f->gw.alloc(ctx, (size_t)N);
+  f->gzero.alloc(ctx, (size_t)N);
+  HIP_CHECK(hipMemsetAsync(f->gzero.p, 0, sizeof(double) * N, ctx->stream));
+  f->gh.alloc(ctx, (size_t)2 * (m + 1) + 8);
+  f->gpart.alloc(ctx, gemm_tn_part_doubles(N, m + 1, 1));
+  f->gy.alloc(ctx, (size_t)m);
+  f->gm = m;
+}
+
+int gmres_column(rw_refined* f, const double* g, double* tau, double tol, int maxit, double* rel, double* rel1) {
+  rw_ctx* ctx = f->ctx;
+  hipStream_t s = ctx->stream;
+  const rw_options& o = ctx->opt;
+  const int m = o.gmres_restart;
+  const bool precond = o.gmres_precond != 0;
+  const int64_t N = 2 * f->Nn;
+  gmres_ensure_ws(f, m);
+  refined_ensure_ws(f, 1);
+  double* V = f->gv.p;
+  double* Z = f->gz.p;
+  double* w = f->gw.p;
+  double* h1 = f->gh.p;            // m + 1
+  double* h2 = f->gh.p + (m + 1);  // m + 1
+  double* nrm = f->gh.p + 2 * (m + 1);   // [0]: |w|^2, [1]: |g|^2, [2]: |r|^2
+  double* hb = (double*)ctx_readback(ctx, sizeof(double) * (2 * (m + 1) + 8));
+  auto matvec = [&](const double* z, double* out) {   // out = A z
+    PhaseTimer t(ctx, "a8_residual", 26.0 * (double)f->Nn * f->Nn, 0.0);
+    launch_residual(f->d_new.p, f->Nn, f->gzero.p, z, out, 1, f->part.p, nullptr, s);
+    launch_scale_copy(out, N, -1.0, out, s);
+  };
+  auto dot_to = [&](const double* a, const double* b, double* dst) {
+    launch_gemm_tn(a, N, b, N, N, 1, 1, dst, 1, false, f->gpart.p, s);
+  };
+  // tau = 0, r = g
+  HIP_CHECK(hipMemsetAsync(tau, 0, sizeof(double) * N, s));
+  dot_to(g, g, nrm + 1);
+  HIP_CHECK(hipMemcpyAsync(hb, nrm + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  refined_settle(f);
+  const double gn = std::sqrt(hb[0]);
+  if (!(gn > 0.0)) {
+    *rel = *rel1 = 0.0;
+    return 0;
+  }
+  double beta = gn;
+  launch_scale_rsqrt(g, N, nrm + 1, V, s);
+  int it = 0;
+  *rel1 = -1.0;
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gam(m + 1);
+  for (;;) {
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(gam.begin(), gam.end(), 0.0);
+    gam[0] = beta;
+    int j = 0;
+    double est = beta;
+    for (; j < m && it < maxit; ++j) {
+      double* vj = V + (size_t)j * N;
+      double* zj = Z + (size_t)j * N;
+      if (precond) {
+        woodbury_apply(f, vj, zj, 1, false);
+      } else {
+        HIP_CHECK(hipMemcpyAsync(zj, vj, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+      }
+      matvec(zj, w);
+      // two passes of classical Gram-Schmidt against v_0 .. v_j
+      launch_gemm_tn(V, N, w, N, N, j + 1, 1, h1, j + 1, false, f->gpart.p, s);
+      launch_sub_xw(V, N, N, j + 1, h1, w, N, 1, s);
+      launch_gemm_tn(V, N, w, N, N, j + 1, 1, h2, j + 1, false, f->gpart.p, s);
+      launch_sub_xw(V, N, N, j + 1, h2, w, N, 1, s);
+      dot_to(w, w, nrm);
+      launch_scale_rsqrt(w, N, nrm, V + (size_t)(j + 1) * N, s);
+      HIP_CHECK(hipMemcpyAsync(hb, h1, sizeof(double) * (2 * (m + 1) + 1), hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipStreamSynchronize(s));
+      ++it;
+      // Hessenberg column j, then the rotations of the previous columns and a new one
+      double* hc = H.data() + (size_t)j * (m + 1);
+      for (int i = 0; i <= j; ++i) hc[i] = hb[i] + hb[(m + 1) + i];
+      hc[j + 1] = std::sqrt(std::max(0.0, hb[2 * (m + 1)]));
+      for (int i = 0; i < j; ++i) {
+        const double a = hc[i], b = hc[i + 1];
+        hc[i] = cs[i] * a + sn[i] * b;
+        hc[i + 1] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = hc[j], b = hc[j + 1];
+      const double r = std::hypot(a, b);
+      cs[j] = r > 0 ? a / r : 1.0;
+      sn[j] = r > 0 ? b / r : 0.0;
+      hc[j] = r;
+      hc[j + 1] = 0.0;
+      gam[j + 1] = -sn[j] * gam[j];
+      gam[j] = cs[j] * gam[j];
+      est = std::fabs(gam[j + 1]);
+      if (*rel1 < 0) *rel1 = est / gn;
+      if (est <= tol * gn || !(r > 0)) {
+        ++j;
+        break;
+      }
+    }
+    // y = H(0:j, 0:j)^{-1} gam(0:j); tau += Z y
+    if (j > 0) {
+      std::vector<double> y(j);
+      for (int i = j - 1; i >= 0; --i) {
+        double v = gam[i];
+        for (int c = i + 1; c < j; ++c) v -= H[(size_t)c * (m + 1) + i] * y[c];
+        y[i] = H[(size_t)i * (m + 1) + i] != 0.0 ? v / H[(size_t)i * (m + 1) + i] : 0.0;
+      }
+      double* hy = (double*)ctx_pinned(ctx, sizeof(double) * j);
+      for (int i = 0; i < j; ++i) hy[i] = -y[i];
+      HIP_CHECK(hipMemcpyAsync(f->gy.p, hy, sizeof(double) * j, hipMemcpyHostToDevice, s));
+      ctx_pinned_used(ctx, s);
+      launch_sub_xw(Z, N, N, j, f->gy.p, tau, N, 1, s);
+    }
+    // true residual r = g - A tau, its norm; restart from it if needed
+    {
+      PhaseTimer t(ctx, "a8_residual", 26.0 * (double)f->Nn * f->Nn, 0.0);
+      launch_residual(f->d_new.p, f->Nn, g, tau, w, 1, f->part.p, nullptr, s);
+    }
+    dot_to(w, w, nrm + 2);
+    HIP_CHECK(hipMemcpyAsync(hb, nrm + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    beta = std::sqrt(std::max(0.0, hb[0]));
+    *rel = beta / gn;
+    if (!(beta > tol * gn) || it >= maxit) break;
+    launch_scale_rsqrt(w, N, nrm + 2, V, s);
+  }
+  return it;
+}
+
 void copy_nodes_out(const std::vector<NodeRec>& nd, double* xy, double* nrm, double* wts, int64_t* n_nodes) {
   if (!n_nodes) RW_THROW(RW_EINVAL, "n_nodes is null");
   const int64_t n = (int64_t)nd.size();
@@ -1025,6 +1173,9 @@ int rw_ctx_create(rw_ctx** out, int device, void* hip_stream, size_t hbm_budget_
   c->opt.far_field = 1;
   c->opt.test_singular = 0;
   c->opt.hbs_merge = 2;
+  c->opt.solver = RW_SOLVE_IR;
+  c->opt.gmres_restart = 30;
+  c->opt.gmres_precond = 1;
   int rc = guarded(c.get(), [&]() {
     hipDeviceProp_t prop;
     HIP_CHECK(hipGetDeviceProperties(&prop, device));
@@ -1066,6 +1217,8 @@ int rw_set_options(rw_ctx* ctx, const rw_options* opt) {
       RW_THROW(RW_EINVAL, "bad refinement options");
     if (opt->test_singular < 0 || opt->test_singular > 2) RW_THROW(RW_EINVAL, "test_singular outside 0..2");
     if (opt->hbs_merge < 1 || opt->hbs_merge > 4) RW_THROW(RW_EINVAL, "hbs_merge outside 1..4");
+    if (opt->solver != RW_SOLVE_IR && opt->solver != RW_SOLVE_GMRES) RW_THROW(RW_EINVAL, "unknown solver");
+    if (opt->gmres_restart < 1 || opt->gmres_restart > 256) RW_THROW(RW_EINVAL, "gmres_restart outside 1..256");
     if (opt->sketch_cols != 32 && opt->sketch_cols != 64 && opt->sketch_cols != 96 && opt->sketch_cols != 128)
       RW_THROW(RW_EINVAL, "sketch_cols must be 32, 64, 96 or 128");
     ctx->opt = *opt;
@@ -1276,9 +1429,34 @@ int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau, rw_solve
     if (f->fail_rc != RW_OK) RW_THROW(f->fail_rc, f->fail_msg);
     const double t0 = wall_ms();
     hipStream_t s = f->ctx->stream;
+    const rw_options& o = f->ctx->opt;
+    if (o.solver == RW_SOLVE_GMRES) {
+      const int64_t N = 2 * f->Nn;
+      int its = 0;
+      double worst = 0.0, worst1 = 0.0;
+      for (int c = 0; c < nrhs; ++c) {
+        double rel = 0.0, rel1 = 0.0;
+        its += gmres_column(f, g + (size_t)c * N, tau + (size_t)c * N, o.ir_tol, std::max(1, o.ir_maxit), &rel,
+                            &rel1);
+        worst = std::max(worst, std::isfinite(rel) ? rel : INFINITY);
+        worst1 = std::max(worst1, rel1);
+      }
+      prof_flush(f->ctx);
+      f->info.ir_iters = its;
+      f->info.resid = worst;
+      f->info.t_solve_ms = wall_ms() - t0;
+      if (sinfo) {
+        sinfo->ir_iters = its;
+        sinfo->k = f->k;
+        sinfo->resid = worst;
+        sinfo->resid_direct = worst1;
+        sinfo->t_solve_ms = f->info.t_solve_ms;
+      }
+      if (!(worst <= o.ir_tol)) RW_THROW(RW_ENOCONV, "GMRES stopped at relative residual " + std::to_string(worst));
+      return;
+    }
     refined_ensure_ws(f, nrhs);
     woodbury_apply(f, g, tau, nrhs, false);
-    const rw_options& o = f->ctx->opt;
     int it = 0;
     double worst = 0;
     // read-back area: the latest norms, then those of the direct solution
