@@ -55,9 +55,10 @@ int64_t hbs_ws1_plan(const HbsDev& w, double* base, HbsWs1& ws);
 void hbs_dev_apply1_at(const HbsDev& w, const double* b, double* x, bool use_f32, double* base, hipStream_t s);
 
 // Passes over the generators that one apply of nrhs right-hand sides makes
-// (8 columns per pass on the vector path, 64 from 40 columns on the matrix
-// cores): the algorithmic generator bytes are passes * entries * width.
-double hbs_gen_passes(int nrhs);
+// (8 columns per pass on the vector path, 64 on the matrix cores: from 40
+// columns with FP64 generators, from 16 with FP32 ones): the algorithmic
+// generator bytes are passes * entries * width.
+double hbs_gen_passes(int nrhs, bool f32 = false);
 
 // Pack a host-built inverse into HBM.
 void hbs_upload(rw_ctx* ctx, const HbsInverse& H, bool with_f32, HbsDev& out);

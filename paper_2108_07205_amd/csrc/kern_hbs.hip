@@ -19,7 +19,10 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kRows = 64;    // rows per workgroup (one per lane)
 constexpr int kUnroll = 16;  // loads in flight per lane
-constexpr int kMfmaMin = 40;  // right-hand sides from which the slab product runs on MFMA (measured crossover)
+constexpr int kMfmaMin = 40;    // right-hand sides from which the FP64 slab product runs on MFMA (measured crossover)
+constexpr int kMfmaMin32 = 16;  // the same for FP32 generators (FP32 matrix cores)
+template <typename T>
+constexpr int mfma_min() { return sizeof(T) == 4 ? kMfmaMin32 : kMfmaMin; }
 
 // The first kUnroll entries of row `row` in the column quarter w of M (R x
 // C, ld R), loaded before the input slice is staged so that the two loads'
@@ -247,6 +250,64 @@ __device__ __forceinline__ void slab_mfma(const T* __restrict__ M, int R, int C,
     }
 }
 
+// FP32 generators on the FP32 matrix cores (v_mfma_f32_16x16x4f32, FP32
+// accumulation): the same tiling as slab_mfma, the input tile rounded to
+// FP32 as it is staged; the products return to the FP64 vectors.  This is
+// the mixed-precision apply; FP64 iterative refinement recovers the digits.
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+template <typename Load, typename Emit>
+__device__ __forceinline__ void slab_mfma_f32(const float* __restrict__ M, int R, int C, int slab, int r0, int nr,
+                                              float (*Bs)[kMR + 4], Load load, Emit emit) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, i16 = lane & 15, k4 = lane >> 4;
+  const int arow = slab * kRows + w * 16 + i16;
+  const bool aval = arow < R;
+  const float* mp = M + (aval ? arow : 0);
+  float4_t acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = (float4_t){0.f, 0.f, 0.f, 0.f};
+  float an[4], bn[4];
+  auto fetch = [&](int c0) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kc = c0 + ks * 4 + k4;
+      an[ks] = (aval && kc < C) ? mp[(int64_t)kc * R] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + kThreads * u, kk = e & 15, c = e >> 4;
+      bn[u] = (c0 + kk < C && c < nr) ? (float)load(c0 + kk, r0 + c) : 0.f;
+    }
+  };
+  if (C > 0) fetch(0);
+  for (int c0 = 0; c0 < C; c0 += 16) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + kThreads * u;
+      Bs[e & 15][e >> 4] = bn[u];
+    }
+    float a[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) a[ks] = an[ks];
+    __syncthreads();
+    if (c0 + 16 < C) fetch(c0 + 16);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], Bs[ks * 4 + k4][cb * 16 + i16], acc[cb], 0, 0, 0);
+  }
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      // v_mfma_f32_16x16x4f32: item r of lane l holds D[4 (l / 16) + r][l % 16]
+      const int row = slab * kRows + w * 16 + 4 * k4 + r, c = cb * 16 + i16;
+      if (row < R && c < nr) emit(row, r0 + c, (double)acc[cb][r]);
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void hbs_up_mfma_kernel(
     int rbmax, const int* __restrict__ nin, const int* __restrict__ kk, const int64_t* __restrict__ in_off,
@@ -280,6 +341,43 @@ __global__ __launch_bounds__(kThreads) void hbs_down_mfma_kernel(
   const int r0 = blockIdx.y * kMR, nr = min(kMR, nrhs - r0);
   const int64_t io = in_off[j], ko = kout_off[j];
   slab_mfma<T>(
+      gen + e_off[j], n, k, rb, r0, nr, Bs, [&](int col, int c) { return xhat[ko + col + (int64_t)c * ld_xh]; },
+      [&](int row, int c, double v) {
+        out[io + row + (int64_t)c * ld_out] = v + gb[io + row + (int64_t)c * ld_gb];
+      });
+}
+
+__global__ __launch_bounds__(kThreads) void hbs_up_mfma32_kernel(
+    int rbmax, const int* __restrict__ nin, const int* __restrict__ kk, const int64_t* __restrict__ in_off,
+    const int64_t* __restrict__ kout_off, const int64_t* __restrict__ up_off, const float* __restrict__ gen,
+    const double* __restrict__ in, int64_t ld_in, double* __restrict__ bhat, int64_t ld_bhat,
+    double* __restrict__ gb, int64_t ld_gb, int nrhs) {
+  __shared__ float Bs[16][kMR + 4];
+  const int j = blockIdx.x / rbmax, rb = blockIdx.x - j * rbmax;
+  const int n = nin[j], k = kk[j], R = k + n;
+  if (rb * kRows >= R) return;
+  const int r0 = blockIdx.y * kMR, nr = min(kMR, nrhs - r0);
+  const int64_t io = in_off[j], ko = kout_off[j];
+  slab_mfma_f32(
+      gen + up_off[j], R, n, rb, r0, nr, Bs, [&](int col, int c) { return in[io + col + (int64_t)c * ld_in]; },
+      [&](int row, int c, double v) {
+        if (row < k) bhat[ko + row + (int64_t)c * ld_bhat] = v;
+        else gb[io + (row - k) + (int64_t)c * ld_gb] = v;
+      });
+}
+
+__global__ __launch_bounds__(kThreads) void hbs_down_mfma32_kernel(
+    int rbmax, const int* __restrict__ nin, const int* __restrict__ kk, const int64_t* __restrict__ in_off,
+    const int64_t* __restrict__ kout_off, const int64_t* __restrict__ e_off, const float* __restrict__ gen,
+    const double* __restrict__ xhat, int64_t ld_xh, const double* __restrict__ gb, int64_t ld_gb,
+    double* __restrict__ out, int64_t ld_out, int nrhs) {
+  __shared__ float Bs[16][kMR + 4];
+  const int j = blockIdx.x / rbmax, rb = blockIdx.x - j * rbmax;
+  const int n = nin[j], k = kk[j];
+  if (rb * kRows >= n) return;
+  const int r0 = blockIdx.y * kMR, nr = min(kMR, nrhs - r0);
+  const int64_t io = in_off[j], ko = kout_off[j];
+  slab_mfma_f32(
       gen + e_off[j], n, k, rb, r0, nr, Bs, [&](int col, int c) { return xhat[ko + col + (int64_t)c * ld_xh]; },
       [&](int row, int c, double v) {
         out[io + row + (int64_t)c * ld_out] = v + gb[io + row + (int64_t)c * ld_gb];
@@ -465,17 +563,21 @@ void up_impl(const HbsLevelDev& L, const T* gen, const double* in, int64_t ld_in
              int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s) {
   if (!L.nnodes || nrhs <= 0) return;
   // generators streamed once per pass of up to 8 right-hand sides
-  const double passes = hbs_gen_passes(nrhs);
+  const double passes = hbs_gen_passes(nrhs, sizeof(T) == 4);
   KernelTimer kt("hbs_up_kernel", 2.0 * L.up_entries * nrhs, sizeof(T) * (double)L.up_entries * passes, s);
   if (nrhs == 1) {
     up_launch<T, 1>(L, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs, s);
-  } else if (nrhs < kMfmaMin) {
+  } else if (nrhs < mfma_min<T>()) {
     up_launch<T, 8>(L, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs, s);
   } else {
     const int rbmax = (L.max_k + L.max_nin + kRows - 1) / kRows;
-    hipLaunchKernelGGL((hbs_up_mfma_kernel<T>), dim3(L.nnodes * rbmax, (nrhs + kMR - 1) / kMR), dim3(kThreads), 0, s,
-                       rbmax, L.nin, L.k, L.in_off, L.kout_off, L.up_off, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb,
-                       nrhs);
+    const dim3 grid(L.nnodes * rbmax, (nrhs + kMR - 1) / kMR);
+    if constexpr (sizeof(T) == 4)
+      hipLaunchKernelGGL(hbs_up_mfma32_kernel, grid, dim3(kThreads), 0, s, rbmax, L.nin, L.k, L.in_off, L.kout_off,
+                         L.up_off, (const float*)gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs);
+    else
+      hipLaunchKernelGGL((hbs_up_mfma_kernel<T>), grid, dim3(kThreads), 0, s, rbmax, L.nin, L.k, L.in_off, L.kout_off,
+                         L.up_off, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs);
   }
   KERNEL_CHECK("hbs_up");
 }
@@ -494,17 +596,21 @@ template <typename T>
 void down_impl(const HbsLevelDev& L, const T* gen, const double* xhat, int64_t ld_xh, const double* gb,
                int64_t ld_gb, double* out, int64_t ld_out, int nrhs, hipStream_t s) {
   if (!L.nnodes || nrhs <= 0) return;
-  const double passes = hbs_gen_passes(nrhs);
+  const double passes = hbs_gen_passes(nrhs, sizeof(T) == 4);
   KernelTimer kt("hbs_down_kernel", 2.0 * L.e_entries * nrhs, sizeof(T) * (double)L.e_entries * passes, s);
   if (nrhs == 1) {
     down_launch<T, 1>(L, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs, s);
-  } else if (nrhs < kMfmaMin) {
+  } else if (nrhs < mfma_min<T>()) {
     down_launch<T, 8>(L, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs, s);
   } else {
     const int rbmax = (L.max_nin + kRows - 1) / kRows;
-    hipLaunchKernelGGL((hbs_down_mfma_kernel<T>), dim3(L.nnodes * rbmax, (nrhs + kMR - 1) / kMR), dim3(kThreads), 0,
-                       s, rbmax, L.nin, L.k, L.in_off, L.kout_off, L.e_off, gen, xhat, ld_xh, gb, ld_gb, out, ld_out,
-                       nrhs);
+    const dim3 grid(L.nnodes * rbmax, (nrhs + kMR - 1) / kMR);
+    if constexpr (sizeof(T) == 4)
+      hipLaunchKernelGGL(hbs_down_mfma32_kernel, grid, dim3(kThreads), 0, s, rbmax, L.nin, L.k, L.in_off, L.kout_off,
+                         L.e_off, (const float*)gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs);
+    else
+      hipLaunchKernelGGL((hbs_down_mfma_kernel<T>), grid, dim3(kThreads), 0, s, rbmax, L.nin, L.k, L.in_off,
+                         L.kout_off, L.e_off, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs);
   }
   KERNEL_CHECK("hbs_down");
 }
@@ -563,9 +669,9 @@ void launch_parts_reduce(const double* in, int64_t stride, int np, int64_t n, do
   KERNEL_CHECK("parts_reduce");
 }
 
-double hbs_gen_passes(int nrhs) {
+double hbs_gen_passes(int nrhs, bool f32) {
   if (nrhs <= 1) return 1.0;
-  return nrhs < kMfmaMin ? (double)((nrhs + 7) / 8) : (double)((nrhs + kMR - 1) / kMR);
+  return nrhs < (f32 ? kMfmaMin32 : kMfmaMin) ? (double)((nrhs + 7) / 8) : (double)((nrhs + kMR - 1) / kMR);
 }
 
 void launch_hbs_up(const HbsLevelDev& L, const double* gen, const double* in, int64_t ld_in, double* bhat,

@@ -565,7 +565,8 @@ void woodbury_ref_apply(rw_refined* f, int nrhs) {
   rw_wall* w = f->wall;
   const int64_t M = 2 * f->Next;
   const double gb = (w->precision == RW_F32 ? 4.0 : 8.0) * w->stats.gen_entries;
-  PhaseTimer t(f->ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * nrhs, gb * hbs_gen_passes(nrhs));
+  PhaseTimer t(f->ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * nrhs,
+               gb * hbs_gen_passes(nrhs, w->precision == RW_F32));
   hbs_apply(w, f->gext.p, M, f->y.p, M, nrhs, w->precision == RW_F32);
 }
 
@@ -1537,7 +1538,8 @@ void batch_woodbury(rw_wall* w, const std::vector<rw_refined*>& fs, const std::v
   }
   {
     const double gb = (w->precision == RW_F32 ? 4.0 : 8.0) * w->stats.gen_entries;
-    PhaseTimer t(w->ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * C, gb * hbs_gen_passes((int)C));
+    PhaseTimer t(w->ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * C,
+                 gb * hbs_gen_passes((int)C, w->precision == RW_F32));
     hbs_apply(w, w->bat_in.p, Mo, w->bat_out.p, Mo, (int)C, w->precision == RW_F32);
   }
   c0 = 0;

@@ -204,7 +204,10 @@ def golden_cases() -> dict:
     * ``wrap_16x4``: 16 consecutive panels across theta = 0 (1021..1023,
       0..12), 4 levels, Stokeslets of seed 3;
     * ``near4x6``: the 4 panels nearest a seeded point at 1e-3, 6 levels
-      (64 children each)."""
+      (64 children each);
+    * ``pattern32x4``: the refinement pattern of the 65536-node workload
+      (32 panels nearest a point at 1e-3, 4 levels) on this wall, where the
+      dense oracle still fits (48128 unknowns)."""
     wrap_ids = [1021, 1022, 1023] + list(range(13))
     return {
         "config2_seed0": config2(seed=0),
@@ -212,4 +215,5 @@ def golden_cases() -> dict:
         "wrap_16x4": small_problem(n_panels=1024, ids=wrap_ids, levels=[4] * 16,
                                    n_stokeslets=16, seed=3),
         "near4x6": near_point_problem("star1024_refine4x6", 1024, 4, 6, 1e-3, 16, 1, seed=5),
+        "pattern32x4": near_point_problem("star1024_refine32x4", 1024, 32, 4, 1e-3, 16, 1, seed=0),
     }
