@@ -478,8 +478,129 @@ def main():
                 "batch_rhs_per_s": nrhs / t_bat, "speedup_vs_sequential": t_seq / t_bat,
                 "max_resid": max(i["resid"] for i in infos), "batch_vs_sequential_rel_diff": agree}
 
+    def config4_mixed(reps: int = 3):
+        """The 65536-node wall (4096 panels; 32 panels nearest a seeded point
+        refined 4 levels; 32 Stokeslet right-hand sides): FP64 generators
+        against FP32 generators on the FP32 matrix cores, both refined in
+        FP64 to the same residual (1e-13; with ||A^-1|| <= 100 an error
+        below 1e-11), and the applies of the reference inverse alone (1 and
+        32 right-hand sides, HIP events, warm)."""
+        p4 = W.config4(seed=0)
+        out = {"workload": "star4096_refine32x4", "nrhs": 32}
+        for prec, name in ((rw.RW_F64, "fp64"), (rw.RW_F32, "fp32_generators")):
+            w4 = rw.Wall(ctx, 4096, precision=prec)
+            st4 = w4.stats()
+            ref4 = w4.refine(p4.refinement.panel_ids, p4.refinement.levels)
+            g4 = torch.stack([ref4.stokeslet_rhs(q.z, q.f) for q in p4.rhs]).contiguous()
+            tau4 = torch.empty_like(g4)
+            rw.rw_solve(ctx.h, ref4.h, g4, tau4, ref4.n_unknowns)
+            ts, its, res = [], 0, 0.0
+            for _ in range(reps):
+                inf = {}
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rw.rw_solve(ctx.h, ref4.h, g4, tau4, ref4.n_unknowns, info=inf)
+                ts.append((time.perf_counter() - t0) * 1e3)
+                its, res = inf["ir_iters"], inf["resid"]
+            n4 = 2 * w4.n_nodes
+            rates = {}
+            for nr in (1, 32):
+                b4 = torch.randn(nr, n4, dtype=torch.float64, device="cuda")
+                x4 = torch.empty_like(b4)
+                for _ in range(3):
+                    rw.rw_hbs_apply(ctx.h, w4.h, b4, x4, n4)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(10):
+                    rw.rw_hbs_apply(ctx.h, w4.h, b4, x4, n4)
+                e1.record()
+                e1.synchronize()
+                us = e0.elapsed_time(e1) * 100.0
+                width = 4 if prec == rw.RW_F32 else 8
+                gen_b = width * st4["gen_entries"]
+                rates[f"apply_{nr}rhs_us"] = us
+                rates[f"apply_{nr}rhs_GBps_per_pass"] = gen_b / (us * 1e-6) / 1e9
+            out[name] = {"solve_32rhs_ms": float(np.median(ts)), "corrections": its, "resid": res,
+                         "refined_nodes": int(ref4.n_nodes), "k": int(ref4.info()["k"]),
+                         "gen_bytes": (4 if prec == rw.RW_F32 else 8) * st4["gen_entries"], **rates}
+            ref4.close()
+            w4.close()
+        out["speedup_solve"] = out["fp64"]["solve_32rhs_ms"] / out["fp32_generators"]["solve_32rhs_ms"]
+        out["speedup_apply_32rhs"] = out["fp64"]["apply_32rhs_us"] / out["fp32_generators"]["apply_32rhs_us"]
+        out["speedup_apply_1rhs"] = out["fp64"]["apply_1rhs_us"] / out["fp32_generators"]["apply_1rhs_us"]
+        return out
+
+    def serving(n_req: int = 48, slots: int = 4):
+        """Serving against one resident 65536-node wall (FP32 generators,
+        FP64 refinement to ||r||/||g|| <= 1e-10, i.e. an error below 1e-8
+        with ||A^-1|| <= 100): n_req requests with Poisson arrivals at
+        2000 req/s, each refining 1..64 contiguous panels by 1..5 levels with
+        1..16 right-hand sides, submitted at their arrival times to a server
+        of `slots` slots; latency = completion - arrival.  Baseline: the same
+        requests solved one after the other by plain FP64 rw_refine +
+        rw_solve on the wall's own ctx (same residual tolerance)."""
+        reqs = W.serving_requests(n_req, rate=2000.0, seed=11, n_panels=4096)
+        old = ctx.options()
+        ctx.set_options(ir_tol=1e-10)
+        out = {"requests": n_req, "offered_rate_per_s": 2000.0, "slots": slots,
+               "rhs_total": int(sum(len(r.problem.rhs) for r in reqs)),
+               "refined_nodes_range": None, "gate": "||g - A tau||/||g|| <= 1e-10 (FP64 residual)"}
+        try:
+            w32 = rw.Wall(ctx, 4096, precision=rw.RW_F32)
+            sv = rw.Server(w32, slots=slots)
+            t0 = time.perf_counter()
+            ids = []
+            for r in reqs:
+                dt = t0 + r.t_arrival - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                p5 = r.problem
+                ids.append(sv.submit(p5.refinement.panel_ids, p5.refinement.levels, [(q.z, q.f) for q in p5.rhs]))
+            infos = []
+            for rid in ids:
+                _, inf = sv.wait(rid, check=False)
+                infos.append(inf)
+            t_end = time.perf_counter()
+            sv.close()
+            w32.close()
+            lat = np.array([inf["t_queue_ms"] + inf["t_run_ms"] for inf in infos])
+            ok = [inf["status"] == rw.RW_OK and inf["resid"] <= 1e-10 for inf in infos]
+            out["refined_nodes_range"] = [int(min(i["n_nodes"] for i in infos)), int(max(i["n_nodes"] for i in infos))]
+            out["served"] = {"solves_per_s": sum(ok) / (t_end - t0), "passed": int(sum(ok)),
+                             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                             "run_ms_p50": float(np.median([i["t_run_ms"] for i in infos])),
+                             "max_resid": float(max(i["resid"] for i in infos)),
+                             "max_ir_iters": int(max(i["ir_iters"] for i in infos)),
+                             "slots_used": sorted({int(i["slot"]) for i in infos})}
+            # baseline: plain FP64, one request after the other on the wall's ctx
+            w64 = rw.Wall(ctx, 4096)
+            torch.cuda.synchronize()
+            tb0 = time.perf_counter()
+            seq, okb = [], 0
+            for r in reqs:
+                p5 = r.problem
+                t1 = time.perf_counter()
+                ref5 = w64.refine(p5.refinement.panel_ids, p5.refinement.levels)
+                g5 = torch.stack([ref5.stokeslet_rhs(q.z, q.f) for q in p5.rhs]).contiguous()
+                inf = {}
+                rc = rw.rw_solve(ctx.h, ref5.h, g5, torch.empty_like(g5), ref5.n_unknowns, check=False, info=inf)
+                ref5.close()
+                seq.append((time.perf_counter() - t1) * 1e3)
+                okb += int(rc == rw.RW_OK and inf["resid"] <= 1e-10)
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - tb0
+            w64.close()
+            out["sequential_fp64"] = {"solves_per_s": okb / tb, "passed": okb, "p50_solve_ms": float(np.median(seq)),
+                                      "p99_solve_ms": float(np.percentile(seq, 99))}
+            out["speedup_vs_sequential_fp64"] = out["served"]["solves_per_s"] / out["sequential_fp64"]["solves_per_s"]
+        finally:
+            ctx.set_options(ir_tol=old["ir_tol"])
+        return out
+
     side = {"hbs_apply_1rhs": hbs_apply_rates(wall)}
     if args.extra_steps > 0:
+        side["config4_mixed_precision"] = config4_mixed()
+        side["serving_config5"] = serving()
         side["batched_fp64"] = batched(wall, 16)
         side["fp64_resident_factors"] = rhs_rate(wall, args.extra_steps)
         w32 = rw.Wall(ctx, 1024, precision=rw.RW_F32)

@@ -237,6 +237,17 @@ int rw_hbs_apply_noalloc(rw_wall* wall, const double* b_dev, double* x_dev);
  * itself.  rw_refined_free waits for the handle's device work. */
 int rw_refine(rw_wall* wall, const int32_t* panel_ids_host, const int32_t* levels_host,
               int32_t n_sel, double q_tol, rw_refined** out);
+/* rw_refine on another ctx of the wall's device: the refinement's device
+ * work, memory and later calls (rw_solve, rw_residual, rw_stokeslet_rhs,
+ * rw_refined_free) use ctx's stream and allocator and ctx's own workspace for
+ * applies of the wall's reference inverse, which is only read.  Several
+ * host threads, each with its own ctx, can thus refine and solve against
+ * one resident wall at once (the wall's own ctx must not be used meanwhile
+ * for rw_hbs_apply or rw_solve_batch, whose workspace is the wall's).  The
+ * wall must outlive the handle; ctx must outlive the handle.  Errors as
+ * rw_refine, and RW_EINVAL when ctx is on another device. */
+int rw_refine_on(rw_ctx* ctx, rw_wall* wall, const int32_t* panel_ids_host, const int32_t* levels_host,
+                 int32_t n_sel, double q_tol, rw_refined** out);
 /* Coarsen: give panel_ids_host[i] back its reference discretization and
  * redo the pre-computation (with the handle's q_tol) for the remaining refinement (coarsening all
  * refined panels returns the reference problem).  Ids that are not refined
@@ -282,7 +293,8 @@ int rw_solve(rw_refined* ref, const double* g_dev, int32_t nrhs, double* tau_dev
  * repeated handles, handles of different walls, nrhs <= 0), RW_ENOMEM,
  * RW_ENOCONV (all results written; at least one instance stopped above the
  * tolerance), RW_ESINGULAR (an instance's deferred refinement checks
- * failed), RW_EDEVICE. */
+ * failed), RW_EDEVICE.  The instances must have been refined on the wall's
+ * own ctx (rw_refine), whose stream runs the batch. */
 int rw_solve_batch(rw_refined* const* inst, int32_t n_inst, const double* const* g_dev,
                    const int32_t* nrhs, double* const* tau_dev, rw_info* info_host);
 
@@ -299,6 +311,52 @@ int rw_residual(rw_refined* ref, const double* g_dev, const double* tau_dev,
  * ctx's stream (not synchronized).  Errors: RW_EINVAL, RW_EDEVICE. */
 int rw_stokeslet_rhs(rw_refined* ref, const double* z_host, const double* f_host,
                      int32_t n_src, double* g_dev);
+
+/* ---- serving (the time-stepping workflow of Sec. 5.3 served to many
+ *      independent requests against one resident wall) ----------------- */
+
+typedef struct rw_server rw_server;
+
+/* Outcome of one served request. */
+typedef struct {
+  int32_t status;            /* RW_OK or the request's error code (RW_ENOCONV: result written) */
+  int32_t slot;              /* slot that ran it */
+  int32_t ir_iters;          /* refinement corrections (or GMRES iterations) */
+  int32_t k;                 /* Woodbury rank */
+  int64_t n_nodes;           /* refined nodes N_n */
+  double resid;              /* max over columns of ||g - A_nn tau|| / ||g|| */
+  double t_queue_ms;         /* submission to start */
+  double t_run_ms;           /* start to end (refine, data, solve, copy back) */
+} rw_request_info;
+
+/* A server of `slots` worker threads (1..16), each with a ctx and stream of
+ * its own (the options of `ctx` copied), that run whole requests against
+ * `wall` (n_panels reference panels; built on ctx, resident, only read):
+ * rw_refine_on, Stokeslet data, rw_solve, result copied back.  Requests
+ * leave the queue in order as soon as a slot is free and the device memory
+ * they are estimated to need fits hbm_budget_bytes (0: no cap) beside the
+ * requests in flight, so the device work of up to `slots` requests of any
+ * size overlaps.  ctx and wall must outlive the server.  Errors: RW_EINVAL,
+ * RW_EDEVICE, or a slot ctx's creation error; rw_server_error(NULL) has the
+ * message. */
+int rw_server_create(rw_ctx* ctx, rw_wall* wall, int32_t n_panels, int32_t slots, size_t hbm_budget_bytes,
+                     rw_server** out);
+/* Queue a request: refine panel_ids_host[i] by levels_host[i] and solve for
+ * nrhs right-hand sides, column r the velocity of the n_src Stokeslets
+ * z_host / f_host rows r*n_src .. r*n_src + n_src - 1 (x, y pairs; copied
+ * before return).  *id: the request's ticket for rw_server_wait.  Errors:
+ * RW_EINVAL, RW_ENOMEM (the request could never fit the budget). */
+int rw_server_submit(rw_server* sv, const int32_t* panel_ids_host, const int32_t* levels_host, int32_t n_sel,
+                     const double* z_host, const double* f_host, int32_t n_src, int32_t nrhs, int64_t* id);
+/* Block until request `id` is done; copy its tau (2 N_n x nrhs column-major,
+ * refined node order) to tau_host (NULL: discard; cap: doubles available)
+ * and its outcome to info (NULL: skip).  Returns the request's status, or
+ * RW_EINVAL for an unknown ticket or a too small tau_host. */
+int rw_server_wait(rw_server* sv, int64_t id, double* tau_host, int64_t cap, rw_request_info* info);
+/* Waits for the requests still queued or running, then frees the slots. */
+void rw_server_destroy(rw_server* sv);
+/* Last error message of sv (NULL: of the last failed rw_server_create). */
+const char* rw_server_error(const rw_server* sv);
 
 #ifdef __cplusplus
 }

@@ -27,7 +27,7 @@ __all__ = [
     "rw_refined_free", "rw_refined_info", "rw_nodes", "rw_solve", "rw_residual", "rw_stokeslet_rhs",
     "rw_ctx_trim", "rw_profile_enable", "rw_profile_reset", "rw_profile_json",
     "RW_OK", "RW_EINVAL", "RW_ENOMEM", "RW_ESINGULAR", "RW_ENOCONV", "RW_EDEVICE", "RW_F64", "RW_F32",
-    "RW_BF16", "RW_SOLVE_IR", "RW_SOLVE_GMRES", "rw_solve_batch",
+    "RW_BF16", "RW_SOLVE_IR", "RW_SOLVE_GMRES", "rw_solve_batch", "rw_refine_on", "Server",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -72,6 +72,12 @@ class rw_solve_info(ctypes.Structure):
                 ("resid_direct", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
 
 
+class rw_request_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("slot", ctypes.c_int32), ("ir_iters", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("n_nodes", ctypes.c_int64), ("resid", ctypes.c_double),
+                ("t_queue_ms", ctypes.c_double), ("t_run_ms", ctypes.c_double)]
+
+
 class rw_wall_stats(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int64), ("n_levels", ctypes.c_int32), ("max_rank", ctypes.c_int32),
                 ("gen_entries", ctypes.c_int64), ("gen_bytes_f64", ctypes.c_int64),
@@ -112,6 +118,13 @@ _SIGS = {
     "rw_solve_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
     "rw_residual": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P]),
     "rw_stokeslet_rhs": (ctypes.c_int, [_P, _DP, _DP, ctypes.c_int32, _P]),
+    "rw_refine_on": (ctypes.c_int, [_P, _P, _I32P, _I32P, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_P)]),
+    "rw_server_create": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER(_P)]),
+    "rw_server_submit": (ctypes.c_int, [_P, _I32P, _I32P, ctypes.c_int32, _DP, _DP, ctypes.c_int32, ctypes.c_int32,
+                                        _I64P]),
+    "rw_server_wait": (ctypes.c_int, [_P, ctypes.c_int64, _DP, ctypes.c_int64, ctypes.POINTER(rw_request_info)]),
+    "rw_server_destroy": (None, [_P]),
+    "rw_server_error": (ctypes.c_char_p, [_P]),
 }
 EXPORTED_SYMBOLS = tuple(_SIGS)
 
@@ -296,6 +309,18 @@ def rw_refine(ctx, wall, panel_ids: Sequence[int], levels: Sequence[int], q_tol:
     return out
 
 
+def rw_refine_on(ctx, wall, panel_ids: Sequence[int], levels: Sequence[int], q_tol: float = 0.0):
+    """rw_refine on ctx (its stream and memory) against a wall built on another ctx."""
+    ids = np.ascontiguousarray(panel_ids, dtype=np.int32)
+    lev = np.ascontiguousarray(levels, dtype=np.int32)
+    if ids.shape != lev.shape:
+        raise ValueError("panel_ids and levels differ in length")
+    out = _P()
+    _check(load_library().rw_refine_on(ctx, wall, ids.ctypes.data_as(_I32P), lev.ctypes.data_as(_I32P), ids.size,
+                                       q_tol, ctypes.byref(out)), ctx)
+    return out
+
+
 def rw_coarsen(ctx, ref, panel_ids: Sequence[int]):
     ids = np.ascontiguousarray(panel_ids, dtype=np.int32)
     _check(load_library().rw_coarsen(ref, ids.ctypes.data_as(_I32P), ids.size), ctx)
@@ -365,6 +390,67 @@ def rw_stokeslet_rhs(ctx, ref, z, f, g, n_unknowns: int):
     f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1, 2)
     pg, _ = _dev_ptr(g, "g", n_unknowns)
     _check(load_library().rw_stokeslet_rhs(ref, z.ctypes.data_as(_DP), f.ctypes.data_as(_DP), z.shape[0], pg), ctx)
+
+
+class Server:
+    """rw_server_*: requests (refinement + Stokeslet right-hand sides) served
+    by `slots` worker threads against one resident wall."""
+
+    def __init__(self, wall: "Wall", slots: int = 4, hbm_budget_bytes: int = 0):
+        self.wall = wall
+        self.h = None
+        out = _P()
+        rc = load_library().rw_server_create(wall.ctx.h, wall.h, wall.n_panels, slots, hbm_budget_bytes,
+                                             ctypes.byref(out))
+        if rc != RW_OK:
+            raise RwError(rc, load_library().rw_server_error(None).decode())
+        self.h = out
+        self._n = {}
+        wall._children.add(self)   # closed before its wall
+
+    def _err(self, rc):
+        if rc != RW_OK:
+            raise RwError(rc, load_library().rw_server_error(self.h).decode())
+
+    def submit(self, panel_ids, levels, stokeslets) -> int:
+        """Queue one request; `stokeslets`: one (z, f) pair of (n_src, 2)
+        arrays per right-hand side (all with the same n_src).  Returns its id."""
+        ids = np.ascontiguousarray(panel_ids, dtype=np.int32)
+        lev = np.ascontiguousarray(levels, dtype=np.int32)
+        z = np.ascontiguousarray(np.concatenate([np.asarray(s[0], np.float64).reshape(-1, 2) for s in stokeslets]))
+        f = np.ascontiguousarray(np.concatenate([np.asarray(s[1], np.float64).reshape(-1, 2) for s in stokeslets]))
+        nrhs = len(stokeslets)
+        n_src = z.shape[0] // nrhs
+        rid = ctypes.c_int64(0)
+        self._err(load_library().rw_server_submit(self.h, ids.ctypes.data_as(_I32P), lev.ctypes.data_as(_I32P),
+                                                  ids.size, z.ctypes.data_as(_DP), f.ctypes.data_as(_DP), n_src,
+                                                  nrhs, ctypes.byref(rid)))
+        q = self.wall.n_nodes // self.wall.n_panels
+        n_nodes = self.wall.n_nodes + sum(q * (2 ** int(l) - 1) for l in lev)
+        self._n[rid.value] = (2 * n_nodes, nrhs)
+        return rid.value
+
+    def wait(self, rid: int, check: bool = True):
+        """(tau of shape (nrhs, 2 N_n), info dict) of request rid."""
+        n2, nrhs = self._n.pop(rid)
+        tau = np.empty((nrhs, n2))
+        inf = rw_request_info()
+        rc = load_library().rw_server_wait(self.h, rid, tau.ctypes.data_as(_DP), tau.size, ctypes.byref(inf))
+        info = {f: getattr(inf, f) for f, _ in rw_request_info._fields_}
+        if check:
+            self._err(rc)
+        return tau, info
+
+    def close(self):
+        if self.h:
+            load_library().rw_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ----------------------------------------------------------------- classes

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <memory>
 #include <unordered_map>
 #include <stdexcept>
 #include <string>
@@ -56,6 +57,8 @@ struct PhaseStat {
 
 struct AuxWorker;
 
+struct HbsWork;
+
 struct rw_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -96,6 +99,10 @@ struct rw_ctx {
   // ctx; its device-side checks are still to be read), and the pinned word
   // its W pivot flag comes back to
   rw_refined* unsettled = nullptr;
+  // apply workspaces of HBS inverses owned by other ctxs that this ctx
+  // applies on its own stream (a wall's reference inverse used by a serving
+  // slot), keyed by the inverse
+  std::unordered_map<const void*, std::shared_ptr<HbsWork>> hbs_work;
   int* defer_pin = nullptr;
   // phase profiler (HIP events on `stream`)
   bool prof = false;

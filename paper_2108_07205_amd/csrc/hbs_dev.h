@@ -6,6 +6,21 @@
 #include "hbs_build.h"
 #include "kernels.h"
 
+// Apply workspace of one HBS inverse for one stream of work: the level
+// vectors of multi-RHS applies and the partial vectors of one-RHS applies,
+// allocated from `ctx` on first use.  An HbsDev holds one for its own ctx;
+// another ctx that applies the same (read-only) inverse on its own stream
+// brings its own (ctx_hbs_work), so that concurrent applies do not share it.
+struct HbsWork {
+  rw_ctx* ctx = nullptr;
+  DBuf<double> ws;
+  int ws_nrhs = 0;
+  int64_t ws_per_rhs = 0;        // doubles per right-hand side of ws (checked against the inverse)
+  std::vector<double*> U, GB, X;
+  DBuf<double> ws1;
+  int64_t ws1_need = 0;          // doubles of the one-RHS plan that ws1 was sized for
+};
+
 struct HbsDev {
   rw_ctx* ctx = nullptr;
   int L = 0, nroot = 0;
@@ -19,12 +34,7 @@ struct HbsDev {
   const int* d_nroot = nullptr;  // GPU build: the root size on the device (nroot is then a bound)
   int64_t entries = 0;           // sum of |E| + |F| + |G| + |G_root|
   int max_rank = 0;
-  // apply workspace
-  DBuf<double> ws;
-  int ws_nrhs = 0;
-  std::vector<double*> U, GB, X;
-  // one-RHS apply: its split partial vectors (hbs_ws1_plan) in ws1
-  DBuf<double> ws1;
+  HbsWork work;                  // apply workspace of the owning ctx
   // GPU build: node records and flags read back without a wait, checked by
   // hbs_gpu_finish (records: pinned host memory of the building context)
   struct Finish {
@@ -67,6 +77,9 @@ void hbs_upload(rw_ctx* ctx, const HbsInverse& H, bool with_f32, HbsDev& out);
 // another stream of the same device, ordered before s by the caller).
 void hbs_dev_apply(HbsDev& h, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32,
                    hipStream_t s);
+// The same with the workspace `wk` (its ctx allocates it on first use).
+void hbs_dev_apply_ws(const HbsDev& h, HbsWork& wk, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
+                      bool use_f32, hipStream_t s);
 
 // GPU build of the HBS inverse of the Nystrom matrix of one node set
 // (contiguous arcs, balanced binary tree with leaves of at most leaf_max

@@ -1816,19 +1816,20 @@ void hbs_upload(rw_ctx* ctx, const HbsInverse& H, bool with_f32, HbsDev& w) {
   w.max_rank = H.max_rank;
 }
 
-static void hbs_ensure_ws(HbsDev& w, int nrhs) {
-  if (nrhs <= w.ws_nrhs) return;
+static void hbs_ensure_ws(const HbsDev& w, HbsWork& wk, int nrhs) {
   int64_t tot = 0;
   for (int l = 1; l <= w.L; ++l) tot += w.K[l] + w.S[l];
   for (int l = 0; l < w.L; ++l) tot += w.S[l];
-  w.ws.alloc(w.ctx, (size_t)tot * nrhs);
-  w.U.assign(w.L + 1, nullptr);
-  w.GB.assign(w.L + 1, nullptr);
-  w.X.assign(w.L + 1, nullptr);
-  double* p = w.ws.p;
-  for (int l = 1; l <= w.L; ++l) { w.U[l] = p; p += w.K[l] * nrhs; w.GB[l] = p; p += w.S[l] * nrhs; }
-  for (int l = 0; l < w.L; ++l) { w.X[l] = p; p += w.S[l] * nrhs; }
-  w.ws_nrhs = nrhs;
+  if (nrhs <= wk.ws_nrhs && tot == wk.ws_per_rhs && (int)wk.U.size() == w.L + 1) return;
+  wk.ws.alloc(wk.ctx, (size_t)tot * nrhs);
+  wk.ws_per_rhs = tot;
+  wk.U.assign(w.L + 1, nullptr);
+  wk.GB.assign(w.L + 1, nullptr);
+  wk.X.assign(w.L + 1, nullptr);
+  double* p = wk.ws.p;
+  for (int l = 1; l <= w.L; ++l) { wk.U[l] = p; p += w.K[l] * nrhs; wk.GB[l] = p; p += w.S[l] * nrhs; }
+  for (int l = 0; l < w.L; ++l) { wk.X[l] = p; p += w.S[l] * nrhs; }
+  wk.ws_nrhs = nrhs;
 }
 
 int64_t hbs_ws1_plan(const HbsDev& w, double* base, HbsWs1& ws) {
@@ -1879,36 +1880,44 @@ void hbs_dev_apply1_at(const HbsDev& w, const double* b, double* x, bool use_f32
   if (ws.nsd[L] > 1) launch_parts_reduce(ws.X1[L], w.S[L], ws.nsd[L], w.S[L], x, s);
 }
 
-void hbs_dev_apply(HbsDev& w, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32,
-                   hipStream_t s) {
+void hbs_dev_apply_ws(const HbsDev& w, HbsWork& wk, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
+                      bool use_f32, hipStream_t s) {
   if (nrhs <= 0) return;
+  if (!wk.ctx) wk.ctx = w.ctx;
   if (nrhs == 1) {
-    if (!w.ws1.p) {
-      HbsWs1 ws;
-      w.ws1.alloc(w.ctx, (size_t)std::max<int64_t>(1, hbs_ws1_plan(w, nullptr, ws)));
+    HbsWs1 ws;
+    const int64_t need = std::max<int64_t>(1, hbs_ws1_plan(w, nullptr, ws));
+    if (!wk.ws1.p || wk.ws1_need != need) {
+      wk.ws1.alloc(wk.ctx, (size_t)need);
+      wk.ws1_need = need;
     }
-    hbs_dev_apply1_at(w, b, x, use_f32 && w.gen32.p, w.ws1.p, s);
+    hbs_dev_apply1_at(w, b, x, use_f32 && w.gen32.p, wk.ws1.p, s);
     return;
   }
-  hbs_ensure_ws(w, nrhs);
+  hbs_ensure_ws(w, wk, nrhs);
   const bool f32 = use_f32 && w.gen32.p;
   for (int l = w.L; l >= 1; --l) {
-    const double* in = (l == w.L) ? b : w.U[l + 1];
+    const double* in = (l == w.L) ? b : wk.U[l + 1];
     const int64_t ldin = (l == w.L) ? ldb : w.K[l + 1];
     if (f32)
-      launch_hbs_up_f32(w.lev[l], w.gen32.p, in, ldin, w.U[l], w.K[l], w.GB[l], w.S[l], nrhs, s);
+      launch_hbs_up_f32(w.lev[l], w.gen32.p, in, ldin, wk.U[l], w.K[l], wk.GB[l], w.S[l], nrhs, s);
     else
-      launch_hbs_up(w.lev[l], w.gen.p, in, ldin, w.U[l], w.K[l], w.GB[l], w.S[l], nrhs, s);
+      launch_hbs_up(w.lev[l], w.gen.p, in, ldin, wk.U[l], w.K[l], wk.GB[l], w.S[l], nrhs, s);
   }
-  launch_hbs_root(w.nroot, w.d_nroot, w.groot.p, w.U[1], w.K[1], w.X[0], w.S[0], nrhs, s);
+  launch_hbs_root(w.nroot, w.d_nroot, w.groot.p, wk.U[1], w.K[1], wk.X[0], w.S[0], nrhs, s);
   for (int l = 1; l <= w.L; ++l) {
-    double* out = (l == w.L) ? x : w.X[l];
+    double* out = (l == w.L) ? x : wk.X[l];
     const int64_t ldout = (l == w.L) ? ldx : w.S[l];
     if (f32)
-      launch_hbs_down_f32(w.lev[l], w.gen32.p, w.X[l - 1], w.S[l - 1], w.GB[l], w.S[l], out, ldout, nrhs, s);
+      launch_hbs_down_f32(w.lev[l], w.gen32.p, wk.X[l - 1], w.S[l - 1], wk.GB[l], w.S[l], out, ldout, nrhs, s);
     else
-      launch_hbs_down(w.lev[l], w.gen.p, w.X[l - 1], w.S[l - 1], w.GB[l], w.S[l], out, ldout, nrhs, s);
+      launch_hbs_down(w.lev[l], w.gen.p, wk.X[l - 1], w.S[l - 1], wk.GB[l], w.S[l], out, ldout, nrhs, s);
   }
+}
+
+void hbs_dev_apply(HbsDev& w, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32,
+                   hipStream_t s) {
+  hbs_dev_apply_ws(w, w.work, b, ldb, x, ldx, nrhs, use_f32, s);
 }
 
 void hbs_gpu_finish(HbsDev& w) {

@@ -430,8 +430,21 @@ struct rw_wall {
 
 namespace {
 
-void hbs_apply(rw_wall* w, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32) {
-  hbs_dev_apply(w->hbs, b, ldb, x, ldx, nrhs, use_f32, w->ctx->stream);
+// The apply workspace that ctx uses for the inverse h (h's own for its ctx).
+HbsWork& ctx_hbs_work(rw_ctx* ctx, HbsDev& h) {
+  if (ctx == h.ctx) return h.work;
+  std::shared_ptr<HbsWork>& p = ctx->hbs_work[&h];
+  if (!p) {
+    p = std::make_shared<HbsWork>();
+    p->ctx = ctx;
+  }
+  return *p;
+}
+
+// x = A_oo^{-1} b on ctx's stream, with ctx's workspace for the wall's inverse.
+void hbs_apply(rw_wall* w, rw_ctx* ctx, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
+               bool use_f32) {
+  hbs_dev_apply_ws(w->hbs, ctx_hbs_work(ctx, w->hbs), b, ldb, x, ldx, nrhs, use_f32, ctx->stream);
 }
 
 void build_wall(rw_ctx* ctx, const rw_curve& cv, int P, int q, int leaf, double tol, int precision, rw_wall& w) {
@@ -567,7 +580,7 @@ void woodbury_ref_apply(rw_refined* f, int nrhs) {
   const double gb = (w->precision == RW_F32 ? 4.0 : 8.0) * w->stats.gen_entries;
   PhaseTimer t(f->ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * nrhs,
                gb * hbs_gen_passes(nrhs, w->precision == RW_F32));
-  hbs_apply(w, f->gext.p, M, f->y.p, M, nrhs, w->precision == RW_F32);
+  hbs_apply(w, f->ctx, f->gext.p, M, f->y.p, M, nrhs, w->precision == RW_F32);
 }
 
 // The A_pp^{-1} block of y on stream s.
@@ -653,7 +666,7 @@ void build_app_inverse(rw_wall* w, rw_refined& f, uint64_t seed, rw_ctx* ax) {
     launch_assemble(f.d_p.p, f.Np, f.d_p.p, f.Np, true, f.App.p, Mp, s);
   }
   // test hook: a zero first column, which the LU's pivot check must report
-  if (w->ctx->opt.test_singular == 2) HIP_CHECK(hipMemsetAsync(f.App.p, 0, sizeof(double) * Mp, s));
+  if (ax->opt.test_singular == 2) HIP_CHECK(hipMemsetAsync(f.App.p, 0, sizeof(double) * Mp, s));
   {
     PhaseTimer t(ax, "a3_app_lu", 2.0 / 3.0 * (double)Mp * Mp * Mp, 0.0);
     launch_lu_nopiv(f.App.p, Mp, Mp, dinfo.p, nullptr, s);
@@ -664,9 +677,10 @@ void build_app_inverse(rw_wall* w, rw_refined& f, uint64_t seed, rw_ctx* ax) {
   if (info) RW_THROW(RW_ESINGULAR, "zero pivot " + std::to_string(info) + " in the LU of A_pp");
 }
 
-// Algorithm 1 pre-computation for the refinement described by level_of_panel.
-void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_refined& f) {
-  rw_ctx* ctx = w->ctx;
+// Algorithm 1 pre-computation for the refinement described by level_of_panel,
+// on ctx (the wall's own, or another ctx of the same device that uses the
+// wall's read-only data on its own stream).
+void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of_panel, rw_refined& f) {
   hipStream_t s = ctx->stream;
   const double t0 = wall_ms();
   // the previous refinement's checks are read first: its read-back word and
@@ -919,7 +933,7 @@ void build_refined(rw_wall* w, const std::vector<int32_t>& level_of_panel, rw_re
     HIP_CHECK(hipMemsetAsync(f.X.p, 0, sizeof(double) * M * f.k, s));
     if (f.k_k) {
       PhaseTimer t_x(ctx, "a4_X", 2.0 * w->stats.gen_entries * f.k_k, 8.0 * w->stats.gen_entries * hbs_gen_passes(f.k_k));
-      hbs_apply(w, f.L.p, M, f.X.p, M, f.k_k, false);
+      hbs_apply(w, ctx, f.L.p, M, f.X.p, M, f.k_k, false);
     }
   }
   // ---- the rest (A_pp^{-1} block of X, W and its inverse) runs on the side
@@ -1194,6 +1208,8 @@ int rw_ctx_create(rw_ctx** out, int device, void* hip_stream, size_t hbm_budget_
 void rw_ctx_destroy(rw_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->hbs_work.clear();   // workspaces from this ctx's allocator, released before its cache
   ctx_destroy_aux(ctx);
   if (ctx->d_sync) dev_free(ctx, ctx->d_sync, sizeof(unsigned) * ctx->sync_words);
   ctx_release_cache(ctx);
@@ -1327,7 +1343,7 @@ int rw_hbs_apply(rw_wall* w, const double* b, int32_t nrhs, double* x) {
   return guarded(w->ctx, [&]() {
     if (nrhs <= 0 || !b || !x) RW_THROW(RW_EINVAL, "bad arguments");
     const int64_t n2 = 2 * (int64_t)w->disc.nodes.size();
-    hbs_apply(w, b, n2, x, n2, nrhs, w->precision == RW_F32);
+    hbs_apply(w, w->ctx, b, n2, x, n2, nrhs, w->precision == RW_F32);
     KERNEL_CHECK("hbs_apply");
   });
 }
@@ -1370,7 +1386,25 @@ int rw_refine(rw_wall* w, const int32_t* ids, const int32_t* levels, int32_t n_s
     for (int i = 0; i < n_sel; ++i) lop[ids[i]] = levels[i];
     std::unique_ptr<rw_refined> f(new rw_refined());
     f->q_tol = q_tol > 0 ? q_tol : w->tol;
-    build_refined(w, lop, *f);
+    build_refined(w, w->ctx, lop, *f);
+    *out = f.release();
+  });
+}
+
+int rw_refine_on(rw_ctx* ctx, rw_wall* w, const int32_t* ids, const int32_t* levels, int32_t n_sel, double q_tol,
+                 rw_refined** out) {
+  if (!ctx || !w) return RW_EINVAL;
+  return guarded(ctx, [&]() {
+    if (!out) RW_THROW(RW_EINVAL, "out is null");
+    *out = nullptr;
+    if (ctx->device != w->ctx->device) RW_THROW(RW_EINVAL, "the ctx and the wall are on different devices");
+    validate_selection(w, ids, levels, n_sel);
+    if (!(q_tol < 1.0) || std::isnan(q_tol)) RW_THROW(RW_EINVAL, "q_tol must be below 1 (<= 0: the wall's id_tol)");
+    std::vector<int32_t> lop(w->P, -1);
+    for (int i = 0; i < n_sel; ++i) lop[ids[i]] = levels[i];
+    std::unique_ptr<rw_refined> f(new rw_refined());
+    f->q_tol = q_tol > 0 ? q_tol : w->tol;
+    build_refined(w, ctx, lop, *f);
     *out = f.release();
   });
 }
@@ -1389,7 +1423,7 @@ int rw_coarsen(rw_refined* f, const int32_t* ids, int32_t n_sel) {
     }
     std::unique_ptr<rw_refined> g(new rw_refined());
     g->q_tol = f->q_tol;
-    build_refined(f->wall, lop, *g);
+    build_refined(f->wall, f->ctx, lop, *g);
     std::swap(*f, *g);
     if (f->ctx->unsettled == g.get()) f->ctx->unsettled = f;
   });
@@ -1540,7 +1574,7 @@ void batch_woodbury(rw_wall* w, const std::vector<rw_refined*>& fs, const std::v
     const double gb = (w->precision == RW_F32 ? 4.0 : 8.0) * w->stats.gen_entries;
     PhaseTimer t(w->ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * C,
                  gb * hbs_gen_passes((int)C, w->precision == RW_F32));
-    hbs_apply(w, w->bat_in.p, Mo, w->bat_out.p, Mo, (int)C, w->precision == RW_F32);
+    hbs_apply(w, w->ctx, w->bat_in.p, Mo, w->bat_out.p, Mo, (int)C, w->precision == RW_F32);
   }
   c0 = 0;
   for (size_t i = 0; i < fs.size(); ++i) {
@@ -1564,6 +1598,7 @@ int rw_solve_batch(rw_refined* const* inst, int32_t n_inst, const double* const*
     std::set<const rw_refined*> seen;
     for (int i = 0; i < n_inst; ++i) {
       if (!inst[i] || inst[i]->wall != w) RW_THROW(RW_EINVAL, "instances must be refinements of one wall");
+      if (inst[i]->ctx != w->ctx) RW_THROW(RW_EINVAL, "instances must be refined on the wall's ctx");
       if (!seen.insert(inst[i]).second) RW_THROW(RW_EINVAL, "an instance appears twice");
       if (nrhs[i] <= 0 || !g[i] || !tau[i]) RW_THROW(RW_EINVAL, "bad arguments of instance " + std::to_string(i));
     }

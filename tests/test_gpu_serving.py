@@ -1,0 +1,82 @@
+"""Serving through the C ABI (rw_server_*): requests of uneven refinement
+size and right-hand-side count, run by several slots whose device work
+overlaps, against one resident wall.
+* each result in the mix equals the same request solved alone (one slot,
+  nothing else running) to 1e-12, and the small wall's results equal the
+  FP64 oracle's dense solutions to the FP64 bar;
+* admission by memory: a request that could never fit the budget is
+  refused at submission; with a budget that fits one request at a time all
+  requests still complete."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import geometry as G, kernels as K, solve as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2108_07205_amd as rw  # noqa: E402
+
+
+def _say(msg):
+    print(f"[gpu-serving] {msg}", flush=True)
+
+
+def _stk(p):
+    return [(s.z, s.f) for s in p.rhs]
+
+
+def _run(wall, reqs, slots, budget=0):
+    sv = rw.Server(wall, slots=slots, hbm_budget_bytes=budget)
+    ids = [sv.submit(r.problem.refinement.panel_ids, r.problem.refinement.levels, _stk(r.problem)) for r in reqs]
+    out = [sv.wait(i) for i in ids]
+    sv.close()
+    return out
+
+
+def test_mix_equals_alone_and_oracle():
+    ctx = rw.Context(0)
+    wall = rw.Wall(ctx, 64)
+    reqs = W.serving_requests(8, rate=2000.0, seed=3, n_panels=64, max_sel=6, max_level=4, max_rhs=3)
+    mix = _run(wall, reqs, slots=4)
+    slots_used = {inf["slot"] for _, inf in mix}
+    _say(f"64-panel mix: slots used {sorted(slots_used)}, "
+         f"nodes {[inf['n_nodes'] for _, inf in mix]}, resid max {max(inf['resid'] for _, inf in mix):.1e}")
+    for r, (tau, inf) in zip(reqs, mix):
+        alone, ainf = _run(wall, [r], slots=1)[0]
+        d = np.max(np.linalg.norm(tau - alone, axis=1) / np.linalg.norm(alone, axis=1))
+        p = r.problem
+        sets = G.refine(p.n_panels, p.refinement.panel_ids, p.refinement.levels, p.curve.a, p.curve.m)
+        A = K.nystrom_matrix(sets.new)
+        g = np.stack([K.rhs_vector(sets.new, s.z, s.f) for s in p.rhs], axis=1)
+        tor = S.solve_refined(A, g).T
+        e = np.max(np.linalg.norm(tau - tor, axis=1) / np.linalg.norm(tor, axis=1))
+        assert inf["status"] == rw.RW_OK and d <= 1e-12 and e <= 1e-10, (d, e)
+    assert len(slots_used) > 1
+    wall.close()
+    ctx.close()
+
+
+def test_mix_equals_alone_full_size_and_admission():
+    ctx = rw.Context(0)
+    wall = rw.Wall(ctx, 1024)
+    reqs = W.serving_requests(6, rate=2000.0, seed=5, n_panels=1024, max_sel=32, max_level=5, max_rhs=4)
+    mix = _run(wall, reqs, slots=3)
+    alone = [_run(wall, [r], slots=1)[0] for r in reqs]
+    worst = max(float(np.max(np.linalg.norm(a[0] - m[0], axis=1) / np.linalg.norm(a[0], axis=1)))
+                for a, m in zip(alone, mix))
+    _say(f"1024-panel mix of {len(reqs)}: nodes {[m[1]['n_nodes'] for m in mix]}, alone vs mix {worst:.1e}")
+    assert all(m[1]["status"] == rw.RW_OK for m in mix) and worst <= 1e-12
+    # a budget too small for any request: refused at submission
+    sv = rw.Server(wall, slots=2, hbm_budget_bytes=1 << 20)
+    with pytest.raises(rw.RwError) as ei:
+        p = reqs[0].problem
+        sv.submit(p.refinement.panel_ids, p.refinement.levels, _stk(p))
+    assert ei.value.code == rw.RW_ENOMEM
+    sv.close()
+    # a budget that fits one request at a time (about 0.6 GB here): all complete
+    seq = _run(wall, reqs[:3], slots=3, budget=700 << 20)
+    assert all(s[1]["status"] == rw.RW_OK for s in seq)
+    wall.close()
+    ctx.close()

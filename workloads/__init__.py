@@ -217,3 +217,34 @@ def golden_cases() -> dict:
         "near4x6": near_point_problem("star1024_refine4x6", 1024, 4, 6, 1e-3, 16, 1, seed=5),
         "pattern32x4": near_point_problem("star1024_refine32x4", 1024, 32, 4, 1e-3, 16, 1, seed=0),
     }
+
+
+@dataclasses.dataclass(frozen=True)
+class Request:
+    """One served solve: arrival time (s), a refinement, nrhs Stokeslet sets."""
+
+    t_arrival: float
+    problem: Problem
+
+
+def serving_requests(n: int, rate: float, seed: int = 0, n_panels: int = 4096, max_sel: int = 64,
+                     max_level: int = 5, max_rhs: int = 16) -> List[Request]:
+    """Poisson arrivals at ``rate`` requests/s; each request refines a
+    contiguous block of n_sel ~ U{1..max_sel} panels around a seeded arc
+    position by level ~ U{1..max_level} and asks for nrhs ~ U{1..max_rhs}
+    right-hand sides of 16 exterior Stokeslets each."""
+    curve = Curve()
+    rng = _rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += float(rng.exponential(1.0 / rate))
+        n_sel = int(rng.integers(1, max_sel + 1))
+        level = int(rng.integers(1, max_level + 1))
+        theta0 = float(rng.uniform(0.0, 2.0 * math.pi))
+        ids = contiguous_panels(n_panels, theta0, n_sel)
+        nrhs = int(rng.integers(1, max_rhs + 1))
+        rhs = [stokeslets(rng, 16) for _ in range(nrhs)]
+        out.append(Request(t, Problem(curve, n_panels, 16, 64, Refinement(tuple(ids), tuple([level] * len(ids))),
+                                      rhs, seed, f"req{i}")))
+    return out
