@@ -601,7 +601,7 @@ def main():
     if args.extra_steps > 0:
         side["config4_mixed_precision"] = config4_mixed()
         side["serving_config5"] = serving()
-        side["batched_fp64"] = batched(wall, 16)
+        side["batched_fp64"] = batched(wall, 64)
         side["fp64_resident_factors"] = rhs_rate(wall, args.extra_steps)
         w32 = rw.Wall(ctx, 1024, precision=rw.RW_F32)
         side["fp32_generators"] = {"refined_solves": solve_rate(w32, args.extra_steps),

@@ -136,6 +136,10 @@ typedef struct {
   int64_t gen_entries;       /* sum over nodes of |E| + |F| + |G| (the generators one apply reads) */
   int64_t gen_bytes_f64;     /* 8 * gen_entries */
   double t_build_ms;         /* host + device time of rw_wall_build */
+  int32_t mfma_from_f64;     /* right-hand-side count from which multi-RHS applies of this wall's inverse
+                                run on the FP64 matrix cores, measured by rw_wall_build (65 or more:
+                                never below 64 in the measurement) */
+  int32_t mfma_from_f32;     /* the same for FP32 generators (0 when the wall has none) */
 } rw_wall_stats;
 
 /* ---- context ---------------------------------------------------------- */

@@ -81,7 +81,8 @@ class rw_request_info(ctypes.Structure):
 class rw_wall_stats(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int64), ("n_levels", ctypes.c_int32), ("max_rank", ctypes.c_int32),
                 ("gen_entries", ctypes.c_int64), ("gen_bytes_f64", ctypes.c_int64),
-                ("t_build_ms", ctypes.c_double)]
+                ("t_build_ms", ctypes.c_double), ("mfma_from_f64", ctypes.c_int32),
+                ("mfma_from_f32", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -132,11 +133,17 @@ _lib = None
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
-    """Load ``librw.so`` (raises if it has not been built)."""
+    """Load ``librw.so`` (raises if it has not been built).  PyTorch is
+    imported first: it brings a HIP runtime of its own, and the library must
+    bind to that one (a second runtime loaded beside it finds no device)."""
     global _lib
     if _lib is None:
         if not os.path.exists(path):
             raise RuntimeError(f"{path} is missing: build it with `python -m paper_2108_07205_amd.build`")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(path)
         for name, (res, args) in _SIGS.items():
             fn = getattr(lib, name)

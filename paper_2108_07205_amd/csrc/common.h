@@ -83,6 +83,7 @@ struct rw_ctx {
   // timing-free events that order the two
   hipStream_t side = nullptr;
   hipStream_t side2 = nullptr;   // a third one, used beside `side` (created on first use)
+  std::vector<hipStream_t> bstreams;   // per-instance streams of rw_solve_batch (created on first use)
   std::vector<hipEvent_t> order_events;
   // pinned host staging for small per-call transfers (grow-only), and a
   // separate pinned area for small read-backs (a pageable one would keep

@@ -34,6 +34,10 @@ struct HbsDev {
   const int* d_nroot = nullptr;  // GPU build: the root size on the device (nroot is then a bound)
   int64_t entries = 0;           // sum of |E| + |F| + |G| + |G_root|
   int max_rank = 0;
+  // right-hand sides from which multi-RHS applies take the matrix cores,
+  // FP64 and FP32 generators (0: the built-in crossover; hbs_autotune
+  // measures them for this inverse)
+  int mfma_from64 = 0, mfma_from32 = 0;
   HbsWork work;                  // apply workspace of the owning ctx
   // GPU build: node records and flags read back without a wait, checked by
   // hbs_gpu_finish (records: pinned host memory of the building context)
@@ -69,6 +73,12 @@ void hbs_dev_apply1_at(const HbsDev& w, const double* b, double* x, bool use_f32
 // columns with FP64 generators, from 16 with FP32 ones): the algorithmic
 // generator bytes are passes * entries * width.
 double hbs_gen_passes(int nrhs, bool f32 = false);
+
+// Measure, on stream s, the apply of this inverse at 16..64 right-hand sides
+// on the vector slab kernels and on the matrix cores, and keep for each
+// generator precision the smallest count from which the matrix cores are
+// faster at every larger measured count (never: a count above 64).
+void hbs_autotune(HbsDev& w, hipStream_t s);
 
 // Pack a host-built inverse into HBM.
 void hbs_upload(rw_ctx* ctx, const HbsInverse& H, bool with_f32, HbsDev& out);

@@ -1900,19 +1900,60 @@ void hbs_dev_apply_ws(const HbsDev& w, HbsWork& wk, const double* b, int64_t ldb
     const double* in = (l == w.L) ? b : wk.U[l + 1];
     const int64_t ldin = (l == w.L) ? ldb : w.K[l + 1];
     if (f32)
-      launch_hbs_up_f32(w.lev[l], w.gen32.p, in, ldin, wk.U[l], w.K[l], wk.GB[l], w.S[l], nrhs, s);
+      launch_hbs_up_f32(w.lev[l], w.gen32.p, in, ldin, wk.U[l], w.K[l], wk.GB[l], w.S[l], nrhs, s, w.mfma_from32);
     else
-      launch_hbs_up(w.lev[l], w.gen.p, in, ldin, wk.U[l], w.K[l], wk.GB[l], w.S[l], nrhs, s);
+      launch_hbs_up(w.lev[l], w.gen.p, in, ldin, wk.U[l], w.K[l], wk.GB[l], w.S[l], nrhs, s, w.mfma_from64);
   }
-  launch_hbs_root(w.nroot, w.d_nroot, w.groot.p, wk.U[1], w.K[1], wk.X[0], w.S[0], nrhs, s);
+  launch_hbs_root(w.nroot, w.d_nroot, w.groot.p, wk.U[1], w.K[1], wk.X[0], w.S[0], nrhs, s, w.mfma_from64);
   for (int l = 1; l <= w.L; ++l) {
     double* out = (l == w.L) ? x : wk.X[l];
     const int64_t ldout = (l == w.L) ? ldx : w.S[l];
     if (f32)
-      launch_hbs_down_f32(w.lev[l], w.gen32.p, wk.X[l - 1], w.S[l - 1], wk.GB[l], w.S[l], out, ldout, nrhs, s);
+      launch_hbs_down_f32(w.lev[l], w.gen32.p, wk.X[l - 1], w.S[l - 1], wk.GB[l], w.S[l], out, ldout, nrhs, s,
+                          w.mfma_from32);
     else
-      launch_hbs_down(w.lev[l], w.gen.p, wk.X[l - 1], w.S[l - 1], wk.GB[l], w.S[l], out, ldout, nrhs, s);
+      launch_hbs_down(w.lev[l], w.gen.p, wk.X[l - 1], w.S[l - 1], wk.GB[l], w.S[l], out, ldout, nrhs, s,
+                      w.mfma_from64);
   }
+}
+
+void hbs_autotune(HbsDev& w, hipStream_t s) {
+  const int64_t n = w.n_unknowns();
+  if (n <= 0) return;
+  constexpr int kCand[] = {16, 24, 32, 40, 48, 56, 64};
+  constexpr int kMax = 64, kNever = 1 << 30;
+  DBuf<double> b(w.ctx, (size_t)n * kMax), x(w.ctx, (size_t)n * kMax);
+  HIP_CHECK(hipMemsetAsync(b.p, 0, sizeof(double) * n * kMax, s));
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  auto timed = [&](int nrhs, bool f32, int from) {
+    int& thr = f32 ? w.mfma_from32 : w.mfma_from64;
+    const int keep = thr;
+    thr = from;
+    hbs_dev_apply(w, b.p, n, x.p, n, nrhs, f32, s);   // warm-up (and workspace)
+    HIP_CHECK(hipEventRecord(e0, s));
+    for (int r = 0; r < 3; ++r) hbs_dev_apply(w, b.p, n, x.p, n, nrhs, f32, s);
+    HIP_CHECK(hipEventRecord(e1, s));
+    HIP_CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    thr = keep;
+    return ms;
+  };
+  for (int prec = 0; prec < 2; ++prec) {
+    const bool f32 = prec == 1;
+    if (f32 && !w.gen32.p) continue;
+    int from = kNever;
+    for (int i = (int)(sizeof kCand / sizeof kCand[0]) - 1; i >= 0; --i) {
+      const int c = kCand[i];
+      if (timed(c, f32, 1) < timed(c, f32, kNever)) from = c;
+      else break;
+    }
+    (f32 ? w.mfma_from32 : w.mfma_from64) = from;
+  }
+  HIP_CHECK(hipEventDestroy(e0));
+  HIP_CHECK(hipEventDestroy(e1));
 }
 
 void hbs_dev_apply(HbsDev& w, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32,

@@ -560,14 +560,15 @@ void up_launch(const HbsLevelDev& L, const T* gen, const double* in, int64_t ld_
 
 template <typename T>
 void up_impl(const HbsLevelDev& L, const T* gen, const double* in, int64_t ld_in, double* bhat,
-             int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s) {
+             int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, int mfma_from, hipStream_t s) {
   if (!L.nnodes || nrhs <= 0) return;
+  if (mfma_from <= 0) mfma_from = mfma_min<T>();
   // generators streamed once per pass of up to 8 right-hand sides
-  const double passes = hbs_gen_passes(nrhs, sizeof(T) == 4);
+  const double passes = nrhs == 1 ? 1.0 : (nrhs < mfma_from ? (nrhs + 7) / 8 : (nrhs + kMR - 1) / kMR);
   KernelTimer kt("hbs_up_kernel", 2.0 * L.up_entries * nrhs, sizeof(T) * (double)L.up_entries * passes, s);
   if (nrhs == 1) {
     up_launch<T, 1>(L, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs, s);
-  } else if (nrhs < mfma_min<T>()) {
+  } else if (nrhs < mfma_from) {
     up_launch<T, 8>(L, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs, s);
   } else {
     const int rbmax = (L.max_k + L.max_nin + kRows - 1) / kRows;
@@ -594,13 +595,14 @@ void down_launch(const HbsLevelDev& L, const T* gen, const double* xhat, int64_t
 
 template <typename T>
 void down_impl(const HbsLevelDev& L, const T* gen, const double* xhat, int64_t ld_xh, const double* gb,
-               int64_t ld_gb, double* out, int64_t ld_out, int nrhs, hipStream_t s) {
+               int64_t ld_gb, double* out, int64_t ld_out, int nrhs, int mfma_from, hipStream_t s) {
   if (!L.nnodes || nrhs <= 0) return;
-  const double passes = hbs_gen_passes(nrhs, sizeof(T) == 4);
+  if (mfma_from <= 0) mfma_from = mfma_min<T>();
+  const double passes = nrhs == 1 ? 1.0 : (nrhs < mfma_from ? (nrhs + 7) / 8 : (nrhs + kMR - 1) / kMR);
   KernelTimer kt("hbs_down_kernel", 2.0 * L.e_entries * nrhs, sizeof(T) * (double)L.e_entries * passes, s);
   if (nrhs == 1) {
     down_launch<T, 1>(L, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs, s);
-  } else if (nrhs < mfma_min<T>()) {
+  } else if (nrhs < mfma_from) {
     down_launch<T, 8>(L, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs, s);
   } else {
     const int rbmax = (L.max_nin + kRows - 1) / kRows;
@@ -675,27 +677,30 @@ double hbs_gen_passes(int nrhs, bool f32) {
 }
 
 void launch_hbs_up(const HbsLevelDev& L, const double* gen, const double* in, int64_t ld_in, double* bhat,
-                   int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s) {
-  up_impl<double>(L, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs, s);
+                   int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s, int mfma_from) {
+  up_impl<double>(L, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs, mfma_from, s);
 }
 void launch_hbs_up_f32(const HbsLevelDev& L, const float* gen, const double* in, int64_t ld_in,
-                       double* bhat, int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s) {
-  up_impl<float>(L, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs, s);
+                       double* bhat, int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s,
+                       int mfma_from) {
+  up_impl<float>(L, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs, mfma_from, s);
 }
 void launch_hbs_down(const HbsLevelDev& L, const double* gen, const double* xhat, int64_t ld_xh,
-                     const double* gb, int64_t ld_gb, double* out, int64_t ld_out, int nrhs, hipStream_t s) {
-  down_impl<double>(L, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs, s);
+                     const double* gb, int64_t ld_gb, double* out, int64_t ld_out, int nrhs, hipStream_t s,
+                     int mfma_from) {
+  down_impl<double>(L, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs, mfma_from, s);
 }
 void launch_hbs_down_f32(const HbsLevelDev& L, const float* gen, const double* xhat, int64_t ld_xh,
                          const double* gb, int64_t ld_gb, double* out, int64_t ld_out, int nrhs,
-                         hipStream_t s) {
-  down_impl<float>(L, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs, s);
+                         hipStream_t s, int mfma_from) {
+  down_impl<float>(L, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs, mfma_from, s);
 }
 void launch_hbs_root(int nroot, const int* d_nroot, const double* G, const double* in, int64_t ld_in, double* out,
-                     int64_t ld_out, int nrhs, hipStream_t s) {
+                     int64_t ld_out, int nrhs, hipStream_t s, int mfma_from) {
   if (nroot <= 0 || nrhs <= 0) return;
   const int nb = (nroot + kRows - 1) / kRows;
-  if (nrhs >= kMfmaMin) {
+  if (mfma_from <= 0) mfma_from = kMfmaMin;
+  if (nrhs >= mfma_from) {
     hipLaunchKernelGGL(hbs_root_mfma_kernel, dim3(nb, (nrhs + kMR - 1) / kMR), dim3(kThreads), 0, s, nroot, d_nroot,
                        G, in, ld_in, out, ld_out, nrhs);
   } else if (nrhs == 1) {

@@ -23,19 +23,25 @@ struct HbsLevelDev {
 };
 
 // up: bhat = F* b (to the parent level's vector), gb = G b (this level).
+// mfma_from: right-hand sides from which the matrix-core path is taken
+// (<= 0: the built-in crossover; a wall measures its own at build time).
 void launch_hbs_up(const HbsLevelDev& L, const double* gen, const double* in, int64_t ld_in,
-                   double* bhat, int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s);
+                   double* bhat, int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s,
+                   int mfma_from = 0);
 void launch_hbs_up_f32(const HbsLevelDev& L, const float* gen, const double* in, int64_t ld_in,
-                       double* bhat, int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s);
+                       double* bhat, int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s,
+                       int mfma_from = 0);
 // root: out = G_root in (nroot x nroot, ld nroot); with d_nroot the size is
 // read on the device (at most nroot).
 void launch_hbs_root(int nroot, const int* d_nroot, const double* G, const double* in, int64_t ld_in, double* out,
-                     int64_t ld_out, int nrhs, hipStream_t s);
+                     int64_t ld_out, int nrhs, hipStream_t s, int mfma_from = 0);
 // down: out = E xhat + gb.
 void launch_hbs_down(const HbsLevelDev& L, const double* gen, const double* xhat, int64_t ld_xh,
-                     const double* gb, int64_t ld_gb, double* out, int64_t ld_out, int nrhs, hipStream_t s);
+                     const double* gb, int64_t ld_gb, double* out, int64_t ld_out, int nrhs, hipStream_t s,
+                     int mfma_from = 0);
 void launch_hbs_down_f32(const HbsLevelDev& L, const float* gen, const double* xhat, int64_t ld_xh,
-                         const double* gb, int64_t ld_gb, double* out, int64_t ld_out, int nrhs, hipStream_t s);
+                         const double* gb, int64_t ld_gb, double* out, int64_t ld_out, int nrhs, hipStream_t s,
+                         int mfma_from = 0);
 
 // One right-hand side: every level's block products split over column
 // ranges of hbs_split_count(columns) workgroups, each writing a partial

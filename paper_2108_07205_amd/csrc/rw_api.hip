@@ -470,12 +470,16 @@ void build_wall(rw_ctx* ctx, const rw_curve& cv, int P, int q, int leaf, double 
   w.d_nodes.alloc(ctx, w.disc.nodes.size());
   w.d_nodes.upload(w.disc.nodes.data(), w.disc.nodes.size(), s);
   hbs_upload(ctx, H, precision == RW_F32, w.hbs);
+  // the multi-RHS apply's crossover to the matrix cores, measured on this inverse
+  hbs_autotune(w.hbs, s);
   HIP_CHECK(hipStreamSynchronize(s));
   w.stats.n_nodes = (int64_t)w.disc.nodes.size();
   w.stats.n_levels = tree_levels;
   w.stats.max_rank = tree_max_rank;
   w.stats.gen_entries = H.entries;
   w.stats.gen_bytes_f64 = 8 * H.entries;
+  w.stats.mfma_from_f64 = w.hbs.mfma_from64;
+  w.stats.mfma_from_f32 = w.hbs.mfma_from32;
   w.stats.t_build_ms = wall_ms() - t0;
 }
 
@@ -569,9 +573,9 @@ void refined_ensure_ws(rw_refined* f, int nrhs) {
 // the reference inverse: in: src -> gext (extended order); the A_oo^{-1}
 // block of y = A~^{-1} gext (ref_apply); out: the A_pp^{-1} block of y, the
 // correction y -= X W^{-1} R y and dst (+)= y in refined order.
-void woodbury_in(rw_refined* f, const double* src, int nrhs) {
+void woodbury_in(rw_refined* f, const double* src, int nrhs, hipStream_t s = nullptr) {
   const int64_t M = 2 * f->Next;
-  launch_to_ext(src, 2 * f->Nn, f->Nn, f->d_new2ext.p, f->gext.p, M, M, nrhs, f->ctx->stream);
+  launch_to_ext(src, 2 * f->Nn, f->Nn, f->d_new2ext.p, f->gext.p, M, M, nrhs, s ? s : f->ctx->stream);
 }
 
 void woodbury_ref_apply(rw_refined* f, int nrhs) {
@@ -592,8 +596,9 @@ void woodbury_app_apply(rw_refined* f, int nrhs, hipStream_t s) {
 }
 
 // app_done: the A_pp^{-1} block of y is already in (woodbury_app_apply).
-void woodbury_out(rw_refined* f, double* dst, int nrhs, bool accumulate, bool app_done = false) {
-  hipStream_t s = f->ctx->stream;
+void woodbury_out(rw_refined* f, double* dst, int nrhs, bool accumulate, bool app_done = false,
+                  hipStream_t s = nullptr) {
+  if (!s) s = f->ctx->stream;
   const int64_t M = 2 * f->Next, Mo = 2 * f->No, Mp = 2 * f->Np;
   // the refinement's last products (X, W, A_pp^{-1}) come from the side
   // stream: with app_done the stream has joined it already
@@ -602,14 +607,14 @@ void woodbury_out(rw_refined* f, double* dst, int nrhs, bool accumulate, bool ap
   } else if (f->Np > 0 && f->app_hbs_on) {
     woodbury_app_apply(f, nrhs, s);
   } else if (f->Np > 0) {
-    PhaseTimer t(f->ctx, "a6_app_solve", 2.0 * (double)Mp * Mp * nrhs, 8.0 * (double)Mp * Mp * nrhs);
+    PhaseTimer t(f->ctx, "a6_app_solve", 2.0 * (double)Mp * Mp * nrhs, 8.0 * (double)Mp * Mp * nrhs, s);
     HIP_CHECK(hipMemcpy2DAsync(f->y.p + Mo, sizeof(double) * M, f->gext.p + Mo, sizeof(double) * M,
                                sizeof(double) * Mp, nrhs, hipMemcpyDeviceToDevice, s));
     launch_lu_solve(f->App.p, Mp, Mp, f->y.p + Mo, M, nrhs, s);
   }
   if (f->k > 0) {
     // z = R y, w = W^{-1} z, y -= X w
-    PhaseTimer t(f->ctx, "a7_woodbury", 4.0 * f->k * (double)M * nrhs, 16.0 * f->k * (double)M);
+    PhaseTimer t(f->ctx, "a7_woodbury", 4.0 * f->k * (double)M * nrhs, 16.0 * f->k * (double)M, s);
     launch_gemm_tn(f->R.p, M, f->y.p, M, M, f->k, nrhs, f->z.p, f->k, false, f->part.p, s);
     if (!launch_woodbury_sub(f->X.p, M, M, f->k, f->W.p, f->z.p, f->y.p, M, nrhs, s)) {
       launch_small_gemm(f->W.p, f->k, f->z.p, nrhs, f->wv.p, s);
@@ -1218,6 +1223,7 @@ void rw_ctx_destroy(rw_ctx* ctx) {
   for (auto e : ctx->order_events) (void)hipEventDestroy(e);
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
   if (ctx->side2) (void)hipStreamDestroy(ctx->side2);
+  for (auto st : ctx->bstreams) (void)hipStreamDestroy(st);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->rb) (void)hipHostFree(ctx->rb);
   if (ctx->pinned_ev) (void)hipEventDestroy(ctx->pinned_ev);
@@ -1549,41 +1555,72 @@ int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau, rw_solve
 
 namespace {
 
-// One Woodbury apply for several instances of one wall: their reference-mesh
-// parts are stacked into one multi-RHS apply of A_oo^{-1} (the generators are
-// streamed once for all of them), the rest runs per instance.
-void batch_woodbury(rw_wall* w, const std::vector<rw_refined*>& fs, const std::vector<const double*>& src,
-                    const std::vector<double*>& dst, const std::vector<int>& nr, bool accumulate) {
-  hipStream_t s = w->ctx->stream;
-  const int64_t Mo = 2 * (int64_t)w->disc.nodes.size();
-  int64_t C = 0;
-  for (size_t i = 0; i < fs.size(); ++i) {
-    woodbury_in(fs[i], src[i], nr[i]);
-    C += nr[i];
+// Streams for the per-instance work of a batch (created on first use,
+// non-blocking, default priority; destroyed with the ctx).
+constexpr int BATCH_STREAMS = 4;
+hipStream_t ctx_batch_stream(rw_ctx* ctx, int i) {
+  if (ctx->bstreams.empty()) {
+    ctx->bstreams.assign(BATCH_STREAMS, nullptr);
+    for (auto& st : ctx->bstreams) HIP_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   }
-  w->bat_in.ensure(w->ctx, (size_t)(Mo * C));
-  w->bat_out.ensure(w->ctx, (size_t)(Mo * C));
+  return ctx->bstreams[i % BATCH_STREAMS];
+}
+
+// One sweep for several instances of one wall: each instance's Woodbury
+// apply of src (eq. wood) followed by its exact residual r = g - A tau and
+// the residual norms (into nrm, pinned host memory, 2 nrhs per instance).
+// The reference-mesh parts of all applies are stacked into one multi-RHS
+// apply of A_oo^{-1} on the ctx stream (the generators are streamed once
+// for all of them); the per-instance work before and after it (extension,
+// A_pp^{-1}, R y, W^{-1} z, X w, residual) runs on BATCH_STREAMS streams
+// side by side, instance i on stream i mod BATCH_STREAMS.
+void batch_sweep(rw_wall* w, const std::vector<rw_refined*>& fs, const std::vector<const double*>& src,
+                 const std::vector<double*>& dst, const std::vector<const double*>& g, const std::vector<int>& nr,
+                 bool accumulate, double* nrm) {
+  rw_ctx* ctx = w->ctx;
+  hipStream_t s = ctx->stream;
+  const int64_t Mo = 2 * (int64_t)w->disc.nodes.size();
+  const int nst = std::min<int>(BATCH_STREAMS, (int)fs.size());
+  int64_t C = 0;
+  for (size_t i = 0; i < fs.size(); ++i) C += nr[i];
+  w->bat_in.ensure(ctx, (size_t)(Mo * C));
+  w->bat_out.ensure(ctx, (size_t)(Mo * C));
+  for (int q = 0; q < nst; ++q) stream_after(ctx, ctx_batch_stream(ctx, q), s, 10);
   int64_t c0 = 0;
   for (size_t i = 0; i < fs.size(); ++i) {
+    const hipStream_t si = ctx_batch_stream(ctx, (int)i);
     const int64_t M = 2 * fs[i]->Next;
+    woodbury_in(fs[i], src[i], nr[i], si);
     HIP_CHECK(hipMemcpy2DAsync(w->bat_in.p + c0 * Mo, sizeof(double) * Mo, fs[i]->gext.p, sizeof(double) * M,
-                               sizeof(double) * Mo, nr[i], hipMemcpyDeviceToDevice, s));
+                               sizeof(double) * Mo, nr[i], hipMemcpyDeviceToDevice, si));
     c0 += nr[i];
   }
+  for (int q = 0; q < nst; ++q) stream_after(ctx, s, ctx_batch_stream(ctx, q), 11);
   {
     const double gb = (w->precision == RW_F32 ? 4.0 : 8.0) * w->stats.gen_entries;
-    PhaseTimer t(w->ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * C,
+    PhaseTimer t(ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * C,
                  gb * hbs_gen_passes((int)C, w->precision == RW_F32));
-    hbs_apply(w, w->ctx, w->bat_in.p, Mo, w->bat_out.p, Mo, (int)C, w->precision == RW_F32);
+    hbs_apply(w, ctx, w->bat_in.p, Mo, w->bat_out.p, Mo, (int)C, w->precision == RW_F32);
   }
+  for (int q = 0; q < nst; ++q) stream_after(ctx, ctx_batch_stream(ctx, q), s, 12);
   c0 = 0;
+  int64_t n0 = 0;
   for (size_t i = 0; i < fs.size(); ++i) {
-    const int64_t M = 2 * fs[i]->Next;
-    HIP_CHECK(hipMemcpy2DAsync(fs[i]->y.p, sizeof(double) * M, w->bat_out.p + c0 * Mo, sizeof(double) * Mo,
-                               sizeof(double) * Mo, nr[i], hipMemcpyDeviceToDevice, s));
+    rw_refined* f = fs[i];
+    const hipStream_t si = ctx_batch_stream(ctx, (int)i);
+    const int64_t M = 2 * f->Next;
+    HIP_CHECK(hipMemcpy2DAsync(f->y.p, sizeof(double) * M, w->bat_out.p + c0 * Mo, sizeof(double) * Mo,
+                               sizeof(double) * Mo, nr[i], hipMemcpyDeviceToDevice, si));
     c0 += nr[i];
-    woodbury_out(fs[i], dst[i], nr[i], accumulate);
+    woodbury_out(f, dst[i], nr[i], accumulate, false, si);
+    {
+      PhaseTimer t(ctx, "a8_residual", 26.0 * (double)f->Nn * f->Nn * nr[i], 0.0, si);
+      launch_residual(f->d_new.p, f->Nn, g[i], dst[i], f->r.p, nr[i], f->part.p, f->norms.p, si);
+    }
+    HIP_CHECK(hipMemcpyAsync(nrm + n0, f->norms.p, sizeof(double) * 2 * nr[i], hipMemcpyDeviceToHost, si));
+    n0 += 2 * nr[i];
   }
+  for (int q = 0; q < nst; ++q) stream_after(ctx, s, ctx_batch_stream(ctx, q), 13);
 }
 
 }  // namespace
@@ -1609,33 +1646,31 @@ int rw_solve_batch(rw_refined* const* inst, int32_t n_inst, const double* const*
     std::vector<int> nr(nrhs, nrhs + n_inst);
     for (int i = 0; i < n_inst; ++i) refined_settle(fs[i]);
     for (int i = 0; i < n_inst; ++i) refined_ensure_ws(fs[i], nr[i]);
-    batch_woodbury(w, fs, std::vector<const double*>(g, g + n_inst), std::vector<double*>(tau, tau + n_inst), nr,
-                   false);
+    int64_t tot_cols = 0;
+    for (int i = 0; i < n_inst; ++i) tot_cols += nr[i];
+    double* hn = (double*)ctx_readback(f0->ctx, sizeof(double) * 2 * tot_cols);
+    std::vector<const double*> gv(g, g + n_inst);
+    std::vector<double*> tv(tau, tau + n_inst);
+    batch_sweep(w, fs, gv, tv, gv, nr, false, hn);
     std::vector<int> it(n_inst, 0);
     std::vector<double> worst(n_inst, 0.0);
-    std::vector<std::vector<double>> nrm(n_inst);
-    for (int i = 0; i < n_inst; ++i) nrm[i].resize(2 * nr[i]);
     std::vector<char> active(n_inst, 1);
+    std::vector<int> idx(n_inst);
+    for (int i = 0; i < n_inst; ++i) idx[i] = i;
     for (;;) {
-      for (int i = 0; i < n_inst; ++i) {
-        if (!active[i]) continue;
-        rw_refined* f = fs[i];
-        {
-          PhaseTimer t(f->ctx, "a8_residual", 26.0 * (double)f->Nn * f->Nn * nr[i], 0.0);
-          launch_residual(f->d_new.p, f->Nn, g[i], tau[i], f->r.p, nr[i], f->part.p, f->norms.p, s);
-        }
-        HIP_CHECK(hipMemcpyAsync(nrm[i].data(), f->norms.p, sizeof(double) * 2 * nr[i], hipMemcpyDeviceToHost, s));
-      }
       HIP_CHECK(hipStreamSynchronize(s));
+      // norms of the instances just swept (in the order they were passed)
       std::vector<rw_refined*> fa;
-      std::vector<const double*> sa;
+      std::vector<const double*> sa, ga;
       std::vector<double*> da;
-      std::vector<int> na;
-      for (int i = 0; i < n_inst; ++i) {
-        if (!active[i]) continue;
+      std::vector<int> na, ia;
+      int64_t n0 = 0;
+      for (int i : idx) {
+        const double* hnv = hn + n0;
+        n0 += 2 * nr[i];
         worst[i] = 0;
         for (int c = 0; c < nr[i]; ++c) {
-          const double rel = nrm[i][nr[i] + c] > 0 ? std::sqrt(nrm[i][c] / nrm[i][nr[i] + c]) : std::sqrt(nrm[i][c]);
+          const double rel = hnv[nr[i] + c] > 0 ? std::sqrt(hnv[c] / hnv[nr[i] + c]) : std::sqrt(hnv[c]);
           worst[i] = std::max(worst[i], std::isfinite(rel) ? rel : INFINITY);
         }
         if (worst[i] <= o.ir_tol || it[i] >= o.ir_maxit) {
@@ -1645,11 +1680,14 @@ int rw_solve_batch(rw_refined* const* inst, int32_t n_inst, const double* const*
         fa.push_back(fs[i]);
         sa.push_back(fs[i]->r.p);
         da.push_back(tau[i]);
+        ga.push_back(g[i]);
         na.push_back(nr[i]);
+        ia.push_back(i);
         ++it[i];
       }
       if (fa.empty()) break;
-      batch_woodbury(w, fa, sa, da, na, true);
+      idx = ia;
+      batch_sweep(w, fa, sa, da, ga, na, true, hn);
     }
     prof_flush(f0->ctx);
     const double tms = wall_ms() - t0;

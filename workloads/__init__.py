@@ -195,6 +195,12 @@ def small_problem(n_panels: int = 16, ids: Sequence[int] = (3,), levels: Sequenc
     return Problem(curve, n_panels, order, leaf_nodes, ref, rhs, seed, "small")
 
 
+# four instances of the 64-instance batched family (seed 0) whose dense
+# oracle fits (at most 48200 unknowns), chosen by
+# numpy.random.default_rng(2024) among the 56 that do
+BATCH_GOLDEN_INSTANCES = (6, 14, 42, 63)
+
+
 def golden_cases() -> dict:
     """Full-size refinements whose dense-oracle solutions are stored under
     tests/golden (1024-panel wall, 16384 reference nodes):
@@ -207,7 +213,9 @@ def golden_cases() -> dict:
       (64 children each);
     * ``pattern32x4``: the refinement pattern of the 65536-node workload
       (32 panels nearest a point at 1e-3, 4 levels) on this wall, where the
-      dense oracle still fits (48128 unknowns)."""
+      dense oracle still fits (48128 unknowns);
+    * ``batch0_inst<i>``: instances of the 64-instance batched family (their
+      first right-hand side)."""
     wrap_ids = [1021, 1022, 1023] + list(range(13))
     return {
         "config2_seed0": config2(seed=0),
@@ -216,6 +224,8 @@ def golden_cases() -> dict:
                                    n_stokeslets=16, seed=3),
         "near4x6": near_point_problem("star1024_refine4x6", 1024, 4, 6, 1e-3, 16, 1, seed=5),
         "pattern32x4": near_point_problem("star1024_refine32x4", 1024, 32, 4, 1e-3, 16, 1, seed=0),
+        **{f"batch0_inst{i}": batched_instances(n_inst=64, seed=0, n_panels=1024, nrhs=8)[i]
+           for i in BATCH_GOLDEN_INSTANCES},
     }
 
 
