@@ -481,13 +481,13 @@ def main():
     def config4_mixed(reps: int = 3):
         """The 65536-node wall (4096 panels; 32 panels nearest a seeded point
         refined 4 levels; 32 Stokeslet right-hand sides): FP64 generators
-        against FP32 generators on the FP32 matrix cores, both refined in
+        against FP32 and BF16 generators on the matrix cores, all refined in
         FP64 to the same residual (1e-13; with ||A^-1|| <= 100 an error
         below 1e-11), and the applies of the reference inverse alone (1 and
         32 right-hand sides, HIP events, warm)."""
         p4 = W.config4(seed=0)
         out = {"workload": "star4096_refine32x4", "nrhs": 32}
-        for prec, name in ((rw.RW_F64, "fp64"), (rw.RW_F32, "fp32_generators")):
+        for prec, name in ((rw.RW_F64, "fp64"), (rw.RW_F32, "fp32_generators"), (rw.RW_BF16, "bf16_generators")):
             w4 = rw.Wall(ctx, 4096, precision=prec)
             st4 = w4.stats()
             ref4 = w4.refine(p4.refinement.panel_ids, p4.refinement.levels)
@@ -516,18 +516,21 @@ def main():
                 e1.record()
                 e1.synchronize()
                 us = e0.elapsed_time(e1) * 100.0
-                width = 4 if prec == rw.RW_F32 else 8
+                width = {rw.RW_F64: 8, rw.RW_F32: 4, rw.RW_BF16: 2}[prec]
                 gen_b = width * st4["gen_entries"]
                 rates[f"apply_{nr}rhs_us"] = us
                 rates[f"apply_{nr}rhs_GBps_per_pass"] = gen_b / (us * 1e-6) / 1e9
             out[name] = {"solve_32rhs_ms": float(np.median(ts)), "corrections": its, "resid": res,
                          "refined_nodes": int(ref4.n_nodes), "k": int(ref4.info()["k"]),
-                         "gen_bytes": (4 if prec == rw.RW_F32 else 8) * st4["gen_entries"], **rates}
+                         "gen_bytes": {rw.RW_F64: 8, rw.RW_F32: 4, rw.RW_BF16: 2}[prec] * st4["gen_entries"],
+                         "mfma_from": st4["mfma_from_f64"] if prec == rw.RW_F64 else st4["mfma_from_f32"], **rates}
             ref4.close()
             w4.close()
-        out["speedup_solve"] = out["fp64"]["solve_32rhs_ms"] / out["fp32_generators"]["solve_32rhs_ms"]
-        out["speedup_apply_32rhs"] = out["fp64"]["apply_32rhs_us"] / out["fp32_generators"]["apply_32rhs_us"]
-        out["speedup_apply_1rhs"] = out["fp64"]["apply_1rhs_us"] / out["fp32_generators"]["apply_1rhs_us"]
+        for name in ("fp32_generators", "bf16_generators"):
+            out[name]["speedup_vs_fp64"] = {
+                "solve": out["fp64"]["solve_32rhs_ms"] / out[name]["solve_32rhs_ms"],
+                "apply_32rhs": out["fp64"]["apply_32rhs_us"] / out[name]["apply_32rhs_us"],
+                "apply_1rhs": out["fp64"]["apply_1rhs_us"] / out[name]["apply_1rhs_us"]}
         return out
 
     def serving(n_req: int = 48, slots: int = 4):

@@ -56,10 +56,12 @@ enum rw_status {
   RW_EDEVICE = -5     /* a HIP runtime call or a kernel reported an error */
 };
 
-/* Storage precision of the reference HBS generators used by the solve
- * (the FP64 copy is always kept for the iterative-refinement path).
- * RW_BF16 is reserved: rw_wall_build rejects it with RW_EINVAL until BF16
- * generators are built. */
+/* Storage precision of the reference HBS generators read by the solve's
+ * applies of A_oo^{-1} (the FP64 copy is always kept and used for X = A~^{-1}
+ * L; the residual, W and its inverse, and the root block stay FP64).  FP32
+ * and BF16 applies accumulate in FP64 with one right-hand side and in FP32
+ * on the matrix cores with many; FP64 iterative refinement (or GMRES)
+ * recovers the digits. */
 enum rw_precision { RW_F64 = 0, RW_F32 = 1, RW_BF16 = 2 };
 
 /* Solver of rw_solve after the refinement's factors are built. */
@@ -95,6 +97,8 @@ typedef struct {
   int32_t gmres_restart;     /* GMRES: Krylov dimension before a restart, 1..256 [30] */
   int32_t gmres_precond;     /* GMRES: 1 = preconditioned by the Woodbury solve (Sec. 4, eq.
                                 left_precond_general applied on the right), 0 = plain GMRES on A_nn [1] */
+  int32_t mfma_from;         /* multi-RHS applies of a wall's inverse on the matrix cores from this many
+                                right-hand sides; 0 = the crossover rw_wall_build measured [0] */
   int32_t test_singular;     /* test hook, 0 in normal use [0]: 1 = zero the first column of W = I + R X
                                 before its inversion, 2 = zero the first column of a dense A_pp before
                                 its LU; the library's own pivot checks then report RW_ESINGULAR */

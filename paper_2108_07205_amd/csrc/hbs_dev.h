@@ -30,6 +30,7 @@ struct HbsDev {
   DBuf<int64_t> d_offs;          // in_off / kout_off / up_off / e_off per level
   DBuf<double> gen;              // packed generators: [F*; G] ((k + nin) x nin) and E (nin x k) per node
   DBuf<float> gen32;             // FP32 copy (optional)
+  DBuf<uint16_t> gen16;          // BF16 copy (optional; high halves of the FP32 words, rounded to nearest even)
   DBuf<double> groot;            // G_root (nroot x nroot)
   const int* d_nroot = nullptr;  // GPU build: the root size on the device (nroot is then a bound)
   int64_t entries = 0;           // sum of |E| + |F| + |G| + |G_root|
@@ -37,7 +38,7 @@ struct HbsDev {
   // right-hand sides from which multi-RHS applies take the matrix cores,
   // FP64 and FP32 generators (0: the built-in crossover; hbs_autotune
   // measures them for this inverse)
-  int mfma_from64 = 0, mfma_from32 = 0;
+  int mfma_from64 = 0, mfma_from32 = 0, mfma_from16 = 0;
   HbsWork work;                  // apply workspace of the owning ctx
   // GPU build: node records and flags read back without a wait, checked by
   // hbs_gpu_finish (records: pinned host memory of the building context)
@@ -66,7 +67,7 @@ struct HbsWs1 {
 int64_t hbs_ws1_plan(const HbsDev& w, double* base, HbsWs1& ws);
 // One-RHS apply x = A^{-1} b with the partial vectors at `base` (at least
 // hbs_ws1_plan doubles); allocates nothing.
-void hbs_dev_apply1_at(const HbsDev& w, const double* b, double* x, bool use_f32, double* base, hipStream_t s);
+void hbs_dev_apply1_at(const HbsDev& w, const double* b, double* x, int prec, double* base, hipStream_t s);
 
 // Passes over the generators that one apply of nrhs right-hand sides makes
 // (8 columns per pass on the vector path, 64 on the matrix cores: from 40
@@ -81,15 +82,19 @@ double hbs_gen_passes(int nrhs, bool f32 = false);
 void hbs_autotune(HbsDev& w, hipStream_t s);
 
 // Pack a host-built inverse into HBM.
-void hbs_upload(rw_ctx* ctx, const HbsInverse& H, bool with_f32, HbsDev& out);
+// prec: RW_F64 (0), RW_F32 (1) or RW_BF16 (2): which narrow copy is added.
+void hbs_upload(rw_ctx* ctx, const HbsInverse& H, int prec, HbsDev& out);
 // x = A^{-1} b (b, x: n x nrhs column-major with leading dimensions ldb, ldx),
 // enqueued on stream s (the caller's; the generators may have been built on
 // another stream of the same device, ordered before s by the caller).
-void hbs_dev_apply(HbsDev& h, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32,
+// prec: which generator copy is read (0 FP64, 1 FP32, 2 BF16; falls back to
+// FP64 when the inverse has no such copy).
+void hbs_dev_apply(HbsDev& h, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, int prec,
                    hipStream_t s);
 // The same with the workspace `wk` (its ctx allocates it on first use).
+// mfma_from > 0 overrides the inverse's measured crossover to the matrix cores.
 void hbs_dev_apply_ws(const HbsDev& h, HbsWork& wk, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
-                      bool use_f32, hipStream_t s);
+                      int prec, hipStream_t s, int mfma_from = 0);
 
 // GPU build of the HBS inverse of the Nystrom matrix of one node set
 // (contiguous arcs, balanced binary tree with leaves of at most leaf_max

@@ -1728,7 +1728,8 @@ __global__ __launch_bounds__(256) void node_inverse_kernel(const GNode* __restri
 }  // namespace
 
 // ================================================================== upload / apply
-void hbs_upload(rw_ctx* ctx, const HbsInverse& H, bool with_f32, HbsDev& w) {
+void hbs_upload(rw_ctx* ctx, const HbsInverse& H, int prec, HbsDev& w) {
+  const bool with_f32 = prec == 1, with_bf16 = prec == 2;
   hipStream_t s = ctx->stream;
   w.ctx = ctx;
   w.L = H.L;
@@ -1799,6 +1800,20 @@ void hbs_upload(rw_ctx* ctx, const HbsInverse& H, bool with_f32, HbsDev& w) {
     w.gen32.upload(g32.data(), g32.size(), s);
     HIP_CHECK(hipStreamSynchronize(s));
   }
+  if (with_bf16) {
+    // FP64 -> FP32 -> BF16, round to nearest even at each step
+    std::vector<uint16_t> g16(gen.size());
+    for (size_t i = 0; i < gen.size(); ++i) {
+      const float f = (float)gen[i];
+      uint32_t u;
+      memcpy(&u, &f, 4);
+      u += 0x7fffu + ((u >> 16) & 1u);
+      g16[i] = (uint16_t)(u >> 16);
+    }
+    w.gen16.alloc(ctx, g16.size());
+    w.gen16.upload(g16.data(), g16.size(), s);
+    HIP_CHECK(hipStreamSynchronize(s));
+  }
   w.groot.alloc(ctx, H.Groot.size());
   w.groot.upload(H.Groot.data(), H.Groot.size(), s);
   for (int l = 1; l <= w.L; ++l) {
@@ -1860,30 +1875,32 @@ int64_t hbs_ws1_plan(const HbsDev& w, double* base, HbsWs1& ws) {
 // One right-hand side: level sweeps of split products whose partial vectors
 // are summed by the next kernel (see kern_hbs.hip).  Every partial vector is
 // written before it is read, so `base` needs no clearing.
-void hbs_dev_apply1_at(const HbsDev& w, const double* b, double* x, bool use_f32, double* base, hipStream_t s) {
+void hbs_dev_apply1_at(const HbsDev& w, const double* b, double* x, int prec, double* base, hipStream_t s) {
   HbsWs1 ws;
   hbs_ws1_plan(w, base, ws);
   const int L = w.L;
-  const float* g32 = use_f32 ? w.gen32.p : nullptr;
+  const float* g32 = prec == 1 ? w.gen32.p : nullptr;
+  const uint16_t* g16 = prec == 2 ? w.gen16.p : nullptr;
   for (int l = L; l >= 1; --l) {
     const bool leaf = l == L;
     launch_hbs_up1(w.lev[l], w.gen.p, g32, leaf ? b : ws.U1[l + 1], leaf ? 0 : w.K[l + 1], leaf ? 1 : ws.nsu[l + 1],
-                   ws.U1[l], w.K[l], ws.GB1[l], w.S[l], s);
+                   ws.U1[l], w.K[l], ws.GB1[l], w.S[l], s, g16);
   }
   launch_hbs_root1(w.nroot, w.d_nroot, w.groot.p, ws.U1[1], w.K[1], ws.nsu[1], ws.X1[0], w.S[0], s);
   for (int l = 1; l <= L; ++l) {
     const int xnp = l == 1 ? ws.nsr : ws.nsd[l - 1];
     const bool direct = l == L && ws.nsd[L] == 1;
     launch_hbs_down1(w.lev[l], w.gen.p, g32, ws.X1[l - 1], w.S[l - 1], xnp, ws.GB1[l], w.S[l], ws.nsu[l],
-                     direct ? x : ws.X1[l], w.S[l], s);
+                     direct ? x : ws.X1[l], w.S[l], s, g16);
   }
   if (ws.nsd[L] > 1) launch_parts_reduce(ws.X1[L], w.S[L], ws.nsd[L], w.S[L], x, s);
 }
 
 void hbs_dev_apply_ws(const HbsDev& w, HbsWork& wk, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
-                      bool use_f32, hipStream_t s) {
+                      int prec, hipStream_t s, int mfma_from) {
   if (nrhs <= 0) return;
   if (!wk.ctx) wk.ctx = w.ctx;
+  if ((prec == 1 && !w.gen32.p) || (prec == 2 && !w.gen16.p)) prec = 0;
   if (nrhs == 1) {
     HbsWs1 ws;
     const int64_t need = std::max<int64_t>(1, hbs_ws1_plan(w, nullptr, ws));
@@ -1891,29 +1908,35 @@ void hbs_dev_apply_ws(const HbsDev& w, HbsWork& wk, const double* b, int64_t ldb
       wk.ws1.alloc(wk.ctx, (size_t)need);
       wk.ws1_need = need;
     }
-    hbs_dev_apply1_at(w, b, x, use_f32 && w.gen32.p, wk.ws1.p, s);
+    hbs_dev_apply1_at(w, b, x, prec, wk.ws1.p, s);
     return;
   }
   hbs_ensure_ws(w, wk, nrhs);
-  const bool f32 = use_f32 && w.gen32.p;
+  const bool f32 = prec == 1, b16 = prec == 2;
+  const int from64 = mfma_from > 0 ? mfma_from : w.mfma_from64, from32 = mfma_from > 0 ? mfma_from : w.mfma_from32,
+            from16 = mfma_from > 0 ? mfma_from : w.mfma_from16;
   for (int l = w.L; l >= 1; --l) {
     const double* in = (l == w.L) ? b : wk.U[l + 1];
     const int64_t ldin = (l == w.L) ? ldb : w.K[l + 1];
-    if (f32)
-      launch_hbs_up_f32(w.lev[l], w.gen32.p, in, ldin, wk.U[l], w.K[l], wk.GB[l], w.S[l], nrhs, s, w.mfma_from32);
+    if (b16)
+      launch_hbs_up_bf16(w.lev[l], w.gen16.p, in, ldin, wk.U[l], w.K[l], wk.GB[l], w.S[l], nrhs, s, from16);
+    else if (f32)
+      launch_hbs_up_f32(w.lev[l], w.gen32.p, in, ldin, wk.U[l], w.K[l], wk.GB[l], w.S[l], nrhs, s, from32);
     else
-      launch_hbs_up(w.lev[l], w.gen.p, in, ldin, wk.U[l], w.K[l], wk.GB[l], w.S[l], nrhs, s, w.mfma_from64);
+      launch_hbs_up(w.lev[l], w.gen.p, in, ldin, wk.U[l], w.K[l], wk.GB[l], w.S[l], nrhs, s, from64);
   }
-  launch_hbs_root(w.nroot, w.d_nroot, w.groot.p, wk.U[1], w.K[1], wk.X[0], w.S[0], nrhs, s, w.mfma_from64);
+  launch_hbs_root(w.nroot, w.d_nroot, w.groot.p, wk.U[1], w.K[1], wk.X[0], w.S[0], nrhs, s, from64);
   for (int l = 1; l <= w.L; ++l) {
     double* out = (l == w.L) ? x : wk.X[l];
     const int64_t ldout = (l == w.L) ? ldx : w.S[l];
-    if (f32)
+    if (b16)
+      launch_hbs_down_bf16(w.lev[l], w.gen16.p, wk.X[l - 1], w.S[l - 1], wk.GB[l], w.S[l], out, ldout, nrhs, s,
+                           from16);
+    else if (f32)
       launch_hbs_down_f32(w.lev[l], w.gen32.p, wk.X[l - 1], w.S[l - 1], wk.GB[l], w.S[l], out, ldout, nrhs, s,
-                          w.mfma_from32);
+                          from32);
     else
-      launch_hbs_down(w.lev[l], w.gen.p, wk.X[l - 1], w.S[l - 1], wk.GB[l], w.S[l], out, ldout, nrhs, s,
-                      w.mfma_from64);
+      launch_hbs_down(w.lev[l], w.gen.p, wk.X[l - 1], w.S[l - 1], wk.GB[l], w.S[l], out, ldout, nrhs, s, from64);
   }
 }
 
@@ -1927,13 +1950,14 @@ void hbs_autotune(HbsDev& w, hipStream_t s) {
   hipEvent_t e0, e1;
   HIP_CHECK(hipEventCreate(&e0));
   HIP_CHECK(hipEventCreate(&e1));
-  auto timed = [&](int nrhs, bool f32, int from) {
-    int& thr = f32 ? w.mfma_from32 : w.mfma_from64;
+  auto thr_of = [&](int prec) -> int& { return prec == 2 ? w.mfma_from16 : (prec == 1 ? w.mfma_from32 : w.mfma_from64); };
+  auto timed = [&](int nrhs, int prec, int from) {
+    int& thr = thr_of(prec);
     const int keep = thr;
     thr = from;
-    hbs_dev_apply(w, b.p, n, x.p, n, nrhs, f32, s);   // warm-up (and workspace)
+    hbs_dev_apply(w, b.p, n, x.p, n, nrhs, prec, s);   // warm-up (and workspace)
     HIP_CHECK(hipEventRecord(e0, s));
-    for (int r = 0; r < 3; ++r) hbs_dev_apply(w, b.p, n, x.p, n, nrhs, f32, s);
+    for (int r = 0; r < 3; ++r) hbs_dev_apply(w, b.p, n, x.p, n, nrhs, prec, s);
     HIP_CHECK(hipEventRecord(e1, s));
     HIP_CHECK(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -1941,24 +1965,23 @@ void hbs_autotune(HbsDev& w, hipStream_t s) {
     thr = keep;
     return ms;
   };
-  for (int prec = 0; prec < 2; ++prec) {
-    const bool f32 = prec == 1;
-    if (f32 && !w.gen32.p) continue;
+  for (int prec = 0; prec < 3; ++prec) {
+    if ((prec == 1 && !w.gen32.p) || (prec == 2 && !w.gen16.p)) continue;
     int from = kNever;
     for (int i = (int)(sizeof kCand / sizeof kCand[0]) - 1; i >= 0; --i) {
       const int c = kCand[i];
-      if (timed(c, f32, 1) < timed(c, f32, kNever)) from = c;
+      if (timed(c, prec, 1) < timed(c, prec, kNever)) from = c;
       else break;
     }
-    (f32 ? w.mfma_from32 : w.mfma_from64) = from;
+    thr_of(prec) = from;
   }
   HIP_CHECK(hipEventDestroy(e0));
   HIP_CHECK(hipEventDestroy(e1));
 }
 
-void hbs_dev_apply(HbsDev& w, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, bool use_f32,
+void hbs_dev_apply(HbsDev& w, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, int prec,
                    hipStream_t s) {
-  hbs_dev_apply_ws(w, w.work, b, ldb, x, ldx, nrhs, use_f32, s);
+  hbs_dev_apply_ws(w, w.work, b, ldb, x, ldx, nrhs, prec, s);
 }
 
 void hbs_gpu_finish(HbsDev& w) {

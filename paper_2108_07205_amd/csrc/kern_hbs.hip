@@ -16,13 +16,19 @@
 
 namespace {
 
+// BF16 generator entry (the high half of an FP32 word), widened on load.
+struct bf16s {
+  uint16_t u;
+  __device__ __forceinline__ operator double() const { return (double)__uint_as_float((unsigned)u << 16); }
+};
+
 constexpr int kThreads = 256;
 constexpr int kRows = 64;    // rows per workgroup (one per lane)
 constexpr int kUnroll = 16;  // loads in flight per lane
 constexpr int kMfmaMin = 40;    // right-hand sides from which the FP64 slab product runs on MFMA (measured crossover)
-constexpr int kMfmaMin32 = 16;  // the same for FP32 generators (FP32 matrix cores)
+constexpr int kMfmaMin32 = 16;  // the same for FP32 and BF16 generators (FP32 accumulation)
 template <typename T>
-constexpr int mfma_min() { return sizeof(T) == 4 ? kMfmaMin32 : kMfmaMin; }
+constexpr int mfma_min() { return sizeof(T) < 8 ? kMfmaMin32 : kMfmaMin; }
 
 // The first kUnroll entries of row `row` in the column quarter w of M (R x
 // C, ld R), loaded before the input slice is staged so that the two loads'
@@ -347,6 +353,105 @@ __global__ __launch_bounds__(kThreads) void hbs_down_mfma_kernel(
       });
 }
 
+// BF16 generators on the BF16 matrix cores (v_mfma_f32_16x16x16bf16_1k, FP32
+// accumulation).  The input tile is split into a high and a low BF16 part
+// (x = hi + lo to about 16 bits) and both are multiplied, so only the
+// generators carry BF16 rounding.  Lane l supplies A(l % 16, 4 (l / 16) + t)
+// and B(4 (l / 16) + t, l % 16), t = 0..3; item r of the result is
+// D(4 (l / 16) + r, l % 16) (both checked with an in-bounds probe).
+typedef short short4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+template <typename Load, typename Emit>
+__device__ __forceinline__ void slab_mfma_bf16(const uint16_t* __restrict__ M, int R, int C, int slab, int r0, int nr,
+                                               short (*Bh)[kMR + 8], short (*Bl)[kMR + 8], Load load, Emit emit) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, i16 = lane & 15, k4 = lane >> 4;
+  const int arow = slab * kRows + w * 16 + i16;
+  const bool aval = arow < R;
+  const uint16_t* mp = M + (aval ? arow : 0);
+  float4_t acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = (float4_t){0.f, 0.f, 0.f, 0.f};
+  for (int c0 = 0; c0 < C; c0 += 16) {
+    short4_t a;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int kc = c0 + 4 * k4 + t;
+      a[t] = (aval && kc < C) ? (short)mp[(int64_t)kc * R] : (short)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + kThreads * u, kk = e & 15, c = e >> 4;
+      const float v = (c0 + kk < C && c < nr) ? (float)load(c0 + kk, r0 + c) : 0.f;
+      const short hi = bf16_rne(v);
+      Bh[kk][c] = hi;
+      Bl[kk][c] = bf16_rne(v - __uint_as_float((unsigned)(unsigned short)hi << 16));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      short4_t bh, bl;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        bh[t] = Bh[4 * k4 + t][cb * 16 + i16];
+        bl[t] = Bl[4 * k4 + t][cb * 16 + i16];
+      }
+      acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bh, acc[cb], 0, 0, 0);
+      acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bl, acc[cb], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = slab * kRows + w * 16 + 4 * k4 + r, c = cb * 16 + i16;
+      if (row < R && c < nr) emit(row, r0 + c, (double)acc[cb][r]);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void hbs_up_mfma16_kernel(
+    int rbmax, const int* __restrict__ nin, const int* __restrict__ kk, const int64_t* __restrict__ in_off,
+    const int64_t* __restrict__ kout_off, const int64_t* __restrict__ up_off, const uint16_t* __restrict__ gen,
+    const double* __restrict__ in, int64_t ld_in, double* __restrict__ bhat, int64_t ld_bhat,
+    double* __restrict__ gb, int64_t ld_gb, int nrhs) {
+  __shared__ short Bh[16][kMR + 8], Bl[16][kMR + 8];
+  const int j = blockIdx.x / rbmax, rb = blockIdx.x - j * rbmax;
+  const int n = nin[j], k = kk[j], R = k + n;
+  if (rb * kRows >= R) return;
+  const int r0 = blockIdx.y * kMR, nr = min(kMR, nrhs - r0);
+  const int64_t io = in_off[j], ko = kout_off[j];
+  slab_mfma_bf16(
+      gen + up_off[j], R, n, rb, r0, nr, Bh, Bl, [&](int col, int c) { return in[io + col + (int64_t)c * ld_in]; },
+      [&](int row, int c, double v) {
+        if (row < k) bhat[ko + row + (int64_t)c * ld_bhat] = v;
+        else gb[io + (row - k) + (int64_t)c * ld_gb] = v;
+      });
+}
+
+__global__ __launch_bounds__(kThreads) void hbs_down_mfma16_kernel(
+    int rbmax, const int* __restrict__ nin, const int* __restrict__ kk, const int64_t* __restrict__ in_off,
+    const int64_t* __restrict__ kout_off, const int64_t* __restrict__ e_off, const uint16_t* __restrict__ gen,
+    const double* __restrict__ xhat, int64_t ld_xh, const double* __restrict__ gb, int64_t ld_gb,
+    double* __restrict__ out, int64_t ld_out, int nrhs) {
+  __shared__ short Bh[16][kMR + 8], Bl[16][kMR + 8];
+  const int j = blockIdx.x / rbmax, rb = blockIdx.x - j * rbmax;
+  const int n = nin[j], k = kk[j];
+  if (rb * kRows >= n) return;
+  const int r0 = blockIdx.y * kMR, nr = min(kMR, nrhs - r0);
+  const int64_t io = in_off[j], ko = kout_off[j];
+  slab_mfma_bf16(
+      gen + e_off[j], n, k, rb, r0, nr, Bh, Bl, [&](int col, int c) { return xhat[ko + col + (int64_t)c * ld_xh]; },
+      [&](int row, int c, double v) {
+        out[io + row + (int64_t)c * ld_out] = v + gb[io + row + (int64_t)c * ld_gb];
+      });
+}
+
 __global__ __launch_bounds__(kThreads) void hbs_up_mfma32_kernel(
     int rbmax, const int* __restrict__ nin, const int* __restrict__ kk, const int64_t* __restrict__ in_off,
     const int64_t* __restrict__ kout_off, const int64_t* __restrict__ up_off, const float* __restrict__ gen,
@@ -576,6 +681,9 @@ void up_impl(const HbsLevelDev& L, const T* gen, const double* in, int64_t ld_in
     if constexpr (sizeof(T) == 4)
       hipLaunchKernelGGL(hbs_up_mfma32_kernel, grid, dim3(kThreads), 0, s, rbmax, L.nin, L.k, L.in_off, L.kout_off,
                          L.up_off, (const float*)gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs);
+    else if constexpr (sizeof(T) == 2)
+      hipLaunchKernelGGL(hbs_up_mfma16_kernel, grid, dim3(kThreads), 0, s, rbmax, L.nin, L.k, L.in_off, L.kout_off,
+                         L.up_off, (const uint16_t*)gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs);
     else
       hipLaunchKernelGGL((hbs_up_mfma_kernel<T>), grid, dim3(kThreads), 0, s, rbmax, L.nin, L.k, L.in_off, L.kout_off,
                          L.up_off, gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs);
@@ -610,6 +718,9 @@ void down_impl(const HbsLevelDev& L, const T* gen, const double* xhat, int64_t l
     if constexpr (sizeof(T) == 4)
       hipLaunchKernelGGL(hbs_down_mfma32_kernel, grid, dim3(kThreads), 0, s, rbmax, L.nin, L.k, L.in_off, L.kout_off,
                          L.e_off, (const float*)gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs);
+    else if constexpr (sizeof(T) == 2)
+      hipLaunchKernelGGL(hbs_down_mfma16_kernel, grid, dim3(kThreads), 0, s, rbmax, L.nin, L.k, L.in_off,
+                         L.kout_off, L.e_off, (const uint16_t*)gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs);
     else
       hipLaunchKernelGGL((hbs_down_mfma_kernel<T>), grid, dim3(kThreads), 0, s, rbmax, L.nin, L.k, L.in_off,
                          L.kout_off, L.e_off, gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs);
@@ -646,15 +757,27 @@ void down1_impl(const HbsLevelDev& L, const T* gen, const double* xh, int64_t xs
 }  // namespace
 
 void launch_hbs_up1(const HbsLevelDev& L, const double* gen, const float* gen32, const double* in, int64_t in_stride,
-                    int in_np, double* bhat, int64_t bstride, double* gb, int64_t gstride, hipStream_t s) {
-  if (gen32) up1_impl<float>(L, gen32, in, in_stride, in_np, bhat, bstride, gb, gstride, s);
+                    int in_np, double* bhat, int64_t bstride, double* gb, int64_t gstride, hipStream_t s,
+                    const uint16_t* gen16) {
+  if (gen16) up1_impl<bf16s>(L, (const bf16s*)gen16, in, in_stride, in_np, bhat, bstride, gb, gstride, s);
+  else if (gen32) up1_impl<float>(L, gen32, in, in_stride, in_np, bhat, bstride, gb, gstride, s);
   else up1_impl<double>(L, gen, in, in_stride, in_np, bhat, bstride, gb, gstride, s);
 }
 void launch_hbs_down1(const HbsLevelDev& L, const double* gen, const float* gen32, const double* xh, int64_t xstride,
                       int xnp, const double* gb, int64_t gstride, int gnp, double* out, int64_t ostride,
-                      hipStream_t s) {
-  if (gen32) down1_impl<float>(L, gen32, xh, xstride, xnp, gb, gstride, gnp, out, ostride, s);
+                      hipStream_t s, const uint16_t* gen16) {
+  if (gen16) down1_impl<bf16s>(L, (const bf16s*)gen16, xh, xstride, xnp, gb, gstride, gnp, out, ostride, s);
+  else if (gen32) down1_impl<float>(L, gen32, xh, xstride, xnp, gb, gstride, gnp, out, ostride, s);
   else down1_impl<double>(L, gen, xh, xstride, xnp, gb, gstride, gnp, out, ostride, s);
+}
+void launch_hbs_up_bf16(const HbsLevelDev& L, const uint16_t* gen, const double* in, int64_t ld_in, double* bhat,
+                        int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s, int mfma_from) {
+  up_impl<bf16s>(L, (const bf16s*)gen, in, ld_in, bhat, ld_bhat, gb, ld_gb, nrhs, mfma_from, s);
+}
+void launch_hbs_down_bf16(const HbsLevelDev& L, const uint16_t* gen, const double* xhat, int64_t ld_xh,
+                          const double* gb, int64_t ld_gb, double* out, int64_t ld_out, int nrhs, hipStream_t s,
+                          int mfma_from) {
+  down_impl<bf16s>(L, (const bf16s*)gen, xhat, ld_xh, gb, ld_gb, out, ld_out, nrhs, mfma_from, s);
 }
 void launch_hbs_root1(int nroot, const int* d_nroot, const double* G, const double* in, int64_t in_stride, int in_np,
                       double* out, int64_t ostride, hipStream_t s) {
@@ -671,9 +794,9 @@ void launch_parts_reduce(const double* in, int64_t stride, int np, int64_t n, do
   KERNEL_CHECK("parts_reduce");
 }
 
-double hbs_gen_passes(int nrhs, bool f32) {
+double hbs_gen_passes(int nrhs, bool narrow) {
   if (nrhs <= 1) return 1.0;
-  return nrhs < (f32 ? kMfmaMin32 : kMfmaMin) ? (double)((nrhs + 7) / 8) : (double)((nrhs + kMR - 1) / kMR);
+  return nrhs < (narrow ? kMfmaMin32 : kMfmaMin) ? (double)((nrhs + 7) / 8) : (double)((nrhs + kMR - 1) / kMR);
 }
 
 void launch_hbs_up(const HbsLevelDev& L, const double* gen, const double* in, int64_t ld_in, double* bhat,

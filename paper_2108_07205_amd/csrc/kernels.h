@@ -50,10 +50,18 @@ void launch_hbs_down_f32(const HbsLevelDev& L, const float* gen, const double* x
 // the FP32 copy of the generators.
 int hbs_split_count(int ncols);
 void launch_hbs_up1(const HbsLevelDev& L, const double* gen, const float* gen32, const double* in, int64_t in_stride,
-                    int in_np, double* bhat, int64_t bstride, double* gb, int64_t gstride, hipStream_t s);
+                    int in_np, double* bhat, int64_t bstride, double* gb, int64_t gstride, hipStream_t s,
+                    const uint16_t* gen16 = nullptr);
 void launch_hbs_down1(const HbsLevelDev& L, const double* gen, const float* gen32, const double* xh, int64_t xstride,
                       int xnp, const double* gb, int64_t gstride, int gnp, double* out, int64_t ostride,
-                      hipStream_t s);
+                      hipStream_t s, const uint16_t* gen16 = nullptr);
+// BF16 generators (uint16 words: the high halves of FP32 values), FP32
+// accumulation on the matrix cores from mfma_from right-hand sides.
+void launch_hbs_up_bf16(const HbsLevelDev& L, const uint16_t* gen, const double* in, int64_t ld_in, double* bhat,
+                        int64_t ld_bhat, double* gb, int64_t ld_gb, int nrhs, hipStream_t s, int mfma_from = 0);
+void launch_hbs_down_bf16(const HbsLevelDev& L, const uint16_t* gen, const double* xhat, int64_t ld_xh,
+                          const double* gb, int64_t ld_gb, double* out, int64_t ld_out, int nrhs, hipStream_t s,
+                          int mfma_from = 0);
 void launch_hbs_root1(int nroot, const int* d_nroot, const double* G, const double* in, int64_t in_stride, int in_np,
                       double* out, int64_t ostride, hipStream_t s);
 void launch_parts_reduce(const double* in, int64_t stride, int np, int64_t n, double* x, hipStream_t s);

@@ -430,6 +430,9 @@ struct rw_wall {
 
 namespace {
 
+// Bytes per generator entry that the solve's applies of the wall's inverse read.
+double gen_width(const rw_wall* w) { return w->precision == RW_BF16 ? 2.0 : (w->precision == RW_F32 ? 4.0 : 8.0); }
+
 // The apply workspace that ctx uses for the inverse h (h's own for its ctx).
 HbsWork& ctx_hbs_work(rw_ctx* ctx, HbsDev& h) {
   if (ctx == h.ctx) return h.work;
@@ -442,9 +445,8 @@ HbsWork& ctx_hbs_work(rw_ctx* ctx, HbsDev& h) {
 }
 
 // x = A_oo^{-1} b on ctx's stream, with ctx's workspace for the wall's inverse.
-void hbs_apply(rw_wall* w, rw_ctx* ctx, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
-               bool use_f32) {
-  hbs_dev_apply_ws(w->hbs, ctx_hbs_work(ctx, w->hbs), b, ldb, x, ldx, nrhs, use_f32, ctx->stream);
+void hbs_apply(rw_wall* w, rw_ctx* ctx, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, int prec) {
+  hbs_dev_apply_ws(w->hbs, ctx_hbs_work(ctx, w->hbs), b, ldb, x, ldx, nrhs, prec, ctx->stream, ctx->opt.mfma_from);
 }
 
 void build_wall(rw_ctx* ctx, const rw_curve& cv, int P, int q, int leaf, double tol, int precision, rw_wall& w) {
@@ -469,7 +471,7 @@ void build_wall(rw_ctx* ctx, const rw_curve& cv, int P, int q, int leaf, double 
   hipStream_t s = ctx->stream;
   w.d_nodes.alloc(ctx, w.disc.nodes.size());
   w.d_nodes.upload(w.disc.nodes.data(), w.disc.nodes.size(), s);
-  hbs_upload(ctx, H, precision == RW_F32, w.hbs);
+  hbs_upload(ctx, H, precision, w.hbs);
   // the multi-RHS apply's crossover to the matrix cores, measured on this inverse
   hbs_autotune(w.hbs, s);
   HIP_CHECK(hipStreamSynchronize(s));
@@ -479,7 +481,7 @@ void build_wall(rw_ctx* ctx, const rw_curve& cv, int P, int q, int leaf, double 
   w.stats.gen_entries = H.entries;
   w.stats.gen_bytes_f64 = 8 * H.entries;
   w.stats.mfma_from_f64 = w.hbs.mfma_from64;
-  w.stats.mfma_from_f32 = w.hbs.mfma_from32;
+  w.stats.mfma_from_f32 = w.hbs.mfma_from32 ? w.hbs.mfma_from32 : w.hbs.mfma_from16;
   w.stats.t_build_ms = wall_ms() - t0;
 }
 
@@ -581,10 +583,10 @@ void woodbury_in(rw_refined* f, const double* src, int nrhs, hipStream_t s = nul
 void woodbury_ref_apply(rw_refined* f, int nrhs) {
   rw_wall* w = f->wall;
   const int64_t M = 2 * f->Next;
-  const double gb = (w->precision == RW_F32 ? 4.0 : 8.0) * w->stats.gen_entries;
+  const double gb = gen_width(w) * w->stats.gen_entries;
   PhaseTimer t(f->ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * nrhs,
-               gb * hbs_gen_passes(nrhs, w->precision == RW_F32));
-  hbs_apply(w, f->ctx, f->gext.p, M, f->y.p, M, nrhs, w->precision == RW_F32);
+               gb * hbs_gen_passes(nrhs, w->precision != RW_F64));
+  hbs_apply(w, f->ctx, f->gext.p, M, f->y.p, M, nrhs, w->precision);
 }
 
 // The A_pp^{-1} block of y on stream s.
@@ -1196,6 +1198,7 @@ int rw_ctx_create(rw_ctx** out, int device, void* hip_stream, size_t hbm_budget_
   c->opt.solver = RW_SOLVE_IR;
   c->opt.gmres_restart = 30;
   c->opt.gmres_precond = 1;
+  c->opt.mfma_from = 0;
   int rc = guarded(c.get(), [&]() {
     hipDeviceProp_t prop;
     HIP_CHECK(hipGetDeviceProperties(&prop, device));
@@ -1242,6 +1245,7 @@ int rw_set_options(rw_ctx* ctx, const rw_options* opt) {
     if (opt->hbs_merge < 1 || opt->hbs_merge > 4) RW_THROW(RW_EINVAL, "hbs_merge outside 1..4");
     if (opt->solver != RW_SOLVE_IR && opt->solver != RW_SOLVE_GMRES) RW_THROW(RW_EINVAL, "unknown solver");
     if (opt->gmres_restart < 1 || opt->gmres_restart > 256) RW_THROW(RW_EINVAL, "gmres_restart outside 1..256");
+    if (opt->mfma_from < 0) RW_THROW(RW_EINVAL, "mfma_from < 0");
     if (opt->sketch_cols != 32 && opt->sketch_cols != 64 && opt->sketch_cols != 96 && opt->sketch_cols != 128)
       RW_THROW(RW_EINVAL, "sketch_cols must be 32, 64, 96 or 128");
     ctx->opt = *opt;
@@ -1318,8 +1322,7 @@ int rw_wall_build(rw_ctx* ctx, const rw_curve* curve, int32_t n_panels, int32_t 
     if (order < 2 || order > 32) RW_THROW(RW_EINVAL, "order outside [2, 32]");
     if (n_panels < 2 || leaf_nodes < order || leaf_nodes % order) RW_THROW(RW_EINVAL, "bad panel / leaf sizes");
     if (!(id_tol > 0 && id_tol < 1)) RW_THROW(RW_EINVAL, "id_tol outside (0, 1)");
-    if (precision == RW_BF16) RW_THROW(RW_EINVAL, "RW_BF16 generators are reserved (not built)");
-    if (precision != RW_F64 && precision != RW_F32) RW_THROW(RW_EINVAL, "unknown precision");
+    if (precision != RW_F64 && precision != RW_F32 && precision != RW_BF16) RW_THROW(RW_EINVAL, "unknown precision");
     if (!(std::fabs(curve->a) < 1.0) || curve->m < 0) RW_THROW(RW_EINVAL, "curve must have |a| < 1, m >= 0");
     std::unique_ptr<rw_wall> w(new rw_wall());
     build_wall(ctx, *curve, n_panels, order, leaf_nodes, id_tol, precision, *w);
@@ -1349,7 +1352,7 @@ int rw_hbs_apply(rw_wall* w, const double* b, int32_t nrhs, double* x) {
   return guarded(w->ctx, [&]() {
     if (nrhs <= 0 || !b || !x) RW_THROW(RW_EINVAL, "bad arguments");
     const int64_t n2 = 2 * (int64_t)w->disc.nodes.size();
-    hbs_apply(w, w->ctx, b, n2, x, n2, nrhs, w->precision == RW_F32);
+    hbs_apply(w, w->ctx, b, n2, x, n2, nrhs, w->precision);
     KERNEL_CHECK("hbs_apply");
   });
 }
@@ -1368,7 +1371,7 @@ int rw_hbs_apply_noalloc(rw_wall* w, const double* b, double* x) {
                               std::to_string(NOALLOC_DOUBLES) + " of rw_hbs_apply_noalloc");
     double* base = g_scratch_ptr[ctx->device];
     if (!base) RW_THROW(RW_EDEVICE, "no-allocation scratch not set up for this device");
-    hbs_dev_apply1_at(w->hbs, b, x, w->precision == RW_F32, base, ctx->stream);
+    hbs_dev_apply1_at(w->hbs, b, x, w->precision, base, ctx->stream);
     KERNEL_CHECK("hbs_apply_noalloc");
     return RW_OK;
   } catch (const RwError& e) {
@@ -1597,10 +1600,10 @@ void batch_sweep(rw_wall* w, const std::vector<rw_refined*>& fs, const std::vect
   }
   for (int q = 0; q < nst; ++q) stream_after(ctx, s, ctx_batch_stream(ctx, q), 11);
   {
-    const double gb = (w->precision == RW_F32 ? 4.0 : 8.0) * w->stats.gen_entries;
+    const double gb = gen_width(w) * w->stats.gen_entries;
     PhaseTimer t(ctx, "a6_hbs_apply", 2.0 * w->stats.gen_entries * C,
-                 gb * hbs_gen_passes((int)C, w->precision == RW_F32));
-    hbs_apply(w, ctx, w->bat_in.p, Mo, w->bat_out.p, Mo, (int)C, w->precision == RW_F32);
+                 gb * hbs_gen_passes((int)C, w->precision != RW_F64));
+    hbs_apply(w, ctx, w->bat_in.p, Mo, w->bat_out.p, Mo, (int)C, w->precision);
   }
   for (int q = 0; q < nst; ++q) stream_after(ctx, ctx_batch_stream(ctx, q), s, 12);
   c0 = 0;

@@ -1,7 +1,7 @@
 """C-ABI boundary behaviour on the GPU: error paths forced from the host
 (RW_ENOCONV, RW_ESINGULAR through the library's own pivot checks), the
 row-ID tolerance q_tol of rw_refine, the rw_solve_info out-parameter, the
-reserved RW_BF16 precision, and run-to-run determinism of the GPU-built
+rejection of an unknown precision, and run-to-run determinism of the GPU-built
 A_pp HBS inverse (Algorithm 1, pre-computation step 2)."""
 import numpy as np
 import pytest
@@ -126,9 +126,9 @@ def test_q_tol_controls_rank(ctx, wall64):
     assert ei.value.code == rw.RW_EINVAL
 
 
-def test_bf16_reserved(ctx):
+def test_unknown_precision_rejected(ctx):
     with pytest.raises(rw.RwError) as ei:
-        rw.Wall(ctx, 64, precision=rw.RW_BF16)
+        rw.Wall(ctx, 64, precision=7)
     assert ei.value.code == rw.RW_EINVAL
 
 
