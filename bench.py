@@ -493,6 +493,10 @@ def main():
             ref4 = w4.refine(p4.refinement.panel_ids, p4.refinement.levels)
             g4 = torch.stack([ref4.stokeslet_rhs(q.z, q.f) for q in p4.rhs]).contiguous()
             tau4 = torch.empty_like(g4)
+            # BF16 generators are refined by preconditioned GMRES: Richardson
+            # stalls with them at this size (residual 7e-3 after 6 corrections)
+            solver = rw.RW_SOLVE_GMRES if prec == rw.RW_BF16 else rw.RW_SOLVE_IR
+            ctx.set_options(solver=solver, ir_maxit=60 if solver == rw.RW_SOLVE_GMRES else 6)
             rw.rw_solve(ctx.h, ref4.h, g4, tau4, ref4.n_unknowns)
             ts, its, res = [], 0, 0.0
             for _ in range(reps):
@@ -520,7 +524,9 @@ def main():
                 gen_b = width * st4["gen_entries"]
                 rates[f"apply_{nr}rhs_us"] = us
                 rates[f"apply_{nr}rhs_GBps_per_pass"] = gen_b / (us * 1e-6) / 1e9
+            ctx.set_options(solver=rw.RW_SOLVE_IR, ir_maxit=6)
             out[name] = {"solve_32rhs_ms": float(np.median(ts)), "corrections": its, "resid": res,
+                         "solver": "GMRES" if solver == rw.RW_SOLVE_GMRES else "Richardson",
                          "refined_nodes": int(ref4.n_nodes), "k": int(ref4.info()["k"]),
                          "gen_bytes": {rw.RW_F64: 8, rw.RW_F32: 4, rw.RW_BF16: 2}[prec] * st4["gen_entries"],
                          "mfma_from": st4["mfma_from_f64"] if prec == rw.RW_F64 else st4["mfma_from_f32"], **rates}
@@ -600,12 +606,19 @@ def main():
             ctx.set_options(ir_tol=old["ir_tol"])
         return out
 
-    side = {"hbs_apply_1rhs": hbs_apply_rates(wall)}
+    def guard(fn, *a):
+        """A side measurement that fails is reported, not fatal to the line."""
+        try:
+            return fn(*a)
+        except Exception as e:  # noqa: BLE001
+            return {"error": f"{type(e).__name__}: {e}"}
+
+    side = {"hbs_apply_1rhs": guard(hbs_apply_rates, wall)}
     if args.extra_steps > 0:
-        side["config4_mixed_precision"] = config4_mixed()
-        side["serving_config5"] = serving()
-        side["batched_fp64"] = batched(wall, 64)
-        side["fp64_resident_factors"] = rhs_rate(wall, args.extra_steps)
+        side["config4_mixed_precision"] = guard(config4_mixed)
+        side["serving_config5"] = guard(serving)
+        side["batched_fp64"] = guard(batched, wall, 64)
+        side["fp64_resident_factors"] = guard(rhs_rate, wall, args.extra_steps)
         w32 = rw.Wall(ctx, 1024, precision=rw.RW_F32)
         side["fp32_generators"] = {"refined_solves": solve_rate(w32, args.extra_steps),
                                    "resident_factors": rhs_rate(w32, args.extra_steps),
