@@ -606,6 +606,47 @@ def main():
             ctx.set_options(ir_tol=old["ir_tol"])
         return out
 
+    def time_stepping(n_steps: int = 40, margin: int = 4):
+        """A particle moving along the 16384-node wall at 0.3 panel widths per
+        step asks for its 16 nearest panels refined 4 levels (one RHS of 16
+        Stokeslets per step): refined-wall solves with the refinement cache
+        (Sec. 5.3: snapshots share a refinement of a region widened by
+        `margin` panels) against a fresh rw_refine every step."""
+        curve = W.Curve()
+        hpan = 2 * math.pi / 1024
+        rng = np.random.default_rng(99)
+        sts = [W.stokeslets(rng, 16) for _ in range(n_steps)]
+        reqs = []
+        for t in range(n_steps):
+            th = 0.7 + 0.3 * hpan * t
+            reqs.append(W.nearest_panels(curve, 1024, curve.point(th) + 1e-3 * curve.outward_normal(th), 16))
+
+        def run(use_cache: bool):
+            cache = rw.RefCache(wall, capacity=2, margin=margin) if use_cache else None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ok = 0
+            for ids, stk in zip(reqs, sts):
+                if cache:
+                    ref, _ = cache.get(ids, [4] * len(ids))
+                else:
+                    ref = wall.refine(ids, [4] * len(ids))
+                gq = ref.stokeslet_rhs(stk.z, stk.f)
+                ok += int(rw.rw_solve(ctx.h, ref.h, gq, torch.empty_like(gq), ref.n_unknowns, check=False) == rw.RW_OK)
+                if not cache:
+                    ref.close()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            st_c = cache.stats() if cache else None
+            if cache:
+                cache.close()
+            return ok / el, st_c
+
+        rate_c, st_c = run(True)
+        rate_f, _ = run(False)
+        return {"steps": n_steps, "margin": margin, "cached_solves_per_s": rate_c, "fresh_solves_per_s": rate_f,
+                "speedup": rate_c / rate_f, "cache": st_c}
+
     def guard(fn, *a):
         """A side measurement that fails is reported, not fatal to the line."""
         try:
@@ -617,6 +658,7 @@ def main():
     if args.extra_steps > 0:
         side["config4_mixed_precision"] = guard(config4_mixed)
         side["serving_config5"] = guard(serving)
+        side["time_stepping_refcache"] = guard(time_stepping)
         side["batched_fp64"] = guard(batched, wall, 64)
         side["fp64_resident_factors"] = guard(rhs_rate, wall, args.extra_steps)
         w32 = rw.Wall(ctx, 1024, precision=rw.RW_F32)

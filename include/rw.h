@@ -320,6 +320,37 @@ int rw_residual(rw_refined* ref, const double* g_dev, const double* tau_dev,
 int rw_stokeslet_rhs(rw_refined* ref, const double* z_host, const double* f_host,
                      int32_t n_src, double* g_dev);
 
+/* ---- refinement reuse across time steps (Sec. 5.3: several snapshots can
+ *      use the same refinement) --------------------------------------- */
+
+typedef struct rw_refcache rw_refcache;
+
+/* A cache of refinements of `wall` (n_panels reference panels; the wall's
+ * ctx runs them), at most `capacity` of them.  rw_refcache_get serves a
+ * request with a cached refinement that covers it (every requested panel
+ * refined at least as deep; the least refined such one); a miss refines
+ * the requested panels widened by `margin` panels on both sides (each at
+ * the deepest requested level within margin panels; runs whose widened
+ * ranges touch form one region), caches it and frees the least recently
+ * used one when full.  q_tol as rw_refine.  Errors: RW_EINVAL. */
+int rw_refcache_create(rw_wall* wall, int32_t n_panels, int32_t capacity, int32_t margin, double q_tol,
+                       rw_refcache** out);
+/* *out: a refined handle owned by the cache (do not free it), valid until
+ * the next rw_refcache_get on the cache or rw_refcache_destroy.  Its
+ * discretization is the covering one: sample right-hand sides on its nodes
+ * (rw_nodes, rw_stokeslet_rhs); rw_refcache_panels lists its refined
+ * panels.  *hit (may be NULL): 1 if a cached refinement served it.  Errors
+ * as rw_refine. */
+int rw_refcache_get(rw_refcache* c, const int32_t* panel_ids_host, const int32_t* levels_host, int32_t n_sel,
+                    rw_refined** out, int32_t* hit);
+/* Refined panels and levels of a handle of the cache; *n in: capacity
+ * (NULL arrays: size query), out: count.  Errors: RW_EINVAL. */
+int rw_refcache_panels(const rw_refcache* c, const rw_refined* ref, int32_t* ids_host, int32_t* levels_host,
+                       int32_t* n);
+void rw_refcache_stats(const rw_refcache* c, int64_t* hits, int64_t* misses, int32_t* held);
+void rw_refcache_destroy(rw_refcache* c);
+const char* rw_refcache_error(const rw_refcache* c);
+
 /* ---- serving (the time-stepping workflow of Sec. 5.3 served to many
  *      independent requests against one resident wall) ----------------- */
 

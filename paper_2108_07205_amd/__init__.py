@@ -27,7 +27,7 @@ __all__ = [
     "rw_refined_free", "rw_refined_info", "rw_nodes", "rw_solve", "rw_residual", "rw_stokeslet_rhs",
     "rw_ctx_trim", "rw_profile_enable", "rw_profile_reset", "rw_profile_json",
     "RW_OK", "RW_EINVAL", "RW_ENOMEM", "RW_ESINGULAR", "RW_ENOCONV", "RW_EDEVICE", "RW_F64", "RW_F32",
-    "RW_BF16", "RW_SOLVE_IR", "RW_SOLVE_GMRES", "rw_solve_batch", "rw_refine_on", "Server",
+    "RW_BF16", "RW_SOLVE_IR", "RW_SOLVE_GMRES", "rw_solve_batch", "rw_refine_on", "Server", "RefCache",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -126,6 +126,13 @@ _SIGS = {
     "rw_server_wait": (ctypes.c_int, [_P, ctypes.c_int64, _DP, ctypes.c_int64, ctypes.POINTER(rw_request_info)]),
     "rw_server_destroy": (None, [_P]),
     "rw_server_error": (ctypes.c_char_p, [_P]),
+    "rw_refcache_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                          ctypes.POINTER(_P)]),
+    "rw_refcache_get": (ctypes.c_int, [_P, _I32P, _I32P, ctypes.c_int32, ctypes.POINTER(_P), _I32P]),
+    "rw_refcache_panels": (ctypes.c_int, [_P, _P, _I32P, _I32P, _I32P]),
+    "rw_refcache_stats": (None, [_P, _I64P, _I64P, _I32P]),
+    "rw_refcache_destroy": (None, [_P]),
+    "rw_refcache_error": (ctypes.c_char_p, [_P]),
 }
 EXPORTED_SYMBOLS = tuple(_SIGS)
 
@@ -618,6 +625,71 @@ class Refined:
         if self.h:
             if self.wall.h and self.ctx.h:
                 rw_refined_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _CachedRefined(Refined):
+    """A refined handle owned by a RefCache (never freed by itself)."""
+
+    def __init__(self, cache: "RefCache", h):
+        self.wall = cache.wall
+        self.ctx = cache.wall.ctx
+        self.h = h
+        self._refresh()
+
+    def close(self):
+        self.h = None
+
+
+class RefCache:
+    """rw_refcache_*: refinements reused across time steps (Sec. 5.3)."""
+
+    def __init__(self, wall: "Wall", capacity: int = 4, margin: int = 2, q_tol: float = 0.0):
+        self.wall = wall
+        self.h = None
+        out = _P()
+        rc = load_library().rw_refcache_create(wall.h, wall.n_panels, capacity, margin, q_tol, ctypes.byref(out))
+        if rc != RW_OK:
+            raise RwError(rc, load_library().rw_refcache_error(None).decode())
+        self.h = out
+        wall._children.add(self)
+
+    def get(self, panel_ids, levels):
+        """(refined handle covering the request, hit flag)."""
+        ids = np.ascontiguousarray(panel_ids, dtype=np.int32)
+        lev = np.ascontiguousarray(levels, dtype=np.int32)
+        out = _P()
+        hit = ctypes.c_int32(0)
+        rc = load_library().rw_refcache_get(self.h, ids.ctypes.data_as(_I32P), lev.ctypes.data_as(_I32P), ids.size,
+                                            ctypes.byref(out), ctypes.byref(hit))
+        if rc != RW_OK:
+            raise RwError(rc, load_library().rw_refcache_error(self.h).decode() or
+                          load_library().rw_last_error(self.wall.ctx.h).decode())
+        return _CachedRefined(self, out), bool(hit.value)
+
+    def panels(self, ref):
+        n = ctypes.c_int32(0)
+        _check(load_library().rw_refcache_panels(self.h, ref.h, None, None, ctypes.byref(n)), self.wall.ctx.h)
+        ids = np.empty(n.value, np.int32)
+        lev = np.empty(n.value, np.int32)
+        _check(load_library().rw_refcache_panels(self.h, ref.h, ids.ctypes.data_as(_I32P), lev.ctypes.data_as(_I32P),
+                                                 ctypes.byref(n)), self.wall.ctx.h)
+        return ids, lev
+
+    def stats(self):
+        h, m, k = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int32(0)
+        load_library().rw_refcache_stats(self.h, ctypes.byref(h), ctypes.byref(m), ctypes.byref(k))
+        return {"hits": h.value, "misses": m.value, "held": k.value}
+
+    def close(self):
+        if self.h:
+            load_library().rw_refcache_destroy(self.h)
             self.h = None
 
     def __del__(self):
