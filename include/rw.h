@@ -100,8 +100,9 @@ typedef struct {
   int32_t mfma_from;         /* multi-RHS applies of a wall's inverse on the matrix cores from this many
                                 right-hand sides; 0 = the crossover rw_wall_build measured [0] */
   int32_t test_singular;     /* test hook, 0 in normal use [0]: 1 = zero the first column of W = I + R X
-                                before its inversion, 2 = zero the first column of a dense A_pp before
-                                its LU; the library's own pivot checks then report RW_ESINGULAR */
+                                before its inversion, whose pivot check then reports RW_ESINGULAR; 2 =
+                                zero the first column of a dense A_pp before its LU, whose pivot check
+                                then hands A_pp to the GPU-built HBS inverse */
 } rw_options;
 
 /* Counts and timings reported by rw_refine / rw_solve. */
@@ -119,6 +120,9 @@ typedef struct {
                                 LU or no added nodes); set once the refinement's device-side checks
                                 have been read (by the first rw_solve / rw_residual on the handle) */
   int32_t app_max_rank;      /* largest node rank of that HBS inverse (0 as above) */
+  double app_lu_mult;        /* largest |entry of L| of the unpivoted dense LU of A_pp (+inf for a zero
+                                pivot, 0 when no dense LU ran); above 1e3 the dense LU is dropped and
+                                A_pp^{-1} is the GPU-built HBS inverse (app_entries > 0) instead */
 } rw_info;
 
 /* Outcome of one rw_solve (Algorithm 1 solve steps + refinement). */

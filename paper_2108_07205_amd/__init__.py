@@ -64,7 +64,8 @@ class rw_info(ctypes.Structure):
                 ("k_k", ctypes.c_int32), ("k_p", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("ir_iters", ctypes.c_int32), ("resid", ctypes.c_double),
                 ("t_refine_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double), ("n_near", ctypes.c_int64),
-                ("app_entries", ctypes.c_int64), ("app_max_rank", ctypes.c_int32)]
+                ("app_entries", ctypes.c_int64), ("app_max_rank", ctypes.c_int32),
+                ("app_lu_mult", ctypes.c_double)]
 
 
 class rw_solve_info(ctypes.Structure):

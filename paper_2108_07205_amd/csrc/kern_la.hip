@@ -644,10 +644,19 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(const double* __restric
 // ================================================================ LU (no pivoting)
 constexpr int LU_NB = 64;
 
+// Largest |multiplier| seen by a wavefront, folded into *mult (the bits of a
+// non-negative double order as the double does); NaN counts as infinity.
+__device__ void lu_note_mult(double m, unsigned long long* mult) {
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0 && m > 0.0) atomicMax(mult, (unsigned long long)__double_as_longlong(m));
+}
+
 // Block 0: factor A11 and write it back; blocks 1..nrt: L21 tiles; the rest:
-// U12 tiles.  Every block factors A11 in LDS from the same input.
+// U12 tiles.  Every block factors A11 in LDS from the same input.  Blocks 0
+// .. nrt fold the largest |multiplier| (entry of L) they produce into *mult.
 __global__ __launch_bounds__(256) void lu_panel_kernel(double* __restrict__ A, int64_t n, int64_t ld, int64_t K0,
-                                                       int nrt, int* __restrict__ info) {
+                                                       int nrt, int* __restrict__ info,
+                                                       unsigned long long* __restrict__ mult) {
   __shared__ double D[LU_NB][LU_NB + 1];
   __shared__ double T[LU_NB][LU_NB + 1];
   const int tid = threadIdx.x;
@@ -657,13 +666,18 @@ __global__ __launch_bounds__(256) void lu_panel_kernel(double* __restrict__ A, i
     D[r][c] = A[K0 + r + (K0 + c) * ld];
   }
   __syncthreads();
+  double mmax = 0.0;
   for (int j = 0; j < nb; ++j) {
     const double pv = D[j][j];
     if (!(fabs(pv) > 0.0) || !isfinite(pv)) {
       if (blockIdx.x == 0 && tid == 0 && *info == 0) *info = (int)(K0 + j + 1);
       return;
     }
-    for (int i = j + 1 + tid; i < nb; i += 256) D[i][j] /= pv;
+    for (int i = j + 1 + tid; i < nb; i += 256) {
+      const double l = D[i][j] / pv;
+      D[i][j] = l;
+      mmax = fabs(l) <= mmax ? mmax : (isnan(l) ? INFINITY : fabs(l));
+    }
     __syncthreads();
     const int rem = nb - j - 1;
     for (int idx = tid; idx < rem * rem; idx += 256) {
@@ -678,6 +692,7 @@ __global__ __launch_bounds__(256) void lu_panel_kernel(double* __restrict__ A, i
       const int r = idx % nb, c = idx / nb;
       A[K0 + r + (K0 + c) * ld] = D[r][c];
     }
+    lu_note_mult(mmax, mult);
     return;
   }
   const int64_t start = K0 + nb;
@@ -690,11 +705,14 @@ __global__ __launch_bounds__(256) void lu_panel_kernel(double* __restrict__ A, i
       T[r][c] = A[rbase + r + (K0 + c) * ld];
     }
     __syncthreads();
+    double lm = 0.0;
     if (tid < rows) {
       for (int c = 0; c < nb; ++c) {
         double v = T[tid][c];
         for (int t = 0; t < c; ++t) v -= T[tid][t] * D[t][c];
-        T[tid][c] = v / D[c][c];
+        const double l = v / D[c][c];
+        T[tid][c] = l;
+        lm = fabs(l) <= lm ? lm : (isnan(l) ? INFINITY : fabs(l));
       }
     }
     __syncthreads();
@@ -702,6 +720,7 @@ __global__ __launch_bounds__(256) void lu_panel_kernel(double* __restrict__ A, i
       const int r = idx % rows, c = idx / rows;
       A[rbase + r + (K0 + c) * ld] = T[r][c];
     }
+    lu_note_mult(lm, mult);
   } else {
     // U12 tile: cols start + (b-1-nrt)*64 ..; solve L11 Y = A12 (unit lower)
     const int64_t cbase = start + (int64_t)(b - 1 - nrt) * LU_NB;
@@ -1021,8 +1040,6 @@ void launch_small_gemm(const double* Winv, int k, const double* z, int nrhs, dou
   KERNEL_CHECK("small_gemm");
 }
 
-size_t lu_work_doubles(int64_t n) { (void)n; return 0; }
-
 void launch_gemm_nn_sub(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc, int64_t m,
                         int64_t n, int64_t kk, hipStream_t s) {
   if (m <= 0 || n <= 0 || kk <= 0) return;
@@ -1037,14 +1054,14 @@ void launch_gemm_nn_sub(const double* A, int64_t lda, const double* B, int64_t l
   KERNEL_CHECK("gemm_nn_sub");
 }
 
-void launch_lu_nopiv(double* A, int64_t n, int64_t ld, int* info, double* work, hipStream_t s) {
-  (void)work;
+void launch_lu_nopiv(double* A, int64_t n, int64_t ld, int* info, unsigned long long* mult, hipStream_t s) {
   HIP_CHECK(hipMemsetAsync(info, 0, sizeof(int), s));
+  HIP_CHECK(hipMemsetAsync(mult, 0, sizeof(unsigned long long), s));
   for (int64_t K0 = 0; K0 < n; K0 += LU_NB) {
     const int nb = (int)std::min<int64_t>(LU_NB, n - K0);
     const int64_t rest = n - K0 - nb;
     const int nrt = (int)((rest + LU_NB - 1) / LU_NB);
-    hipLaunchKernelGGL(lu_panel_kernel, dim3(1 + 2 * nrt), dim3(256), 0, s, A, n, ld, K0, nrt, info);
+    hipLaunchKernelGGL(lu_panel_kernel, dim3(1 + 2 * nrt), dim3(256), 0, s, A, n, ld, K0, nrt, info, mult);
     KERNEL_CHECK("lu_panel");
     if (rest > 0)
       launch_gemm_nn_sub(A + (K0 + nb) + K0 * ld, ld, A + K0 + (K0 + nb) * ld, ld, A + (K0 + nb) + (K0 + nb) * ld, ld,

@@ -164,9 +164,10 @@ void launch_small_gemm(const double* Winv, int k, const double* z, int nrhs, dou
 bool launch_woodbury_sub(const double* X, int64_t ldx, int64_t M, int k, const double* Winv, const double* z,
                          double* Y, int64_t ldy, int nrhs, hipStream_t s);
 
-// unpivoted blocked LU of an n x n matrix (ld), in place; *info = first tiny pivot + 1
-void launch_lu_nopiv(double* A, int64_t n, int64_t ld, int* info, double* work, hipStream_t s);
-size_t lu_work_doubles(int64_t n);
+// unpivoted blocked LU of an n x n matrix (ld), in place; *info = first zero
+// or non-finite pivot + 1 (0 if none); *mult = bits of the largest |entry of
+// L| (a growth measure: partial pivoting would keep it <= 1)
+void launch_lu_nopiv(double* A, int64_t n, int64_t ld, int* info, unsigned long long* mult, hipStream_t s);
 // B = U^{-1} L^{-1} B (nrhs columns, ldb) with the factors of launch_lu_nopiv
 void launch_lu_solve(const double* LU, int64_t n, int64_t ld, double* B, int64_t ldb, int nrhs,
                      hipStream_t s);

@@ -656,8 +656,16 @@ void validate_selection(const rw_wall* w, const int32_t* ids, const int32_t* lev
   }
 }
 
+// Largest |entry of L| accepted from the unpivoted dense LU of A_pp.  A_pp
+// is a second-kind matrix (-1/2 I plus a smooth part), whose multipliers
+// stay far below 1; a larger one means growth that partial pivoting would
+// have avoided, and A_pp then goes to the HBS inverse, whose node blocks are
+// factored with pivoting.
+constexpr double kAppLuMultMax = 1e3;
+
 // Algorithm 1, pre-computation step 2: an inverse of A_pp on ctx ax (its
-// own stream): dense LU for few added points, else the GPU-built HBS inverse.
+// own stream): dense LU for few added points, else (or when the LU meets a
+// zero pivot or a multiplier above kAppLuMultMax) the GPU-built HBS inverse.
 void build_app_inverse(rw_wall* w, rw_refined& f, uint64_t seed, rw_ctx* ax) {
   hipStream_t s = ax->stream;
   const int64_t Mp = 2 * f.Np;
@@ -666,7 +674,7 @@ void build_app_inverse(rw_wall* w, rw_refined& f, uint64_t seed, rw_ctx* ax) {
     hbs_gpu_build(ax, f.d_p.p, f.pnodes, w->leaf, w->tol, seed, f.app_hbs);
     return;
   }
-  DBuf<int> dinfo(ax, 1);
+  DBuf<int> dinfo(ax, 4);   // pivot flag, then (8-byte aligned) the multiplier bits
   f.App.alloc(ax, (size_t)Mp * Mp);
   {
     PhaseTimer t(ax, "a3_app_assemble", 0.0, 8.0 * (double)Mp * Mp);
@@ -676,12 +684,21 @@ void build_app_inverse(rw_wall* w, rw_refined& f, uint64_t seed, rw_ctx* ax) {
   if (ax->opt.test_singular == 2) HIP_CHECK(hipMemsetAsync(f.App.p, 0, sizeof(double) * Mp, s));
   {
     PhaseTimer t(ax, "a3_app_lu", 2.0 / 3.0 * (double)Mp * Mp * Mp, 0.0);
-    launch_lu_nopiv(f.App.p, Mp, Mp, dinfo.p, nullptr, s);
+    launch_lu_nopiv(f.App.p, Mp, Mp, dinfo.p, (unsigned long long*)(dinfo.p + 2), s);
   }
-  int info = 0;
-  HIP_CHECK(hipMemcpyAsync(&info, dinfo.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  int hinfo[4] = {0, 0, 0, 0};
+  HIP_CHECK(hipMemcpyAsync(hinfo, dinfo.p, sizeof(hinfo), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
-  if (info) RW_THROW(RW_ESINGULAR, "zero pivot " + std::to_string(info) + " in the LU of A_pp");
+  unsigned long long bits = 0;
+  memcpy(&bits, hinfo + 2, sizeof(bits));
+  double mult = 0.0;
+  memcpy(&mult, &bits, sizeof(mult));
+  f.info.app_lu_mult = hinfo[0] ? INFINITY : mult;
+  if (hinfo[0] == 0 && mult <= kAppLuMultMax) return;
+  f.App = DBuf<double>();
+  f.app_hbs_on = true;
+  PhaseTimer t(ax, "a3_app_hbs_build", 0.0, 0.0);
+  hbs_gpu_build(ax, f.d_p.p, f.pnodes, w->leaf, w->tol, seed, f.app_hbs);
 }
 
 // Algorithm 1 pre-computation for the refinement described by level_of_panel,
@@ -785,6 +802,7 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
   // ---- a3: A_pp^{-1} (dense LU for few added points, else a GPU-built HBS
   // inverse) on the helper ctx, beside the compression of Q on this stream
   f.app_hbs_on = f.Np > ctx->opt.app_dense_max_nodes;
+  f.info.app_lu_mult = 0.0;
   AuxTask a3;
   if (f.Np > 0) {
     const uint64_t seed = ctx->opt.seed ^ 0x3C6EF372FE94F82Bull;
