@@ -103,6 +103,10 @@ typedef struct {
                                 before its inversion, whose pivot check then reports RW_ESINGULAR; 2 =
                                 zero the first column of a dense A_pp before its LU, whose pivot check
                                 then hands A_pp to the GPU-built HBS inverse */
+  int32_t one_stream;        /* 1 = every step of rw_refine and rw_solve on the ctx's own stream, with no
+                                helper thread and no side streams (the A_pp inverse then runs before the
+                                compression of Q instead of beside it): for contexts that run side by side,
+                                each on one hardware queue, such as the slots of rw_server_create [0] */
 } rw_options;
 
 /* Counts and timings reported by rw_refine / rw_solve. */
@@ -373,7 +377,8 @@ typedef struct {
 } rw_request_info;
 
 /* A server of `slots` worker threads (1..16), each with a ctx and stream of
- * its own (the options of `ctx` copied), that run whole requests against
+ * its own (the options of `ctx` copied; with more than one slot, each slot's
+ * ctx keeps to its one stream: one_stream = 1), that run whole requests against
  * `wall` (n_panels reference panels; built on ctx, resident, only read):
  * rw_refine_on, Stokeslet data, rw_solve, result copied back.  Requests
  * leave the queue in order as soon as a slot is free and the device memory

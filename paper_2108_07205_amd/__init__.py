@@ -56,7 +56,8 @@ class rw_options(ctypes.Structure):
                 ("sketch_cols", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("app_dense_max_nodes", ctypes.c_int32), ("far_field", ctypes.c_int32),
                 ("hbs_merge", ctypes.c_int32), ("solver", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
-                ("gmres_precond", ctypes.c_int32), ("mfma_from", ctypes.c_int32), ("test_singular", ctypes.c_int32)]
+                ("gmres_precond", ctypes.c_int32), ("mfma_from", ctypes.c_int32), ("test_singular", ctypes.c_int32),
+                ("one_stream", ctypes.c_int32)]
 
 
 class rw_info(ctypes.Structure):
@@ -206,7 +207,7 @@ def rw_ctx_destroy(ctx):
 
 def rw_set_options(ctx, ir_tol=None, ir_maxit=None, sketch_cols=None, seed=None, app_dense_max_nodes=None,
                    far_field=None, test_singular=None, hbs_merge=None, solver=None, gmres_restart=None,
-                   gmres_precond=None, mfma_from=None):
+                   gmres_precond=None, mfma_from=None, one_stream=None):
     lib = load_library()
     o = rw_options()
     _check(lib.rw_get_options(ctx, ctypes.byref(o)), ctx)
@@ -234,6 +235,8 @@ def rw_set_options(ctx, ir_tol=None, ir_maxit=None, sketch_cols=None, seed=None,
         o.gmres_precond = int(gmres_precond)
     if mfma_from is not None:
         o.mfma_from = int(mfma_from)
+    if one_stream is not None:
+        o.one_stream = int(bool(one_stream))
     _check(lib.rw_set_options(ctx, ctypes.byref(o)), ctx)
 
 

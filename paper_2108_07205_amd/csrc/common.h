@@ -92,6 +92,12 @@ struct rw_ctx {
   size_t pinned_bytes = 0;
   void* rb = nullptr;
   size_t rb_bytes = 0;
+  // pinned area of the GPU HBS build on this ctx (node records and candidate
+  // lists going down, the records and flags coming back), used by nothing
+  // else: the records stay there until the refinement is settled, which
+  // happens before the next build on the ctx
+  void* hbs_pin = nullptr;
+  size_t hbs_pin_bytes = 0;
   // event after the last enqueued copy out of `pinned` (ctx_pinned waits
   // for it before handing the buffer out again)
   hipEvent_t pinned_ev = nullptr;
@@ -157,6 +163,9 @@ void func_lds_at_least(const void* fn, int bytes);
 // Pinned read-back area of at least `bytes` (grow-only; its contents are
 // valid until the next call that reads back on this ctx).
 void* ctx_readback(rw_ctx* ctx, size_t bytes);
+// The ctx's pinned area of the GPU HBS build (rw_ctx::hbs_pin), at least
+// `bytes` (grow-only; growing waits for the ctx's stream first).
+void* ctx_hbs_pinned(rw_ctx* ctx, size_t bytes);
 // `waiter` waits for everything enqueued on `src` so far (event i).
 void stream_after(rw_ctx* ctx, hipStream_t waiter, hipStream_t src, int i);
 
@@ -166,13 +175,19 @@ void stream_after(rw_ctx* ctx, hipStream_t waiter, hipStream_t src, int i);
 // error.  Between
 // the two, the caller's thread may use ctx but not the helper, and fn may
 // use the helper but not ctx.  AuxTask joins (ignoring errors) if the caller
-// leaves early.
+// leaves early.  With the ctx's one_stream option, AuxTask runs fn(ctx) at
+// once on the caller's thread and stream instead.
 void aux_fork(rw_ctx* ctx, std::function<void(rw_ctx*)> fn);
 void aux_join(rw_ctx* ctx, hipStream_t into = nullptr);
 struct AuxTask {
   rw_ctx* ctx = nullptr;
   bool active = false;
-  void fork(rw_ctx* c, std::function<void(rw_ctx*)> fn) { aux_fork(c, std::move(fn)); ctx = c; active = true; }
+  void fork(rw_ctx* c, std::function<void(rw_ctx*)> fn) {
+    if (c->opt.one_stream) { fn(c); return; }
+    aux_fork(c, std::move(fn));
+    ctx = c;
+    active = true;
+  }
   void join(hipStream_t into = nullptr) { if (active) { active = false; aux_join(ctx, into); } }
   ~AuxTask() { if (active) { active = false; try { aux_join(ctx); } catch (...) {} } }
 };

@@ -2118,7 +2118,7 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
   w.groot.alloc(ctx, (size_t)(2 * SK_KCAP) * (2 * SK_KCAP));
   HIP_CHECK(hipMemsetAsync(ctl.p, 0, sizeof(int64_t) * ctl.n, s));
   // pinned staging: node records (level l at [2^l, 2^(l+1))) and the leaf candidate lists
-  char* pin = (char*)ctx_pinned(ctx, sizeof(GNode) * (size_t)(int64_t(2) << L) + sizeof(int64_t) * 4 +
+  char* pin = (char*)ctx_hbs_pinned(ctx, sizeof(GNode) * (size_t)(int64_t(2) << L) + sizeof(int64_t) * 4 +
                                           sizeof(int) * (size_t)(2 * N));
   GNode* hG = (GNode*)pin;
   int64_t* hCtl = (int64_t*)(pin + sizeof(GNode) * (size_t)(int64_t(2) << L));

@@ -158,11 +158,13 @@ KernelTimer::KernelTimer(const char* name, double flops, double bytes, hipStream
 KernelTimer::~KernelTimer() { delete t; }
 
 hipStream_t ctx_side_stream(rw_ctx* ctx) {
+  if (ctx->opt.one_stream) return ctx->stream;
   if (!ctx->side) HIP_CHECK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
   return ctx->side;
 }
 
 hipStream_t ctx_side2_stream(rw_ctx* ctx) {
+  if (ctx->opt.one_stream) return ctx->stream;
   if (!ctx->side2) HIP_CHECK(hipStreamCreateWithFlags(&ctx->side2, hipStreamNonBlocking));
   return ctx->side2;
 }
@@ -230,7 +232,22 @@ void* ctx_readback(rw_ctx* ctx, size_t bytes) {
   return ctx->rb;
 }
 
+void* ctx_hbs_pinned(rw_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->hbs_pin_bytes) return ctx->hbs_pin;
+  if (ctx->hbs_pin) {
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    (void)hipHostFree(ctx->hbs_pin);
+    ctx->hbs_pin = nullptr;
+    ctx->hbs_pin_bytes = 0;
+  }
+  bytes = std::max<size_t>(bytes, size_t(256) << 10);
+  HIP_CHECK(hipHostMalloc(&ctx->hbs_pin, bytes, hipHostMallocDefault));
+  ctx->hbs_pin_bytes = bytes;
+  return ctx->hbs_pin;
+}
+
 void stream_after(rw_ctx* ctx, hipStream_t waiter, hipStream_t src, int i) {
+  if (waiter == src) return;
   hipEvent_t e = ctx_order_event(ctx, i);
   HIP_CHECK(hipEventRecord(e, src));
   HIP_CHECK(hipStreamWaitEvent(waiter, e, 0));
@@ -339,6 +356,7 @@ static void ctx_destroy_aux(rw_ctx* ctx) {
     if (a->side2) (void)hipStreamDestroy(a->side2);
     if (a->pinned) (void)hipHostFree(a->pinned);
     if (a->rb) (void)hipHostFree(a->rb);
+    if (a->hbs_pin) (void)hipHostFree(a->hbs_pin);
     (void)hipStreamDestroy(a->stream);
     delete a;
     ctx->aux = nullptr;
@@ -1212,6 +1230,7 @@ int rw_ctx_create(rw_ctx** out, int device, void* hip_stream, size_t hbm_budget_
   c->opt.app_dense_max_nodes = 1024;
   c->opt.far_field = 1;
   c->opt.test_singular = 0;
+  c->opt.one_stream = 0;
   c->opt.hbs_merge = 2;
   c->opt.solver = RW_SOLVE_IR;
   c->opt.gmres_restart = 30;
@@ -1247,6 +1266,7 @@ void rw_ctx_destroy(rw_ctx* ctx) {
   for (auto st : ctx->bstreams) (void)hipStreamDestroy(st);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->rb) (void)hipHostFree(ctx->rb);
+  if (ctx->hbs_pin) (void)hipHostFree(ctx->hbs_pin);
   if (ctx->pinned_ev) (void)hipEventDestroy(ctx->pinned_ev);
   if (ctx->defer_pin) (void)hipHostFree(ctx->defer_pin);
   delete ctx;
@@ -1264,6 +1284,7 @@ int rw_set_options(rw_ctx* ctx, const rw_options* opt) {
     if (opt->solver != RW_SOLVE_IR && opt->solver != RW_SOLVE_GMRES) RW_THROW(RW_EINVAL, "unknown solver");
     if (opt->gmres_restart < 1 || opt->gmres_restart > 256) RW_THROW(RW_EINVAL, "gmres_restart outside 1..256");
     if (opt->mfma_from < 0) RW_THROW(RW_EINVAL, "mfma_from < 0");
+    if (opt->one_stream != 0 && opt->one_stream != 1) RW_THROW(RW_EINVAL, "one_stream must be 0 or 1");
     if (opt->sketch_cols != 32 && opt->sketch_cols != 64 && opt->sketch_cols != 96 && opt->sketch_cols != 128)
       RW_THROW(RW_EINVAL, "sketch_cols must be 32, 64, 96 or 128");
     ctx->opt = *opt;
@@ -1580,6 +1601,7 @@ namespace {
 // non-blocking, default priority; destroyed with the ctx).
 constexpr int BATCH_STREAMS = 4;
 hipStream_t ctx_batch_stream(rw_ctx* ctx, int i) {
+  if (ctx->opt.one_stream) return ctx->stream;
   if (ctx->bstreams.empty()) {
     ctx->bstreams.assign(BATCH_STREAMS, nullptr);
     for (auto& st : ctx->bstreams) HIP_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));

@@ -228,6 +228,10 @@ int rw_server_create(rw_ctx* ctx, rw_wall* wall, int32_t n_panels, int32_t slots
   }
   rw_options opt{};
   rw_get_options(ctx, &opt);
+  // several slots: each request on its slot's one stream, so that the slots
+  // overlap on separate hardware queues instead of a request's side streams
+  // sharing queues with the other slots' work
+  if (slots > 1) opt.one_stream = 1;
   for (int s = 0; s < slots; ++s) {
     std::unique_ptr<rw_server::Slot> sl(new rw_server::Slot());
     if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) {

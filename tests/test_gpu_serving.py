@@ -80,3 +80,32 @@ def test_mix_equals_alone_full_size_and_admission():
     assert all(s[1]["status"] == rw.RW_OK for s in seq)
     wall.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("app_dense_max_nodes", [1024, 0])
+def test_one_stream_ctx_matches_default(app_dense_max_nodes):
+    """A ctx with one_stream = 1 (what each slot of a multi-slot server
+    uses: A_pp^{-1} built before the compression of Q, on the same stream,
+    no helper thread) gives the same refinement and solution as the default
+    ctx, for the dense and the GPU-built HBS A_pp^{-1}."""
+    res = []
+    for one in (0, 1):
+        ctx = rw.Context(0)
+        ctx.set_options(app_dense_max_nodes=app_dense_max_nodes, one_stream=one)
+        wall = rw.Wall(ctx, 64)
+        p = W.config1(seed=4)
+        ref = wall.refine(p.refinement.panel_ids, p.refinement.levels)
+        g = torch.stack([ref.stokeslet_rhs(s.z, s.f) for s in p.rhs]).contiguous()
+        tau = torch.empty_like(g)
+        info = {}
+        rw.rw_solve(ctx.h, ref.h, g, tau, ref.n_unknowns, info=info)
+        inf = ref.info()
+        res.append((tau.cpu().numpy(), inf["k"], inf["app_entries"], info["ir_iters"]))
+        ref.close()
+        wall.close()
+        ctx.close()
+    d = np.max(np.linalg.norm(res[0][0] - res[1][0], axis=1) / np.linalg.norm(res[0][0], axis=1))
+    _say(f"one_stream vs default (dense max {app_dense_max_nodes}): k {res[0][1]}/{res[1][1]}, "
+         f"app entries {res[0][2]}/{res[1][2]}, diff {d:.1e}")
+    assert res[0][1:] == res[1][1:]
+    assert d <= 1e-13
