@@ -1250,9 +1250,9 @@ __global__ __launch_bounds__(BWV * 64) void node_factor_bordered_kernel(
   // row by readlane: no barrier), the new inverse column replacing the
   // eliminated one in place; its columns then hold E(:, I), the block's
   // row operations E = E_15 ... E_0 restricted to the pivot rows I.  After
-  // one barrier every other wave applies them to its columns,
+  // one barrier every other wave's columns take
   //   A <- A + (E(:, I) - I(:, I)) A(I, :),
-  // a rank-16 update.  Pivot rows are not scaled during the sweep (a later
+  // a rank-16 update (the next block's columns first, on the matrix cores).  Pivot rows are not scaled during the sweep (a later
   // elimination with an unscaled pivot row gives the same result for the
   // other rows, and the pivot row stays piv times its scaled form), so each
   // row is divided by its own pivot once at the end.
@@ -1403,17 +1403,51 @@ __global__ __launch_bounds__(BWV * 64) void node_factor_bordered_kernel(
       }
       __builtin_amdgcn_wave_barrier();
     };
-    // The update is bound by the LDS reads of the pivot rows (broadcast to
-    // every lane) when all waves run it at once, so the next panel's wave
-    // runs it alone, at raised priority, and then factors its panel while
-    // the other waves update theirs (the panel steps read no LDS).  Waves
-    // whose columns all lie beyond T have nothing to update.
-    if (w == bj + 1) {
-      __builtin_amdgcn_s_setprio(3);
-      update();
+    // The next panel's columns (wave bj + 1) are updated first, by every
+    // wave at once on the matrix cores: wave v forms rows 16 v .. 16 v + 15
+    // of (E(:, I) - I(:, I)) A(I, columns of wave bj + 1), a 16 x 16 x nb
+    // product (four v_mfma_f64_16x16x4f64), into the other panel slot, which
+    // nobody uses until that wave publishes its own panel.  That wave adds
+    // the product to its columns and factors its panel at raised priority,
+    // while the other waves update their own columns (the panel steps read
+    // no LDS).  Waves whose columns all lie beyond T have nothing to update.
+    const int nx = bj + 1;
+    if (nx < BWV && BC * nx < T) {   // uniform
+      if (w == nx) {
+#pragma unroll
+        for (int sr = 0; sr < BS; ++sr)
+          if (tt[sr] >= 0) {
+#pragma unroll
+            for (int cc = 0; cc < BC; ++cc) S.rows[w][tt[sr]][cc] = a[sr][cc];
+          }
+      }
+      __syncthreads();
+      double(*dl)[BC + 1] = S.pan[slot ^ 1];
+      const int i16 = lane & 15, k4 = lane >> 4, row = 16 * w + i16;
+      double4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) {
+        // A(i, t) = coefficient of row 16 w + i for step t; B(t, j) = pivot
+        // row of step t in column j of wave nx (zero past the block's nb steps)
+        const int t = 4 * kb + k4;
+        const bool in = t < nb;
+        const double av = in ? S.pan[slot][row][t] - (S.piv[j0 + t] == row ? 1.0 : 0.0) : 0.0;
+        const double bv = in ? S.rows[nx][t][i16] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+      // item r of lane l holds row 16 w + l / 16 + 4 r, column l % 16
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dl[16 * w + k4 + 4 * r][i16] = acc[r];
+      __syncthreads();
+      if (w == nx) {
+        __builtin_amdgcn_s_setprio(3);
+#pragma unroll
+        for (int sr = 0; sr < BS; ++sr)
+#pragma unroll
+          for (int cc = 0; cc < BC; ++cc) a[sr][cc] += dl[lane + 64 * sr][cc];
+      }
     }
-    __syncthreads();
-    if (w != bj && w != bj + 1 && BC * w < T) update();
+    if (w != bj && w != nx && BC * w < T) update();
   }
 #pragma unroll
   for (int sr = 0; sr < BS; ++sr)
