@@ -71,21 +71,40 @@ void discretize(double a, int m, int order, const std::vector<double>& gl_s,
   out.order = order;
   out.panels = std::move(panels);
   out.nodes.resize(out.panels.size() * order);
+  // theta_j = mid + d_j with d_j = half * s_j: cos / sin of theta_j and of
+  // m theta_j by the angle-addition formulas from those of mid (per panel)
+  // and of d_j (per panel width: refined children share it), so that the
+  // trigonometric calls are per panel, not per node.  The results differ
+  // from direct evaluation by a few units in the last place.
+  std::vector<double> cd(order), sd(order), cmd(order), smd(order);
+  double half_done = -1.0;
   for (size_t p = 0; p < out.panels.size(); ++p) {
     const double ta = out.panels[p].ta, tb = out.panels[p].tb;
     const double half = 0.5 * (tb - ta), mid = 0.5 * (tb + ta);
+    if (!(std::fabs(half - half_done) <= 1e-15 * half)) {
+      for (int j = 0; j < order; ++j) {
+        const double d = half * gl_s[j];
+        cd[j] = std::cos(d);
+        sd[j] = std::sin(d);
+        cmd[j] = std::cos(m * d);
+        smd[j] = std::sin(m * d);
+      }
+      half_done = half;
+    }
+    const double cm = std::cos(mid), sm = std::sin(mid);
+    const double cmm = std::cos(m * mid), smm = std::sin(m * mid);
     for (int j = 0; j < order; ++j) {
-      const double th = mid + half * gl_s[j];
-      const double c = std::cos(th), s = std::sin(th);
-      const double r = 1.0 + a * std::cos(m * th);
-      const double r1 = -a * m * std::sin(m * th);
-      const double r2 = -a * m * m * std::cos(m * th);
+      const double c = cm * cd[j] - sm * sd[j], s = sm * cd[j] + cm * sd[j];
+      const double cmt = cmm * cmd[j] - smm * smd[j], smt = smm * cmd[j] + cmm * smd[j];
+      const double r = 1.0 + a * cmt;
+      const double r1 = -a * m * smt;
+      const double r2 = -a * m * m * cmt;
       const double x1 = r1 * c - r * s, y1 = r1 * s + r * c;                  // gamma'
       const double x2 = r2 * c - 2.0 * r1 * s - r * c, y2 = r2 * s + 2.0 * r1 * c - r * s;  // gamma''
-      const double sp = std::sqrt(x1 * x1 + y1 * y1);
-      const double tx = x1 / sp, ty = y1 / sp;
+      const double sp = std::sqrt(x1 * x1 + y1 * y1), isp = 1.0 / sp;
+      const double tx = x1 * isp, ty = y1 * isp;
       const double nx = ty, ny = -tx;
-      const double kap = (x1 * y2 - y1 * x2) / (sp * sp * sp);
+      const double kap = (x1 * y2 - y1 * x2) * (isp * isp * isp);
       const double w = gl_w[j] * half * sp;
       const double dl = -kap / (2.0 * M_PI);
       NodeRec& nd = out.nodes[p * order + j];

@@ -751,6 +751,8 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
   f.No = (int64_t)w->disc.nodes.size();
   f.Nn = (int64_t)f.disc.panels.size() * q;
   std::vector<int> k_ref, c_ref, new2ext(f.Nn), ref_kind(f.No, 0);
+  k_ref.reserve(f.No);
+  c_ref.reserve(f.No);
   for (int i = 0; i < w->P; ++i)
     for (int j = 0; j < q; ++j) {
       if (level_of_panel[i] >= 0) { c_ref.push_back(i * q + j); ref_kind[i * q + j] = 1; }
