@@ -179,6 +179,9 @@ void stream_after(rw_ctx* ctx, hipStream_t waiter, hipStream_t src, int i);
 // once on the caller's thread and stream instead.
 void aux_fork(rw_ctx* ctx, std::function<void(rw_ctx*)> fn);
 void aux_join(rw_ctx* ctx, hipStream_t into = nullptr);
+// Wake the helper's worker thread ahead of an aux_fork that follows shortly,
+// so that the fork does not wait for the thread to wake (no-op with one_stream).
+void aux_prewake(rw_ctx* ctx);
 struct AuxTask {
   rw_ctx* ctx = nullptr;
   bool active = false;

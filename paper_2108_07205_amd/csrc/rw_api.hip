@@ -2,6 +2,7 @@
 // reference-wall build, Algorithm 1 pre-computation per refinement and the
 // Woodbury solve with FP64 iterative refinement.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
@@ -260,6 +261,8 @@ struct AuxWorker {
   std::condition_variable cv;
   std::function<void()> job;
   bool has_job = false, busy = false, stop = false;
+  bool soon = false;                    // aux_prewake: a job is on its way
+  std::atomic<bool> job_flag{false};    // has_job, readable without the lock
   std::exception_ptr err;
 };
 
@@ -268,10 +271,21 @@ static void aux_loop(rw_ctx* aux, AuxWorker* wk) {
     std::function<void()> job;
     {
       std::unique_lock<std::mutex> lk(wk->mu);
-      wk->cv.wait(lk, [&] { return wk->has_job || wk->stop; });
-      if (!wk->has_job) return;
+      wk->cv.wait(lk, [&] { return wk->has_job || wk->stop || wk->soon; });
+      if (!wk->has_job && wk->stop) return;
+      if (!wk->has_job) {
+        // a job is on its way: wait for it awake (a sleeping thread takes
+        // tens of microseconds to wake), at most 2 ms, then sleep again
+        wk->soon = false;
+        lk.unlock();
+        const auto until = std::chrono::steady_clock::now() + std::chrono::milliseconds(2);
+        while (!wk->job_flag.load(std::memory_order_acquire) && std::chrono::steady_clock::now() < until)
+          __builtin_ia32_pause();
+        continue;
+      }
       job = std::move(wk->job);
       wk->has_job = false;
+      wk->job_flag.store(false, std::memory_order_relaxed);
     }
     std::exception_ptr e;
     set_current_ctx(aux);
@@ -317,6 +331,19 @@ void aux_fork(rw_ctx* ctx, std::function<void(rw_ctx*)> fn) {
     wk->job = [fn, a]() { fn(a); };
     wk->has_job = true;
     wk->busy = true;
+    wk->job_flag.store(true, std::memory_order_release);
+  }
+  wk->cv.notify_all();
+}
+
+void aux_prewake(rw_ctx* ctx) {
+  if (ctx->opt.one_stream) return;
+  ctx_aux(ctx);
+  AuxWorker* wk = ctx->worker;
+  {
+    std::lock_guard<std::mutex> lk(wk->mu);
+    if (wk->has_job || wk->busy) return;
+    wk->soon = true;
   }
   wk->cv.notify_all();
 }
@@ -729,6 +756,7 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
   // pinned staging are reused below (its outcome stays with its handle)
   if (ctx->unsettled) refined_settle(ctx->unsettled, true);
   if (!ctx->defer_pin) HIP_CHECK(hipHostMalloc((void**)&ctx->defer_pin, 64, hipHostMallocDefault));
+  aux_prewake(ctx);   // a3 is handed to the helper once the added nodes are known
   f.wall = w;
   f.ctx = ctx;
   f.level_of_panel = level_of_panel;
@@ -750,27 +778,11 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
   const std::vector<NodeRec>& pnodes = f.pnodes;
   f.No = (int64_t)w->disc.nodes.size();
   f.Nn = (int64_t)f.disc.panels.size() * q;
-  std::vector<int> k_ref, c_ref, new2ext(f.Nn), ref_kind(f.No, 0);
-  k_ref.reserve(f.No);
-  c_ref.reserve(f.No);
-  for (int i = 0; i < w->P; ++i)
-    for (int j = 0; j < q; ++j) {
-      if (level_of_panel[i] >= 0) { c_ref.push_back(i * q + j); ref_kind[i * q + j] = 1; }
-      else k_ref.push_back(i * q + j);
-    }
-  {
-    int64_t np = 0;
-    for (size_t pi = 0; pi < f.disc.panels.size(); ++pi) {
-      const Panel& p = f.disc.panels[pi];
-      for (int j = 0; j < q; ++j) {
-        const int64_t n = (int64_t)pi * q + j;
-        new2ext[n] = p.added ? (int)(f.No + np++) : p.ref_id * q + j;
-      }
-    }
-  }
-  f.Nk = (int64_t)k_ref.size();
-  f.Nc = (int64_t)c_ref.size();
   f.Np = (int64_t)pnodes.size();
+  int64_t n_cut_panels = 0;
+  for (int i = 0; i < w->P; ++i) n_cut_panels += level_of_panel[i] >= 0;
+  f.Nc = n_cut_panels * q;
+  f.Nk = f.No - f.Nc;
   f.Next = f.No + f.Np;
   const int64_t M = 2 * f.Next, Mo = 2 * f.No, Mp = 2 * f.Np;
   // host arrays go to the device through the ctx's pinned staging buffer
@@ -789,9 +801,41 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
     memcpy(st, src, bytes);
     HIP_CHECK(hipMemcpyAsync(dst, st, bytes, hipMemcpyHostToDevice, s));
   };
+  // the added nodes first: a3 needs only them, so it starts before the rest of a1
+  f.d_p.alloc(ctx, f.Np);
+  up(f.d_p.p, pnodes.data(), sizeof(NodeRec) * f.Np);
+  // ---- a3: A_pp^{-1} (dense LU for few added points, else a GPU-built HBS
+  // inverse) on the helper ctx, beside the rest of a1 and the compression of
+  // Q on this stream
+  f.app_hbs_on = f.Np > ctx->opt.app_dense_max_nodes;
+  f.info.app_lu_mult = 0.0;
+  AuxTask a3;
+  if (f.Np > 0) {
+    const uint64_t seed = ctx->opt.seed ^ 0x3C6EF372FE94F82Bull;
+    a3.fork(ctx, [&f, w, seed](rw_ctx* ax) { build_app_inverse(w, f, seed, ax); });
+  }
+  std::vector<int> k_ref, c_ref, new2ext(f.Nn), ref_kind(f.No, 0);
+  k_ref.reserve(f.Nk);
+  c_ref.reserve(f.Nc);
+  for (int i = 0; i < w->P; ++i)
+    for (int j = 0; j < q; ++j) {
+      if (level_of_panel[i] >= 0) { c_ref.push_back(i * q + j); ref_kind[i * q + j] = 1; }
+      else k_ref.push_back(i * q + j);
+    }
+  {
+    int64_t np = 0;
+    for (size_t pi = 0; pi < f.disc.panels.size(); ++pi) {
+      const Panel& p = f.disc.panels[pi];
+      for (int j = 0; j < q; ++j) {
+        const int64_t n = (int64_t)pi * q + j;
+        new2ext[n] = p.added ? (int)(f.No + np++) : p.ref_id * q + j;
+      }
+    }
+  }
   f.d_ext.alloc(ctx, f.Next);
   HIP_CHECK(hipMemcpyAsync(f.d_ext.p, w->d_nodes.p, sizeof(NodeRec) * f.No, hipMemcpyDeviceToDevice, s));
-  up(f.d_ext.p + f.No, pnodes.data(), sizeof(NodeRec) * f.Np);
+  if (f.Np)
+    HIP_CHECK(hipMemcpyAsync(f.d_ext.p + f.No, f.d_p.p, sizeof(NodeRec) * f.Np, hipMemcpyDeviceToDevice, s));
   f.d_new2ext.alloc(ctx, f.Nn);
   up(f.d_new2ext.p, new2ext.data(), sizeof(int) * f.Nn);
   f.d_ref_kind.alloc(ctx, f.No);
@@ -815,19 +859,7 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
     launch_gather_nodes(w->d_nodes.p, idx_c.p, f.Nc, f.d_c.p, s);
   }
   ctx_pinned_used(ctx, s);
-  f.d_p.alloc(ctx, f.Np);
-  if (f.Np) HIP_CHECK(hipMemcpyAsync(f.d_p.p, f.d_ext.p + f.No, sizeof(NodeRec) * f.Np, hipMemcpyDeviceToDevice, s));
-
   t_geo.reset();
-  // ---- a3: A_pp^{-1} (dense LU for few added points, else a GPU-built HBS
-  // inverse) on the helper ctx, beside the compression of Q on this stream
-  f.app_hbs_on = f.Np > ctx->opt.app_dense_max_nodes;
-  f.info.app_lu_mult = 0.0;
-  AuxTask a3;
-  if (f.Np > 0) {
-    const uint64_t seed = ctx->opt.seed ^ 0x3C6EF372FE94F82Bull;
-    a3.fork(ctx, [&f, w, seed](rw_ctx* ax) { build_app_inverse(w, f, seed, ax); });
-  }
   f.k_k = f.k_p = f.k = 0;
   f.info.n_near = -1;
   if (f.Nc > 0) {
