@@ -66,45 +66,50 @@ std::vector<Panel> refined_panels(int n_panels, const std::vector<int32_t>& leve
   return out;
 }
 
+// sin and cos of x for |x| < 1e-2 by their Taylor series (through x^9 and
+// x^8: the first omitted terms are below 1e-26)
+static inline void sincos_small(double x, double& s, double& c) {
+  const double x2 = x * x;
+  c = 1.0 + x2 * (-1.0 / 2 + x2 * (1.0 / 24 + x2 * (-1.0 / 720 + x2 * (1.0 / 40320))));
+  s = x * (1.0 + x2 * (-1.0 / 6 + x2 * (1.0 / 120 + x2 * (-1.0 / 5040 + x2 * (1.0 / 362880)))));
+}
+
+// sin and cos of t = b + e given those of b (e = t - b, exact for t near b):
+// angle addition with the small angle's by Taylor series, so that the
+// library's sine and cosine are called per panel, not per node (within
+// about one unit in the last place of direct evaluation)
+static inline void sincos_near(double sb, double cb, double e, double& s, double& c) {
+  double se, ce;
+  if (std::fabs(e) < 1e-2) sincos_small(e, se, ce);
+  else { se = std::sin(e); ce = std::cos(e); }
+  c = std::fma(cb, ce, -(sb * se));
+  s = std::fma(sb, ce, cb * se);
+}
+
 void discretize(double a, int m, int order, const std::vector<double>& gl_s,
                 const std::vector<double>& gl_w, std::vector<Panel> panels, Discretization& out) {
   out.order = order;
   out.panels = std::move(panels);
   out.nodes.resize(out.panels.size() * order);
-  // theta_j = mid + d_j with d_j = half * s_j: cos / sin of theta_j and of
-  // m theta_j by the angle-addition formulas from those of mid (per panel)
-  // and of d_j (per panel width: refined children share it), so that the
-  // trigonometric calls are per panel, not per node.  The results differ
-  // from direct evaluation by a few units in the last place.
-  std::vector<double> cd(order), sd(order), cmd(order), smd(order);
-  double half_done = -1.0;
   for (size_t p = 0; p < out.panels.size(); ++p) {
     const double ta = out.panels[p].ta, tb = out.panels[p].tb;
     const double half = 0.5 * (tb - ta), mid = 0.5 * (tb + ta);
-    if (!(std::fabs(half - half_done) <= 1e-15 * half)) {
-      for (int j = 0; j < order; ++j) {
-        const double d = half * gl_s[j];
-        cd[j] = std::cos(d);
-        sd[j] = std::sin(d);
-        cmd[j] = std::cos(m * d);
-        smd[j] = std::sin(m * d);
-      }
-      half_done = half;
-    }
-    const double cm = std::cos(mid), sm = std::sin(mid);
-    const double cmm = std::cos(m * mid), smm = std::sin(m * mid);
+    const double smid = std::sin(mid), cmid = std::cos(mid);
+    const double bm = m * mid, sbm = std::sin(bm), cbm = std::cos(bm);
     for (int j = 0; j < order; ++j) {
-      const double c = cm * cd[j] - sm * sd[j], s = sm * cd[j] + cm * sd[j];
-      const double cmt = cmm * cmd[j] - smm * smd[j], smt = smm * cmd[j] + cmm * smd[j];
+      const double th = mid + half * gl_s[j], tm = m * th;
+      double s, c, smt, cmt;
+      sincos_near(smid, cmid, th - mid, s, c);   // theta
+      sincos_near(sbm, cbm, tm - bm, smt, cmt);  // m theta
       const double r = 1.0 + a * cmt;
       const double r1 = -a * m * smt;
       const double r2 = -a * m * m * cmt;
       const double x1 = r1 * c - r * s, y1 = r1 * s + r * c;                  // gamma'
       const double x2 = r2 * c - 2.0 * r1 * s - r * c, y2 = r2 * s + 2.0 * r1 * c - r * s;  // gamma''
-      const double sp = std::sqrt(x1 * x1 + y1 * y1), isp = 1.0 / sp;
-      const double tx = x1 * isp, ty = y1 * isp;
+      const double sp = std::sqrt(x1 * x1 + y1 * y1);
+      const double tx = x1 / sp, ty = y1 / sp;
       const double nx = ty, ny = -tx;
-      const double kap = (x1 * y2 - y1 * x2) * (isp * isp * isp);
+      const double kap = (x1 * y2 - y1 * x2) / (sp * sp * sp);
       const double w = gl_w[j] * half * sp;
       const double dl = -kap / (2.0 * M_PI);
       NodeRec& nd = out.nodes[p * order + j];

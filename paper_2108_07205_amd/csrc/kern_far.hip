@@ -288,7 +288,7 @@ void launch_far_sketch(const SketchSeg* segs, int nseg, const NodeRec* tgt, int6
   const double inv_rho = 1.0 / rho;
   const int64_t len = (int64_t)FAR_ROWS * ncols;
   {
-    KernelTimer kt("far_coef_kernel", 0.0, 0.0);
+    KernelTimer kt("far_coef_kernel", 0.0, 0.0, s);
     const dim3 grid((unsigned)nsplit, (unsigned)((ncols + 63) / 64));
     if (local)
       hipLaunchKernelGGL(far_coef_kernel<true>, grid, dim3(256), 0, s, sa, cx, cy, inv_rho, seed, ncols, nsplit, part);
@@ -298,7 +298,7 @@ void launch_far_sketch(const SketchSeg* segs, int nseg, const NodeRec* tgt, int6
     hipLaunchKernelGGL(far_coef_sum_kernel, dim3(nblocks(len)), dim3(256), 0, s, part, nsplit, len, coef);
     KERNEL_CHECK("far_coef_sum");
   }
-  KernelTimer kt("far_eval_kernel", 0.0, 0.0);
+  KernelTimer kt("far_eval_kernel", 0.0, 0.0, s);
   const dim3 grid(nblocks(nt), (unsigned)(ncols / FE_COLS));
   if (local)
     hipLaunchKernelGGL(far_eval_kernel<true>, grid, dim3(256), 0, s, tgt, nt, pos, cx, cy, inv_rho, coef, ncols,

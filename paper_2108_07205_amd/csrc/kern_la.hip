@@ -890,7 +890,7 @@ static int rowid_cooperative(rw_ctx* ctx, const double* Y, int64_t m, int ncols,
   void* args[] = {&a};
   func_lds_at_least((const void*)rowid_kernel, (int)shmem);
   {
-    KernelTimer kt("rowid_kernel", 6.0 * (double)m * ncols * kmax, 0.0);
+    KernelTimer kt("rowid_kernel", 6.0 * (double)m * ncols * kmax, 0.0, s);
     HIP_CHECK(hipLaunchCooperativeKernel((const void*)rowid_kernel, dim3(G), dim3(256), args, shmem, s));
   }
   KERNEL_CHECK("rowid");
@@ -911,7 +911,7 @@ bool launch_rowid_enqueue(rw_ctx* ctx, const double* Y, int64_t m, int ncols, do
   int* idx[2] = {(int*)(dmax + 2), (int*)(dmax + 2) + nb0 * kmax};
   int* cnt[2] = {idx[1] + nb0 * kmax, idx[1] + nb0 * kmax + nb0};
   double* Q = (double*)(((uintptr_t)(cnt[1] + nb0) + 15) & ~(uintptr_t)15);
-  KernelTimer kt("rowid_select_kernel", 0.0, 0.0);
+  KernelTimer kt("rowid_select_kernel", 0.0, 0.0, s);
   HIP_CHECK(hipMemsetAsync(dmax, 0, 2 * sizeof(unsigned long long), s));
   hipLaunchKernelGGL(rowid_maxnorm_kernel, dim3((unsigned)std::min<int64_t>(1024, blocks(m))), dim3(256), 0, s, Y, m,
                      ncols, dmax);

@@ -644,7 +644,7 @@ void launch_residual(const NodeRec* nodes, int64_t n, const double* g, const dou
   // algorithmic work: 12 flops per 2x2 block (r, r^2, r.n, 1/r^2 scaling) + 6 per
   // block and right-hand side; the division counts as one flop
   {
-    KernelTimer kt("resid_tiles_kernel", (double)n * n * (12.0 + 6.0 * nrhs), 0.0);
+    KernelTimer kt("resid_tiles_kernel", (double)n * n * (12.0 + 6.0 * nrhs), 0.0, s);
     if (nrhs == 1) {
       double* pk = npart + (size_t)2 * nb * nrhs;
       hipLaunchKernelGGL(resid_pack_kernel, dim3(nb), dim3(256), 0, s, nodes, n, tau, pk, fpart);
@@ -718,7 +718,7 @@ void launch_sketch(const NodeRec* tgt, int64_t nt, const SketchSeg* segs, int ns
   // accumulators in registers without spilling
   for (int off = 0; off < ncols;) {
     const int w = (ncols - off >= 64) ? 64 : 32;
-    KernelTimer kt("sketch_kernel", 2.0 * rows * 2.0 * nsrc * w, 0.0);
+    KernelTimer kt("sketch_kernel", 2.0 * rows * 2.0 * nsrc * w, 0.0, s);
     if (w == 64)
       hipLaunchKernelGGL(sketch_kernel<4>, grid, dim3(256), 0, s, tgt, nt, sa, seed, off, ns, part);
     else

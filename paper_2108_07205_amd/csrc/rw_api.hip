@@ -867,9 +867,12 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
     int ncols = ctx->opt.sketch_cols;
     const double tol = f.q_tol;
     DBuf<char> dres(ctx, 256);   // ranks and certificates of the two row IDs
-    DBuf<double> Yk, Yp, Ck, Cp, part, Ynear;
-    DBuf<double2> fpart, fcoef;
-    DBuf<char> work;
+    DBuf<double> Yk, Yp, Ck, Cp, part, part_p, Ynear;
+    DBuf<double2> fpart, fcoef, fpart_p, fcoef_p;
+    DBuf<char> work, work_p;
+    // the p-row sketch and row ID run on the side stream beside the k-row
+    // ones (they share only the inputs enqueued so far on this stream)
+    const hipStream_t sp = ctx_side_stream(ctx);
     DBuf<int> dJ(ctx, 256);
     // Sec. 3.3: a circle of radius rho about the refined arc Gamma_r (its
     // cut and added nodes) splits the kept nodes into near (within
@@ -921,6 +924,7 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
       const int kmax = ncols - 8;
       Yk.alloc(ctx, (size_t)2 * f.Nk * ncols);
       Yp.alloc(ctx, (size_t)2 * f.Np * ncols);
+      stream_after(ctx, sp, s, 11);
       SketchSeg sk[2] = {{f.d_c.p, f.Nc, -1.0, 0}, {f.d_p.p, f.Np, 1.0, 2 * f.Nc}};
       const uint64_t seed_k = ctx->opt.seed, seed_p = ctx->opt.seed ^ 0xA5A5A5A5ull;
       if (far_on) {
@@ -930,46 +934,50 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
         // the near list after those of all kept nodes, so none repeats)
         const int ns_k = (int)std::min<int64_t>(256, std::max<int64_t>(1, (f.Nc + f.Np) / 32));
         const int ns_p = (int)std::min<int64_t>(256, std::max<int64_t>(1, n_far / 32));
-        part.alloc(ctx, std::max<size_t>(1, std::max(sketch_part_doubles(n_near, f.Nc + f.Np),
-                                                     sketch_part_doubles(f.Np, n_near))));
+        part.alloc(ctx, std::max<size_t>(1, sketch_part_doubles(n_near, f.Nc + f.Np)));
+        part_p.alloc(ctx, std::max<size_t>(1, sketch_part_doubles(f.Np, n_near)));
         Ynear.alloc(ctx, (size_t)std::max<int64_t>(1, 2 * n_near * ncols));
-        fpart.alloc(ctx, far_part_elems(ncols, std::max(ns_k, ns_p)));
+        fpart.alloc(ctx, far_part_elems(ncols, ns_k));
         fcoef.alloc(ctx, far_part_elems(ncols, 1));
+        fpart_p.alloc(ctx, far_part_elems(ncols, ns_p));
+        fcoef_p.alloc(ctx, far_part_elems(ncols, 1));
         const double fl = 2.0 * ncols * (2.0 * n_near * 2.0 * (f.Nc + f.Np) + 2.0 * f.Np * 2.0 * n_near) +
                           8.0 * 4.0 * FAR_P * ncols * ((f.Nc + f.Np) + n_far + n_far + f.Np);
         PhaseTimer t(ctx, "a2_sketch", fl, 8.0 * ncols * 2.0 * (f.Nk + f.Np));
+        SketchSeg spn[1] = {{d_near.p, n_near, 1.0, 2 * f.Nk}};
+        launch_sketch(f.d_p.p, f.Np, spn, 1, ncols, seed_p, Yp.p, part_p.p, sp);
+        SketchSeg spf[1] = {{d_far.p, n_far, 1.0, 0}};
+        if (n_far)
+          launch_far_sketch(spf, 1, f.d_p.p, f.Np, nullptr, true, fcx, fcy, rho, ncols, seed_p, true, Yp.p,
+                            fpart_p.p, ns_p, fcoef_p.p, sp);
         launch_far_sketch(sk, 2, d_far.p, n_far, d_far_pos.p, false, fcx, fcy, rho, ncols, seed_k, false, Yk.p,
                           fpart.p, ns_k, fcoef.p, s);
         launch_sketch(d_near.p, n_near, sk, 2, ncols, seed_k, Ynear.p, part.p, s);
         launch_scatter_rows(Ynear.p, n_near, d_near_pos.p, ncols, Yk.p, s);
-        SketchSeg spn[1] = {{d_near.p, n_near, 1.0, 2 * f.Nk}};
-        launch_sketch(f.d_p.p, f.Np, spn, 1, ncols, seed_p, Yp.p, part.p, s);
-        SketchSeg spf[1] = {{d_far.p, n_far, 1.0, 0}};
-        if (n_far)
-          launch_far_sketch(spf, 1, f.d_p.p, f.Np, nullptr, true, fcx, fcy, rho, ncols, seed_p, true, Yp.p, fpart.p,
-                            ns_p, fcoef.p, s);
       } else {
-        part.alloc(ctx, std::max(sketch_part_doubles(f.Nk, f.Nc + f.Np), sketch_part_doubles(f.Np, f.Nk)));
+        part.alloc(ctx, sketch_part_doubles(f.Nk, f.Nc + f.Np));
+        part_p.alloc(ctx, sketch_part_doubles(f.Np, f.Nk));
         const double fl = 2.0 * ncols * (2.0 * f.Nk * 2.0 * (f.Nc + f.Np) + 2.0 * f.Np * 2.0 * f.Nk);
         PhaseTimer t(ctx, "a2_sketch", fl, 8.0 * ncols * 2.0 * (f.Nk + f.Np));
+        SketchSeg spk[1] = {{f.d_k.p, f.Nk, 1.0, 0}};
+        launch_sketch(f.d_p.p, f.Np, spk, 1, ncols, seed_p, Yp.p, part_p.p, sp);
         launch_sketch(f.d_k.p, f.Nk, sk, 2, ncols, seed_k, Yk.p, part.p, s);
-        SketchSeg sp[1] = {{f.d_k.p, f.Nk, 1.0, 0}};
-        launch_sketch(f.d_p.p, f.Np, sp, 1, ncols, seed_p, Yp.p, part.p, s);
       }
-      part.release();
       Ck.alloc(ctx, (size_t)2 * f.Nk * kmax);
       Cp.alloc(ctx, (size_t)2 * f.Np * kmax);
       const int ng = std::max(256, ctx->n_cu);
       work.alloc(ctx, std::max(rowid_work_bytes(2 * f.Nk, ncols, kmax, ng), rowid_work_bytes(2 * f.Np, ncols, kmax, ng)));
+      work_p.alloc(ctx, rowid_work_bytes(2 * f.Np, ncols, kmax, ng));
       PhaseTimer t_id(ctx, "a2_row_id", 8.0 * ncols * 2.0 * (f.Nk + f.Np) * 40.0, 8.0 * ncols * 2.0 * (f.Nk + f.Np));
-      // both row IDs enqueued, one read-back of their ranks and certificates
-      // (the shared `work` is free again once a job's results are copied out)
+      // both row IDs enqueued (the p rows' on the side stream), one read-back
+      // of their ranks and certificates once this stream has joined the side
       int* rk = (int*)dres.p;
       unsigned long long* rm = (unsigned long long*)(dres.p + 64);
+      const bool qp = f.Np > 0 && launch_rowid_enqueue(ctx, Yp.p, 2 * f.Np, ncols, tol, kmax, dJ.p + 128, Cp.p,
+                                                       work_p.p, rk + 1, rm + 2, sp);
       const bool qk = f.Nk > 0 && launch_rowid_enqueue(ctx, Yk.p, 2 * f.Nk, ncols, tol, kmax, dJ.p, Ck.p, work.p, rk,
                                                        rm, s);
-      const bool qp = f.Np > 0 && launch_rowid_enqueue(ctx, Yp.p, 2 * f.Np, ncols, tol, kmax, dJ.p + 128, Cp.p, work.p,
-                                                       rk + 1, rm + 2, s);
+      stream_after(ctx, s, sp, 12);
       char* rbk = (char*)ctx_readback(ctx, 64 + 4 * sizeof(unsigned long long));
       int* hk = (int*)rbk;
       unsigned long long* hm = (unsigned long long*)(rbk + 64);
