@@ -2175,19 +2175,16 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
   // this function ends, later work on the main stream waits for it
   const hipStream_t sf = ctx_side_stream(ctx);
   stream_after(ctx, sf, s, 0);
-  // the block-inverse fallbacks of a level run on a third stream beside the
-  // level's bordered factorization (they take disjoint nodes)
-  const hipStream_t sf2 = ctx_side2_stream(ctx);
   struct SideJoin {
     rw_ctx* c;
-    hipStream_t main, side, side2;
+    hipStream_t main, side;
     ~SideJoin() {
-      hipEvent_t e = nullptr, e2 = nullptr;
-      try { e = ctx_order_event(c, 2); e2 = ctx_order_event(c, 10); } catch (...) { return; }
-      if (hipEventRecord(e2, side2) == hipSuccess) (void)hipStreamWaitEvent(main, e2, 0);
+      if (main == side) return;
+      hipEvent_t e = nullptr;
+      try { e = ctx_order_event(c, 2); } catch (...) { return; }
       if (hipEventRecord(e, side) == hipSuccess) (void)hipStreamWaitEvent(main, e, 0);
     }
-  } side_join{ctx, s, sf, sf2};
+  } side_join{ctx, s, sf};
   w.ctx = ctx;
   w.L = L;
   w.lev.assign(L + 1, HbsLevelDev());
@@ -2203,36 +2200,35 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
   // profiler entries of the factor launches (their flops are known once the ranks are read back)
   std::vector<size_t> fac_entry(L + 1, SIZE_MAX);
   auto factor_launch = [&](const GNode* gn, const GNode* gch, int nn, int is_leaf, int is_root, const int* cr,
-                           const int* cc, const double* U, const double* V, double* groot, int mx_known, int lvl) {
+                           const int* cc, const double* U, const double* V, double* groot, int mx_known, int lvl,
+                           hipStream_t fs) {
     // nodes with n + k <= BT: bordered Gauss-Jordan; the others: block
-    // inverse in registers (n <= FN) or LDS Gauss-Jordan, on sf2 beside it:
-    // sf2 starts from sf's point before this launch (the level's inputs and
-    // the children's D^), and sf's later work waits for it
+    // inverse in registers (n <= FN) or LDS Gauss-Jordan, launched first on
+    // the same stream (each kernel takes only its own nodes and returns at
+    // once when it has none)
     const bool small = !is_root && (mx_known < 0 || mx_known <= FN);
     const bool large = !is_root && (mx_known < 0 || mx_known > FN);
-    if (small || large) stream_after(ctx, sf2, sf, 8);
+    if (small) {
+      KernelTimer kt("node_factor_kernel", 0.0, 0.0, fs);
+      hipLaunchKernelGGL(node_factor_kernel, dim3(nn), dim3(256), 0, fs, gn, gch, is_leaf, is_root, cr, cc, d_nodes,
+                         U, V, dh_child, dh_cur, ws.p, w.gen.p, groot, failp, 0, FN);
+      KERNEL_CHECK("node_factor");
+    }
+    if (large) {
+      KernelTimer kt("node_inverse_kernel", 0.0, 0.0, fs);
+      hipLaunchKernelGGL(node_inverse_kernel, dim3(nn), dim3(256), shv, fs, gn, gch, is_leaf, is_root, cr, cc, d_nodes,
+                         U, V, dh_child, dh_cur, ws.p, w.gen.p, groot, failp, FN, MANY);
+      KERNEL_CHECK("node_inverse");
+    }
     {
-      KernelTimer kt("node_factor_bordered_kernel", 0.0, 0.0, sf);
-      hipLaunchKernelGGL(node_factor_bordered_kernel, dim3(nn), dim3(BWV * 64), 0, sf, gn, gch, is_leaf, is_root, cr, cc,
+      KernelTimer kt("node_factor_bordered_kernel", 0.0, 0.0, fs);
+      hipLaunchKernelGGL(node_factor_bordered_kernel, dim3(nn), dim3(BWV * 64), 0, fs, gn, gch, is_leaf, is_root, cr, cc,
                          d_nodes, U, V, dh_child, dh_cur, ws.p, w.gen.p, groot, failp);
       KERNEL_CHECK("node_factor_bordered");
     }
     if (ctx->prof && !ctx->pending.empty()) fac_entry[lvl] = ctx->pending.size() - 1;
     // the root block (n = k_1 + k_2 <= 2 SK_KCAP) always fits the bordered kernel
     static_assert(2 * SK_KCAP <= BT, "the root block fits the bordered factorization");
-    if (small) {
-      KernelTimer kt("node_factor_kernel", 0.0, 0.0, sf2);
-      hipLaunchKernelGGL(node_factor_kernel, dim3(nn), dim3(256), 0, sf2, gn, gch, is_leaf, is_root, cr, cc, d_nodes,
-                         U, V, dh_child, dh_cur, ws.p, w.gen.p, groot, failp, 0, FN);
-      KERNEL_CHECK("node_factor");
-    }
-    if (large) {
-      KernelTimer kt("node_inverse_kernel", 0.0, 0.0, sf2);
-      hipLaunchKernelGGL(node_inverse_kernel, dim3(nn), dim3(256), shv, sf2, gn, gch, is_leaf, is_root, cr, cc, d_nodes,
-                         U, V, dh_child, dh_cur, ws.p, w.gen.p, groot, failp, FN, MANY);
-      KERNEL_CHECK("node_inverse");
-    }
-    if (small || large) stream_after(ctx, sf, sf2, 9);
   };
   int mx_leaf = 0;
   for (const GNode& g : G[L]) mx_leaf = std::max(mx_leaf, g.m);
@@ -2290,18 +2286,21 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRe
                        candc.p + cand_base[l - 1]);
     KERNEL_CHECK("node_interp");
     // ---- node factorizations of this level on the side stream, once the
-    // interpolation matrices are in; the children's D^ come from the
-    // previous launch on the same stream
-    stream_after(ctx, sf, s, 1);
+    // interpolation matrices are in (the children's D^ come from the
+    // previous level's launches on the same stream), while this stream goes
+    // on with the next level's sketches and IDs; level 1, after which no ID
+    // work is left, runs on this stream once the side stream is through
     const GNode* dch = leaf ? dgl : dg.p + 2 * nn;
+    hipStream_t fs = sf;
+    if (l > 1) stream_after(ctx, sf, s, 1);
+    else { stream_after(ctx, s, sf, 1); fs = s; }
     factor_launch(dgl, dch, nn, leaf ? 1 : 0, 0, cr, cc, Ub.p + uv_base[l], Vb.p + uv_base[l], (double*)nullptr,
-                  leaf ? mx : -1, l);
+                  leaf ? mx : -1, l, fs);
     std::swap(dh_child, dh_cur);
   }
-  // ---- root (side stream; its record was completed by the level-1 plan)
+  // ---- root (its record was completed by the level-1 plan)
   factor_launch(dg.p + 1, dg.p + 2, 1, 0, 1, candr.p + cand_base[0], candc.p + cand_base[0], Ub.p, Vb.p, w.groot.p,
-                -1, 0);
-  stream_after(ctx, s, sf, 2);
+                -1, 0, s);
   // ---- apply descriptors on the device; the host keeps bounds of the
   // sizes, and the records and flags are read back without a wait
   w.d_ints.alloc(ctx, (size_t)((int64_t(4) << L) - 3));
