@@ -558,6 +558,7 @@ struct rw_refined {
   // end, `pending` that its device-side checks (W pivot flag, A_pp build
   // flags) are still to be read; their outcome then sticks to the handle
   OwnedEvent done;
+  OwnedEvent app_ready;                // on the side stream once the A_pp inverse is built
   bool pending = false;
   DBuf<int> dinfo;                     // W pivot flag (device)
   DBuf<double> wpart;                  // split partial sums of R X
@@ -676,7 +677,28 @@ void woodbury_out(rw_refined* f, double* dst, int nrhs, bool accumulate, bool ap
 // side stream while the reference inverse runs on the main one.
 void woodbury_apply(rw_refined* f, const double* src, double* dst, int nrhs, bool accumulate) {
   woodbury_in(f, src, nrhs);
-  const bool fork = f->Np > 0 && f->app_hbs_on;
+  const bool hbs_app = f->Np > 0 && f->app_hbs_on;
+  bool side_busy = false;
+  // (with k_p = 1 the side stream's A_pp^{-1} L_p uses the same one-column
+  // workspace of the A_pp inverse, so that case keeps to the side stream)
+  if (hbs_app && f->app_ready.e && f->k_p != 1) {
+    const hipError_t q = hipEventQuery(f->done.e);
+    if (q == hipErrorNotReady) (void)hipGetLastError();   // not an error: the side stream is still at work
+    else HIP_CHECK(q);
+    side_busy = q == hipErrorNotReady;
+  }
+  if (side_busy) {
+    // the refinement's last part (X_p, W) still runs on the side stream:
+    // the A_pp^{-1} block, which needs only the finished A_pp inverse, runs
+    // on this stream after the reference block instead of queuing behind it
+    woodbury_ref_apply(f, nrhs);
+    HIP_CHECK(hipStreamWaitEvent(f->ctx->stream, f->app_ready.e, 0));
+    woodbury_app_apply(f, nrhs, f->ctx->stream);
+    HIP_CHECK(hipStreamWaitEvent(f->ctx->stream, f->done.e, 0));
+    woodbury_out(f, dst, nrhs, accumulate, true);
+    return;
+  }
+  const bool fork = hbs_app;
   if (fork) {
     rw_ctx* ctx = f->ctx;
     const hipStream_t side = ctx_side_stream(ctx);
@@ -1038,6 +1060,10 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
   } drain{st};
   stream_after(ctx, st, s, 7);
   a3.join(st);
+  if (f.Np > 0 && f.app_hbs_on) {
+    if (!f.app_ready.e) HIP_CHECK(hipEventCreateWithFlags(&f.app_ready.e, hipEventDisableTiming));
+    HIP_CHECK(hipEventRecord(f.app_ready.e, st));
+  }
   if (f.k > 0) {
     if (f.k_p) {
       double* xp = f.X.p + Mo + (size_t)f.k_k * M;
