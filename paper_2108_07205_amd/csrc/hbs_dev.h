@@ -106,6 +106,6 @@ void hbs_dev_apply_ws(const HbsDev& h, HbsWork& wk, const double* b, int64_t ldb
 // throws RW_ESINGULAR on a singular node block or a rank that exceeds the
 // node sketch (the descriptors are then empty, so applies enqueued before
 // give zeros) and fills the statistics.
-void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRec>& h_nodes, int leaf_max,
-                   double tol, uint64_t seed, HbsDev& out);
+void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, int64_t n_nodes, int leaf_max, double tol, uint64_t seed,
+                   HbsDev& out);
 void hbs_gpu_finish(HbsDev& w);

@@ -2074,10 +2074,10 @@ void hbs_gpu_finish(HbsDev& w) {
 }
 
 // ================================================================== GPU build
-void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, const std::vector<NodeRec>& hn, int leaf_max, double tol,
-                   uint64_t seed, HbsDev& w) {
+void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, int64_t n_nodes, int leaf_max, double tol, uint64_t seed,
+                   HbsDev& w) {
   hipStream_t s = ctx->stream;
-  const int64_t N = (int64_t)hn.size();
+  const int64_t N = n_nodes;
   if (N < 2) RW_THROW(RW_EINVAL, "HBS build needs at least two nodes");
   int L = 1;
   while ((N >> L) > leaf_max) ++L;

@@ -746,6 +746,55 @@ void launch_from_ext(const double* ext, int64_t ld_ext, int64_t n_new, const int
   KERNEL_CHECK("from_ext");
 }
 
+// grid ceil(n / 256): node t of panel t / q, whose parameter interval is
+// (pan[2 (t / q)], pan[2 (t / q) + 1]); the node record of the star curve
+// gamma(theta) = (1 + a cos(m theta)) (cos theta, sin theta) at the
+// Gauss-Legendre point j = t % q (position, outward normal, weight
+// w_GL (dtheta / 2) |gamma'| and the self block, Sec. 2.1).
+__global__ __launch_bounds__(256) void discretize_kernel(const double* __restrict__ pan, int64_t n, int q,
+                                                         GlRule gl, double a, int m, NodeRec* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  const int64_t p = t / q;
+  const int j = (int)(t - p * q);
+  const double ta = pan[2 * p], tb = pan[2 * p + 1];
+  const double half = 0.5 * (tb - ta), mid = 0.5 * (tb + ta);
+  const double th = mid + half * gl.s[j];
+  double s, c, smt, cmt;
+  sincos(th, &s, &c);
+  sincos(m * th, &smt, &cmt);
+  const double r = 1.0 + a * cmt;
+  const double r1 = -a * m * smt;
+  const double r2 = -a * m * m * cmt;
+  const double x1 = r1 * c - r * s, y1 = r1 * s + r * c;                                   // gamma'
+  const double x2 = r2 * c - 2.0 * r1 * s - r * c, y2 = r2 * s + 2.0 * r1 * c - r * s;    // gamma''
+  const double sp = sqrt(x1 * x1 + y1 * y1);
+  const double tx = x1 / sp, ty = y1 / sp;
+  const double nx = ty, ny = -tx;
+  const double kap = (x1 * y2 - y1 * x2) / (sp * sp * sp);
+  const double w = gl.w[j] * half * sp;
+  const double dl = -kap / (2.0 * M_PI);
+  NodeRec o;
+  o.x = r * c;
+  o.y = r * s;
+  o.nx = nx;
+  o.ny = ny;
+  o.w = w;
+  o.s00 = -0.5 + w * (dl * tx * tx + nx * nx);
+  o.s01 = w * (dl * tx * ty + nx * ny);
+  o.s11 = -0.5 + w * (dl * ty * ty + ny * ny);
+  out[t] = o;
+}
+
+void launch_discretize(const double* pan, int64_t n_panels, int q, const GlRule& gl, double a, int m, NodeRec* out,
+                       hipStream_t s) {
+  const int64_t n = n_panels * q;
+  if (n <= 0) return;
+  if (q < 1 || q > GlRule::kMax) RW_THROW(RW_EINVAL, "panel order outside 1..32");
+  hipLaunchKernelGGL(discretize_kernel, dim3(blocks(n)), dim3(256), 0, s, pan, n, q, gl, a, m, out);
+  KERNEL_CHECK("discretize");
+}
+
 void launch_gather_nodes(const NodeRec* src, const int* idx, int64_t n, NodeRec* dst, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(gather_nodes_kernel, dim3(blocks(n)), dim3(256), 0, s, src, idx, n, dst);

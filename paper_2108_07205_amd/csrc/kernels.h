@@ -119,6 +119,15 @@ void launch_to_ext(const double* g, int64_t ld_g, int64_t n_new, const int* new2
 void launch_from_ext(const double* ext, int64_t ld_ext, int64_t n_new, const int* new2ext, double* out,
                      int64_t ld_out, int nrhs, bool accumulate, hipStream_t s);
 void launch_gather_nodes(const NodeRec* src, const int* idx, int64_t n, NodeRec* dst, hipStream_t s);
+// Gauss-Legendre rule of a panel order up to kMax, passed by value to kernels
+struct GlRule {
+  static constexpr int kMax = 32;
+  double s[kMax], w[kMax];
+};
+// node records of n_panels panels of q nodes on the star curve (a, m): panel
+// i's parameter interval is (pan[2 i], pan[2 i + 1]) (device); out: n_panels q
+void launch_discretize(const double* pan, int64_t n_panels, int q, const GlRule& gl, double a, int m, NodeRec* out,
+                       hipStream_t s);
 
 // ------------------------------------------------------- dense FP64 algebra
 // cooperative row ID of Y (m x ncols, row-major): pivots J (k), coefficient

@@ -538,8 +538,7 @@ struct rw_refined {
   rw_ctx* ctx = nullptr;
   std::vector<int32_t> level_of_panel;
   double q_tol = 1e-10;                // row-ID tolerance of Q (rw_refine's q_tol or the wall's id_tol)
-  Discretization disc;                 // refined panels I_n (node records of added panels in pnodes)
-  std::vector<NodeRec> pnodes;         // added nodes I_p, in panel order
+  Discretization disc;                 // refined panels I_n (their node records: d_p, d_new)
   int64_t No = 0, Nk = 0, Nc = 0, Np = 0, Nn = 0, Next = 0;
   DBuf<NodeRec> d_ext;                 // [reference nodes | added nodes]
   DBuf<NodeRec> d_new, d_k, d_c, d_p;
@@ -738,7 +737,7 @@ void build_app_inverse(rw_wall* w, rw_refined& f, uint64_t seed, rw_ctx* ax) {
   const int64_t Mp = 2 * f.Np;
   if (f.app_hbs_on) {
     PhaseTimer t(ax, "a3_app_hbs_build", 0.0, 0.0);
-    hbs_gpu_build(ax, f.d_p.p, f.pnodes, w->leaf, w->tol, seed, f.app_hbs);
+    hbs_gpu_build(ax, f.d_p.p, f.Np, w->leaf, w->tol, seed, f.app_hbs);
     return;
   }
   DBuf<int> dinfo(ax, 4);   // pivot flag, then (8-byte aligned) the multiplier bits
@@ -765,7 +764,7 @@ void build_app_inverse(rw_wall* w, rw_refined& f, uint64_t seed, rw_ctx* ax) {
   f.App = DBuf<double>();
   f.app_hbs_on = true;
   PhaseTimer t(ax, "a3_app_hbs_build", 0.0, 0.0);
-  hbs_gpu_build(ax, f.d_p.p, f.pnodes, w->leaf, w->tol, seed, f.app_hbs);
+  hbs_gpu_build(ax, f.d_p.p, f.Np, w->leaf, w->tol, seed, f.app_hbs);
 }
 
 // Algorithm 1 pre-computation for the refinement described by level_of_panel,
@@ -789,18 +788,13 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
   f.disc.order = q;
   f.disc.panels = refined_panels(w->P, level_of_panel);
   f.disc.nodes.clear();
-  {
-    std::vector<Panel> added;
-    for (const Panel& p : f.disc.panels)
-      if (p.added) added.push_back(p);
-    Discretization dp;
-    discretize(w->curve.a, w->curve.m, q, w->gl_s, w->gl_w, std::move(added), dp);
-    f.pnodes = std::move(dp.nodes);
-  }
-  const std::vector<NodeRec>& pnodes = f.pnodes;
+  // the added panels' parameter intervals; their nodes are formed on the device
+  std::vector<double> added_iv;
+  for (const Panel& p : f.disc.panels)
+    if (p.added) { added_iv.push_back(p.ta); added_iv.push_back(p.tb); }
   f.No = (int64_t)w->disc.nodes.size();
   f.Nn = (int64_t)f.disc.panels.size() * q;
-  f.Np = (int64_t)pnodes.size();
+  f.Np = (int64_t)(added_iv.size() / 2) * q;
   int64_t n_cut_panels = 0;
   for (int i = 0; i < w->P; ++i) n_cut_panels += level_of_panel[i] >= 0;
   f.Nc = n_cut_panels * q;
@@ -811,7 +805,7 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
   // (one region per array), so the copies are asynchronous and the host
   // vectors may go out of scope at once; the buffer is next handed out once
   // these copies have run (ctx_pinned_used)
-  const size_t stage_bytes = sizeof(NodeRec) * f.Np +
+  const size_t stage_bytes = sizeof(double) * added_iv.size() +
                              sizeof(int) * (f.Nn + f.No + 3 * f.Nk + 2 * f.Np + f.Nc + 4 * f.Nk) + 16 * 256;
   char* stage_base = (char*)ctx_pinned(ctx, stage_bytes);
   size_t stage_off = 0;
@@ -825,7 +819,14 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
   };
   // the added nodes first: a3 needs only them, so it starts before the rest of a1
   f.d_p.alloc(ctx, f.Np);
-  up(f.d_p.p, pnodes.data(), sizeof(NodeRec) * f.Np);
+  DBuf<double> d_iv;
+  if (f.Np) {
+    d_iv.alloc(ctx, added_iv.size());
+    up(d_iv.p, added_iv.data(), sizeof(double) * added_iv.size());
+    GlRule gl{};
+    for (int j = 0; j < q; ++j) { gl.s[j] = w->gl_s[j]; gl.w[j] = w->gl_w[j]; }
+    launch_discretize(d_iv.p, (int64_t)added_iv.size() / 2, q, gl, w->curve.a, w->curve.m, f.d_p.p, s);
+  }
   // ---- a3: A_pp^{-1} (dense LU for few added points, else a GPU-built HBS
   // inverse) on the helper ctx, beside the rest of a1 and the compression of
   // Q on this stream
@@ -898,21 +899,32 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
     DBuf<int> dJ(ctx, 256);
     // Sec. 3.3: a circle of radius rho about the refined arc Gamma_r (its
     // cut and added nodes) splits the kept nodes into near (within
-    // FAR_RATIO rho: exact entries) and far (expansions about the center)
+    // FAR_RATIO rho: exact entries) and far (expansions about the center).
+    // The arc is sampled at its cut nodes and at the end points of the
+    // refined panels (the added nodes lie between them on the curve), and
+    // rho is widened by a relative 1e-4 for the curve between samples
     const std::vector<NodeRec>& rn = w->disc.nodes;
+    std::vector<double> ax, ay;
+    for (int i : c_ref) { ax.push_back(rn[i].x); ay.push_back(rn[i].y); }
+    const double hp = 2.0 * M_PI / w->P;
+    for (int i = 0; i < w->P; ++i)
+      if (level_of_panel[i] >= 0)
+        for (const double th : {i * hp, (i + 1) * hp}) {
+          const double r = 1.0 + w->curve.a * std::cos(w->curve.m * th);
+          ax.push_back(r * std::cos(th));
+          ay.push_back(r * std::sin(th));
+        }
     double bx0 = 1e300, bx1 = -1e300, by0 = 1e300, by1 = -1e300;
-    auto bbox = [&](const NodeRec& q) {
-      bx0 = std::min(bx0, q.x); bx1 = std::max(bx1, q.x);
-      by0 = std::min(by0, q.y); by1 = std::max(by1, q.y);
-    };
-    for (int i : c_ref) bbox(rn[i]);
-    for (const NodeRec& q : pnodes) bbox(q);
+    for (size_t i = 0; i < ax.size(); ++i) {
+      bx0 = std::min(bx0, ax[i]); bx1 = std::max(bx1, ax[i]);
+      by0 = std::min(by0, ay[i]); by1 = std::max(by1, ay[i]);
+    }
     const double fcx = 0.5 * (bx0 + bx1), fcy = 0.5 * (by0 + by1);
     auto d2 = [&](const NodeRec& q) { return (q.x - fcx) * (q.x - fcx) + (q.y - fcy) * (q.y - fcy); };
     double rho2 = 0.0;
-    for (int i : c_ref) rho2 = std::max(rho2, d2(rn[i]));
-    for (const NodeRec& q : pnodes) rho2 = std::max(rho2, d2(q));
-    const double rho = std::sqrt(rho2), near2 = FAR_RATIO * FAR_RATIO * rho2;
+    for (size_t i = 0; i < ax.size(); ++i)
+      rho2 = std::max(rho2, (ax[i] - fcx) * (ax[i] - fcx) + (ay[i] - fcy) * (ay[i] - fcy));
+    const double rho = std::sqrt(rho2) * (1.0 + 1e-4), near2 = FAR_RATIO * FAR_RATIO * rho * rho;
     std::vector<int> near_a, far_a, near_ref, far_ref;
     near_a.reserve(f.Nk);
     far_a.reserve(f.Nk);
@@ -1561,13 +1573,12 @@ int rw_refined_info(const rw_refined* f, rw_info* info) {
 int rw_nodes(const rw_refined* f, double* xy, double* nrm, double* wts, int64_t* n_nodes) {
   if (!f) return RW_EINVAL;
   return guarded(f->ctx, [&]() {
-    // refined nodes in panel order: kept panels from the reference wall, added ones from pnodes
-    const int q = f->disc.order;
-    std::vector<NodeRec> nd;
-    nd.reserve((size_t)f->Nn);
-    size_t ip = 0;
-    for (const Panel& p : f->disc.panels)
-      for (int j = 0; j < q; ++j) nd.push_back(p.added ? f->pnodes[ip++] : f->wall->disc.nodes[(size_t)p.ref_id * q + j]);
+    // refined nodes in panel order (the device's node records of the refined discretization)
+    std::vector<NodeRec> nd((size_t)f->Nn);
+    if (f->Nn && (xy || nrm || wts)) {
+      HIP_CHECK(hipMemcpyAsync(nd.data(), f->d_new.p, sizeof(NodeRec) * f->Nn, hipMemcpyDeviceToHost, f->ctx->stream));
+      HIP_CHECK(hipStreamSynchronize(f->ctx->stream));
+    }
     copy_nodes_out(nd, xy, nrm, wts, n_nodes);
   });
 }
