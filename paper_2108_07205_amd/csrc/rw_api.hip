@@ -678,9 +678,11 @@ void woodbury_apply(rw_refined* f, const double* src, double* dst, int nrhs, boo
   woodbury_in(f, src, nrhs);
   const bool hbs_app = f->Np > 0 && f->app_hbs_on;
   bool side_busy = false;
-  // (with k_p = 1 the side stream's A_pp^{-1} L_p uses the same one-column
-  // workspace of the A_pp inverse, so that case keeps to the side stream)
-  if (hbs_app && f->app_ready.e && f->k_p != 1) {
+  // Only for one right-hand side, and not with k_p = 1: the side stream's
+  // A_pp^{-1} L_p uses the A_pp inverse's multi-column workspace (its
+  // one-column one when k_p = 1), which this apply must not share while
+  // that runs; other cases keep to the side stream, behind it
+  if (hbs_app && f->app_ready.e && nrhs == 1 && f->k_p != 1) {
     const hipError_t q = hipEventQuery(f->done.e);
     if (q == hipErrorNotReady) (void)hipGetLastError();   // not an error: the side stream is still at work
     else HIP_CHECK(q);

@@ -109,3 +109,30 @@ def test_one_stream_ctx_matches_default(app_dense_max_nodes):
          f"app entries {res[0][2]}/{res[1][2]}, diff {d:.1e}")
     assert res[0][1:] == res[1][1:]
     assert d <= 1e-13
+
+
+def test_multi_rhs_solve_right_after_refine():
+    """A solve of several right-hand sides enqueued right behind its
+    refinement (whose last part still runs on the side stream) equals the
+    same solve repeated once everything has finished, bit for bit, on the
+    GPU-built A_pp inverse (16384-node wall, 16 panels x 4 levels), and
+    meets the FP64 residual bar: the solve's A_pp^{-1} applies must not share
+    a workspace with the refinement's X_p = A_pp^{-1} L_p."""
+    ctx = rw.Context(0)
+    wall = rw.Wall(ctx, 1024)
+    for seed in (0, 3):
+        p = W.config2(seed=seed)
+        rng = np.random.default_rng(seed)
+        sts = [W.stokeslets(rng, 16) for _ in range(8)]
+        ref = wall.refine(p.refinement.panel_ids, p.refinement.levels)
+        g = torch.stack([ref.stokeslet_rhs(s.z, s.f) for s in sts]).contiguous()
+        info1, info2 = {}, {}
+        t1 = ref.solve(g, info=info1)
+        torch.cuda.synchronize()
+        t2 = ref.solve(g, info=info2)
+        _say(f"multi-RHS right after refine (seed {seed}): resid {info1['resid']:.1e} / {info2['resid']:.1e}, "
+             f"equal {bool(torch.equal(t1, t2))}")
+        assert info1["resid"] <= 1e-13 and torch.equal(t1, t2)
+        ref.close()
+    wall.close()
+    ctx.close()
