@@ -2200,13 +2200,15 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, int64_t n_nodes, int lea
   // profiler entries of the factor launches (their flops are known once the ranks are read back)
   std::vector<size_t> fac_entry(L + 1, SIZE_MAX);
   auto factor_launch = [&](const GNode* gn, const GNode* gch, int nn, int is_leaf, int is_root, const int* cr,
-                           const int* cc, const double* U, const double* V, double* groot, int mx_known, int lvl,
-                           hipStream_t fs) {
+                           const int* cc, const double* U, const double* V, double* groot, int mn_known, int mx_known,
+                           int lvl, hipStream_t fs) {
     // nodes with n + k <= BT: bordered Gauss-Jordan; the others: block
     // inverse in registers (n <= FN) or LDS Gauss-Jordan, launched first on
     // the same stream (each kernel takes only its own nodes and returns at
-    // once when it has none)
-    const bool small = !is_root && (mx_known < 0 || mx_known <= FN);
+    // once when it has none).  mn_known / mx_known: the smallest and largest
+    // node input of the level when the host knows them (the leaves, whose
+    // sizes can differ by one node), else -1
+    const bool small = !is_root && (mn_known < 0 || mn_known <= FN);
     const bool large = !is_root && (mx_known < 0 || mx_known > FN);
     if (small) {
       KernelTimer kt("node_factor_kernel", 0.0, 0.0, fs);
@@ -2239,10 +2241,10 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, int64_t n_nodes, int lea
     int* cr = candr.p + cand_base[l];
     int* cc = candc.p + cand_base[l];
     // host-known sizes at the leaves; bounds above them
-    int mx = 0;
+    int mx = 0, mn = 1 << 30;
     int64_t off = 0;
     if (leaf) {
-      for (const GNode& g : G[L]) { off += g.m; mx = std::max(mx, g.m); }
+      for (const GNode& g : G[L]) { off += g.m; mx = std::max(mx, g.m); mn = std::min(mn, g.m); }
       if (mx > mmax) RW_THROW(RW_ESINGULAR, "HBS node input exceeds the sketch bound");
       if (mx > ID_NT / 2) RW_THROW(RW_EINVAL, "HBS leaf of more than 128 nodes");
     } else {
@@ -2260,7 +2262,8 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, int64_t n_nodes, int lea
         hipLaunchKernelGGL(node_sketch_kernel, grid, dim3(256), 0, s, dgl, cr, cc, d_nodes, N, sd, len, part_r.p,
                            part_c.p, 0, MANY);
       } else {
-        if (!leaf || mx <= 128)
+        // each kernel takes the nodes of its size range (leaves can straddle 128)
+        if (!leaf || mn <= 128)
           hipLaunchKernelGGL(node_sketch_mfma_kernel<2>, grid, dim3(256), 0, s, dgl, cr, cc, d_nodes, N, sd, len,
                              outr, outc, 0, 128);
         if (!leaf || mx > 128)
@@ -2295,12 +2298,12 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, int64_t n_nodes, int lea
     if (l > 1) stream_after(ctx, sf, s, 1);
     else { stream_after(ctx, s, sf, 1); fs = s; }
     factor_launch(dgl, dch, nn, leaf ? 1 : 0, 0, cr, cc, Ub.p + uv_base[l], Vb.p + uv_base[l], (double*)nullptr,
-                  leaf ? mx : -1, l, fs);
+                  leaf ? mn : -1, leaf ? mx : -1, l, fs);
     std::swap(dh_child, dh_cur);
   }
   // ---- root (its record was completed by the level-1 plan)
   factor_launch(dg.p + 1, dg.p + 2, 1, 0, 1, candr.p + cand_base[0], candc.p + cand_base[0], Ub.p, Vb.p, w.groot.p,
-                -1, 0, s);
+                -1, -1, 0, s);
   // ---- apply descriptors on the device; the host keeps bounds of the
   // sizes, and the records and flags are read back without a wait
   w.d_ints.alloc(ctx, (size_t)((int64_t(4) << L) - 3));

@@ -174,3 +174,26 @@ def test_app_hbs_build_is_deterministic(ctx, n_panels, maker):
     assert seen[0][0] > 0
     assert seen[0] == seen[1] == seen[2]
     wall.close()
+
+
+def test_app_hbs_leaves_of_two_sizes(ctx):
+    """4128 added nodes (one panel at level 8, one at level 1): the arc tree's
+    leaves hold 64 or 65 nodes, so its leaf level straddles the 128-unknown
+    limit between kernel variants.  Every leaf must be sketched and factored
+    whichever variant takes it: three builds agree, and the solve reaches
+    the FP64 residual bar."""
+    wall = rw.Wall(ctx, 64)
+    st = W.stokeslets(np.random.default_rng(12), 8)
+    seen = []
+    for rep in range(3):
+        ref = wall.refine([10, 40], [8, 1])
+        g = ref.stokeslet_rhs(st.z, st.f)
+        info = {}
+        ref.solve(g, info=info)
+        inf = ref.info()
+        seen.append((inf["app_entries"], inf["app_max_rank"], inf["k"]))
+        assert inf["n_p"] == 4128 and info["resid"] <= 1e-13
+        ref.close()
+    _say(f"two leaf sizes: (entries, max rank, k) = {seen}")
+    assert seen[0][0] > 0 and seen[0] == seen[1] == seen[2]
+    wall.close()

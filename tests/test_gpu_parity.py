@@ -141,6 +141,7 @@ def test_refined_solve_config1(ctx, wall64, seed):
     assert (inf["n_k"], inf["n_c"], inf["n_p"]) == (sets.k_in_ref.size, sets.c_in_ref.size, sets.p_in_new.size)
     xy, nr, w = ref.nodes()
     assert np.max(np.abs(xy - sets.new.x)) < 1e-13 and np.max(np.abs(w - sets.new.w) / sets.new.w) < 1e-13
+    assert np.max(np.abs(nr - sets.new.normal)) < 1e-13
     st = p.rhs[0]
     g = ref.stokeslet_rhs(st.z, st.f)
     g_or = K.rhs_vector(sets.new, st.z, st.f)
@@ -316,6 +317,28 @@ def test_unrefined_and_level_zero(ctx, wall64):
     inf = ref.info()
     assert inf["n_p"] == inf["n_c"] == 32
     assert relerr(ref.solve(_dev(g)).cpu().numpy(), tau_or) <= 1e-10
+    ref.close()
+
+
+def test_max_level_parity(ctx, wall64):
+    """The deepest refinement the boundary allows (level 8: one panel of the
+    64-panel wall split into 256 children, 4096 added nodes, the GPU-built
+    A_pp inverse) against the dense oracle, with a second panel at level 1
+    beside it (uneven levels).  The children have the size of a 4-level
+    refinement of the 1024-panel wall, so the same FP64 bar holds."""
+    ids, levels = [10, 40], [8, 1]
+    sets = G.refine(64, ids, levels, 0.3, 5)
+    st = W.stokeslets(np.random.default_rng(12), 8)
+    g = K.rhs_vector(sets.new, st.z, st.f)
+    tau_or = S.solve_refined(K.nystrom_matrix(sets.new), g)
+    ref = wall64.refine(ids, levels)
+    info = {}
+    tau = ref.solve(_dev(g), info=info).cpu().numpy()
+    inf = ref.info()   # (the A_pp inverse's statistics are read with the first solve)
+    e = relerr(tau, tau_or)
+    _say(f"level 8: n_p={inf['n_p']} k={inf['k']} ir={info['ir_iters']} resid={info['resid']:.1e} err={e:.2e}")
+    assert inf["n_p"] == 16 * (256 + 2) and inf["app_entries"] > 0
+    assert info["resid"] <= 1e-13 and e <= 1e-10
     ref.close()
 
 
