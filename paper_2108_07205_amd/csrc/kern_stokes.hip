@@ -24,6 +24,7 @@ constexpr int RRB = 4;   // right-hand sides per pass
 constexpr int RT1 = 4;   // targets per thread of the one-right-hand-side kernel
 
 int resid_splits(int64_t n, int nrhs) {
+  if (n <= 0 || nrhs <= 0) return 1;
   if (nrhs == 1) {
     // scalar-broadcast kernel: 256 RT1 targets per workgroup; about 8 waves per SIMD
     const int64_t tb = (n + 256 * RT1 - 1) / (256 * RT1);
@@ -579,6 +580,7 @@ __global__ __launch_bounds__(256) void sum_parts_kernel(const double* __restrict
 }
 
 int sketch_splits(int64_t nt, int64_t nsrc) {
+  if (nt <= 0) return 1;   // no targets (a near set can be empty): no splits to size
   const int64_t rb = (2 * nt + 63) / 64;
   int64_t s = (2048 + rb - 1) / rb;
   const int64_t pairs = (nsrc + 1) / 2;

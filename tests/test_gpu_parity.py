@@ -552,3 +552,36 @@ def test_golden_full_tau(ctx, wall1024, case):
     assert e2 <= 1e-10
     assert emax <= GOLDEN_MAX_TOL[case]
     ref.close()
+
+
+@pytest.mark.parametrize("ids,levels,dense_max", [
+    (list(range(64)), [1] * 64, 1024 * 1024),     # every panel refined: no kept nodes
+    (list(range(1, 64)), [1] * 63, 1024 * 1024),  # one kept panel
+    ([63, 0], [3, 3], 1024),                      # a run across theta = 0
+    ([7], [0], 0),                                # 16 added nodes through the GPU-built A_pp inverse
+    ([7, 9], [1, 0], 0),                          # 48 added nodes, two runs, GPU-built A_pp inverse
+])
+def test_edge_refinements(ctx, wall64, ids, levels, dense_max):
+    """Degenerate and boundary refinements against the dense oracle: no or
+    one kept panel, a run that wraps around theta = 0, and GPU-built A_pp
+    inverses of very few added nodes."""
+    sets = G.refine(64, ids, levels, 0.3, 5)
+    st = W.stokeslets(np.random.default_rng(5), 8)
+    g = K.rhs_vector(sets.new, st.z, st.f)
+    tau_or = S.solve_refined(K.nystrom_matrix(sets.new), g)
+    ctx.set_options(app_dense_max_nodes=dense_max)
+    try:
+        ref = wall64.refine(ids, levels)
+        info = {}
+        tau = ref.solve(_dev(g), info=info).cpu().numpy()
+        inf = ref.info()
+    finally:
+        ctx.set_options(app_dense_max_nodes=1024)
+    e = relerr(tau, tau_or)
+    _say(f"edge {len(ids)} panels levels {sorted(set(levels))}: n_k={inf['n_k']} n_p={inf['n_p']} k={inf['k']} "
+         f"app entries={inf['app_entries']} ir={info['ir_iters']} err={e:.2e}")
+    assert (inf["n_k"], inf["n_c"], inf["n_p"]) == (sets.k_in_ref.size, sets.c_in_ref.size, sets.p_in_new.size)
+    assert info["resid"] <= 1e-13 and e <= 1e-10
+    if dense_max == 0:
+        assert inf["app_entries"] > 0
+    ref.close()
