@@ -195,9 +195,10 @@ int64_t rw_profile_json(rw_ctx* ctx, char* buf, int64_t len);
  * nodes, uniform in theta, and build the HBS compressed inverse A_oo^{-1}
  * (tree of contiguous arcs, leaves of `leaf_nodes` nodes; interpolative
  * decompositions at relative tolerance id_tol, Definition 3.1).  The
- * generators are uploaded to HBM.  Requirements: order in [2, 32],
- * n_panels*order divisible by leaf_nodes, leaf_nodes % order == 0,
- * n_panels*order/leaf_nodes a power of two >= 2.
+ * generators are uploaded to HBM.  The tree has the fewest binary levels
+ * whose leaves hold at most leaf_nodes nodes (2^L leaves of consecutive
+ * nodes, their sizes differing by at most one).  Requirements: order in
+ * [2, 32], n_panels >= 2, leaf_nodes a positive multiple of order.
  * Errors: RW_EINVAL, RW_ENOMEM, RW_ESINGULAR, RW_EDEVICE. */
 int rw_wall_build(rw_ctx* ctx, const rw_curve* curve, int32_t n_panels, int32_t order,
                   int32_t leaf_nodes, double id_tol, int32_t precision, rw_wall** out);

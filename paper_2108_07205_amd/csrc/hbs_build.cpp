@@ -171,11 +171,13 @@ void compress_node(const std::vector<NodeRec>& nd, const HbsParams& prm, CNode& 
 
 void hbs_build_inverse(const std::vector<NodeRec>& nd, const HbsParams& prm, HbsInverse& out) {
   const int64_t N = (int64_t)nd.size();
-  const int64_t nleaf = N / prm.leaf_nodes;
-  int L = 0;
-  while ((int64_t(1) << L) < nleaf) ++L;
-  if ((int64_t(1) << L) != nleaf || nleaf * prm.leaf_nodes != N || L < 1)
-    RW_THROW(RW_EINVAL, "HBS tree needs N / leaf_nodes to be a power of two >= 2");
+  if (prm.leaf_nodes < 1 || N < 2) RW_THROW(RW_EINVAL, "HBS tree needs at least two nodes");
+  // 2^L leaves of floor or ceil(N / 2^L) <= leaf_nodes consecutive nodes:
+  // node j of binary depth d covers [(j N) >> d, ((j + 1) N) >> d), so the
+  // ranges nest whatever N
+  int L = 1;
+  while (((N + (int64_t(1) << L) - 1) >> L) > prm.leaf_nodes) ++L;
+  if ((int64_t(1) << L) > N) RW_THROW(RW_EINVAL, "HBS leaves would be empty");
   if (prm.merge < 1 || prm.merge > 4) RW_THROW(RW_EINVAL, "HBS merge outside [1, 4]");
   // tree levels t = 0 (root) .. T (leaves) at binary depths dep[t]: a node
   // at level t covers N / 2^dep[t] nodes and has 2^(dep[t+1] - dep[t])
@@ -195,13 +197,13 @@ void hbs_build_inverse(const std::vector<NodeRec>& nd, const HbsParams& prm, Hbs
 
   // ---- compression, leaves to level 1
   for (int t = T; t >= 1; --t) {
-    const int64_t cnt = int64_t(1) << dep[t], sz = N / cnt;
+    const int64_t cnt = int64_t(1) << dep[t];
     const int B = nchild(t);
     cn[t].resize(cnt);
     parallel_for(cnt, [&](int64_t j) {
       CNode& c = cn[t][j];
-      c.n0 = j * sz;
-      c.n1 = (j + 1) * sz;
+      c.n0 = (j * N) >> dep[t];
+      c.n1 = ((j + 1) * N) >> dep[t];
       if (t == T) {
         for (int64_t d = 2 * c.n0; d < 2 * c.n1; ++d) c.candr.push_back((int)d);
         c.candc = c.candr;

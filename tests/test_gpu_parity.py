@@ -585,3 +585,31 @@ def test_edge_refinements(ctx, wall64, ids, levels, dense_max):
     if dense_max == 0:
         assert inf["app_entries"] > 0
     ref.close()
+
+
+@pytest.mark.parametrize("n_panels", [37, 75, 100])
+def test_walls_of_any_panel_count(ctx, n_panels):
+    """Reference walls whose panel counts are not powers of two (leaves of
+    37, of 37 and 38, and of 50 nodes) against the dense oracle: the reference inverse applied to a
+    vector, and a refined solve with two runs of uneven levels."""
+    wall = rw.Wall(ctx, n_panels)
+    d = G.discretize(G.reference_panels(n_panels), 0.3, 5)
+    A = K.nystrom_matrix(d)
+    rng = np.random.default_rng(n_panels)
+    b = rng.standard_normal(2 * d.n)
+    x = torch.empty(2 * d.n, dtype=torch.float64, device="cuda")
+    rw.rw_hbs_apply(ctx.h, wall.h, _dev(b), x, 2 * d.n)
+    ea = relerr(x.cpu().numpy(), np.linalg.solve(A, b))
+    ids, levels = [3, 4, n_panels - 2], [3, 1, 4]
+    sets = G.refine(n_panels, ids, levels, 0.3, 5)
+    st = W.stokeslets(np.random.default_rng(3), 8)
+    g = K.rhs_vector(sets.new, st.z, st.f)
+    tau_or = S.solve_refined(K.nystrom_matrix(sets.new), g)
+    ref = wall.refine(ids, levels)
+    info = {}
+    tau = ref.solve(_dev(g), info=info).cpu().numpy()
+    e = relerr(tau, tau_or)
+    _say(f"{n_panels} panels: apply err {ea:.2e}; refined k={ref.info()['k']} ir={info['ir_iters']} err={e:.2e}")
+    assert ea <= 1e-9 and info["resid"] <= 1e-13 and e <= 1e-10
+    ref.close()
+    wall.close()
