@@ -613,3 +613,26 @@ def test_walls_of_any_panel_count(ctx, n_panels):
     assert ea <= 1e-9 and info["resid"] <= 1e-13 and e <= 1e-10
     ref.close()
     wall.close()
+
+
+@pytest.mark.parametrize("order,leaf,a,m", [(8, 64, 0.3, 5), (24, 72, 0.3, 5), (16, 64, 0.2, 3)])
+def test_other_orders_and_curves(ctx, order, leaf, a, m):
+    """Panel orders other than 16 and another star curve (a, m) against the
+    dense oracle, which takes the same parameters: a refined solve with two
+    runs of uneven levels on a 64-panel wall."""
+    wall = rw.Wall(ctx, 64, order=order, leaf_nodes=leaf, a=a, m=m)
+    ids, levels = [5, 6, 40], [2, 3, 1]
+    sets = G.refine(64, ids, levels, a, m, q=order)
+    st = W.stokeslets(np.random.default_rng(order), 8)
+    g = K.rhs_vector(sets.new, st.z, st.f)
+    tau_or = S.solve_refined(K.nystrom_matrix(sets.new), g)
+    ref = wall.refine(ids, levels)
+    xy, nr, w = ref.nodes()
+    assert np.max(np.abs(xy - sets.new.x)) < 1e-13 and np.max(np.abs(w - sets.new.w) / sets.new.w) < 1e-12
+    info = {}
+    tau = ref.solve(_dev(g), info=info).cpu().numpy()
+    e = relerr(tau, tau_or)
+    _say(f"order {order}, leaf {leaf}, curve ({a}, {m}): k={ref.info()['k']} ir={info['ir_iters']} err={e:.2e}")
+    assert info["resid"] <= 1e-13 and e <= 1e-10
+    ref.close()
+    wall.close()
