@@ -443,8 +443,10 @@ def test_invalid_arguments_and_budget(ctx, wall64):
         rw.Wall(small, 64)
     assert ei.value.code == rw.RW_ENOMEM
     small.close()
-    with pytest.raises(rw.RwError):
-        rw.Wall(ctx, 60)   # 60 * 16 / 64 = 15 leaves: not a power of two
+    for bad in (dict(n_panels=1), dict(n_panels=64, leaf_nodes=40), dict(n_panels=64, order=40)):
+        with pytest.raises(rw.RwError) as ei:
+            rw.Wall(ctx, **bad)   # one panel; leaves not a multiple of the order; order above 32
+        assert ei.value.code == rw.RW_EINVAL
 
 
 def test_config2_full_size_sampled(ctx):
