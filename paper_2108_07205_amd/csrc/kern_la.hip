@@ -1005,13 +1005,17 @@ void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, 
 
 void launch_sub_xw(const double* X, int64_t ldx, int64_t M, int k, const double* W, double* Y, int64_t ldy, int nrhs,
                    hipStream_t s) {
-  if (k <= 0 || M <= 0) return;
-  const size_t sh = sizeof(double) * k * nrhs;
-  if (sh > 150 * 1024) RW_THROW(RW_EINVAL, "too many right-hand sides for one Woodbury pass");
-  func_lds_at_least((const void*)sub_xw_kernel, (int)sh);
-  hipLaunchKernelGGL(sub_xw_kernel, dim3(blocks(M)), dim3(256), sizeof(double) * k * nrhs, s, X, ldx, M, k, W, Y, ldy,
-                     nrhs);
-  KERNEL_CHECK("sub_xw");
+  if (k <= 0 || M <= 0 || nrhs <= 0) return;
+  // W (k x nrhs) is staged in LDS: as many columns per launch as 150 KB hold
+  const int per = (int)std::min<int64_t>(nrhs, (150 * 1024) / (sizeof(double) * k));
+  if (per < 1) RW_THROW(RW_EINVAL, "Woodbury rank too large for one column in LDS");
+  func_lds_at_least((const void*)sub_xw_kernel, (int)(sizeof(double) * k * per));
+  for (int c0 = 0; c0 < nrhs; c0 += per) {
+    const int nc = std::min(per, nrhs - c0);
+    hipLaunchKernelGGL(sub_xw_kernel, dim3(blocks(M)), dim3(256), sizeof(double) * k * nc, s, X, ldx, M, k,
+                       W + (size_t)c0 * k, Y + (size_t)c0 * ldy, ldy, nc);
+    KERNEL_CHECK("sub_xw");
+  }
 }
 
 bool launch_woodbury_sub(const double* X, int64_t ldx, int64_t M, int k, const double* Winv, const double* z,

@@ -638,3 +638,22 @@ def test_other_orders_and_curves(ctx, order, leaf, a, m):
     assert info["resid"] <= 1e-13 and e <= 1e-10
     ref.close()
     wall.close()
+
+
+def test_many_rhs(ctx, wall64):
+    """One solve of 300 right-hand sides (more Woodbury columns than one LDS
+    pass holds, several matrix-core passes of the reference inverse) against
+    the dense oracle, column by column."""
+    p = W.config1(seed=6)
+    sets = _oracle_sets(p)
+    rng = np.random.default_rng(60)
+    sts = [W.stokeslets(rng, 8) for _ in range(300)]
+    G_or = np.stack([K.rhs_vector(sets.new, s.z, s.f) for s in sts], axis=1)
+    T_or = S.solve_refined(K.nystrom_matrix(sets.new), G_or)
+    ref = wall64.refine(p.refinement.panel_ids, p.refinement.levels)
+    info = {}
+    tau = ref.solve(_dev(G_or.T.copy()), info=info).cpu().numpy()
+    e = float(np.max(np.linalg.norm(tau - T_or.T, axis=1) / np.linalg.norm(T_or.T, axis=1)))
+    _say(f"300 RHS: k={ref.info()['k']} ir={info['ir_iters']} resid={info['resid']:.1e} worst column err={e:.2e}")
+    assert info["resid"] <= 1e-13 and e <= 1e-10
+    ref.close()
