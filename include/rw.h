@@ -70,6 +70,18 @@ enum rw_solver {
   RW_SOLVE_GMRES = 1  /* GMRES on the exact A_nn, right-preconditioned by the Woodbury solve (Sec. 4) */
 };
 
+/* How the products A_nn tau of the residual (and of GMRES) are formed.  Both
+ * are the Nystrom operator of Sec. 2 in FP64 with no approximation beyond
+ * rounding: the expansions cut the multipole series of the double layer
+ * (Sec. 4.2 names fast products of this kind) where the dropped terms are
+ * below 1e-17 of the cluster's own contribution. */
+enum rw_resid {
+  RW_RESID_AUTO = 0,   /* RW_RESID_EXPAND from 4096 nodes, RW_RESID_PAIRS below */
+  RW_RESID_PAIRS = 1,  /* every pair of nodes summed directly */
+  RW_RESID_EXPAND = 2  /* clusters of 256 consecutive nodes farther than 3 cluster radii from a wave of 64
+                          targets through their 40-term multipole expansions, the others pair by pair */
+};
+
 /* Star curve gamma(theta) = (1 + a cos(m theta)) (cos theta, sin theta),
  * theta in [0, 2 pi), counter-clockwise (a = 0: unit circle). */
 typedef struct {
@@ -107,6 +119,7 @@ typedef struct {
                                 helper thread and no side streams (the A_pp inverse then runs before the
                                 compression of Q instead of beside it): for contexts that run side by side,
                                 each on one hardware queue, such as the slots of rw_server_create [0] */
+  int32_t resid_mode;        /* an rw_resid value [RW_RESID_AUTO] */
 } rw_options;
 
 /* Counts and timings reported by rw_refine / rw_solve. */

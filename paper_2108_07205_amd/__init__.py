@@ -27,7 +27,8 @@ __all__ = [
     "rw_refined_free", "rw_refined_info", "rw_nodes", "rw_solve", "rw_residual", "rw_stokeslet_rhs",
     "rw_ctx_trim", "rw_profile_enable", "rw_profile_reset", "rw_profile_json",
     "RW_OK", "RW_EINVAL", "RW_ENOMEM", "RW_ESINGULAR", "RW_ENOCONV", "RW_EDEVICE", "RW_F64", "RW_F32",
-    "RW_BF16", "RW_SOLVE_IR", "RW_SOLVE_GMRES", "rw_solve_batch", "rw_refine_on", "Server", "RefCache",
+    "RW_BF16", "RW_SOLVE_IR", "RW_SOLVE_GMRES", "RW_RESID_AUTO", "RW_RESID_PAIRS", "RW_RESID_EXPAND",
+    "rw_solve_batch", "rw_refine_on", "Server", "RefCache",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -37,6 +38,7 @@ LIB_PATH = os.path.join(HERE, "librw.so")
 RW_OK, RW_EINVAL, RW_ENOMEM, RW_ESINGULAR, RW_ENOCONV, RW_EDEVICE = 0, -1, -2, -3, -4, -5
 RW_F64, RW_F32, RW_BF16 = 0, 1, 2
 RW_SOLVE_IR, RW_SOLVE_GMRES = 0, 1
+RW_RESID_AUTO, RW_RESID_PAIRS, RW_RESID_EXPAND = 0, 1, 2
 _CODES = {RW_EINVAL: "RW_EINVAL", RW_ENOMEM: "RW_ENOMEM", RW_ESINGULAR: "RW_ESINGULAR",
           RW_ENOCONV: "RW_ENOCONV", RW_EDEVICE: "RW_EDEVICE"}
 
@@ -57,7 +59,8 @@ class rw_options(ctypes.Structure):
                 ("app_dense_max_nodes", ctypes.c_int32), ("far_field", ctypes.c_int32),
                 ("hbs_merge", ctypes.c_int32), ("solver", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
                 ("gmres_precond", ctypes.c_int32), ("mfma_from", ctypes.c_int32), ("test_singular", ctypes.c_int32),
-                ("one_stream", ctypes.c_int32)]
+                ("one_stream", ctypes.c_int32),
+                ("resid_mode", ctypes.c_int32)]
 
 
 class rw_info(ctypes.Structure):
@@ -207,7 +210,7 @@ def rw_ctx_destroy(ctx):
 
 def rw_set_options(ctx, ir_tol=None, ir_maxit=None, sketch_cols=None, seed=None, app_dense_max_nodes=None,
                    far_field=None, test_singular=None, hbs_merge=None, solver=None, gmres_restart=None,
-                   gmres_precond=None, mfma_from=None, one_stream=None):
+                   gmres_precond=None, mfma_from=None, one_stream=None, resid_mode=None):
     lib = load_library()
     o = rw_options()
     _check(lib.rw_get_options(ctx, ctypes.byref(o)), ctx)
@@ -237,6 +240,8 @@ def rw_set_options(ctx, ir_tol=None, ir_maxit=None, sketch_cols=None, seed=None,
         o.mfma_from = int(mfma_from)
     if one_stream is not None:
         o.one_stream = int(bool(one_stream))
+    if resid_mode is not None:
+        o.resid_mode = int(resid_mode)
     _check(lib.rw_set_options(ctx, ctypes.byref(o)), ctx)
 
 

@@ -344,6 +344,381 @@ __global__ __launch_bounds__(64) void resid_norms_kernel(const double* __restric
   }
 }
 
+// ------------------------------------------- residual, far clusters by expansion
+// The sources are cut into clusters of RC_CS consecutive nodes (arcs of the
+// curve, since a discretization stores its panels in curve order).  A wave of
+// 64 consecutive targets, inside a circle of radius R_t about c_t, takes a
+// cluster (radius R_s about c_s) whose centre is at least RC_RATIO R_s + R_t
+// from c_t through the cluster's multipole expansion, every other cluster
+// pair by pair (as resid_scalar_kernel).  The expansion comes from the
+// complex form of the double layer D of Sec. 2 (source zeta with normal nu,
+// weight w, density mu; target z):
+//   D mu = (w / 4 pi) [ nu mu / r + 2 Re(conj(nu) mu) / conj(r)
+//                       + r conj(nu mu) / conj(r)^2 ],   r = z - zeta,
+// with Z = z - c_s, t = zeta - c_s, s = t / R_s and W = R_s / Z (|s| <= 1):
+//   sum_j D_j mu_j = iz G(W) + conj(iz E(W)) + Z conj(iz^2 F(W)),  iz = 1 / Z,
+//   G_p = sum_j a_j s_j^p,   F_p = (p + 1) G_p,
+//   E_q = sum_j b_j s_j^q - q a_j conj(s_j) s_j^(q - 1),
+//   a_j = w_j nu_j mu_j / (4 pi),   b_j = w_j Re(conj(nu_j) mu_j) / (2 pi),
+// the geometric series of 1 / (Z - t) and 1 / (Z - t)^2 in t / Z.  The far
+// test keeps |W| <= 1 / RC_RATIO = 1/3 at every target of the wave, where
+// the series cut after p = RC_P = 40 leaves less than 1e-17 of the
+// cluster's sum_j |a_j| / |Z| (the squared series, with its factor p + 1,
+// included).
+constexpr int RC_CS = 256;       // nodes per source cluster (one packing workgroup)
+constexpr int RC_P = 40;         // highest power kept
+constexpr int RC_NP = RC_P + 1;
+constexpr double RC_RATIO = 3.0;
+constexpr int RC_REC = 256;      // doubles per cluster record: c_x, c_y, R, 0, then (G_p, F_p, E_p), p = 0..RC_P
+constexpr int RC_PG = (RC_NP + 3) / 4;   // groups of four powers in the coefficient sums
+constexpr int RC_SG = 256 / RC_PG;        // source groups in the coefficient sums
+constexpr int64_t RC_MIN_N = 4096;   // RW_RESID_AUTO: expansions from this many nodes
+static_assert(4 + 6 * RC_NP <= RC_REC, "cluster record too small");
+
+__device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Wave-wide min / max / sum by butterfly (every lane holds the result).
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+// A double that is the same in every lane, moved to scalar registers (so that
+// branches on it and addresses from it are scalar).
+__device__ __forceinline__ double uniform_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// grid (ceil(n / RC_CS), nrhs), 256 threads.  Block b, column c: packs the
+// sources of cluster b (the RPK format of resid_scalar_kernel, at
+// pk + (c n + j) RPK), writes the flux partial of its nodes to
+// fpart[c nb + b] and the cluster's record to rec + (c nb + b) RC_REC.
+__global__ __launch_bounds__(256) void resid_clusters_kernel(const NodeRec* __restrict__ nd, int64_t n,
+                                                             const double* __restrict__ tau, double* __restrict__ pk,
+                                                             double* __restrict__ fpart, double* __restrict__ rec) {
+  __shared__ double red4[4];
+  __shared__ double wred[4][4];
+  __shared__ double2 sa[RC_CS], sas[RC_CS], ss[RC_CS];   // a_j, a_j conj(s_j), s_j
+  __shared__ double sb[RC_CS];                           // b_j
+  __shared__ double2 gpart[RC_SG][4 * RC_PG], epart[RC_SG][4 * RC_PG];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int b = blockIdx.x, c = blockIdx.y, nb = gridDim.x;
+  const int64_t j = (int64_t)b * RC_CS + tid;
+  const bool ok = j < n;
+  const double* tc = tau + (int64_t)c * 2 * n;
+  NodeRec q{};
+  double tx = 0.0, ty = 0.0, fl = 0.0;
+  if (ok) {
+    q = nd[j];
+    tx = tc[2 * j];
+    ty = tc[2 * j + 1];
+    double* o = pk + ((int64_t)c * n + j) * RPK;
+    o[0] = q.x;
+    o[1] = q.y;
+    o[2] = q.nx * q.w * kInvPi;
+    o[3] = q.ny * q.w * kInvPi;
+    o[4] = tx;
+    o[5] = ty;
+    o[6] = 0.0;
+    o[7] = 0.0;
+    fl = flux_term(q, tc, j);
+  }
+  const double fsum = block_sum256(fl, red4);
+  if (tid == 0) fpart[(int64_t)c * nb + b] = fsum;
+  // bounding box of the cluster, its centre and radius
+  {
+    const double v0 = wave_min(ok ? q.x : INFINITY), v1 = wave_max(ok ? q.x : -INFINITY);
+    const double v2 = wave_min(ok ? q.y : INFINITY), v3 = wave_max(ok ? q.y : -INFINITY);
+    if (lane == 0) { wred[wv][0] = v0; wred[wv][1] = v1; wred[wv][2] = v2; wred[wv][3] = v3; }
+  }
+  __syncthreads();
+  const double x0 = fmin(fmin(wred[0][0], wred[1][0]), fmin(wred[2][0], wred[3][0]));
+  const double x1 = fmax(fmax(wred[0][1], wred[1][1]), fmax(wred[2][1], wred[3][1]));
+  const double y0 = fmin(fmin(wred[0][2], wred[1][2]), fmin(wred[2][2], wred[3][2]));
+  const double y1 = fmax(fmax(wred[0][3], wred[1][3]), fmax(wred[2][3], wred[3][3]));
+  const double cx = 0.5 * (x0 + x1), cy = 0.5 * (y0 + y1);
+  const double ex = q.x - cx, ey = q.y - cy;
+  const double d2 = wave_max(ok ? ex * ex + ey * ey : 0.0);
+  __syncthreads();
+  if (lane == 0) wred[wv][0] = d2;
+  __syncthreads();
+  // R > 0 even for a cluster of one point (its s_j are then 0 and only the
+  // p = 0 terms remain)
+  const double R = fmax(sqrt(fmax(fmax(wred[0][0], wred[1][0]), fmax(wred[2][0], wred[3][0]))), 1e-300);
+  {
+    constexpr double kInv4Pi = 0.25 * kInvPi;
+    const double2 a = ok ? make_double2(q.w * kInv4Pi * (q.nx * tx - q.ny * ty), q.w * kInv4Pi * (q.nx * ty + q.ny * tx))
+                         : make_double2(0.0, 0.0);
+    const double2 s = ok ? make_double2(ex / R, ey / R) : make_double2(0.0, 0.0);
+    sa[tid] = a;
+    ss[tid] = s;
+    sas[tid] = cmul2(a, make_double2(s.x, -s.y));
+    sb[tid] = ok ? q.w * (2.0 * kInv4Pi) * (q.nx * tx + q.ny * ty) : 0.0;
+  }
+  __syncthreads();
+  // thread (pg, g): powers p = 4 pg .. 4 pg + 3 of the sources g, g + RC_SG,
+  // ... (one binary powering per source, then three products), partial
+  // sums of G_p and E_p for its four p
+  if (tid < RC_PG * RC_SG) {
+    const int pg = tid / RC_SG, g = tid % RC_SG, p0 = 4 * pg;
+    double2 G[4], E[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) G[u] = E[u] = make_double2(0.0, 0.0);
+    for (int k = g; k < RC_CS; k += RC_SG) {
+      const double2 s = ss[k], a = sa[k], as = sas[k];
+      const double bj = sb[k];
+      // prev = s^(p0 - 1) (1 for p0 = 0, where it is multiplied by p = 0)
+      double2 prev = make_double2(1.0, 0.0), base = s;
+      for (int m = p0 > 0 ? p0 - 1 : 0; m; m >>= 1) {
+        if (m & 1) prev = cmul2(prev, base);
+        base = cmul2(base, base);
+      }
+      double2 cur = p0 > 0 ? cmul2(prev, s) : make_double2(1.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double pp = (double)(p0 + u);
+        G[u].x = fma(a.x, cur.x, fma(-a.y, cur.y, G[u].x));
+        G[u].y = fma(a.x, cur.y, fma(a.y, cur.x, G[u].y));
+        const double2 t = cmul2(as, prev);
+        E[u].x = fma(bj, cur.x, fma(-pp, t.x, E[u].x));
+        E[u].y = fma(bj, cur.y, fma(-pp, t.y, E[u].y));
+        prev = cur;
+        cur = cmul2(cur, s);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      gpart[g][p0 + u] = G[u];
+      epart[g][p0 + u] = E[u];
+    }
+  }
+  __syncthreads();
+  double* r = rec + ((int64_t)c * nb + b) * RC_REC;
+  if (tid < RC_NP) {
+    const int p = tid;
+    double2 G = gpart[0][p], E = epart[0][p];
+    for (int g = 1; g < RC_SG; ++g) {
+      G.x += gpart[g][p].x;
+      G.y += gpart[g][p].y;
+      E.x += epart[g][p].x;
+      E.y += epart[g][p].y;
+    }
+    double* o = r + 4 + 6 * p;
+    o[0] = G.x;
+    o[1] = G.y;
+    o[2] = (p + 1) * G.x;
+    o[3] = (p + 1) * G.y;
+    o[4] = E.x;
+    o[5] = E.y;
+  } else if (tid == 64) {
+    r[0] = cx;
+    r[1] = cy;
+    r[2] = R;
+    r[3] = 0.0;
+  }
+}
+
+// grid (ceil(n / (4 RC_TG)), nrhs, nnear + nfar), 256 threads: wave w of
+// block x takes the target group 4 x + w, RC_TG = 128 consecutive nodes, two
+// per lane (64 apart), so that every source record or coefficient the wave
+// loads serves two targets.  Half a cluster summed pair by pair (a "near"
+// unit) costs about as much as eight clusters taken by expansion ("far"
+// units), so the work of a group is cut into items of similar cost: item
+// z < nnear takes the near units of rank z, z + nnear, ... among the group's
+// near ones, item nnear + z' the far units of rank z', z' + nfar, ... (with
+// nnear = 0 the single item takes every unit).  The near / far test runs for
+// 64 clusters at once (one per lane) and its ballot is walked bit by bit.
+// Each item writes the double-layer sum of its units (the pair i = j
+// contributes 0) to part[((z nrhs + c) n + i) 2 + {0, 1}], as
+// resid_scalar_kernel does.
+constexpr int RC_TG = 128;   // targets per group (a wave)
+__global__ __launch_bounds__(256) void resid_far_eval_kernel(const NodeRec* __restrict__ nd, int64_t n,
+                                                             const double* __restrict__ pk,
+                                                             const double* __restrict__ rec, int ncl, int nnear,
+                                                             int nfar, double* __restrict__ part) {
+  const int c = blockIdx.y, nrhs = gridDim.y, z = blockIdx.z;
+  const int lane = threadIdx.x & 63;
+  const int64_t g0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * RC_TG;
+  if (g0 >= n) return;   // the whole wave
+  double xi[2], yi[2], ax[2] = {0.0, 0.0}, ay[2] = {0.0, 0.0};
+  bool ok[2];
+  double bx0 = INFINITY, bx1 = -INFINITY, by0 = INFINITY, by1 = -INFINITY;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int64_t i = g0 + lane + 64 * u;
+    ok[u] = i < n;
+    xi[u] = ok[u] ? nd[i].x : 0.0;
+    yi[u] = ok[u] ? nd[i].y : 0.0;
+    if (ok[u]) {
+      bx0 = fmin(bx0, xi[u]);
+      bx1 = fmax(bx1, xi[u]);
+      by0 = fmin(by0, yi[u]);
+      by1 = fmax(by1, yi[u]);
+    }
+  }
+  // the group's circle (centre of its bounding box)
+  const double tcx = uniform_d(0.5 * (wave_min(bx0) + wave_max(bx1)));
+  const double tcy = uniform_d(0.5 * (wave_min(by0) + wave_max(by1)));
+  double e2 = 0.0;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+    if (ok[u]) e2 = fmax(e2, (xi[u] - tcx) * (xi[u] - tcx) + (yi[u] - tcy) * (yi[u] - tcy));
+  const double rt = uniform_d(sqrt(wave_max(e2)));
+  constexpr double kR2Floor = 1e-60;   // as resid_scalar_kernel: keeps the pair i = j finite (and zero)
+  auto r2f = [](double rx, double ry) { return fma(rx, rx, fma(ry, ry, kR2Floor)); };
+  auto term = [&](int u, const double* q, double rx, double ry, double inv) {
+    const double cf = (rx * q[2] + ry * q[3]) * inv * inv;
+    const double d = cf * (rx * q[4] + ry * q[5]);
+    ax[u] += d * rx;
+    ay[u] += d * ry;
+  };
+  const double* pkc = pk + (int64_t)c * n * RPK;
+  // kind of work this item takes (0 near, 1 far, 2 both), its slot among
+  // the items of that kind and their count
+  const int kind = nnear == 0 ? 2 : (z < nnear ? 0 : 1);
+  const int slot = kind == 0 ? z : (nnear == 0 ? z : z - nnear);
+  const int nslot = kind == 0 ? nnear : nfar;
+  int rank = 0;           // units of this item's kind met so far (a near cluster is two units of RC_CS / 2 sources)
+  int next = kind == 2 ? 0 : slot;   // rank of the next unit this item takes
+  const int step_r = kind == 2 ? 1 : nslot;
+  for (int base = 0; base < ncl; base += 64) {
+    // near / far test of 64 clusters at once, lane l taking cluster base + l
+    const int sl = base + lane;
+    double gx = 0.0, gy = 0.0, gr = 0.0;
+    bool far_l = false;
+    if (sl < ncl) {
+      const double* cr = rec + ((int64_t)c * ncl + sl) * RC_REC;
+      gx = cr[0];
+      gy = cr[1];
+      gr = cr[2];
+      const double dx = tcx - gx, dy = tcy - gy, lim = RC_RATIO * gr + rt;
+      far_l = dx * dx + dy * dy >= lim * lim;
+    }
+    const uint64_t fm = __ballot(sl < ncl && far_l);
+    const uint64_t vm = __ballot(sl < ncl);
+    uint64_t m = kind == 0 ? (vm & ~fm) : (kind == 1 ? fm : vm);
+    while (m) {
+      const int b = __builtin_ctzll(m);
+      m &= m - 1;
+      const int s = base + b;
+      const bool far = (fm >> b) & 1;
+      // the units of this cluster that are this item's (near halves 0 / 1)
+      int h0 = -1, h1 = -1;
+      if (rank == next) { h0 = 0; next += step_r; }
+      ++rank;
+      if (!far) {
+        if (rank == next) { (h0 < 0 ? h0 : h1) = 1; next += step_r; }
+        ++rank;
+      }
+      if (h0 < 0) continue;
+      const double cx = __shfl(gx, b), cy = __shfl(gy, b), R = __shfl(gr, b);
+      const double* cr = rec + ((int64_t)c * ncl + s) * RC_REC;
+      if (far) {
+        // rho = R / (|c_t - c_s| - R_t) >= |W| at every target of the group;
+        // the terms after p = P sum to at most (P + 2) rho^(P + 1) / (1 - rho)^2
+        // of the cluster's scale, and P is the smallest that keeps this below
+        // 1e-17 (P + 2 <= 42 in the bound; one term more for the float logs)
+        const double dx = tcx - cx, dy = tcy - cy;
+        const double rho = R / (sqrt(dx * dx + dy * dy) - rt);
+        const float l2r = __log2f((float)rho), l2q = __log2f((float)(1.0 - rho));
+        const float pf = (-56.5f + 2.0f * l2q - 5.4f) / l2r;   // log2(1e-17) = -56.47
+        const int pe = pf >= (float)RC_P ? RC_P : (pf > 0.0f ? (int)pf + 1 : 1);
+        const int P = __builtin_amdgcn_readfirstlane(pe < RC_P ? pe : RC_P);
+        double2 Zt[2], iz[2], W[2], G[2], F[2], E[2];
+        const double* co = cr + 4 + 6 * P;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          Zt[u] = make_double2(xi[u] - cx, yi[u] - cy);
+          const double in2 = 1.0 / fma(Zt[u].x, Zt[u].x, Zt[u].y * Zt[u].y);
+          iz[u] = make_double2(Zt[u].x * in2, -Zt[u].y * in2);
+          W[u] = make_double2(R * iz[u].x, R * iz[u].y);
+          G[u] = make_double2(co[0], co[1]);
+          F[u] = make_double2(co[2], co[3]);
+          E[u] = make_double2(co[4], co[5]);
+        }
+        auto step = [&](const double* cp) {
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const double2 w = W[u];
+            G[u] = make_double2(fma(G[u].x, w.x, fma(-G[u].y, w.y, cp[0])), fma(G[u].x, w.y, fma(G[u].y, w.x, cp[1])));
+            F[u] = make_double2(fma(F[u].x, w.x, fma(-F[u].y, w.y, cp[2])), fma(F[u].x, w.y, fma(F[u].y, w.x, cp[3])));
+            E[u] = make_double2(fma(E[u].x, w.x, fma(-E[u].y, w.y, cp[4])), fma(E[u].x, w.y, fma(E[u].y, w.x, cp[5])));
+          }
+        };
+        int p = P - 1;
+        for (; p >= 3; p -= 4) {
+          const double* cp = cr + 4 + 6 * p;
+          step(cp);
+          step(cp - 6);
+          step(cp - 12);
+          step(cp - 18);
+        }
+        for (; p >= 0; --p) step(cr + 4 + 6 * p);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const double2 u1 = cmul2(iz[u], G[u]);
+          const double2 u2 = cmul2(iz[u], E[u]);
+          const double2 f2 = cmul2(cmul2(iz[u], iz[u]), F[u]);
+          // Z conj(f2)
+          const double2 u3 = make_double2(Zt[u].x * f2.x + Zt[u].y * f2.y, Zt[u].y * f2.x - Zt[u].x * f2.y);
+          ax[u] += u1.x + u2.x + u3.x;
+          ay[u] += u1.y - u2.y + u3.y;
+        }
+      } else {
+        // sources of the near units taken: half h0 (and h1) of the cluster
+        const int64_t c0 = (int64_t)s * RC_CS;
+        const int64_t j0 = min(n, c0 + (int64_t)h0 * (RC_CS / 2));
+        const int64_t j1 = min(n, c0 + (int64_t)((h1 >= 0 ? h1 : h0) + 1) * (RC_CS / 2));
+        int64_t sj = j0;
+        for (; sj + 4 <= j1; sj += 4) {
+          const double* q0 = pkc + sj * RPK;
+          const double* q1 = q0 + RPK;
+          const double* q2 = q1 + RPK;
+          const double* q3 = q2 + RPK;
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const double rx0 = xi[u] - q0[0], ry0 = yi[u] - q0[1], rx1 = xi[u] - q1[0], ry1 = yi[u] - q1[1];
+            const double rx2 = xi[u] - q2[0], ry2 = yi[u] - q2[1], rx3 = xi[u] - q3[0], ry3 = yi[u] - q3[1];
+            const double a = r2f(rx0, ry0), bb = r2f(rx1, ry1), cc = r2f(rx2, ry2), d = r2f(rx3, ry3);
+            const double ab = a * bb, cd = cc * d;
+            const double y = rcp_nr3(ab * cd);
+            const double yab = y * cd, ycd = y * ab;
+            term(u, q0, rx0, ry0, bb * yab);
+            term(u, q1, rx1, ry1, a * yab);
+            term(u, q2, rx2, ry2, d * ycd);
+            term(u, q3, rx3, ry3, cc * ycd);
+          }
+        }
+        for (; sj < j1; ++sj) {
+          const double* q = pkc + sj * RPK;
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const double rx = xi[u] - q[0], ry = yi[u] - q[1];
+            term(u, q, rx, ry, rcp_nr3(r2f(rx, ry)));
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+    if (ok[u]) {
+      double* p = part + (((int64_t)z * nrhs + c) * n + g0 + lane + 64 * u) * 2;
+      p[0] = ax[u];
+      p[1] = ay[u];
+    }
+}
+
 // ---------------------------------------------------------------- RHS
 __global__ __launch_bounds__(256) void stokeslet_kernel(const NodeRec* __restrict__ nd, int64_t n,
                                                         const double* __restrict__ zf, int n_src,
@@ -629,23 +1004,78 @@ inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) /
 
 }  // namespace
 
-// workspace: split partials (nsplit x nrhs x 2n), flux partials (nrhs x nb),
-// norm partials (2 x nrhs x nb), packed sources (RPK x n, one right-hand side)
-size_t resid_part_doubles(int64_t n, int nrhs) {
+// Items per target group of the cluster-expansion residual: about 6000 waves
+// in all, at most 24 (a little over half of them near); with one item, near
+// and far clusters in the same one.
+static void far_items(int64_t n, int nrhs, int* nnear, int* nfar) {
+  const int64_t waves = ((n + RC_TG - 1) / RC_TG) * nrhs;
+  int64_t it = (6000 + waves - 1) / waves;
+  it = it < 1 ? 1 : (it > 24 ? 24 : it);
+  if (it == 1) {
+    *nnear = 0;
+    *nfar = 1;
+  } else {
+    const int64_t nn = (it * 11 + 19) / 20;   // 55 % near, rounded up, and at least one far item
+    *nnear = (int)(nn < it ? nn : it - 1);
+    *nfar = (int)it - *nnear;
+  }
+}
+static int far_splits(int64_t n, int nrhs) {
+  int a, b;
+  far_items(n, nrhs, &a, &b);
+  return a + b;
+}
+
+bool resid_far_on(int mode, int64_t n) { return mode == RW_RESID_EXPAND || (mode == RW_RESID_AUTO && n >= RC_MIN_N); }
+
+// workspace of one call: split partials (nsplit x nrhs x 2n), flux partials
+// (nrhs x nb), norm partials (2 x nrhs x nb), packed sources (RPK x n, one
+// right-hand side; RPK x n x nrhs with the cluster expansions) and, with
+// those, the cluster records (RC_REC x nb x nrhs); the larger of the two forms
+static size_t resid_call_doubles(int64_t n, int nrhs) {
   const int64_t nb = blocks(n);
-  return (size_t)resid_splits(n, nrhs) * nrhs * 2 * n + (size_t)(3 * nb * nrhs) + (nrhs == 1 ? (size_t)RPK * n : 0);
+  const size_t pairs =
+      (size_t)resid_splits(n, nrhs) * nrhs * 2 * n + (size_t)(3 * nb * nrhs) + (nrhs == 1 ? (size_t)RPK * n : 0);
+  const size_t far = (size_t)far_splits(n, nrhs) * nrhs * 2 * n + (size_t)(3 * nb * nrhs) +
+                     (size_t)RPK * n * nrhs + (size_t)RC_REC * nb * nrhs;
+  return pairs > far ? pairs : far;
+}
+
+// The split counts shrink as columns are added, so one call's workspace is
+// not monotone in nrhs (the one-column kernel takes up to 64 splits, four
+// columns 13 at 20224 nodes): the largest over 1..nrhs columns, so that a
+// workspace sized for nrhs serves every smaller count.
+size_t resid_part_doubles(int64_t n, int nrhs) {
+  if (n <= 0 || nrhs <= 0) return 0;
+  size_t m = 0;
+  for (int c = 1; c <= nrhs; ++c) {
+    const size_t v = resid_call_doubles(n, c);
+    if (v > m) m = v;
+  }
+  return m;
 }
 
 void launch_residual(const NodeRec* nodes, int64_t n, const double* g, const double* tau, double* r, int nrhs,
-                     double* part, double* norms, hipStream_t s) {
+                     double* part, double* norms, hipStream_t s, int mode) {
   if (n <= 0 || nrhs <= 0) return;
-  const int ns = resid_splits(n, nrhs);
+  const bool far = resid_far_on(mode, n);
+  const int ns = far ? far_splits(n, nrhs) : resid_splits(n, nrhs);
   const int nb = (int)blocks(n);
   double* fpart = part + (size_t)ns * nrhs * 2 * n;
   double* npart = fpart + (size_t)nb * nrhs;
-  // algorithmic work: 12 flops per 2x2 block (r, r^2, r.n, 1/r^2 scaling) + 6 per
-  // block and right-hand side; the division counts as one flop
-  {
+  if (far) {
+    double* pk = npart + (size_t)2 * nb * nrhs;
+    double* rec = pk + (size_t)RPK * n * nrhs;
+    KernelTimer kt("resid_far_eval_kernel", 0.0, 0.0, s);
+    hipLaunchKernelGGL(resid_clusters_kernel, dim3(nb, nrhs), dim3(256), 0, s, nodes, n, tau, pk, fpart, rec);
+    int nnear, nfar;
+    far_items(n, nrhs, &nnear, &nfar);
+    hipLaunchKernelGGL(resid_far_eval_kernel, dim3(blocks(n, 4 * RC_TG), nrhs, ns), dim3(256), 0, s, nodes, n, pk, rec,
+                       nb, nnear, nfar, part);
+    KERNEL_CHECK("resid_far_eval");
+  } else {
+    // algorithmic work: 12 flops per 2x2 block (r, r^2, r.n, 1/r^2 scaling) + 6 per
+    // block and right-hand side; the division counts as one flop
     KernelTimer kt("resid_tiles_kernel", (double)n * n * (12.0 + 6.0 * nrhs), 0.0, s);
     if (nrhs == 1) {
       double* pk = npart + (size_t)2 * nb * nrhs;

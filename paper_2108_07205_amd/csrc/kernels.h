@@ -68,11 +68,16 @@ void launch_parts_reduce(const double* in, int64_t stride, int np, int64_t n, do
 
 // ----------------------------------------------------------- Stokes tiles
 // r = g - A tau on one node set (exact Nystrom operator, tiles on the fly).
-// part: workspace of resid_part_doubles(n, nrhs) doubles.  norms (optional,
+// part: workspace of resid_part_doubles(n, nrhs) doubles (non-decreasing in
+// nrhs: a workspace sized for nrhs columns serves any smaller count).  norms (optional,
 // 2 nrhs doubles): |r_c|^2 in norms[c], |g_c|^2 in norms[nrhs + c].
+// mode (an rw_resid value): every pair of nodes summed directly, or node
+// clusters far from a wave of targets through their multipole expansions
+// (resid_far_on tells which one a call takes).
 size_t resid_part_doubles(int64_t n, int nrhs);
+bool resid_far_on(int mode, int64_t n);
 void launch_residual(const NodeRec* nodes, int64_t n, const double* g, const double* tau, double* r,
-                     int nrhs, double* part, double* norms, hipStream_t s);
+                     int nrhs, double* part, double* norms, hipStream_t s, int mode);
 // g = sum_m S(x_i, z_m) f_m at all nodes (z, f device arrays, n_src x 2 row-major)
 void launch_stokeslet_rhs(const NodeRec* nodes, int64_t n, const double* zf, int n_src, double* g,
                           hipStream_t s);

@@ -1167,7 +1167,7 @@ int gmres_column(rw_refined* f, const double* g, double* tau, double tol, int ma
   double* hb = (double*)ctx_readback(ctx, sizeof(double) * (2 * (m + 1) + 8));
   auto matvec = [&](const double* z, double* out) {   // out = A z
     PhaseTimer t(ctx, "a8_residual", 26.0 * (double)f->Nn * f->Nn, 0.0);
-    launch_residual(f->d_new.p, f->Nn, f->gzero.p, z, out, 1, f->part.p, nullptr, s);
+    launch_residual(f->d_new.p, f->Nn, f->gzero.p, z, out, 1, f->part.p, nullptr, s, ctx->opt.resid_mode);
     launch_scale_copy(out, N, -1.0, out, s);
   };
   auto dot_to = [&](const double* a, const double* b, double* dst) {
@@ -1255,7 +1255,7 @@ int gmres_column(rw_refined* f, const double* g, double* tau, double tol, int ma
     // true residual r = g - A tau, its norm; restart from it if needed
     {
       PhaseTimer t(ctx, "a8_residual", 26.0 * (double)f->Nn * f->Nn, 0.0);
-      launch_residual(f->d_new.p, f->Nn, g, tau, w, 1, f->part.p, nullptr, s);
+      launch_residual(f->d_new.p, f->Nn, g, tau, w, 1, f->part.p, nullptr, s, ctx->opt.resid_mode);
     }
     dot_to(w, w, nrm + 2);
     HIP_CHECK(hipMemcpyAsync(hb, nrm + 2, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1313,6 +1313,7 @@ int rw_ctx_create(rw_ctx** out, int device, void* hip_stream, size_t hbm_budget_
   c->opt.far_field = 1;
   c->opt.test_singular = 0;
   c->opt.one_stream = 0;
+  c->opt.resid_mode = RW_RESID_AUTO;
   c->opt.hbs_merge = 2;
   c->opt.solver = RW_SOLVE_IR;
   c->opt.gmres_restart = 30;
@@ -1367,6 +1368,7 @@ int rw_set_options(rw_ctx* ctx, const rw_options* opt) {
     if (opt->gmres_restart < 1 || opt->gmres_restart > 256) RW_THROW(RW_EINVAL, "gmres_restart outside 1..256");
     if (opt->mfma_from < 0) RW_THROW(RW_EINVAL, "mfma_from < 0");
     if (opt->one_stream != 0 && opt->one_stream != 1) RW_THROW(RW_EINVAL, "one_stream must be 0 or 1");
+    if (opt->resid_mode < RW_RESID_AUTO || opt->resid_mode > RW_RESID_EXPAND) RW_THROW(RW_EINVAL, "unknown resid_mode");
     if (opt->sketch_cols != 32 && opt->sketch_cols != 64 && opt->sketch_cols != 96 && opt->sketch_cols != 128)
       RW_THROW(RW_EINVAL, "sketch_cols must be 32, 64, 96 or 128");
     ctx->opt = *opt;
@@ -1628,7 +1630,7 @@ int rw_solve(rw_refined* f, const double* g, int32_t nrhs, double* tau, rw_solve
     double* hn0 = hn + 2 * nrhs;
     auto residual = [&]() {
       PhaseTimer t(f->ctx, "a8_residual", 26.0 * (double)f->Nn * f->Nn * nrhs, 0.0);
-      launch_residual(f->d_new.p, f->Nn, g, tau, f->r.p, nrhs, f->part.p, f->norms.p, s);
+      launch_residual(f->d_new.p, f->Nn, g, tau, f->r.p, nrhs, f->part.p, f->norms.p, s, f->ctx->opt.resid_mode);
     };
     auto correct = [&]() {
       woodbury_apply(f, f->r.p, tau, nrhs, true);
@@ -1739,7 +1741,7 @@ void batch_sweep(rw_wall* w, const std::vector<rw_refined*>& fs, const std::vect
     woodbury_out(f, dst[i], nr[i], accumulate, false, si);
     {
       PhaseTimer t(ctx, "a8_residual", 26.0 * (double)f->Nn * f->Nn * nr[i], 0.0, si);
-      launch_residual(f->d_new.p, f->Nn, g[i], dst[i], f->r.p, nr[i], f->part.p, f->norms.p, si);
+      launch_residual(f->d_new.p, f->Nn, g[i], dst[i], f->r.p, nr[i], f->part.p, f->norms.p, si, ctx->opt.resid_mode);
     }
     HIP_CHECK(hipMemcpyAsync(nrm + n0, f->norms.p, sizeof(double) * 2 * nr[i], hipMemcpyDeviceToHost, si));
     n0 += 2 * nr[i];
@@ -1833,7 +1835,7 @@ int rw_residual(rw_refined* f, const double* g, const double* tau, int32_t nrhs,
     if (nrhs <= 0 || !g || !tau || !r) RW_THROW(RW_EINVAL, "bad arguments");
     refined_settle(f);
     refined_ensure_ws(f, nrhs);
-    launch_residual(f->d_new.p, f->Nn, g, tau, r, nrhs, f->part.p, nullptr, f->ctx->stream);
+    launch_residual(f->d_new.p, f->Nn, g, tau, r, nrhs, f->part.p, nullptr, f->ctx->stream, f->ctx->opt.resid_mode);
   });
 }
 
