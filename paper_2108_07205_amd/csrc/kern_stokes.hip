@@ -399,42 +399,55 @@ __device__ __forceinline__ double uniform_d(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// grid (ceil(n / RC_CS), nrhs), 256 threads.  Block b, column c: packs the
-// sources of cluster b (the RPK format of resid_scalar_kernel, at
-// pk + (c n + j) RPK), writes the flux partial of its nodes to
-// fpart[c nb + b] and the cluster's record to rec + (c nb + b) RC_REC.
+// grid (ceil(n / RC_CS), nrhs, RC_CZ), 256 threads.  Block (b, c, z): the
+// coefficients of cluster b, column c for the powers of slice z (groups of
+// four powers z RC_PGZ .. z RC_PGZ + RC_PGZ - 1); slice 0 also packs the
+// sources (the RPK format of resid_scalar_kernel, at pk + (c n + j) RPK),
+// writes the flux partial of its nodes to fpart[c nb + b] and the record's
+// centre and radius, also to the compact geo + (c nb + b) 4 (c_x, c_y, R, 0)
+// that the evaluation scans.  Record: rec + (c nb + b) RC_REC.
+constexpr int RC_CZ = 4;                             // power slices per cluster
+constexpr int RC_PGZ = (RC_PG + RC_CZ - 1) / RC_CZ;  // groups of four powers per slice
+constexpr int RC_SGZ = 256 / RC_PGZ;                 // source groups per slice
 __global__ __launch_bounds__(256) void resid_clusters_kernel(const NodeRec* __restrict__ nd, int64_t n,
                                                              const double* __restrict__ tau, double* __restrict__ pk,
-                                                             double* __restrict__ fpart, double* __restrict__ rec) {
+                                                             double* __restrict__ fpart, double* __restrict__ rec,
+                                                             double* __restrict__ geo) {
   __shared__ double red4[4];
   __shared__ double wred[4][4];
   __shared__ double2 sa[RC_CS], sas[RC_CS], ss[RC_CS];   // a_j, a_j conj(s_j), s_j
   __shared__ double sb[RC_CS];                           // b_j
-  __shared__ double2 gpart[RC_SG][4 * RC_PG], epart[RC_SG][4 * RC_PG];
+  __shared__ double2 gpart[RC_SGZ][4 * RC_PGZ], epart[RC_SGZ][4 * RC_PGZ];
+  __shared__ double2 gred[4 * RC_PGZ][16], ered[4 * RC_PGZ][16];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int b = blockIdx.x, c = blockIdx.y, nb = gridDim.x;
+  const int b = blockIdx.x, c = blockIdx.y, nb = gridDim.x, z = blockIdx.z;
   const int64_t j = (int64_t)b * RC_CS + tid;
   const bool ok = j < n;
   const double* tc = tau + (int64_t)c * 2 * n;
   NodeRec q{};
-  double tx = 0.0, ty = 0.0, fl = 0.0;
+  double tx = 0.0, ty = 0.0;
   if (ok) {
     q = nd[j];
     tx = tc[2 * j];
     ty = tc[2 * j + 1];
-    double* o = pk + ((int64_t)c * n + j) * RPK;
-    o[0] = q.x;
-    o[1] = q.y;
-    o[2] = q.nx * q.w * kInvPi;
-    o[3] = q.ny * q.w * kInvPi;
-    o[4] = tx;
-    o[5] = ty;
-    o[6] = 0.0;
-    o[7] = 0.0;
-    fl = flux_term(q, tc, j);
   }
-  const double fsum = block_sum256(fl, red4);
-  if (tid == 0) fpart[(int64_t)c * nb + b] = fsum;
+  if (z == 0) {   // uniform
+    double fl = 0.0;
+    if (ok) {
+      double* o = pk + ((int64_t)c * n + j) * RPK;
+      o[0] = q.x;
+      o[1] = q.y;
+      o[2] = q.nx * q.w * kInvPi;
+      o[3] = q.ny * q.w * kInvPi;
+      o[4] = tx;
+      o[5] = ty;
+      o[6] = 0.0;
+      o[7] = 0.0;
+      fl = flux_term(q, tc, j);
+    }
+    const double fsum = block_sum256(fl, red4);
+    if (tid == 0) fpart[(int64_t)c * nb + b] = fsum;
+  }
   // bounding box of the cluster, its centre and radius
   {
     const double v0 = wave_min(ok ? q.x : INFINITY), v1 = wave_max(ok ? q.x : -INFINITY);
@@ -466,52 +479,71 @@ __global__ __launch_bounds__(256) void resid_clusters_kernel(const NodeRec* __re
     sb[tid] = ok ? q.w * (2.0 * kInv4Pi) * (q.nx * tx + q.ny * ty) : 0.0;
   }
   __syncthreads();
-  // thread (pg, g): powers p = 4 pg .. 4 pg + 3 of the sources g, g + RC_SG,
-  // ... (one binary powering per source, then three products), partial
-  // sums of G_p and E_p for its four p
-  if (tid < RC_PG * RC_SG) {
-    const int pg = tid / RC_SG, g = tid % RC_SG, p0 = 4 * pg;
+  // thread (pgl, g): powers p = 4 pg .. 4 pg + 3 (pg = z RC_PGZ + pgl) of the
+  // sources g, g + RC_SGZ, ... (one binary powering per source, then three
+  // products), partial sums of G_p and E_p for its four p
+  const int pg0 = z * RC_PGZ;
+  if (tid < RC_PGZ * RC_SGZ) {
+    const int pgl = tid / RC_SGZ, g = tid % RC_SGZ, p0 = 4 * (pg0 + pgl);
     double2 G[4], E[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) G[u] = E[u] = make_double2(0.0, 0.0);
-    for (int k = g; k < RC_CS; k += RC_SG) {
-      const double2 s = ss[k], a = sa[k], as = sas[k];
-      const double bj = sb[k];
-      // prev = s^(p0 - 1) (1 for p0 = 0, where it is multiplied by p = 0)
-      double2 prev = make_double2(1.0, 0.0), base = s;
-      for (int m = p0 > 0 ? p0 - 1 : 0; m; m >>= 1) {
-        if (m & 1) prev = cmul2(prev, base);
-        base = cmul2(base, base);
-      }
-      double2 cur = p0 > 0 ? cmul2(prev, s) : make_double2(1.0, 0.0);
+    if (p0 <= RC_P) {
+      for (int k = g; k < RC_CS; k += RC_SGZ) {
+        const double2 s = ss[k], a = sa[k], as = sas[k];
+        const double bj = sb[k];
+        // prev = s^(p0 - 1) (1 for p0 = 0, where it is multiplied by p = 0)
+        double2 prev = make_double2(1.0, 0.0), base = s;
+        for (int m = p0 > 0 ? p0 - 1 : 0; m; m >>= 1) {
+          if (m & 1) prev = cmul2(prev, base);
+          base = cmul2(base, base);
+        }
+        double2 cur = p0 > 0 ? cmul2(prev, s) : make_double2(1.0, 0.0);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double pp = (double)(p0 + u);
-        G[u].x = fma(a.x, cur.x, fma(-a.y, cur.y, G[u].x));
-        G[u].y = fma(a.x, cur.y, fma(a.y, cur.x, G[u].y));
-        const double2 t = cmul2(as, prev);
-        E[u].x = fma(bj, cur.x, fma(-pp, t.x, E[u].x));
-        E[u].y = fma(bj, cur.y, fma(-pp, t.y, E[u].y));
-        prev = cur;
-        cur = cmul2(cur, s);
+        for (int u = 0; u < 4; ++u) {
+          const double pp = (double)(p0 + u);
+          G[u].x = fma(a.x, cur.x, fma(-a.y, cur.y, G[u].x));
+          G[u].y = fma(a.x, cur.y, fma(a.y, cur.x, G[u].y));
+          const double2 t = cmul2(as, prev);
+          E[u].x = fma(bj, cur.x, fma(-pp, t.x, E[u].x));
+          E[u].y = fma(bj, cur.y, fma(-pp, t.y, E[u].y));
+          prev = cur;
+          cur = cmul2(cur, s);
+        }
       }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      gpart[g][p0 + u] = G[u];
-      epart[g][p0 + u] = E[u];
+      gpart[g][4 * pgl + u] = G[u];
+      epart[g][4 * pgl + u] = E[u];
     }
   }
   __syncthreads();
+  // fixed-order sums over the source groups: 16 partial sums per power, then
+  // their sum
+  constexpr int NPZ = 4 * RC_PGZ;
+  if (tid < NPZ * 16) {
+    const int pl = tid / 16, h = tid % 16;
+    double2 G = make_double2(0.0, 0.0), E = make_double2(0.0, 0.0);
+    for (int g = h; g < RC_SGZ; g += 16) {
+      G.x += gpart[g][pl].x;
+      G.y += gpart[g][pl].y;
+      E.x += epart[g][pl].x;
+      E.y += epart[g][pl].y;
+    }
+    gred[pl][h] = G;
+    ered[pl][h] = E;
+  }
+  __syncthreads();
   double* r = rec + ((int64_t)c * nb + b) * RC_REC;
-  if (tid < RC_NP) {
-    const int p = tid;
-    double2 G = gpart[0][p], E = epart[0][p];
-    for (int g = 1; g < RC_SG; ++g) {
-      G.x += gpart[g][p].x;
-      G.y += gpart[g][p].y;
-      E.x += epart[g][p].x;
-      E.y += epart[g][p].y;
+  const int p = 4 * pg0 + tid;
+  if (tid < NPZ && p <= RC_P) {
+    double2 G = gred[tid][0], E = ered[tid][0];
+    for (int h = 1; h < 16; ++h) {
+      G.x += gred[tid][h].x;
+      G.y += gred[tid][h].y;
+      E.x += ered[tid][h].x;
+      E.y += ered[tid][h].y;
     }
     double* o = r + 4 + 6 * p;
     o[0] = G.x;
@@ -520,11 +552,16 @@ __global__ __launch_bounds__(256) void resid_clusters_kernel(const NodeRec* __re
     o[3] = (p + 1) * G.y;
     o[4] = E.x;
     o[5] = E.y;
-  } else if (tid == 64) {
+  } else if (tid == 64 && z == 0) {
     r[0] = cx;
     r[1] = cy;
     r[2] = R;
     r[3] = 0.0;
+    double* gc = geo + ((int64_t)c * nb + b) * 4;
+    gc[0] = cx;
+    gc[1] = cy;
+    gc[2] = R;
+    gc[3] = 0.0;
   }
 }
 
@@ -544,7 +581,8 @@ __global__ __launch_bounds__(256) void resid_clusters_kernel(const NodeRec* __re
 constexpr int RC_TG = 128;   // targets per group (a wave)
 __global__ __launch_bounds__(256) void resid_far_eval_kernel(const NodeRec* __restrict__ nd, int64_t n,
                                                              const double* __restrict__ pk,
-                                                             const double* __restrict__ rec, int ncl, int nnear,
+                                                             const double* __restrict__ rec,
+                                                             const double* __restrict__ geo, int ncl, int nnear,
                                                              int nfar, double* __restrict__ part) {
   const int c = blockIdx.y, nrhs = gridDim.y, z = blockIdx.z;
   const int lane = threadIdx.x & 63;
@@ -583,6 +621,9 @@ __global__ __launch_bounds__(256) void resid_far_eval_kernel(const NodeRec* __re
     ay[u] += d * ry;
   };
   const double* pkc = pk + (int64_t)c * n * RPK;
+  // this wave's slice of the near-source staging: positions, n w / pi, tau
+  __shared__ double2 stage[4][3][128];
+  double2(*sp)[128] = stage[threadIdx.x >> 6];
   // kind of work this item takes (0 near, 1 far, 2 both), its slot among
   // the items of that kind and their count
   const int kind = nnear == 0 ? 2 : (z < nnear ? 0 : 1);
@@ -597,10 +638,10 @@ __global__ __launch_bounds__(256) void resid_far_eval_kernel(const NodeRec* __re
     double gx = 0.0, gy = 0.0, gr = 0.0;
     bool far_l = false;
     if (sl < ncl) {
-      const double* cr = rec + ((int64_t)c * ncl + sl) * RC_REC;
-      gx = cr[0];
-      gy = cr[1];
-      gr = cr[2];
+      const double* gc = geo + ((int64_t)c * ncl + sl) * 4;
+      gx = gc[0];
+      gy = gc[1];
+      gr = gc[2];
       const double dx = tcx - gx, dy = tcy - gy, lim = RC_RATIO * gr + rt;
       far_l = dx * dx + dy * dy >= lim * lim;
     }
@@ -675,36 +716,60 @@ __global__ __launch_bounds__(256) void resid_far_eval_kernel(const NodeRec* __re
           ay[u] += u1.y - u2.y + u3.y;
         }
       } else {
-        // sources of the near units taken: half h0 (and h1) of the cluster
+        // sources of the near units taken: half h0 (and h1) of the cluster,
+        // staged in this wave's LDS slice 128 at a time (coalesced loads),
+        // then read with the same address in every lane (broadcast)
         const int64_t c0 = (int64_t)s * RC_CS;
         const int64_t j0 = min(n, c0 + (int64_t)h0 * (RC_CS / 2));
         const int64_t j1 = min(n, c0 + (int64_t)((h1 >= 0 ? h1 : h0) + 1) * (RC_CS / 2));
-        int64_t sj = j0;
-        for (; sj + 4 <= j1; sj += 4) {
-          const double* q0 = pkc + sj * RPK;
-          const double* q1 = q0 + RPK;
-          const double* q2 = q1 + RPK;
-          const double* q3 = q2 + RPK;
+        for (int64_t b0 = j0; b0 < j1; b0 += 128) {
+          const int cnt = (int)min<int64_t>(128, j1 - b0);
+          __builtin_amdgcn_wave_barrier();   // the previous chunk's reads are issued
 #pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const double rx0 = xi[u] - q0[0], ry0 = yi[u] - q0[1], rx1 = xi[u] - q1[0], ry1 = yi[u] - q1[1];
-            const double rx2 = xi[u] - q2[0], ry2 = yi[u] - q2[1], rx3 = xi[u] - q3[0], ry3 = yi[u] - q3[1];
-            const double a = r2f(rx0, ry0), bb = r2f(rx1, ry1), cc = r2f(rx2, ry2), d = r2f(rx3, ry3);
-            const double ab = a * bb, cd = cc * d;
-            const double y = rcp_nr3(ab * cd);
-            const double yab = y * cd, ycd = y * ab;
-            term(u, q0, rx0, ry0, bb * yab);
-            term(u, q1, rx1, ry1, a * yab);
-            term(u, q2, rx2, ry2, d * ycd);
-            term(u, q3, rx3, ry3, cc * ycd);
+          for (int h = 0; h < 2; ++h) {
+            const int t = lane + 64 * h;
+            if (t < cnt) {
+              const double* q = pkc + (b0 + t) * RPK;
+              sp[0][t] = make_double2(q[0], q[1]);
+              sp[1][t] = make_double2(q[2], q[3]);
+              sp[2][t] = make_double2(q[4], q[5]);
+            }
           }
-        }
-        for (; sj < j1; ++sj) {
-          const double* q = pkc + sj * RPK;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          auto terml = [&](int u, double2 nw, double2 tv, double rx, double ry, double inv) {
+            const double cf = (rx * nw.x + ry * nw.y) * inv * inv;
+            const double d = cf * (rx * tv.x + ry * tv.y);
+            ax[u] += d * rx;
+            ay[u] += d * ry;
+          };
+          int t = 0;
+          for (; t + 4 <= cnt; t += 4) {
+            const double2 p0 = sp[0][t], p1 = sp[0][t + 1], p2 = sp[0][t + 2], p3 = sp[0][t + 3];
+            const double2 n0 = sp[1][t], n1 = sp[1][t + 1], n2 = sp[1][t + 2], n3 = sp[1][t + 3];
+            const double2 v0 = sp[2][t], v1 = sp[2][t + 1], v2 = sp[2][t + 2], v3 = sp[2][t + 3];
 #pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const double rx = xi[u] - q[0], ry = yi[u] - q[1];
-            term(u, q, rx, ry, rcp_nr3(r2f(rx, ry)));
+            for (int u = 0; u < 2; ++u) {
+              const double rx0 = xi[u] - p0.x, ry0 = yi[u] - p0.y, rx1 = xi[u] - p1.x, ry1 = yi[u] - p1.y;
+              const double rx2 = xi[u] - p2.x, ry2 = yi[u] - p2.y, rx3 = xi[u] - p3.x, ry3 = yi[u] - p3.y;
+              const double a = r2f(rx0, ry0), bb = r2f(rx1, ry1), cc = r2f(rx2, ry2), d = r2f(rx3, ry3);
+              const double ab = a * bb, cd = cc * d;
+              const double y = rcp_nr3(ab * cd);
+              const double yab = y * cd, ycd = y * ab;
+              terml(u, n0, v0, rx0, ry0, bb * yab);
+              terml(u, n1, v1, rx1, ry1, a * yab);
+              terml(u, n2, v2, rx2, ry2, d * ycd);
+              terml(u, n3, v3, rx3, ry3, cc * ycd);
+            }
+          }
+          for (; t < cnt; ++t) {
+            const double2 p0 = sp[0][t], n0 = sp[1][t], v0 = sp[2][t];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              const double rx = xi[u] - p0.x, ry = yi[u] - p0.y;
+              terml(u, n0, v0, rx, ry, rcp_nr3(r2f(rx, ry)));
+            }
           }
         }
       }
@@ -1005,12 +1070,12 @@ inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) /
 }  // namespace
 
 // Items per target group of the cluster-expansion residual: about 6000 waves
-// in all, at most 24 (a little over half of them near); with one item, near
+// in all, at most 32 (a little over half of them near); with one item, near
 // and far clusters in the same one.
 static void far_items(int64_t n, int nrhs, int* nnear, int* nfar) {
   const int64_t waves = ((n + RC_TG - 1) / RC_TG) * nrhs;
   int64_t it = (6000 + waves - 1) / waves;
-  it = it < 1 ? 1 : (it > 24 ? 24 : it);
+  it = it < 1 ? 1 : (it > 32 ? 32 : it);
   if (it == 1) {
     *nnear = 0;
     *nfar = 1;
@@ -1037,7 +1102,7 @@ static size_t resid_call_doubles(int64_t n, int nrhs) {
   const size_t pairs =
       (size_t)resid_splits(n, nrhs) * nrhs * 2 * n + (size_t)(3 * nb * nrhs) + (nrhs == 1 ? (size_t)RPK * n : 0);
   const size_t far = (size_t)far_splits(n, nrhs) * nrhs * 2 * n + (size_t)(3 * nb * nrhs) +
-                     (size_t)RPK * n * nrhs + (size_t)RC_REC * nb * nrhs;
+                     (size_t)RPK * n * nrhs + (size_t)(RC_REC + 4) * nb * nrhs;
   return pairs > far ? pairs : far;
 }
 
@@ -1066,12 +1131,14 @@ void launch_residual(const NodeRec* nodes, int64_t n, const double* g, const dou
   if (far) {
     double* pk = npart + (size_t)2 * nb * nrhs;
     double* rec = pk + (size_t)RPK * n * nrhs;
+    double* geo = rec + (size_t)RC_REC * nb * nrhs;
     KernelTimer kt("resid_far_eval_kernel", 0.0, 0.0, s);
-    hipLaunchKernelGGL(resid_clusters_kernel, dim3(nb, nrhs), dim3(256), 0, s, nodes, n, tau, pk, fpart, rec);
+    hipLaunchKernelGGL(resid_clusters_kernel, dim3(nb, nrhs, RC_CZ), dim3(256), 0, s, nodes, n, tau, pk, fpart, rec,
+                       geo);
     int nnear, nfar;
     far_items(n, nrhs, &nnear, &nfar);
     hipLaunchKernelGGL(resid_far_eval_kernel, dim3(blocks(n, 4 * RC_TG), nrhs, ns), dim3(256), 0, s, nodes, n, pk, rec,
-                       nb, nnear, nfar, part);
+                       geo, nb, nnear, nfar, part);
     KERNEL_CHECK("resid_far_eval");
   } else {
     // algorithmic work: 12 flops per 2x2 block (r, r^2, r.n, 1/r^2 scaling) + 6 per
