@@ -346,11 +346,11 @@ __global__ __launch_bounds__(64) void resid_norms_kernel(const double* __restric
 
 // ------------------------------------------- residual, far clusters by expansion
 // The sources are cut into clusters of RC_CS consecutive nodes (arcs of the
-// curve, since a discretization stores its panels in curve order).  A wave of
-// 64 consecutive targets, inside a circle of radius R_t about c_t, takes a
-// cluster (radius R_s about c_s) whose centre is at least RC_RATIO R_s + R_t
-// from c_t through the cluster's multipole expansion, every other cluster
-// pair by pair (as resid_scalar_kernel).  The expansion comes from the
+// curve, since a discretization stores its panels in curve order).  A group
+// of RC_TG consecutive targets (one wave), inside a circle of radius R_t
+// about c_t, takes a cluster (radius R_s about c_s) whose centre is at least
+// RC_RATIO R_s + R_t from c_t through the cluster's multipole expansion,
+// every other cluster pair by pair (as resid_scalar_kernel).  The expansion comes from the
 // complex form of the double layer D of Sec. 2 (source zeta with normal nu,
 // weight w, density mu; target z):
 //   D mu = (w / 4 pi) [ nu mu / r + 2 Re(conj(nu) mu) / conj(r)
@@ -361,17 +361,16 @@ __global__ __launch_bounds__(64) void resid_norms_kernel(const double* __restric
 //   E_q = sum_j b_j s_j^q - q a_j conj(s_j) s_j^(q - 1),
 //   a_j = w_j nu_j mu_j / (4 pi),   b_j = w_j Re(conj(nu_j) mu_j) / (2 pi),
 // the geometric series of 1 / (Z - t) and 1 / (Z - t)^2 in t / Z.  The far
-// test keeps |W| <= 1 / RC_RATIO = 1/3 at every target of the wave, where
-// the series cut after p = RC_P = 40 leaves less than 1e-17 of the
-// cluster's sum_j |a_j| / |Z| (the squared series, with its factor p + 1,
-// included).
+// test keeps |W| <= 1 / RC_RATIO = 1/3 at every target of the group; each
+// far cluster keeps the powers up to the smallest P (at most RC_P = 40) for
+// which the dropped terms stay below 1e-17 of the cluster's sum_j |a_j| /
+// |Z| (the squared series, with its factor p + 1, included).
 constexpr int RC_CS = 256;       // nodes per source cluster (one packing workgroup)
 constexpr int RC_P = 40;         // highest power kept
 constexpr int RC_NP = RC_P + 1;
 constexpr double RC_RATIO = 3.0;
 constexpr int RC_REC = 256;      // doubles per cluster record: c_x, c_y, R, 0, then (G_p, F_p, E_p), p = 0..RC_P
 constexpr int RC_PG = (RC_NP + 3) / 4;   // groups of four powers in the coefficient sums
-constexpr int RC_SG = 256 / RC_PG;        // source groups in the coefficient sums
 constexpr int64_t RC_MIN_N = 4096;   // RW_RESID_AUTO: expansions from this many nodes
 static_assert(4 + 6 * RC_NP <= RC_REC, "cluster record too small");
 
