@@ -328,10 +328,12 @@ int rw_solve(rw_refined* ref, const double* g_dev, int32_t nrhs, double* tau_dev
 int rw_solve_batch(rw_refined* const* inst, int32_t n_inst, const double* const* g_dev,
                    const int32_t* nrhs, double* const* tau_dev, rw_info* info_host);
 
-/* r = g - A_nn tau on the refined discretization (exact Nystrom operator,
- * entries generated on the fly).  Shapes as rw_solve.  Enqueued on the ctx's
- * stream (not synchronized).  Errors: RW_EINVAL, RW_ENOMEM, RW_ESINGULAR
- * (the refinement's deferred checks failed), RW_EDEVICE. */
+/* r = g - A_nn tau on the refined discretization (the Nystrom operator of
+ * Sec. 2 in FP64, entries generated on the fly; far node clusters through
+ * their multipole expansions as rw_options.resid_mode selects).  Shapes as
+ * rw_solve.  Enqueued on the ctx's stream (not synchronized).  Errors:
+ * RW_EINVAL, RW_ENOMEM, RW_ESINGULAR (the refinement's deferred checks
+ * failed), RW_EDEVICE. */
 int rw_residual(rw_refined* ref, const double* g_dev, const double* tau_dev,
                 int32_t nrhs, double* r_dev);
 
