@@ -398,26 +398,127 @@ __device__ __forceinline__ double uniform_d(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// grid (ceil(n / RC_CS), nrhs, RC_CZ), 256 threads.  Block (b, c, z): the
-// coefficients of cluster b, column c for the powers of slice z (groups of
-// four powers z RC_PGZ .. z RC_PGZ + RC_PGZ - 1); slice 0 also packs the
-// sources (the RPK format of resid_scalar_kernel, at pk + (c n + j) RPK),
-// writes the flux partial of its nodes to fpart[c nb + b] and the record's
-// centre and radius, also to the compact geo + (c nb + b) 4 (c_x, c_y, R, 0)
-// that the evaluation scans.  Record: rec + (c nb + b) RC_REC.
 constexpr int RC_CZ = 4;                             // power slices per cluster
 constexpr int RC_PGZ = (RC_PG + RC_CZ - 1) / RC_CZ;  // groups of four powers per slice
 constexpr int RC_SGZ = 256 / RC_PGZ;                 // source groups per slice
+constexpr int RC_NPZ = 4 * RC_PGZ;                   // powers per slice
+constexpr int RC_GEO = 8;    // doubles per compact cluster record: c_x, c_y, R, x0, x1, y0, y1, 0
+constexpr int RC_L2 = 8;     // first-level clusters per second-level cluster
+constexpr int64_t RC_L2_MIN_N = 32768;   // second-level clusters from this many nodes
+
+// Shared memory of the coefficient sums of one cluster slice.
+struct ClusterSums {
+  double2 sa[RC_CS], sas[RC_CS], ss[RC_CS];   // a_j, a_j conj(s_j), s_j
+  double sb[RC_CS];                           // b_j
+  double2 gpart[RC_SGZ][RC_NPZ], epart[RC_SGZ][RC_NPZ];
+  double2 gred[RC_NPZ][16], ered[RC_NPZ][16];
+};
+
+// Stage source tid's a_j, b_j and s_j (t_j = zeta_j - c, s_j = t_j / R)
+// from its packed record q (x, y, n_x w / pi, n_y w / pi, tau_x, tau_y):
+// a_j = w nu mu / (4 pi), b_j = w Re(conj(nu) mu) / (2 pi); q = nullptr
+// stages a zero source.
+__device__ __forceinline__ void cluster_stage(ClusterSums& S, const double* q, double cx, double cy, double R) {
+  const int tid = threadIdx.x;
+  double2 a = make_double2(0.0, 0.0), sv = make_double2(0.0, 0.0);
+  double bj = 0.0;
+  if (q) {
+    a = make_double2(0.25 * (q[2] * q[4] - q[3] * q[5]), 0.25 * (q[2] * q[5] + q[3] * q[4]));
+    bj = 0.5 * (q[2] * q[4] + q[3] * q[5]);
+    sv = make_double2((q[0] - cx) / R, (q[1] - cy) / R);
+  }
+  S.sa[tid] = a;
+  S.ss[tid] = sv;
+  S.sas[tid] = cmul2(a, make_double2(sv.x, -sv.y));
+  S.sb[tid] = bj;
+}
+
+// The sums G_p and E_p over the RC_CS staged sources for the powers of slice
+// z (p = 4 z RC_PGZ + tid for tid < RC_NPZ, valid while p <= RC_P), in a
+// fixed order.  Thread (pgl, g): powers p = 4 pg .. 4 pg + 3 (pg = z RC_PGZ +
+// pgl) of the sources g, g + RC_SGZ, ... (one binary powering per source,
+// then three products); then 16 partial sums per power and their sum.  Call
+// after the staging is visible to the block; every thread must call it.
+__device__ void cluster_power_sums(ClusterSums& S, int z, double2& Gout, double2& Eout) {
+  const int tid = threadIdx.x;
+  const int pg0 = z * RC_PGZ;
+  if (tid < RC_PGZ * RC_SGZ) {
+    const int pgl = tid / RC_SGZ, g = tid % RC_SGZ, p0 = 4 * (pg0 + pgl);
+    double2 G[4], E[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) G[u] = E[u] = make_double2(0.0, 0.0);
+    if (p0 <= RC_P) {
+      for (int k = g; k < RC_CS; k += RC_SGZ) {
+        const double2 sv = S.ss[k], a = S.sa[k], as = S.sas[k];
+        const double bj = S.sb[k];
+        // prev = s^(p0 - 1) (1 for p0 = 0, where it is multiplied by p = 0)
+        double2 prev = make_double2(1.0, 0.0), base = sv;
+        for (int m = p0 > 0 ? p0 - 1 : 0; m; m >>= 1) {
+          if (m & 1) prev = cmul2(prev, base);
+          base = cmul2(base, base);
+        }
+        double2 cur = p0 > 0 ? cmul2(prev, sv) : make_double2(1.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double pp = (double)(p0 + u);
+          G[u].x = fma(a.x, cur.x, fma(-a.y, cur.y, G[u].x));
+          G[u].y = fma(a.x, cur.y, fma(a.y, cur.x, G[u].y));
+          const double2 t = cmul2(as, prev);
+          E[u].x = fma(bj, cur.x, fma(-pp, t.x, E[u].x));
+          E[u].y = fma(bj, cur.y, fma(-pp, t.y, E[u].y));
+          prev = cur;
+          cur = cmul2(cur, sv);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      S.gpart[g][4 * pgl + u] = G[u];
+      S.epart[g][4 * pgl + u] = E[u];
+    }
+  }
+  __syncthreads();
+  if (tid < RC_NPZ * 16) {
+    const int pl = tid / 16, h = tid % 16;
+    double2 G = make_double2(0.0, 0.0), E = make_double2(0.0, 0.0);
+    for (int g = h; g < RC_SGZ; g += 16) {
+      G.x += S.gpart[g][pl].x;
+      G.y += S.gpart[g][pl].y;
+      E.x += S.epart[g][pl].x;
+      E.y += S.epart[g][pl].y;
+    }
+    S.gred[pl][h] = G;
+    S.ered[pl][h] = E;
+  }
+  __syncthreads();
+  Gout = Eout = make_double2(0.0, 0.0);
+  if (tid < RC_NPZ) {
+    double2 G = S.gred[tid][0], E = S.ered[tid][0];
+    for (int h = 1; h < 16; ++h) {
+      G.x += S.gred[tid][h].x;
+      G.y += S.gred[tid][h].y;
+      E.x += S.ered[tid][h].x;
+      E.y += S.ered[tid][h].y;
+    }
+    Gout = G;
+    Eout = E;
+  }
+}
+
+// grid (ceil(n / RC_CS), nrhs, RC_CZ), 256 threads.  Block (b, c, z): the
+// coefficients of cluster b, column c for the powers of slice z; slice 0
+// also packs the sources (the RPK format of resid_scalar_kernel, at
+// pk + (c n + j) RPK), writes the flux partial of its nodes to fpart[c nb + b]
+// and the record's centre and radius, also to the compact geo + (c nb + b)
+// RC_GEO (c_x, c_y, R and the bounding box) that the evaluation scans.
+// Record: rec + (c nb + b) RC_REC.
 __global__ __launch_bounds__(256) void resid_clusters_kernel(const NodeRec* __restrict__ nd, int64_t n,
                                                              const double* __restrict__ tau, double* __restrict__ pk,
                                                              double* __restrict__ fpart, double* __restrict__ rec,
                                                              double* __restrict__ geo) {
   __shared__ double red4[4];
   __shared__ double wred[4][4];
-  __shared__ double2 sa[RC_CS], sas[RC_CS], ss[RC_CS];   // a_j, a_j conj(s_j), s_j
-  __shared__ double sb[RC_CS];                           // b_j
-  __shared__ double2 gpart[RC_SGZ][4 * RC_PGZ], epart[RC_SGZ][4 * RC_PGZ];
-  __shared__ double2 gred[4 * RC_PGZ][16], ered[4 * RC_PGZ][16];
+  __shared__ ClusterSums S;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int b = blockIdx.x, c = blockIdx.y, nb = gridDim.x, z = blockIdx.z;
   const int64_t j = (int64_t)b * RC_CS + tid;
@@ -430,16 +531,13 @@ __global__ __launch_bounds__(256) void resid_clusters_kernel(const NodeRec* __re
     tx = tc[2 * j];
     ty = tc[2 * j + 1];
   }
+  const double qr[6] = {q.x, q.y, q.nx * q.w * kInvPi, q.ny * q.w * kInvPi, tx, ty};
   if (z == 0) {   // uniform
     double fl = 0.0;
     if (ok) {
       double* o = pk + ((int64_t)c * n + j) * RPK;
-      o[0] = q.x;
-      o[1] = q.y;
-      o[2] = q.nx * q.w * kInvPi;
-      o[3] = q.ny * q.w * kInvPi;
-      o[4] = tx;
-      o[5] = ty;
+#pragma unroll
+      for (int e = 0; e < 6; ++e) o[e] = qr[e];
       o[6] = 0.0;
       o[7] = 0.0;
       fl = flux_term(q, tc, j);
@@ -467,83 +565,13 @@ __global__ __launch_bounds__(256) void resid_clusters_kernel(const NodeRec* __re
   // R > 0 even for a cluster of one point (its s_j are then 0 and only the
   // p = 0 terms remain)
   const double R = fmax(sqrt(fmax(fmax(wred[0][0], wred[1][0]), fmax(wred[2][0], wred[3][0]))), 1e-300);
-  {
-    constexpr double kInv4Pi = 0.25 * kInvPi;
-    const double2 a = ok ? make_double2(q.w * kInv4Pi * (q.nx * tx - q.ny * ty), q.w * kInv4Pi * (q.nx * ty + q.ny * tx))
-                         : make_double2(0.0, 0.0);
-    const double2 s = ok ? make_double2(ex / R, ey / R) : make_double2(0.0, 0.0);
-    sa[tid] = a;
-    ss[tid] = s;
-    sas[tid] = cmul2(a, make_double2(s.x, -s.y));
-    sb[tid] = ok ? q.w * (2.0 * kInv4Pi) * (q.nx * tx + q.ny * ty) : 0.0;
-  }
+  cluster_stage(S, ok ? qr : nullptr, cx, cy, R);
   __syncthreads();
-  // thread (pgl, g): powers p = 4 pg .. 4 pg + 3 (pg = z RC_PGZ + pgl) of the
-  // sources g, g + RC_SGZ, ... (one binary powering per source, then three
-  // products), partial sums of G_p and E_p for its four p
-  const int pg0 = z * RC_PGZ;
-  if (tid < RC_PGZ * RC_SGZ) {
-    const int pgl = tid / RC_SGZ, g = tid % RC_SGZ, p0 = 4 * (pg0 + pgl);
-    double2 G[4], E[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) G[u] = E[u] = make_double2(0.0, 0.0);
-    if (p0 <= RC_P) {
-      for (int k = g; k < RC_CS; k += RC_SGZ) {
-        const double2 s = ss[k], a = sa[k], as = sas[k];
-        const double bj = sb[k];
-        // prev = s^(p0 - 1) (1 for p0 = 0, where it is multiplied by p = 0)
-        double2 prev = make_double2(1.0, 0.0), base = s;
-        for (int m = p0 > 0 ? p0 - 1 : 0; m; m >>= 1) {
-          if (m & 1) prev = cmul2(prev, base);
-          base = cmul2(base, base);
-        }
-        double2 cur = p0 > 0 ? cmul2(prev, s) : make_double2(1.0, 0.0);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const double pp = (double)(p0 + u);
-          G[u].x = fma(a.x, cur.x, fma(-a.y, cur.y, G[u].x));
-          G[u].y = fma(a.x, cur.y, fma(a.y, cur.x, G[u].y));
-          const double2 t = cmul2(as, prev);
-          E[u].x = fma(bj, cur.x, fma(-pp, t.x, E[u].x));
-          E[u].y = fma(bj, cur.y, fma(-pp, t.y, E[u].y));
-          prev = cur;
-          cur = cmul2(cur, s);
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      gpart[g][4 * pgl + u] = G[u];
-      epart[g][4 * pgl + u] = E[u];
-    }
-  }
-  __syncthreads();
-  // fixed-order sums over the source groups: 16 partial sums per power, then
-  // their sum
-  constexpr int NPZ = 4 * RC_PGZ;
-  if (tid < NPZ * 16) {
-    const int pl = tid / 16, h = tid % 16;
-    double2 G = make_double2(0.0, 0.0), E = make_double2(0.0, 0.0);
-    for (int g = h; g < RC_SGZ; g += 16) {
-      G.x += gpart[g][pl].x;
-      G.y += gpart[g][pl].y;
-      E.x += epart[g][pl].x;
-      E.y += epart[g][pl].y;
-    }
-    gred[pl][h] = G;
-    ered[pl][h] = E;
-  }
-  __syncthreads();
+  double2 G, E;
+  cluster_power_sums(S, z, G, E);
   double* r = rec + ((int64_t)c * nb + b) * RC_REC;
-  const int p = 4 * pg0 + tid;
-  if (tid < NPZ && p <= RC_P) {
-    double2 G = gred[tid][0], E = ered[tid][0];
-    for (int h = 1; h < 16; ++h) {
-      G.x += gred[tid][h].x;
-      G.y += gred[tid][h].y;
-      E.x += ered[tid][h].x;
-      E.y += ered[tid][h].y;
-    }
+  const int p = 4 * z * RC_PGZ + tid;
+  if (tid < RC_NPZ && p <= RC_P) {
     double* o = r + 4 + 6 * p;
     o[0] = G.x;
     o[1] = G.y;
@@ -556,11 +584,103 @@ __global__ __launch_bounds__(256) void resid_clusters_kernel(const NodeRec* __re
     r[1] = cy;
     r[2] = R;
     r[3] = 0.0;
-    double* gc = geo + ((int64_t)c * nb + b) * 4;
-    gc[0] = cx;
-    gc[1] = cy;
-    gc[2] = R;
-    gc[3] = 0.0;
+    double* gc = geo + ((int64_t)c * nb + b) * RC_GEO;
+    const double gv[RC_GEO] = {cx, cy, R, x0, x1, y0, y1, 0.0};
+#pragma unroll
+    for (int e = 0; e < RC_GEO; ++e) gc[e] = gv[e];
+  }
+}
+
+// Second-level cluster b2 (first-level clusters RC_L2 b2 .. RC_L2 b2 +
+// RC_L2 - 1): centre at the middle of the union of their bounding boxes, and
+// a radius that bounds every node's distance from it (the largest of
+// |c_1 - c_2| + R_1 over its clusters; at least the true radius, so the far
+// test and the truncation bound hold).
+__device__ __forceinline__ void l2_geometry(const double* geo1c, int nb1, int b2, double& cx, double& cy, double& R) {
+  double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+  const int e1 = min(nb1, RC_L2 * (b2 + 1));
+  for (int b1 = RC_L2 * b2; b1 < e1; ++b1) {
+    const double* g = geo1c + (int64_t)b1 * RC_GEO;
+    x0 = fmin(x0, g[3]);
+    x1 = fmax(x1, g[4]);
+    y0 = fmin(y0, g[5]);
+    y1 = fmax(y1, g[6]);
+  }
+  cx = 0.5 * (x0 + x1);
+  cy = 0.5 * (y0 + y1);
+  R = 1e-300;
+  for (int b1 = RC_L2 * b2; b1 < e1; ++b1) {
+    const double* g = geo1c + (int64_t)b1 * RC_GEO;
+    R = fmax(R, sqrt((g[0] - cx) * (g[0] - cx) + (g[1] - cy) * (g[1] - cy)) + g[2]);
+  }
+}
+
+// grid (nb2 RC_L2, nrhs, RC_CZ), 256 threads: block (b2 RC_L2 + u, c, z) sums
+// the powers of slice z over first-level cluster RC_L2 b2 + u (packed
+// sources of column c) about second-level cluster b2's centre, into
+// part2 + ((c nb2 + b2) RC_L2 + u) 4 RC_NP (G_p, E_p; zero for a cluster
+// past the end).
+__global__ __launch_bounds__(256) void resid_clusters2_kernel(int64_t n, const double* __restrict__ pk,
+                                                              const double* __restrict__ geo1, int nb1, int nb2,
+                                                              double* __restrict__ part2) {
+  __shared__ ClusterSums S;
+  const int tid = threadIdx.x;
+  const int b2 = blockIdx.x / RC_L2, u = blockIdx.x % RC_L2, c = blockIdx.y, z = blockIdx.z;
+  const int b1 = RC_L2 * b2 + u;
+  double cx, cy, R;
+  l2_geometry(geo1 + (int64_t)c * nb1 * RC_GEO, nb1, b2, cx, cy, R);
+  const int64_t j = (int64_t)b1 * RC_CS + tid;
+  cluster_stage(S, (b1 < nb1 && j < n) ? pk + ((int64_t)c * n + j) * RPK : nullptr, cx, cy, R);
+  __syncthreads();
+  double2 G, E;
+  cluster_power_sums(S, z, G, E);
+  const int p = 4 * z * RC_PGZ + tid;
+  if (tid < RC_NPZ && p <= RC_P) {
+    double* o = part2 + (((int64_t)c * nb2 + b2) * RC_L2 + u) * 4 * RC_NP + 4 * p;
+    o[0] = G.x;
+    o[1] = G.y;
+    o[2] = E.x;
+    o[3] = E.y;
+  }
+}
+
+// grid (nb2, nrhs), 64 threads: second-level records from the RC_L2 partial
+// sums (fixed order), rec2 + (c nb2 + b2) RC_REC and geo2 + (c nb2 + b2) RC_GEO.
+__global__ __launch_bounds__(64) void resid_clusters2_sum_kernel(const double* __restrict__ geo1, int nb1, int nb2,
+                                                                 const double* __restrict__ part2,
+                                                                 double* __restrict__ rec2, double* __restrict__ geo2) {
+  const int b2 = blockIdx.x, c = blockIdx.y, lane = threadIdx.x;
+  double* r = rec2 + ((int64_t)c * nb2 + b2) * RC_REC;
+  const double* pp = part2 + ((int64_t)c * nb2 + b2) * RC_L2 * 4 * RC_NP;
+  if (lane <= RC_P) {
+    const int p = lane;
+    double g0 = 0.0, g1 = 0.0, e0 = 0.0, e1 = 0.0;
+    for (int u = 0; u < RC_L2; ++u) {
+      const double* o = pp + (int64_t)u * 4 * RC_NP + 4 * p;
+      g0 += o[0];
+      g1 += o[1];
+      e0 += o[2];
+      e1 += o[3];
+    }
+    double* o = r + 4 + 6 * p;
+    o[0] = g0;
+    o[1] = g1;
+    o[2] = (p + 1) * g0;
+    o[3] = (p + 1) * g1;
+    o[4] = e0;
+    o[5] = e1;
+  }
+  if (lane == 63) {
+    double cx, cy, R;
+    l2_geometry(geo1 + (int64_t)c * nb1 * RC_GEO, nb1, b2, cx, cy, R);
+    r[0] = cx;
+    r[1] = cy;
+    r[2] = R;
+    r[3] = 0.0;
+    double* gc = geo2 + ((int64_t)c * nb2 + b2) * RC_GEO;
+    const double gv[RC_GEO] = {cx, cy, R, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < RC_GEO; ++e) gc[e] = gv[e];
   }
 }
 
@@ -578,10 +698,13 @@ __global__ __launch_bounds__(256) void resid_clusters_kernel(const NodeRec* __re
 // contributes 0) to part[((z nrhs + c) n + i) 2 + {0, 1}], as
 // resid_scalar_kernel does.
 constexpr int RC_TG = 128;   // targets per group (a wave)
+template <bool TWO>   // second-level clusters (ncl2 > 0)
 __global__ __launch_bounds__(256) void resid_far_eval_kernel(const NodeRec* __restrict__ nd, int64_t n,
                                                              const double* __restrict__ pk,
                                                              const double* __restrict__ rec,
-                                                             const double* __restrict__ geo, int ncl, int nnear,
+                                                             const double* __restrict__ geo, int ncl,
+                                                             const double* __restrict__ rec2,
+                                                             const double* __restrict__ geo2, int ncl2, int nnear,
                                                              int nfar, double* __restrict__ part) {
   const int c = blockIdx.y, nrhs = gridDim.y, z = blockIdx.z;
   const int lane = threadIdx.x & 63;
@@ -628,148 +751,241 @@ __global__ __launch_bounds__(256) void resid_far_eval_kernel(const NodeRec* __re
   const int kind = nnear == 0 ? 2 : (z < nnear ? 0 : 1);
   const int slot = kind == 0 ? z : (nnear == 0 ? z : z - nnear);
   const int nslot = kind == 0 ? nnear : nfar;
-  int rank = 0;           // units of this item's kind met so far (a near cluster is two units of RC_CS / 2 sources)
+  int rank = 0;   // units of this item's kind met so far (a near cluster is two units of RC_CS / 2 sources)
   int next = kind == 2 ? 0 : slot;   // rank of the next unit this item takes
   const int step_r = kind == 2 ? 1 : nslot;
-  for (int base = 0; base < ncl; base += 64) {
-    // near / far test of 64 clusters at once, lane l taking cluster base + l
-    const int sl = base + lane;
-    double gx = 0.0, gy = 0.0, gr = 0.0;
-    bool far_l = false;
-    if (sl < ncl) {
-      const double* gc = geo + ((int64_t)c * ncl + sl) * 4;
-      gx = gc[0];
-      gy = gc[1];
-      gr = gc[2];
-      const double dx = tcx - gx, dy = tcy - gy, lim = RC_RATIO * gr + rt;
-      far_l = dx * dx + dy * dy >= lim * lim;
+  auto take = [&]() __attribute__((always_inline)) {
+    const bool t = rank == next;
+    if (t) next += step_r;
+    ++rank;
+    return t;
+  };
+  // ---- a cluster (record cr, centre (cx, cy), radius R) by its expansion
+  auto eval_far = [&](const double* cr, double cx, double cy, double R) __attribute__((always_inline)) {
+    // rho = R / (|c_t - c_s| - R_t) >= |W| at every target of the group;
+    // the terms after p = P sum to at most (P + 2) rho^(P + 1) / (1 - rho)^2
+    // of the cluster's scale, and P is the smallest that keeps this below
+    // 1e-17 (P + 2 <= 42 in the bound; one term more for the float logs)
+    const double dx = tcx - cx, dy = tcy - cy;
+    const double rho = R / (sqrt(dx * dx + dy * dy) - rt);
+    const float l2r = __log2f((float)rho), l2q = __log2f((float)(1.0 - rho));
+    const float pf = (-56.5f + 2.0f * l2q - 5.4f) / l2r;   // log2(1e-17) = -56.47
+    const int pe = pf >= (float)RC_P ? RC_P : (pf > 0.0f ? (int)pf + 1 : 1);
+    const int P = __builtin_amdgcn_readfirstlane(pe < RC_P ? pe : RC_P);
+    double2 Zt[2], iz[2], W[2], G[2], F[2], E[2];
+    const double* co = cr + 4 + 6 * P;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      Zt[u] = make_double2(xi[u] - cx, yi[u] - cy);
+      const double in2 = 1.0 / fma(Zt[u].x, Zt[u].x, Zt[u].y * Zt[u].y);
+      iz[u] = make_double2(Zt[u].x * in2, -Zt[u].y * in2);
+      W[u] = make_double2(R * iz[u].x, R * iz[u].y);
+      G[u] = make_double2(co[0], co[1]);
+      F[u] = make_double2(co[2], co[3]);
+      E[u] = make_double2(co[4], co[5]);
     }
-    const uint64_t fm = __ballot(sl < ncl && far_l);
-    const uint64_t vm = __ballot(sl < ncl);
-    uint64_t m = kind == 0 ? (vm & ~fm) : (kind == 1 ? fm : vm);
-    while (m) {
-      const int b = __builtin_ctzll(m);
-      m &= m - 1;
-      const int s = base + b;
-      const bool far = (fm >> b) & 1;
-      // the units of this cluster that are this item's (near halves 0 / 1)
-      int h0 = -1, h1 = -1;
-      if (rank == next) { h0 = 0; next += step_r; }
-      ++rank;
-      if (!far) {
-        if (rank == next) { (h0 < 0 ? h0 : h1) = 1; next += step_r; }
-        ++rank;
+    auto step = [&](const double* cp) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const double2 w = W[u];
+        G[u] = make_double2(fma(G[u].x, w.x, fma(-G[u].y, w.y, cp[0])), fma(G[u].x, w.y, fma(G[u].y, w.x, cp[1])));
+        F[u] = make_double2(fma(F[u].x, w.x, fma(-F[u].y, w.y, cp[2])), fma(F[u].x, w.y, fma(F[u].y, w.x, cp[3])));
+        E[u] = make_double2(fma(E[u].x, w.x, fma(-E[u].y, w.y, cp[4])), fma(E[u].x, w.y, fma(E[u].y, w.x, cp[5])));
       }
-      if (h0 < 0) continue;
-      const double cx = __shfl(gx, b), cy = __shfl(gy, b), R = __shfl(gr, b);
-      const double* cr = rec + ((int64_t)c * ncl + s) * RC_REC;
-      if (far) {
-        // rho = R / (|c_t - c_s| - R_t) >= |W| at every target of the group;
-        // the terms after p = P sum to at most (P + 2) rho^(P + 1) / (1 - rho)^2
-        // of the cluster's scale, and P is the smallest that keeps this below
-        // 1e-17 (P + 2 <= 42 in the bound; one term more for the float logs)
-        const double dx = tcx - cx, dy = tcy - cy;
-        const double rho = R / (sqrt(dx * dx + dy * dy) - rt);
-        const float l2r = __log2f((float)rho), l2q = __log2f((float)(1.0 - rho));
-        const float pf = (-56.5f + 2.0f * l2q - 5.4f) / l2r;   // log2(1e-17) = -56.47
-        const int pe = pf >= (float)RC_P ? RC_P : (pf > 0.0f ? (int)pf + 1 : 1);
-        const int P = __builtin_amdgcn_readfirstlane(pe < RC_P ? pe : RC_P);
-        double2 Zt[2], iz[2], W[2], G[2], F[2], E[2];
-        const double* co = cr + 4 + 6 * P;
+    };
+    int p = P - 1;
+    for (; p >= 3; p -= 4) {
+      const double* cp = cr + 4 + 6 * p;
+      step(cp);
+      step(cp - 6);
+      step(cp - 12);
+      step(cp - 18);
+    }
+    for (; p >= 0; --p) step(cr + 4 + 6 * p);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const double2 u1 = cmul2(iz[u], G[u]);
+      const double2 u2 = cmul2(iz[u], E[u]);
+      const double2 f2 = cmul2(cmul2(iz[u], iz[u]), F[u]);
+      // Z conj(f2)
+      const double2 u3 = make_double2(Zt[u].x * f2.x + Zt[u].y * f2.y, Zt[u].y * f2.x - Zt[u].x * f2.y);
+      ax[u] += u1.x + u2.x + u3.x;
+      ay[u] += u1.y - u2.y + u3.y;
+    }
+  };
+  // ---- halves h0 (and h1) of first-level cluster s1 pair by pair, staged
+  // in this wave's LDS slice 128 at a time (coalesced loads), then read
+  // with the same address in every lane (broadcast)
+  auto eval_near = [&](int s1, int h0, int h1) __attribute__((always_inline)) {
+    const int64_t c0 = (int64_t)s1 * RC_CS;
+    const int64_t j0 = min(n, c0 + (int64_t)h0 * (RC_CS / 2));
+    const int64_t j1 = min(n, c0 + (int64_t)((h1 >= 0 ? h1 : h0) + 1) * (RC_CS / 2));
+    for (int64_t b0 = j0; b0 < j1; b0 += 128) {
+      const int cnt = (int)min<int64_t>(128, j1 - b0);
+      __builtin_amdgcn_wave_barrier();   // the previous chunk's reads are issued
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int t = lane + 64 * h;
+        if (t < cnt) {
+          const double* q = pkc + (b0 + t) * RPK;
+          sp[0][t] = make_double2(q[0], q[1]);
+          sp[1][t] = make_double2(q[2], q[3]);
+          sp[2][t] = make_double2(q[4], q[5]);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      auto terml = [&](int u, double2 nw, double2 tv, double rx, double ry, double inv) {
+        const double cf = (rx * nw.x + ry * nw.y) * inv * inv;
+        const double d = cf * (rx * tv.x + ry * tv.y);
+        ax[u] += d * rx;
+        ay[u] += d * ry;
+      };
+      int t = 0;
+      for (; t + 4 <= cnt; t += 4) {
+        const double2 p0 = sp[0][t], p1 = sp[0][t + 1], p2 = sp[0][t + 2], p3 = sp[0][t + 3];
+        const double2 n0 = sp[1][t], n1 = sp[1][t + 1], n2 = sp[1][t + 2], n3 = sp[1][t + 3];
+        const double2 v0 = sp[2][t], v1 = sp[2][t + 1], v2 = sp[2][t + 2], v3 = sp[2][t + 3];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          Zt[u] = make_double2(xi[u] - cx, yi[u] - cy);
-          const double in2 = 1.0 / fma(Zt[u].x, Zt[u].x, Zt[u].y * Zt[u].y);
-          iz[u] = make_double2(Zt[u].x * in2, -Zt[u].y * in2);
-          W[u] = make_double2(R * iz[u].x, R * iz[u].y);
-          G[u] = make_double2(co[0], co[1]);
-          F[u] = make_double2(co[2], co[3]);
-          E[u] = make_double2(co[4], co[5]);
+          const double rx0 = xi[u] - p0.x, ry0 = yi[u] - p0.y, rx1 = xi[u] - p1.x, ry1 = yi[u] - p1.y;
+          const double rx2 = xi[u] - p2.x, ry2 = yi[u] - p2.y, rx3 = xi[u] - p3.x, ry3 = yi[u] - p3.y;
+          const double a = r2f(rx0, ry0), bb = r2f(rx1, ry1), cc = r2f(rx2, ry2), d = r2f(rx3, ry3);
+          const double ab = a * bb, cd = cc * d;
+          const double y = rcp_nr3(ab * cd);
+          const double yab = y * cd, ycd = y * ab;
+          terml(u, n0, v0, rx0, ry0, bb * yab);
+          terml(u, n1, v1, rx1, ry1, a * yab);
+          terml(u, n2, v2, rx2, ry2, d * ycd);
+          terml(u, n3, v3, rx3, ry3, cc * ycd);
         }
-        auto step = [&](const double* cp) {
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const double2 w = W[u];
-            G[u] = make_double2(fma(G[u].x, w.x, fma(-G[u].y, w.y, cp[0])), fma(G[u].x, w.y, fma(G[u].y, w.x, cp[1])));
-            F[u] = make_double2(fma(F[u].x, w.x, fma(-F[u].y, w.y, cp[2])), fma(F[u].x, w.y, fma(F[u].y, w.x, cp[3])));
-            E[u] = make_double2(fma(E[u].x, w.x, fma(-E[u].y, w.y, cp[4])), fma(E[u].x, w.y, fma(E[u].y, w.x, cp[5])));
-          }
-        };
-        int p = P - 1;
-        for (; p >= 3; p -= 4) {
-          const double* cp = cr + 4 + 6 * p;
-          step(cp);
-          step(cp - 6);
-          step(cp - 12);
-          step(cp - 18);
-        }
-        for (; p >= 0; --p) step(cr + 4 + 6 * p);
+      }
+      for (; t < cnt; ++t) {
+        const double2 p0 = sp[0][t], n0 = sp[1][t], v0 = sp[2][t];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          const double2 u1 = cmul2(iz[u], G[u]);
-          const double2 u2 = cmul2(iz[u], E[u]);
-          const double2 f2 = cmul2(cmul2(iz[u], iz[u]), F[u]);
-          // Z conj(f2)
-          const double2 u3 = make_double2(Zt[u].x * f2.x + Zt[u].y * f2.y, Zt[u].y * f2.x - Zt[u].x * f2.y);
-          ax[u] += u1.x + u2.x + u3.x;
-          ay[u] += u1.y - u2.y + u3.y;
+          const double rx = xi[u] - p0.x, ry = yi[u] - p0.y;
+          terml(u, n0, v0, rx, ry, rcp_nr3(r2f(rx, ry)));
         }
-      } else {
-        // sources of the near units taken: half h0 (and h1) of the cluster,
-        // staged in this wave's LDS slice 128 at a time (coalesced loads),
-        // then read with the same address in every lane (broadcast)
-        const int64_t c0 = (int64_t)s * RC_CS;
-        const int64_t j0 = min(n, c0 + (int64_t)h0 * (RC_CS / 2));
-        const int64_t j1 = min(n, c0 + (int64_t)((h1 >= 0 ? h1 : h0) + 1) * (RC_CS / 2));
-        for (int64_t b0 = j0; b0 < j1; b0 += 128) {
-          const int cnt = (int)min<int64_t>(128, j1 - b0);
-          __builtin_amdgcn_wave_barrier();   // the previous chunk's reads are issued
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int t = lane + 64 * h;
-            if (t < cnt) {
-              const double* q = pkc + (b0 + t) * RPK;
-              sp[0][t] = make_double2(q[0], q[1]);
-              sp[1][t] = make_double2(q[2], q[3]);
-              sp[2][t] = make_double2(q[4], q[5]);
+      }
+    }
+  };
+  // near / far test of a cluster against the group's circle
+  auto is_far = [&](double gx, double gy, double gr) __attribute__((always_inline)) {
+    const double dx = tcx - gx, dy = tcy - gy, lim = RC_RATIO * gr + rt;
+    return dx * dx + dy * dy >= lim * lim;
+  };
+  // ---- the clusters, tested 64 at a time (one per lane) and walked bit by
+  // bit; with second-level clusters, a far one is one far unit and a near
+  // one has its first-level clusters tested and walked the same way.  One
+  // place below takes every unit: a far cluster (either level) is one far
+  // unit, a near first-level cluster two near units.
+  if constexpr (!TWO) {
+    // one level: the clusters of this item's kind only, each met once
+    for (int base = 0; base < ncl; base += 64) {
+      const int sl = base + lane;
+      double gx = 0.0, gy = 0.0, gr = 0.0;
+      bool far_l = false;
+      if (sl < ncl) {
+        const double* gc = geo + ((int64_t)c * ncl + sl) * RC_GEO;
+        gx = gc[0];
+        gy = gc[1];
+        gr = gc[2];
+        far_l = is_far(gx, gy, gr);
+      }
+      const uint64_t fm = __ballot(sl < ncl && far_l);
+      const uint64_t vm = __ballot(sl < ncl);
+      uint64_t m = kind == 0 ? (vm & ~fm) : (kind == 1 ? fm : vm);
+      while (m) {
+        const int b = __builtin_ctzll(m);
+        m &= m - 1;
+        const int s1 = base + b;
+        const bool far = (fm >> b) & 1;
+        // the units of this cluster that are this item's (near halves 0 / 1)
+        int h0 = -1, h1 = -1;
+        if (take()) h0 = 0;
+        if (!far && take()) (h0 < 0 ? h0 : h1) = 1;
+        if (h0 < 0) continue;
+        if (far)
+          eval_far(rec + ((int64_t)c * ncl + s1) * RC_REC, __shfl(gx, b), __shfl(gy, b), __shfl(gr, b));
+        else
+          eval_near(s1, h0, h1);
+      }
+    }
+  } else {
+    const int ntop = TWO ? ncl2 : ncl;
+    const double* geot = TWO ? geo2 + (int64_t)c * ncl2 * RC_GEO : geo + (int64_t)c * ncl * RC_GEO;
+    for (int base = 0; base < ntop; base += 64) {
+      const int sl = base + lane;
+      double gx = 0.0, gy = 0.0, gr = 0.0;
+      bool far_l = false;
+      if (sl < ntop) {
+        const double* gc = geot + (int64_t)sl * RC_GEO;
+        gx = gc[0];
+        gy = gc[1];
+        gr = gc[2];
+        far_l = is_far(gx, gy, gr);
+      }
+      const uint64_t fm = __ballot(sl < ntop && far_l);
+      uint64_t m = __ballot(sl < ntop);
+      if (!TWO && kind == 0) m &= ~fm;   // near items meet no far unit at one level
+      if (!TWO && kind == 1) m &= fm;
+      uint64_t cm = 0, fm1 = 0;   // first-level clusters of the near second-level cluster cs2 still to walk
+      int cs2 = 0;
+      double hx = 0.0, hy = 0.0, hr = 0.0;
+      for (;;) {
+        int s1;
+        bool far;
+        double cx, cy, R;
+        const double* cr;
+        if (TWO && cm) {
+          const int k = __builtin_ctzll(cm);
+          cm &= cm - 1;
+          s1 = RC_L2 * cs2 + k;
+          far = (fm1 >> k) & 1;
+          cx = __shfl(hx, k);
+          cy = __shfl(hy, k);
+          R = __shfl(hr, k);
+          cr = rec + ((int64_t)c * ncl + s1) * RC_REC;
+        } else if (m) {
+          const int b = __builtin_ctzll(m);
+          m &= m - 1;
+          const int st = base + b;
+          far = (fm >> b) & 1;
+          if (TWO && !far) {
+            // its first-level clusters, lane k taking cluster RC_L2 st + k
+            const int k1 = RC_L2 * st + (lane & (RC_L2 - 1));
+            const bool v1 = lane < RC_L2 && k1 < ncl;
+            bool f1 = false;
+            hx = hy = hr = 0.0;
+            if (v1) {
+              const double* gc = geo + ((int64_t)c * ncl + k1) * RC_GEO;
+              hx = gc[0];
+              hy = gc[1];
+              hr = gc[2];
+              f1 = is_far(hx, hy, hr);
             }
+            fm1 = __ballot(v1 && f1);
+            cm = __ballot(v1);
+            cs2 = st;
+            continue;
           }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          auto terml = [&](int u, double2 nw, double2 tv, double rx, double ry, double inv) {
-            const double cf = (rx * nw.x + ry * nw.y) * inv * inv;
-            const double d = cf * (rx * tv.x + ry * tv.y);
-            ax[u] += d * rx;
-            ay[u] += d * ry;
-          };
-          int t = 0;
-          for (; t + 4 <= cnt; t += 4) {
-            const double2 p0 = sp[0][t], p1 = sp[0][t + 1], p2 = sp[0][t + 2], p3 = sp[0][t + 3];
-            const double2 n0 = sp[1][t], n1 = sp[1][t + 1], n2 = sp[1][t + 2], n3 = sp[1][t + 3];
-            const double2 v0 = sp[2][t], v1 = sp[2][t + 1], v2 = sp[2][t + 2], v3 = sp[2][t + 3];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-              const double rx0 = xi[u] - p0.x, ry0 = yi[u] - p0.y, rx1 = xi[u] - p1.x, ry1 = yi[u] - p1.y;
-              const double rx2 = xi[u] - p2.x, ry2 = yi[u] - p2.y, rx3 = xi[u] - p3.x, ry3 = yi[u] - p3.y;
-              const double a = r2f(rx0, ry0), bb = r2f(rx1, ry1), cc = r2f(rx2, ry2), d = r2f(rx3, ry3);
-              const double ab = a * bb, cd = cc * d;
-              const double y = rcp_nr3(ab * cd);
-              const double yab = y * cd, ycd = y * ab;
-              terml(u, n0, v0, rx0, ry0, bb * yab);
-              terml(u, n1, v1, rx1, ry1, a * yab);
-              terml(u, n2, v2, rx2, ry2, d * ycd);
-              terml(u, n3, v3, rx3, ry3, cc * ycd);
-            }
-          }
-          for (; t < cnt; ++t) {
-            const double2 p0 = sp[0][t], n0 = sp[1][t], v0 = sp[2][t];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-              const double rx = xi[u] - p0.x, ry = yi[u] - p0.y;
-              terml(u, n0, v0, rx, ry, rcp_nr3(r2f(rx, ry)));
-            }
-          }
+          s1 = st;
+          cx = __shfl(gx, b);
+          cy = __shfl(gy, b);
+          R = __shfl(gr, b);
+          cr = TWO ? rec2 + ((int64_t)c * ncl2 + st) * RC_REC : rec + ((int64_t)c * ncl + st) * RC_REC;
+        } else {
+          break;
+        }
+        if (far) {
+          if (kind != 0 && take()) eval_far(cr, cx, cy, R);
+        } else if (kind != 1) {
+          int h0 = -1, h1 = -1;
+          if (take()) h0 = 0;
+          if (take()) (h0 < 0 ? h0 : h1) = 1;
+          if (h0 >= 0) eval_near(s1, h0, h1);
         }
       }
     }
@@ -1100,8 +1316,10 @@ static size_t resid_call_doubles(int64_t n, int nrhs) {
   const int64_t nb = blocks(n);
   const size_t pairs =
       (size_t)resid_splits(n, nrhs) * nrhs * 2 * n + (size_t)(3 * nb * nrhs) + (nrhs == 1 ? (size_t)RPK * n : 0);
+  const int64_t nb2 = n >= RC_L2_MIN_N ? (nb + RC_L2 - 1) / RC_L2 : 0;
   const size_t far = (size_t)far_splits(n, nrhs) * nrhs * 2 * n + (size_t)(3 * nb * nrhs) +
-                     (size_t)RPK * n * nrhs + (size_t)(RC_REC + 4) * nb * nrhs;
+                     (size_t)RPK * n * nrhs + (size_t)(RC_REC + RC_GEO) * nb * nrhs +
+                     (size_t)(RC_REC + RC_GEO + RC_L2 * 4 * RC_NP) * nb2 * nrhs;
   return pairs > far ? pairs : far;
 }
 
@@ -1131,13 +1349,26 @@ void launch_residual(const NodeRec* nodes, int64_t n, const double* g, const dou
     double* pk = npart + (size_t)2 * nb * nrhs;
     double* rec = pk + (size_t)RPK * n * nrhs;
     double* geo = rec + (size_t)RC_REC * nb * nrhs;
+    const int nb2 = n >= RC_L2_MIN_N ? (nb + RC_L2 - 1) / RC_L2 : 0;
+    double* rec2 = geo + (size_t)RC_GEO * nb * nrhs;
+    double* geo2 = rec2 + (size_t)RC_REC * nb2 * nrhs;
+    double* part2 = geo2 + (size_t)RC_GEO * nb2 * nrhs;
     KernelTimer kt("resid_far_eval_kernel", 0.0, 0.0, s);
     hipLaunchKernelGGL(resid_clusters_kernel, dim3(nb, nrhs, RC_CZ), dim3(256), 0, s, nodes, n, tau, pk, fpart, rec,
                        geo);
+    if (nb2 > 0) {
+      hipLaunchKernelGGL(resid_clusters2_kernel, dim3(nb2 * RC_L2, nrhs, RC_CZ), dim3(256), 0, s, n, pk, geo, nb, nb2,
+                         part2);
+      hipLaunchKernelGGL(resid_clusters2_sum_kernel, dim3(nb2, nrhs), dim3(64), 0, s, geo, nb, nb2, part2, rec2, geo2);
+    }
     int nnear, nfar;
     far_items(n, nrhs, &nnear, &nfar);
-    hipLaunchKernelGGL(resid_far_eval_kernel, dim3(blocks(n, 4 * RC_TG), nrhs, ns), dim3(256), 0, s, nodes, n, pk, rec,
-                       geo, nb, nnear, nfar, part);
+    if (nb2 > 0)
+      hipLaunchKernelGGL(resid_far_eval_kernel<true>, dim3(blocks(n, 4 * RC_TG), nrhs, ns), dim3(256), 0, s, nodes, n,
+                         pk, rec, geo, nb, rec2, geo2, nb2, nnear, nfar, part);
+    else
+      hipLaunchKernelGGL(resid_far_eval_kernel<false>, dim3(blocks(n, 4 * RC_TG), nrhs, ns), dim3(256), 0, s, nodes, n,
+                         pk, rec, geo, nb, rec2, geo2, nb2, nnear, nfar, part);
     KERNEL_CHECK("resid_far_eval");
   } else {
     // algorithmic work: 12 flops per 2x2 block (r, r^2, r.n, 1/r^2 scaling) + 6 per

@@ -128,6 +128,47 @@ def test_expansions_full_size(ctx):
     wall.close()
 
 
+def test_expansions_two_levels(ctx):
+    """4096 panels, 32 panels x 4 levels (73216 nodes, 286 clusters of 256
+    nodes under 36 of 2048): second-level clusters far from a target group
+    are taken by one expansion each, near ones by their first-level clusters;
+    against the pairwise form on random densities (1 and 3 right-hand sides)
+    and in the refined solve."""
+    p = W.config4(seed=1, nrhs=1)
+    wall = rw.Wall(ctx, 4096)
+    ref = wall.refine(p.refinement.panel_ids, p.refinement.levels)
+    n = ref.n_nodes
+    assert n == 73216
+    rng = np.random.default_rng(9)
+    for nrhs in (1, 3):
+        t = rng.standard_normal((nrhs, 2 * n))
+        g = rng.standard_normal((nrhs, 2 * n))
+        gg, tt = (g[0], t[0]) if nrhs == 1 else (g, t)
+        r_e = _resid(ctx, ref, gg, tt, rw.RW_RESID_EXPAND).reshape(nrhs, -1)
+        r_p = _resid(ctx, ref, gg, tt, rw.RW_RESID_PAIRS).reshape(nrhs, -1)
+        worst = 0.0
+        for c in range(nrhs):
+            at = np.max(np.abs(g[c] - r_p[c]))
+            d = np.max(np.abs(r_e[c] - r_p[c]))
+            worst = max(worst, d / at)
+            assert d <= 1e-13 * at
+        _say(f"73216 nodes, {nrhs} rhs: largest |expand - pairs| / max |A tau| {worst:.2e}")
+    g = ref.stokeslet_rhs(p.rhs[0].z, p.rhs[0].f)
+    out = {}
+    for mode in (rw.RW_RESID_EXPAND, rw.RW_RESID_PAIRS):
+        ctx.set_options(resid_mode=mode)
+        tau = ref.solve(g).cpu().numpy()
+        inf = ref.info()
+        out[mode] = (tau, inf["ir_iters"], inf["resid"])
+    ctx.set_options(resid_mode=rw.RW_RESID_AUTO)
+    (te, ie, re), (tp, ip, rp) = out[rw.RW_RESID_EXPAND], out[rw.RW_RESID_PAIRS]
+    rel = np.linalg.norm(te - tp) / np.linalg.norm(tp)
+    _say(f"73216-node solve: ir {ie}/{ip}, resid {re:.2e}/{rp:.2e}, |tau_e - tau_p| / |tau_p| {rel:.2e}")
+    assert ie == ip and re <= 1e-13 and rp <= 1e-13 and rel <= 1e-13
+    ref.close()
+    wall.close()
+
+
 def test_resid_mode_checked(ctx):
     with pytest.raises(rw.RwError):
         ctx.set_options(resid_mode=3)
