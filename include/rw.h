@@ -78,8 +78,9 @@ enum rw_solver {
 enum rw_resid {
   RW_RESID_AUTO = 0,   /* RW_RESID_EXPAND from 4096 nodes, RW_RESID_PAIRS below */
   RW_RESID_PAIRS = 1,  /* every pair of nodes summed directly */
-  RW_RESID_EXPAND = 2  /* clusters of 256 consecutive nodes farther than 3 cluster radii from a wave of 64
-                          targets through their 40-term multipole expansions, the others pair by pair */
+  RW_RESID_EXPAND = 2  /* clusters of 256 consecutive nodes farther than 3 cluster radii from a group of
+                          128 targets through their multipole expansions (at most 40 terms), the others
+                          pair by pair; from 32768 nodes, far clusters of 2048 nodes by one expansion each */
 };
 
 /* Star curve gamma(theta) = (1 + a cos(m theta)) (cos theta, sin theta),
