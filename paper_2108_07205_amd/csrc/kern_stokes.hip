@@ -404,6 +404,7 @@ constexpr int RC_SGZ = 256 / RC_PGZ;                 // source groups per slice
 constexpr int RC_NPZ = 4 * RC_PGZ;                   // powers per slice
 constexpr int RC_GEO = 8;    // doubles per compact cluster record: c_x, c_y, R, x0, x1, y0, y1, 0
 constexpr int RC_L2 = 8;     // first-level clusters per second-level cluster
+constexpr int RC_CC = 8;     // right-hand sides per workgroup of the coefficient kernels
 constexpr int64_t RC_L2_MIN_N = 32768;   // second-level clusters from this many nodes
 
 // Shared memory of the coefficient sums of one cluster slice.
@@ -505,14 +506,15 @@ __device__ void cluster_power_sums(ClusterSums& S, int z, double2& Gout, double2
   }
 }
 
-// grid (ceil(n / RC_CS), nrhs, RC_CZ), 256 threads.  Block (b, c, z): the
-// coefficients of cluster b, column c for the powers of slice z; slice 0
-// also packs the sources (the RPK format of resid_scalar_kernel, at
+// grid (ceil(n / RC_CS), ceil(nrhs / RC_CC), RC_CZ), 256 threads.  Block
+// (b, y, z): the coefficients of cluster b for the powers of slice z, for
+// columns c = y RC_CC .. y RC_CC + RC_CC - 1 in turn (the cluster's geometry
+// found once); slice 0 also packs the sources (the RPK format of resid_scalar_kernel, at
 // pk + (c n + j) RPK), writes the flux partial of its nodes to fpart[c nb + b]
 // and the record's centre and radius, also to the compact geo + (c nb + b)
 // RC_GEO (c_x, c_y, R and the bounding box) that the evaluation scans.
 // Record: rec + (c nb + b) RC_REC.
-__global__ __launch_bounds__(256) void resid_clusters_kernel(const NodeRec* __restrict__ nd, int64_t n,
+__global__ __launch_bounds__(256) void resid_clusters_kernel(const NodeRec* __restrict__ nd, int64_t n, int nrhs,
                                                              const double* __restrict__ tau, double* __restrict__ pk,
                                                              double* __restrict__ fpart, double* __restrict__ rec,
                                                              double* __restrict__ geo) {
@@ -520,32 +522,13 @@ __global__ __launch_bounds__(256) void resid_clusters_kernel(const NodeRec* __re
   __shared__ double wred[4][4];
   __shared__ ClusterSums S;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int b = blockIdx.x, c = blockIdx.y, nb = gridDim.x, z = blockIdx.z;
+  const int b = blockIdx.x, nb = gridDim.x, z = blockIdx.z;
+  const int c0 = blockIdx.y * RC_CC, c1 = min(nrhs, c0 + RC_CC);
   const int64_t j = (int64_t)b * RC_CS + tid;
   const bool ok = j < n;
-  const double* tc = tau + (int64_t)c * 2 * n;
   NodeRec q{};
-  double tx = 0.0, ty = 0.0;
-  if (ok) {
-    q = nd[j];
-    tx = tc[2 * j];
-    ty = tc[2 * j + 1];
-  }
-  const double qr[6] = {q.x, q.y, q.nx * q.w * kInvPi, q.ny * q.w * kInvPi, tx, ty};
-  if (z == 0) {   // uniform
-    double fl = 0.0;
-    if (ok) {
-      double* o = pk + ((int64_t)c * n + j) * RPK;
-#pragma unroll
-      for (int e = 0; e < 6; ++e) o[e] = qr[e];
-      o[6] = 0.0;
-      o[7] = 0.0;
-      fl = flux_term(q, tc, j);
-    }
-    const double fsum = block_sum256(fl, red4);
-    if (tid == 0) fpart[(int64_t)c * nb + b] = fsum;
-  }
-  // bounding box of the cluster, its centre and radius
+  if (ok) q = nd[j];
+  // bounding box of the cluster, its centre and radius (the same for every column)
   {
     const double v0 = wave_min(ok ? q.x : INFINITY), v1 = wave_max(ok ? q.x : -INFINITY);
     const double v2 = wave_min(ok ? q.y : INFINITY), v3 = wave_max(ok ? q.y : -INFINITY);
@@ -565,29 +548,52 @@ __global__ __launch_bounds__(256) void resid_clusters_kernel(const NodeRec* __re
   // R > 0 even for a cluster of one point (its s_j are then 0 and only the
   // p = 0 terms remain)
   const double R = fmax(sqrt(fmax(fmax(wred[0][0], wred[1][0]), fmax(wred[2][0], wred[3][0]))), 1e-300);
-  cluster_stage(S, ok ? qr : nullptr, cx, cy, R);
-  __syncthreads();
-  double2 G, E;
-  cluster_power_sums(S, z, G, E);
-  double* r = rec + ((int64_t)c * nb + b) * RC_REC;
-  const int p = 4 * z * RC_PGZ + tid;
-  if (tid < RC_NPZ && p <= RC_P) {
-    double* o = r + 4 + 6 * p;
-    o[0] = G.x;
-    o[1] = G.y;
-    o[2] = (p + 1) * G.x;
-    o[3] = (p + 1) * G.y;
-    o[4] = E.x;
-    o[5] = E.y;
-  } else if (tid == 64 && z == 0) {
-    r[0] = cx;
-    r[1] = cy;
-    r[2] = R;
-    r[3] = 0.0;
-    double* gc = geo + ((int64_t)c * nb + b) * RC_GEO;
-    const double gv[RC_GEO] = {cx, cy, R, x0, x1, y0, y1, 0.0};
+  for (int c = c0; c < c1; ++c) {
+    const double* tc = tau + (int64_t)c * 2 * n;
+    double tx = 0.0, ty = 0.0;
+    if (ok) {
+      tx = tc[2 * j];
+      ty = tc[2 * j + 1];
+    }
+    const double qr[6] = {q.x, q.y, q.nx * q.w * kInvPi, q.ny * q.w * kInvPi, tx, ty};
+    if (z == 0) {   // uniform
+      double fl = 0.0;
+      if (ok) {
+        double* o = pk + ((int64_t)c * n + j) * RPK;
 #pragma unroll
-    for (int e = 0; e < RC_GEO; ++e) gc[e] = gv[e];
+        for (int e = 0; e < 6; ++e) o[e] = qr[e];
+        o[6] = 0.0;
+        o[7] = 0.0;
+        fl = flux_term(q, tc, j);
+      }
+      const double fsum = block_sum256(fl, red4);
+      if (tid == 0) fpart[(int64_t)c * nb + b] = fsum;
+    }
+    __syncthreads();   // the previous column's sums have read the staging
+    cluster_stage(S, ok ? qr : nullptr, cx, cy, R);
+    __syncthreads();
+    double2 G, E;
+    cluster_power_sums(S, z, G, E);
+    double* r = rec + ((int64_t)c * nb + b) * RC_REC;
+    const int p = 4 * z * RC_PGZ + tid;
+    if (tid < RC_NPZ && p <= RC_P) {
+      double* o = r + 4 + 6 * p;
+      o[0] = G.x;
+      o[1] = G.y;
+      o[2] = (p + 1) * G.x;
+      o[3] = (p + 1) * G.y;
+      o[4] = E.x;
+      o[5] = E.y;
+    } else if (tid == 64 && z == 0) {
+      r[0] = cx;
+      r[1] = cy;
+      r[2] = R;
+      r[3] = 0.0;
+      double* gc = geo + ((int64_t)c * nb + b) * RC_GEO;
+      const double gv[RC_GEO] = {cx, cy, R, x0, x1, y0, y1, 0.0};
+#pragma unroll
+      for (int e = 0; e < RC_GEO; ++e) gc[e] = gv[e];
+    }
   }
 }
 
@@ -615,32 +621,37 @@ __device__ __forceinline__ void l2_geometry(const double* geo1c, int nb1, int b2
   }
 }
 
-// grid (nb2 RC_L2, nrhs, RC_CZ), 256 threads: block (b2 RC_L2 + u, c, z) sums
-// the powers of slice z over first-level cluster RC_L2 b2 + u (packed
-// sources of column c) about second-level cluster b2's centre, into
+// grid (nb2 RC_L2, ceil(nrhs / RC_CC), RC_CZ), 256 threads: block (b2 RC_L2 +
+// u, y, z) sums the powers of slice z over first-level cluster RC_L2 b2 + u
+// (packed sources of each column c = y RC_CC ..) about second-level cluster
+// b2's centre, into
 // part2 + ((c nb2 + b2) RC_L2 + u) 4 RC_NP (G_p, E_p; zero for a cluster
 // past the end).
-__global__ __launch_bounds__(256) void resid_clusters2_kernel(int64_t n, const double* __restrict__ pk,
+__global__ __launch_bounds__(256) void resid_clusters2_kernel(int64_t n, int nrhs, const double* __restrict__ pk,
                                                               const double* __restrict__ geo1, int nb1, int nb2,
                                                               double* __restrict__ part2) {
   __shared__ ClusterSums S;
   const int tid = threadIdx.x;
-  const int b2 = blockIdx.x / RC_L2, u = blockIdx.x % RC_L2, c = blockIdx.y, z = blockIdx.z;
+  const int b2 = blockIdx.x / RC_L2, u = blockIdx.x % RC_L2, z = blockIdx.z;
+  const int c0 = blockIdx.y * RC_CC, c1 = min(nrhs, c0 + RC_CC);
   const int b1 = RC_L2 * b2 + u;
   double cx, cy, R;
-  l2_geometry(geo1 + (int64_t)c * nb1 * RC_GEO, nb1, b2, cx, cy, R);
+  l2_geometry(geo1 + (int64_t)c0 * nb1 * RC_GEO, nb1, b2, cx, cy, R);
   const int64_t j = (int64_t)b1 * RC_CS + tid;
-  cluster_stage(S, (b1 < nb1 && j < n) ? pk + ((int64_t)c * n + j) * RPK : nullptr, cx, cy, R);
-  __syncthreads();
-  double2 G, E;
-  cluster_power_sums(S, z, G, E);
-  const int p = 4 * z * RC_PGZ + tid;
-  if (tid < RC_NPZ && p <= RC_P) {
-    double* o = part2 + (((int64_t)c * nb2 + b2) * RC_L2 + u) * 4 * RC_NP + 4 * p;
-    o[0] = G.x;
-    o[1] = G.y;
-    o[2] = E.x;
-    o[3] = E.y;
+  for (int c = c0; c < c1; ++c) {
+    __syncthreads();   // the previous column's sums have read the staging
+    cluster_stage(S, (b1 < nb1 && j < n) ? pk + ((int64_t)c * n + j) * RPK : nullptr, cx, cy, R);
+    __syncthreads();
+    double2 G, E;
+    cluster_power_sums(S, z, G, E);
+    const int p = 4 * z * RC_PGZ + tid;
+    if (tid < RC_NPZ && p <= RC_P) {
+      double* o = part2 + (((int64_t)c * nb2 + b2) * RC_L2 + u) * 4 * RC_NP + 4 * p;
+      o[0] = G.x;
+      o[1] = G.y;
+      o[2] = E.x;
+      o[3] = E.y;
+    }
   }
 }
 
@@ -1354,11 +1365,12 @@ void launch_residual(const NodeRec* nodes, int64_t n, const double* g, const dou
     double* geo2 = rec2 + (size_t)RC_REC * nb2 * nrhs;
     double* part2 = geo2 + (size_t)RC_GEO * nb2 * nrhs;
     KernelTimer kt("resid_far_eval_kernel", 0.0, 0.0, s);
-    hipLaunchKernelGGL(resid_clusters_kernel, dim3(nb, nrhs, RC_CZ), dim3(256), 0, s, nodes, n, tau, pk, fpart, rec,
-                       geo);
+    const unsigned ncc = (unsigned)((nrhs + RC_CC - 1) / RC_CC);
+    hipLaunchKernelGGL(resid_clusters_kernel, dim3(nb, ncc, RC_CZ), dim3(256), 0, s, nodes, n, nrhs, tau, pk, fpart,
+                       rec, geo);
     if (nb2 > 0) {
-      hipLaunchKernelGGL(resid_clusters2_kernel, dim3(nb2 * RC_L2, nrhs, RC_CZ), dim3(256), 0, s, n, pk, geo, nb, nb2,
-                         part2);
+      hipLaunchKernelGGL(resid_clusters2_kernel, dim3(nb2 * RC_L2, ncc, RC_CZ), dim3(256), 0, s, n, nrhs, pk, geo, nb,
+                         nb2, part2);
       hipLaunchKernelGGL(resid_clusters2_sum_kernel, dim3(nb2, nrhs), dim3(64), 0, s, geo, nb, nb2, part2, rec2, geo2);
     }
     int nnear, nfar;
