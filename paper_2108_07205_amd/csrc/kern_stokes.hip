@@ -248,77 +248,103 @@ __global__ __launch_bounds__(256) void resid_scalar_kernel(const NodeRec* __rest
   }
 }
 
-// grid (nb = ceil(n / 256), nrhs).  s_N[c] is the sum of the nb flux
-// partials, taken in the same order by every wave; with npart, block b
-// also writes the partial sums of |r|^2 and |g|^2 over its nodes to
-// npart[2 (c nb + b)] and npart[2 (c nb + b) + 1].
-__global__ __launch_bounds__(256) void resid_finalize_kernel(const NodeRec* __restrict__ nd, int64_t n,
-                                                             const double* __restrict__ g,
-                                                             const double* __restrict__ tau, int nrhs, int nsplit,
-                                                             const double* __restrict__ part,
-                                                             const double* __restrict__ fpart,
-                                                             double* __restrict__ r, double* __restrict__ npart) {
+// grid (nb = ceil(n / 256), nrhs), 1024 threads: four quarters of 256
+// threads, one target node per thread; quarter h sums the split partials
+// z = h, h + 4, ... of the block's 256 targets (eight loads in flight), and
+// quarter 0 adds the four sums in a fixed order and finishes.  s_N[c] is the
+// sum of the nb flux partials, taken in the same order by every wave of
+// quarter 0; with npart, block b also writes the partial sums of |r|^2 and
+// |g|^2 over its nodes to npart[2 (c nb + b)] and npart[2 (c nb + b) + 1].
+constexpr int RFQ = 4;   // quarters (threads per target)
+__global__ __launch_bounds__(256 * RFQ) void resid_finalize_kernel(const NodeRec* __restrict__ nd, int64_t n,
+                                                                   const double* __restrict__ g,
+                                                                   const double* __restrict__ tau, int nrhs,
+                                                                   int nsplit, const double* __restrict__ part,
+                                                                   const double* __restrict__ fpart,
+                                                                   double* __restrict__ r,
+                                                                   double* __restrict__ npart) {
+  __shared__ double2 qs[RFQ - 1][256];
   __shared__ double red4[2][4];
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int tq = threadIdx.x & 255;
+  const int h = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8);
+  const int64_t i = (int64_t)blockIdx.x * 256 + tq;
   const int c = blockIdx.y, nb = gridDim.x;
   const int64_t ld = 2 * n;
-  // s_N: lane l sums the partials b = l (mod 64) in order, then a butterfly
-  // over the wave; every wave of every block takes the same steps, so all
-  // hold the same value
-  double sN = 0.0;
-  for (int b = threadIdx.x & 63; b < nb; b += 64) sN += fpart[(int64_t)c * nb + b];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) sN += __shfl_xor(sN, o);
-  double r2 = 0.0, g2 = 0.0;
+  // this quarter's splits: eight independent sums (z / RFQ mod 8), added
+  // pairwise in a fixed order
+  double sx = 0.0, sy = 0.0;
   if (i < n) {
-    const NodeRec q = nd[i];
-    const double tx = tau[2 * i + (int64_t)c * ld], ty = tau[2 * i + 1 + (int64_t)c * ld];
-    // self block without its nullspace part (added through s_N below)
-    const double a00 = q.s00 - q.w * q.nx * q.nx, a01 = q.s01 - q.w * q.nx * q.ny, a11 = q.s11 - q.w * q.ny * q.ny;
-    double ax = a00 * tx + a01 * ty + q.nx * sN;
-    double ay = a01 * tx + a11 * ty + q.ny * sN;
-    // split partials in RSUM independent sums (z mod RSUM), so that RSUM
-    // loads are in flight at a time, combined pairwise in a fixed order
-    constexpr int RSUM = 16;
-    double sx[RSUM] = {}, sy[RSUM] = {};
+    constexpr int U = 8;
+    double px[U] = {}, py[U] = {};
     const double2* p2 = reinterpret_cast<const double2*>(part + (int64_t)c * ld) + i;
     const int64_t zst = (int64_t)nrhs * n;   // split stride in double2
-    int z = 0;
-    for (; z + RSUM <= nsplit; z += RSUM) {
+    int z = h;
+    for (; z + RFQ * (U - 1) < nsplit; z += RFQ * U) {
 #pragma unroll
-      for (int u = 0; u < RSUM; ++u) {
-        const double2 v = p2[(int64_t)(z + u) * zst];
-        sx[u] += v.x;
-        sy[u] += v.y;
+      for (int u = 0; u < U; ++u) {
+        const double2 v = p2[(int64_t)(z + RFQ * u) * zst];
+        px[u] += v.x;
+        py[u] += v.y;
       }
     }
-    for (int u = 0; z < nsplit; ++z, ++u) {
+    for (int u = 0; z < nsplit; z += RFQ, ++u) {
       const double2 v = p2[(int64_t)z * zst];
-      sx[u] += v.x;
-      sy[u] += v.y;
+      px[u] += v.x;
+      py[u] += v.y;
     }
 #pragma unroll
-    for (int h = RSUM / 2; h > 0; h >>= 1)
+    for (int w = U / 2; w > 0; w >>= 1)
 #pragma unroll
-      for (int u = 0; u < h; ++u) {
-        sx[u] += sx[u + h];
-        sy[u] += sy[u + h];
+      for (int u = 0; u < w; ++u) {
+        px[u] += px[u + w];
+        py[u] += py[u + w];
       }
-    ax += sx[0];
-    ay += sy[0];
-    const double gx = g[2 * i + (int64_t)c * ld], gy = g[2 * i + 1 + (int64_t)c * ld];
-    const double rx = gx - ax, ry = gy - ay;
-    r[2 * i + (int64_t)c * ld] = rx;
-    r[2 * i + 1 + (int64_t)c * ld] = ry;
-    r2 = rx * rx + ry * ry;
-    g2 = gx * gx + gy * gy;
+    sx = px[0];
+    sy = py[0];
   }
-  if (npart) {
-    const double sr = block_sum256(r2, red4[0]);
-    const double sg = block_sum256(g2, red4[1]);
+  if (h > 0) qs[h - 1][tq] = make_double2(sx, sy);
+  __syncthreads();
+  double r2 = 0.0, g2 = 0.0;
+  if (h == 0) {
+    // s_N: lane l sums the partials b = l (mod 64) in order, then a
+    // butterfly over the wave; every wave of quarter 0 takes the same steps,
+    // so all hold the same value
+    double sN = 0.0;
+    for (int b = threadIdx.x & 63; b < nb; b += 64) sN += fpart[(int64_t)c * nb + b];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sN += __shfl_xor(sN, o);
+    if (i < n) {
+      const NodeRec q = nd[i];
+      const double tx = tau[2 * i + (int64_t)c * ld], ty = tau[2 * i + 1 + (int64_t)c * ld];
+      // self block without its nullspace part (added through s_N below)
+      const double a00 = q.s00 - q.w * q.nx * q.nx, a01 = q.s01 - q.w * q.nx * q.ny, a11 = q.s11 - q.w * q.ny * q.ny;
+      double ax = a00 * tx + a01 * ty + q.nx * sN;
+      double ay = a01 * tx + a11 * ty + q.ny * sN;
+      const double2 q1 = qs[0][tq], q2 = qs[1][tq], q3 = qs[2][tq];
+      ax += (sx + q1.x) + (q2.x + q3.x);
+      ay += (sy + q1.y) + (q2.y + q3.y);
+      const double gx = g[2 * i + (int64_t)c * ld], gy = g[2 * i + 1 + (int64_t)c * ld];
+      const double rx = gx - ax, ry = gy - ay;
+      r[2 * i + (int64_t)c * ld] = rx;
+      r[2 * i + 1 + (int64_t)c * ld] = ry;
+      r2 = rx * rx + ry * ry;
+      g2 = gx * gx + gy * gy;
+    }
+  }
+  if (npart) {   // uniform
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      r2 += __shfl_xor(r2, o);
+      g2 += __shfl_xor(g2, o);
+    }
+    if (h == 0 && (threadIdx.x & 63) == 0) {
+      red4[0][threadIdx.x >> 6] = r2;
+      red4[1][threadIdx.x >> 6] = g2;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-      npart[2 * ((int64_t)c * nb + blockIdx.x)] = sr;
-      npart[2 * ((int64_t)c * nb + blockIdx.x) + 1] = sg;
+      npart[2 * ((int64_t)c * nb + blockIdx.x)] = (red4[0][0] + red4[0][1]) + (red4[0][2] + red4[0][3]);
+      npart[2 * ((int64_t)c * nb + blockIdx.x) + 1] = (red4[1][0] + red4[1][1]) + (red4[1][2] + red4[1][3]);
     }
   }
 }
@@ -1398,7 +1424,7 @@ void launch_residual(const NodeRec* nodes, int64_t n, const double* g, const dou
     }
     KERNEL_CHECK("resid_tiles");
   }
-  hipLaunchKernelGGL(resid_finalize_kernel, dim3(nb, nrhs), dim3(256), 0, s, nodes, n, g, tau, nrhs, ns, part, fpart,
+  hipLaunchKernelGGL(resid_finalize_kernel, dim3(nb, nrhs), dim3(256 * RFQ), 0, s, nodes, n, g, tau, nrhs, ns, part, fpart,
                      r, norms ? npart : (double*)nullptr);
   KERNEL_CHECK("resid_finalize");
   if (norms) {
