@@ -1052,15 +1052,20 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
     // ---- a4: X = A~^{-1} L; the A_oo^{-1} block needs only the reference inverse
     f.X.alloc(ctx, (size_t)M * f.k);
     HIP_CHECK(hipMemsetAsync(f.X.p, 0, sizeof(double) * M * f.k, s));
-    if (f.k_k) {
-      PhaseTimer t_x(ctx, "a4_X", 2.0 * w->stats.gen_entries * f.k_k, 8.0 * w->stats.gen_entries * hbs_gen_passes(f.k_k));
-      hbs_apply(w, ctx, f.L.p, M, f.X.p, M, f.k_k, false);
-    }
+  }
+  // the side stream's A_pp^{-1} block of X below needs L, R and the cleared X
+  // from this stream, not the A_oo^{-1} block: it waits for this event only
+  const hipEvent_t x_in = ctx_order_event(ctx, 8);
+  HIP_CHECK(hipEventRecord(x_in, s));
+  if (f.k > 0 && f.k_k) {
+    PhaseTimer t_x(ctx, "a4_X", 2.0 * w->stats.gen_entries * f.k_k, 8.0 * w->stats.gen_entries * hbs_gen_passes(f.k_k));
+    hbs_apply(w, ctx, f.L.p, M, f.X.p, M, f.k_k, false);
   }
   // ---- the rest (A_pp^{-1} block of X, W and its inverse) runs on the side
-  // stream, behind this stream's work so far and the A_pp build, so that the
-  // main stream is free for the solve's A_oo^{-1} apply meanwhile; the solve
-  // joins the side stream before the Woodbury correction
+  // stream, behind the A_pp build and this stream's inputs to it (the A_pp^{-1}
+  // block of X beside the A_oo^{-1} block, W behind both), so that the main
+  // stream is free for the solve's A_oo^{-1} apply meanwhile; the solve joins
+  // the side stream before the Woodbury correction
   if (f.k > 0) {
     f.W.alloc(ctx, (size_t)2 * f.k * f.k);
     f.wpart.alloc(ctx, gemm_tn_part_doubles(M, f.k, f.k));
@@ -1072,7 +1077,7 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
     bool armed = true;
     ~SideDrain() { if (armed) (void)hipStreamSynchronize(st); }
   } drain{st};
-  stream_after(ctx, st, s, 7);
+  HIP_CHECK(hipStreamWaitEvent(st, x_in, 0));
   a3.join(st);
   if (f.Np > 0 && f.app_hbs_on) {
     if (!f.app_ready.e) HIP_CHECK(hipEventCreateWithFlags(&f.app_ready.e, hipEventDisableTiming));
@@ -1092,7 +1097,8 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
         launch_lu_solve(f.App.p, Mp, Mp, xp, M, f.k_p, st);
       }
     }
-    // ---- a5: W = I + R X and its inverse (FP64)
+    // ---- a5: W = I + R X and its inverse (FP64), behind the A_oo^{-1} block of X
+    stream_after(ctx, st, s, 7);
     PhaseTimer t_w(ctx, "a5_W", 2.0 * f.k * (double)f.k * M + 2.0 * (double)f.k * f.k * f.k, 16.0 * f.k * (double)M,
                    st);
     launch_gemm_tn(f.R.p, M, f.X.p, M, M, f.k, f.k, f.W.p, f.k, true, f.wpart.p, st);
@@ -1101,6 +1107,7 @@ void build_refined(rw_wall* w, rw_ctx* ctx, const std::vector<int32_t>& level_of
     launch_small_inverse(f.W.p, f.k, f.dinfo.p + 1, st);
     HIP_CHECK(hipMemcpyAsync(ctx->defer_pin, f.dinfo.p + 1, sizeof(int), hipMemcpyDeviceToHost, st));
   } else {
+    stream_after(ctx, st, s, 7);
     *ctx->defer_pin = 0;
   }
   // the W pivot flag and the A_pp build's flags and statistics (read back on
