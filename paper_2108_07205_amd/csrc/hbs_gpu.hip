@@ -536,9 +536,13 @@ __device__ __forceinline__ double dot_by4(const double (&a)[CPT], const double (
 // The pivot keys and the pivot vector alternate between two LDS slots, so a
 // step needs two barriers: a slot is written again two steps later, after
 // every thread has passed the first barrier of the step in between.
+// The pivot vector's TPR slices of SK_R / TPR entries lie ID_QST(TPR)
+// doubles apart, a stride of 2 (mod 16) doubles, so that the lanes of a wave
+// reading the same pair of entries of the TPR slices hit disjoint LDS banks.
 constexpr int ID_NT = 512;
+__host__ __device__ constexpr int ID_QST(int tpr) { return SK_R / tpr + (18 - (SK_R / tpr) % 16) % 16; }
 struct IdScratch {
-  double q[2][SK_R];
+  double q[2][4 * ID_QST(4)];
   double rv[2][ID_NT / 64];
   int other[2];
 };
@@ -547,8 +551,9 @@ template <int TPR>
 __device__ __forceinline__ void node_id_body(const GNode& g, const double* __restrict__ S, double tol2, int* pv,
                                              double* __restrict__ C, int* __restrict__ inf, long long* mine,
                                              long long* theirs, long long tag, IdScratch& L) {
-  constexpr int NW = ID_NT / 64, CPT = SK_R / TPR;
+  constexpr int NW = ID_NT / 64, CPT = SK_R / TPR, QST = ID_QST(TPR);
   static_assert(CPT % 4 == 0, "four partial sums per dot product");
+  static_assert(QST % 16 == 2 && TPR * QST <= 4 * ID_QST(4), "pivot vector slices");
   const int m = g.m, tid = threadIdx.x;
   const int i = tid / TPR, h = tid % TPR;
   const bool valid = i < m;
@@ -589,13 +594,13 @@ __device__ __forceinline__ void node_id_body(const GNode& g, const double* __res
     if (i == p) {
       const double inv = 1.0 / sqrt(nrm);
 #pragma unroll
-      for (int c = 0; c < CPT; ++c) L.q[b][h * CPT + c] = y[c] * inv;
+      for (int c = 0; c < CPT; ++c) L.q[b][h * QST + c] = y[c] * inv;
     }
     if (tid == 0) pv[step] = p;
     __syncthreads();
     double qr[CPT];
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) qr[c] = L.q[b][h * CPT + c];
+    for (int c = 0; c < CPT; ++c) qr[c] = L.q[b][h * QST + c];
     const double cf = row_group_sum<TPR>(dot_by4<CPT>(y, qr));
 #pragma unroll
     for (int c = 0; c < CPT; ++c) y[c] = fma(-cf, qr[c], y[c]);
