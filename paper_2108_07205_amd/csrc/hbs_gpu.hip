@@ -1189,7 +1189,8 @@ static_assert(BC == 16 && BS == 3, "the column switches and pivot-row branches b
 
 struct BorderScratch {
   double pan[2][BT][BC + 1];   // transformed panel of the block (alternating slots)
-  double rows[BWV][BC][BC];    // per wave: its columns of the block's pivot rows
+  double rows[BWV][BC][BC + 1];   // per wave: its columns of the block's pivot rows (rows padded
+                                  // so that the lanes storing different pivot rows hit different banks)
   double pinv[BT];             // 1 / pivot of each step
   int piv[BT];                 // pivot row of each step
   int bad;                     // a panel met a zero or non-finite pivot
