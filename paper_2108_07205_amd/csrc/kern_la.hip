@@ -277,7 +277,8 @@ __global__ __launch_bounds__(SEL_ROWS) void rowid_select_kernel(const double* __
 
 // Orthonormal rows Q (k x nc) of Y(J, :) in pivot order: classical
 // Gram-Schmidt with one reorthogonalization, one wave (thread u computes the
-// coefficient on q_u, thread c updates column c).  k <= 64.
+// coefficient on q_u, thread c updates column c; every sum in four
+// independent partial sums).  k <= 64, nc a multiple of 4.
 // The selected rows J (idx[0..*kp)) are copied to Jout and orthonormalized
 // in order into Q (k x nc, row-major); k is read on the device.
 __global__ __launch_bounds__(64) void rowid_basis_kernel(const double* __restrict__ Y, int nc,
@@ -293,20 +294,38 @@ __global__ __launch_bounds__(64) void rowid_basis_kernel(const double* __restric
     __syncthreads();
     for (int pass = 0; pass < 2; ++pass) {
       if (c < s) {
-        double a = 0.0;
-        for (int u = 0; u < nc; ++u) a += v[u] * qs[c][u];
-        d[c] = a;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int u = 0; u < nc; u += 4) {
+          a0 += v[u] * qs[c][u];
+          a1 += v[u + 1] * qs[c][u + 1];
+          a2 += v[u + 2] * qs[c][u + 2];
+          a3 += v[u + 3] * qs[c][u + 3];
+        }
+        d[c] = (a0 + a1) + (a2 + a3);
       }
       __syncthreads();
       if (c < nc) {
-        double a = v[c];
-        for (int u = 0; u < s; ++u) a -= d[u] * qs[u][c];
-        v[c] = a;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int u = 0;
+        for (; u + 4 <= s; u += 4) {
+          a0 += d[u] * qs[u][c];
+          a1 += d[u + 1] * qs[u + 1][c];
+          a2 += d[u + 2] * qs[u + 2][c];
+          a3 += d[u + 3] * qs[u + 3][c];
+        }
+        for (; u < s; ++u) a0 += d[u] * qs[u][c];
+        v[c] -= (a0 + a1) + (a2 + a3);
       }
       __syncthreads();
     }
-    double n2 = 0.0;
-    for (int u = 0; u < nc; ++u) n2 += v[u] * v[u];
+    double n0 = 0.0, n1 = 0.0, n2a = 0.0, n3 = 0.0;
+    for (int u = 0; u < nc; u += 4) {
+      n0 += v[u] * v[u];
+      n1 += v[u + 1] * v[u + 1];
+      n2a += v[u + 2] * v[u + 2];
+      n3 += v[u + 3] * v[u + 3];
+    }
+    const double n2 = (n0 + n1) + (n2a + n3);
     const double inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
     if (c < nc) {
       qs[s][c] = v[c] * inv;
@@ -317,34 +336,61 @@ __global__ __launch_bounds__(64) void rowid_basis_kernel(const double* __restric
 }
 
 // C(i, t) = <y_i, q_t> (row-major, ld kmax) for every row, and the largest
-// squared residual |y_i - C_i Q|^2 (ordered bits) in *maxres.
+// squared residual |y_i - C_i Q|^2 (ordered bits) in *maxres.  Four threads
+// per row (RCW columns each; 64 rows per workgroup): each projection's dot
+// product is four partial sums per thread, added over the thread's quad by
+// DPP (every lane of the quad gets the same bits), then the quad's columns
+// are updated.  Q is staged in LDS with the four column slices of a row
+// RCQ doubles apart (2 mod 16), so that the quad's reads hit disjoint banks.
+constexpr int RC4 = 4, RCW = SEL_NC / RC4, RCQ = RCW + 2;
+static_assert(RCW % 4 == 0 && RCQ % 16 == 2, "row-coefficient layout");
+__device__ __forceinline__ double quad_sum(double t) {
+  t += dpp_f64<0xB1, 0xf>(t);   // quad_perm [1,0,3,2]
+  return t + dpp_f64<0x4E, 0xf>(t);   // quad_perm [2,3,0,1]
+}
 __global__ __launch_bounds__(256) void rowid_coef_kernel(const double* __restrict__ Y, int64_t m, int nc,
                                                          const double* __restrict__ Q, const int* __restrict__ kp,
                                                          int kmax, double* __restrict__ C,
                                                          unsigned long long* __restrict__ maxres) {
-  extern __shared__ double qs[];  // k x nc
+  extern __shared__ double qs[];  // k x (RC4 RCQ): column c of q_s at s RC4 RCQ + (c / RCW) RCQ + c % RCW
   const int k = *kp;
   if (k == 0) return;
-  for (int u = threadIdx.x; u < k * nc; u += 256) qs[u] = Q[u];
-  __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  double res = 0.0;
-  if (i < m) {
-    double y[SEL_NC];
-#pragma unroll
-    for (int c = 0; c < SEL_NC; ++c) y[c] = c < nc ? Y[i * nc + c] : 0.0;
-    for (int s = 0; s < k; ++s) {
-      const double* qv = qs + s * nc;
-      double d = 0.0;
-#pragma unroll
-      for (int c = 0; c < SEL_NC; ++c) d += (c < nc ? y[c] * qv[c] : 0.0);
-      C[i * kmax + s] = d;
-#pragma unroll
-      for (int c = 0; c < SEL_NC; ++c) y[c] -= (c < nc ? d * qv[c] : 0.0);
-    }
-#pragma unroll
-    for (int c = 0; c < SEL_NC; ++c) res += y[c] * y[c];
+  for (int u = threadIdx.x; u < k * SEL_NC; u += 256) {
+    const int s = u / SEL_NC, c = u - s * SEL_NC;
+    qs[s * (RC4 * RCQ) + (c / RCW) * RCQ + c % RCW] = c < nc ? Q[s * nc + c] : 0.0;
   }
+  __syncthreads();
+  const int h = threadIdx.x & (RC4 - 1);
+  const int64_t i = (int64_t)blockIdx.x * (256 / RC4) + (threadIdx.x >> 2);
+  const bool valid = i < m;
+  double y[RCW];
+#pragma unroll
+  for (int c = 0; c < RCW; ++c) {
+    const int col = h * RCW + c;
+    y[c] = (valid && col < nc) ? Y[i * nc + col] : 0.0;
+  }
+  for (int s = 0; s < k; ++s) {
+    const double* qv = qs + s * (RC4 * RCQ) + h * RCQ;
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+#pragma unroll
+    for (int c = 0; c < RCW; c += 4) {
+      d0 = fma(y[c], qv[c], d0);
+      d1 = fma(y[c + 1], qv[c + 1], d1);
+      d2 = fma(y[c + 2], qv[c + 2], d2);
+      d3 = fma(y[c + 3], qv[c + 3], d3);
+    }
+    const double d = quad_sum((d0 + d1) + (d2 + d3));
+    if (valid && h == 0) C[i * kmax + s] = d;
+#pragma unroll
+    for (int c = 0; c < RCW; ++c) y[c] -= d * qv[c];
+  }
+  double r0 = 0.0, r1 = 0.0;
+#pragma unroll
+  for (int c = 0; c < RCW; c += 2) {
+    r0 = fma(y[c], y[c], r0);
+    r1 = fma(y[c + 1], y[c + 1], r1);
+  }
+  double res = quad_sum(r0 + r1);
   for (int off = 32; off > 0; off >>= 1) res = fmax(res, __shfl_xor(res, off));
   if ((threadIdx.x & 63) == 0) atomicMax(maxres, (unsigned long long)__double_as_longlong(res));
 }
@@ -903,7 +949,7 @@ static int rowid_cooperative(rw_ctx* ctx, const double* Y, int64_t m, int ncols,
 bool launch_rowid_enqueue(rw_ctx* ctx, const double* Y, int64_t m, int ncols, double tol, int kmax, int* J,
                           double* C, void* work, int* res_k, unsigned long long* res_m, hipStream_t s) {
   const int64_t nb0 = (m + SEL_ROWS - 1) / SEL_ROWS;
-  if (m <= 0 || ncols > SEL_NC || kmax > 64 || nb0 > 1024) return false;
+  if (m <= 0 || ncols > SEL_NC || ncols % 4 != 0 || kmax > 64 || nb0 > 1024) return false;
   // the selection buffers sit behind the cooperative kernel's share of `work`
   char* w = (char*)work + (rowid_work_bytes(m, ncols, kmax, std::max(256, ctx->n_cu)) - rowid_sel_bytes(m, ncols, kmax));
   w = (char*)(((uintptr_t)w + 255) & ~(uintptr_t)255);
@@ -932,8 +978,8 @@ bool launch_rowid_enqueue(rw_ctx* ctx, const double* Y, int64_t m, int ncols, do
   // basis and coefficients read the selected count on the device
   hipLaunchKernelGGL(rowid_basis_kernel, dim3(1), dim3(64), 0, s, Y, ncols, idx[cur], cnt[cur], J, Q);
   KERNEL_CHECK("rowid_basis");
-  hipLaunchKernelGGL(rowid_coef_kernel, dim3(blocks(m)), dim3(256), sizeof(double) * kmax * ncols, s, Y, m, ncols, Q,
-                     cnt[cur], kmax, C, dmax + 1);
+  hipLaunchKernelGGL(rowid_coef_kernel, dim3((unsigned)((m + 256 / RC4 - 1) / (256 / RC4))), dim3(256),
+                     sizeof(double) * kmax * RC4 * RCQ, s, Y, m, ncols, Q, cnt[cur], kmax, C, dmax + 1);
   KERNEL_CHECK("rowid_coef");
   HIP_CHECK(hipMemcpyAsync(res_k, cnt[cur], sizeof(int), hipMemcpyDeviceToDevice, s));
   HIP_CHECK(hipMemcpyAsync(res_m, dmax, 2 * sizeof(unsigned long long), hipMemcpyDeviceToDevice, s));
