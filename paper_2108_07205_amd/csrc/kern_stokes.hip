@@ -1283,15 +1283,25 @@ int sketch_splits(int64_t nt, int64_t nsrc) {
 }
 
 // ---------------------------------------------------------------- orderings
+// grid (ceil(max(n_new, n_ref) / 256), nrhs): thread i moves refined node i
+// to its extended position, and zeroes reference node i if the refinement
+// cut it (ref_kind 1).  The two sets are disjoint and together cover the
+// extended vector, so no separate clearing runs.
 __global__ __launch_bounds__(256) void to_ext_kernel(const double* __restrict__ g, int64_t ld_g, int64_t n_new,
-                                                     const int* __restrict__ new2ext, double* __restrict__ ext,
-                                                     int64_t ld_ext) {
+                                                     const int* __restrict__ new2ext,
+                                                     const int* __restrict__ ref_kind, int64_t n_ref,
+                                                     double* __restrict__ ext, int64_t ld_ext) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int c = blockIdx.y;
-  if (i >= n_new) return;
-  const int64_t e = new2ext[i];
-  ext[2 * e + c * ld_ext] = g[2 * i + c * ld_g];
-  ext[2 * e + 1 + c * ld_ext] = g[2 * i + 1 + c * ld_g];
+  if (i < n_new) {
+    const int64_t e = new2ext[i];
+    ext[2 * e + c * ld_ext] = g[2 * i + c * ld_g];
+    ext[2 * e + 1 + c * ld_ext] = g[2 * i + 1 + c * ld_g];
+  }
+  if (i < n_ref && ref_kind[i] == 1) {
+    ext[2 * i + c * ld_ext] = 0.0;
+    ext[2 * i + 1 + c * ld_ext] = 0.0;
+  }
 }
 
 __global__ __launch_bounds__(256) void from_ext_kernel(const double* __restrict__ ext, int64_t ld_ext,
@@ -1497,12 +1507,12 @@ void launch_sketch(const NodeRec* tgt, int64_t nt, const SketchSeg* segs, int ns
   }
 }
 
-void launch_to_ext(const double* g, int64_t ld_g, int64_t n_new, const int* new2ext, double* ext, int64_t ld_ext,
-                   int64_t n_ext_dofs, int nrhs, hipStream_t s) {
-  for (int c = 0; c < nrhs; ++c)
-    HIP_CHECK(hipMemsetAsync(ext + (int64_t)c * ld_ext, 0, sizeof(double) * n_ext_dofs, s));
-  hipLaunchKernelGGL(to_ext_kernel, dim3(blocks(n_new), nrhs), dim3(256), 0, s, g, ld_g, n_new, new2ext, ext,
-                     ld_ext);
+void launch_to_ext(const double* g, int64_t ld_g, int64_t n_new, const int* new2ext, const int* ref_kind,
+                   int64_t n_ref, double* ext, int64_t ld_ext, int nrhs, hipStream_t s) {
+  const int64_t n = n_new > n_ref ? n_new : n_ref;
+  if (n <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(to_ext_kernel, dim3(blocks(n), nrhs), dim3(256), 0, s, g, ld_g, n_new, new2ext, ref_kind, n_ref,
+                     ext, ld_ext);
   KERNEL_CHECK("to_ext");
 }
 

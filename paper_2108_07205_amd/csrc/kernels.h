@@ -118,9 +118,11 @@ void launch_far_sketch(const SketchSeg* segs, int nseg, const NodeRec* tgt, int6
 // Y rows 2 pos[i], 2 pos[i] + 1 <- rows 2 i, 2 i + 1 of Yc (row-major, ncols)
 void launch_scatter_rows(const double* Yc, int64_t n, const int* pos, int ncols, double* Y, hipStream_t s);
 
-// gather / scatter between refined order and extended order
-void launch_to_ext(const double* g, int64_t ld_g, int64_t n_new, const int* new2ext, double* ext,
-                   int64_t ld_ext, int64_t n_ext_dofs, int nrhs, hipStream_t s);
+// gather / scatter between refined order and extended order; to_ext also
+// zeroes the extended entries of the cut reference nodes (ref_kind 1 of
+// n_ref), so it writes every entry of the extended vector
+void launch_to_ext(const double* g, int64_t ld_g, int64_t n_new, const int* new2ext, const int* ref_kind,
+                   int64_t n_ref, double* ext, int64_t ld_ext, int nrhs, hipStream_t s);
 void launch_from_ext(const double* ext, int64_t ld_ext, int64_t n_new, const int* new2ext, double* out,
                      int64_t ld_out, int nrhs, bool accumulate, hipStream_t s);
 void launch_gather_nodes(const NodeRec* src, const int* idx, int64_t n, NodeRec* dst, hipStream_t s);

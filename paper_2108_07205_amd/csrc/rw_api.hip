@@ -622,7 +622,8 @@ void refined_ensure_ws(rw_refined* f, int nrhs) {
 // correction y -= X W^{-1} R y and dst (+)= y in refined order.
 void woodbury_in(rw_refined* f, const double* src, int nrhs, hipStream_t s = nullptr) {
   const int64_t M = 2 * f->Next;
-  launch_to_ext(src, 2 * f->Nn, f->Nn, f->d_new2ext.p, f->gext.p, M, M, nrhs, s ? s : f->ctx->stream);
+  launch_to_ext(src, 2 * f->Nn, f->Nn, f->d_new2ext.p, f->d_ref_kind.p, f->No, f->gext.p, M, nrhs,
+                s ? s : f->ctx->stream);
 }
 
 void woodbury_ref_apply(rw_refined* f, int nrhs) {
