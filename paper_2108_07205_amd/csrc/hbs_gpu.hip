@@ -615,31 +615,8 @@ __device__ __forceinline__ void node_id_body(const GNode& g, const double* __res
 }
 
 // grid (nodes, 2), ID_NT threads: y = 0 the row side, y = 1 the column side.
-// Nodes of at most 128 candidates take four threads per row, larger ones (up
-// to 256) two.  pub: 2 slots per node, zero at the start of the build; tag:
-// a positive number unique to the level.
-__global__ __launch_bounds__(ID_NT) void node_id_kernel(const GNode* __restrict__ gn, const double* __restrict__ Sr,
-                                                        const double* __restrict__ Sc, double tol2,
-                                                        int* __restrict__ piv, double* __restrict__ Cr,
-                                                        double* __restrict__ Cc, int* __restrict__ info,
-                                                        long long* __restrict__ pub, long long tag) {
-  __shared__ IdScratch L;
-  const GNode g = gn[blockIdx.x];
-  const int side = blockIdx.y;
-  const double* S = (side == 0 ? Sr : Sc) + g.cand_off * SK_R;
-  double* C = (side == 0 ? Cr : Cc) + g.cand_off * SK_KCAP;
-  int* pv = piv + ((int64_t)blockIdx.x * 2 + side) * SK_KCAP;
-  int* inf = info + (blockIdx.x * 2 + side) * 2;
-  long long* mine = pub + blockIdx.x * 2 + side;
-  long long* theirs = pub + blockIdx.x * 2 + (1 - side);
-  if (g.m <= 128)
-    node_id_body<4>(g, S, tol2, pv, C, inf, mine, theirs, tag, L);
-  else
-    node_id_body<2>(g, S, tol2, pv, C, inf, mine, theirs, tag, L);
-}
-
 // ---------------------------------------------------------------- 2b. level plan
-// grid 1, one wave: the ID ranks of level l (info: row rank, row steps,
+// One wave: the ID ranks of level l (info: row rank, row steps,
 // column rank, column steps per node) give each node's rank k (the larger
 // tolerance rank, at most the smaller step count) and, by prefix sums in
 // node order, its U / V, D^, workspace and generator offsets; the skeleton
@@ -658,11 +635,9 @@ __device__ __forceinline__ long long wave_incl_scan(long long v, int lane) {
   return v;
 }
 
-__global__ __launch_bounds__(64) void level_plan_kernel(GNode* __restrict__ gl, int nn, const int* __restrict__ info,
-                                                        GNode* __restrict__ gpar, int64_t* __restrict__ ppos,
-                                                        int64_t* __restrict__ cnt, int64_t gen_cap, int64_t ws_cap,
-                                                        int* __restrict__ fail) {
-  const int lane = threadIdx.x;
+// Run by one wave (lane = 0 .. 63) of the level's last ID workgroup.
+__device__ void level_plan_wave(GNode* gl, int nn, const int* info, GNode* gpar, int64_t* ppos, int64_t* cnt,
+                                int64_t gen_cap, int64_t ws_cap, int* fail, int lane) {
   long long base[5] = {0, 0, 0, (long long)cnt[0], 0};   // U/V, D^, workspace, generators, skeleton positions
   for (int j0 = 0; j0 < nn; j0 += 64) {
     const int j = j0 + lane;
@@ -703,6 +678,46 @@ __global__ __launch_bounds__(64) void level_plan_kernel(GNode* __restrict__ gl, 
   if (lane == 0) {
     cnt[0] = base[3];
     if (base[3] > gen_cap || base[2] > ws_cap) fail[2] = 1;
+  }
+}
+
+// Nodes of at most 128 candidates take four threads per row, larger ones (up
+// to 256) two.  pub: 2 slots per node, zero at the start of the build; tag:
+// a positive number unique to the level.  The workgroup that finishes last
+// (a device-scope counter, done, zero at the start of the build, counts the
+// finished workgroups after each has fenced its results) runs the level plan
+// below on its first wave, so that the plan needs no launch of its own.
+__global__ __launch_bounds__(ID_NT) void node_id_kernel(GNode* gl, const double* __restrict__ Sr,
+                                                        const double* __restrict__ Sc, double tol2,
+                                                        int* __restrict__ piv, double* __restrict__ Cr,
+                                                        double* __restrict__ Cc, int* info,
+                                                        long long* __restrict__ pub, long long tag,
+                                                        GNode* gpar, int64_t* ppos, int64_t* cnt, int64_t gen_cap,
+                                                        int64_t ws_cap, int* fail,
+                                                        unsigned long long* __restrict__ done) {
+  __shared__ IdScratch L;
+  __shared__ int last;
+  const GNode g = gl[blockIdx.x];
+  const int side = blockIdx.y;
+  const double* S = (side == 0 ? Sr : Sc) + g.cand_off * SK_R;
+  double* C = (side == 0 ? Cr : Cc) + g.cand_off * SK_KCAP;
+  int* pv = piv + ((int64_t)blockIdx.x * 2 + side) * SK_KCAP;
+  int* inf = info + (blockIdx.x * 2 + side) * 2;
+  long long* mine = pub + blockIdx.x * 2 + side;
+  long long* theirs = pub + blockIdx.x * 2 + (1 - side);
+  if (g.m <= 128)
+    node_id_body<4>(g, S, tol2, pv, C, inf, mine, theirs, tag, L);
+  else
+    node_id_body<2>(g, S, tol2, pv, C, inf, mine, theirs, tag, L);
+  // thread 0 wrote this workgroup's info; release it, then count
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(done, 1ull) == 2ull * gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last && threadIdx.x < 64) {   // uniform per workgroup
+    __threadfence();   // acquire the other workgroups' info
+    level_plan_wave(gl, gridDim.x, info, gpar, ppos, cnt, gen_cap, ws_cap, fail, threadIdx.x);
   }
 }
 
@@ -2129,11 +2144,13 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, int64_t n_nodes, int lea
   DBuf<double> Cr(ctx, cap_max * SK_KCAP), Cc(ctx, cap_max * SK_KCAP);
   DBuf<int> piv(ctx, (size_t)(int64_t(2) << L) * SK_KCAP), info(ctx, (size_t)(int64_t(4) << L));
   // control words, cleared together: fail flags (4 ints), generator / spare
-  // counters (2), the ID sides' published ranks (2 per node of a level)
-  DBuf<int64_t> ctl(ctx, (size_t)(4 + (int64_t(2) << L)));
+  // counters (2), the ID sides' published ranks (2 per node of a level), the
+  // finished ID workgroups of each level (L + 1)
+  DBuf<int64_t> ctl(ctx, (size_t)(4 + (int64_t(2) << L) + L + 1));
   int* const failp = (int*)ctl.p;
   int64_t* const cntp = ctl.p + 2;
   long long* const pubp = (long long*)(ctl.p + 4);
+  unsigned long long* const donep = (unsigned long long*)(ctl.p + 4 + (int64_t(2) << L));
   DBuf<double> Ub(ctx, uv_total), Vb(ctx, uv_total);
   DBuf<double> dhA(ctx, (int64_t(1) << L) * SK_KCAP * SK_KCAP), dhB(ctx, (int64_t(1) << L) * SK_KCAP * SK_KCAP);
   DBuf<double> ws(ctx, ws_bound);
@@ -2164,7 +2181,7 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, int64_t n_nodes, int lea
   int64_t* hCtl = (int64_t*)(pin + sizeof(GNode) * (size_t)(int64_t(2) << L));
   int* hC = (int*)(hCtl + 4);
   // leaf records carry their counts and offsets; a parent's are set on the
-  // device from its children's ranks (level_plan_kernel)
+  // device from its children's ranks (level_plan_wave)
   {
     int64_t off = 0;
     for (GNode& g : G[L]) { g.cand_off = off; off += g.m; }
@@ -2283,13 +2300,12 @@ void hbs_gpu_build(rw_ctx* ctx, const NodeRec* d_nodes, int64_t n_nodes, int lea
     }
     {
       KernelTimer kt_id("node_id_kernel", 0.0, 0.0);
+      // the level plan runs in the last workgroup to finish
       hipLaunchKernelGGL(node_id_kernel, dim3(nn, 2), dim3(ID_NT), 0, s, dgl, Sr.p, Sc.p, tol * tol, piv.p, Cr.p,
-                         Cc.p, info.p, pubp, (long long)(l + 1));
+                         Cc.p, info.p, pubp, (long long)(l + 1), dg.p + nn / 2, dpar.p + nn, cntp,
+                         (int64_t)w.gen.n, (int64_t)ws.n, failp, donep + l);
       KERNEL_CHECK("node_id");
     }
-    hipLaunchKernelGGL(level_plan_kernel, dim3(1), dim3(64), 0, s, dgl, nn, info.p, dg.p + nn / 2, dpar.p + nn, cntp,
-                       (int64_t)w.gen.n, (int64_t)ws.n, failp);
-    KERNEL_CHECK("level_plan");
     hipLaunchKernelGGL(node_interp_kernel, dim3(nn, 2), dim3(256), shi, s, dgl, cr, cc, piv.p, Cr.p, Cc.p,
                        Ub.p + uv_base[l], Vb.p + uv_base[l], dpar.p + nn, candr.p + cand_base[l - 1],
                        candc.p + cand_base[l - 1]);
