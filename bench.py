@@ -64,11 +64,11 @@ KERNEL_BOUND = {
 # the counters were taken; otherwise the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
     "node_factor_bordered_kernel": {
-        "fetch_kib": 1256.8, "write_kib": 3293.2, "fetch_scale": 1.9999, "write_scale": 1.0000,
+        "fetch_kib": 1256.9, "write_kib": 3293.0, "fetch_scale": 1.9999, "write_scale": 1.0000,
         "sources": ["paper_2108_07205_amd/csrc/hbs_gpu.hip", "paper_2108_07205_amd/csrc/dev_gj.h",
                     "paper_2108_07205_amd/csrc/dev_reduce.h", "paper_2108_07205_amd/csrc/hbs_dev.h",
                     "paper_2108_07205_amd/csrc/common.h"],
-        "sha256": "f42084696504e82b740dc17357e35df1a8d46cfe3d5b0ce7d1cd2b1be1527cd2",
+        "sha256": "8d14affa40fd2832a4fb49f94fb8bd25a627df3be7f5771099784c6c50d56806",
         "summary": "profiles/star1024_refine16x4_hbm_traffic.md",
     },
 }
